@@ -1,0 +1,236 @@
+"""Seeded synthetic scene generators shared by the oracle, the tests and the benchmark.
+
+This module only lays out inputs: particle lattices, jitter, initial fields and the
+material / solver parameters of each workload.  It contains none of the method's
+arithmetic (no B-splines, no surface sampling, no transfers, no solves), so both the
+CPU oracle and the GPU path may consume what it returns.
+
+Every array is float64, natural (particle-major) order.  Positions live in the unit
+domain [0,1]^d; the background grid has n nodes per axis at cell centres with
+spacing dx = 1/n (the paper's cell-centred quadratic B-spline grid, Section 4.2).
+
+Workloads (the paper uses no dataset; every scene here is procedural):
+  square2d     2D square droplet relaxing under constant surface tension (64^2)
+  marangoni3d  3D droplet with a linear temperature field and gamma(T) (128^3)
+  contact3d    3D hemisphere-cap droplet on a static slab, three surface energies (192^3)
+  meltslab3d   3D slab heated by the ambient through the Robin term, mu(T) (256^3)
+  serving      stream of small droplet scenes (n in {16,32,48,64,96})
+"""
+from __future__ import annotations
+
+import copy
+import math
+
+import numpy as np
+
+# Parameter defaults.  Keys mirror the fields of the C struct mpm_params.
+DEFAULT_PARAMS = dict(
+    dim=3, n=64, dx=1.0 / 64, dt=1e-3,
+    gravity=(0.0, 0.0, 0.0),
+    bulk=1e4,                       # lambda^l of Psi^p(J) = lambda/2 (J-1)^2
+    mu0=0.0, mu_k=0.0, mu_T0=0.0,   # mu(T) = mu0 * exp(-mu_k (T - mu_T0))
+    g0=0.07, g1=0.0, gT0=0.0,       # gamma(T) = clamp(g0 + g1 (T - gT0), gmin, gmax)
+    gmin=0.0, gmax=1e30,
+    gamma_by_label=0, gamma_label=(0.0, 0.0, 0.0, 0.0),
+    heat=0, cp=1.0, K=0.0, h=0.0, T_amb=0.0, b=0.0, H=0.0,
+    wall_layers=0,
+    slab=0, slab_lo=(0.0, 0.0, 0.0), slab_hi=(0.0, 0.0, 0.0), slab_axis=1,
+    label_lo=(0.0, 0.0, 0.0), label_hi=(0.0, 0.0, 0.0),
+    newton_tol=1e-8, newton_max=20, cg_rel=1e-2, cg_max=1000, ls_max=10, ls_c1=1e-4,
+    heat_tol=1e-10, heat_max=1000,
+    hess_mode=0,                    # 0 = PSD (definiteness fix), 1 = EXACT
+    momentum_fix=1,
+    term_mask=7,                    # bit0 J-term, bit1 surface, bit2 viscosity
+    ls_radius=None,                 # union-of-spheres radius; None -> 0.73 dx (2D) / 0.867 dx (3D)
+    sample_density=None,            # samples per unit area (3D) / length (2D); None -> 8/dx^2, 4/dx
+    seed=0,
+)
+
+
+def make_params(**kw):
+    p = copy.deepcopy(DEFAULT_PARAMS)
+    for k, v in kw.items():
+        if k not in p:
+            raise KeyError(f"unknown parameter {k}")
+        p[k] = v
+    p["dx"] = 1.0 / p["n"]
+    if p["ls_radius"] is None:
+        p["ls_radius"] = (0.73 if p["dim"] == 2 else 0.867) * p["dx"]
+    if p["sample_density"] is None:
+        p["sample_density"] = (4.0 / p["dx"]) if p["dim"] == 2 else (8.0 / p["dx"] ** 2)
+    g = list(p["gravity"]) + [0.0] * 3
+    p["gravity"] = tuple(float(t) for t in g[:3])
+    return p
+
+
+def lattice(n, dim, inside, seed, ppc_axis=2, jitter=0.25, lo=None, hi=None):
+    """Jittered sub-cell lattice: ppc_axis^dim points per cell at offsets
+    (k + 1/2)/ppc_axis * dx, each coordinate jittered by U[-jitter, jitter]*dx, kept
+    where inside(x) is true.  Cells are visited z-major, x fastest; the jitter stream is
+    numpy PCG64(seed), one draw per point and axis in visiting order."""
+    dx = 1.0 / n
+    lo = np.zeros(dim, int) if lo is None else np.asarray(lo, int)
+    hi = np.full(dim, n, int) if hi is None else np.asarray(hi, int)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    axes = [np.arange(lo[a], hi[a]) for a in range(dim)]
+    cells = np.stack(np.meshgrid(*axes[::-1], indexing="ij")[::-1], -1).reshape(-1, dim)
+    sub = np.stack(np.meshgrid(*([np.arange(ppc_axis)] * dim)[::-1], indexing="ij")[::-1], -1).reshape(-1, dim)
+    off = (sub + 0.5) / ppc_axis
+    pts = (cells[:, None, :] + off[None, :, :]).reshape(-1, dim) * dx
+    pts = pts + rng.uniform(-jitter, jitter, size=pts.shape) * dx
+    keep = inside(pts)
+    return np.ascontiguousarray(pts[keep])
+
+
+def particles_from_positions(x, dim, dx, rho=1000.0, ppc=None, T=None, gradT=None):
+    N = x.shape[0]
+    ppc = (2 ** dim) if ppc is None else ppc
+    V0 = np.full(N, dx ** dim / ppc)
+    return dict(
+        x=np.ascontiguousarray(x, dtype=np.float64),
+        v=np.zeros((N, dim)), A=np.zeros((N, dim, dim)), J=np.ones(N),
+        V0=V0, m=rho * V0,
+        T=np.zeros(N) if T is None else np.asarray(T, np.float64),
+        gradT=np.zeros((N, dim)) if gradT is None else np.asarray(gradT, np.float64),
+    )
+
+
+def square2d(seed=1, n=64):
+    """2D square droplet: [0.25,0.75]^2 at 2x2 per cell, rho 1000, bulk 1e4, gamma 0.07,
+    no gravity, dt 1e-3, Newton tol 1e-8."""
+    p = make_params(dim=2, n=n, dt=1e-3, bulk=1e4, g0=0.07, newton_tol=1e-8, seed=seed)
+    inside = lambda q: np.all((q >= 0.25) & (q < 0.75), axis=1)
+    x = lattice(n, 2, inside, seed)
+    return dict(params=p, particles=particles_from_positions(x, 2, p["dx"]), name="square2d", steps=5)
+
+
+def marangoni3d(seed=2, n=128, radius=0.2):
+    """3D droplet, linear temperature in x (300 K at x=0.3 to 350 K at x=0.7),
+    gamma(T) = 0.072 - 1.5e-4 (T-300), insulated heat solve (c_p 1, K 0.1)."""
+    p = make_params(dim=3, n=n, dt=5e-4, bulk=1e4, g0=0.072, g1=-1.5e-4, gT0=300.0,
+                    heat=1, cp=1.0, K=0.1, h=0.0, b=0.0, T_amb=300.0, seed=seed)
+    c = np.array([0.5, 0.5, 0.5])
+    inside = lambda q: np.sum((q - c) ** 2, axis=1) < radius ** 2
+    lo = np.floor((c - radius) * n).astype(int) - 1
+    hi = np.ceil((c + radius) * n).astype(int) + 1
+    x = lattice(n, 3, inside, seed, lo=lo, hi=hi)
+    T = 300.0 + 50.0 * (x[:, 0] - 0.3) / 0.4
+    gT = np.zeros_like(x)
+    gT[:, 0] = 125.0
+    return dict(params=p, particles=particles_from_positions(x, 3, p["dx"], T=T, gradT=gT),
+                name="marangoni3d", steps=20)
+
+
+def contact3d(seed=3, n=192, radius=0.15):
+    """3D hemisphere-cap droplet resting on a static slab y in [2dx, 6dx).  Surface
+    samples inside the slab's (dilated) box take gamma_SL - gamma_SA, the rest gamma_LA.
+    Nodes inside the slab box have zero normal (y) velocity."""
+    dx = 1.0 / n
+    yb = 6 * dx
+    rls = 0.867 * dx
+    p = make_params(dim=3, n=n, dt=5e-4, bulk=1e4, gravity=(0.0, -9.8, 0.0),
+                    gamma_by_label=1, gamma_label=(0.072, 0.06 - 0.04, 0.0, 0.0),
+                    slab=1, slab_lo=(2 * dx, 2 * dx, 2 * dx), slab_hi=(1 - 2 * dx, yb, 1 - 2 * dx),
+                    slab_axis=1,
+                    label_lo=(2 * dx - rls, 2 * dx - rls, 2 * dx - rls),
+                    label_hi=(1 - 2 * dx + rls, yb + rls, 1 - 2 * dx + rls),
+                    momentum_fix=0, seed=seed)
+    c = np.array([0.5, yb, 0.5])
+    inside = lambda q: (np.sum((q - c) ** 2, axis=1) < radius ** 2) & (q[:, 1] >= yb)
+    lo = np.floor((c - radius) * n).astype(int) - 1
+    hi = np.ceil((c + radius) * n).astype(int) + 1
+    lo[1] = int(round(yb * n))
+    x = lattice(n, 3, inside, seed, lo=lo, hi=hi)
+    return dict(params=p, particles=particles_from_positions(x, 3, dx), name="contact3d", steps=50)
+
+
+def meltslab3d(seed=4, n=256, ppc_axis=2):
+    """3D wax slab x,z in [0.2,0.8], y in [2dx, 2dx+0.2], T0 290 K heated by a 400 K
+    ambient through the Robin term (h 20, b 0, K 0.25, c_p 1), mu(T) = 1e3 exp(-0.05
+    (T-290)), gamma(T) as in marangoni3d, gravity -9.8, slip floor (two node layers)."""
+    dx = 1.0 / n
+    p = make_params(dim=3, n=n, dt=1e-3, bulk=1e4, gravity=(0.0, -9.8, 0.0),
+                    mu0=1e3, mu_k=0.05, mu_T0=290.0,
+                    g0=0.072, g1=-1.5e-4, gT0=300.0,
+                    heat=1, cp=1.0, K=0.25, h=20.0, b=0.0, T_amb=400.0,
+                    wall_layers=2, momentum_fix=0, seed=seed)
+    y0, y1 = 2 * dx, 2 * dx + 0.2
+    inside = lambda q: (np.all((q[:, [0, 2]] >= 0.2) & (q[:, [0, 2]] < 0.8), axis=1)
+                        & (q[:, 1] >= y0) & (q[:, 1] < y1))
+    lo = np.array([int(0.2 * n) - 1, 2, int(0.2 * n) - 1])
+    hi = np.array([int(0.8 * n) + 2, int(y1 * n) + 2, int(0.8 * n) + 2])
+    x = lattice(n, 3, inside, seed, ppc_axis=ppc_axis, lo=lo, hi=hi)
+    T = np.full(x.shape[0], 290.0)
+    return dict(params=p, particles=particles_from_positions(x, 3, dx, ppc=ppc_axis ** 3, T=T),
+                name="meltslab3d", steps=20)
+
+
+def droplet3d(n, seed, gamma0, grad, radius=0.24, dt=5e-4):
+    """One serving-stream scene: sphere r=0.24 at the centre, linear temperature
+    T = 300 + grad . (x - c), gamma(T) = gamma0 - 1.5e-4 (T - 300)."""
+    p = make_params(dim=3, n=n, dt=dt, bulk=1e4, g0=gamma0, g1=-1.5e-4, gT0=300.0,
+                    heat=1, cp=1.0, K=0.1, h=0.0, b=0.0, T_amb=300.0, seed=seed)
+    c = np.full(3, 0.5)
+    inside = lambda q: np.sum((q - c) ** 2, axis=1) < radius ** 2
+    lo = np.floor((c - radius) * n).astype(int) - 1
+    hi = np.ceil((c + radius) * n).astype(int) + 1
+    x = lattice(n, 3, inside, seed, lo=lo, hi=hi)
+    grad = np.asarray(grad, np.float64)
+    T = 300.0 + (x - c) @ grad
+    gT = np.tile(grad, (x.shape[0], 1))
+    return dict(params=p, particles=particles_from_positions(x, 3, p["dx"], T=T, gradT=gT),
+                name=f"droplet{n}", steps=1)
+
+
+def serving_stream(count=512, rate=200.0, seed=5, sizes=(16, 32, 48, 64, 96)):
+    """Request stream: exponential inter-arrival times (mean 1/rate), grid edge uniform
+    in sizes, gamma0 ~ U[0.02,0.08], temperature gradient = random direction x U[0,125]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = np.cumsum(rng.exponential(1.0 / rate, size=count))
+    reqs = []
+    for i in range(count):
+        n = int(rng.choice(sizes))
+        g0 = float(rng.uniform(0.02, 0.08))
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        grad = d * rng.uniform(0.0, 125.0)
+        reqs.append(dict(arrival=float(t[i]), n=n, gamma0=g0, grad=grad.tolist(), seed=1000 + i))
+    return reqs
+
+
+def random_scene(dim, n, count, seed, box=(0.3, 0.7), vel=0.5, affine=5.0, temp=True,
+                 **param_kw):
+    """Small random scene for unit and property tests: count particles uniform in
+    box^dim with random v, A, J, T, grad T."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    p = make_params(dim=dim, n=n, seed=seed, **param_kw)
+    x = rng.uniform(box[0], box[1], size=(count, dim))
+    P = particles_from_positions(x, dim, p["dx"])
+    P["v"] = rng.uniform(-vel, vel, size=(count, dim))
+    P["A"] = rng.uniform(-affine, affine, size=(count, dim, dim))
+    P["J"] = rng.uniform(0.9, 1.1, size=count)
+    P["m"] = P["m"] * rng.uniform(0.5, 1.5, size=count)
+    if temp:
+        P["T"] = rng.uniform(280.0, 320.0, size=count)
+        P["gradT"] = rng.uniform(-50.0, 50.0, size=(count, dim))
+    return dict(params=p, particles=P, name=f"random{dim}d", steps=1)
+
+
+def random_surface(P, count, seed, spread=1.0, dx=None, dim=None):
+    """Synthetic surface quadrature points for unit tests of the transfer and energy
+    operators: points near randomly chosen particles with random area-weighted normals.
+    (The real workloads sample the union-of-spheres level set instead.)"""
+    rng = np.random.Generator(np.random.PCG64(seed + 7919))
+    x = P["x"]
+    dim = x.shape[1] if dim is None else dim
+    base = x[rng.integers(0, x.shape[0], size=count)]
+    s = base + rng.uniform(-spread, spread, size=(count, dim)) * dx
+    nrm = rng.normal(size=(count, dim))
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    dA = nrm * rng.uniform(0.05, 0.3, size=(count, 1)) * dx ** (dim - 1)
+    label = rng.integers(0, 2, size=count).astype(np.int32)
+    return dict(s=np.ascontiguousarray(s), dA=np.ascontiguousarray(dA), label=label)
+
+
+CONFIGS = dict(square2d=square2d, marangoni3d=marangoni3d, contact3d=contact3d,
+               meltslab3d=meltslab3d)

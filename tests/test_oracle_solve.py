@@ -1,0 +1,119 @@
+"""Pins of the implicit heat update (Section 4.3.2), the Newton momentum solve
+(Section 4.3.1) and the end-to-end conservation claims (Section 6.1)."""
+import numpy as np
+import pytest
+
+import mpm_scenes as sc
+from oracle import bspline, resample, sampler, solve, step, transfer
+
+
+def _heat(dim, seed, **kw):
+    S = sc.random_scene(dim, 16, 40, seed, cp=2.0, K=0.3, h=4.0, T_amb=350.0, b=7.0, heat=1, dt=1e-3, **kw)
+    P, p = S["particles"], S["params"]
+    surf = sc.random_surface(P, 30, seed, dx=p["dx"], spread=0.7)
+    sp = resample.split(P, surf)
+    g = transfer.p2g(P, surf, sp, p)
+    st = transfer.grid_setup(P, surf, sp, g, p)
+    return solve.Heat(P, surf, g, st, p), P, surf, sp, g, st, p
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_heat_operator_symmetric_positive(dim):
+    H, *_ = _heat(dim, 1)
+    rng = np.random.default_rng(2)
+    u = rng.normal(size=H.nn) * H.dof
+    w = rng.normal(size=H.nn) * H.dof
+    assert np.sum(u * H.apply(w)) == pytest.approx(np.sum(w * H.apply(u)), rel=1e-12)
+    assert np.sum(u * H.apply(u)) > 0
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_heat_uniform_ambient_is_fixed_point(dim):
+    H, P, surf, sp, g, st, p = _heat(dim, 3)
+    P2 = dict(P, T=np.full(len(P["T"]), 350.0), gradT=np.zeros_like(P["gradT"]))
+    g2 = transfer.p2g(P2, surf, sp, p)
+    st2 = transfer.grid_setup(P2, surf, sp, g2, p)
+    H2 = solve.Heat(P2, surf, g2, st2, dict(p, b=0.0))
+    T, info = H2.solve(dict(p, heat_tol=1e-14))
+    assert np.allclose(T[H2.dof], 350.0, rtol=1e-12)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_heat_balance_law(dim):
+    """1^T L = 0, so sum_i c_p m_i (T^_i - T^n_i)/dt equals the Robin flux
+    sum_r |dA_r| (h (T_amb - T^(s_r)) + b)."""
+    H, P, surf, sp, g, st, p = _heat(dim, 4)
+    T, info = H.solve(dict(p, heat_tol=1e-14))
+    lhs = np.sum(H.c * H.m * (T - st["Tn"]) * H.dof)
+    Ts = np.sum(H.sN * T[H.sidx], axis=1)
+    rhs = np.sum(H.area * (p["h"] * (p["T_amb"] - Ts) + p["b"]))
+    assert lhs == pytest.approx(rhs, rel=1e-9)
+
+
+def test_newton_solution_is_stationary_and_conserves_momentum():
+    S = sc.square2d(n=32)
+    P, p = S["particles"], dict(S["params"], newton_tol=1e-12)
+    rng = np.random.default_rng(5)
+    P["v"] = rng.normal(size=P["v"].shape) * 0.05
+    newP, info = step.step(P, p)
+    assert info["converged"]
+    ctx = step.prepare(P, p, info["surf"])[-1]
+    g = ctx.project(ctx.grad_Phi(info["vhat"]))
+    assert np.linalg.norm(g) <= 1e-9 * info["g0"]
+    mom0 = (P["m"][:, None] * P["v"]).sum(0)
+    mom1 = (P["m"][:, None] * newP["v"]).sum(0)
+    assert np.allclose(mom0, mom1, rtol=0, atol=1e-15 * np.abs(P["m"][:, None] * P["v"]).sum())
+
+
+def ellipse2d(n=63, seed=6):
+    p = sc.make_params(dim=2, n=64, dt=1e-5, bulk=4166.67, g0=0.1, seed=seed)
+    c = np.array([0.5, 0.5])
+    inside = lambda q: ((q[:, 0] - c[0]) / 0.2) ** 2 + ((q[:, 1] - c[1]) / 0.12) ** 2 < 1
+    # 8 particles per cell, uniformly random (Section 6.1)
+    rng = np.random.default_rng(seed)
+    cells = np.stack(np.meshgrid(np.arange(16, 48), np.arange(16, 48), indexing="xy"), -1).reshape(-1, 2)
+    x = (cells[:, None, :] + rng.uniform(0, 1, size=(len(cells), 8, 2))).reshape(-1, 2) / 64
+    x = x[inside(x)]
+    P = sc.particles_from_positions(x, 2, p["dx"], ppc=8)
+    return P, p
+
+
+def test_explicit_steps_conserve_momentum_and_centre_of_mass():
+    """Section 6.1: with the conservative split, total linear and angular momentum and
+    the centre of mass are conserved to round-off under explicit stepping."""
+    P, p = ellipse2d()
+    xi = None
+    mom = []
+    L = []
+    com = []
+    for k in range(6):
+        mom.append((P["m"][:, None] * P["v"]).sum(0))
+        L.append(np.sum(P["m"] * (P["x"][:, 0] * P["v"][:, 1] - P["x"][:, 1] * P["v"][:, 0]))
+                 + np.sum(P["m"] * (P["A"][:, 1, 0] - P["A"][:, 0, 1])) * p["dx"] ** 2 / 4)
+        com.append((P["m"][:, None] * P["x"]).sum(0) / P["m"].sum())
+        P, info = step.step(P, p, implicit=False, step_index=k)
+    scale = np.abs(P["m"][:, None] * P["v"]).sum()
+    assert scale > 0
+    assert np.allclose(mom, 0, atol=1e-14 * scale)
+    assert np.allclose(L, 0, atol=1e-14 * scale)
+    assert np.allclose(com, com[0], rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_droplet_surface_energy_converges(dim):
+    """A resting droplet of radius R: e_sigma = gamma * (mesh area) approaches gamma 4 pi R^2
+    (2 pi R in 2D) under refinement; the offset is O(dx) because the union of spheres
+    sits outside the particles."""
+    R, gamma = 0.2, 0.07
+    errs = []
+    for n in ((32, 64, 128) if dim == 2 else (16, 32, 64)):
+        c = np.full(dim, 0.5)
+        x = sc.lattice(n, dim, lambda q: np.sum((q - c) ** 2, 1) < R * R, seed=n)
+        p = sc.make_params(dim=dim, n=n, g0=gamma)
+        surf = sampler.sample_surface(x, p)
+        es = gamma * np.linalg.norm(surf["dA"], axis=1).sum()
+        exact = gamma * (4 * np.pi * R * R if dim == 3 else 2 * np.pi * R)
+        errs.append(abs(es - exact) / exact)
+        if R * n >= 16:
+            assert errs[-1] < 0.10
+    assert errs[0] > errs[1] > errs[2]
