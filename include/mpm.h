@@ -1,0 +1,240 @@
+/*
+ * mpm.h - C ABI of the MI355X implicit APIC MPM hot path.
+ *
+ * The library implements one time step of the implicit Material Point Method with
+ * spatially varying surface energy of Chen et al., "A Momentum-Conserving Implicit
+ * Material Point Method for Surface Energies with Spatial Gradients" (arXiv 2101.12408):
+ * the conservative split into surface and balance particles (Sections 4.1.2-4.1.3), the
+ * APIC particle-to-grid transfer of mass, momentum and temperature (Section 4.2), the
+ * backward-Euler grid momentum update with its energy, forces (eq. fe) and
+ * Hessian-vector product (Section 4.3.1), the implicit heat update with the particle
+ * Robin term (Section 4.3.2), and the grid-to-particle transfer with merge (Section 5).
+ *
+ * Conventions
+ *  - Every entry point returns an int status (MPM_OK = 0 or an MPM_E* code) and never
+ *    throws.  mpm_last_error() returns a message for the last failure on a context
+ *    (with NULL: the last failure of the calling thread that had no context to hold it,
+ *    e.g. a failed mpm_ctx_create).
+ *  - Real numbers are double in MPM_FP64 mode and float in MPM_MIXED mode ("real" below).
+ *    Scalar results (energies, norms, momentum sums) are always double.
+ *  - All particle, surface and grid buffers are DEVICE pointers owned by the caller,
+ *    structure-of-arrays: component a of item i is at [a * count + i].
+ *  - Grid vectors are dense over all n^dim nodes, component-major ([dim][n^dim]), with
+ *    nodes numbered tile by tile: the grid is cut into tiles of 4x4x4 nodes (3D) or 8x8
+ *    nodes (2D); node (i0,i1[,i2]) has index tile*64 + local with
+ *      tile  = t0 + nt*(t1 + nt*t2),  t_a = i_a / E,  nt = n / E,  E = 4 (3D) or 8 (2D)
+ *      local = l0 + E*(l1 + E*l2),    l_a = i_a % E.
+ *    mpm_node_index() computes it.  Node (i) sits at the cell centre (i + 1/2) dx
+ *    (Section 4.2).  Only nodes with mass are unknowns; the library writes 0 elsewhere.
+ *  - Every call is asynchronous on the caller's stream (a hipStream_t passed as void*;
+ *    NULL is the null stream) unless documented otherwise.  Calls on one context must
+ *    not overlap: a context owns its workspace.
+ *  - The library allocates no device memory.  mpm_workspace_bytes() sizes a workspace
+ *    that the caller allocates and hands to mpm_ctx_create(); the context borrows it
+ *    until mpm_ctx_destroy().
+ */
+#ifndef MPM_H_
+#define MPM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mpm_ctx mpm_ctx;
+
+enum mpm_status {
+  MPM_OK = 0,
+  MPM_EINVAL = 1,     /* invalid argument: dim, n, dx, null pointer, size           */
+  MPM_ENOMEM = 2,     /* count above the capacity the workspace was sized for        */
+  MPM_EBUDGET = 3,    /* admission refused: over the memory budget                   */
+  MPM_EDOMAIN = 4,    /* a point's stencil leaves the grid (not in [dx, 1-dx)^dim)   */
+  MPM_ENOCONV = 5,    /* Newton or a Krylov solve hit its iteration cap              */
+  MPM_ENONFINITE = 6, /* a residual norm or energy became NaN or Inf                 */
+  MPM_EHIP = 7        /* a HIP runtime call failed                                   */
+};
+
+enum mpm_precision { MPM_FP64 = 0, MPM_MIXED = 1 };
+enum mpm_hess_mode { MPM_HESS_PSD = 0, MPM_HESS_EXACT = 1 };
+enum mpm_term { MPM_TERM_J = 1, MPM_TERM_SURF = 2, MPM_TERM_VISC = 4 };
+
+/* Scene and solver parameters (Sections 3, 4 and the per-example values of Section 6). */
+typedef struct mpm_params {
+  int32_t dim;            /* 2 or 3                                                    */
+  int32_t n;              /* nodes per axis, a multiple of 8; dx must equal 1/n        */
+  int32_t precision;      /* mpm_precision                                             */
+  int32_t hess_mode;      /* mpm_hess_mode: PSD drops the indefinite surface part      */
+  int32_t term_mask;      /* mpm_term bits of the energy terms to include (default 7)  */
+  int32_t momentum_fix;   /* 1: exact minimization along translations after each Newton
+                             iteration when no velocity component is constrained       */
+  int32_t wall_layers;    /* slip walls: velocity component a is fixed to 0 on nodes
+                             with i_a < wall_layers or i_a >= n - wall_layers          */
+  int32_t slab;           /* 1: component slab_axis fixed to 0 on nodes inside the box */
+  int32_t slab_axis;
+  int32_t heat;           /* 1: run the implicit heat update (Section 4.3.2)           */
+  int32_t gamma_by_label; /* 1: k_r = gamma_label[label_r] (piecewise constant, Sec 3.6) */
+  int32_t newton_max, cg_max, ls_max, heat_max;
+  double dx, dt;
+  double gravity[3];
+  double bulk;            /* lambda^l in Psi^p(J) = lambda/2 (J-1)^2 (Section 3.2.1)   */
+  double mu0, mu_k, mu_T0;/* viscosity mu(T) = mu0 exp(-mu_k (T - mu_T0))              */
+  double g0, g1, gT0, gmin, gmax; /* k^sigma(T) = clamp(g0 + g1 (T - gT0), gmin, gmax) */
+  double gamma_label[4];
+  double cp, K, h, T_amb, b, H;   /* heat: c_p, conductivity, Robin h, ambient, b, source */
+  double slab_lo[3], slab_hi[3];
+  double newton_tol;      /* stop when |P grad Phi| <= newton_tol |P grad Phi_0|       */
+  double cg_rel;          /* inner CG: |r| <= max(cg_rel |g|, 0.1 newton_tol |g_0|)    */
+  double ls_c1;           /* Armijo constant of the backtracking line search           */
+  double heat_tol;        /* heat CG: |r| <= heat_tol |rhs|                            */
+} mpm_params;
+
+/* Interior MPM particles (Section 4): SoA device buffers of real, n items each.
+ * x, v: [dim][n]; A: [dim*dim][n] with entry (a,b) at component a*dim+b; gradT: [dim][n]. */
+typedef struct mpm_particles {
+  int64_t n;
+  void* x;
+  void* v;
+  void* A;
+  void* J;
+  void* V0;
+  void* m;
+  void* T;
+  void* gradT;
+} mpm_particles;
+
+/* Surface samples s_r with area-weighted outward normals dA_r (Section 4.1.1), device
+ * buffers: s, dA [dim][n] real; label [n] int32 (may be NULL unless gamma_by_label). */
+typedef struct mpm_surface {
+  int64_t n;
+  const void* s;
+  const void* dA;
+  const int32_t* label;
+} mpm_surface;
+
+/* Solver statistics of the last step / solve on a context (host copy).  converged: 1 when
+ * |g| met the tolerance, 2 when a MIXED-mode solve stopped at the FP32 floor of the
+ * gradient (|g| <= 1e-4 |g0| and a Newton step no longer halves it), 0 otherwise. */
+typedef struct mpm_stats {
+  int32_t newton_iters, cg_iters, heat_iters, line_search_halvings;
+  int32_t energy_evals, hessvecs, converged, status;
+  double g0, gnorm, phi, heat_res;
+  double momentum[3];     /* sum_i m_i v^_i over the grid after the solve (FP64)        */
+  int64_t n_part, n_surf, n_dof, n_tiles;
+} mpm_stats;
+
+/* Grid fields readable through mpm_grid_view (device pointers into the workspace). */
+enum mpm_field {
+  MPM_F_MASS = 0,   /* m_i                        real [n^dim]                          */
+  MPM_F_MOM = 1,    /* (mv)_i                     real [dim][n^dim]                     */
+  MPM_F_W = 2,      /* sum_p m_p N_i(x_p)         real [n^dim]                          */
+  MPM_F_WT = 3,     /* sum_p m_p N_i (T_p + (x_i-x_p).grad T_p)   real [n^dim]          */
+  MPM_F_E = 4,      /* split-member mass weights  real [n^dim]                          */
+  MPM_F_ET = 5,     /* split-member temperature   real [n^dim]                          */
+  MPM_F_VN = 6,     /* v^n_i = (mv)_i / m_i       real [dim][n^dim]                     */
+  MPM_F_TN = 7,     /* T^n_i                      real [n^dim]                          */
+  MPM_F_FREE = 8,   /* uint8 [n^dim]: bit a set = component a free, bit 7 = has mass     */
+  MPM_F_HEAT_RHS = 9,   /* right side of the heat system   real [n^dim]                 */
+  MPM_F_HEAT_DIAG = 10, /* Jacobi diagonal of the heat system  real [n^dim]             */
+  MPM_F_VHAT = 11,  /* v^ after the last momentum solve   real [dim][n^dim]             */
+  MPM_F_THAT = 12,  /* T^ after the last heat solve       real [n^dim]                  */
+  MPM_F_PARENT = 13,/* int32 [n_surf]: parent p(r) of each surface sample (input order) */
+  MPM_F_COUNT = 14, /* int32 [n_part]: |Pi_p| (input order)                             */
+  MPM_F_KSURF = 15, /* real [n_surf]: k_r (input order)                                 */
+  MPM_F_MOM_DIAG = 16 /* Jacobi diagonal of the Newton matrix  real [dim][n^dim]        */
+};
+
+/* Node numbering helper (tile-major order described above). */
+static inline int64_t mpm_node_index(int32_t dim, int32_t n, int32_t i0, int32_t i1, int32_t i2) {
+  const int32_t E = (dim == 3) ? 4 : 8;
+  const int64_t nt = n / E;
+  int64_t tile = (i0 / E) + nt * ((i1 / E) + (dim == 3 ? nt * (i2 / E) : 0));
+  int64_t local = (i0 % E) + E * ((i1 % E) + (dim == 3 ? E * (i2 % E) : 0));
+  return tile * 64 + local;
+}
+
+/* Fills *p with defaults for dimension dim and n nodes per axis (dx = 1/n, FP64, PSD,
+ * all terms, 20 Newton / 1000 CG / 10 line-search / 1000 heat iterations, tolerances
+ * 1e-8 / 1e-2 / 1e-10, Armijo 1e-4).  Returns MPM_EINVAL for dim not 2 or 3. */
+int mpm_params_default(mpm_params* p, int32_t dim, int32_t n);
+
+/* Device workspace bytes for a context holding up to cap_part interior particles and
+ * cap_surf surface samples with parameters p.  Host only; synchronous. */
+int mpm_workspace_bytes(const mpm_params* p, int64_t cap_part, int64_t cap_surf, size_t* out_bytes);
+
+/* Creates a context over a caller-allocated device workspace of ws_bytes (at least
+ * mpm_workspace_bytes, 256-byte aligned).  The parameters are copied.  Host only. */
+int mpm_ctx_create(const mpm_params* p, void* workspace, size_t ws_bytes, int64_t cap_part,
+                   int64_t cap_surf, mpm_ctx** out);
+int mpm_ctx_destroy(mpm_ctx* ctx);
+const char* mpm_last_error(const mpm_ctx* ctx);
+/* Replaces the parameters of a context (same dim, n, precision and capacities). */
+int mpm_ctx_set_params(mpm_ctx* ctx, const mpm_params* p);
+
+/* Sections 4.1.2-4.2 and the grid set-up: bins particles and samples by cell, finds each
+ * sample's nearest interior particle (ties to the lower index), forms the balance points
+ * b_r = s_r + 2 (x_p(r) - s_r) and split masses m_p / (2|Pi_p| + 1), transfers mass,
+ * APIC momentum and temperature to the grid, and prepares the grid unknowns (nodes with
+ * mass, v^n, T^n, constraints, k_r, mu_p, Jacobi diagonals, heat right side).  P and S
+ * are read, never written.  Points outside [dx, 1-dx)^dim latch MPM_EDOMAIN, returned by
+ * the next synchronizing call. */
+int mpm_p2g(mpm_ctx* ctx, const mpm_particles* P, const mpm_surface* S, void* stream);
+
+/* Section 4.3.1: Phi(v^) = 1/2 sum m |v^-v^n|^2 - dt sum m g.v^ + e(x + dt v^) + dt D(v^)
+ * (energy_dev: one device double) and its gradient with respect to v^ (grad: real
+ * [dim][n^dim], projected onto the free components).  Requires mpm_p2g. */
+int mpm_energy_grad(mpm_ctx* ctx, const void* v_hat, double* energy_dev, void* grad, void* stream);
+
+/* Section 4.3.1: out = P (alpha M P w + d2Psi/dv^2 (v_lin) P w), P the projection onto
+ * free components, Psi = e(x + dt v^) + dt D(v^).  alpha = 1 gives the Newton matrix,
+ * alpha = 0 the energy Hessian alone.  The surface part is the PSD part or the exact
+ * second derivative per hess_mode.  Requires mpm_p2g. */
+int mpm_hessvec(mpm_ctx* ctx, const void* v_lin, const void* w, double alpha_mass, void* out,
+                void* stream);
+
+/* Section 4.3.2: T_out = A T_in with A = c_p/dt diag(m) + L + R over the nodes with mass
+ * (L the particle conduction matrix, R the particle Robin matrix).  Requires mpm_p2g. */
+int mpm_heat_apply(mpm_ctx* ctx, const void* T_in, void* T_out, void* stream);
+
+/* Section 5: G2P with merge of split groups, then J_p and x_p advanced; writes v, A, T,
+ * gradT, J, x of P in place (input order).  T_hat may be NULL: T and gradT are then left
+ * unchanged.  Requires mpm_p2g on the same P and S. */
+int mpm_g2p(mpm_ctx* ctx, const void* v_hat, const void* T_hat, mpm_particles* P, void* stream);
+
+/* Momentum solve only (after mpm_p2g): Newton-CG on Phi; v^ lands in MPM_F_VHAT.
+ * Synchronizes the stream.  Returns MPM_ENOCONV if Newton hit newton_max. */
+int mpm_solve_momentum(mpm_ctx* ctx, void* stream);
+/* Heat solve only (after mpm_p2g): CG on the heat system; T^ lands in MPM_F_THAT. */
+int mpm_solve_heat(mpm_ctx* ctx, void* stream);
+
+/* One full step for each of n_scenes scenes: p2g, momentum solve (implicit = 1:
+ * backward Euler with Newton; implicit = 0: explicit, forces at y = x), heat solve when
+ * enabled, g2p.  Particles are updated in place.  Synchronizes the stream.  Returns the
+ * first non-OK status; per-scene status is in mpm_stats. */
+int mpm_step(mpm_ctx* const* ctxs, mpm_particles* const* P, const mpm_surface* const* S,
+             int32_t n_scenes, int32_t implicit, void* stream);
+
+/* Device pointer of a grid field of the last mpm_p2g / solve (see mpm_field). */
+int mpm_grid_view(mpm_ctx* ctx, int32_t field, void** out_ptr);
+int mpm_get_stats(const mpm_ctx* ctx, mpm_stats* out);
+/* Latched device status of the context (synchronizes the stream). */
+int mpm_scene_status(mpm_ctx* ctx, void* stream);
+
+/* Host input stage (Section 4.1.1), not part of the timed device path: samples the zero
+ * isocontour of the union-of-spheres level set around host positions x ([dim][n_part]
+ * double).  Marching tetrahedra (3D) / triangles (2D) on the node lattice; per element
+ * max(1, floor(density * measure + u)) samples with SplitMix64 counter draws keyed by
+ * (seed, step, element id).  Writes at most cap samples to host buffers s, dA
+ * ([dim][cap] double) and label ([cap] int32: 1 inside [label_lo, label_hi)); *out_n
+ * receives the sample count (which may exceed cap: call again with a larger buffer).
+ * radius and density <= 0 select 0.73 dx / 0.867 dx and 4/dx / 8/dx^2. */
+int mpm_sample_surface(int32_t dim, int32_t n, const double* x, int64_t n_part, double radius,
+                       double density, uint64_t seed, uint64_t step, const double* label_lo,
+                       const double* label_hi, double* s, double* dA, int32_t* label, int64_t cap,
+                       int64_t* out_n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPM_H_ */

@@ -3,9 +3,12 @@
 Momentum (Section 4.3.1): backward Euler solved with Newton's method.  The paper names
 Newton's method and defers the linear algebra to earlier work, so the solver details are
 readings (R9): Jacobi-preconditioned CG on the projected Newton system, Armijo
-backtracking on Phi, and an optional exact minimization of Phi along rigid translations
-(e and D are translation invariant, so Phi restricted to v^ - c 1 is a quadratic whose
-minimizer is c = [sum m (v^ - v^n) - dt g sum m] / sum m).
+backtracking on Phi (a trial is accepted when Phi does not exceed the Armijo bound by
+more than the round-off of Phi, 8 eps |Phi|, eps the unit round-off of the arithmetic:
+near convergence the Newton decrement falls below that round-off and the comparison
+would otherwise be decided by summation order), and an optional exact minimization of
+Phi along rigid translations (e and D are translation invariant, so Phi restricted to
+v^ - c 1 is a quadratic whose minimizer is c = [sum m (v^ - v^n) - dt g sum m] / sum m).
 
 Temperature (Section 4.3.2): with the surface samples as quadrature points of the Robin
 term and interior particles as quadrature points of the conduction term,
@@ -77,7 +80,9 @@ def newton(ctx, params):
         alpha = 1.0
         for ls in range(params["ls_max"]):
             stats["energy"] += 1
-            if ctx.Phi(v + alpha * delta) <= phi0 + params["ls_c1"] * alpha * slope:
+            phit = ctx.Phi(v + alpha * delta)
+            noise = 8.0 * np.finfo(np.float64).eps * max(abs(phi0), abs(phit))
+            if phit <= phi0 + params["ls_c1"] * alpha * slope + noise:
                 break
             alpha *= 0.5
             stats["line_search"] += 1

@@ -1,0 +1,89 @@
+"""ctypes declarations of the C ABI in include/mpm.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmpm.so")
+
+MPM_OK, MPM_EINVAL, MPM_ENOMEM, MPM_EBUDGET, MPM_EDOMAIN, MPM_ENOCONV, MPM_ENONFINITE, MPM_EHIP = range(8)
+STATUS_NAMES = {0: "MPM_OK", 1: "MPM_EINVAL", 2: "MPM_ENOMEM", 3: "MPM_EBUDGET", 4: "MPM_EDOMAIN",
+                5: "MPM_ENOCONV", 6: "MPM_ENONFINITE", 7: "MPM_EHIP"}
+MPM_FP64, MPM_MIXED = 0, 1
+(F_MASS, F_MOM, F_W, F_WT, F_E, F_ET, F_VN, F_TN, F_FREE, F_HEAT_RHS, F_HEAT_DIAG, F_VHAT, F_THAT,
+ F_PARENT, F_COUNT, F_KSURF, F_MOM_DIAG) = range(17)
+
+
+class MpmParams(C.Structure):
+    _fields_ = [(k, C.c_int32) for k in (
+        "dim", "n", "precision", "hess_mode", "term_mask", "momentum_fix", "wall_layers", "slab",
+        "slab_axis", "heat", "gamma_by_label", "newton_max", "cg_max", "ls_max", "heat_max")] + [
+        ("dx", C.c_double), ("dt", C.c_double), ("gravity", C.c_double * 3), ("bulk", C.c_double),
+        ("mu0", C.c_double), ("mu_k", C.c_double), ("mu_T0", C.c_double),
+        ("g0", C.c_double), ("g1", C.c_double), ("gT0", C.c_double), ("gmin", C.c_double), ("gmax", C.c_double),
+        ("gamma_label", C.c_double * 4),
+        ("cp", C.c_double), ("K", C.c_double), ("h", C.c_double), ("T_amb", C.c_double), ("b", C.c_double),
+        ("H", C.c_double), ("slab_lo", C.c_double * 3), ("slab_hi", C.c_double * 3),
+        ("newton_tol", C.c_double), ("cg_rel", C.c_double), ("ls_c1", C.c_double), ("heat_tol", C.c_double)]
+
+
+class MpmParticles(C.Structure):
+    _fields_ = [("n", C.c_int64)] + [(k, C.c_void_p) for k in ("x", "v", "A", "J", "V0", "m", "T", "gradT")]
+
+
+class MpmSurface(C.Structure):
+    _fields_ = [("n", C.c_int64), ("s", C.c_void_p), ("dA", C.c_void_p), ("label", C.c_void_p)]
+
+
+class MpmStats(C.Structure):
+    _fields_ = [(k, C.c_int32) for k in (
+        "newton_iters", "cg_iters", "heat_iters", "line_search_halvings", "energy_evals", "hessvecs",
+        "converged", "status")] + [
+        ("g0", C.c_double), ("gnorm", C.c_double), ("phi", C.c_double), ("heat_res", C.c_double),
+        ("momentum", C.c_double * 3), ("n_part", C.c_int64), ("n_surf", C.c_int64), ("n_dof", C.c_int64),
+        ("n_tiles", C.c_int64)]
+
+
+EXPORTS = {
+    "mpm_params_default": (C.c_int, [C.POINTER(MpmParams), C.c_int32, C.c_int32]),
+    "mpm_workspace_bytes": (C.c_int, [C.POINTER(MpmParams), C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]),
+    "mpm_ctx_create": (C.c_int, [C.POINTER(MpmParams), C.c_void_p, C.c_size_t, C.c_int64, C.c_int64,
+                                 C.POINTER(C.c_void_p)]),
+    "mpm_ctx_destroy": (C.c_int, [C.c_void_p]),
+    "mpm_last_error": (C.c_char_p, [C.c_void_p]),
+    "mpm_ctx_set_params": (C.c_int, [C.c_void_p, C.POINTER(MpmParams)]),
+    "mpm_p2g": (C.c_int, [C.c_void_p, C.POINTER(MpmParticles), C.POINTER(MpmSurface), C.c_void_p]),
+    "mpm_energy_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mpm_hessvec": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]),
+    "mpm_heat_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mpm_g2p": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(MpmParticles), C.c_void_p]),
+    "mpm_solve_momentum": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "mpm_solve_heat": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "mpm_step": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(C.POINTER(MpmParticles)),
+                           C.POINTER(C.POINTER(MpmSurface)), C.c_int32, C.c_int32, C.c_void_p]),
+    "mpm_grid_view": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]),
+    "mpm_get_stats": (C.c_int, [C.c_void_p, C.POINTER(MpmStats)]),
+    "mpm_scene_status": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "mpm_sample_surface": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_int64, C.c_double, C.c_double,
+                                     C.c_uint64, C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]),
+}
+
+_lib = None
+
+
+def load(path=LIB_PATH):
+    """Loads libmpm.so; raises if it was not built (there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2101_12408_amd.build`")
+    lib = C.CDLL(path)
+    for name, (res, args) in EXPORTS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib

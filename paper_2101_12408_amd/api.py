@@ -1,0 +1,294 @@
+"""Python binding of the C ABI (include/mpm.h): argument marshalling around torch tensors.
+
+Every computation runs in libmpm.so; this module only converts parameters, hands device
+pointers of torch tensors to the library, and exposes workspace fields as tensor views.
+The functions keep the C names (mpm_p2g, mpm_energy_grad, mpm_hessvec, mpm_heat_apply,
+mpm_g2p, mpm_step); Scene bundles a context with its workspace.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib as L
+
+
+class MpmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{L.STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _check(rc, lib, ctx=None):
+    if rc != L.MPM_OK:
+        msg = lib.mpm_last_error(ctx).decode()
+        raise MpmError(rc, msg)
+
+
+def make_params(d, precision="fp64"):
+    """mpm_params from a parameter dict (keys as in mpm_scenes.DEFAULT_PARAMS)."""
+    lib = L.load()
+    p = L.MpmParams()
+    _check(lib.mpm_params_default(C.byref(p), int(d["dim"]), int(d["n"])), lib)
+    p.precision = L.MPM_FP64 if precision == "fp64" else L.MPM_MIXED
+    ints = ("hess_mode", "term_mask", "momentum_fix", "wall_layers", "slab", "slab_axis", "heat",
+            "gamma_by_label", "newton_max", "cg_max", "ls_max", "heat_max")
+    for k in ints:
+        if k in d:
+            setattr(p, k, int(d[k]))
+    for k in ("dx", "dt", "bulk", "mu0", "mu_k", "mu_T0", "g0", "g1", "gT0", "gmin", "gmax", "cp", "K", "h",
+              "T_amb", "b", "H", "newton_tol", "cg_rel", "ls_c1", "heat_tol"):
+        if k in d:
+            setattr(p, k, float(d[k]))
+    for k, ln in (("gravity", 3), ("gamma_label", 4), ("slab_lo", 3), ("slab_hi", 3)):
+        if k in d:
+            vals = list(d[k]) + [0.0] * ln
+            getattr(p, k)[:] = [float(v) for v in vals[:ln]]
+    return p
+
+
+def tiled_index(dim, n):
+    """Tiled node number of every node in natural order (x fastest), as in mpm_node_index."""
+    E = 4 if dim == 3 else 8
+    nt = n // E
+    g = np.arange(n)
+    if dim == 3:
+        k, j, i = np.meshgrid(g, g, g, indexing="ij")
+        tile = i // E + nt * (j // E + nt * (k // E))
+        loc = i % E + E * (j % E + E * (k % E))
+    else:
+        j, i = np.meshgrid(g, g, indexing="ij")
+        tile = i // E + nt * (j // E)
+        loc = i % E + E * (j % E)
+    return (tile * 64 + loc).ravel()
+
+
+def sample_surface(x, params, step=0):
+    """Host sampler (mpm_sample_surface) around positions x (N, d) float64."""
+    lib = L.load()
+    x = np.ascontiguousarray(np.asarray(x, np.float64).T)
+    dim, n = int(params["dim"]), int(params["n"])
+    N = x.shape[1]
+    lo = np.ascontiguousarray(np.asarray(list(params.get("label_lo", (0, 0, 0)))[:3] + [0] * 3, np.float64)[:3])
+    hi = np.ascontiguousarray(np.asarray(list(params.get("label_hi", (0, 0, 0)))[:3] + [0] * 3, np.float64)[:3])
+    cnt = C.c_int64(0)
+    radius = float(params.get("ls_radius") or 0.0)
+    density = float(params.get("sample_density") or 0.0)
+    seed = int(params.get("seed", 0))
+    cap = max(16, int(64 * N) + 1024)
+    for _ in range(3):
+        s = np.zeros((dim, cap))
+        dA = np.zeros((dim, cap))
+        lab = np.zeros(cap, np.int32)
+        _check(lib.mpm_sample_surface(dim, n, x.ctypes.data, N, radius, density, seed, int(step),
+                                      lo.ctypes.data, hi.ctypes.data, s.ctypes.data, dA.ctypes.data,
+                                      lab.ctypes.data, cap, C.byref(cnt)), lib)
+        if cnt.value <= cap:
+            S = cnt.value
+            return dict(s=np.ascontiguousarray(s[:, :S].T), dA=np.ascontiguousarray(dA[:, :S].T),
+                        label=lab[:S].copy())
+        cap = cnt.value
+    raise MpmError(L.MPM_ENOMEM, "sample buffer")
+
+
+class Scene:
+    """One simulation context: parameters, a device workspace and the C context."""
+
+    def __init__(self, params, cap_part, cap_surf, precision="fp64", device="cuda"):
+        import torch
+        self.torch = torch
+        self.lib = L.load()
+        self.params = dict(params)
+        self.p = make_params(params, precision)
+        self.dim, self.n = int(self.p.dim), int(self.p.n)
+        self.nn = self.n ** self.dim
+        self.dtype = torch.float64 if precision == "fp64" else torch.float32
+        self.precision = precision
+        nbytes = C.c_size_t(0)
+        _check(self.lib.mpm_workspace_bytes(C.byref(self.p), int(cap_part), int(cap_surf), C.byref(nbytes)), self.lib)
+        self.ws_bytes = nbytes.value
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device)
+        base = self.ws.data_ptr()
+        self.ws_off = (-base) % 256
+        self.ws_base = base + self.ws_off
+        ctx = C.c_void_p()
+        _check(self.lib.mpm_ctx_create(C.byref(self.p), C.c_void_p(self.ws_base), self.ws_bytes, int(cap_part),
+                                       int(cap_surf), C.byref(ctx)), self.lib)
+        self.ctx = ctx
+        self.cap_part, self.cap_surf = int(cap_part), int(cap_surf)
+        self._keep = []
+
+    def close(self):
+        if self.ctx:
+            self.lib.mpm_ctx_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, **kw):
+        self.params.update(kw)
+        prec = self.precision
+        self.p = make_params(self.params, prec)
+        _check(self.lib.mpm_ctx_set_params(self.ctx, C.byref(self.p)), self.lib, self.ctx)
+
+    # ---- marshalling ------------------------------------------------------------------
+    def stream(self):
+        return C.c_void_p(self.torch.cuda.current_stream().cuda_stream)
+
+    def particles_struct(self, P):
+        st = L.MpmParticles()
+        st.n = int(P["m"].shape[0])
+        for k in ("x", "v", "A", "J", "V0", "m", "T", "gradT"):
+            t = P[k]
+            assert t.dtype == self.dtype and t.is_contiguous() and t.is_cuda, k
+            setattr(st, k, t.data_ptr())
+        return st
+
+    def surface_struct(self, S):
+        st = L.MpmSurface()
+        if S is None:
+            st.n = 0
+            return st
+        st.n = int(S["s"].shape[1])
+        st.s = S["s"].data_ptr() if st.n else None
+        st.dA = S["dA"].data_ptr() if st.n else None
+        st.label = S["label"].data_ptr() if (st.n and S.get("label") is not None) else None
+        return st
+
+    def to_device(self, P=None, S=None):
+        """Converts natural-order numpy particle / surface dicts to SoA device tensors."""
+        torch = self.torch
+        out = []
+        if P is not None:
+            N = P["x"].shape[0]
+            d = self.dim
+            f = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=self.dtype).contiguous()
+            out.append(dict(x=f(P["x"].T), v=f(P["v"].T), A=f(P["A"].reshape(N, d * d).T), J=f(P["J"]),
+                            V0=f(P["V0"]), m=f(P["m"]), T=f(P["T"]), gradT=f(P["gradT"].T)))
+        if S is not None:
+            f = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=self.dtype).contiguous()
+            lab = S.get("label")
+            lab = np.zeros(S["s"].shape[0], np.int32) if lab is None else lab
+            out.append(dict(s=f(S["s"].T), dA=f(S["dA"].T),
+                            label=torch.from_numpy(np.ascontiguousarray(lab.astype(np.int32))).cuda()))
+        return out[0] if len(out) == 1 else tuple(out)
+
+    def grid_vector(self, ncomp=None):
+        ncomp = self.dim if ncomp is None else ncomp
+        return self.torch.zeros((ncomp, self.nn), dtype=self.dtype, device="cuda")
+
+    # ---- the ABI calls ------------------------------------------------------------------
+    def p2g(self, P, S=None):
+        self._P = self.particles_struct(P)
+        self._S = self.surface_struct(S)
+        self._keep = [P, S]
+        _check(self.lib.mpm_p2g(self.ctx, C.byref(self._P), C.byref(self._S), self.stream()), self.lib, self.ctx)
+
+    def energy_grad(self, v, grad, energy=None):
+        torch = self.torch
+        e = torch.zeros(1, dtype=torch.float64, device="cuda") if energy is None else energy
+        _check(self.lib.mpm_energy_grad(self.ctx, v.data_ptr(), e.data_ptr(), grad.data_ptr(), self.stream()),
+               self.lib, self.ctx)
+        return e
+
+    def hessvec(self, vlin, w, alpha, out):
+        _check(self.lib.mpm_hessvec(self.ctx, vlin.data_ptr(), w.data_ptr(), float(alpha), out.data_ptr(),
+                                    self.stream()), self.lib, self.ctx)
+
+    def heat_apply(self, T, out):
+        _check(self.lib.mpm_heat_apply(self.ctx, T.data_ptr(), out.data_ptr(), self.stream()), self.lib, self.ctx)
+
+    def g2p(self, vhat, That, P):
+        st = self.particles_struct(P)
+        _check(self.lib.mpm_g2p(self.ctx, vhat.data_ptr(), That.data_ptr() if That is not None else None,
+                                C.byref(st), self.stream()), self.lib, self.ctx)
+
+    def solve_momentum(self, check=True):
+        rc = self.lib.mpm_solve_momentum(self.ctx, self.stream())
+        if check:
+            _check(rc, self.lib, self.ctx)
+        return rc
+
+    def solve_heat(self, check=True):
+        rc = self.lib.mpm_solve_heat(self.ctx, self.stream())
+        if check:
+            _check(rc, self.lib, self.ctx)
+        return rc
+
+    def step(self, P, S=None, implicit=True, check=True):
+        return mpm_step([self], [P], [S], implicit=implicit, check=check)
+
+    def status(self):
+        return self.lib.mpm_scene_status(self.ctx, self.stream())
+
+    def stats(self):
+        st = L.MpmStats()
+        _check(self.lib.mpm_get_stats(self.ctx, C.byref(st)), self.lib, self.ctx)
+        out = {k: getattr(st, k) for k, _ in L.MpmStats._fields_}
+        out["momentum"] = list(st.momentum)
+        return out
+
+    def view(self, field, count=None):
+        """Workspace field as a tensor view (no copy)."""
+        torch = self.torch
+        ptr = C.c_void_p()
+        _check(self.lib.mpm_grid_view(self.ctx, int(field), C.byref(ptr)), self.lib, self.ctx)
+        off = ptr.value - self.ws.data_ptr()
+        d, nn = self.dim, self.nn
+        st = self.stats()
+        if field in (L.F_MOM, L.F_VN, L.F_VHAT, L.F_MOM_DIAG):
+            dt, shape = self.dtype, (d, nn)
+        elif field == L.F_FREE:
+            dt, shape = torch.uint8, (nn,)
+        elif field == L.F_PARENT:
+            dt, shape = torch.int32, (st["n_surf"],)
+        elif field == L.F_COUNT:
+            dt, shape = torch.int32, (st["n_part"],)
+        elif field == L.F_KSURF:
+            dt, shape = self.dtype, (st["n_surf"],)
+        else:
+            dt, shape = self.dtype, (nn,)
+        esz = torch.tensor([], dtype=dt).element_size()
+        nbytes = int(np.prod(shape)) * esz
+        return self.ws[off:off + nbytes].view(dt).view(shape)
+
+
+def mpm_step(scenes, Ps, Ss, implicit=True, check=True):
+    """mpm_step over a batch of scenes (each with its own context)."""
+    lib = L.load()
+    n = len(scenes)
+    ctxs = (C.c_void_p * n)(*[s.ctx.value for s in scenes])
+    pstructs = [s.particles_struct(P) for s, P in zip(scenes, Ps)]
+    sstructs = [s.surface_struct(S) for s, S in zip(scenes, Ss)]
+    parr = (C.POINTER(L.MpmParticles) * n)(*[C.pointer(p) for p in pstructs])
+    sarr = (C.POINTER(L.MpmSurface) * n)(*[C.pointer(p) for p in sstructs])
+    rc = lib.mpm_step(ctxs, parr, sarr, n, 1 if implicit else 0, scenes[0].stream())
+    if check:
+        _check(rc, lib, scenes[0].ctx if n == 1 else None)
+    return rc
+
+
+# C-named functional aliases
+def mpm_p2g(scene, P, S=None):
+    return scene.p2g(P, S)
+
+
+def mpm_energy_grad(scene, v, grad, energy=None):
+    return scene.energy_grad(v, grad, energy)
+
+
+def mpm_hessvec(scene, vlin, w, alpha, out):
+    return scene.hessvec(vlin, w, alpha, out)
+
+
+def mpm_heat_apply(scene, T, out):
+    return scene.heat_apply(T, out)
+
+
+def mpm_g2p(scene, vhat, That, P):
+    return scene.g2p(vhat, That, P)

@@ -1,0 +1,180 @@
+// Shared device helpers of the MPM hot path: node/cell tiling, the quadratic B-spline in
+// cell-relative form, wave-shuffle reductions and the status word.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mpm.h"
+
+#define MPM_DEV __device__ __forceinline__
+#define MPM_HD __host__ __device__ __forceinline__
+
+namespace mpm {
+
+constexpr int kTileNodes = 64;   // nodes per tile: 4x4x4 (3D) or 8x8 (2D)
+constexpr int kMaxPartials = 1024;
+constexpr int kWave = 64;
+
+template <int D> struct Tiling;
+template <> struct Tiling<3> { static constexpr int E = 4; static constexpr int LOG = 2; };
+template <> struct Tiling<2> { static constexpr int E = 8; static constexpr int LOG = 3; };
+
+// Index of node / cell (i0,i1,i2) in tile-major order (include/mpm.h, mpm_node_index).
+template <int D>
+MPM_HD int64_t tiled_index(const int* i, int nt) {
+  constexpr int E = Tiling<D>::E, L = Tiling<D>::LOG;
+  int64_t tile = (i[0] >> L) + (int64_t)nt * ((i[1] >> L) + (D == 3 ? (int64_t)nt * (i[2] >> L) : 0));
+  int local = (i[0] & (E - 1)) + E * ((i[1] & (E - 1)) + (D == 3 ? E * (i[2] & (E - 1)) : 0));
+  return tile * kTileNodes + local;
+}
+
+// Multi-index of node number tile*64+local.
+template <int D>
+MPM_HD void tiled_coords(int64_t tile, int local, int nt, int* i) {
+  constexpr int E = Tiling<D>::E, L = Tiling<D>::LOG;
+  int64_t t0 = tile % nt;
+  int64_t rest = tile / nt;
+  i[0] = (int)(t0 << L) + (local & (E - 1));
+  if (D == 3) {
+    int64_t t1 = rest % nt, t2 = rest / nt;
+    i[1] = (int)(t1 << L) + ((local >> L) & (E - 1));
+    i[2] = (int)(t2 << L) + (local >> (2 * L));
+  } else {
+    i[1] = (int)(rest << L) + (local >> L);
+  }
+}
+
+// Quadratic B-spline at cell-centred nodes, in the cell-relative variable f = x/dx - c,
+// c = floor(x/dx), f in [0,1).  The point's 3^D stencil is nodes c-1+k, k = 0,1,2, with
+// 1D weights  k=0: (1-f)^2/2,  k=1: 3/4 - (f-1/2)^2,  k=2: f^2/2
+// and derivatives (per dx)  -(1-f),  1-2f,  f.  (Same kernel as N(u) of Section 4.2 with
+// u = f + 1/2 - k.)
+template <typename R>
+MPM_DEV R bs_w(int k, R f) {
+  return k == 0 ? R(0.5) * (R(1) - f) * (R(1) - f)
+       : (k == 1 ? R(0.75) - (f - R(0.5)) * (f - R(0.5)) : R(0.5) * f * f);
+}
+template <typename R>
+MPM_DEV R bs_dw(int k, R f) {
+  return k == 0 ? f - R(1) : (k == 1 ? R(1) - R(2) * f : f);
+}
+
+template <int D, typename R>
+struct Stencil {
+  int c[D];        // cell of the point
+  R f[D];          // cell-relative position
+  R w[D][3];       // 1D weights of nodes c-1+k
+  R dw[D][3];      // 1D derivatives, already divided by dx
+};
+
+// Cell and cell-relative coordinate of a position.  Positions outside [dx, 1-dx) are
+// clamped (so every access stays inside the grid) and reported through *bad.
+template <int D, typename R>
+MPM_DEV void locate(const R* x, int n, R fn, int* c, R* f, bool* bad) {
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    R xs = x[a] * fn;
+    R cf = floor(xs);
+    bool ok = (xs >= R(1)) && (xs < R(n - 1));   // also false for NaN
+    if (!ok) { *bad = true; cf = xs < R(1) || !(xs == xs) ? R(1) : R(n - 2); xs = cf; }
+    c[a] = (int)cf;
+    f[a] = xs - cf;
+  }
+}
+
+template <int D, typename R>
+MPM_DEV void make_stencil(const R* x, int n, R fn, Stencil<D, R>& s, bool* bad) {
+  locate<D, R>(x, n, fn, s.c, s.f, bad);
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      s.w[a][k] = bs_w<R>(k, s.f[a]);
+      s.dw[a][k] = bs_dw<R>(k, s.f[a]) * fn;
+    }
+  }
+}
+
+// Loop over the 3^D stencil offsets, k0 fastest.
+template <int D, class F>
+MPM_DEV void for_stencil(F&& fn) {
+  if constexpr (D == 3) {
+#pragma unroll
+    for (int k2 = 0; k2 < 3; ++k2)
+#pragma unroll
+      for (int k1 = 0; k1 < 3; ++k1)
+#pragma unroll
+        for (int k0 = 0; k0 < 3; ++k0) fn(k0, k1, k2);
+  } else {
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1)
+#pragma unroll
+      for (int k0 = 0; k0 < 3; ++k0) fn(k0, k1, 0);
+  }
+}
+
+// Weight and gradient of stencil node (k0,k1,k2).
+template <int D, typename R>
+MPM_DEV R node_weight(const Stencil<D, R>& s, int k0, int k1, int k2, R* g) {
+  if constexpr (D == 3) {
+    R wx = s.w[0][k0], wy = s.w[1][k1], wz = s.w[2][k2];
+    g[0] = s.dw[0][k0] * wy * wz;
+    g[1] = wx * s.dw[1][k1] * wz;
+    g[2] = wx * wy * s.dw[2][k2];
+    return wx * wy * wz;
+  } else {
+    R wx = s.w[0][k0], wy = s.w[1][k1];
+    g[0] = s.dw[0][k0] * wy;
+    g[1] = wx * s.dw[1][k1];
+    return wx * wy;
+  }
+}
+
+// Weight and gradient of node i for a point in cell c with cell-relative f (node-gather
+// form: k_a = i_a - c_a + 1 in {0,1,2}).
+template <int D, typename R>
+MPM_DEV R weight_from_cell(const int* k, const R* f, R fn, R* g) {
+  R w[D], dw[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) { w[a] = bs_w<R>(k[a], f[a]); dw[a] = bs_dw<R>(k[a], f[a]) * fn; }
+  if constexpr (D == 3) {
+    g[0] = dw[0] * w[1] * w[2];
+    g[1] = w[0] * dw[1] * w[2];
+    g[2] = w[0] * w[1] * dw[2];
+    return w[0] * w[1] * w[2];
+  } else {
+    g[0] = dw[0] * w[1];
+    g[1] = w[0] * dw[1];
+    return w[0] * w[1];
+  }
+}
+
+// ---- deterministic reductions -------------------------------------------------------
+MPM_DEV double wave_sum(double v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_down(v, o, kWave);
+  return v;
+}
+
+// Sum over the block (fixed order: lanes by shuffle tree, then waves in index order).
+// Result valid in thread 0.  sh must hold blockDim/64 doubles.
+MPM_DEV double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = 0;
+  if (threadIdx.x == 0) {
+    int nw = (blockDim.x + kWave - 1) / kWave;
+    for (int k = 0; k < nw; ++k) r += sh[k];
+  }
+  return r;
+}
+
+// Latched device status word bits.
+enum : int { ST_DOMAIN = 1, ST_NONFINITE = 2, ST_NOCONV = 4 };
+
+MPM_DEV void flag_status(int* st, int bit) { atomicOr(st, bit); }
+
+}  // namespace mpm

@@ -1,0 +1,1357 @@
+// Device kernels of the MPM hot path.  Every kernel is deterministic: integer atomics
+// only build counts and slots (followed by an order fix-up), and every floating-point sum
+// runs in a fixed order (node-owner gathers over cell-sorted points, fixed-tree block
+// reductions, single-block final reductions).
+#pragma once
+#include "common.h"
+
+namespace mpm {
+
+// Device view of one scene's workspace.  R is double (FP64) or float (MIXED).
+template <typename R>
+struct Dev {
+  // grid
+  int n, nt, nn;
+  R fn, dx, dt;
+  // parameters
+  R lam, mu0, mu_k, mu_T0, g0, g1, gT0, gmin, gmax, cp, K, h, T_amb, b, H;
+  R gamma_label[4];
+  R grav[3];
+  R slab_lo[3], slab_hi[3];
+  int slab, slab_axis, wall, term_mask, exact, gamma_by_label;
+  // point counts
+  int np, ns;
+  // interior particles, cell-sorted
+  int* p_start; int* p_perm; int* p_key;
+  R *px, *pv, *pA, *pm, *pmt, *pJ, *pV0, *pT, *pgT, *pmu, *pVn, *pS;
+  int* pcnt; int* pcnt_orig; int* grp_start; int* grp; int* gcur;
+  // surface samples, cell-sorted
+  int* s_start; int* s_perm; int* s_key;
+  R *ss, *sdA, *sk, *sk_orig, *sS, *sc;
+  int* slabel; int* spar; int* s_parent_orig;
+  // balance points, cell-sorted
+  int* b_start; int* b_src; int* b_key; R* bx; R* bx_unsorted;
+  // scratch per cell
+  int* ccount;
+  // grid fields
+  R *gm, *gmv, *gW, *gWT, *gE, *gET, *gvn, *gTn, *gdiag, *hdiag, *hrhs;
+  uint8_t* gfree;
+  // tiles
+  int* tile_flag; int* tile_list;
+  // status, reductions
+  int* status;
+  double* part;
+  double* scal;
+};
+
+constexpr int kPartSlot = 1 << 18;  // partial sums per reduction slot
+
+// ======================================================================================
+// Cell sort: keys, counts, slots, per-cell order fix-up.
+// ======================================================================================
+template <int D, typename R>
+__global__ void k_cell_keys(const R* pos, int cnt, int n, int nt, R fn, int* key, int* ccount,
+                            int* status) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  R x[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) x[a] = pos[(int64_t)a * cnt + i];
+  int c[D]; R f[D]; bool bad = false;
+  locate<D, R>(x, n, fn, c, f, &bad);
+  if (bad) flag_status(status, ST_DOMAIN);
+  int k = (int)tiled_index<D>(c, nt);
+  key[i] = k;
+  atomicAdd(&ccount[k], 1);
+}
+
+constexpr int kScanT = 256, kScanI = 16, kScanBlock = kScanT * kScanI;
+
+// Exclusive scan of in[0,len) into out[0,len), block totals into bsum.
+__global__ void k_scan_local(const int* in, int* out, int len, int* bsum) {
+  __shared__ int sh[kScanT];
+  int base = blockIdx.x * kScanBlock + threadIdx.x * kScanI;
+  int v[kScanI];
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanI; ++k) {
+    int idx = base + k;
+    v[k] = idx < len ? in[idx] : 0;
+    s += v[k];
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < kScanT; off <<= 1) {      // Hillis-Steele inclusive scan
+    int t = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += t;
+    __syncthreads();
+  }
+  int run = sh[threadIdx.x] - s;
+#pragma unroll
+  for (int k = 0; k < kScanI; ++k) {
+    int idx = base + k;
+    if (idx < len) out[idx] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == kScanT - 1) bsum[blockIdx.x] = sh[kScanT - 1];
+}
+
+// Single block: exclusive scan of bsum[0,nb) in place; total -> *total.
+__global__ void k_scan_sums(int* bsum, int nb, int* total) {
+  __shared__ int sh[kScanT];
+  int base = threadIdx.x * kScanI;
+  int v[kScanI];
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanI; ++k) {
+    int idx = base + k;
+    v[k] = idx < nb ? bsum[idx] : 0;
+    s += v[k];
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < kScanT; off <<= 1) {
+    int t = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += t;
+    __syncthreads();
+  }
+  int run = sh[threadIdx.x] - s;
+#pragma unroll
+  for (int k = 0; k < kScanI; ++k) {
+    int idx = base + k;
+    if (idx < nb) bsum[idx] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == kScanT - 1) *total = sh[kScanT - 1];
+}
+
+__global__ void k_scan_add(int* out, int len, const int* bsum) {
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= len) return;
+  out[idx] += bsum[idx / kScanBlock];
+}
+
+// slot = start[key] + (remaining count - 1); leaves ccount at zero.
+__global__ void k_cell_scatter(const int* key, int cnt, const int* start, int* ccount, int* perm) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  int k = key[i];
+  int slot = start[k] + atomicSub(&ccount[k], 1) - 1;
+  perm[slot] = i;
+}
+
+// Sort each segment [start[c], start[c+1]) of vals ascending (insertion sort; segments
+// hold a handful of items).  Makes the slot order independent of atomic arrival order.
+__global__ void k_segment_order(const int* start, int nseg, int* vals) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nseg) return;
+  int b = start[c], e = start[c + 1];
+  for (int i = b + 1; i < e; ++i) {
+    int v = vals[i];
+    int j = i - 1;
+    while (j >= b && vals[j] > v) { vals[j + 1] = vals[j]; --j; }
+    vals[j + 1] = v;
+  }
+}
+
+__global__ void k_fill_i32(int* p, int v, int64_t len) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) p[i] = v;
+}
+
+template <typename R>
+__global__ void k_fill_r(R* p, R v, int64_t len) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) p[i] = v;
+}
+
+// ======================================================================================
+// Particle and sample staging in cell order.
+// ======================================================================================
+template <int D, typename R>
+__global__ void k_gather_particles(Dev<R> d, const R* x, const R* v, const R* A, const R* J,
+                                   const R* V0, const R* m, const R* T, const R* gT) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  int N = d.np;
+  if (k >= N) return;
+  int i = d.p_perm[k];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    d.px[a * N + k] = x[a * N + i];
+    d.pv[a * N + k] = v[a * N + i];
+    d.pgT[a * N + k] = gT[a * N + i];
+  }
+#pragma unroll
+  for (int a = 0; a < D * D; ++a) d.pA[a * N + k] = A[a * N + i];
+  R Jk = J[i], V0k = V0[i], Tk = T[i];
+  d.pJ[k] = Jk;
+  d.pV0[k] = V0k;
+  d.pm[k] = m[i];
+  d.pT[k] = Tk;
+  d.pVn[k] = Jk * V0k;
+  d.pmu[k] = d.mu0 == R(0) ? R(0) : d.mu0 * exp(-d.mu_k * (Tk - d.mu_T0));
+  d.pcnt[k] = 0;
+}
+
+template <int D, typename R>
+__global__ void k_gather_surface(Dev<R> d, const R* s, const R* dA, const int* label) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  int S = d.ns;
+  if (k >= S) return;
+  int i = d.s_perm[k];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    d.ss[a * S + k] = s[a * S + i];
+    d.sdA[a * S + k] = dA[a * S + i];
+  }
+  d.slabel[k] = label ? label[i] : 0;
+}
+
+// Squared distance in double with separate roundings (no contraction), summed axis by
+// axis: the same arithmetic any reference evaluating ((d0^2 + d1^2) + d2^2) performs.
+template <int D>
+MPM_DEV double dist2_exact(const double* a, const double* b) {
+  double acc = __dmul_rn(a[0] - b[0], a[0] - b[0]);
+#pragma unroll
+  for (int k = 1; k < D; ++k) acc = __dadd_rn(acc, __dmul_rn(a[k] - b[k], a[k] - b[k]));
+  return acc;
+}
+
+// Nearest interior particle of each sample (Section 4.1.2); ties to the lower input
+// index.  Searches the cells within 2, then 3 cells of the sample; a winner closer than
+// the searched radius is exact.  Otherwise falls back to a scan of all particles.
+template <int D, typename R>
+__global__ void k_parents(Dev<R> d) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  int S = d.ns, N = d.np;
+  if (r >= S) return;
+  double sd[D];
+  R sr[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) { sr[a] = d.ss[a * S + r]; sd[a] = (double)sr[a]; }
+  int c[D]; R f[D]; bool bad = false;
+  locate<D, R>(sr, d.n, d.fn, c, f, &bad);
+  double best = 1e300;
+  int bk = -1, borig = 0x7fffffff;
+  auto visit = [&](int k) {
+    double xp[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) xp[a] = (double)d.px[a * N + k];
+    double d2 = dist2_exact<D>(sd, xp);
+    int o = d.p_perm[k];
+    if (d2 < best || (d2 == best && o < borig)) { best = d2; bk = k; borig = o; }
+  };
+  double dxd = (double)d.dx;
+  for (int rad = 2; rad <= 3; ++rad) {
+    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < D; ++a) { lo[a] = max(c[a] - rad, 0); hi[a] = min(c[a] + rad, d.n - 1); }
+    for (int z = (D == 3 ? lo[2] : 0); z <= (D == 3 ? hi[2] : 0); ++z)
+      for (int y = lo[1]; y <= hi[1]; ++y)
+        for (int x = lo[0]; x <= hi[0]; ++x) {
+          int cc[3] = {x, y, z};
+          int ci = (int)tiled_index<D>(cc, d.nt);
+          for (int k = d.p_start[ci]; k < d.p_start[ci + 1]; ++k) visit(k);
+        }
+    if (best < (rad * dxd) * (rad * dxd)) break;
+    if (rad == 3) {
+      best = 1e300; bk = -1; borig = 0x7fffffff;
+      for (int k = 0; k < N; ++k) visit(k);
+    }
+  }
+  if (bk < 0) { flag_status(d.status, ST_DOMAIN); bk = 0; borig = d.p_perm[0]; }
+  d.spar[r] = bk;
+  d.s_parent_orig[d.s_perm[r]] = borig;
+  atomicAdd(&d.pcnt[bk], 1);
+}
+
+// m~_p = m_p / (2 |Pi_p| + 1) (Section 4.1.3); cursor copy for the group CSR.
+template <typename R>
+__global__ void k_split_mass(Dev<R> d) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= d.np) return;
+  int c = d.pcnt[k];
+  d.pmt[k] = d.pm[k] / (R(2) * R(c) + R(1));
+  d.gcur[k] = c;
+  d.pcnt_orig[d.p_perm[k]] = c;
+}
+
+// Balance point b_r = s_r + 2 (x_p(r) - s_r) (eq. pbal), in sample order; group slots.
+template <int D, typename R>
+__global__ void k_balance(Dev<R> d) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  int S = d.ns, N = d.np;
+  if (r >= S) return;
+  int p = d.spar[r];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    R s = d.ss[a * S + r];
+    d.bx_unsorted[a * S + r] = s + R(2) * (d.px[a * N + p] - s);
+  }
+  int slot = d.grp_start[p] + atomicSub(&d.gcur[p], 1) - 1;
+  d.grp[slot] = r;
+}
+
+template <int D, typename R>
+__global__ void k_gather_balance(Dev<R> d) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  int S = d.ns;
+  if (k >= S) return;
+  int r = d.b_src[k];
+#pragma unroll
+  for (int a = 0; a < D; ++a) d.bx[a * S + k] = d.bx_unsorted[a * S + r];
+}
+
+// Marks the tiles that hold a node of any occupied cell's stencil.
+template <int D, typename R>
+__global__ void k_mark_tiles(Dev<R> d) {
+  int ci = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ci >= d.nn) return;
+  int occ = (d.p_start[ci + 1] - d.p_start[ci]) + (d.ns ? (d.s_start[ci + 1] - d.s_start[ci]) + (d.b_start[ci + 1] - d.b_start[ci]) : 0);
+  if (occ == 0) return;
+  int c[3] = {0, 0, 0};
+  tiled_coords<D>(ci / kTileNodes, ci % kTileNodes, d.nt, c);
+  constexpr int L = Tiling<D>::LOG;
+  int tlo[3] = {0, 0, 0}, thi[3] = {0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    tlo[a] = max(c[a] - 1, 0) >> L;
+    thi[a] = min(c[a] + 1, d.n - 1) >> L;
+  }
+  for (int t2 = tlo[2]; t2 <= thi[2]; ++t2)
+    for (int t1 = tlo[1]; t1 <= thi[1]; ++t1)
+      for (int t0 = tlo[0]; t0 <= thi[0]; ++t0) {
+        int t = t0 + d.nt * (t1 + (D == 3 ? d.nt * t2 : 0));
+        d.tile_flag[t] = 1;
+      }
+}
+
+__global__ void k_compact_tiles(const int* flag, const int* pos, int ntile, int* list) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < ntile && flag[t]) list[pos[t]] = t;
+}
+
+// Zeroes every grid field on the listed tiles and clears their flags.
+template <int D, typename R>
+__global__ void k_clear_tiles(Dev<R> d, const int* list, R* const* extra, int nextra, int ncomp_extra) {
+  int t = list[blockIdx.x];
+  int node = t * kTileNodes + threadIdx.x;
+  int nn = d.nn;
+  d.gm[node] = 0; d.gW[node] = 0; d.gWT[node] = 0; d.gE[node] = 0; d.gET[node] = 0;
+  d.gTn[node] = 0; d.hdiag[node] = 0; d.hrhs[node] = 0; d.gfree[node] = 0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    d.gmv[a * nn + node] = 0; d.gvn[a * nn + node] = 0; d.gdiag[a * nn + node] = 0;
+  }
+  for (int e = 0; e < nextra; ++e)
+    for (int a = 0; a < ncomp_extra; ++a) extra[e][a * nn + node] = 0;
+  if (threadIdx.x == 0) d.tile_flag[t] = 0;
+}
+
+// ======================================================================================
+// P2G (Section 4.2) with the grid set-up fused: one thread per node of the active tiles
+// gathers, in fixed cell order, every interior particle, surface sample and balance point
+// whose stencil holds the node.
+// ======================================================================================
+template <int D, typename R>
+__global__ void __launch_bounds__(64) k_p2g_nodes(Dev<R> d) {
+  int t = d.tile_list[blockIdx.x];
+  int lane = threadIdx.x;
+  int node = t * kTileNodes + lane;
+  int i[3] = {0, 0, 0};
+  tiled_coords<D>(t, lane, d.nt, i);
+  const int N = d.np, S = d.ns, nn = d.nn;
+  R m = 0, W = 0, WT = 0, E = 0, ET = 0, hdg = 0, hsrc = 0, hrob = 0;
+  R mv[D], dg[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) { mv[a] = 0; dg[a] = 0; }
+  const bool useJ = d.term_mask & 1, useV = d.term_mask & 4;
+  const R dt = d.dt;
+  for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dxo = -1; dxo <= 1; ++dxo) {
+        int c[3] = {i[0] + dxo, i[1] + dy, i[2] + dz};
+        int off[3] = {dxo, dy, dz};
+        bool in = true;
+#pragma unroll
+        for (int a = 0; a < D; ++a) in = in && c[a] >= 0 && c[a] < d.n;
+        if (!in) continue;
+        int ci = (int)tiled_index<D>(c, d.nt);
+        int kk[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) kk[a] = 1 - off[a];
+        // interior particles
+        for (int k = d.p_start[ci]; k < d.p_start[ci + 1]; ++k) {
+          R f[D], rel[D], g[D];
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            f[a] = d.px[a * N + k] * d.fn - R(c[a]);
+            rel[a] = (R(0.5) - R(off[a]) - f[a]) * d.dx;      // x_i - x_p, node i = cell - off
+          }
+          R Nw = weight_from_cell<D, R>(kk, f, d.fn, g);
+          R mt = d.pmt[k], mp = d.pm[k];
+          R w = mt * Nw;
+          m += w;
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            R va = d.pv[a * N + k];
+#pragma unroll
+            for (int b2 = 0; b2 < D; ++b2) va += d.pA[(a * D + b2) * N + k] * rel[b2];
+            mv[a] += w * va;
+          }
+          R Tq = d.pT[k];
+#pragma unroll
+          for (int a = 0; a < D; ++a) Tq += rel[a] * d.pgT[a * N + k];
+          W += mp * Nw;
+          WT += mp * Nw * Tq;
+          R g2 = 0;
+#pragma unroll
+          for (int a = 0; a < D; ++a) g2 += g[a] * g[a];
+          R Jn = d.pJ[k], Vn = d.pVn[k];
+          R cJ = useJ ? dt * dt * d.lam * d.pV0[k] * Jn * Jn : R(0);
+          R cV = useV ? dt * d.pmu[k] * Vn : R(0);
+#pragma unroll
+          for (int a = 0; a < D; ++a) dg[a] += cJ * g[a] * g[a] + cV * (R(0.5) * g2 + R(0.5) * g[a] * g[a]);
+          hdg += d.K * Vn * g2;
+          hsrc += Nw * d.H * Vn;
+        }
+        if (S == 0) continue;
+        // surface samples (Sections 4.1.3, 4.2, 4.3.2)
+        for (int r = d.s_start[ci]; r < d.s_start[ci + 1]; ++r) {
+          R f[D], rel[D], g[D];
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            f[a] = d.ss[a * S + r] * d.fn - R(c[a]);
+            rel[a] = (R(0.5) - R(off[a]) - f[a]) * d.dx;
+          }
+          R Nw = weight_from_cell<D, R>(kk, f, d.fn, g);
+          int p = d.spar[r];
+          R w = d.pmt[p] * Nw;
+          m += w;
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            R va = d.pv[a * N + p];
+#pragma unroll
+            for (int b2 = 0; b2 < D; ++b2) va += d.pA[(a * D + b2) * N + p] * rel[b2];
+            mv[a] += w * va;
+          }
+          E += w;
+          ET += w * d.pT[p];
+          R area = 0;
+#pragma unroll
+          for (int a = 0; a < D; ++a) area += d.sdA[a * S + r] * d.sdA[a * S + r];
+          area = sqrt(area);
+          hdg += d.h * area * Nw * Nw;
+          hrob += Nw * (d.h * d.T_amb + d.b) * area;
+        }
+        // balance points
+        for (int q = d.b_start[ci]; q < d.b_start[ci + 1]; ++q) {
+          R f[D], rel[D], g[D];
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            f[a] = d.bx[a * S + q] * d.fn - R(c[a]);
+            rel[a] = (R(0.5) - R(off[a]) - f[a]) * d.dx;
+          }
+          R Nw = weight_from_cell<D, R>(kk, f, d.fn, g);
+          int p = d.spar[d.b_src[q]];
+          R w = d.pmt[p] * Nw;
+          m += w;
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            R va = d.pv[a * N + p];
+#pragma unroll
+            for (int b2 = 0; b2 < D; ++b2) va += d.pA[(a * D + b2) * N + p] * rel[b2];
+            mv[a] += w * va;
+          }
+          E += w;
+          ET += w * d.pT[p];
+        }
+      }
+  // grid set-up
+  bool dof = m > R(0);
+  d.gm[node] = m; d.gW[node] = W; d.gWT[node] = WT; d.gE[node] = E; d.gET[node] = ET;
+  R Tn = W > R(0) ? WT / W : (E > R(0) ? ET / E : R(0));
+  d.gTn[node] = dof ? Tn : R(0);
+  uint8_t fr = dof ? 0x80 : 0;
+  R xi[3];
+#pragma unroll
+  for (int a = 0; a < D; ++a) xi[a] = (R(i[a]) + R(0.5)) * d.dx;
+  bool in_slab = d.slab != 0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) in_slab = in_slab && xi[a] >= d.slab_lo[a] && xi[a] < d.slab_hi[a];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    bool wall = d.wall > 0 && (i[a] < d.wall || i[a] >= d.n - d.wall);
+    bool fixed = wall || (in_slab && a == d.slab_axis);
+    bool fa = dof && !fixed;
+    if (fa) fr |= (uint8_t)(1u << a);
+    d.gmv[a * nn + node] = mv[a];
+    d.gvn[a * nn + node] = dof ? mv[a] / m : R(0);
+    d.gdiag[a * nn + node] = fa ? m + dg[a] : R(1);
+  }
+  d.gfree[node] = fr;
+  R cm = d.cp / dt * m;
+  d.hdiag[node] = dof ? cm + hdg : R(1);
+  d.hrhs[node] = dof ? cm * Tn + hrob + hsrc : R(0);
+}
+
+// k_r = gamma(T^s_r), T^s_r = sum_i N_i(s_r) T^n_i (Section 4.3.1), or by label (Sec. 3.6).
+template <int D, typename R>
+__global__ void k_surface_k(Dev<R> d) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  int S = d.ns;
+  if (r >= S) return;
+  R kr;
+  if (d.gamma_by_label) {
+    int l = d.slabel[r];
+    kr = d.gamma_label[l & 3];
+  } else {
+    R x[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) x[a] = d.ss[a * S + r];
+    Stencil<D, R> st; bool bad = false;
+    make_stencil<D, R>(x, d.n, d.fn, st, &bad);
+    R Ts = 0;
+    for_stencil<D>([&](int k0, int k1, int k2) {
+      int nd[3] = {st.c[0] - 1 + k0, st.c[1] - 1 + k1, D == 3 ? st.c[2] - 1 + k2 : 0};
+      R g[D];
+      R Nw = node_weight<D, R>(st, k0, k1, k2, g);
+      Ts += Nw * d.gTn[tiled_index<D>(nd, d.nt)];
+    });
+    kr = d.g0 + d.g1 * (Ts - d.gT0);
+    kr = kr < d.gmin ? d.gmin : (kr > d.gmax ? d.gmax : kr);
+  }
+  d.sk[r] = kr;
+  d.sk_orig[d.s_perm[r]] = kr;
+}
+
+// ======================================================================================
+// Energy, gradient and Hessian-vector product (Section 4.3.1).  Point phase: every
+// quadrature point gathers the velocity (or direction) gradient from its stencil and
+// forms a stress-like matrix S_q; node phase: every node gathers sum_q S_q grad N_i(x_q).
+// ======================================================================================
+enum PointMode { PM_ENERGY = 0, PM_HESS = 1 };
+
+// Gradient sum_j u_j (x) grad N_j at a stencil; optional projection by the free mask.
+template <int D, typename R>
+MPM_DEV void gather_grad(const Dev<R>& d, const Stencil<D, R>& st, const R* u, bool mask, R (&G)[D][D]) {
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) G[a][b] = 0;
+  for_stencil<D>([&](int k0, int k1, int k2) {
+    int nd[3] = {st.c[0] - 1 + k0, st.c[1] - 1 + k1, D == 3 ? st.c[2] - 1 + k2 : 0};
+    int node = (int)tiled_index<D>(nd, d.nt);
+    R g[D];
+    node_weight<D, R>(st, k0, k1, k2, g);
+    uint8_t fr = mask ? d.gfree[node] : 0xff;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      R ua = (fr >> a) & 1 ? u[a * d.nn + node] : R(0);
+#pragma unroll
+      for (int b = 0; b < D; ++b) G[a][b] += ua * g[b];
+    }
+  });
+}
+
+// Interior particles: J-term and viscosity.
+template <int D, typename R>
+__global__ void k_points_interior(Dev<R> d, const R* u, int mode, int mask_in, const int* done,
+                                  int part_slot) {
+  __shared__ double sh[16];
+  if (done && *done) return;
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int N = d.np;
+  double e = 0;
+  if (k < N) {
+    R x[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) x[a] = d.px[a * N + k];
+    Stencil<D, R> st; bool bad = false;
+    make_stencil<D, R>(x, d.n, d.fn, st, &bad);
+    R G[D][D];
+    gather_grad<D, R>(d, st, u, mask_in, G);
+    R S[D][D];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int b = 0; b < D; ++b) S[a][b] = 0;
+    R tr = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) tr += G[a][a];
+    const R dt = d.dt, Jn = d.pJ[k], V0 = d.pV0[k];
+    if (d.term_mask & 1) {
+      R s;
+      if (mode == PM_ENERGY) {
+        R Jm1 = (R(1) + dt * tr) * Jn - R(1);
+        e += (double)(R(0.5) * d.lam * Jm1 * Jm1 * V0);
+        s = dt * d.lam * V0 * Jn * Jm1;
+      } else {
+        s = dt * dt * d.lam * V0 * Jn * Jn * tr;
+      }
+#pragma unroll
+      for (int a = 0; a < D; ++a) S[a][a] += s;
+    }
+    if (d.term_mask & 4) {
+      R cV = dt * d.pmu[k] * d.pVn[k];
+      R ee = 0;
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+          R eps = R(0.5) * (G[a][b] + G[b][a]);
+          S[a][b] += cV * eps;
+          ee += eps * eps;
+        }
+      if (mode == PM_ENERGY) e += (double)(R(0.5) * cV * ee);   // dt * D_p
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int b = 0; b < D; ++b) d.pS[(a * D + b) * N + k] = S[a][b];
+  }
+  if (mode == PM_ENERGY) {
+    double bsum = block_sum(e, sh);
+    if (threadIdx.x == 0) d.part[part_slot * kPartSlot + blockIdx.x] = bsum;
+  }
+}
+
+// cof(F) N with cof(F) column m = f_{m+1} x f_{m+2} (3D) or R F R^T (2D).
+template <int D, typename R>
+MPM_DEV void cof_normal(const R (&F)[D][D], const R* Nv, R* a) {
+  if constexpr (D == 3) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a[c] = 0;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      int p = (m + 1) % 3, q = (m + 2) % 3;
+      // column m of cof(F) = column p x column q
+      R cx = F[1][p] * F[2][q] - F[2][p] * F[1][q];
+      R cy = F[2][p] * F[0][q] - F[0][p] * F[2][q];
+      R cz = F[0][p] * F[1][q] - F[1][p] * F[0][q];
+      a[0] += cx * Nv[m]; a[1] += cy * Nv[m]; a[2] += cz * Nv[m];
+    }
+  } else {
+    a[0] = F[1][1] * Nv[0] - F[1][0] * Nv[1];
+    a[1] = -F[0][1] * Nv[0] + F[0][0] * Nv[1];
+  }
+}
+
+template <typename R>
+MPM_DEV void cross3(const R* u, const R* v, R* w) {
+  w[0] = u[1] * v[2] - u[2] * v[1];
+  w[1] = u[2] * v[0] - u[0] * v[2];
+  w[2] = u[0] * v[1] - u[1] * v[0];
+}
+
+// Surface samples: e_sigma = k |cof(F) dA|, its derivative Q and its linearization.
+template <int D, typename R>
+__global__ void k_points_surface(Dev<R> d, const R* vlin, const R* u, int mode, int mask_in,
+                                 const int* done, int part_slot) {
+  __shared__ double sh[16];
+  if (done && *done) return;
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int S = d.ns;
+  double e = 0;
+  if (r < S && (d.term_mask & 2)) {
+    R x[D], Nv[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) { x[a] = d.ss[a * S + r]; Nv[a] = d.sdA[a * S + r]; }
+    Stencil<D, R> st; bool bad = false;
+    make_stencil<D, R>(x, d.n, d.fn, st, &bad);
+    const R dt = d.dt, kr = d.sk[r];
+    R F[D][D];
+    gather_grad<D, R>(d, st, vlin, false, F);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+#pragma unroll
+      for (int b = 0; b < D; ++b) F[a][b] *= dt;
+      F[a][a] += R(1);
+    }
+    R av[D];
+    cof_normal<D, R>(F, Nv, av);
+    R an = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) an += av[a] * av[a];
+    an = sqrt(an);
+    R ah[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) ah[a] = av[a] / an;
+    R Q[D][D];
+    if (mode == PM_ENERGY) {
+      e = (double)(kr * an);
+      if constexpr (D == 3) {
+        for (int m = 0; m < 3; ++m) {
+          R gp[3] = {F[0][(m + 1) % 3], F[1][(m + 1) % 3], F[2][(m + 1) % 3]};
+          R gq[3] = {F[0][(m + 2) % 3], F[1][(m + 2) % 3], F[2][(m + 2) % 3]};
+          R c1[3], c2[3];
+          cross3<R>(gp, ah, c1);
+          cross3<R>(ah, gq, c2);
+          for (int a = 0; a < 3; ++a) Q[a][m] = Nv[(m + 2) % 3] * c1[a] + Nv[(m + 1) % 3] * c2[a];
+        }
+      } else {
+        R tau[2] = {Nv[1], -Nv[0]};
+        R cvec[2] = {F[0][0] * tau[0] + F[0][1] * tau[1], F[1][0] * tau[0] + F[1][1] * tau[1]};
+        R cn = sqrt(cvec[0] * cvec[0] + cvec[1] * cvec[1]);
+        for (int a = 0; a < 2; ++a)
+          for (int b = 0; b < 2; ++b) Q[a][b] = cvec[a] / cn * tau[b];
+      }
+    } else {
+      R dG[D][D];
+      gather_grad<D, R>(d, st, u, mask_in, dG);
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = 0; b < D; ++b) dG[a][b] *= dt;
+      if constexpr (D == 3) {
+        R da[3] = {0, 0, 0};
+        for (int k = 0; k < 3; ++k) {
+          R dg1[3] = {dG[0][(k + 1) % 3], dG[1][(k + 1) % 3], dG[2][(k + 1) % 3]};
+          R dg2[3] = {dG[0][(k + 2) % 3], dG[1][(k + 2) % 3], dG[2][(k + 2) % 3]};
+          R g1[3] = {F[0][(k + 1) % 3], F[1][(k + 1) % 3], F[2][(k + 1) % 3]};
+          R g2[3] = {F[0][(k + 2) % 3], F[1][(k + 2) % 3], F[2][(k + 2) % 3]};
+          R c1[3], c2[3];
+          cross3<R>(dg1, g2, c1);
+          cross3<R>(g1, dg2, c2);
+          for (int a = 0; a < 3; ++a) da[a] += Nv[k] * (c1[a] + c2[a]);
+        }
+        R ad = ah[0] * da[0] + ah[1] * da[1] + ah[2] * da[2];
+        R uu[3];
+        for (int a = 0; a < 3; ++a) uu[a] = (da[a] - ah[a] * ad) / an;
+        for (int m = 0; m < 3; ++m) {
+          R gp[3] = {F[0][(m + 1) % 3], F[1][(m + 1) % 3], F[2][(m + 1) % 3]};
+          R gq[3] = {F[0][(m + 2) % 3], F[1][(m + 2) % 3], F[2][(m + 2) % 3]};
+          R c1[3], c2[3];
+          cross3<R>(gp, uu, c1);
+          cross3<R>(uu, gq, c2);
+          for (int a = 0; a < 3; ++a) Q[a][m] = Nv[(m + 2) % 3] * c1[a] + Nv[(m + 1) % 3] * c2[a];
+          if (d.exact) {
+            R dp[3] = {dG[0][(m + 1) % 3], dG[1][(m + 1) % 3], dG[2][(m + 1) % 3]};
+            R dq[3] = {dG[0][(m + 2) % 3], dG[1][(m + 2) % 3], dG[2][(m + 2) % 3]};
+            cross3<R>(dp, ah, c1);
+            cross3<R>(ah, dq, c2);
+            for (int a = 0; a < 3; ++a) Q[a][m] += Nv[(m + 2) % 3] * c1[a] + Nv[(m + 1) % 3] * c2[a];
+          }
+        }
+      } else {
+        R tau[2] = {Nv[1], -Nv[0]};
+        R cvec[2] = {F[0][0] * tau[0] + F[0][1] * tau[1], F[1][0] * tau[0] + F[1][1] * tau[1]};
+        R cn = sqrt(cvec[0] * cvec[0] + cvec[1] * cvec[1]);
+        R ch[2] = {cvec[0] / cn, cvec[1] / cn};
+        R dc[2] = {dG[0][0] * tau[0] + dG[0][1] * tau[1], dG[1][0] * tau[0] + dG[1][1] * tau[1]};
+        R cd = ch[0] * dc[0] + ch[1] * dc[1];
+        for (int a = 0; a < 2; ++a) {
+          R ua = (dc[a] - ch[a] * cd) / cn;
+          for (int b = 0; b < 2; ++b) Q[a][b] = ua * tau[b];
+        }
+      }
+    }
+    R sc = dt * kr;
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int b = 0; b < D; ++b) d.sS[(a * D + b) * S + r] = sc * Q[a][b];
+  } else if (r < S) {
+#pragma unroll
+    for (int a = 0; a < D * D; ++a) d.sS[a * S + r] = 0;
+  }
+  if (mode == PM_ENERGY) {
+    double bsum = block_sum(e, sh);
+    if (threadIdx.x == 0) d.part[part_slot * kPartSlot + blockIdx.x] = bsum;
+  }
+}
+
+// Node phase: out_i = sum_q S_q grad N_i(x_q) plus the inertia / mass term, projected.
+//  NM_GRAD: out = P[ acc + m (v^ - v^n) - dt m g ]; energy partial of the node terms.
+//  NM_HESS: out = P[ acc + alpha m w ]; optional partial of w . out (CG p.Ap).
+enum NodeMode { NM_GRAD = 0, NM_HESS = 1 };
+
+template <int D, typename R>
+__global__ void __launch_bounds__(64) k_stress_nodes(Dev<R> d, const R* u, R* out, int mode, double alpha,
+                                                     int mask_in, const int* done, int part_slot,
+                                                     int dot_slot) {
+  __shared__ double sh[16];
+  if (done && *done) return;
+  int t = d.tile_list[blockIdx.x];
+  int lane = threadIdx.x;
+  int node = t * kTileNodes + lane;
+  int i[3] = {0, 0, 0};
+  tiled_coords<D>(t, lane, d.nt, i);
+  const int N = d.np, S = d.ns, nn = d.nn;
+  R acc[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) acc[a] = 0;
+  const bool surf = (d.term_mask & 2) && S > 0;
+  const bool vol = (d.term_mask & 5) != 0;
+  for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dxo = -1; dxo <= 1; ++dxo) {
+        int c[3] = {i[0] + dxo, i[1] + dy, i[2] + dz};
+        int off[3] = {dxo, dy, dz};
+        bool in = true;
+#pragma unroll
+        for (int a = 0; a < D; ++a) in = in && c[a] >= 0 && c[a] < d.n;
+        if (!in) continue;
+        int ci = (int)tiled_index<D>(c, d.nt);
+        int kk[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) kk[a] = 1 - off[a];
+        if (vol)
+          for (int k = d.p_start[ci]; k < d.p_start[ci + 1]; ++k) {
+            R f[D], g[D];
+#pragma unroll
+            for (int a = 0; a < D; ++a) f[a] = d.px[a * N + k] * d.fn - R(c[a]);
+            weight_from_cell<D, R>(kk, f, d.fn, g);
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+#pragma unroll
+              for (int b = 0; b < D; ++b) acc[a] += d.pS[(a * D + b) * N + k] * g[b];
+          }
+        if (surf)
+          for (int r = d.s_start[ci]; r < d.s_start[ci + 1]; ++r) {
+            R f[D], g[D];
+#pragma unroll
+            for (int a = 0; a < D; ++a) f[a] = d.ss[a * S + r] * d.fn - R(c[a]);
+            weight_from_cell<D, R>(kk, f, d.fn, g);
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+#pragma unroll
+              for (int b = 0; b < D; ++b) acc[a] += d.sS[(a * D + b) * S + r] * g[b];
+          }
+      }
+  uint8_t fr = d.gfree[node];
+  R m = d.gm[node];
+  double e = 0, dotv = 0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    bool fa = (fr >> a) & 1;
+    R ua = u[a * nn + node];
+    R o;
+    if (mode == NM_GRAD) {
+      R vn = d.gvn[a * nn + node];
+      o = acc[a] + m * (ua - vn) - d.dt * m * d.grav[a];
+      if (fr & 0x80) {
+        double dv = (double)ua - (double)vn;
+        e += 0.5 * (double)m * dv * dv - (double)d.dt * (double)m * (double)d.grav[a] * (double)ua;
+      }
+    } else {
+      R wa = (!mask_in || fa) ? ua : R(0);
+      o = acc[a] + R(alpha) * m * wa;
+      if (fa) dotv += (double)wa * (double)o;
+    }
+    o = fa ? o : R(0);
+    out[a * nn + node] = o;
+  }
+  if (mode == NM_GRAD && part_slot >= 0) {
+    double bsum = block_sum(e, sh);
+    if (threadIdx.x == 0) d.part[part_slot * kPartSlot + blockIdx.x] = bsum;
+  }
+  if (mode == NM_HESS && dot_slot >= 0) {
+    double bsum = block_sum(dotv, sh);
+    if (threadIdx.x == 0) d.part[dot_slot * kPartSlot + blockIdx.x] = bsum;
+  }
+}
+
+// ======================================================================================
+// Heat operator (Section 4.3.2): point phase stores K V^n grad T_p and h |dA_r| T(s_r);
+// node phase forms c_p/dt m_i T_i + sum_p (K V grad T_p) . grad N_i + sum_r h|dA| T_r N_i.
+// ======================================================================================
+template <int D, typename R>
+__global__ void k_heat_points(Dev<R> d, const R* T, const int* done) {
+  if (done && *done) return;
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int N = d.np, S = d.ns;
+  if (q < N) {
+    R x[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) x[a] = d.px[a * N + q];
+    Stencil<D, R> st; bool bad = false;
+    make_stencil<D, R>(x, d.n, d.fn, st, &bad);
+    R gT[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) gT[a] = 0;
+    for_stencil<D>([&](int k0, int k1, int k2) {
+      int nd[3] = {st.c[0] - 1 + k0, st.c[1] - 1 + k1, D == 3 ? st.c[2] - 1 + k2 : 0};
+      R g[D];
+      node_weight<D, R>(st, k0, k1, k2, g);
+      R Tj = T[tiled_index<D>(nd, d.nt)];
+#pragma unroll
+      for (int a = 0; a < D; ++a) gT[a] += Tj * g[a];
+    });
+    R c = d.K * d.pVn[q];
+#pragma unroll
+    for (int a = 0; a < D; ++a) d.pS[a * N + q] = c * gT[a];
+  } else if (q < N + S) {
+    int r = q - N;
+    R x[D], area = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) { x[a] = d.ss[a * S + r]; area += d.sdA[a * S + r] * d.sdA[a * S + r]; }
+    Stencil<D, R> st; bool bad = false;
+    make_stencil<D, R>(x, d.n, d.fn, st, &bad);
+    R Ts = 0;
+    for_stencil<D>([&](int k0, int k1, int k2) {
+      int nd[3] = {st.c[0] - 1 + k0, st.c[1] - 1 + k1, D == 3 ? st.c[2] - 1 + k2 : 0};
+      R g[D];
+      R Nw = node_weight<D, R>(st, k0, k1, k2, g);
+      Ts += Nw * T[tiled_index<D>(nd, d.nt)];
+    });
+    d.sS[r] = d.h * sqrt(area) * Ts;
+  }
+}
+
+template <int D, typename R>
+__global__ void __launch_bounds__(64) k_heat_nodes(Dev<R> d, const R* T, R* out, const int* done, int dot_slot) {
+  __shared__ double sh[16];
+  if (done && *done) return;
+  int t = d.tile_list[blockIdx.x];
+  int lane = threadIdx.x;
+  int node = t * kTileNodes + lane;
+  int i[3] = {0, 0, 0};
+  tiled_coords<D>(t, lane, d.nt, i);
+  const int N = d.np, S = d.ns;
+  R acc = 0;
+  for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dxo = -1; dxo <= 1; ++dxo) {
+        int c[3] = {i[0] + dxo, i[1] + dy, i[2] + dz};
+        int off[3] = {dxo, dy, dz};
+        bool in = true;
+#pragma unroll
+        for (int a = 0; a < D; ++a) in = in && c[a] >= 0 && c[a] < d.n;
+        if (!in) continue;
+        int ci = (int)tiled_index<D>(c, d.nt);
+        int kk[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) kk[a] = 1 - off[a];
+        for (int k = d.p_start[ci]; k < d.p_start[ci + 1]; ++k) {
+          R f[D], g[D];
+#pragma unroll
+          for (int a = 0; a < D; ++a) f[a] = d.px[a * N + k] * d.fn - R(c[a]);
+          weight_from_cell<D, R>(kk, f, d.fn, g);
+#pragma unroll
+          for (int a = 0; a < D; ++a) acc += d.pS[a * N + k] * g[a];
+        }
+        if (S)
+          for (int r = d.s_start[ci]; r < d.s_start[ci + 1]; ++r) {
+            R f[D], g[D];
+#pragma unroll
+            for (int a = 0; a < D; ++a) f[a] = d.ss[a * S + r] * d.fn - R(c[a]);
+            R Nw = weight_from_cell<D, R>(kk, f, d.fn, g);
+            acc += d.sS[r] * Nw;
+          }
+      }
+  bool dof = d.gfree[node] & 0x80;
+  R Ti = T[node];
+  R o = dof ? d.cp / d.dt * d.gm[node] * Ti + acc : R(0);
+  out[node] = o;
+  if (dot_slot >= 0) {
+    double bsum = block_sum(dof ? (double)Ti * (double)o : 0.0, sh);
+    if (threadIdx.x == 0) d.part[dot_slot * kPartSlot + blockIdx.x] = bsum;
+  }
+}
+
+// ======================================================================================
+// G2P with merge (Section 5).
+// ======================================================================================
+// Interpolated velocity and first moment about ref: sum_i N_i(q) v^_i and
+// sum_i N_i(q) v^_i (x_i - ref)^T, with x_i - ref = (x_i - q) + (q - ref).
+template <int D, typename R>
+MPM_DEV void g2p_moments(const Dev<R>& d, const R* q, const R* qref, const R* vh, R* vq, R (&tq)[D][D]) {
+  Stencil<D, R> st; bool bad = false;
+  make_stencil<D, R>(q, d.n, d.fn, st, &bad);
+#pragma unroll
+  for (int a = 0; a < D; ++a) { vq[a] = 0; for (int b = 0; b < D; ++b) tq[a][b] = 0; }
+  R shift[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) shift[a] = q[a] - qref[a];
+  for_stencil<D>([&](int k0, int k1, int k2) {
+    int kk[3] = {k0, k1, k2};
+    int nd[3] = {st.c[0] - 1 + k0, st.c[1] - 1 + k1, D == 3 ? st.c[2] - 1 + k2 : 0};
+    int node = (int)tiled_index<D>(nd, d.nt);
+    R g[D];
+    R Nw = node_weight<D, R>(st, k0, k1, k2, g);
+    R rel[D];
+#pragma unroll
+    for (int b = 0; b < D; ++b) rel[b] = (R(kk[b]) - R(0.5) - st.f[b]) * d.dx + shift[b];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      R nv = Nw * vh[a * d.nn + node];
+      vq[a] += nv;
+#pragma unroll
+      for (int b = 0; b < D; ++b) tq[a][b] += nv * rel[b];
+    }
+  });
+}
+
+// Per sample r: v(s_r) + v(b_r) and the first moments of both about x_p(r).
+template <int D, typename R>
+__global__ void k_g2p_split(Dev<R> d, const R* vh) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int S = d.ns, N = d.np;
+  if (r >= S) return;
+  int p = d.spar[r];
+  R xp[D], s[D], b[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    xp[a] = d.px[a * N + p];
+    s[a] = d.ss[a * S + r];
+    b[a] = s[a] + R(2) * (xp[a] - s[a]);
+  }
+  R v1[D], v2[D], t1[D][D], t2[D][D];
+  g2p_moments<D, R>(d, s, xp, vh, v1, t1);
+  g2p_moments<D, R>(d, b, xp, vh, v2, t2);
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    d.sc[a * S + r] = v1[a] + v2[a];
+#pragma unroll
+    for (int c = 0; c < D; ++c) d.sc[(D + a * D + c) * S + r] = t1[a][c] + t2[a][c];
+  }
+}
+
+template <int D, typename R>
+__global__ void k_g2p_particles(Dev<R> d, const R* vh, const R* Th, R* x, R* v, R* A, R* J, R* T, R* gT) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int N = d.np, S = d.ns;
+  if (k >= N) return;
+  R xp[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) xp[a] = d.px[a * N + k];
+  Stencil<D, R> st; bool bad = false;
+  make_stencil<D, R>(xp, d.n, d.fn, st, &bad);
+  R vq[D], tq[D][D], gTq[D];
+  R Tq = 0, div = 0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) { vq[a] = 0; gTq[a] = 0; for (int b = 0; b < D; ++b) tq[a][b] = 0; }
+  for_stencil<D>([&](int k0, int k1, int k2) {
+    int kk[3] = {k0, k1, k2};
+    int nd[3] = {st.c[0] - 1 + k0, st.c[1] - 1 + k1, D == 3 ? st.c[2] - 1 + k2 : 0};
+    int node = (int)tiled_index<D>(nd, d.nt);
+    R g[D];
+    R Nw = node_weight<D, R>(st, k0, k1, k2, g);
+    R rel[D];
+#pragma unroll
+    for (int b = 0; b < D; ++b) rel[b] = (R(kk[b]) - R(0.5) - st.f[b]) * d.dx;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      R va = vh[a * d.nn + node];
+      R nv = Nw * va;
+      vq[a] += nv;
+      div += va * g[a];
+#pragma unroll
+      for (int b = 0; b < D; ++b) tq[a][b] += nv * rel[b];
+    }
+    if (Th) {
+      R Tj = Th[node];
+      Tq += Nw * Tj;
+#pragma unroll
+      for (int a = 0; a < D; ++a) gTq[a] += Tj * g[a];
+    }
+  });
+  R mt = d.pmt[k], mp = d.pm[k];
+  R mom[D], tt[D][D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    mom[a] = mt * vq[a];
+#pragma unroll
+    for (int b = 0; b < D; ++b) tt[a][b] = mt * tq[a][b];
+  }
+  for (int j = d.grp_start[k]; j < d.grp_start[k + 1]; ++j) {
+    int r = d.grp[j];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      mom[a] += mt * d.sc[a * S + r];
+#pragma unroll
+      for (int b = 0; b < D; ++b) tt[a][b] += mt * d.sc[(D + a * D + b) * S + r];
+    }
+  }
+  int i = d.p_perm[k];
+  R inv_m = R(1) / mp;
+  R cA = R(4) / (mp * d.dx * d.dx);
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    R va = mom[a] * inv_m;
+    v[a * N + i] = va;
+    x[a * N + i] = xp[a] + d.dt * va;
+#pragma unroll
+    for (int b = 0; b < D; ++b) A[(a * D + b) * N + i] = cA * tt[a][b];
+  }
+  J[i] = (R(1) + d.dt * div) * d.pJ[k];
+  if (Th) {
+    T[i] = Tq;
+#pragma unroll
+    for (int a = 0; a < D; ++a) gT[a * N + i] = gTq[a];
+  }
+}
+
+// ======================================================================================
+// Krylov BLAS-1 over the nodes of the active tiles (ncomp components, dense arrays of nn
+// per component).  Grid-stride with a fixed grid, so the partial-sum partition depends
+// only on the problem size.
+// ======================================================================================
+struct CgScal {
+  double rz, rr, pAp, tol2, alpha, beta, rz0, spare;
+  int done, iters, maxit, breakdown;
+};
+
+MPM_DEV int elem_node(const int* tile_list, int e) { return tile_list[e >> 6] * kTileNodes + (e & 63); }
+
+template <typename R>
+__global__ void k_dot(const int* tl, int nelem, int nn, int ncomp, const R* a, const R* b, double* part,
+                      const int* done) {
+  __shared__ double sh[16];
+  if (done && *done) return;
+  double s = 0;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nelem; e += gridDim.x * blockDim.x) {
+    int node = elem_node(tl, e);
+    for (int c = 0; c < ncomp; ++c) s += (double)a[c * nn + node] * (double)b[c * nn + node];
+  }
+  double t = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ void k_sum3(const double* a, double* out, double* out2) {
+  double v = a[0] + a[1] + a[2];
+  *out = v;
+  if (out2) *out2 = v;
+}
+
+// misc[2] += number of nodes with mass; misc[1] |= 1 if one of them has a fixed component.
+template <int D>
+__global__ void k_dof_flags(const int* tl, const uint8_t* fr, int* misc) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  uint8_t f = fr[tl[blockIdx.x] * kTileNodes + threadIdx.x];
+  const uint8_t all = (uint8_t)((1u << D) - 1);
+  if (f & 0x80) {
+    atomicAdd(&cnt, 1);
+    if ((f & all) != all) atomicOr(&misc[1], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && cnt) atomicAdd(&misc[2], cnt);
+}
+
+// Sums nslot partial arrays of nb entries each (fixed order) into dst[0..nslot).
+__global__ void k_finalize(const double* part, int nb, int nslot, double* dst) {
+  __shared__ double sh[16];
+  for (int s = 0; s < nslot; ++s) {
+    double v = 0;
+    for (int k = threadIdx.x; k < nb; k += blockDim.x) v += part[s * kPartSlot + k];
+    double t = block_sum(v, sh);
+    if (threadIdx.x == 0) dst[s] = t;
+    __syncthreads();
+  }
+}
+
+// r = b, x = 0, z = r/diag, p = z; partials r.z, r.r (slots 0, 1).
+template <typename R>
+__global__ void k_cg_start(const int* tl, int nelem, int nn, int ncomp, const R* b, const R* diag, R* x,
+                           R* r, R* z, R* p, double* part, int zero_x) {
+  __shared__ double sh[16];
+  double rz = 0, rr = 0;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nelem; e += gridDim.x * blockDim.x) {
+    int node = elem_node(tl, e);
+    for (int c = 0; c < ncomp; ++c) {
+      int j = c * nn + node;
+      R rv = b[j];
+      R zv = rv / diag[j];
+      if (zero_x) x[j] = 0;
+      r[j] = rv; z[j] = zv; p[j] = zv;
+      rz += (double)rv * (double)zv;
+      rr += (double)rv * (double)rv;
+    }
+  }
+  double t0 = block_sum(rz, sh);
+  double t1 = block_sum(rr, sh);
+  if (threadIdx.x == 0) { part[blockIdx.x] = t0; part[kPartSlot + blockIdx.x] = t1; }
+}
+
+// r = b - Ax (for a given initial guess), then as k_cg_start.
+template <typename R>
+__global__ void k_cg_start_x0(const int* tl, int nelem, int nn, int ncomp, const R* b, const R* Ax,
+                              const R* diag, R* r, R* z, R* p, double* part) {
+  __shared__ double sh[16];
+  double rz = 0, rr = 0;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nelem; e += gridDim.x * blockDim.x) {
+    int node = elem_node(tl, e);
+    for (int c = 0; c < ncomp; ++c) {
+      int j = c * nn + node;
+      R rv = b[j] - Ax[j];
+      R zv = rv / diag[j];
+      r[j] = rv; z[j] = zv; p[j] = zv;
+      rz += (double)rv * (double)zv;
+      rr += (double)rv * (double)rv;
+    }
+  }
+  double t0 = block_sum(rz, sh);
+  double t1 = block_sum(rr, sh);
+  if (threadIdx.x == 0) { part[blockIdx.x] = t0; part[kPartSlot + blockIdx.x] = t1; }
+}
+
+__global__ void k_cg_init_scal(CgScal* s, const double* red, double tol2, int maxit) {
+  s->rz = red[0];
+  s->rr = red[1];
+  s->tol2 = tol2;
+  s->maxit = maxit;
+  s->iters = 0;
+  s->breakdown = 0;
+  s->done = (red[1] <= tol2) || maxit <= 0;
+  if (!(red[1] == red[1]) || red[1] > 1e300) s->done = 1;
+}
+
+// pAp from the reduction; stops on breakdown (non-positive curvature).
+__global__ void k_cg_pap(CgScal* s, const double* red) {
+  if (s->done) return;
+  double pAp = red[0];
+  s->pAp = pAp;
+  if (!(pAp > 0.0)) { s->done = 1; s->breakdown = 1; return; }
+  s->alpha = s->rz / pAp;
+}
+
+template <typename R>
+__global__ void k_cg_update(const int* tl, int nelem, int nn, int ncomp, const CgScal* s, R* x, R* r, R* z,
+                            const R* p, const R* Ap, const R* diag, double* part) {
+  __shared__ double sh[16];
+  if (s->done) return;
+  R alpha = (R)s->alpha;
+  double rz = 0, rr = 0;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nelem; e += gridDim.x * blockDim.x) {
+    int node = elem_node(tl, e);
+    for (int c = 0; c < ncomp; ++c) {
+      int j = c * nn + node;
+      x[j] += alpha * p[j];
+      R rv = r[j] - alpha * Ap[j];
+      R zv = rv / diag[j];
+      r[j] = rv; z[j] = zv;
+      rz += (double)rv * (double)zv;
+      rr += (double)rv * (double)rv;
+    }
+  }
+  double t0 = block_sum(rz, sh);
+  double t1 = block_sum(rr, sh);
+  if (threadIdx.x == 0) { part[blockIdx.x] = t0; part[kPartSlot + blockIdx.x] = t1; }
+}
+
+__global__ void k_cg_scal_after(CgScal* s, const double* red) {
+  if (s->done) return;
+  double rz_new = red[0], rr = red[1];
+  s->beta = rz_new / s->rz;
+  s->rz = rz_new;
+  s->rr = rr;
+  s->iters += 1;
+  if (rr <= s->tol2 || s->iters >= s->maxit || !(rr == rr)) s->done = 1;
+}
+
+template <typename R>
+__global__ void k_cg_p(const int* tl, int nelem, int nn, int ncomp, const CgScal* s, const R* z, R* p,
+                       int* done_flag) {
+  // runs even on the iteration that finished (harmless: p is not used afterwards)
+  if (s->done) return;
+  R beta = (R)s->beta;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nelem; e += gridDim.x * blockDim.x) {
+    int node = elem_node(tl, e);
+    for (int c = 0; c < ncomp; ++c) {
+      int j = c * nn + node;
+      p[j] = z[j] + beta * p[j];
+    }
+  }
+}
+
+// After the loop: breakdown at the first iteration takes the preconditioned residual.
+template <typename R>
+__global__ void k_cg_fixup(const int* tl, int nelem, int nn, int ncomp, const CgScal* s, R* x, const R* z) {
+  if (!(s->breakdown && s->iters == 0)) return;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nelem; e += gridDim.x * blockDim.x) {
+    int node = elem_node(tl, e);
+    for (int c = 0; c < ncomp; ++c) x[c * nn + node] = z[c * nn + node];
+  }
+}
+
+// y = a + s b on free components (s from a device double or a host value).
+template <typename R>
+__global__ void k_axpy_to(const int* tl, int nelem, int nn, int ncomp, const R* a, const R* b, double sh,
+                          R* y) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nelem; e += gridDim.x * blockDim.x) {
+    int node = elem_node(tl, e);
+    for (int c = 0; c < ncomp; ++c) y[c * nn + node] = a[c * nn + node] + (R)sh * b[c * nn + node];
+  }
+}
+
+// v^ = P v^n.
+template <typename R>
+__global__ void k_project_copy(const int* tl, int nelem, int nn, int ncomp, const uint8_t* fr, const R* a,
+                               R* y) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nelem; e += gridDim.x * blockDim.x) {
+    int node = elem_node(tl, e);
+    uint8_t f = fr[node];
+    for (int c = 0; c < ncomp; ++c) y[c * nn + node] = ((f >> c) & 1) ? a[c * nn + node] : R(0);
+  }
+}
+
+template <typename R>
+__global__ void k_neg(const int* tl, int nelem, int nn, int ncomp, const R* a, R* y) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nelem; e += gridDim.x * blockDim.x) {
+    int node = elem_node(tl, e);
+    for (int c = 0; c < ncomp; ++c) y[c * nn + node] = -a[c * nn + node];
+  }
+}
+
+// Momentum sums over nodes with mass: slots 0..D-1 sum m (v^ - v^n), slot D sum m,
+// slots D+1..2D sum m v^.
+template <int D, typename R>
+__global__ void k_mom_sums(const int* tl, int nelem, int nn, const uint8_t* fr, const R* m, const R* vh,
+                           const R* vn, double* part) {
+  __shared__ double sh[16];
+  double s[2 * D + 1];
+  for (int k = 0; k < 2 * D + 1; ++k) s[k] = 0;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nelem; e += gridDim.x * blockDim.x) {
+    int node = elem_node(tl, e);
+    if (!(fr[node] & 0x80)) continue;
+    double mm = m[node];
+    s[D] += mm;
+    for (int a = 0; a < D; ++a) {
+      s[a] += mm * ((double)vh[a * nn + node] - (double)vn[a * nn + node]);
+      s[D + 1 + a] += mm * (double)vh[a * nn + node];
+    }
+  }
+  for (int k = 0; k < 2 * D + 1; ++k) {
+    double t = block_sum(s[k], sh);
+    if (threadIdx.x == 0) part[k * kPartSlot + blockIdx.x] = t;
+    __syncthreads();
+  }
+}
+
+// v^ -= c on nodes with mass, c_a = [sum m (v^-v^n) - dt g_a sum m] / sum m.
+template <int D, typename R>
+__global__ void k_mom_fix(const int* tl, int nelem, int nn, const uint8_t* fr, const double* red, double dt,
+                          double g0, double g1, double g2, R* vh) {
+  double msum = red[D];
+  double gg[3] = {g0, g1, g2};
+  R c[D];
+  for (int a = 0; a < D; ++a) c[a] = (R)((red[a] - dt * gg[a] * msum) / msum);
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nelem; e += gridDim.x * blockDim.x) {
+    int node = elem_node(tl, e);
+    if (!(fr[node] & 0x80)) continue;
+    for (int a = 0; a < D; ++a) vh[a * nn + node] -= c[a];
+  }
+}
+
+// Explicit update (q^ = 0): v^ = P[v^n - f/m + dt g] with f = dPsi/dv^ evaluated by the
+// caller (J and surface terms at v^ = 0, viscosity at v^n).
+template <int D, typename R>
+__global__ void k_explicit_update(const int* tl, int nelem, int nn, const uint8_t* fr, const R* m, const R* vn,
+                                  const R* f, R g0, R g1, R g2, R dt, R* vh) {
+  R gg[3] = {g0, g1, g2};
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nelem; e += gridDim.x * blockDim.x) {
+    int node = elem_node(tl, e);
+    uint8_t fl = fr[node];
+    for (int a = 0; a < D; ++a) {
+      int j = a * nn + node;
+      vh[j] = ((fl >> a) & 1) ? vn[j] - f[j] / m[node] + dt * gg[a] : R(0);
+    }
+  }
+}
+
+}  // namespace mpm

@@ -1,0 +1,897 @@
+// Host side of the MPM hot-path library: workspace layout, contexts, the step pipeline
+// and the C ABI declared in include/mpm.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+using namespace mpm;
+
+namespace {
+
+constexpr int kNumParts = 8;
+constexpr int kScalDoubles = 64;
+
+struct HipError {
+  hipError_t e;
+  const char* what;
+};
+
+#define HIPCHK(x)                                   \
+  do {                                              \
+    hipError_t e_ = (x);                            \
+    if (e_ != hipSuccess) throw HipError{e_, #x};   \
+  } while (0)
+
+struct ApiError {
+  int code;
+  std::string msg;
+};
+
+inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// Bump allocator over the workspace (256-byte aligned pieces).
+struct Bump {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+}  // namespace
+
+struct mpm_ctx {
+  mpm_params p;
+  int dim = 3, n = 0, nt = 0, nn = 0, ntile_total = 0;
+  int64_t cap_part = 0, cap_surf = 0;
+  bool fp64 = true;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  // typed device views (only the one matching the precision is used)
+  Dev<double> d64{};
+  Dev<float> d32{};
+  // real-typed vectors (void* so both precisions share the host code)
+  void *vhat = nullptr, *vtrial = nullptr, *grad = nullptr, *delta = nullptr, *r = nullptr, *z = nullptr,
+       *pp = nullptr, *Ap = nullptr, *zero = nullptr, *gscratch = nullptr;
+  void *That = nullptr, *hr = nullptr, *hz = nullptr, *hp = nullptr, *hAp = nullptr;
+  int* tile_pos = nullptr;
+  int* scan_bsum = nullptr;
+  int* misc = nullptr;          // [0] status, [1] constrained flag, [2] tile count
+  double* part = nullptr;
+  double* scal = nullptr;
+  CgScal* cg = nullptr;
+  // pinned host mirror
+  double* hbuf = nullptr;
+  int* hint = nullptr;
+  CgScal* hcg = nullptr;
+  // state
+  int np = 0, ns = 0, ntiles = 0, prev_ntiles = 0;
+  bool have_p2g = false, constrained = false;
+  int status = 0;
+  mpm_stats stats{};
+  std::string err;
+};
+
+namespace {
+
+template <typename R>
+size_t layout(mpm_ctx* c, char* base) {
+  Bump b{base};
+  const int D = c->dim;
+  const int64_t NP = std::max<int64_t>(c->cap_part, 1), NS = std::max<int64_t>(c->cap_surf, 1);
+  const int64_t NN = c->nn, NT = c->ntile_total;
+  Dev<R> d{};
+  d.p_start = b.take<int>(NN + 1); d.p_perm = b.take<int>(NP); d.p_key = b.take<int>(NP);
+  d.pcnt = b.take<int>(NP); d.pcnt_orig = b.take<int>(NP); d.grp_start = b.take<int>(NP + 1); d.grp = b.take<int>(NS); d.gcur = b.take<int>(NP);
+  d.s_start = b.take<int>(NN + 1); d.s_perm = b.take<int>(NS); d.s_key = b.take<int>(NS);
+  d.slabel = b.take<int>(NS); d.spar = b.take<int>(NS); d.s_parent_orig = b.take<int>(NS);
+  d.b_start = b.take<int>(NN + 1); d.b_src = b.take<int>(NS); d.b_key = b.take<int>(NS);
+  d.ccount = b.take<int>(NN);
+  d.tile_flag = b.take<int>(NT); d.tile_list = b.take<int>(NT);
+  int* tile_pos = b.take<int>(NT + 1);
+  int* scan_bsum = b.take<int>(kScanBlock + 1);
+  int* misc = b.take<int>(64);
+  d.px = b.take<R>(D * NP); d.pv = b.take<R>(D * NP); d.pA = b.take<R>(D * D * NP);
+  d.pm = b.take<R>(NP); d.pmt = b.take<R>(NP); d.pJ = b.take<R>(NP); d.pV0 = b.take<R>(NP);
+  d.pT = b.take<R>(NP); d.pgT = b.take<R>(D * NP); d.pmu = b.take<R>(NP); d.pVn = b.take<R>(NP);
+  d.pS = b.take<R>(D * D * NP);
+  d.ss = b.take<R>(D * NS); d.sdA = b.take<R>(D * NS); d.sk = b.take<R>(NS); d.sk_orig = b.take<R>(NS); d.sS = b.take<R>(D * D * NS);
+  d.sc = b.take<R>((D + D * D) * NS); d.bx = b.take<R>(D * NS); d.bx_unsorted = b.take<R>(D * NS);
+  d.gm = b.take<R>(NN); d.gW = b.take<R>(NN); d.gWT = b.take<R>(NN); d.gE = b.take<R>(NN);
+  d.gET = b.take<R>(NN); d.gTn = b.take<R>(NN); d.hdiag = b.take<R>(NN); d.hrhs = b.take<R>(NN);
+  d.gmv = b.take<R>(D * NN); d.gvn = b.take<R>(D * NN); d.gdiag = b.take<R>(D * NN);
+  d.gfree = b.take<uint8_t>(NN);
+  void* vecs[10];
+  for (int k = 0; k < 10; ++k) vecs[k] = b.take<R>(D * NN);
+  void* hvecs[5];
+  for (int k = 0; k < 5; ++k) hvecs[k] = b.take<R>(NN);
+  d.part = b.take<double>((size_t)kNumParts * kPartSlot);
+  d.scal = b.take<double>(kScalDoubles);
+  CgScal* cg = b.take<CgScal>(2);
+  d.status = misc;
+  if (base) {
+    c->vhat = vecs[0]; c->vtrial = vecs[1]; c->grad = vecs[2]; c->delta = vecs[3]; c->r = vecs[4];
+    c->z = vecs[5]; c->pp = vecs[6]; c->Ap = vecs[7]; c->zero = vecs[8]; c->gscratch = vecs[9];
+    c->That = hvecs[0]; c->hr = hvecs[1]; c->hz = hvecs[2]; c->hp = hvecs[3]; c->hAp = hvecs[4];
+    c->tile_pos = tile_pos; c->scan_bsum = scan_bsum; c->misc = misc;
+    c->part = d.part; c->scal = d.scal; c->cg = cg;
+    if constexpr (sizeof(R) == 8) c->d64 = d; else c->d32 = d;
+  }
+  return b.off + 256;
+}
+
+template <typename R>
+void fill_params(Dev<R>& d, const mpm_params& p, int nt) {
+  d.n = p.n; d.nt = nt; d.nn = 1;
+  for (int a = 0; a < p.dim; ++a) d.nn *= p.n;
+  d.fn = (R)p.n; d.dx = (R)p.dx; d.dt = (R)p.dt;
+  d.lam = (R)p.bulk; d.mu0 = (R)p.mu0; d.mu_k = (R)p.mu_k; d.mu_T0 = (R)p.mu_T0;
+  d.g0 = (R)p.g0; d.g1 = (R)p.g1; d.gT0 = (R)p.gT0; d.gmin = (R)p.gmin; d.gmax = (R)p.gmax;
+  d.cp = (R)p.cp; d.K = (R)p.K; d.h = (R)p.h; d.T_amb = (R)p.T_amb; d.b = (R)p.b; d.H = (R)p.H;
+  for (int k = 0; k < 4; ++k) d.gamma_label[k] = (R)p.gamma_label[k];
+  for (int k = 0; k < 3; ++k) {
+    d.grav[k] = (R)p.gravity[k]; d.slab_lo[k] = (R)p.slab_lo[k]; d.slab_hi[k] = (R)p.slab_hi[k];
+  }
+  d.slab = p.slab; d.slab_axis = p.slab_axis; d.wall = p.wall_layers; d.term_mask = p.term_mask;
+  d.exact = p.hess_mode == MPM_HESS_EXACT; d.gamma_by_label = p.gamma_by_label;
+}
+
+void check_params(const mpm_params* p) {
+  if (!p) throw ApiError{MPM_EINVAL, "null params"};
+  if (p->dim != 2 && p->dim != 3) throw ApiError{MPM_EINVAL, "dim must be 2 or 3"};
+  if (p->n < 8 || p->n % 8 != 0) throw ApiError{MPM_EINVAL, "n must be a positive multiple of 8"};
+  double nn = std::pow((double)p->n, p->dim);
+  if (nn > (double)(kScanBlock) * kScanBlock) throw ApiError{MPM_EINVAL, "n^dim above 2^24"};
+  if (!(std::fabs(p->dx * p->n - 1.0) < 1e-9)) throw ApiError{MPM_EINVAL, "dx must equal 1/n"};
+  if (!(p->dt > 0)) throw ApiError{MPM_EINVAL, "dt must be positive"};
+  if (p->precision != MPM_FP64 && p->precision != MPM_MIXED) throw ApiError{MPM_EINVAL, "bad precision"};
+  if (p->slab_axis < 0 || p->slab_axis >= p->dim) throw ApiError{MPM_EINVAL, "bad slab_axis"};
+}
+
+// ---- exclusive scan of len ints: out[0..len) and out[len] = total ----------------------
+void scan(mpm_ctx* c, const int* in, int* out, int len, hipStream_t s) {
+  int nb = cdiv(len, kScanBlock);
+  if (nb > kScanBlock) throw ApiError{MPM_EINVAL, "scan length above 2^24"};
+  if (len > 0) hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(kScanT), 0, s, in, out, len, c->scan_bsum);
+  else hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(1), 0, s, c->scan_bsum, 0, (int64_t)1);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanT), 0, s, c->scan_bsum, std::max(nb, 1), out + len);
+  if (len > 0) hipLaunchKernelGGL(k_scan_add, dim3(cdiv(len, 256)), dim3(256), 0, s, out, len, (const int*)c->scan_bsum);
+}
+
+// Stable cell sort of cnt points: perm (sorted slot -> input index) and start[nn+1].
+template <int D, typename R>
+void cell_sort(mpm_ctx* c, Dev<R>& d, const R* pos, int cnt, int* key, int* perm, int* start, hipStream_t s) {
+  if (cnt > 0)
+    hipLaunchKernelGGL((k_cell_keys<D, R>), dim3(cdiv(cnt, 256)), dim3(256), 0, s, pos, cnt, d.n, d.nt, d.fn, key,
+                       d.ccount, d.status);
+  scan(c, d.ccount, start, d.nn, s);
+  if (cnt > 0) {
+    hipLaunchKernelGGL(k_cell_scatter, dim3(cdiv(cnt, 256)), dim3(256), 0, s, (const int*)key, cnt,
+                       (const int*)start, d.ccount, perm);
+    hipLaunchKernelGGL(k_segment_order, dim3(cdiv(d.nn, 256)), dim3(256), 0, s, (const int*)start, d.nn, perm);
+  }
+}
+
+template <typename R> Dev<R>& dev(mpm_ctx* c);
+template <> Dev<double>& dev<double>(mpm_ctx* c) { return c->d64; }
+template <> Dev<float>& dev<float>(mpm_ctx* c) { return c->d32; }
+
+int krylov_blocks(int nelem) { return std::max(1, std::min(1024, cdiv(nelem, 256))); }
+
+void sync_read(mpm_ctx* c, hipStream_t s, const void* src, void* dst, size_t bytes) {
+  HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+// ---------------------------------------------------------------------------------------
+template <int D, typename R>
+void do_p2g(mpm_ctx* c, const mpm_particles* P, const mpm_surface* S, hipStream_t s) {
+  if (!P || P->n < 0 || P->n > c->cap_part) throw ApiError{MPM_ENOMEM, "particle count above capacity"};
+  int64_t ns = S ? S->n : 0;
+  if (ns < 0 || ns > c->cap_surf) throw ApiError{MPM_ENOMEM, "surface count above capacity"};
+  if (P->n > 0 && (!P->x || !P->v || !P->A || !P->J || !P->V0 || !P->m || !P->T || !P->gradT))
+    throw ApiError{MPM_EINVAL, "null particle buffer"};
+  if (ns > 0 && (!S->s || !S->dA)) throw ApiError{MPM_EINVAL, "null surface buffer"};
+  if (ns > 0 && P->n == 0) throw ApiError{MPM_EINVAL, "surface samples without particles"};
+  Dev<R>& d = dev<R>(c);
+  c->np = (int)P->n;
+  c->ns = (int)ns;
+  d.np = c->np;
+  d.ns = c->ns;
+  // clear the previous step's tiles so that views read zero outside the new active set
+  if (c->prev_ntiles > 0) {
+    hipLaunchKernelGGL((k_clear_tiles<D, R>), dim3(c->prev_ntiles), dim3(64), 0, s, d, (const int*)d.tile_list,
+                       (R* const*)nullptr, 0, 0);
+  }
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, c->misc, 0, (int64_t)8);
+  // A0: bin interior particles by cell and stage them in cell order
+  cell_sort<D, R>(c, d, (const R*)P->x, c->np, d.p_key, d.p_perm, d.p_start, s);
+  if (c->np > 0)
+    hipLaunchKernelGGL((k_gather_particles<D, R>), dim3(cdiv(c->np, 256)), dim3(256), 0, s, d, (const R*)P->x,
+                       (const R*)P->v, (const R*)P->A, (const R*)P->J, (const R*)P->V0, (const R*)P->m,
+                       (const R*)P->T, (const R*)P->gradT);
+  // A1: surface samples, parents, split masses, balance points, groups
+  if (c->ns > 0) {
+    cell_sort<D, R>(c, d, (const R*)S->s, c->ns, d.s_key, d.s_perm, d.s_start, s);
+    hipLaunchKernelGGL((k_gather_surface<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d, (const R*)S->s,
+                       (const R*)S->dA, S->label);
+    hipLaunchKernelGGL((k_parents<D, R>), dim3(cdiv(c->ns, 64)), dim3(64), 0, s, d);
+  }
+  if (c->np > 0) hipLaunchKernelGGL((k_split_mass<R>), dim3(cdiv(c->np, 256)), dim3(256), 0, s, d);
+  scan(c, d.pcnt, d.grp_start, c->np, s);
+  if (c->ns > 0) {
+    hipLaunchKernelGGL((k_balance<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d);
+    hipLaunchKernelGGL(k_segment_order, dim3(cdiv(c->np, 256)), dim3(256), 0, s, (const int*)d.grp_start, c->np,
+                       d.grp);
+    cell_sort<D, R>(c, d, (const R*)d.bx_unsorted, c->ns, d.b_key, d.b_src, d.b_start, s);
+    hipLaunchKernelGGL((k_gather_balance<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d);
+  }
+  // active tiles
+  hipLaunchKernelGGL((k_mark_tiles<D, R>), dim3(cdiv(d.nn, 256)), dim3(256), 0, s, d);
+  scan(c, d.tile_flag, c->tile_pos, c->ntile_total, s);
+  hipLaunchKernelGGL(k_compact_tiles, dim3(cdiv(c->ntile_total, 256)), dim3(256), 0, s, (const int*)d.tile_flag,
+                     (const int*)c->tile_pos, c->ntile_total, d.tile_list);
+  sync_read(c, s, c->tile_pos + c->ntile_total, c->hint, sizeof(int));
+  c->ntiles = c->hint[0];
+  c->prev_ntiles = c->ntiles;
+  // A2/A3: P2G and grid set-up
+  if (c->ntiles > 0) hipLaunchKernelGGL((k_p2g_nodes<D, R>), dim3(c->ntiles), dim3(64), 0, s, d);
+  if (c->ns > 0) hipLaunchKernelGGL((k_surface_k<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d);
+  // degrees of freedom and whether any of them has a fixed component
+  if (c->ntiles > 0)
+    hipLaunchKernelGGL((k_dof_flags<D>), dim3(c->ntiles), dim3(64), 0, s, (const int*)d.tile_list,
+                       (const uint8_t*)d.gfree, c->misc);
+  c->have_p2g = true;
+  c->stats = mpm_stats{};
+  c->stats.n_part = c->np;
+  c->stats.n_surf = c->ns;
+  c->stats.n_tiles = c->ntiles;
+}
+
+// Reads the degree-of-freedom count and the constrained flag written by k_dof_flags.
+bool any_constrained(mpm_ctx* c, hipStream_t s) {
+  sync_read(c, s, c->misc, c->hint, 4 * sizeof(int));
+  c->stats.n_dof = c->hint[2];
+  c->status |= c->hint[0];
+  return c->hint[1] != 0;
+}
+
+// Phi(u) into scal[0] (and energy_dev if given), gradient into g.
+template <int D, typename R>
+void do_energy_grad(mpm_ctx* c, const R* u, R* g, double* energy_dev, hipStream_t s) {
+  Dev<R>& d = dev<R>(c);
+  int nbp = std::max(1, cdiv(c->np, 256)), nbs = std::max(1, cdiv(c->ns, 256));
+  if (c->np > 0)
+    hipLaunchKernelGGL((k_points_interior<D, R>), dim3(nbp), dim3(256), 0, s, d, u, (int)PM_ENERGY, 0,
+                       (const int*)nullptr, 2);
+  else
+    hipLaunchKernelGGL(k_fill_r<double>, dim3(1), dim3(1), 0, s, c->part + 2 * kPartSlot, 0.0, (int64_t)1);
+  if (c->ns > 0)
+    hipLaunchKernelGGL((k_points_surface<D, R>), dim3(nbs), dim3(256), 0, s, d, u, u, (int)PM_ENERGY, 0,
+                       (const int*)nullptr, 3);
+  else
+    hipLaunchKernelGGL(k_fill_r<double>, dim3(1), dim3(1), 0, s, c->part + 3 * kPartSlot, 0.0, (int64_t)1);
+  if (c->ntiles > 0)
+    hipLaunchKernelGGL((k_stress_nodes<D, R>), dim3(c->ntiles), dim3(64), 0, s, d, u, g, (int)NM_GRAD, 0.0, 0,
+                       (const int*)nullptr, 4, -1);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, c->part + 2 * kPartSlot, c->np > 0 ? nbp : 1, 1, c->scal + 8);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, c->part + 3 * kPartSlot, c->ns > 0 ? nbs : 1, 1, c->scal + 9);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, c->part + 4 * kPartSlot, std::max(c->ntiles, 1), 1, c->scal + 10);
+  hipLaunchKernelGGL(k_sum3, dim3(1), dim3(1), 0, s, (const double*)(c->scal + 8), c->scal + 0, energy_dev);
+}
+
+template <int D, typename R>
+void do_hessvec(mpm_ctx* c, const R* vlin, const R* w, double alpha, R* out, bool mask_in, const int* done,
+                int dot_slot, hipStream_t s) {
+  Dev<R>& d = dev<R>(c);
+  if (c->np > 0 && (d.term_mask & 5))
+    hipLaunchKernelGGL((k_points_interior<D, R>), dim3(cdiv(c->np, 256)), dim3(256), 0, s, d, w, (int)PM_HESS,
+                       (int)mask_in, done, -1);
+  if (c->ns > 0 && (d.term_mask & 2))
+    hipLaunchKernelGGL((k_points_surface<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d, vlin, w,
+                       (int)PM_HESS, (int)mask_in, done, -1);
+  if (c->ntiles > 0)
+    hipLaunchKernelGGL((k_stress_nodes<D, R>), dim3(c->ntiles), dim3(64), 0, s, d, w, out, (int)NM_HESS, alpha,
+                       (int)mask_in, done, -1, dot_slot);
+}
+
+// Forces only (no inertia term): out = P sum_q S_q grad N_i for the stress of u.
+template <int D, typename R>
+void do_hessvec_force(mpm_ctx* c, const R* u, R* out, hipStream_t s) {
+  Dev<R>& d = dev<R>(c);
+  int nbp = std::max(1, cdiv(c->np, 256)), nbs = std::max(1, cdiv(c->ns, 256));
+  if (c->np > 0 && (d.term_mask & 5))
+    hipLaunchKernelGGL((k_points_interior<D, R>), dim3(nbp), dim3(256), 0, s, d, u, (int)PM_ENERGY, 0,
+                       (const int*)nullptr, 2);
+  if (c->ns > 0 && (d.term_mask & 2))
+    hipLaunchKernelGGL((k_points_surface<D, R>), dim3(nbs), dim3(256), 0, s, d, u, u, (int)PM_ENERGY, 0,
+                       (const int*)nullptr, 3);
+  if (c->ntiles > 0)
+    hipLaunchKernelGGL((k_stress_nodes<D, R>), dim3(c->ntiles), dim3(64), 0, s, d, u, out, (int)NM_HESS, 0.0, 0,
+                       (const int*)nullptr, -1, -1);
+}
+
+template <int D, typename R>
+void do_heat_apply(mpm_ctx* c, const R* T, R* out, const int* done, int dot_slot, hipStream_t s) {
+  Dev<R>& d = dev<R>(c);
+  if (c->np + c->ns > 0)
+    hipLaunchKernelGGL((k_heat_points<D, R>), dim3(cdiv(c->np + c->ns, 256)), dim3(256), 0, s, d, T, done);
+  if (c->ntiles > 0)
+    hipLaunchKernelGGL((k_heat_nodes<D, R>), dim3(c->ntiles), dim3(64), 0, s, d, T, out, done, dot_slot);
+}
+
+template <int D, typename R>
+void do_g2p(mpm_ctx* c, const R* vh, const R* Th, mpm_particles* P, hipStream_t s) {
+  Dev<R>& d = dev<R>(c);
+  if (!P || P->n != c->np) throw ApiError{MPM_EINVAL, "g2p particle count differs from p2g"};
+  if (c->ns > 0) hipLaunchKernelGGL((k_g2p_split<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d, vh);
+  if (c->np > 0)
+    hipLaunchKernelGGL((k_g2p_particles<D, R>), dim3(cdiv(c->np, 256)), dim3(256), 0, s, d, vh, Th, (R*)P->x,
+                       (R*)P->v, (R*)P->A, (R*)P->J, (R*)P->T, (R*)P->gradT);
+}
+
+// Scalar readback helpers -----------------------------------------------------------------
+template <typename R>
+double dot_sync(mpm_ctx* c, const R* a, const R* b, int ncomp, hipStream_t s) {
+  Dev<R>& d = dev<R>(c);
+  int nelem = c->ntiles * 64, nb = krylov_blocks(nelem);
+  hipLaunchKernelGGL(k_dot<R>, dim3(nb), dim3(256), 0, s, (const int*)d.tile_list, nelem, d.nn, ncomp, a, b,
+                     c->part, (const int*)nullptr);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, (const double*)c->part, nb, 1, c->scal + 16);
+  sync_read(c, s, c->scal + 16, c->hbuf, sizeof(double));
+  return c->hbuf[0];
+}
+
+// Jacobi-preconditioned CG with device-side scalars; the host only polls the done flag
+// every `chunk` iterations.  apply(p, Ap, done, dot_slot) must write A p and the partial
+// sums of p . A p into dot_slot.
+template <typename R, class Apply>
+int cg_solve(mpm_ctx* c, Apply&& apply, const R* b, R* x, bool x0_given, const R* diag, R* r, R* z, R* p, R* Ap,
+             int ncomp, double tol_abs, int maxit, hipStream_t s) {
+  Dev<R>& d = dev<R>(c);
+  int nelem = c->ntiles * 64, nb = krylov_blocks(nelem);
+  const int* tl = d.tile_list;
+  if (x0_given) {
+    apply(x, Ap, (const int*)nullptr, -1);
+    hipLaunchKernelGGL(k_cg_start_x0<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, b, (const R*)Ap, diag,
+                       r, z, p, c->part);
+  } else {
+    hipLaunchKernelGGL(k_cg_start<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, b, diag, x, r, z, p,
+                       c->part, 1);
+  }
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, (const double*)c->part, nb, 2, c->scal + 20);
+  hipLaunchKernelGGL(k_cg_init_scal, dim3(1), dim3(1), 0, s, c->cg, (const double*)(c->scal + 20),
+                     tol_abs * tol_abs, maxit);
+  const int* done = &c->cg->done;
+  int chunk = 4;
+  for (int it = 0; it < maxit + chunk; it += chunk) {
+    for (int j = 0; j < chunk; ++j) {
+      apply(p, Ap, done, 0);
+      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, (const double*)c->part, std::max(c->ntiles, 1), 1,
+                         c->scal + 22);
+      hipLaunchKernelGGL(k_cg_pap, dim3(1), dim3(1), 0, s, c->cg, (const double*)(c->scal + 22));
+      hipLaunchKernelGGL(k_cg_update<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, (const CgScal*)c->cg, x,
+                         r, z, (const R*)p, (const R*)Ap, diag, c->part);
+      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, (const double*)c->part, nb, 2, c->scal + 20);
+      hipLaunchKernelGGL(k_cg_scal_after, dim3(1), dim3(1), 0, s, c->cg, (const double*)(c->scal + 20));
+      hipLaunchKernelGGL(k_cg_p<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, (const CgScal*)c->cg,
+                         (const R*)z, p, (int*)nullptr);
+    }
+    sync_read(c, s, c->cg, c->hcg, sizeof(CgScal));
+    if (c->hcg->done) break;
+    chunk = std::min(chunk * 2, 32);
+  }
+  hipLaunchKernelGGL(k_cg_fixup<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, (const CgScal*)c->cg, x,
+                     (const R*)z);
+  if (!(c->hcg->rr == c->hcg->rr)) c->status |= ST_NONFINITE;
+  return c->hcg->iters;
+}
+
+template <int D, typename R>
+void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
+  if (!c->have_p2g) throw ApiError{MPM_EINVAL, "mpm_p2g must run first"};
+  Dev<R>& d = dev<R>(c);
+  const mpm_params& p = c->p;
+  int nelem = c->ntiles * 64, nb = krylov_blocks(nelem);
+  const int* tl = d.tile_list;
+  R* vhat = (R*)c->vhat;
+  R* vtrial = (R*)c->vtrial;
+  R* g = (R*)c->grad;
+  R* delta = (R*)c->delta;
+  mpm_stats& st = c->stats;
+  c->constrained = any_constrained(c, s);
+  const bool fix = p.momentum_fix && !c->constrained;
+  // mass sum for the absolute floor and the translation correction
+  hipLaunchKernelGGL((k_mom_sums<D, R>), dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, (const uint8_t*)d.gfree,
+                     (const R*)d.gm, (const R*)d.gvn, (const R*)d.gvn, c->part);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, (const double*)c->part, nb, 2 * D + 1, c->scal + 32);
+  sync_read(c, s, c->scal + 32, c->hbuf, sizeof(double) * (2 * D + 1));
+  double msum = c->hbuf[D];
+  double floor_abs = 1e-14 * msum * p.dx / p.dt;
+  hipLaunchKernelGGL(k_project_copy<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const uint8_t*)d.gfree,
+                     (const R*)d.gvn, vhat);
+  do_energy_grad<D, R>(c, vhat, g, nullptr, s);
+  double phi = 0;
+  sync_read(c, s, c->scal, &phi, sizeof(double));
+  double gn = std::sqrt(dot_sync<R>(c, g, g, D, s));
+  double g0 = gn;
+  st.g0 = g0;
+  st.energy_evals = 1;
+  st.converged = 0;
+  auto apply = [&](const R* pv, R* Apv, const int* done, int slot) {
+    do_hessvec<D, R>(c, vhat, pv, 1.0, Apv, false, done, slot, s);
+  };
+  int it = 0;
+  double gn_prev = 1e300;
+  for (; it < p.newton_max; ++it) {
+    if (!(gn == gn) || !(phi == phi)) { c->status |= ST_NONFINITE; break; }
+    if (gn <= std::max(p.newton_tol * g0, floor_abs)) { st.converged = 1; break; }
+    // MIXED: the FP32 gradient cannot fall below its own round-off; once |g| is small
+    // (1e-4 |g0|) and a Newton step no longer halves it, the solve has reached that floor.
+    if (sizeof(R) == 4 && gn <= 1e-4 * g0 && gn > 0.5 * gn_prev) { st.converged = 2; break; }
+    gn_prev = gn;
+    hipLaunchKernelGGL(k_neg<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const R*)g, vtrial);
+    double cg_tol = std::max(p.cg_rel * gn, 0.1 * p.newton_tol * g0);
+    int cit = cg_solve<R>(c, apply, vtrial, delta, false, (const R*)d.gdiag, (R*)c->r, (R*)c->z, (R*)c->pp,
+                          (R*)c->Ap, D, cg_tol, p.cg_max, s);
+    st.cg_iters += cit;
+    st.hessvecs += cit;
+    double slope = dot_sync<R>(c, g, delta, D, s);
+    double alpha = 1.0, phit = phi;
+    for (int ls = 0; ls < std::max(p.ls_max, 1); ++ls) {
+      hipLaunchKernelGGL(k_axpy_to<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const R*)vhat,
+                         (const R*)delta, alpha, vtrial);
+      do_energy_grad<D, R>(c, vtrial, (R*)c->gscratch, nullptr, s);
+      sync_read(c, s, c->scal, &phit, sizeof(double));
+      st.energy_evals++;
+      // Armijo with the round-off of Phi as allowance (8 eps |Phi|, eps of the arithmetic):
+      // near convergence the decrement is below it and the test would be decided by noise.
+      const double eps = sizeof(R) == 8 ? 2.220446049250313e-16 : 1.1920928955078125e-07;
+      const double noise = 8.0 * eps * std::max(std::fabs(phi), std::fabs(phit));
+      if (phit <= phi + p.ls_c1 * alpha * slope + noise) break;
+      if (ls + 1 < std::max(p.ls_max, 1)) { alpha *= 0.5; st.line_search_halvings++; }
+    }
+    std::swap(c->vhat, c->vtrial);
+    vhat = (R*)c->vhat;
+    vtrial = (R*)c->vtrial;
+    if (fix) {
+      hipLaunchKernelGGL((k_mom_sums<D, R>), dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, (const uint8_t*)d.gfree,
+                         (const R*)d.gm, (const R*)vhat, (const R*)d.gvn, c->part);
+      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, (const double*)c->part, nb, 2 * D + 1, c->scal + 32);
+      hipLaunchKernelGGL((k_mom_fix<D, R>), dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, (const uint8_t*)d.gfree,
+                         (const double*)(c->scal + 32), p.dt, p.gravity[0], p.gravity[1], p.gravity[2], vhat);
+    }
+    do_energy_grad<D, R>(c, vhat, g, nullptr, s);
+    sync_read(c, s, c->scal, &phi, sizeof(double));
+    st.energy_evals++;
+    gn = std::sqrt(dot_sync<R>(c, g, g, D, s));
+  }
+  if (it == p.newton_max && gn <= std::max(p.newton_tol * g0, floor_abs)) st.converged = 1;
+  st.newton_iters = it;
+  st.gnorm = gn;
+  st.phi = phi;
+  if (!st.converged && !(c->status & ST_NONFINITE)) c->status |= ST_NOCONV;
+  // grid momentum after the solve
+  hipLaunchKernelGGL((k_mom_sums<D, R>), dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, (const uint8_t*)d.gfree,
+                     (const R*)d.gm, (const R*)vhat, (const R*)d.gvn, c->part);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, (const double*)c->part, nb, 2 * D + 1, c->scal + 32);
+  sync_read(c, s, c->scal + 32, c->hbuf, sizeof(double) * (2 * D + 1));
+  for (int a = 0; a < 3; ++a) st.momentum[a] = a < D ? c->hbuf[D + 1 + a] : 0.0;
+}
+
+template <int D, typename R>
+void do_explicit(mpm_ctx* c, hipStream_t s) {
+  if (!c->have_p2g) throw ApiError{MPM_EINVAL, "mpm_p2g must run first"};
+  Dev<R>& d = dev<R>(c);
+  int nelem = c->ntiles * 64, nb = krylov_blocks(nelem);
+  const int* tl = d.tile_list;
+  R* f = (R*)c->grad;
+  R* f2 = (R*)c->gscratch;
+  R* zero = (R*)c->zero;
+  hipLaunchKernelGGL(k_axpy_to<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const R*)d.gvn, (const R*)d.gvn,
+                     -1.0, zero);
+  Dev<R> saved = d;
+  // J and surface terms at y = x (v^ = 0)
+  d.term_mask = saved.term_mask & 3;
+  do_hessvec_force<D, R>(c, zero, f, s);
+  // viscous term at the strain rate of v^n
+  d.term_mask = saved.term_mask & 4;
+  if (d.term_mask) {
+    do_hessvec_force<D, R>(c, (const R*)d.gvn, f2, s);
+    hipLaunchKernelGGL(k_axpy_to<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const R*)f, (const R*)f2, 1.0, f);
+  }
+  d = saved;
+  hipLaunchKernelGGL((k_explicit_update<D, R>), dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, (const uint8_t*)d.gfree,
+                     (const R*)d.gm, (const R*)d.gvn, (const R*)f, (R)c->p.gravity[0], (R)c->p.gravity[1],
+                     (R)c->p.gravity[2], (R)c->p.dt, (R*)c->vhat);
+  c->stats.converged = 1;
+}
+
+template <int D, typename R>
+void do_solve_heat(mpm_ctx* c, hipStream_t s) {
+  if (!c->have_p2g) throw ApiError{MPM_EINVAL, "mpm_p2g must run first"};
+  Dev<R>& d = dev<R>(c);
+  int nelem = c->ntiles * 64, nb = krylov_blocks(nelem);
+  const int* tl = d.tile_list;
+  R* T = (R*)c->That;
+  hipLaunchKernelGGL(k_axpy_to<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, 1, (const R*)d.gTn, (const R*)d.gTn,
+                     0.0, T);
+  double bn = std::sqrt(dot_sync<R>(c, d.hrhs, d.hrhs, 1, s));
+  auto apply = [&](const R* pv, R* Apv, const int* done, int slot) { do_heat_apply<D, R>(c, pv, Apv, done, slot, s); };
+  int it = cg_solve<R>(c, apply, d.hrhs, T, true, (const R*)d.hdiag, (R*)c->hr, (R*)c->hz, (R*)c->hp, (R*)c->hAp, 1,
+                       c->p.heat_tol * bn, c->p.heat_max, s);
+  c->stats.heat_iters = it;
+  c->stats.heat_res = std::sqrt(std::max(c->hcg->rr, 0.0));
+  if (it >= c->p.heat_max && c->hcg->rr > c->hcg->tol2) c->status |= ST_NOCONV;
+}
+
+// ---- dispatch ----------------------------------------------------------------------------
+template <class F>
+void dispatch(mpm_ctx* c, F&& f) {
+  if (c->dim == 3) {
+    if (c->fp64) f(std::integral_constant<int, 3>{}, double{});
+    else f(std::integral_constant<int, 3>{}, float{});
+  } else {
+    if (c->fp64) f(std::integral_constant<int, 2>{}, double{});
+    else f(std::integral_constant<int, 2>{}, float{});
+  }
+}
+
+int status_code(int bits) {
+  if (bits & ST_DOMAIN) return MPM_EDOMAIN;
+  if (bits & ST_NONFINITE) return MPM_ENONFINITE;
+  if (bits & ST_NOCONV) return MPM_ENOCONV;
+  return MPM_OK;
+}
+
+// Message of the last failure that had no context to hold it (mpm_last_error(NULL)).
+thread_local std::string g_last_error;
+
+template <class F>
+int guarded(mpm_ctx* c, F&& f) {
+  std::string& err = c ? c->err : g_last_error;
+  try {
+    f();
+    return MPM_OK;
+  } catch (const ApiError& e) {
+    err = e.msg;
+    return e.code;
+  } catch (const HipError& e) {
+    err = std::string(e.what) + ": " + hipGetErrorString(e.e);
+    return MPM_EHIP;
+  } catch (...) {
+    err = "unexpected exception";
+    return MPM_EHIP;
+  }
+}
+
+int check_launch(mpm_ctx* c) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    c->err = std::string("kernel launch: ") + hipGetErrorString(e);
+    return MPM_EHIP;
+  }
+  return MPM_OK;
+}
+
+}  // namespace
+
+// =========================================================================================
+// C ABI
+// =========================================================================================
+extern "C" {
+
+int mpm_params_default(mpm_params* p, int32_t dim, int32_t n) {
+  if (!p || (dim != 2 && dim != 3) || n <= 0) return MPM_EINVAL;
+  std::memset(p, 0, sizeof(*p));
+  p->dim = dim;
+  p->n = n;
+  p->dx = 1.0 / n;
+  p->dt = 1e-3;
+  p->precision = MPM_FP64;
+  p->hess_mode = MPM_HESS_PSD;
+  p->term_mask = 7;
+  p->momentum_fix = 1;
+  p->slab_axis = 1;
+  p->newton_max = 20;
+  p->cg_max = 1000;
+  p->ls_max = 10;
+  p->heat_max = 1000;
+  p->bulk = 1e4;
+  p->gmax = 1e30;
+  p->cp = 1.0;
+  p->newton_tol = 1e-8;
+  p->cg_rel = 1e-2;
+  p->ls_c1 = 1e-4;
+  p->heat_tol = 1e-10;
+  return MPM_OK;
+}
+
+int mpm_workspace_bytes(const mpm_params* p, int64_t cap_part, int64_t cap_surf, size_t* out_bytes) {
+  return guarded(nullptr, [&] {
+    check_params(p);
+    if (!out_bytes || cap_part < 0 || cap_surf < 0) throw ApiError{MPM_EINVAL, "bad arguments"};
+    if (cap_part > (int64_t)kScanBlock * kScanBlock || cap_surf > (int64_t)kScanBlock * kScanBlock)
+      throw ApiError{MPM_EINVAL, "capacity above 2^24"};
+    mpm_ctx tmp;
+    tmp.p = *p;
+    tmp.dim = p->dim;
+    tmp.n = p->n;
+    tmp.nn = 1;
+    for (int a = 0; a < p->dim; ++a) tmp.nn *= p->n;
+    tmp.ntile_total = tmp.nn / 64;
+    tmp.cap_part = cap_part;
+    tmp.cap_surf = cap_surf;
+    *out_bytes = p->precision == MPM_FP64 ? layout<double>(&tmp, nullptr) : layout<float>(&tmp, nullptr);
+  });
+}
+
+int mpm_ctx_create(const mpm_params* p, void* workspace, size_t ws_bytes, int64_t cap_part, int64_t cap_surf,
+                   mpm_ctx** out) {
+  if (!out) return MPM_EINVAL;
+  *out = nullptr;
+  size_t need = 0;
+  int rc = mpm_workspace_bytes(p, cap_part, cap_surf, &need);
+  if (rc != MPM_OK) return rc;
+  if (!workspace || ws_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255)) return MPM_EINVAL;
+  mpm_ctx* c = new mpm_ctx();
+  rc = guarded(c, [&] {
+    c->p = *p;
+    c->dim = p->dim;
+    c->n = p->n;
+    c->nt = p->n / (p->dim == 3 ? 4 : 8);
+    c->nn = 1;
+    for (int a = 0; a < p->dim; ++a) c->nn *= p->n;
+    c->ntile_total = c->nn / 64;
+    c->cap_part = cap_part;
+    c->cap_surf = cap_surf;
+    c->fp64 = p->precision == MPM_FP64;
+    c->ws = (char*)workspace;
+    c->ws_bytes = ws_bytes;
+    if (c->fp64) {
+      layout<double>(c, c->ws);
+      fill_params(c->d64, *p, c->nt);
+    } else {
+      layout<float>(c, c->ws);
+      fill_params(c->d32, *p, c->nt);
+    }
+    HIPCHK(hipHostMalloc((void**)&c->hbuf, 64 * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&c->hint, 64 * sizeof(int), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&c->hcg, sizeof(CgScal), hipHostMallocDefault));
+    // zero the workspace once (fill kernels; the cell counters must start at zero)
+    hipLaunchKernelGGL(k_fill_i32, dim3(cdiv((int64_t)(need / 4), 256)), dim3(256), 0, 0, (int*)c->ws, 0,
+                       (int64_t)(need / 4));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(0));
+  });
+  if (rc != MPM_OK) {
+    g_last_error = c->err;
+    if (c->hbuf) hipHostFree(c->hbuf);
+    if (c->hint) hipHostFree(c->hint);
+    if (c->hcg) hipHostFree(c->hcg);
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return MPM_OK;
+}
+
+int mpm_ctx_destroy(mpm_ctx* ctx) {
+  if (!ctx) return MPM_EINVAL;
+  if (ctx->hbuf) hipHostFree(ctx->hbuf);
+  if (ctx->hint) hipHostFree(ctx->hint);
+  if (ctx->hcg) hipHostFree(ctx->hcg);
+  delete ctx;
+  return MPM_OK;
+}
+
+const char* mpm_last_error(const mpm_ctx* ctx) { return ctx ? ctx->err.c_str() : g_last_error.c_str(); }
+
+int mpm_ctx_set_params(mpm_ctx* ctx, const mpm_params* p) {
+  if (!ctx) return MPM_EINVAL;
+  return guarded(ctx, [&] {
+    check_params(p);
+    if (p->dim != ctx->dim || p->n != ctx->n || (p->precision == MPM_FP64) != ctx->fp64)
+      throw ApiError{MPM_EINVAL, "dim, n and precision are fixed per context"};
+    ctx->p = *p;
+    if (ctx->fp64) fill_params(ctx->d64, *p, ctx->nt);
+    else fill_params(ctx->d32, *p, ctx->nt);
+  });
+}
+
+int mpm_p2g(mpm_ctx* ctx, const mpm_particles* P, const mpm_surface* S, void* stream) {
+  if (!ctx) return MPM_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  int rc = guarded(ctx, [&] {
+    ctx->status = 0;
+    dispatch(ctx, [&](auto Dc, auto Rv) {
+      constexpr int D = decltype(Dc)::value;
+      using R = decltype(Rv);
+      do_p2g<D, R>(ctx, P, S, s);
+    });
+  });
+  return rc != MPM_OK ? rc : check_launch(ctx);
+}
+
+int mpm_energy_grad(mpm_ctx* ctx, const void* v_hat, double* energy_dev, void* grad, void* stream) {
+  if (!ctx || !v_hat || !grad) return MPM_EINVAL;
+  if (!ctx->have_p2g) { ctx->err = "mpm_p2g must run first"; return MPM_EINVAL; }
+  hipStream_t s = (hipStream_t)stream;
+  int rc = guarded(ctx, [&] {
+    dispatch(ctx, [&](auto Dc, auto Rv) {
+      constexpr int D = decltype(Dc)::value;
+      using R = decltype(Rv);
+      do_energy_grad<D, R>(ctx, (const R*)v_hat, (R*)grad, energy_dev, s);
+    });
+  });
+  return rc != MPM_OK ? rc : check_launch(ctx);
+}
+
+int mpm_hessvec(mpm_ctx* ctx, const void* v_lin, const void* w, double alpha_mass, void* out, void* stream) {
+  if (!ctx || !v_lin || !w || !out) return MPM_EINVAL;
+  if (!ctx->have_p2g) { ctx->err = "mpm_p2g must run first"; return MPM_EINVAL; }
+  hipStream_t s = (hipStream_t)stream;
+  int rc = guarded(ctx, [&] {
+    dispatch(ctx, [&](auto Dc, auto Rv) {
+      constexpr int D = decltype(Dc)::value;
+      using R = decltype(Rv);
+      do_hessvec<D, R>(ctx, (const R*)v_lin, (const R*)w, alpha_mass, (R*)out, true, nullptr, -1, s);
+    });
+  });
+  return rc != MPM_OK ? rc : check_launch(ctx);
+}
+
+int mpm_heat_apply(mpm_ctx* ctx, const void* T_in, void* T_out, void* stream) {
+  if (!ctx || !T_in || !T_out) return MPM_EINVAL;
+  if (!ctx->have_p2g) { ctx->err = "mpm_p2g must run first"; return MPM_EINVAL; }
+  hipStream_t s = (hipStream_t)stream;
+  int rc = guarded(ctx, [&] {
+    dispatch(ctx, [&](auto Dc, auto Rv) {
+      constexpr int D = decltype(Dc)::value;
+      using R = decltype(Rv);
+      do_heat_apply<D, R>(ctx, (const R*)T_in, (R*)T_out, nullptr, -1, s);
+    });
+  });
+  return rc != MPM_OK ? rc : check_launch(ctx);
+}
+
+int mpm_g2p(mpm_ctx* ctx, const void* v_hat, const void* T_hat, mpm_particles* P, void* stream) {
+  if (!ctx || !v_hat || !P) return MPM_EINVAL;
+  if (!ctx->have_p2g) { ctx->err = "mpm_p2g must run first"; return MPM_EINVAL; }
+  hipStream_t s = (hipStream_t)stream;
+  int rc = guarded(ctx, [&] {
+    dispatch(ctx, [&](auto Dc, auto Rv) {
+      constexpr int D = decltype(Dc)::value;
+      using R = decltype(Rv);
+      do_g2p<D, R>(ctx, (const R*)v_hat, (const R*)T_hat, P, s);
+    });
+  });
+  return rc != MPM_OK ? rc : check_launch(ctx);
+}
+
+int mpm_solve_momentum(mpm_ctx* ctx, void* stream) {
+  if (!ctx) return MPM_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  int rc = guarded(ctx, [&] {
+    dispatch(ctx, [&](auto Dc, auto Rv) {
+      constexpr int D = decltype(Dc)::value;
+      using R = decltype(Rv);
+      do_solve_momentum<D, R>(ctx, s);
+    });
+  });
+  if (rc != MPM_OK) return rc;
+  rc = check_launch(ctx);
+  if (rc != MPM_OK) return rc;
+  return mpm_scene_status(ctx, stream);
+}
+
+int mpm_solve_heat(mpm_ctx* ctx, void* stream) {
+  if (!ctx) return MPM_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  int rc = guarded(ctx, [&] {
+    dispatch(ctx, [&](auto Dc, auto Rv) {
+      constexpr int D = decltype(Dc)::value;
+      using R = decltype(Rv);
+      do_solve_heat<D, R>(ctx, s);
+    });
+  });
+  if (rc != MPM_OK) return rc;
+  rc = check_launch(ctx);
+  if (rc != MPM_OK) return rc;
+  return mpm_scene_status(ctx, stream);
+}
+
+int mpm_step(mpm_ctx* const* ctxs, mpm_particles* const* P, const mpm_surface* const* S, int32_t n_scenes,
+             int32_t implicit, void* stream) {
+  if (!ctxs || !P || n_scenes < 0) return MPM_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  int first = MPM_OK;
+  for (int k = 0; k < n_scenes; ++k) {
+    mpm_ctx* c = ctxs[k];
+    if (!c) { if (first == MPM_OK) first = MPM_EINVAL; continue; }
+    int rc = mpm_p2g(c, P[k], S ? S[k] : nullptr, stream);
+    if (rc == MPM_OK) {
+      rc = guarded(c, [&] {
+        dispatch(c, [&](auto Dc, auto Rv) {
+          constexpr int D = decltype(Dc)::value;
+          using R = decltype(Rv);
+          if (implicit) do_solve_momentum<D, R>(c, s);
+          else do_explicit<D, R>(c, s);
+          if (c->p.heat) do_solve_heat<D, R>(c, s);
+          do_g2p<D, R>(c, (const R*)c->vhat, c->p.heat ? (const R*)c->That : nullptr, P[k], s);
+        });
+      });
+    }
+    if (rc == MPM_OK) rc = check_launch(c);
+    int st = mpm_scene_status(c, stream);
+    if (rc == MPM_OK) rc = st;
+    c->stats.status = rc;
+    if (first == MPM_OK && rc != MPM_OK) first = rc;
+  }
+  return first;
+}
+
+int mpm_grid_view(mpm_ctx* ctx, int32_t field, void** out_ptr) {
+  if (!ctx || !out_ptr) return MPM_EINVAL;
+  void* p = nullptr;
+  auto pick = [&](auto& d) {
+    switch (field) {
+      case MPM_F_MASS: p = d.gm; break;
+      case MPM_F_MOM: p = d.gmv; break;
+      case MPM_F_W: p = d.gW; break;
+      case MPM_F_WT: p = d.gWT; break;
+      case MPM_F_E: p = d.gE; break;
+      case MPM_F_ET: p = d.gET; break;
+      case MPM_F_VN: p = d.gvn; break;
+      case MPM_F_TN: p = d.gTn; break;
+      case MPM_F_FREE: p = d.gfree; break;
+      case MPM_F_HEAT_RHS: p = d.hrhs; break;
+      case MPM_F_HEAT_DIAG: p = d.hdiag; break;
+      case MPM_F_VHAT: p = ctx->vhat; break;
+      case MPM_F_THAT: p = ctx->That; break;
+      case MPM_F_PARENT: p = d.s_parent_orig; break;
+      case MPM_F_COUNT: p = d.pcnt_orig; break;
+      case MPM_F_KSURF: p = d.sk_orig; break;
+      case MPM_F_MOM_DIAG: p = d.gdiag; break;
+      default: p = nullptr;
+    }
+  };
+  if (ctx->fp64) pick(ctx->d64); else pick(ctx->d32);
+  if (!p) { ctx->err = "unknown field"; return MPM_EINVAL; }
+  *out_ptr = p;
+  return MPM_OK;
+}
+
+int mpm_get_stats(const mpm_ctx* ctx, mpm_stats* out) {
+  if (!ctx || !out) return MPM_EINVAL;
+  *out = ctx->stats;
+  return MPM_OK;
+}
+
+int mpm_scene_status(mpm_ctx* ctx, void* stream) {
+  if (!ctx) return MPM_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  int rc = guarded(ctx, [&] {
+    sync_read(ctx, s, ctx->misc, ctx->hint, sizeof(int));
+    ctx->status |= ctx->hint[0];
+  });
+  if (rc != MPM_OK) return rc;
+  int code = status_code(ctx->status);
+  if (code == MPM_EDOMAIN) ctx->err = "point outside [dx, 1-dx)^dim";
+  else if (code == MPM_ENONFINITE) ctx->err = "non-finite residual or energy";
+  else if (code == MPM_ENOCONV) ctx->err = "iteration cap reached";
+  return code;
+}
+
+}  // extern "C"

@@ -1,0 +1,207 @@
+"""GPU parity: every ABI call against the oracle on identical seeded inputs.
+
+FP64 mode: 1e-10 relative (norm-wise) on every floating output, bit-exact on integer
+outputs (parents, group sizes, degree-of-freedom masks).  MIXED mode: 1e-4 relative on
+the grid forces (energy gradient); the other outputs are checked at the FP32 level
+stated per test."""
+import numpy as np
+import pytest
+
+from gpu_cases import TOL_FP64, TOL_MIXED_FORCE, GpuState, OracleState, log, make_case, rel
+
+pytestmark = pytest.mark.gpu
+
+CASES = [("random", 2, 1), ("random", 3, 2), ("square2d", 2, 0), ("marangoni3d_small", 3, 0)]
+
+
+def _case(kind, dim, seed, precision, **kw):
+    if kind == "marangoni3d_small":
+        import mpm_scenes as sc
+        from oracle import sampler
+        S = sc.marangoni3d(n=32, radius=0.25)
+        P, p = S["particles"], dict(S["params"], **kw)
+        surf = sampler.sample_surface(P["x"], p)
+        from gpu_cases import round_inputs
+        P, surf = round_inputs(P, surf, precision)
+    elif kind == "square2d":
+        P, surf, p = make_case("square2d", n=32, precision=precision, **kw)
+    else:
+        P, surf, p = make_case(kind, dim=dim, seed=seed, precision=precision, **kw)
+    return P, surf, p
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("kind,dim,seed", CASES)
+def test_p2g_parity(kind, dim, seed, precision):
+    log(f"case p2g {kind} dim={dim} seed={seed} {precision}")
+    P, surf, p = _case(kind, dim, seed, precision)
+    o = OracleState(P, surf, p)
+    g = GpuState(P, surf, p, precision)
+    from paper_2101_12408_amd import _lib as L
+    sc_ = g.scene
+    tol = TOL_FP64 if precision == "fp64" else 2e-5
+    # integer outputs: bit-exact
+    assert np.array_equal(sc_.view(L.F_PARENT).cpu().numpy(), o.split["parent"])
+    assert np.array_equal(sc_.view(L.F_COUNT).cpu().numpy(), o.split["count"])
+    free = g.to_natural(sc_.view(L.F_FREE))
+    assert np.array_equal((free & 0x80) != 0, o.setup["dof"])
+    for a in range(dim):
+        assert np.array_equal(((free >> a) & 1) != 0, o.setup["free"][:, a])
+    for f, ref in ((L.F_MASS, o.grid["m"]), (L.F_MOM, o.grid["mv"]), (L.F_W, o.grid["W"]),
+                   (L.F_WT, o.grid["WT"]), (L.F_E, o.grid["E"]), (L.F_ET, o.grid["ET"]),
+                   (L.F_VN, o.setup["vn"]), (L.F_TN, o.setup["Tn"])):
+        got = g.to_natural(sc_.view(f))
+        e = rel(got, ref)
+        log(f"  field {f}: rel {e:.3e}")
+        assert e < tol, (f, e)
+    k = sc_.view(L.F_KSURF).cpu().numpy()
+    assert rel(k, o.setup["k"]) < tol
+    # heat system: right side and diagonal; Newton diagonal
+    dof = o.setup["dof"]
+    assert rel(g.to_natural(sc_.view(L.F_HEAT_RHS))[dof], o.heat.rhs[dof]) < tol
+    assert rel(g.to_natural(sc_.view(L.F_HEAT_DIAG))[dof], o.heat.diag()[dof]) < tol
+    md = g.to_natural(sc_.view(L.F_MOM_DIAG))
+    assert rel(md[o.setup["free"]], o.ctx.jacobi_diag()[o.setup["free"]]) < tol
+
+
+def _rand_field(o, seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    return rng.normal(size=o.ctx.vn.shape) * scale * o.setup["dof"][:, None]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("kind,dim,seed", CASES)
+def test_energy_grad_parity(kind, dim, seed, precision):
+    log(f"case energy_grad {kind} dim={dim} seed={seed} {precision}")
+    P, surf, p = _case(kind, dim, seed, precision)
+    o = OracleState(P, surf, p)
+    g = GpuState(P, surf, p, precision)
+    v = o.setup["vn"] + _rand_field(o, seed + 5, 0.3)
+    if precision != "fp64":
+        v = v.astype(np.float32).astype(np.float64)
+    vd = g.from_natural(v)
+    grad = g.scene.grid_vector()
+    e = g.scene.energy_grad(vd, grad)
+    ref_g = o.ctx.project(o.ctx.grad_Phi(v))
+    got_g = g.to_natural(grad)
+    eg = rel(got_g[o.setup["dof"]], ref_g[o.setup["dof"]])
+    phi = float(e.cpu().numpy()[0])
+    ref_phi = o.ctx.Phi(v)
+    log(f"  grad rel {eg:.3e}  phi {phi:.12e} ref {ref_phi:.12e}")
+    tol = TOL_FP64 if precision == "fp64" else TOL_MIXED_FORCE
+    assert eg < tol
+    assert abs(phi - ref_phi) <= (TOL_FP64 if precision == "fp64" else 1e-5) * max(abs(ref_phi), 1e-300)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("hess_mode", [0, 1])
+@pytest.mark.parametrize("kind,dim,seed", CASES)
+def test_hessvec_parity(kind, dim, seed, precision, hess_mode):
+    log(f"case hessvec {kind} dim={dim} seed={seed} {precision} mode={hess_mode}")
+    P, surf, p = _case(kind, dim, seed, precision, hess_mode=hess_mode)
+    o = OracleState(P, surf, p)
+    g = GpuState(P, surf, p, precision)
+    vl = o.setup["vn"] + _rand_field(o, seed + 7, 0.3)
+    w = _rand_field(o, seed + 8)
+    if precision != "fp64":
+        vl = vl.astype(np.float32).astype(np.float64)
+        w = w.astype(np.float32).astype(np.float64)
+    out = g.scene.grid_vector()
+    for alpha in (1.0, 0.0):
+        g.scene.hessvec(g.from_natural(vl), g.from_natural(w), alpha, out)
+        ref = o.ctx.project(o.ctx.hessvec(vl, o.ctx.project(w), alpha))
+        got = g.to_natural(out)
+        e = rel(got[o.setup["dof"]], ref[o.setup["dof"]])
+        log(f"  alpha {alpha}: rel {e:.3e}")
+        assert e < (TOL_FP64 if precision == "fp64" else 1e-4)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("kind,dim,seed", CASES)
+def test_heat_apply_parity(kind, dim, seed, precision):
+    log(f"case heat_apply {kind} dim={dim} seed={seed} {precision}")
+    P, surf, p = _case(kind, dim, seed, precision, heat=1, K=0.3, h=4.0)
+    o = OracleState(P, surf, p)
+    g = GpuState(P, surf, p, precision)
+    rng = np.random.default_rng(seed + 11)
+    T = (300 + rng.normal(size=o.setup["Tn"].shape) * 10) * o.setup["dof"]
+    if precision != "fp64":
+        T = T.astype(np.float32).astype(np.float64)
+    out = g.scene.grid_vector(1)[0]
+    g.scene.heat_apply(g.from_natural(T), out)
+    ref = o.heat.apply(T)
+    got = g.to_natural(out)
+    e = rel(got[o.setup["dof"]], ref[o.setup["dof"]])
+    log(f"  rel {e:.3e}")
+    assert e < (TOL_FP64 if precision == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("kind,dim,seed", CASES)
+def test_g2p_parity(kind, dim, seed, precision):
+    log(f"case g2p {kind} dim={dim} seed={seed} {precision}")
+    P, surf, p = _case(kind, dim, seed, precision)
+    o = OracleState(P, surf, p)
+    g = GpuState(P, surf, p, precision)
+    vh = o.ctx.project(o.setup["vn"] + _rand_field(o, seed + 13, 0.3))
+    rng = np.random.default_rng(seed + 14)
+    Th = (300 + rng.normal(size=o.setup["Tn"].shape)) * o.setup["dof"]
+    if precision != "fp64":
+        vh = vh.astype(np.float32).astype(np.float64)
+        Th = Th.astype(np.float32).astype(np.float64)
+    ref = transfer_g2p(o, vh, Th)
+    g.scene.g2p(g.from_natural(vh), g.from_natural(Th), g.Pd)
+    N = len(P["m"])
+    d = dim
+    got = dict(x=g.Pd["x"].cpu().numpy().T, v=g.Pd["v"].cpu().numpy().T,
+               A=g.Pd["A"].cpu().numpy().T.reshape(N, d, d), J=g.Pd["J"].cpu().numpy(),
+               T=g.Pd["T"].cpu().numpy(), gradT=g.Pd["gradT"].cpu().numpy().T)
+    tol = TOL_FP64 if precision == "fp64" else 1e-4
+    for k in ("v", "A", "J", "T", "gradT", "x"):
+        if k == "x" and precision == "fp64":
+            e = rel(got[k] - P["x"], ref[k] - P["x"])
+        elif k == "x":
+            e = rel(got[k], ref[k])        # float32 storage of x bounds the displacement error
+        elif k == "J":
+            e = rel(got[k] - P["J"], ref[k] - P["J"])
+        else:
+            e = rel(got[k], ref[k])
+        log(f"  {k}: rel {e:.3e}")
+        assert e < tol, k
+
+
+def transfer_g2p(o, vh, Th):
+    from oracle import transfer
+    return transfer.g2p(o.P, o.surf, o.split, vh, Th, o.p)
+
+
+def test_determinism_bitwise():
+    log("case determinism")
+    P, surf, p = _case("random", 3, 4, "mixed")
+    o = OracleState(P, surf, p)
+    outs = []
+    for rep in range(2):
+        g = GpuState(P, surf, p, "mixed")
+        w = g.from_natural(_rand_field(o, 3))
+        out = g.scene.grid_vector()
+        g.scene.hessvec(w, w, 1.0, out)
+        from paper_2101_12408_amd import _lib as L
+        outs.append((out.cpu().numpy().copy(), g.scene.view(L.F_MOM).cpu().numpy().copy()))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_domain_error_is_reported():
+    log("case domain error")
+    from paper_2101_12408_amd import _lib as L
+    from paper_2101_12408_amd.api import MpmError
+    P, surf, p = _case("random", 3, 5, "fp64")
+    P = dict(P)
+    P["x"] = P["x"].copy()
+    P["x"][3] = [0.5 / p["n"], 0.5, 0.5]           # stencil would leave the grid
+    g = None
+    from paper_2101_12408_amd import api
+    sc_ = api.Scene(p, cap_part=len(P["m"]), cap_surf=len(surf["s"]))
+    Pd, Sd = sc_.to_device(P, surf)
+    sc_.p2g(Pd, Sd)
+    assert sc_.status() == L.MPM_EDOMAIN

@@ -1,0 +1,155 @@
+"""GPU end-to-end: one full step (split, P2G, Newton-CG, heat CG, G2P) against the oracle,
+conservation under explicit stepping (Section 6.1), momentum with the translation
+correction, and batch invariance of mpm_step.
+
+End-to-end parity is bounded by the solver tolerances, not by the arithmetic: both
+sides stop Newton at |g| <= tol |g0| with tol = 1e-12 here, so the velocities agree to
+about 1e-8 relative.  The single operators are checked at 1e-10 in test_gpu_parity."""
+import numpy as np
+import pytest
+
+import mpm_scenes as sc
+from gpu_cases import log, rel, round_inputs
+from oracle import sampler, step as ostep
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_step(P, surf, p, precision="fp64", implicit=True):
+    from paper_2101_12408_amd import api
+    s = api.Scene(p, cap_part=len(P["m"]), cap_surf=max(1, len(surf["s"])), precision=precision)
+    Pd, Sd = s.to_device(P, surf)
+    rc = s.step(Pd, Sd, implicit=implicit, check=False)
+    N, d = len(P["m"]), p["dim"]
+    out = dict(x=Pd["x"].cpu().numpy().T.astype(np.float64), v=Pd["v"].cpu().numpy().T.astype(np.float64),
+               A=Pd["A"].cpu().numpy().T.reshape(N, d, d).astype(np.float64),
+               J=Pd["J"].cpu().numpy().astype(np.float64), T=Pd["T"].cpu().numpy().astype(np.float64),
+               gradT=Pd["gradT"].cpu().numpy().T.astype(np.float64), m=P["m"], V0=P["V0"])
+    return out, s.stats(), rc
+
+
+TIGHT = dict(newton_tol=1e-12, cg_rel=1e-3, heat_tol=1e-13)
+
+
+@pytest.mark.parametrize("case", ["square2d", "marangoni3d_small", "meltslab_small"])
+def test_implicit_step_matches_oracle_fp64(case):
+    log(f"case step {case}")
+    if case == "square2d":
+        S = sc.square2d(n=32)
+        rng = np.random.default_rng(1)
+        S["particles"]["v"] = rng.normal(size=S["particles"]["v"].shape) * 0.05
+    elif case == "marangoni3d_small":
+        S = sc.marangoni3d(n=32, radius=0.25)
+    else:
+        S = sc.meltslab3d(n=32)
+    P, p = S["particles"], dict(S["params"], **TIGHT)
+    surf = sampler.sample_surface(P["x"], p)
+    ref, info = ostep.step(P, p, surf)
+    got, st, rc = _gpu_step(P, surf, p)
+    log(f"  gpu newton {st['newton_iters']} cg {st['cg_iters']} heat {st['heat_iters']} rc {rc}; "
+        f"oracle newton {info['newton']} cg {info['cg']} heat {info.get('heat_cg')}")
+    assert rc == 0
+    for k in ("v", "A", "J", "x", "T", "gradT"):
+        if k in ("x", "J"):
+            e = rel(got[k] - P[k], ref[k] - P[k])
+        else:
+            e = rel(got[k], ref[k])
+        log(f"  {k}: rel {e:.3e}")
+        assert e < 1e-7, k
+
+
+def test_mixed_step_error_report():
+    """MIXED mode step against the FP64 oracle: reported, bounded at the FP32 level."""
+    S = sc.marangoni3d(n=32, radius=0.25)
+    P, p = S["particles"], dict(S["params"], newton_tol=1e-6)
+    surf = sampler.sample_surface(P["x"], p)
+    P32, surf32 = round_inputs(P, surf, "mixed")
+    ref, info = ostep.step(P32, p, surf32)
+    got, st, rc = _gpu_step(P32, surf32, p, precision="mixed")
+    assert rc == 0
+    for k in ("v", "A", "T"):
+        e = rel(got[k], ref[k])
+        log(f"  mixed {k}: rel {e:.3e}")
+        assert e < 1e-3, k
+
+
+def _momenta(P, dx):
+    m = P["m"]
+    mom = (m[:, None] * P["v"]).sum(0)
+    x, v, A = P["x"], P["v"], P["A"]
+    L = np.sum(m * (x[:, 0] * v[:, 1] - x[:, 1] * v[:, 0])) + np.sum(m * (A[:, 1, 0] - A[:, 0, 1])) * dx * dx / 4
+    com = (m[:, None] * x).sum(0) / m.sum()
+    return mom, L, com
+
+
+def test_explicit_steps_conserve_on_gpu():
+    """Section 6.1 on the GPU path: 2D ellipse, explicit stepping, surface tension only;
+    linear and angular momentum and the centre of mass are conserved to round-off."""
+    from paper_2101_12408_amd import api
+    p = sc.make_params(dim=2, n=64, dt=1e-5, bulk=4166.67, g0=0.1, seed=6)
+    rng = np.random.default_rng(6)
+    cells = np.stack(np.meshgrid(np.arange(16, 48), np.arange(16, 48), indexing="xy"), -1).reshape(-1, 2)
+    x = (cells[:, None, :] + rng.uniform(0, 1, size=(len(cells), 8, 2))).reshape(-1, 2) / 64
+    x = x[((x[:, 0] - 0.5) / 0.2) ** 2 + ((x[:, 1] - 0.5) / 0.12) ** 2 < 1]
+    P = sc.particles_from_positions(x, 2, p["dx"], ppc=8)
+    s = api.Scene(p, cap_part=len(x), cap_surf=20 * len(x), precision="fp64")
+    Pd = s.to_device(P)
+    hist = []
+    for k in range(10):
+        xh = Pd["x"].cpu().numpy().T.copy()
+        surf = api.sample_surface(xh, p, step=k)
+        Sd = s.to_device(S=surf)
+        s.step(Pd, Sd, implicit=False)
+        Q = dict(m=P["m"], x=Pd["x"].cpu().numpy().T, v=Pd["v"].cpu().numpy().T,
+                 A=Pd["A"].cpu().numpy().T.reshape(-1, 2, 2))
+        hist.append(_momenta(Q, p["dx"]))
+    scale = np.abs(P["m"][:, None] * Q["v"]).sum()
+    log(f"  momentum scale {scale:.3e}; final mom {hist[-1][0]}, L {hist[-1][1]:.3e}")
+    assert scale > 0
+    for mom, L, com in hist:
+        assert np.all(np.abs(mom) < 1e-13 * scale)
+        assert abs(L) < 1e-13 * scale
+        assert np.allclose(com, hist[0][2], rtol=0, atol=1e-13)
+
+
+def test_implicit_momentum_fix_conserves():
+    from paper_2101_12408_amd import api
+    S = sc.square2d(n=32)
+    P, p = S["particles"], S["params"]
+    rng = np.random.default_rng(2)
+    P["v"] = rng.normal(size=P["v"].shape) * 0.05
+    mom0 = (P["m"][:, None] * P["v"]).sum(0)
+    s = api.Scene(p, cap_part=len(P["m"]), cap_surf=20 * len(P["m"]))
+    Pd = s.to_device(P)
+    for k in range(3):
+        surf = api.sample_surface(Pd["x"].cpu().numpy().T.copy(), p, step=k)
+        s.step(Pd, s.to_device(S=surf), implicit=True)
+    v = Pd["v"].cpu().numpy().T
+    mom = (P["m"][:, None] * v).sum(0)
+    log(f"  momentum {mom0} -> {mom}")
+    assert np.allclose(mom, mom0, rtol=0, atol=1e-14 * np.abs(P["m"][:, None] * v).sum())
+
+
+def test_batch_invariance_bitwise():
+    """A scene stepped alone and inside a batch gives bitwise-identical results."""
+    from paper_2101_12408_amd import api
+    scenes = [sc.droplet3d(16, 11, 0.05, [40, 0, 0]), sc.droplet3d(32, 12, 0.03, [0, 30, 10])]
+    runs = []
+    for batch in (False, True):
+        outs = []
+        objs, Ps, Ss = [], [], []
+        for S in scenes:
+            P, p = S["particles"], S["params"]
+            surf = api.sample_surface(P["x"], p)
+            s = api.Scene(p, cap_part=len(P["m"]), cap_surf=len(surf["s"]), precision="mixed")
+            Pd, Sd = s.to_device(P, surf)
+            objs.append(s); Ps.append(Pd); Ss.append(Sd)
+        if batch:
+            api.mpm_step(objs, Ps, Ss)
+        else:
+            for s, Pd, Sd in zip(objs, Ps, Ss):
+                s.step(Pd, Sd)
+        runs.append([{k: v.cpu().numpy().copy() for k, v in Pd.items()} for Pd in Ps])
+    for a, b in zip(runs[0], runs[1]):
+        for k in a:
+            assert np.array_equal(a[k], b[k]), k
