@@ -145,6 +145,26 @@ enum mpm_field {
   MPM_F_MOM_DIAG = 16 /* Jacobi diagonal of the Newton matrix  real [dim][n^dim]        */
 };
 
+/* Kernel classes timed by mpm_timing (HIP events on the launch stream). */
+enum mpm_kernel_class {
+  MPM_K_SORT = 0,        /* cell keys, scans, slot scatter, per-cell order              */
+  MPM_K_SETUP = 1,       /* staging, parents, split, balance points, tiles, k_r         */
+  MPM_K_P2G = 2,         /* P2G node gather with the grid set-up                        */
+  MPM_K_ENERGY_INT = 3,  /* energy/gradient point phase, interior particles             */
+  MPM_K_ENERGY_SURF = 4, /* energy/gradient point phase, surface samples                */
+  MPM_K_ENERGY_NODE = 5, /* energy/gradient node phase                                  */
+  MPM_K_HESS_INT = 6,    /* Hessian-vector product point phase, interior particles      */
+  MPM_K_HESS_SURF = 7,   /* Hessian-vector product point phase, surface samples         */
+  MPM_K_HESS_NODE = 8,   /* Hessian-vector product node phase                           */
+  MPM_K_HEAT_PT = 9,     /* heat operator point phase                                   */
+  MPM_K_HEAT_NODE = 10,  /* heat operator node phase                                    */
+  MPM_K_G2P_SPLIT = 11,  /* G2P moments of surface and balance points                   */
+  MPM_K_G2P = 12,        /* G2P with merge and advection                                */
+  MPM_K_BLAS = 13,       /* Krylov vector updates and dot products                      */
+  MPM_K_REDUCE = 14,     /* single-block final reductions and scalar updates            */
+  MPM_K_COUNT = 15
+};
+
 /* Node numbering helper (tile-major order described above). */
 static inline int64_t mpm_node_index(int32_t dim, int32_t n, int32_t i0, int32_t i1, int32_t i2) {
   const int32_t E = (dim == 3) ? 4 : 8;
@@ -218,6 +238,12 @@ int mpm_step(mpm_ctx* const* ctxs, mpm_particles* const* P, const mpm_surface* c
 /* Device pointer of a grid field of the last mpm_p2g / solve (see mpm_field). */
 int mpm_grid_view(mpm_ctx* ctx, int32_t field, void** out_ptr);
 int mpm_get_stats(const mpm_ctx* ctx, mpm_stats* out);
+/* Timing of the context's kernels by class: enable = 1 starts (and resets) recording of a
+ * HIP event pair around every launch on the call's stream, 0 stops it.  Host only. */
+int mpm_timing(mpm_ctx* ctx, int32_t enable);
+/* Synchronizes on the recorded events and returns, per kernel class, the summed
+ * duration in milliseconds (ms[MPM_K_COUNT]) and the number of launches. */
+int mpm_timing_read(mpm_ctx* ctx, double* ms, int64_t* launches);
 /* Latched device status of the context (synchronizes the stream). */
 int mpm_scene_status(mpm_ctx* ctx, void* stream);
 

@@ -64,11 +64,16 @@ EXPORTS = {
                            C.POINTER(C.POINTER(MpmSurface)), C.c_int32, C.c_int32, C.c_void_p]),
     "mpm_grid_view": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]),
     "mpm_get_stats": (C.c_int, [C.c_void_p, C.POINTER(MpmStats)]),
+    "mpm_timing": (C.c_int, [C.c_void_p, C.c_int32]),
+    "mpm_timing_read": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "mpm_scene_status": (C.c_int, [C.c_void_p, C.c_void_p]),
     "mpm_sample_surface": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_int64, C.c_double, C.c_double,
                                      C.c_uint64, C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]),
 }
+
+KERNEL_CLASSES = ["sort", "setup", "p2g", "energy_int", "energy_surf", "energy_node", "hess_int",
+                  "hess_surf", "hess_node", "heat_pt", "heat_node", "g2p_split", "g2p", "blas", "reduce"]
 
 _lib = None
 

@@ -233,6 +233,17 @@ class Scene:
         out["momentum"] = list(st.momentum)
         return out
 
+    def timing(self, enable=True):
+        """Starts (and resets) or stops per-kernel-class HIP-event timing."""
+        _check(self.lib.mpm_timing(self.ctx, 1 if enable else 0), self.lib, self.ctx)
+
+    def timing_read(self):
+        """{kernel class: (total ms, launches)} since timing was enabled."""
+        ms = (C.c_double * len(L.KERNEL_CLASSES))()
+        cnt = (C.c_int64 * len(L.KERNEL_CLASSES))()
+        _check(self.lib.mpm_timing_read(self.ctx, C.cast(ms, C.c_void_p), C.cast(cnt, C.c_void_p)), self.lib, self.ctx)
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(L.KERNEL_CLASSES)}
+
     def view(self, field, count=None):
         """Workspace field as a tensor view (no copy)."""
         torch = self.torch

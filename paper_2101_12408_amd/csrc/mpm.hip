@@ -51,8 +51,19 @@ struct Bump {
 
 }  // namespace
 
+// Per-kernel-class timing with HIP events recorded on the launch stream.
+struct Prof {
+  bool on = false;
+  std::vector<hipEvent_t> ev;      // pairs (start, stop)
+  std::vector<int> cls;
+  size_t used = 0;
+  double ms[MPM_K_COUNT] = {};
+  int64_t launches[MPM_K_COUNT] = {};
+};
+
 struct mpm_ctx {
   mpm_params p;
+  Prof prof;
   int dim = 3, n = 0, nt = 0, nn = 0, ntile_total = 0;
   int64_t cap_part = 0, cap_surf = 0;
   bool fp64 = true;
@@ -84,6 +95,47 @@ struct mpm_ctx {
 };
 
 namespace {
+
+void prof_begin(mpm_ctx* c, int cls, hipStream_t s, hipEvent_t* stop) {
+  Prof& pr = c->prof;
+  if (pr.used * 2 + 2 > pr.ev.size()) {
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    pr.ev.push_back(a);
+    pr.ev.push_back(b);
+    pr.cls.push_back(0);
+  }
+  pr.cls[pr.used] = cls;
+  HIPCHK(hipEventRecord(pr.ev[2 * pr.used], s));
+  *stop = pr.ev[2 * pr.used + 1];
+  pr.used++;
+}
+
+void prof_collect(mpm_ctx* c) {
+  Prof& pr = c->prof;
+  for (size_t k = 0; k < pr.used; ++k) {
+    HIPCHK(hipEventSynchronize(pr.ev[2 * k + 1]));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, pr.ev[2 * k], pr.ev[2 * k + 1]));
+    pr.ms[pr.cls[k]] += ms;
+    pr.launches[pr.cls[k]] += 1;
+  }
+  pr.used = 0;
+}
+
+// Launch on stream s (in scope), timed as kernel class cls when timing is on.
+#define LAUNCH(c, cls, ...)                                       \
+  do {                                                            \
+    if ((c)->prof.on) {                                           \
+      hipEvent_t stop_;                                           \
+      prof_begin((c), (cls), s, &stop_);                          \
+      hipLaunchKernelGGL(__VA_ARGS__);                            \
+      HIPCHK(hipEventRecord(stop_, s));                           \
+    } else {                                                      \
+      hipLaunchKernelGGL(__VA_ARGS__);                            \
+    }                                                             \
+  } while (0)
 
 template <typename R>
 size_t layout(mpm_ctx* c, char* base) {
@@ -163,23 +215,23 @@ void check_params(const mpm_params* p) {
 void scan(mpm_ctx* c, const int* in, int* out, int len, hipStream_t s) {
   int nb = cdiv(len, kScanBlock);
   if (nb > kScanBlock) throw ApiError{MPM_EINVAL, "scan length above 2^24"};
-  if (len > 0) hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(kScanT), 0, s, in, out, len, c->scan_bsum);
-  else hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(1), 0, s, c->scan_bsum, 0, (int64_t)1);
-  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanT), 0, s, c->scan_bsum, std::max(nb, 1), out + len);
-  if (len > 0) hipLaunchKernelGGL(k_scan_add, dim3(cdiv(len, 256)), dim3(256), 0, s, out, len, (const int*)c->scan_bsum);
+  if (len > 0) LAUNCH(c, MPM_K_SORT, k_scan_local, dim3(nb), dim3(kScanT), 0, s, in, out, len, c->scan_bsum);
+  else LAUNCH(c, MPM_K_SORT, k_fill_i32, dim3(1), dim3(1), 0, s, c->scan_bsum, 0, (int64_t)1);
+  LAUNCH(c, MPM_K_SORT, k_scan_sums, dim3(1), dim3(kScanT), 0, s, c->scan_bsum, std::max(nb, 1), out + len);
+  if (len > 0) LAUNCH(c, MPM_K_SORT, k_scan_add, dim3(cdiv(len, 256)), dim3(256), 0, s, out, len, (const int*)c->scan_bsum);
 }
 
 // Stable cell sort of cnt points: perm (sorted slot -> input index) and start[nn+1].
 template <int D, typename R>
 void cell_sort(mpm_ctx* c, Dev<R>& d, const R* pos, int cnt, int* key, int* perm, int* start, hipStream_t s) {
   if (cnt > 0)
-    hipLaunchKernelGGL((k_cell_keys<D, R>), dim3(cdiv(cnt, 256)), dim3(256), 0, s, pos, cnt, d.n, d.nt, d.fn, key,
+    LAUNCH(c, MPM_K_SORT, (k_cell_keys<D, R>), dim3(cdiv(cnt, 256)), dim3(256), 0, s, pos, cnt, d.n, d.nt, d.fn, key,
                        d.ccount, d.status);
   scan(c, d.ccount, start, d.nn, s);
   if (cnt > 0) {
-    hipLaunchKernelGGL(k_cell_scatter, dim3(cdiv(cnt, 256)), dim3(256), 0, s, (const int*)key, cnt,
+    LAUNCH(c, MPM_K_SORT, k_cell_scatter, dim3(cdiv(cnt, 256)), dim3(256), 0, s, (const int*)key, cnt,
                        (const int*)start, d.ccount, perm);
-    hipLaunchKernelGGL(k_segment_order, dim3(cdiv(d.nn, 256)), dim3(256), 0, s, (const int*)start, d.nn, perm);
+    LAUNCH(c, MPM_K_SORT, k_segment_order, dim3(cdiv(d.nn, 256)), dim3(256), 0, s, (const int*)start, d.nn, perm);
   }
 }
 
@@ -211,46 +263,46 @@ void do_p2g(mpm_ctx* c, const mpm_particles* P, const mpm_surface* S, hipStream_
   d.ns = c->ns;
   // clear the previous step's tiles so that views read zero outside the new active set
   if (c->prev_ntiles > 0) {
-    hipLaunchKernelGGL((k_clear_tiles<D, R>), dim3(c->prev_ntiles), dim3(64), 0, s, d, (const int*)d.tile_list,
+    LAUNCH(c, MPM_K_SETUP, (k_clear_tiles<D, R>), dim3(c->prev_ntiles), dim3(64), 0, s, d, (const int*)d.tile_list,
                        (R* const*)nullptr, 0, 0);
   }
-  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, c->misc, 0, (int64_t)8);
+  LAUNCH(c, MPM_K_SORT, k_fill_i32, dim3(1), dim3(64), 0, s, c->misc, 0, (int64_t)8);
   // A0: bin interior particles by cell and stage them in cell order
   cell_sort<D, R>(c, d, (const R*)P->x, c->np, d.p_key, d.p_perm, d.p_start, s);
   if (c->np > 0)
-    hipLaunchKernelGGL((k_gather_particles<D, R>), dim3(cdiv(c->np, 256)), dim3(256), 0, s, d, (const R*)P->x,
+    LAUNCH(c, MPM_K_SETUP, (k_gather_particles<D, R>), dim3(cdiv(c->np, 256)), dim3(256), 0, s, d, (const R*)P->x,
                        (const R*)P->v, (const R*)P->A, (const R*)P->J, (const R*)P->V0, (const R*)P->m,
                        (const R*)P->T, (const R*)P->gradT);
   // A1: surface samples, parents, split masses, balance points, groups
   if (c->ns > 0) {
     cell_sort<D, R>(c, d, (const R*)S->s, c->ns, d.s_key, d.s_perm, d.s_start, s);
-    hipLaunchKernelGGL((k_gather_surface<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d, (const R*)S->s,
+    LAUNCH(c, MPM_K_SETUP, (k_gather_surface<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d, (const R*)S->s,
                        (const R*)S->dA, S->label);
-    hipLaunchKernelGGL((k_parents<D, R>), dim3(cdiv(c->ns, 64)), dim3(64), 0, s, d);
+    LAUNCH(c, MPM_K_SETUP, (k_parents<D, R>), dim3(cdiv(c->ns, 64)), dim3(64), 0, s, d);
   }
-  if (c->np > 0) hipLaunchKernelGGL((k_split_mass<R>), dim3(cdiv(c->np, 256)), dim3(256), 0, s, d);
+  if (c->np > 0) LAUNCH(c, MPM_K_SETUP, (k_split_mass<R>), dim3(cdiv(c->np, 256)), dim3(256), 0, s, d);
   scan(c, d.pcnt, d.grp_start, c->np, s);
   if (c->ns > 0) {
-    hipLaunchKernelGGL((k_balance<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d);
-    hipLaunchKernelGGL(k_segment_order, dim3(cdiv(c->np, 256)), dim3(256), 0, s, (const int*)d.grp_start, c->np,
+    LAUNCH(c, MPM_K_SETUP, (k_balance<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d);
+    LAUNCH(c, MPM_K_SORT, k_segment_order, dim3(cdiv(c->np, 256)), dim3(256), 0, s, (const int*)d.grp_start, c->np,
                        d.grp);
     cell_sort<D, R>(c, d, (const R*)d.bx_unsorted, c->ns, d.b_key, d.b_src, d.b_start, s);
-    hipLaunchKernelGGL((k_gather_balance<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d);
+    LAUNCH(c, MPM_K_SETUP, (k_gather_balance<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d);
   }
   // active tiles
-  hipLaunchKernelGGL((k_mark_tiles<D, R>), dim3(cdiv(d.nn, 256)), dim3(256), 0, s, d);
+  LAUNCH(c, MPM_K_SETUP, (k_mark_tiles<D, R>), dim3(cdiv(d.nn, 256)), dim3(256), 0, s, d);
   scan(c, d.tile_flag, c->tile_pos, c->ntile_total, s);
-  hipLaunchKernelGGL(k_compact_tiles, dim3(cdiv(c->ntile_total, 256)), dim3(256), 0, s, (const int*)d.tile_flag,
+  LAUNCH(c, MPM_K_SETUP, k_compact_tiles, dim3(cdiv(c->ntile_total, 256)), dim3(256), 0, s, (const int*)d.tile_flag,
                      (const int*)c->tile_pos, c->ntile_total, d.tile_list);
   sync_read(c, s, c->tile_pos + c->ntile_total, c->hint, sizeof(int));
   c->ntiles = c->hint[0];
   c->prev_ntiles = c->ntiles;
   // A2/A3: P2G and grid set-up
-  if (c->ntiles > 0) hipLaunchKernelGGL((k_p2g_nodes<D, R>), dim3(c->ntiles), dim3(64), 0, s, d);
-  if (c->ns > 0) hipLaunchKernelGGL((k_surface_k<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d);
+  if (c->ntiles > 0) LAUNCH(c, MPM_K_P2G, (k_p2g_nodes<D, R>), dim3(c->ntiles), dim3(64), 0, s, d);
+  if (c->ns > 0) LAUNCH(c, MPM_K_SETUP, (k_surface_k<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d);
   // degrees of freedom and whether any of them has a fixed component
   if (c->ntiles > 0)
-    hipLaunchKernelGGL((k_dof_flags<D>), dim3(c->ntiles), dim3(64), 0, s, (const int*)d.tile_list,
+    LAUNCH(c, MPM_K_SETUP, (k_dof_flags<D>), dim3(c->ntiles), dim3(64), 0, s, (const int*)d.tile_list,
                        (const uint8_t*)d.gfree, c->misc);
   c->have_p2g = true;
   c->stats = mpm_stats{};
@@ -273,22 +325,22 @@ void do_energy_grad(mpm_ctx* c, const R* u, R* g, double* energy_dev, hipStream_
   Dev<R>& d = dev<R>(c);
   int nbp = std::max(1, cdiv(c->np, 256)), nbs = std::max(1, cdiv(c->ns, 256));
   if (c->np > 0)
-    hipLaunchKernelGGL((k_points_interior<D, R>), dim3(nbp), dim3(256), 0, s, d, u, (int)PM_ENERGY, 0,
+    LAUNCH(c, MPM_K_ENERGY_INT, (k_points_interior<D, R>), dim3(nbp), dim3(256), 0, s, d, u, (int)PM_ENERGY, 0,
                        (const int*)nullptr, 2);
   else
-    hipLaunchKernelGGL(k_fill_r<double>, dim3(1), dim3(1), 0, s, c->part + 2 * kPartSlot, 0.0, (int64_t)1);
+    LAUNCH(c, MPM_K_BLAS, k_fill_r<double>, dim3(1), dim3(1), 0, s, c->part + 2 * kPartSlot, 0.0, (int64_t)1);
   if (c->ns > 0)
-    hipLaunchKernelGGL((k_points_surface<D, R>), dim3(nbs), dim3(256), 0, s, d, u, u, (int)PM_ENERGY, 0,
+    LAUNCH(c, MPM_K_ENERGY_SURF, (k_points_surface<D, R>), dim3(nbs), dim3(256), 0, s, d, u, u, (int)PM_ENERGY, 0,
                        (const int*)nullptr, 3);
   else
-    hipLaunchKernelGGL(k_fill_r<double>, dim3(1), dim3(1), 0, s, c->part + 3 * kPartSlot, 0.0, (int64_t)1);
+    LAUNCH(c, MPM_K_BLAS, k_fill_r<double>, dim3(1), dim3(1), 0, s, c->part + 3 * kPartSlot, 0.0, (int64_t)1);
   if (c->ntiles > 0)
-    hipLaunchKernelGGL((k_stress_nodes<D, R>), dim3(c->ntiles), dim3(64), 0, s, d, u, g, (int)NM_GRAD, 0.0, 0,
+    LAUNCH(c, MPM_K_ENERGY_NODE, (k_stress_nodes<D, R>), dim3(c->ntiles), dim3(64), 0, s, d, u, g, (int)NM_GRAD, 0.0, 0,
                        (const int*)nullptr, 4, -1);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, c->part + 2 * kPartSlot, c->np > 0 ? nbp : 1, 1, c->scal + 8);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, c->part + 3 * kPartSlot, c->ns > 0 ? nbs : 1, 1, c->scal + 9);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, c->part + 4 * kPartSlot, std::max(c->ntiles, 1), 1, c->scal + 10);
-  hipLaunchKernelGGL(k_sum3, dim3(1), dim3(1), 0, s, (const double*)(c->scal + 8), c->scal + 0, energy_dev);
+  LAUNCH(c, MPM_K_REDUCE, k_finalize, dim3(1), dim3(256), 0, s, c->part + 2 * kPartSlot, c->np > 0 ? nbp : 1, 1, c->scal + 8);
+  LAUNCH(c, MPM_K_REDUCE, k_finalize, dim3(1), dim3(256), 0, s, c->part + 3 * kPartSlot, c->ns > 0 ? nbs : 1, 1, c->scal + 9);
+  LAUNCH(c, MPM_K_REDUCE, k_finalize, dim3(1), dim3(256), 0, s, c->part + 4 * kPartSlot, std::max(c->ntiles, 1), 1, c->scal + 10);
+  LAUNCH(c, MPM_K_REDUCE, k_sum3, dim3(1), dim3(1), 0, s, (const double*)(c->scal + 8), c->scal + 0, energy_dev);
 }
 
 template <int D, typename R>
@@ -296,13 +348,13 @@ void do_hessvec(mpm_ctx* c, const R* vlin, const R* w, double alpha, R* out, boo
                 int dot_slot, hipStream_t s) {
   Dev<R>& d = dev<R>(c);
   if (c->np > 0 && (d.term_mask & 5))
-    hipLaunchKernelGGL((k_points_interior<D, R>), dim3(cdiv(c->np, 256)), dim3(256), 0, s, d, w, (int)PM_HESS,
+    LAUNCH(c, MPM_K_HESS_INT, (k_points_interior<D, R>), dim3(cdiv(c->np, 256)), dim3(256), 0, s, d, w, (int)PM_HESS,
                        (int)mask_in, done, -1);
   if (c->ns > 0 && (d.term_mask & 2))
-    hipLaunchKernelGGL((k_points_surface<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d, vlin, w,
+    LAUNCH(c, MPM_K_HESS_SURF, (k_points_surface<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d, vlin, w,
                        (int)PM_HESS, (int)mask_in, done, -1);
   if (c->ntiles > 0)
-    hipLaunchKernelGGL((k_stress_nodes<D, R>), dim3(c->ntiles), dim3(64), 0, s, d, w, out, (int)NM_HESS, alpha,
+    LAUNCH(c, MPM_K_HESS_NODE, (k_stress_nodes<D, R>), dim3(c->ntiles), dim3(64), 0, s, d, w, out, (int)NM_HESS, alpha,
                        (int)mask_in, done, -1, dot_slot);
 }
 
@@ -312,13 +364,13 @@ void do_hessvec_force(mpm_ctx* c, const R* u, R* out, hipStream_t s) {
   Dev<R>& d = dev<R>(c);
   int nbp = std::max(1, cdiv(c->np, 256)), nbs = std::max(1, cdiv(c->ns, 256));
   if (c->np > 0 && (d.term_mask & 5))
-    hipLaunchKernelGGL((k_points_interior<D, R>), dim3(nbp), dim3(256), 0, s, d, u, (int)PM_ENERGY, 0,
+    LAUNCH(c, MPM_K_ENERGY_INT, (k_points_interior<D, R>), dim3(nbp), dim3(256), 0, s, d, u, (int)PM_ENERGY, 0,
                        (const int*)nullptr, 2);
   if (c->ns > 0 && (d.term_mask & 2))
-    hipLaunchKernelGGL((k_points_surface<D, R>), dim3(nbs), dim3(256), 0, s, d, u, u, (int)PM_ENERGY, 0,
+    LAUNCH(c, MPM_K_ENERGY_SURF, (k_points_surface<D, R>), dim3(nbs), dim3(256), 0, s, d, u, u, (int)PM_ENERGY, 0,
                        (const int*)nullptr, 3);
   if (c->ntiles > 0)
-    hipLaunchKernelGGL((k_stress_nodes<D, R>), dim3(c->ntiles), dim3(64), 0, s, d, u, out, (int)NM_HESS, 0.0, 0,
+    LAUNCH(c, MPM_K_ENERGY_NODE, (k_stress_nodes<D, R>), dim3(c->ntiles), dim3(64), 0, s, d, u, out, (int)NM_HESS, 0.0, 0,
                        (const int*)nullptr, -1, -1);
 }
 
@@ -326,18 +378,18 @@ template <int D, typename R>
 void do_heat_apply(mpm_ctx* c, const R* T, R* out, const int* done, int dot_slot, hipStream_t s) {
   Dev<R>& d = dev<R>(c);
   if (c->np + c->ns > 0)
-    hipLaunchKernelGGL((k_heat_points<D, R>), dim3(cdiv(c->np + c->ns, 256)), dim3(256), 0, s, d, T, done);
+    LAUNCH(c, MPM_K_HEAT_PT, (k_heat_points<D, R>), dim3(cdiv(c->np + c->ns, 256)), dim3(256), 0, s, d, T, done);
   if (c->ntiles > 0)
-    hipLaunchKernelGGL((k_heat_nodes<D, R>), dim3(c->ntiles), dim3(64), 0, s, d, T, out, done, dot_slot);
+    LAUNCH(c, MPM_K_HEAT_NODE, (k_heat_nodes<D, R>), dim3(c->ntiles), dim3(64), 0, s, d, T, out, done, dot_slot);
 }
 
 template <int D, typename R>
 void do_g2p(mpm_ctx* c, const R* vh, const R* Th, mpm_particles* P, hipStream_t s) {
   Dev<R>& d = dev<R>(c);
   if (!P || P->n != c->np) throw ApiError{MPM_EINVAL, "g2p particle count differs from p2g"};
-  if (c->ns > 0) hipLaunchKernelGGL((k_g2p_split<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d, vh);
+  if (c->ns > 0) LAUNCH(c, MPM_K_G2P_SPLIT, (k_g2p_split<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d, vh);
   if (c->np > 0)
-    hipLaunchKernelGGL((k_g2p_particles<D, R>), dim3(cdiv(c->np, 256)), dim3(256), 0, s, d, vh, Th, (R*)P->x,
+    LAUNCH(c, MPM_K_G2P, (k_g2p_particles<D, R>), dim3(cdiv(c->np, 256)), dim3(256), 0, s, d, vh, Th, (R*)P->x,
                        (R*)P->v, (R*)P->A, (R*)P->J, (R*)P->T, (R*)P->gradT);
 }
 
@@ -346,9 +398,9 @@ template <typename R>
 double dot_sync(mpm_ctx* c, const R* a, const R* b, int ncomp, hipStream_t s) {
   Dev<R>& d = dev<R>(c);
   int nelem = c->ntiles * 64, nb = krylov_blocks(nelem);
-  hipLaunchKernelGGL(k_dot<R>, dim3(nb), dim3(256), 0, s, (const int*)d.tile_list, nelem, d.nn, ncomp, a, b,
+  LAUNCH(c, MPM_K_BLAS, k_dot<R>, dim3(nb), dim3(256), 0, s, (const int*)d.tile_list, nelem, d.nn, ncomp, a, b,
                      c->part, (const int*)nullptr);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, (const double*)c->part, nb, 1, c->scal + 16);
+  LAUNCH(c, MPM_K_REDUCE, k_finalize, dim3(1), dim3(256), 0, s, (const double*)c->part, nb, 1, c->scal + 16);
   sync_read(c, s, c->scal + 16, c->hbuf, sizeof(double));
   return c->hbuf[0];
 }
@@ -364,35 +416,35 @@ int cg_solve(mpm_ctx* c, Apply&& apply, const R* b, R* x, bool x0_given, const R
   const int* tl = d.tile_list;
   if (x0_given) {
     apply(x, Ap, (const int*)nullptr, -1);
-    hipLaunchKernelGGL(k_cg_start_x0<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, b, (const R*)Ap, diag,
+    LAUNCH(c, MPM_K_BLAS, k_cg_start_x0<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, b, (const R*)Ap, diag,
                        r, z, p, c->part);
   } else {
-    hipLaunchKernelGGL(k_cg_start<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, b, diag, x, r, z, p,
+    LAUNCH(c, MPM_K_BLAS, k_cg_start<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, b, diag, x, r, z, p,
                        c->part, 1);
   }
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, (const double*)c->part, nb, 2, c->scal + 20);
-  hipLaunchKernelGGL(k_cg_init_scal, dim3(1), dim3(1), 0, s, c->cg, (const double*)(c->scal + 20),
+  LAUNCH(c, MPM_K_REDUCE, k_finalize, dim3(1), dim3(256), 0, s, (const double*)c->part, nb, 2, c->scal + 20);
+  LAUNCH(c, MPM_K_REDUCE, k_cg_init_scal, dim3(1), dim3(1), 0, s, c->cg, (const double*)(c->scal + 20),
                      tol_abs * tol_abs, maxit);
   const int* done = &c->cg->done;
   int chunk = 4;
   for (int it = 0; it < maxit + chunk; it += chunk) {
     for (int j = 0; j < chunk; ++j) {
       apply(p, Ap, done, 0);
-      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, (const double*)c->part, std::max(c->ntiles, 1), 1,
+      LAUNCH(c, MPM_K_REDUCE, k_finalize, dim3(1), dim3(256), 0, s, (const double*)c->part, std::max(c->ntiles, 1), 1,
                          c->scal + 22);
-      hipLaunchKernelGGL(k_cg_pap, dim3(1), dim3(1), 0, s, c->cg, (const double*)(c->scal + 22));
-      hipLaunchKernelGGL(k_cg_update<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, (const CgScal*)c->cg, x,
+      LAUNCH(c, MPM_K_REDUCE, k_cg_pap, dim3(1), dim3(1), 0, s, c->cg, (const double*)(c->scal + 22));
+      LAUNCH(c, MPM_K_BLAS, k_cg_update<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, (const CgScal*)c->cg, x,
                          r, z, (const R*)p, (const R*)Ap, diag, c->part);
-      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, (const double*)c->part, nb, 2, c->scal + 20);
-      hipLaunchKernelGGL(k_cg_scal_after, dim3(1), dim3(1), 0, s, c->cg, (const double*)(c->scal + 20));
-      hipLaunchKernelGGL(k_cg_p<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, (const CgScal*)c->cg,
+      LAUNCH(c, MPM_K_REDUCE, k_finalize, dim3(1), dim3(256), 0, s, (const double*)c->part, nb, 2, c->scal + 20);
+      LAUNCH(c, MPM_K_REDUCE, k_cg_scal_after, dim3(1), dim3(1), 0, s, c->cg, (const double*)(c->scal + 20));
+      LAUNCH(c, MPM_K_BLAS, k_cg_p<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, (const CgScal*)c->cg,
                          (const R*)z, p, (int*)nullptr);
     }
     sync_read(c, s, c->cg, c->hcg, sizeof(CgScal));
     if (c->hcg->done) break;
     chunk = std::min(chunk * 2, 32);
   }
-  hipLaunchKernelGGL(k_cg_fixup<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, (const CgScal*)c->cg, x,
+  LAUNCH(c, MPM_K_BLAS, k_cg_fixup<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, (const CgScal*)c->cg, x,
                      (const R*)z);
   if (!(c->hcg->rr == c->hcg->rr)) c->status |= ST_NONFINITE;
   return c->hcg->iters;
@@ -413,13 +465,13 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
   c->constrained = any_constrained(c, s);
   const bool fix = p.momentum_fix && !c->constrained;
   // mass sum for the absolute floor and the translation correction
-  hipLaunchKernelGGL((k_mom_sums<D, R>), dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, (const uint8_t*)d.gfree,
+  LAUNCH(c, MPM_K_BLAS, (k_mom_sums<D, R>), dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, (const uint8_t*)d.gfree,
                      (const R*)d.gm, (const R*)d.gvn, (const R*)d.gvn, c->part);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, (const double*)c->part, nb, 2 * D + 1, c->scal + 32);
+  LAUNCH(c, MPM_K_REDUCE, k_finalize, dim3(1), dim3(256), 0, s, (const double*)c->part, nb, 2 * D + 1, c->scal + 32);
   sync_read(c, s, c->scal + 32, c->hbuf, sizeof(double) * (2 * D + 1));
   double msum = c->hbuf[D];
   double floor_abs = 1e-14 * msum * p.dx / p.dt;
-  hipLaunchKernelGGL(k_project_copy<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const uint8_t*)d.gfree,
+  LAUNCH(c, MPM_K_BLAS, k_project_copy<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const uint8_t*)d.gfree,
                      (const R*)d.gvn, vhat);
   do_energy_grad<D, R>(c, vhat, g, nullptr, s);
   double phi = 0;
@@ -441,7 +493,7 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
     // (1e-4 |g0|) and a Newton step no longer halves it, the solve has reached that floor.
     if (sizeof(R) == 4 && gn <= 1e-4 * g0 && gn > 0.5 * gn_prev) { st.converged = 2; break; }
     gn_prev = gn;
-    hipLaunchKernelGGL(k_neg<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const R*)g, vtrial);
+    LAUNCH(c, MPM_K_BLAS, k_neg<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const R*)g, vtrial);
     double cg_tol = std::max(p.cg_rel * gn, 0.1 * p.newton_tol * g0);
     int cit = cg_solve<R>(c, apply, vtrial, delta, false, (const R*)d.gdiag, (R*)c->r, (R*)c->z, (R*)c->pp,
                           (R*)c->Ap, D, cg_tol, p.cg_max, s);
@@ -450,7 +502,7 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
     double slope = dot_sync<R>(c, g, delta, D, s);
     double alpha = 1.0, phit = phi;
     for (int ls = 0; ls < std::max(p.ls_max, 1); ++ls) {
-      hipLaunchKernelGGL(k_axpy_to<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const R*)vhat,
+      LAUNCH(c, MPM_K_BLAS, k_axpy_to<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const R*)vhat,
                          (const R*)delta, alpha, vtrial);
       do_energy_grad<D, R>(c, vtrial, (R*)c->gscratch, nullptr, s);
       sync_read(c, s, c->scal, &phit, sizeof(double));
@@ -466,10 +518,10 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
     vhat = (R*)c->vhat;
     vtrial = (R*)c->vtrial;
     if (fix) {
-      hipLaunchKernelGGL((k_mom_sums<D, R>), dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, (const uint8_t*)d.gfree,
+      LAUNCH(c, MPM_K_BLAS, (k_mom_sums<D, R>), dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, (const uint8_t*)d.gfree,
                          (const R*)d.gm, (const R*)vhat, (const R*)d.gvn, c->part);
-      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, (const double*)c->part, nb, 2 * D + 1, c->scal + 32);
-      hipLaunchKernelGGL((k_mom_fix<D, R>), dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, (const uint8_t*)d.gfree,
+      LAUNCH(c, MPM_K_REDUCE, k_finalize, dim3(1), dim3(256), 0, s, (const double*)c->part, nb, 2 * D + 1, c->scal + 32);
+      LAUNCH(c, MPM_K_BLAS, (k_mom_fix<D, R>), dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, (const uint8_t*)d.gfree,
                          (const double*)(c->scal + 32), p.dt, p.gravity[0], p.gravity[1], p.gravity[2], vhat);
     }
     do_energy_grad<D, R>(c, vhat, g, nullptr, s);
@@ -483,9 +535,9 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
   st.phi = phi;
   if (!st.converged && !(c->status & ST_NONFINITE)) c->status |= ST_NOCONV;
   // grid momentum after the solve
-  hipLaunchKernelGGL((k_mom_sums<D, R>), dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, (const uint8_t*)d.gfree,
+  LAUNCH(c, MPM_K_BLAS, (k_mom_sums<D, R>), dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, (const uint8_t*)d.gfree,
                      (const R*)d.gm, (const R*)vhat, (const R*)d.gvn, c->part);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, (const double*)c->part, nb, 2 * D + 1, c->scal + 32);
+  LAUNCH(c, MPM_K_REDUCE, k_finalize, dim3(1), dim3(256), 0, s, (const double*)c->part, nb, 2 * D + 1, c->scal + 32);
   sync_read(c, s, c->scal + 32, c->hbuf, sizeof(double) * (2 * D + 1));
   for (int a = 0; a < 3; ++a) st.momentum[a] = a < D ? c->hbuf[D + 1 + a] : 0.0;
 }
@@ -499,7 +551,7 @@ void do_explicit(mpm_ctx* c, hipStream_t s) {
   R* f = (R*)c->grad;
   R* f2 = (R*)c->gscratch;
   R* zero = (R*)c->zero;
-  hipLaunchKernelGGL(k_axpy_to<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const R*)d.gvn, (const R*)d.gvn,
+  LAUNCH(c, MPM_K_BLAS, k_axpy_to<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const R*)d.gvn, (const R*)d.gvn,
                      -1.0, zero);
   Dev<R> saved = d;
   // J and surface terms at y = x (v^ = 0)
@@ -509,10 +561,10 @@ void do_explicit(mpm_ctx* c, hipStream_t s) {
   d.term_mask = saved.term_mask & 4;
   if (d.term_mask) {
     do_hessvec_force<D, R>(c, (const R*)d.gvn, f2, s);
-    hipLaunchKernelGGL(k_axpy_to<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const R*)f, (const R*)f2, 1.0, f);
+    LAUNCH(c, MPM_K_BLAS, k_axpy_to<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const R*)f, (const R*)f2, 1.0, f);
   }
   d = saved;
-  hipLaunchKernelGGL((k_explicit_update<D, R>), dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, (const uint8_t*)d.gfree,
+  LAUNCH(c, MPM_K_BLAS, (k_explicit_update<D, R>), dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, (const uint8_t*)d.gfree,
                      (const R*)d.gm, (const R*)d.gvn, (const R*)f, (R)c->p.gravity[0], (R)c->p.gravity[1],
                      (R)c->p.gravity[2], (R)c->p.dt, (R*)c->vhat);
   c->stats.converged = 1;
@@ -525,7 +577,7 @@ void do_solve_heat(mpm_ctx* c, hipStream_t s) {
   int nelem = c->ntiles * 64, nb = krylov_blocks(nelem);
   const int* tl = d.tile_list;
   R* T = (R*)c->That;
-  hipLaunchKernelGGL(k_axpy_to<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, 1, (const R*)d.gTn, (const R*)d.gTn,
+  LAUNCH(c, MPM_K_BLAS, k_axpy_to<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, 1, (const R*)d.gTn, (const R*)d.gTn,
                      0.0, T);
   double bn = std::sqrt(dot_sync<R>(c, d.hrhs, d.hrhs, 1, s));
   auto apply = [&](const R* pv, R* Apv, const int* done, int slot) { do_heat_apply<D, R>(c, pv, Apv, done, slot, s); };
@@ -689,6 +741,7 @@ int mpm_ctx_create(const mpm_params* p, void* workspace, size_t ws_bytes, int64_
 
 int mpm_ctx_destroy(mpm_ctx* ctx) {
   if (!ctx) return MPM_EINVAL;
+  for (hipEvent_t e : ctx->prof.ev) hipEventDestroy(e);
   if (ctx->hbuf) hipHostFree(ctx->hbuf);
   if (ctx->hint) hipHostFree(ctx->hint);
   if (ctx->hcg) hipHostFree(ctx->hcg);
@@ -871,6 +924,23 @@ int mpm_grid_view(mpm_ctx* ctx, int32_t field, void** out_ptr) {
   if (!p) { ctx->err = "unknown field"; return MPM_EINVAL; }
   *out_ptr = p;
   return MPM_OK;
+}
+
+int mpm_timing(mpm_ctx* ctx, int32_t enable) {
+  if (!ctx) return MPM_EINVAL;
+  return guarded(ctx, [&] {
+    prof_collect(ctx);
+    for (int k = 0; k < MPM_K_COUNT; ++k) { ctx->prof.ms[k] = 0; ctx->prof.launches[k] = 0; }
+    ctx->prof.on = enable != 0;
+  });
+}
+
+int mpm_timing_read(mpm_ctx* ctx, double* ms, int64_t* launches) {
+  if (!ctx || !ms || !launches) return MPM_EINVAL;
+  return guarded(ctx, [&] {
+    prof_collect(ctx);
+    for (int k = 0; k < MPM_K_COUNT; ++k) { ms[k] = ctx->prof.ms[k]; launches[k] = ctx->prof.launches[k]; }
+  });
 }
 
 int mpm_get_stats(const mpm_ctx* ctx, mpm_stats* out) {
