@@ -27,7 +27,7 @@ struct Dev {
   int* pcnt; int* pcnt_orig; int* grp_start; int* grp; int* gcur;
   // surface samples, cell-sorted
   int* s_start; int* s_perm; int* s_key;
-  R *ss, *sdA, *sk, *sk_orig, *sS, *sc;
+  R *ss, *sdA, *sk, *sk_orig, *sS, *sc, *sF;
   int* slabel; int* spar; int* s_parent_orig;
   // balance points, cell-sorted
   int* b_start; int* b_src; int* b_key; R* bx; R* bx_unsorted;
@@ -350,153 +350,6 @@ __global__ void k_clear_tiles(Dev<R> d, const int* list, R* const* extra, int ne
   if (threadIdx.x == 0) d.tile_flag[t] = 0;
 }
 
-// ======================================================================================
-// P2G (Section 4.2) with the grid set-up fused: one thread per node of the active tiles
-// gathers, in fixed cell order, every interior particle, surface sample and balance point
-// whose stencil holds the node.
-// ======================================================================================
-template <int D, typename R>
-__global__ void __launch_bounds__(64) k_p2g_nodes(Dev<R> d) {
-  int t = d.tile_list[blockIdx.x];
-  int lane = threadIdx.x;
-  int node = t * kTileNodes + lane;
-  int i[3] = {0, 0, 0};
-  tiled_coords<D>(t, lane, d.nt, i);
-  const int N = d.np, S = d.ns, nn = d.nn;
-  R m = 0, W = 0, WT = 0, E = 0, ET = 0, hdg = 0, hsrc = 0, hrob = 0;
-  R mv[D], dg[D];
-#pragma unroll
-  for (int a = 0; a < D; ++a) { mv[a] = 0; dg[a] = 0; }
-  const bool useJ = d.term_mask & 1, useV = d.term_mask & 4;
-  const R dt = d.dt;
-  for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
-    for (int dy = -1; dy <= 1; ++dy)
-      for (int dxo = -1; dxo <= 1; ++dxo) {
-        int c[3] = {i[0] + dxo, i[1] + dy, i[2] + dz};
-        int off[3] = {dxo, dy, dz};
-        bool in = true;
-#pragma unroll
-        for (int a = 0; a < D; ++a) in = in && c[a] >= 0 && c[a] < d.n;
-        if (!in) continue;
-        int ci = (int)tiled_index<D>(c, d.nt);
-        int kk[D];
-#pragma unroll
-        for (int a = 0; a < D; ++a) kk[a] = 1 - off[a];
-        // interior particles
-        for (int k = d.p_start[ci]; k < d.p_start[ci + 1]; ++k) {
-          R f[D], rel[D], g[D];
-#pragma unroll
-          for (int a = 0; a < D; ++a) {
-            f[a] = d.px[a * N + k] * d.fn - R(c[a]);
-            rel[a] = (R(0.5) - R(off[a]) - f[a]) * d.dx;      // x_i - x_p, node i = cell - off
-          }
-          R Nw = weight_from_cell<D, R>(kk, f, d.fn, g);
-          R mt = d.pmt[k], mp = d.pm[k];
-          R w = mt * Nw;
-          m += w;
-#pragma unroll
-          for (int a = 0; a < D; ++a) {
-            R va = d.pv[a * N + k];
-#pragma unroll
-            for (int b2 = 0; b2 < D; ++b2) va += d.pA[(a * D + b2) * N + k] * rel[b2];
-            mv[a] += w * va;
-          }
-          R Tq = d.pT[k];
-#pragma unroll
-          for (int a = 0; a < D; ++a) Tq += rel[a] * d.pgT[a * N + k];
-          W += mp * Nw;
-          WT += mp * Nw * Tq;
-          R g2 = 0;
-#pragma unroll
-          for (int a = 0; a < D; ++a) g2 += g[a] * g[a];
-          R Jn = d.pJ[k], Vn = d.pVn[k];
-          R cJ = useJ ? dt * dt * d.lam * d.pV0[k] * Jn * Jn : R(0);
-          R cV = useV ? dt * d.pmu[k] * Vn : R(0);
-#pragma unroll
-          for (int a = 0; a < D; ++a) dg[a] += cJ * g[a] * g[a] + cV * (R(0.5) * g2 + R(0.5) * g[a] * g[a]);
-          hdg += d.K * Vn * g2;
-          hsrc += Nw * d.H * Vn;
-        }
-        if (S == 0) continue;
-        // surface samples (Sections 4.1.3, 4.2, 4.3.2)
-        for (int r = d.s_start[ci]; r < d.s_start[ci + 1]; ++r) {
-          R f[D], rel[D], g[D];
-#pragma unroll
-          for (int a = 0; a < D; ++a) {
-            f[a] = d.ss[a * S + r] * d.fn - R(c[a]);
-            rel[a] = (R(0.5) - R(off[a]) - f[a]) * d.dx;
-          }
-          R Nw = weight_from_cell<D, R>(kk, f, d.fn, g);
-          int p = d.spar[r];
-          R w = d.pmt[p] * Nw;
-          m += w;
-#pragma unroll
-          for (int a = 0; a < D; ++a) {
-            R va = d.pv[a * N + p];
-#pragma unroll
-            for (int b2 = 0; b2 < D; ++b2) va += d.pA[(a * D + b2) * N + p] * rel[b2];
-            mv[a] += w * va;
-          }
-          E += w;
-          ET += w * d.pT[p];
-          R area = 0;
-#pragma unroll
-          for (int a = 0; a < D; ++a) area += d.sdA[a * S + r] * d.sdA[a * S + r];
-          area = sqrt(area);
-          hdg += d.h * area * Nw * Nw;
-          hrob += Nw * (d.h * d.T_amb + d.b) * area;
-        }
-        // balance points
-        for (int q = d.b_start[ci]; q < d.b_start[ci + 1]; ++q) {
-          R f[D], rel[D], g[D];
-#pragma unroll
-          for (int a = 0; a < D; ++a) {
-            f[a] = d.bx[a * S + q] * d.fn - R(c[a]);
-            rel[a] = (R(0.5) - R(off[a]) - f[a]) * d.dx;
-          }
-          R Nw = weight_from_cell<D, R>(kk, f, d.fn, g);
-          int p = d.spar[d.b_src[q]];
-          R w = d.pmt[p] * Nw;
-          m += w;
-#pragma unroll
-          for (int a = 0; a < D; ++a) {
-            R va = d.pv[a * N + p];
-#pragma unroll
-            for (int b2 = 0; b2 < D; ++b2) va += d.pA[(a * D + b2) * N + p] * rel[b2];
-            mv[a] += w * va;
-          }
-          E += w;
-          ET += w * d.pT[p];
-        }
-      }
-  // grid set-up
-  bool dof = m > R(0);
-  d.gm[node] = m; d.gW[node] = W; d.gWT[node] = WT; d.gE[node] = E; d.gET[node] = ET;
-  R Tn = W > R(0) ? WT / W : (E > R(0) ? ET / E : R(0));
-  d.gTn[node] = dof ? Tn : R(0);
-  uint8_t fr = dof ? 0x80 : 0;
-  R xi[3];
-#pragma unroll
-  for (int a = 0; a < D; ++a) xi[a] = (R(i[a]) + R(0.5)) * d.dx;
-  bool in_slab = d.slab != 0;
-#pragma unroll
-  for (int a = 0; a < D; ++a) in_slab = in_slab && xi[a] >= d.slab_lo[a] && xi[a] < d.slab_hi[a];
-#pragma unroll
-  for (int a = 0; a < D; ++a) {
-    bool wall = d.wall > 0 && (i[a] < d.wall || i[a] >= d.n - d.wall);
-    bool fixed = wall || (in_slab && a == d.slab_axis);
-    bool fa = dof && !fixed;
-    if (fa) fr |= (uint8_t)(1u << a);
-    d.gmv[a * nn + node] = mv[a];
-    d.gvn[a * nn + node] = dof ? mv[a] / m : R(0);
-    d.gdiag[a * nn + node] = fa ? m + dg[a] : R(1);
-  }
-  d.gfree[node] = fr;
-  R cm = d.cp / dt * m;
-  d.hdiag[node] = dof ? cm + hdg : R(1);
-  d.hrhs[node] = dof ? cm * Tn + hrob + hsrc : R(0);
-}
-
 // k_r = gamma(T^s_r), T^s_r = sum_i N_i(s_r) T^n_i (Section 4.3.1), or by label (Sec. 3.6).
 template <int D, typename R>
 __global__ void k_surface_k(Dev<R> d) {
@@ -556,89 +409,6 @@ MPM_DEV void gather_grad(const Dev<R>& d, const Stencil<D, R>& st, const R* u, b
   });
 }
 
-// Interior particles: J-term and viscosity.
-template <int D, typename R>
-__global__ void k_points_interior(Dev<R> d, const R* u, int mode, int mask_in, const int* done,
-                                  int part_slot) {
-  __shared__ double sh[16];
-  if (done && *done) return;
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
-  const int N = d.np;
-  double e = 0;
-  if (k < N) {
-    R x[D];
-#pragma unroll
-    for (int a = 0; a < D; ++a) x[a] = d.px[a * N + k];
-    Stencil<D, R> st; bool bad = false;
-    make_stencil<D, R>(x, d.n, d.fn, st, &bad);
-    R G[D][D];
-    gather_grad<D, R>(d, st, u, mask_in, G);
-    R S[D][D];
-#pragma unroll
-    for (int a = 0; a < D; ++a)
-#pragma unroll
-      for (int b = 0; b < D; ++b) S[a][b] = 0;
-    R tr = 0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) tr += G[a][a];
-    const R dt = d.dt, Jn = d.pJ[k], V0 = d.pV0[k];
-    if (d.term_mask & 1) {
-      R s;
-      if (mode == PM_ENERGY) {
-        R Jm1 = (R(1) + dt * tr) * Jn - R(1);
-        e += (double)(R(0.5) * d.lam * Jm1 * Jm1 * V0);
-        s = dt * d.lam * V0 * Jn * Jm1;
-      } else {
-        s = dt * dt * d.lam * V0 * Jn * Jn * tr;
-      }
-#pragma unroll
-      for (int a = 0; a < D; ++a) S[a][a] += s;
-    }
-    if (d.term_mask & 4) {
-      R cV = dt * d.pmu[k] * d.pVn[k];
-      R ee = 0;
-#pragma unroll
-      for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int b = 0; b < D; ++b) {
-          R eps = R(0.5) * (G[a][b] + G[b][a]);
-          S[a][b] += cV * eps;
-          ee += eps * eps;
-        }
-      if (mode == PM_ENERGY) e += (double)(R(0.5) * cV * ee);   // dt * D_p
-    }
-#pragma unroll
-    for (int a = 0; a < D; ++a)
-#pragma unroll
-      for (int b = 0; b < D; ++b) d.pS[(a * D + b) * N + k] = S[a][b];
-  }
-  if (mode == PM_ENERGY) {
-    double bsum = block_sum(e, sh);
-    if (threadIdx.x == 0) d.part[part_slot * kPartSlot + blockIdx.x] = bsum;
-  }
-}
-
-// cof(F) N with cof(F) column m = f_{m+1} x f_{m+2} (3D) or R F R^T (2D).
-template <int D, typename R>
-MPM_DEV void cof_normal(const R (&F)[D][D], const R* Nv, R* a) {
-  if constexpr (D == 3) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) a[c] = 0;
-#pragma unroll
-    for (int m = 0; m < 3; ++m) {
-      int p = (m + 1) % 3, q = (m + 2) % 3;
-      // column m of cof(F) = column p x column q
-      R cx = F[1][p] * F[2][q] - F[2][p] * F[1][q];
-      R cy = F[2][p] * F[0][q] - F[0][p] * F[2][q];
-      R cz = F[0][p] * F[1][q] - F[1][p] * F[0][q];
-      a[0] += cx * Nv[m]; a[1] += cy * Nv[m]; a[2] += cz * Nv[m];
-    }
-  } else {
-    a[0] = F[1][1] * Nv[0] - F[1][0] * Nv[1];
-    a[1] = -F[0][1] * Nv[0] + F[0][0] * Nv[1];
-  }
-}
-
 template <typename R>
 MPM_DEV void cross3(const R* u, const R* v, R* w) {
   w[0] = u[1] * v[2] - u[2] * v[1];
@@ -646,311 +416,7 @@ MPM_DEV void cross3(const R* u, const R* v, R* w) {
   w[2] = u[0] * v[1] - u[1] * v[0];
 }
 
-// Surface samples: e_sigma = k |cof(F) dA|, its derivative Q and its linearization.
-template <int D, typename R>
-__global__ void k_points_surface(Dev<R> d, const R* vlin, const R* u, int mode, int mask_in,
-                                 const int* done, int part_slot) {
-  __shared__ double sh[16];
-  if (done && *done) return;
-  int r = blockIdx.x * blockDim.x + threadIdx.x;
-  const int S = d.ns;
-  double e = 0;
-  if (r < S && (d.term_mask & 2)) {
-    R x[D], Nv[D];
-#pragma unroll
-    for (int a = 0; a < D; ++a) { x[a] = d.ss[a * S + r]; Nv[a] = d.sdA[a * S + r]; }
-    Stencil<D, R> st; bool bad = false;
-    make_stencil<D, R>(x, d.n, d.fn, st, &bad);
-    const R dt = d.dt, kr = d.sk[r];
-    R F[D][D];
-    gather_grad<D, R>(d, st, vlin, false, F);
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-#pragma unroll
-      for (int b = 0; b < D; ++b) F[a][b] *= dt;
-      F[a][a] += R(1);
-    }
-    R av[D];
-    cof_normal<D, R>(F, Nv, av);
-    R an = 0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) an += av[a] * av[a];
-    an = sqrt(an);
-    R ah[D];
-#pragma unroll
-    for (int a = 0; a < D; ++a) ah[a] = av[a] / an;
-    R Q[D][D];
-    if (mode == PM_ENERGY) {
-      e = (double)(kr * an);
-      if constexpr (D == 3) {
-        for (int m = 0; m < 3; ++m) {
-          R gp[3] = {F[0][(m + 1) % 3], F[1][(m + 1) % 3], F[2][(m + 1) % 3]};
-          R gq[3] = {F[0][(m + 2) % 3], F[1][(m + 2) % 3], F[2][(m + 2) % 3]};
-          R c1[3], c2[3];
-          cross3<R>(gp, ah, c1);
-          cross3<R>(ah, gq, c2);
-          for (int a = 0; a < 3; ++a) Q[a][m] = Nv[(m + 2) % 3] * c1[a] + Nv[(m + 1) % 3] * c2[a];
-        }
-      } else {
-        R tau[2] = {Nv[1], -Nv[0]};
-        R cvec[2] = {F[0][0] * tau[0] + F[0][1] * tau[1], F[1][0] * tau[0] + F[1][1] * tau[1]};
-        R cn = sqrt(cvec[0] * cvec[0] + cvec[1] * cvec[1]);
-        for (int a = 0; a < 2; ++a)
-          for (int b = 0; b < 2; ++b) Q[a][b] = cvec[a] / cn * tau[b];
-      }
-    } else {
-      R dG[D][D];
-      gather_grad<D, R>(d, st, u, mask_in, dG);
-#pragma unroll
-      for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int b = 0; b < D; ++b) dG[a][b] *= dt;
-      if constexpr (D == 3) {
-        R da[3] = {0, 0, 0};
-        for (int k = 0; k < 3; ++k) {
-          R dg1[3] = {dG[0][(k + 1) % 3], dG[1][(k + 1) % 3], dG[2][(k + 1) % 3]};
-          R dg2[3] = {dG[0][(k + 2) % 3], dG[1][(k + 2) % 3], dG[2][(k + 2) % 3]};
-          R g1[3] = {F[0][(k + 1) % 3], F[1][(k + 1) % 3], F[2][(k + 1) % 3]};
-          R g2[3] = {F[0][(k + 2) % 3], F[1][(k + 2) % 3], F[2][(k + 2) % 3]};
-          R c1[3], c2[3];
-          cross3<R>(dg1, g2, c1);
-          cross3<R>(g1, dg2, c2);
-          for (int a = 0; a < 3; ++a) da[a] += Nv[k] * (c1[a] + c2[a]);
-        }
-        R ad = ah[0] * da[0] + ah[1] * da[1] + ah[2] * da[2];
-        R uu[3];
-        for (int a = 0; a < 3; ++a) uu[a] = (da[a] - ah[a] * ad) / an;
-        for (int m = 0; m < 3; ++m) {
-          R gp[3] = {F[0][(m + 1) % 3], F[1][(m + 1) % 3], F[2][(m + 1) % 3]};
-          R gq[3] = {F[0][(m + 2) % 3], F[1][(m + 2) % 3], F[2][(m + 2) % 3]};
-          R c1[3], c2[3];
-          cross3<R>(gp, uu, c1);
-          cross3<R>(uu, gq, c2);
-          for (int a = 0; a < 3; ++a) Q[a][m] = Nv[(m + 2) % 3] * c1[a] + Nv[(m + 1) % 3] * c2[a];
-          if (d.exact) {
-            R dp[3] = {dG[0][(m + 1) % 3], dG[1][(m + 1) % 3], dG[2][(m + 1) % 3]};
-            R dq[3] = {dG[0][(m + 2) % 3], dG[1][(m + 2) % 3], dG[2][(m + 2) % 3]};
-            cross3<R>(dp, ah, c1);
-            cross3<R>(ah, dq, c2);
-            for (int a = 0; a < 3; ++a) Q[a][m] += Nv[(m + 2) % 3] * c1[a] + Nv[(m + 1) % 3] * c2[a];
-          }
-        }
-      } else {
-        R tau[2] = {Nv[1], -Nv[0]};
-        R cvec[2] = {F[0][0] * tau[0] + F[0][1] * tau[1], F[1][0] * tau[0] + F[1][1] * tau[1]};
-        R cn = sqrt(cvec[0] * cvec[0] + cvec[1] * cvec[1]);
-        R ch[2] = {cvec[0] / cn, cvec[1] / cn};
-        R dc[2] = {dG[0][0] * tau[0] + dG[0][1] * tau[1], dG[1][0] * tau[0] + dG[1][1] * tau[1]};
-        R cd = ch[0] * dc[0] + ch[1] * dc[1];
-        for (int a = 0; a < 2; ++a) {
-          R ua = (dc[a] - ch[a] * cd) / cn;
-          for (int b = 0; b < 2; ++b) Q[a][b] = ua * tau[b];
-        }
-      }
-    }
-    R sc = dt * kr;
-#pragma unroll
-    for (int a = 0; a < D; ++a)
-#pragma unroll
-      for (int b = 0; b < D; ++b) d.sS[(a * D + b) * S + r] = sc * Q[a][b];
-  } else if (r < S) {
-#pragma unroll
-    for (int a = 0; a < D * D; ++a) d.sS[a * S + r] = 0;
-  }
-  if (mode == PM_ENERGY) {
-    double bsum = block_sum(e, sh);
-    if (threadIdx.x == 0) d.part[part_slot * kPartSlot + blockIdx.x] = bsum;
-  }
-}
-
-// Node phase: out_i = sum_q S_q grad N_i(x_q) plus the inertia / mass term, projected.
-//  NM_GRAD: out = P[ acc + m (v^ - v^n) - dt m g ]; energy partial of the node terms.
-//  NM_HESS: out = P[ acc + alpha m w ]; optional partial of w . out (CG p.Ap).
 enum NodeMode { NM_GRAD = 0, NM_HESS = 1 };
-
-template <int D, typename R>
-__global__ void __launch_bounds__(64) k_stress_nodes(Dev<R> d, const R* u, R* out, int mode, double alpha,
-                                                     int mask_in, const int* done, int part_slot,
-                                                     int dot_slot) {
-  __shared__ double sh[16];
-  if (done && *done) return;
-  int t = d.tile_list[blockIdx.x];
-  int lane = threadIdx.x;
-  int node = t * kTileNodes + lane;
-  int i[3] = {0, 0, 0};
-  tiled_coords<D>(t, lane, d.nt, i);
-  const int N = d.np, S = d.ns, nn = d.nn;
-  R acc[D];
-#pragma unroll
-  for (int a = 0; a < D; ++a) acc[a] = 0;
-  const bool surf = (d.term_mask & 2) && S > 0;
-  const bool vol = (d.term_mask & 5) != 0;
-  for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
-    for (int dy = -1; dy <= 1; ++dy)
-      for (int dxo = -1; dxo <= 1; ++dxo) {
-        int c[3] = {i[0] + dxo, i[1] + dy, i[2] + dz};
-        int off[3] = {dxo, dy, dz};
-        bool in = true;
-#pragma unroll
-        for (int a = 0; a < D; ++a) in = in && c[a] >= 0 && c[a] < d.n;
-        if (!in) continue;
-        int ci = (int)tiled_index<D>(c, d.nt);
-        int kk[D];
-#pragma unroll
-        for (int a = 0; a < D; ++a) kk[a] = 1 - off[a];
-        if (vol)
-          for (int k = d.p_start[ci]; k < d.p_start[ci + 1]; ++k) {
-            R f[D], g[D];
-#pragma unroll
-            for (int a = 0; a < D; ++a) f[a] = d.px[a * N + k] * d.fn - R(c[a]);
-            weight_from_cell<D, R>(kk, f, d.fn, g);
-#pragma unroll
-            for (int a = 0; a < D; ++a)
-#pragma unroll
-              for (int b = 0; b < D; ++b) acc[a] += d.pS[(a * D + b) * N + k] * g[b];
-          }
-        if (surf)
-          for (int r = d.s_start[ci]; r < d.s_start[ci + 1]; ++r) {
-            R f[D], g[D];
-#pragma unroll
-            for (int a = 0; a < D; ++a) f[a] = d.ss[a * S + r] * d.fn - R(c[a]);
-            weight_from_cell<D, R>(kk, f, d.fn, g);
-#pragma unroll
-            for (int a = 0; a < D; ++a)
-#pragma unroll
-              for (int b = 0; b < D; ++b) acc[a] += d.sS[(a * D + b) * S + r] * g[b];
-          }
-      }
-  uint8_t fr = d.gfree[node];
-  R m = d.gm[node];
-  double e = 0, dotv = 0;
-#pragma unroll
-  for (int a = 0; a < D; ++a) {
-    bool fa = (fr >> a) & 1;
-    R ua = u[a * nn + node];
-    R o;
-    if (mode == NM_GRAD) {
-      R vn = d.gvn[a * nn + node];
-      o = acc[a] + m * (ua - vn) - d.dt * m * d.grav[a];
-      if (fr & 0x80) {
-        double dv = (double)ua - (double)vn;
-        e += 0.5 * (double)m * dv * dv - (double)d.dt * (double)m * (double)d.grav[a] * (double)ua;
-      }
-    } else {
-      R wa = (!mask_in || fa) ? ua : R(0);
-      o = acc[a] + R(alpha) * m * wa;
-      if (fa) dotv += (double)wa * (double)o;
-    }
-    o = fa ? o : R(0);
-    out[a * nn + node] = o;
-  }
-  if (mode == NM_GRAD && part_slot >= 0) {
-    double bsum = block_sum(e, sh);
-    if (threadIdx.x == 0) d.part[part_slot * kPartSlot + blockIdx.x] = bsum;
-  }
-  if (mode == NM_HESS && dot_slot >= 0) {
-    double bsum = block_sum(dotv, sh);
-    if (threadIdx.x == 0) d.part[dot_slot * kPartSlot + blockIdx.x] = bsum;
-  }
-}
-
-// ======================================================================================
-// Heat operator (Section 4.3.2): point phase stores K V^n grad T_p and h |dA_r| T(s_r);
-// node phase forms c_p/dt m_i T_i + sum_p (K V grad T_p) . grad N_i + sum_r h|dA| T_r N_i.
-// ======================================================================================
-template <int D, typename R>
-__global__ void k_heat_points(Dev<R> d, const R* T, const int* done) {
-  if (done && *done) return;
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
-  const int N = d.np, S = d.ns;
-  if (q < N) {
-    R x[D];
-#pragma unroll
-    for (int a = 0; a < D; ++a) x[a] = d.px[a * N + q];
-    Stencil<D, R> st; bool bad = false;
-    make_stencil<D, R>(x, d.n, d.fn, st, &bad);
-    R gT[D];
-#pragma unroll
-    for (int a = 0; a < D; ++a) gT[a] = 0;
-    for_stencil<D>([&](int k0, int k1, int k2) {
-      int nd[3] = {st.c[0] - 1 + k0, st.c[1] - 1 + k1, D == 3 ? st.c[2] - 1 + k2 : 0};
-      R g[D];
-      node_weight<D, R>(st, k0, k1, k2, g);
-      R Tj = T[tiled_index<D>(nd, d.nt)];
-#pragma unroll
-      for (int a = 0; a < D; ++a) gT[a] += Tj * g[a];
-    });
-    R c = d.K * d.pVn[q];
-#pragma unroll
-    for (int a = 0; a < D; ++a) d.pS[a * N + q] = c * gT[a];
-  } else if (q < N + S) {
-    int r = q - N;
-    R x[D], area = 0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) { x[a] = d.ss[a * S + r]; area += d.sdA[a * S + r] * d.sdA[a * S + r]; }
-    Stencil<D, R> st; bool bad = false;
-    make_stencil<D, R>(x, d.n, d.fn, st, &bad);
-    R Ts = 0;
-    for_stencil<D>([&](int k0, int k1, int k2) {
-      int nd[3] = {st.c[0] - 1 + k0, st.c[1] - 1 + k1, D == 3 ? st.c[2] - 1 + k2 : 0};
-      R g[D];
-      R Nw = node_weight<D, R>(st, k0, k1, k2, g);
-      Ts += Nw * T[tiled_index<D>(nd, d.nt)];
-    });
-    d.sS[r] = d.h * sqrt(area) * Ts;
-  }
-}
-
-template <int D, typename R>
-__global__ void __launch_bounds__(64) k_heat_nodes(Dev<R> d, const R* T, R* out, const int* done, int dot_slot) {
-  __shared__ double sh[16];
-  if (done && *done) return;
-  int t = d.tile_list[blockIdx.x];
-  int lane = threadIdx.x;
-  int node = t * kTileNodes + lane;
-  int i[3] = {0, 0, 0};
-  tiled_coords<D>(t, lane, d.nt, i);
-  const int N = d.np, S = d.ns;
-  R acc = 0;
-  for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
-    for (int dy = -1; dy <= 1; ++dy)
-      for (int dxo = -1; dxo <= 1; ++dxo) {
-        int c[3] = {i[0] + dxo, i[1] + dy, i[2] + dz};
-        int off[3] = {dxo, dy, dz};
-        bool in = true;
-#pragma unroll
-        for (int a = 0; a < D; ++a) in = in && c[a] >= 0 && c[a] < d.n;
-        if (!in) continue;
-        int ci = (int)tiled_index<D>(c, d.nt);
-        int kk[D];
-#pragma unroll
-        for (int a = 0; a < D; ++a) kk[a] = 1 - off[a];
-        for (int k = d.p_start[ci]; k < d.p_start[ci + 1]; ++k) {
-          R f[D], g[D];
-#pragma unroll
-          for (int a = 0; a < D; ++a) f[a] = d.px[a * N + k] * d.fn - R(c[a]);
-          weight_from_cell<D, R>(kk, f, d.fn, g);
-#pragma unroll
-          for (int a = 0; a < D; ++a) acc += d.pS[a * N + k] * g[a];
-        }
-        if (S)
-          for (int r = d.s_start[ci]; r < d.s_start[ci + 1]; ++r) {
-            R f[D], g[D];
-#pragma unroll
-            for (int a = 0; a < D; ++a) f[a] = d.ss[a * S + r] * d.fn - R(c[a]);
-            R Nw = weight_from_cell<D, R>(kk, f, d.fn, g);
-            acc += d.sS[r] * Nw;
-          }
-      }
-  bool dof = d.gfree[node] & 0x80;
-  R Ti = T[node];
-  R o = dof ? d.cp / d.dt * d.gm[node] * Ti + acc : R(0);
-  out[node] = o;
-  if (dot_slot >= 0) {
-    double bsum = block_sum(dof ? (double)Ti * (double)o : 0.0, sh);
-    if (threadIdx.x == 0) d.part[dot_slot * kPartSlot + blockIdx.x] = bsum;
-  }
-}
 
 // ======================================================================================
 // G2P with merge (Section 5).

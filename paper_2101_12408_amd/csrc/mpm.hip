@@ -9,7 +9,7 @@
 #include <string>
 #include <vector>
 
-#include "kernels.h"
+#include "tiles.h"
 
 using namespace mpm;
 
@@ -77,6 +77,12 @@ struct mpm_ctx {
        *pp = nullptr, *Ap = nullptr, *zero = nullptr, *gscratch = nullptr;
   void *That = nullptr, *hr = nullptr, *hz = nullptr, *hp = nullptr, *hAp = nullptr;
   int* tile_pos = nullptr;
+  int* ctile_flag = nullptr;
+  int* ctile_pos = nullptr;
+  int* ctile_list = nullptr;
+  int* ctile_slot = nullptr;
+  void* tpart = nullptr;        // per-cell-tile region partials
+  int nctile = 0;
   int* scan_bsum = nullptr;
   int* misc = nullptr;          // [0] status, [1] constrained flag, [2] tile count
   double* part = nullptr;
@@ -152,6 +158,14 @@ size_t layout(mpm_ctx* c, char* base) {
   d.ccount = b.take<int>(NN);
   d.tile_flag = b.take<int>(NT); d.tile_list = b.take<int>(NT);
   int* tile_pos = b.take<int>(NT + 1);
+  int* ctile_flag = b.take<int>(NT);
+  int* ctile_pos = b.take<int>(NT + 1);
+  int* ctile_list = b.take<int>(NT);
+  int* ctile_slot = b.take<int>(NT);
+  const int64_t nct_cap = std::min<int64_t>(NT, NP + 2 * NS);
+  const int RNd = D == 3 ? TileGeo<3>::RN : TileGeo<2>::RN;
+  const int NFmax = std::max(2 * D + 7, D);
+  void* tpart = b.take<R>((size_t)nct_cap * RNd * NFmax);
   int* scan_bsum = b.take<int>(kScanBlock + 1);
   int* misc = b.take<int>(64);
   d.px = b.take<R>(D * NP); d.pv = b.take<R>(D * NP); d.pA = b.take<R>(D * D * NP);
@@ -159,7 +173,7 @@ size_t layout(mpm_ctx* c, char* base) {
   d.pT = b.take<R>(NP); d.pgT = b.take<R>(D * NP); d.pmu = b.take<R>(NP); d.pVn = b.take<R>(NP);
   d.pS = b.take<R>(D * D * NP);
   d.ss = b.take<R>(D * NS); d.sdA = b.take<R>(D * NS); d.sk = b.take<R>(NS); d.sk_orig = b.take<R>(NS); d.sS = b.take<R>(D * D * NS);
-  d.sc = b.take<R>((D + D * D) * NS); d.bx = b.take<R>(D * NS); d.bx_unsorted = b.take<R>(D * NS);
+  d.sc = b.take<R>((D + D * D) * NS); d.sF = b.take<R>(D * D * NS); d.bx = b.take<R>(D * NS); d.bx_unsorted = b.take<R>(D * NS);
   d.gm = b.take<R>(NN); d.gW = b.take<R>(NN); d.gWT = b.take<R>(NN); d.gE = b.take<R>(NN);
   d.gET = b.take<R>(NN); d.gTn = b.take<R>(NN); d.hdiag = b.take<R>(NN); d.hrhs = b.take<R>(NN);
   d.gmv = b.take<R>(D * NN); d.gvn = b.take<R>(D * NN); d.gdiag = b.take<R>(D * NN);
@@ -177,6 +191,8 @@ size_t layout(mpm_ctx* c, char* base) {
     c->z = vecs[5]; c->pp = vecs[6]; c->Ap = vecs[7]; c->zero = vecs[8]; c->gscratch = vecs[9];
     c->That = hvecs[0]; c->hr = hvecs[1]; c->hz = hvecs[2]; c->hp = hvecs[3]; c->hAp = hvecs[4];
     c->tile_pos = tile_pos; c->scan_bsum = scan_bsum; c->misc = misc;
+    c->ctile_flag = ctile_flag; c->ctile_pos = ctile_pos; c->ctile_list = ctile_list; c->ctile_slot = ctile_slot;
+    c->tpart = tpart;
     c->part = d.part; c->scal = d.scal; c->cg = cg;
     if constexpr (sizeof(R) == 8) c->d64 = d; else c->d32 = d;
   }
@@ -239,6 +255,14 @@ template <typename R> Dev<R>& dev(mpm_ctx* c);
 template <> Dev<double>& dev<double>(mpm_ctx* c) { return c->d64; }
 template <> Dev<float>& dev<float>(mpm_ctx* c) { return c->d32; }
 
+TileLists tiles(mpm_ctx* c) {
+  TileLists t;
+  t.ctile_list = c->ctile_list;
+  t.ctile_slot = c->ctile_slot;
+  t.nctile = c->nctile;
+  return t;
+}
+
 int krylov_blocks(int nelem) { return std::max(1, std::min(1024, cdiv(nelem, 256))); }
 
 void sync_read(mpm_ctx* c, hipStream_t s, const void* src, void* dst, size_t bytes) {
@@ -289,21 +313,33 @@ void do_p2g(mpm_ctx* c, const mpm_particles* P, const mpm_surface* S, hipStream_
     cell_sort<D, R>(c, d, (const R*)d.bx_unsorted, c->ns, d.b_key, d.b_src, d.b_start, s);
     LAUNCH(c, MPM_K_SETUP, (k_gather_balance<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d);
   }
-  // active tiles
+  // active cell tiles (hold points) and node tiles (hold a stencil node of a point)
+  LAUNCH(c, MPM_K_SETUP, (k_flag_ctiles<D, R>), dim3(cdiv(c->ntile_total, 256)), dim3(256), 0, s, d, c->ctile_flag,
+         c->ntile_total);
+  scan(c, c->ctile_flag, c->ctile_pos, c->ntile_total, s);
+  LAUNCH(c, MPM_K_SETUP, k_ctile_slots, dim3(cdiv(c->ntile_total, 256)), dim3(256), 0, s, (const int*)c->ctile_flag,
+         (const int*)c->ctile_pos, c->ntile_total, c->ctile_list, c->ctile_slot);
   LAUNCH(c, MPM_K_SETUP, (k_mark_tiles<D, R>), dim3(cdiv(d.nn, 256)), dim3(256), 0, s, d);
   scan(c, d.tile_flag, c->tile_pos, c->ntile_total, s);
   LAUNCH(c, MPM_K_SETUP, k_compact_tiles, dim3(cdiv(c->ntile_total, 256)), dim3(256), 0, s, (const int*)d.tile_flag,
-                     (const int*)c->tile_pos, c->ntile_total, d.tile_list);
-  sync_read(c, s, c->tile_pos + c->ntile_total, c->hint, sizeof(int));
+         (const int*)c->tile_pos, c->ntile_total, d.tile_list);
+  HIPCHK(hipMemcpyAsync(c->hint, c->tile_pos + c->ntile_total, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(c->hint + 1, c->ctile_pos + c->ntile_total, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
   c->ntiles = c->hint[0];
+  c->nctile = c->hint[1];
   c->prev_ntiles = c->ntiles;
-  // A2/A3: P2G and grid set-up
-  if (c->ntiles > 0) LAUNCH(c, MPM_K_P2G, (k_p2g_nodes<D, R>), dim3(c->ntiles), dim3(64), 0, s, d);
+  // A2/A3: P2G (cell-tile scatter, merge) and grid set-up
+  TileLists tl = tiles(c);
+  if (c->nctile > 0)
+    LAUNCH(c, MPM_K_P2G, (k_tile_p2g<D, R>), dim3(c->nctile), dim3(TileGeo<D>::NT), 0, s, d, tl, (R*)c->tpart);
+  if (c->ntiles > 0)
+    LAUNCH(c, MPM_K_P2G, (k_merge_p2g<D, R>), dim3(c->ntiles), dim3(64), 0, s, d, tl, (const R*)c->tpart);
   if (c->ns > 0) LAUNCH(c, MPM_K_SETUP, (k_surface_k<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d);
   // degrees of freedom and whether any of them has a fixed component
   if (c->ntiles > 0)
     LAUNCH(c, MPM_K_SETUP, (k_dof_flags<D>), dim3(c->ntiles), dim3(64), 0, s, (const int*)d.tile_list,
-                       (const uint8_t*)d.gfree, c->misc);
+           (const uint8_t*)d.gfree, c->misc);
   c->have_p2g = true;
   c->stats = mpm_stats{};
   c->stats.n_part = c->np;
@@ -323,64 +359,70 @@ bool any_constrained(mpm_ctx* c, hipStream_t s) {
 template <int D, typename R>
 void do_energy_grad(mpm_ctx* c, const R* u, R* g, double* energy_dev, hipStream_t s) {
   Dev<R>& d = dev<R>(c);
-  int nbp = std::max(1, cdiv(c->np, 256)), nbs = std::max(1, cdiv(c->ns, 256));
-  if (c->np > 0)
-    LAUNCH(c, MPM_K_ENERGY_INT, (k_points_interior<D, R>), dim3(nbp), dim3(256), 0, s, d, u, (int)PM_ENERGY, 0,
-                       (const int*)nullptr, 2);
+  TileLists tl = tiles(c);
+  if (c->nctile > 0)
+    LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_ENERGY>), dim3(c->nctile), dim3(TileGeo<D>::NT), 0, s, d, tl,
+           u, (R*)c->tpart, 0, (const int*)nullptr, 2);
   else
     LAUNCH(c, MPM_K_BLAS, k_fill_r<double>, dim3(1), dim3(1), 0, s, c->part + 2 * kPartSlot, 0.0, (int64_t)1);
-  if (c->ns > 0)
-    LAUNCH(c, MPM_K_ENERGY_SURF, (k_points_surface<D, R>), dim3(nbs), dim3(256), 0, s, d, u, u, (int)PM_ENERGY, 0,
-                       (const int*)nullptr, 3);
-  else
-    LAUNCH(c, MPM_K_BLAS, k_fill_r<double>, dim3(1), dim3(1), 0, s, c->part + 3 * kPartSlot, 0.0, (int64_t)1);
   if (c->ntiles > 0)
-    LAUNCH(c, MPM_K_ENERGY_NODE, (k_stress_nodes<D, R>), dim3(c->ntiles), dim3(64), 0, s, d, u, g, (int)NM_GRAD, 0.0, 0,
-                       (const int*)nullptr, 4, -1);
-  LAUNCH(c, MPM_K_REDUCE, k_finalize, dim3(1), dim3(256), 0, s, c->part + 2 * kPartSlot, c->np > 0 ? nbp : 1, 1, c->scal + 8);
-  LAUNCH(c, MPM_K_REDUCE, k_finalize, dim3(1), dim3(256), 0, s, c->part + 3 * kPartSlot, c->ns > 0 ? nbs : 1, 1, c->scal + 9);
-  LAUNCH(c, MPM_K_REDUCE, k_finalize, dim3(1), dim3(256), 0, s, c->part + 4 * kPartSlot, std::max(c->ntiles, 1), 1, c->scal + 10);
+    LAUNCH(c, MPM_K_ENERGY_NODE, (k_merge_stress<D, R>), dim3(c->ntiles), dim3(64), 0, s, d, tl, (const R*)c->tpart,
+           u, g, (int)NM_GRAD, 0.0, 0, (const int*)nullptr, 4, -1);
+  else
+    LAUNCH(c, MPM_K_BLAS, k_fill_r<double>, dim3(1), dim3(1), 0, s, c->part + 4 * kPartSlot, 0.0, (int64_t)1);
+  LAUNCH(c, MPM_K_REDUCE, k_finalize, dim3(1), dim3(256), 0, s, c->part + 2 * kPartSlot, std::max(c->nctile, 1), 1,
+         c->scal + 8);
+  LAUNCH(c, MPM_K_REDUCE, k_fill_r<double>, dim3(1), dim3(1), 0, s, c->scal + 9, 0.0, (int64_t)1);
+  LAUNCH(c, MPM_K_REDUCE, k_finalize, dim3(1), dim3(256), 0, s, c->part + 4 * kPartSlot, std::max(c->ntiles, 1), 1,
+         c->scal + 10);
   LAUNCH(c, MPM_K_REDUCE, k_sum3, dim3(1), dim3(1), 0, s, (const double*)(c->scal + 8), c->scal + 0, energy_dev);
 }
 
+// Caches the surface linearization point F_r = I + dt grad v_lin(s_r).
 template <int D, typename R>
-void do_hessvec(mpm_ctx* c, const R* vlin, const R* w, double alpha, R* out, bool mask_in, const int* done,
-                int dot_slot, hipStream_t s) {
+void do_surface_lin(mpm_ctx* c, const R* vlin, hipStream_t s) {
   Dev<R>& d = dev<R>(c);
-  if (c->np > 0 && (d.term_mask & 5))
-    LAUNCH(c, MPM_K_HESS_INT, (k_points_interior<D, R>), dim3(cdiv(c->np, 256)), dim3(256), 0, s, d, w, (int)PM_HESS,
-                       (int)mask_in, done, -1);
   if (c->ns > 0 && (d.term_mask & 2))
-    LAUNCH(c, MPM_K_HESS_SURF, (k_points_surface<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d, vlin, w,
-                       (int)PM_HESS, (int)mask_in, done, -1);
+    LAUNCH(c, MPM_K_HESS_SURF, (k_surface_F<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d, vlin);
+}
+
+// out = P(alpha M P w + H P w) with the surface term linearized at the cached F_r.
+template <int D, typename R>
+void do_hessvec(mpm_ctx* c, const R* w, double alpha, R* out, bool mask_in, const int* done, int dot_slot,
+                hipStream_t s) {
+  Dev<R>& d = dev<R>(c);
+  TileLists tl = tiles(c);
+  if (c->nctile > 0)
+    LAUNCH(c, MPM_K_HESS_INT, (k_tile_stress<D, R, TM_HESS>), dim3(c->nctile), dim3(TileGeo<D>::NT), 0, s, d, tl, w,
+           (R*)c->tpart, (int)mask_in, done, -1);
   if (c->ntiles > 0)
-    LAUNCH(c, MPM_K_HESS_NODE, (k_stress_nodes<D, R>), dim3(c->ntiles), dim3(64), 0, s, d, w, out, (int)NM_HESS, alpha,
-                       (int)mask_in, done, -1, dot_slot);
+    LAUNCH(c, MPM_K_HESS_NODE, (k_merge_stress<D, R>), dim3(c->ntiles), dim3(64), 0, s, d, tl, (const R*)c->tpart,
+           w, out, (int)NM_HESS, alpha, (int)mask_in, done, -1, dot_slot);
 }
 
 // Forces only (no inertia term): out = P sum_q S_q grad N_i for the stress of u.
 template <int D, typename R>
 void do_hessvec_force(mpm_ctx* c, const R* u, R* out, hipStream_t s) {
   Dev<R>& d = dev<R>(c);
-  int nbp = std::max(1, cdiv(c->np, 256)), nbs = std::max(1, cdiv(c->ns, 256));
-  if (c->np > 0 && (d.term_mask & 5))
-    LAUNCH(c, MPM_K_ENERGY_INT, (k_points_interior<D, R>), dim3(nbp), dim3(256), 0, s, d, u, (int)PM_ENERGY, 0,
-                       (const int*)nullptr, 2);
-  if (c->ns > 0 && (d.term_mask & 2))
-    LAUNCH(c, MPM_K_ENERGY_SURF, (k_points_surface<D, R>), dim3(nbs), dim3(256), 0, s, d, u, u, (int)PM_ENERGY, 0,
-                       (const int*)nullptr, 3);
+  TileLists tl = tiles(c);
+  if (c->nctile > 0)
+    LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_FORCE>), dim3(c->nctile), dim3(TileGeo<D>::NT), 0, s, d, tl,
+           u, (R*)c->tpart, 0, (const int*)nullptr, -1);
   if (c->ntiles > 0)
-    LAUNCH(c, MPM_K_ENERGY_NODE, (k_stress_nodes<D, R>), dim3(c->ntiles), dim3(64), 0, s, d, u, out, (int)NM_HESS, 0.0, 0,
-                       (const int*)nullptr, -1, -1);
+    LAUNCH(c, MPM_K_ENERGY_NODE, (k_merge_stress<D, R>), dim3(c->ntiles), dim3(64), 0, s, d, tl, (const R*)c->tpart,
+           u, out, (int)NM_HESS, 0.0, 0, (const int*)nullptr, -1, -1);
 }
 
 template <int D, typename R>
 void do_heat_apply(mpm_ctx* c, const R* T, R* out, const int* done, int dot_slot, hipStream_t s) {
   Dev<R>& d = dev<R>(c);
-  if (c->np + c->ns > 0)
-    LAUNCH(c, MPM_K_HEAT_PT, (k_heat_points<D, R>), dim3(cdiv(c->np + c->ns, 256)), dim3(256), 0, s, d, T, done);
+  TileLists tl = tiles(c);
+  if (c->nctile > 0)
+    LAUNCH(c, MPM_K_HEAT_PT, (k_tile_heat<D, R>), dim3(c->nctile), dim3(TileGeo<D>::NT), 0, s, d, tl, T,
+           (R*)c->tpart, done);
   if (c->ntiles > 0)
-    LAUNCH(c, MPM_K_HEAT_NODE, (k_heat_nodes<D, R>), dim3(c->ntiles), dim3(64), 0, s, d, T, out, done, dot_slot);
+    LAUNCH(c, MPM_K_HEAT_NODE, (k_merge_heat<D, R>), dim3(c->ntiles), dim3(64), 0, s, d, tl, (const R*)c->tpart, T,
+           out, done, dot_slot);
 }
 
 template <int D, typename R>
@@ -482,7 +524,7 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
   st.energy_evals = 1;
   st.converged = 0;
   auto apply = [&](const R* pv, R* Apv, const int* done, int slot) {
-    do_hessvec<D, R>(c, vhat, pv, 1.0, Apv, false, done, slot, s);
+    do_hessvec<D, R>(c, pv, 1.0, Apv, false, done, slot, s);
   };
   int it = 0;
   double gn_prev = 1e300;
@@ -493,6 +535,7 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
     // (1e-4 |g0|) and a Newton step no longer halves it, the solve has reached that floor.
     if (sizeof(R) == 4 && gn <= 1e-4 * g0 && gn > 0.5 * gn_prev) { st.converged = 2; break; }
     gn_prev = gn;
+    do_surface_lin<D, R>(c, vhat, s);
     LAUNCH(c, MPM_K_BLAS, k_neg<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const R*)g, vtrial);
     double cg_tol = std::max(p.cg_rel * gn, 0.1 * p.newton_tol * g0);
     int cit = cg_solve<R>(c, apply, vtrial, delta, false, (const R*)d.gdiag, (R*)c->r, (R*)c->z, (R*)c->pp,
@@ -799,7 +842,8 @@ int mpm_hessvec(mpm_ctx* ctx, const void* v_lin, const void* w, double alpha_mas
     dispatch(ctx, [&](auto Dc, auto Rv) {
       constexpr int D = decltype(Dc)::value;
       using R = decltype(Rv);
-      do_hessvec<D, R>(ctx, (const R*)v_lin, (const R*)w, alpha_mass, (R*)out, true, nullptr, -1, s);
+      do_surface_lin<D, R>(ctx, (const R*)v_lin, s);
+      do_hessvec<D, R>(ctx, (const R*)w, alpha_mass, (R*)out, true, nullptr, -1, s);
     });
   });
   return rc != MPM_OK ? rc : check_launch(ctx);

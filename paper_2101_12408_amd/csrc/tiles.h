@@ -1,0 +1,970 @@
+// Cell-tile kernels: the scatter halves of P2G, the energy gradient, the Hessian-vector
+// product and the heat operator.
+//
+// One workgroup owns one tile of cells (4x4x4 in 3D, 8x8 in 2D).  Its points (interior
+// particles, surface samples, balance points: contiguous ranges after the cell sort) are
+// staged through LDS in chunks.  The point phase gathers what it needs from the tile's
+// node region (6^3 / 10^2 nodes, staged in LDS) and stores a per-point payload; the
+// scatter phase maps lanes to (cell, k0, k1): each lane accumulates, in registers and in
+// the fixed order of the cell's points, the contributions to the 3 nodes
+// (c0-1+k0, c1-1+k1, c2-1+k2), k2 = 0..2 (3D) or to the 3 nodes along k1 (2D); the
+// per-cell partials are then reduced in LDS, in fixed order, onto the node region, which
+// is written to a per-tile partial buffer.  A merge kernel sums, for every node, the
+// partials of the <= 2^d tiles whose region holds it (fixed order) and applies the
+// node-level terms.  No float atomics anywhere: results are bitwise reproducible.
+#pragma once
+#include "kernels.h"
+
+namespace mpm {
+
+template <int D> struct TileGeo;
+template <> struct TileGeo<3> {
+  static constexpr int E = 4;          // cells per tile edge
+  static constexpr int RE = 6;         // node-region edge (E + 2)
+  static constexpr int RN = 216;       // region nodes
+  static constexpr int LPC = 9;        // scatter lanes per cell (k0, k1)
+  static constexpr int NT = 576;       // threads per workgroup (64 cells x 9)
+};
+template <> struct TileGeo<2> {
+  static constexpr int E = 8;
+  static constexpr int RE = 10;
+  static constexpr int RN = 100;
+  static constexpr int LPC = 3;        // (k0), k1 looped
+  static constexpr int NT = 192;
+};
+
+// Device view of the tile lists.
+struct TileLists {
+  const int* ctile_list;   // active cell tiles (compact)
+  const int* ctile_slot;   // cell tile -> slot in ctile_list, -1 when inactive
+  int nctile;
+};
+
+// Local coordinates of cell lc (tile-local tiled order) and of region node rn.
+template <int D>
+MPM_DEV void local_cell(int lc, int* c) {
+  constexpr int E = TileGeo<D>::E, L = Tiling<D>::LOG;
+  c[0] = lc & (E - 1);
+  c[1] = (lc >> L) & (E - 1);
+  c[2] = D == 3 ? (lc >> (2 * L)) : 0;
+}
+
+template <int D>
+MPM_DEV void region_coords(int rn, int* r) {
+  constexpr int RE = TileGeo<D>::RE;
+  r[0] = rn % RE;
+  r[1] = (rn / RE) % RE;
+  r[2] = D == 3 ? rn / (RE * RE) : 0;
+}
+
+template <int D>
+MPM_DEV int region_index(const int* r) {
+  constexpr int RE = TileGeo<D>::RE;
+  return r[0] + RE * (r[1] + (D == 3 ? RE * r[2] : 0));
+}
+
+// Global tiled index of region node r of cell tile ct (region origin = first cell - 1);
+// -1 outside the grid.
+template <int D>
+MPM_DEV int region_node_global(int ct, const int* r, int n, int nt) {
+  int t[3] = {0, 0, 0};
+  tiled_coords<D>(ct, 0, nt, t);       // first cell of the tile
+  int g[3] = {0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    g[a] = t[a] - 1 + r[a];
+    if (g[a] < 0 || g[a] >= n) return -1;
+  }
+  return (int)tiled_index<D>(g, nt);
+}
+
+// ---------------------------------------------------------------------------------------
+// Scatter engine: lanes (cell, k0[, k1]) accumulate NF fields on their 3 nodes.
+//   contrib(q, w, g, out[NF]) adds point q's contribution at one node with weight w and
+//   weight gradient g (node-relative offsets known to the lane through kk).
+// ---------------------------------------------------------------------------------------
+template <int D, typename R, int NF>
+struct LaneAcc {
+  R v[3][NF];
+  MPM_DEV void zero() {
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int f = 0; f < NF; ++f) v[k][f] = 0;
+  }
+};
+
+// Writes the lane accumulators to the per-cell LDS partial buffer (fields f0..f0+FC) and
+// reduces them onto the node region: reg[rn][f] = sum over cells c, offsets k with
+// c + k = rn (fixed order).  Caller synchronizes around.
+template <int D, typename R, int NF, int FC>
+MPM_DEV void reduce_cells_to_region(const LaneAcc<D, R, NF>& acc, int f0, R* cellpart, R* reg, int lane_cell,
+                                    int lane_k0, int lane_k1, bool lane_on) {
+  constexpr int RN = TileGeo<D>::RN, NT = TileGeo<D>::NT, E = TileGeo<D>::E;
+  // cellpart layout: [cell 64][k2 3][k1 3][k0 3][FC]  (3D)  /  [cell 64][k1 3][k0 3][FC] (2D)
+  if (lane_on) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int f = 0; f < FC; ++f) {
+        if (f0 + f >= NF) continue;
+        int kk2 = D == 3 ? k : 0, kk1 = D == 3 ? lane_k1 : k;
+        int idx = (((lane_cell * 3 + kk2) * 3 + kk1) * 3 + lane_k0) * FC + f;
+        cellpart[idx] = acc.v[k][f0 + f];
+      }
+  }
+  __syncthreads();
+  for (int rn = threadIdx.x; rn < RN; rn += NT) {
+    int r[3];
+    region_coords<D>(rn, r);
+    R s[FC];
+#pragma unroll
+    for (int f = 0; f < FC; ++f) s[f] = 0;
+    // cells c = r - k in [0, E)
+    for (int k2 = (D == 3 ? 0 : 0); k2 < (D == 3 ? 3 : 1); ++k2) {
+      int c2 = D == 3 ? r[2] - k2 : 0;
+      if (c2 < 0 || c2 >= (D == 3 ? E : 1)) continue;
+      for (int k1 = 0; k1 < 3; ++k1) {
+        int c1 = r[1] - k1;
+        if (c1 < 0 || c1 >= E) continue;
+        for (int k0 = 0; k0 < 3; ++k0) {
+          int c0 = r[0] - k0;
+          if (c0 < 0 || c0 >= E) continue;
+          int cc[3] = {c0, c1, c2};
+          int lc = (int)tiled_index<D>(cc, 1) & 63;
+          int base = (((lc * 3 + (D == 3 ? k2 : 0)) * 3 + k1) * 3 + k0) * FC;
+#pragma unroll
+          for (int f = 0; f < FC; ++f) s[f] += cellpart[base + f];
+        }
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < FC; ++f) reg[rn * FC + f] = s[f];
+  }
+  __syncthreads();
+}
+
+// Lane mapping of the scatter phase.
+template <int D>
+MPM_DEV void lane_map(int t, int& cell, int& k0, int& k1) {
+  if constexpr (D == 3) {
+    cell = t / 9;
+    k0 = t % 3;
+    k1 = (t / 3) % 3;
+  } else {
+    cell = t / 3;
+    k0 = t % 3;
+    k1 = 0;
+  }
+}
+
+// Weight / gradient of the lane's node number k (k2 in 3D, k1 in 2D) from cell-relative f.
+template <int D, typename R>
+MPM_DEV R lane_weight(const R* f, int k0, int k1, int k, R fn, R* g) {
+  int kk[3] = {k0, D == 3 ? k1 : k, D == 3 ? k : 0};
+  return weight_from_cell<D, R>(kk, f, fn, g);
+}
+
+// Surface derivative Q = d|cof(F) N|/dF (HESS = false) or its linearization along
+// dG = dt G (HESS = true, PSD part plus the indefinite part when exact); returns |cof(F) N|.
+template <int D, typename R>
+MPM_DEV R surface_q(const R (&F)[D][D], const R* Nv, bool hess, const R (&G)[D][D], R dt, int exact, R (&Q)[D][D]) {
+  if constexpr (D == 3) {
+    R av[3] = {0, 0, 0};
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      int p = (m + 1) % 3, q = (m + 2) % 3;
+      R cx = F[1][p] * F[2][q] - F[2][p] * F[1][q];
+      R cy = F[2][p] * F[0][q] - F[0][p] * F[2][q];
+      R cz = F[0][p] * F[1][q] - F[1][p] * F[0][q];
+      av[0] += cx * Nv[m]; av[1] += cy * Nv[m]; av[2] += cz * Nv[m];
+    }
+    R an = sqrt(av[0] * av[0] + av[1] * av[1] + av[2] * av[2]);
+    R ah[3] = {av[0] / an, av[1] / an, av[2] / an};
+    R uu[3] = {ah[0], ah[1], ah[2]};
+    R dG[3][3];
+    if (hess) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) dG[a][b] = dt * G[a][b];
+      R da[3] = {0, 0, 0};
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
+        R dg1[3] = {dG[0][k1], dG[1][k1], dG[2][k1]}, dg2[3] = {dG[0][k2], dG[1][k2], dG[2][k2]};
+        R g1[3] = {F[0][k1], F[1][k1], F[2][k1]}, g2[3] = {F[0][k2], F[1][k2], F[2][k2]};
+        R c1[3], c2[3];
+        cross3<R>(dg1, g2, c1);
+        cross3<R>(g1, dg2, c2);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) da[a] += Nv[k] * (c1[a] + c2[a]);
+      }
+      R ad = ah[0] * da[0] + ah[1] * da[1] + ah[2] * da[2];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) uu[a] = (da[a] - ah[a] * ad) / an;
+    }
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      int m1 = (m + 1) % 3, m2 = (m + 2) % 3;
+      R gp[3] = {F[0][m1], F[1][m1], F[2][m1]}, gq[3] = {F[0][m2], F[1][m2], F[2][m2]};
+      R c1[3], c2[3];
+      cross3<R>(gp, uu, c1);
+      cross3<R>(uu, gq, c2);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) Q[a][m] = Nv[m2] * c1[a] + Nv[m1] * c2[a];
+      if (hess && exact) {
+        R dp[3] = {dG[0][m1], dG[1][m1], dG[2][m1]}, dq[3] = {dG[0][m2], dG[1][m2], dG[2][m2]};
+        cross3<R>(dp, ah, c1);
+        cross3<R>(ah, dq, c2);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) Q[a][m] += Nv[m2] * c1[a] + Nv[m1] * c2[a];
+      }
+    }
+    return an;
+  } else {
+    R tau[2] = {Nv[1], -Nv[0]};
+    R cv[2] = {F[0][0] * tau[0] + F[0][1] * tau[1], F[1][0] * tau[0] + F[1][1] * tau[1]};
+    R cn = sqrt(cv[0] * cv[0] + cv[1] * cv[1]);
+    R ch[2] = {cv[0] / cn, cv[1] / cn};
+    R uu[2] = {ch[0], ch[1]};
+    if (hess) {
+      R dc[2] = {dt * (G[0][0] * tau[0] + G[0][1] * tau[1]), dt * (G[1][0] * tau[0] + G[1][1] * tau[1])};
+      R cd = ch[0] * dc[0] + ch[1] * dc[1];
+      uu[0] = (dc[0] - ch[0] * cd) / cn;
+      uu[1] = (dc[1] - ch[1] * cd) / cn;
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) Q[a][b] = uu[a] * tau[b];
+    // |cof(F) N| = |F tau| in 2D
+    return cn;
+  }
+}
+
+// ======================================================================================
+// Stress scatter: energy gradient (ENERGY), Hessian-vector product (HESS) or the force
+// of a given velocity field (FORCE, no energy).  Output: per-tile partial of
+// sum_q S_q grad N_i over the region (D components per node).
+// ======================================================================================
+enum TileMode { TM_ENERGY = 0, TM_HESS = 1, TM_FORCE = 2 };
+
+template <int D, typename R>
+struct StressLds {
+  static constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
+  R u[RN * D];                 // input field on the node region
+  R pf[NT * D];                // point cell-relative positions
+  R pS[NT * D * D];            // point stresses
+  R cellpart[64 * 27 * D];     // per-cell partials (FC = D)
+  double red[16];
+};
+
+template <int D, typename R, int MODE>
+__global__ void __launch_bounds__(TileGeo<D>::NT) k_tile_stress(Dev<R> d, TileLists tl, const R* u, R* tpart,
+                                                                int mask_in, const int* done, int energy_slot) {
+  constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN, RE = TileGeo<D>::RE;
+  __shared__ StressLds<D, R> sm;
+  if (done && *done) return;
+  const int ct = tl.ctile_list[blockIdx.x];
+  const int N = d.np, S = d.ns, nn = d.nn;
+  const int t = threadIdx.x;
+  const R dt = d.dt;
+  // region origin (global node coordinates of region node 0)
+  int org[3] = {0, 0, 0};
+  tiled_coords<D>(ct, 0, d.nt, org);
+#pragma unroll
+  for (int a = 0; a < D; ++a) org[a] -= 1;
+  // stage u on the region
+  for (int rn = t; rn < RN; rn += NT) {
+    int r[3];
+    region_coords<D>(rn, r);
+    int gnode = region_node_global<D>(ct, r, d.n, d.nt);
+    uint8_t fr = (gnode >= 0 && mask_in) ? d.gfree[gnode] : 0xff;
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+      sm.u[rn * D + a] = (gnode >= 0 && ((fr >> a) & 1)) ? u[a * nn + gnode] : R(0);
+  }
+  const int cb = ct * 64;
+  const int pb = d.p_start[cb], pe = d.p_start[cb + 64];
+  const bool surf = (d.term_mask & 2) && S > 0;
+  const int sb = surf ? d.s_start[cb] : 0, se = surf ? d.s_start[cb + 64] : 0;
+  const bool vol = (d.term_mask & 5) != 0;
+  const int npi = vol ? pe - pb : 0;
+  const int ntot = npi + (se - sb);
+  int lcell, lk0, lk1;
+  lane_map<D>(t, lcell, lk0, lk1);
+  const bool lane_on = t < 64 * TileGeo<D>::LPC;
+  // the lane's cell ranges
+  int cpb = 0, cpe = 0, csb = 0, cse = 0;
+  if (lane_on) {
+    if (vol) { cpb = d.p_start[cb + lcell] - pb; cpe = d.p_start[cb + lcell + 1] - pb; }
+    if (surf) { csb = d.s_start[cb + lcell] - sb + npi; cse = d.s_start[cb + lcell + 1] - sb + npi; }
+  }
+  LaneAcc<D, R, D> acc;
+  acc.zero();
+  double e = 0;
+  __syncthreads();
+  for (int q0 = 0; q0 < ntot; q0 += NT) {
+    // ---- point phase ----
+    int q = q0 + t;
+    if (q < ntot) {
+      R x[D];
+      bool interior = q < npi;
+      int k = interior ? pb + q : sb + (q - npi);
+#pragma unroll
+      for (int a = 0; a < D; ++a) x[a] = interior ? d.px[a * N + k] : d.ss[a * S + k];
+      R f[D];
+      int lc[3];
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        R xs = x[a] * d.fn;
+        R cf = floor(xs);
+        f[a] = xs - cf;
+        lc[a] = (int)cf - (org[a] + 1);
+        lc[a] = lc[a] < 0 ? 0 : (lc[a] > TileGeo<D>::E - 1 ? TileGeo<D>::E - 1 : lc[a]);   // clamped points only
+      }
+      // gradient of u at the point from the staged region (nodes lc + k in region coords)
+      R G[D][D];
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = 0; b < D; ++b) G[a][b] = 0;
+      for_stencil<D>([&](int k0, int k1, int k2) {
+        int kk[3] = {k0, k1, k2};
+        R g[D];
+        weight_from_cell<D, R>(kk, f, d.fn, g);
+        int rr[3] = {lc[0] + k0, lc[1] + k1, D == 3 ? lc[2] + k2 : 0};
+        int rn = region_index<D>(rr);
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          R ua = sm.u[rn * D + a];
+#pragma unroll
+          for (int b = 0; b < D; ++b) G[a][b] += ua * g[b];
+        }
+      });
+      R Sq[D][D];
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = 0; b < D; ++b) Sq[a][b] = 0;
+      if (interior) {
+        R tr = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) tr += G[a][a];
+        const R Jn = d.pJ[k], V0 = d.pV0[k];
+        if (d.term_mask & 1) {
+          R s;
+          if (MODE == TM_HESS) {
+            s = dt * dt * d.lam * V0 * Jn * Jn * tr;
+          } else {
+            R Jm1 = (R(1) + dt * tr) * Jn - R(1);
+            if (MODE == TM_ENERGY) e += (double)(R(0.5) * d.lam * Jm1 * Jm1 * V0);
+            s = dt * d.lam * V0 * Jn * Jm1;
+          }
+#pragma unroll
+          for (int a = 0; a < D; ++a) Sq[a][a] += s;
+        }
+        if (d.term_mask & 4) {
+          R cV = dt * d.pmu[k] * d.pVn[k];
+          R ee = 0;
+#pragma unroll
+          for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int b = 0; b < D; ++b) {
+              R eps = R(0.5) * (G[a][b] + G[b][a]);
+              Sq[a][b] += cV * eps;
+              ee += eps * eps;
+            }
+          if (MODE == TM_ENERGY) e += (double)(R(0.5) * cV * ee);
+        }
+      } else {
+        R Nv[D], F[D][D];
+        const R kr = d.sk[k];
+#pragma unroll
+        for (int a = 0; a < D; ++a) Nv[a] = d.sdA[a * S + k];
+        if (MODE == TM_HESS) {
+#pragma unroll
+          for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int b = 0; b < D; ++b) F[a][b] = d.sF[(a * D + b) * S + k];
+        } else {
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+#pragma unroll
+            for (int b = 0; b < D; ++b) F[a][b] = dt * G[a][b];
+            F[a][a] += R(1);
+          }
+        }
+        R Q[D][D];
+        R an = surface_q<D, R>(F, Nv, MODE == TM_HESS, G, dt, d.exact, Q);
+        if (MODE == TM_ENERGY) e += (double)(kr * an);
+        const R sc = dt * kr;
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+          for (int b = 0; b < D; ++b) Sq[a][b] = sc * Q[a][b];
+      }
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        sm.pf[t * D + a] = f[a];
+#pragma unroll
+        for (int b = 0; b < D; ++b) sm.pS[(t * D + a) * D + b] = Sq[a][b];
+      }
+    }
+    __syncthreads();
+    // ---- scatter phase: the lane's cell points inside this chunk ----
+    if (lane_on) {
+      int lo = q0, hi = min(q0 + NT, ntot);
+      for (int pass = 0; pass < 2; ++pass) {
+        int b0 = pass == 0 ? cpb : csb, b1 = pass == 0 ? cpe : cse;
+        b0 = max(b0, lo);
+        b1 = min(b1, hi);
+        for (int qq = b0; qq < b1; ++qq) {
+          int sl = qq - q0;
+          R f[D];
+#pragma unroll
+          for (int a = 0; a < D; ++a) f[a] = sm.pf[sl * D + a];
+          R Sq[D][D];
+#pragma unroll
+          for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int b = 0; b < D; ++b) Sq[a][b] = sm.pS[(sl * D + a) * D + b];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            R g[D];
+            lane_weight<D, R>(f, lk0, lk1, k, d.fn, g);
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+              R s = 0;
+#pragma unroll
+              for (int b = 0; b < D; ++b) s += Sq[a][b] * g[b];
+              acc.v[k][a] += s;
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // ---- reduce onto the region and write the tile partial ----
+  R* reg = reinterpret_cast<R*>(sm.pS);        // reuse (RN * D <= NT * D * D)
+  reduce_cells_to_region<D, R, D, D>(acc, 0, sm.cellpart, reg, lcell, lk0, lk1, lane_on);
+  R* dst = tpart + (size_t)blockIdx.x * RN * D;
+  for (int i = t; i < RN * D; i += NT) dst[i] = reg[i];
+  if (MODE == TM_ENERGY && energy_slot >= 0) {
+    double bs = block_sum(e, sm.red);
+    if (t == 0) d.part[energy_slot * kPartSlot + blockIdx.x] = bs;
+  }
+}
+
+// Linearization point of the surface term: F_r = I + dt grad v_lin(s_r), cached per sample.
+template <int D, typename R>
+__global__ void k_surface_F(Dev<R> d, const R* vlin) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int S = d.ns;
+  if (r >= S) return;
+  R x[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) x[a] = d.ss[a * S + r];
+  Stencil<D, R> st; bool bad = false;
+  make_stencil<D, R>(x, d.n, d.fn, st, &bad);
+  R G[D][D];
+  gather_grad<D, R>(d, st, vlin, false, G);
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) d.sF[(a * D + b) * S + r] = (a == b ? R(1) : R(0)) + d.dt * G[a][b];
+}
+
+// ======================================================================================
+// Heat operator scatter: interior points carry q_p = K V^n grad T_p (vector), surface
+// samples c_r = h |dA_r| T(s_r) (scalar); contribution c N_i + q . grad N_i.
+// ======================================================================================
+template <int D, typename R>
+struct HeatLds {
+  static constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
+  R u[RN];
+  R pf[NT * D];
+  R pq[NT * (D + 1)];
+  R cellpart[64 * 27];
+};
+
+template <int D, typename R>
+__global__ void __launch_bounds__(TileGeo<D>::NT) k_tile_heat(Dev<R> d, TileLists tl, const R* T, R* tpart,
+                                                              const int* done) {
+  constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
+  __shared__ HeatLds<D, R> sm;
+  if (done && *done) return;
+  const int ct = tl.ctile_list[blockIdx.x];
+  const int N = d.np, S = d.ns;
+  const int t = threadIdx.x;
+  int org[3] = {0, 0, 0};
+  tiled_coords<D>(ct, 0, d.nt, org);
+#pragma unroll
+  for (int a = 0; a < D; ++a) org[a] -= 1;
+  for (int rn = t; rn < RN; rn += NT) {
+    int r[3];
+    region_coords<D>(rn, r);
+    int gnode = region_node_global<D>(ct, r, d.n, d.nt);
+    sm.u[rn] = gnode >= 0 ? T[gnode] : R(0);
+  }
+  const int cb = ct * 64;
+  const int pb = d.p_start[cb], pe = d.p_start[cb + 64];
+  const int sb = S ? d.s_start[cb] : 0, se = S ? d.s_start[cb + 64] : 0;
+  const int npi = pe - pb, ntot = npi + (se - sb);
+  int lcell, lk0, lk1;
+  lane_map<D>(t, lcell, lk0, lk1);
+  const bool lane_on = t < 64 * TileGeo<D>::LPC;
+  int cpb = 0, cpe = 0, csb = 0, cse = 0;
+  if (lane_on) {
+    cpb = d.p_start[cb + lcell] - pb; cpe = d.p_start[cb + lcell + 1] - pb;
+    if (S) { csb = d.s_start[cb + lcell] - sb + npi; cse = d.s_start[cb + lcell + 1] - sb + npi; }
+  }
+  LaneAcc<D, R, 1> acc;
+  acc.zero();
+  __syncthreads();
+  for (int q0 = 0; q0 < ntot; q0 += NT) {
+    int q = q0 + t;
+    if (q < ntot) {
+      bool interior = q < npi;
+      int k = interior ? pb + q : sb + (q - npi);
+      R x[D], f[D];
+      int lc[3] = {0, 0, 0};
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        x[a] = interior ? d.px[a * N + k] : d.ss[a * S + k];
+        R xs = x[a] * d.fn;
+        R cf = floor(xs);
+        f[a] = xs - cf;
+        lc[a] = (int)cf - (org[a] + 1);
+        lc[a] = lc[a] < 0 ? 0 : (lc[a] > TileGeo<D>::E - 1 ? TileGeo<D>::E - 1 : lc[a]);
+      }
+      R gT[D], Tq = 0;
+#pragma unroll
+      for (int a = 0; a < D; ++a) gT[a] = 0;
+      for_stencil<D>([&](int k0, int k1, int k2) {
+        int kk[3] = {k0, k1, k2};
+        R g[D];
+        R w = weight_from_cell<D, R>(kk, f, d.fn, g);
+        int rr[3] = {lc[0] + k0, lc[1] + k1, D == 3 ? lc[2] + k2 : 0};
+        R Tj = sm.u[region_index<D>(rr)];
+        Tq += w * Tj;
+#pragma unroll
+        for (int a = 0; a < D; ++a) gT[a] += Tj * g[a];
+      });
+#pragma unroll
+      for (int a = 0; a < D; ++a) sm.pf[t * D + a] = f[a];
+      if (interior) {
+        R c = d.K * d.pVn[k];
+        sm.pq[t * (D + 1)] = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) sm.pq[t * (D + 1) + 1 + a] = c * gT[a];
+      } else {
+        R area = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) area += d.sdA[a * S + k] * d.sdA[a * S + k];
+        sm.pq[t * (D + 1)] = d.h * sqrt(area) * Tq;
+#pragma unroll
+        for (int a = 0; a < D; ++a) sm.pq[t * (D + 1) + 1 + a] = 0;
+      }
+    }
+    __syncthreads();
+    if (lane_on) {
+      int lo = q0, hi = min(q0 + NT, ntot);
+      for (int pass = 0; pass < 2; ++pass) {
+        int b0 = max(pass == 0 ? cpb : csb, lo), b1 = min(pass == 0 ? cpe : cse, hi);
+        for (int qq = b0; qq < b1; ++qq) {
+          int sl = qq - q0;
+          R f[D];
+#pragma unroll
+          for (int a = 0; a < D; ++a) f[a] = sm.pf[sl * D + a];
+          R c = sm.pq[sl * (D + 1)];
+          R qv[D];
+#pragma unroll
+          for (int a = 0; a < D; ++a) qv[a] = sm.pq[sl * (D + 1) + 1 + a];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            R g[D];
+            R w = lane_weight<D, R>(f, lk0, lk1, k, d.fn, g);
+            R s = c * w;
+#pragma unroll
+            for (int a = 0; a < D; ++a) s += qv[a] * g[a];
+            acc.v[k][0] += s;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  R* reg = sm.pf;   // RN <= NT * D
+  reduce_cells_to_region<D, R, 1, 1>(acc, 0, sm.cellpart, reg, lcell, lk0, lk1, lane_on);
+  R* dst = tpart + (size_t)blockIdx.x * RN;
+  for (int i = t; i < RN; i += NT) dst[i] = reg[i];
+}
+
+// ======================================================================================
+// P2G scatter (Section 4.2) with the set-up sums.  Fields per node:
+//   0 m, 1..D mv, D+1 W, D+2 WT, D+3 E, D+4 ET, D+5..2D+4 Newton diagonal terms,
+//   2D+5 heat diagonal terms, 2D+6 heat right-side terms.   NF = 2D + 7.
+// Per point: m~ and the APIC momentum, or unsplit m with T, grad T (interior), or the
+// parent's temperature (split members); contributions N (c + B rel) with rel = x_i - x_q,
+// plus quadratic terms of grad N for the diagonals.
+// ======================================================================================
+template <int D> struct P2GF {
+  static constexpr int NF = 2 * D + 7;
+  static constexpr int M = 0, MV = 1, W = D + 1, WT = D + 2, E = D + 3, ET = D + 4, DG = D + 5, HD = 2 * D + 5,
+                       HR = 2 * D + 6;
+  static constexpr int PL = 1 + D + D * D + 4 + D + 5;   // payload per point (see k_tile_p2g)
+};
+
+template <int D, typename R>
+struct P2GLds {
+  static constexpr int NT = TileGeo<D>::NT;
+  static constexpr int CH = sizeof(R) == 8 ? NT / 2 : NT;   // points per chunk (LDS budget)
+  static constexpr int PW = D + P2GF<D>::PL;    // f + payload
+  R pay[CH * PW];
+  R cellpart[64 * 27 * 3];                      // field chunks of 3
+};
+
+template <int D, typename R>
+__global__ void __launch_bounds__(TileGeo<D>::NT) k_tile_p2g(Dev<R> d, TileLists tl, R* tpart) {
+  constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
+  using FI = P2GF<D>;
+  constexpr int NF = FI::NF, PW = P2GLds<D, R>::PW, CH = P2GLds<D, R>::CH;
+  __shared__ P2GLds<D, R> sm;
+  const int ct = tl.ctile_list[blockIdx.x];
+  const int N = d.np, S = d.ns;
+  const int t = threadIdx.x;
+  const R dt = d.dt;
+  int org[3] = {0, 0, 0};
+  tiled_coords<D>(ct, 0, d.nt, org);
+#pragma unroll
+  for (int a = 0; a < D; ++a) org[a] -= 1;
+  const int cb = ct * 64;
+  const int pb = d.p_start[cb], pe = d.p_start[cb + 64];
+  const int sb = S ? d.s_start[cb] : 0, se = S ? d.s_start[cb + 64] : 0;
+  const int bb = S ? d.b_start[cb] : 0, be = S ? d.b_start[cb + 64] : 0;
+  const int n1 = pe - pb, n2 = n1 + (se - sb), ntot = n2 + (be - bb);
+  int lcell, lk0, lk1;
+  lane_map<D>(t, lcell, lk0, lk1);
+  const bool lane_on = t < 64 * TileGeo<D>::LPC;
+  int rb[3] = {0, 0, 0}, re[3] = {0, 0, 0};
+  if (lane_on) {
+    rb[0] = d.p_start[cb + lcell] - pb; re[0] = d.p_start[cb + lcell + 1] - pb;
+    if (S) {
+      rb[1] = d.s_start[cb + lcell] - sb + n1; re[1] = d.s_start[cb + lcell + 1] - sb + n1;
+      rb[2] = d.b_start[cb + lcell] - bb + n2; re[2] = d.b_start[cb + lcell + 1] - bb + n2;
+    }
+  }
+  const bool useJ = d.term_mask & 1, useV = d.term_mask & 4;
+  LaneAcc<D, R, NF> acc;
+  acc.zero();
+  for (int q0 = 0; q0 < ntot; q0 += CH) {
+    int q = q0 + t;
+    if (t < CH && q < ntot) {
+      // payload: f[D] | m~ | m~ v[D] | m~ A[D*D] | c_W | c_WT | c_E | c_ET | m grad T[D] |
+      //          cJ | cV | cK (|grad N|^2 heat term) | cR (N^2 Robin term) | cS (N heat right side)
+      R* P = &sm.pay[t * PW];
+      int type = q < n1 ? 0 : (q < n2 ? 1 : 2);
+      int k, p;
+      R x[D];
+      if (type == 0) { k = pb + q; p = k; for (int a = 0; a < D; ++a) x[a] = d.px[a * N + k]; }
+      else if (type == 1) { k = sb + (q - n1); p = d.spar[k]; for (int a = 0; a < D; ++a) x[a] = d.ss[a * S + k]; }
+      else { k = bb + (q - n2); p = d.spar[d.b_src[k]]; for (int a = 0; a < D; ++a) x[a] = d.bx[a * S + k]; }
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        R xs = x[a] * d.fn;
+        P[a] = xs - floor(xs);
+      }
+      R* Q = P + D;
+      R mt = d.pmt[p];
+      Q[0] = mt;
+#pragma unroll
+      for (int a = 0; a < D; ++a) Q[1 + a] = mt * d.pv[a * N + p];
+#pragma unroll
+      for (int a = 0; a < D * D; ++a) Q[1 + D + a] = mt * d.pA[a * N + p];
+      R* Z = Q + 1 + D + D * D;          // c_W, c_WT, c_E, c_ET
+      R* bW = Z + 4;                      // bWT[D]
+      R* H = bW + D;                      // cJ, cV, cK, cR, cS
+      if (type == 0) {
+        R mp = d.pm[k];
+        Z[0] = mp; Z[1] = mp * d.pT[k]; Z[2] = 0; Z[3] = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) bW[a] = mp * d.pgT[a * N + k];
+        R Jn = d.pJ[k], Vn = d.pVn[k];
+        H[0] = useJ ? dt * dt * d.lam * d.pV0[k] * Jn * Jn : R(0);
+        H[1] = useV ? dt * d.pmu[k] * Vn : R(0);
+        H[2] = d.K * Vn;
+        H[3] = 0;
+        H[4] = d.H * Vn;
+      } else {
+        Z[0] = 0; Z[1] = 0; Z[2] = mt; Z[3] = mt * d.pT[p];
+#pragma unroll
+        for (int a = 0; a < D; ++a) bW[a] = 0;
+        H[0] = 0; H[1] = 0; H[2] = 0; H[3] = 0; H[4] = 0;
+        if (type == 1) {
+          R area = 0;
+#pragma unroll
+          for (int a = 0; a < D; ++a) area += d.sdA[a * S + k] * d.sdA[a * S + k];
+          area = sqrt(area);
+          H[3] = d.h * area;
+          H[4] = (d.h * d.T_amb + d.b) * area;
+        }
+      }
+    }
+    __syncthreads();
+    if (lane_on) {
+      int lo = q0, hi = min(q0 + CH, ntot);
+      for (int pass = 0; pass < 3; ++pass) {
+        int b0 = max(rb[pass], lo), b1 = min(re[pass], hi);
+        for (int qq = b0; qq < b1; ++qq) {
+          const R* P = &sm.pay[(qq - q0) * PW];
+          R f[D];
+#pragma unroll
+          for (int a = 0; a < D; ++a) f[a] = P[a];
+          const R* Q = P + D;
+          const R* Z = Q + 1 + D + D * D;
+          const R* bW = Z + 4;
+          const R* H = bW + D;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            R g[D];
+            R w = lane_weight<D, R>(f, lk0, lk1, k, d.fn, g);
+            int kk[3] = {lk0, D == 3 ? lk1 : k, D == 3 ? k : 0};
+            R rel[D];
+#pragma unroll
+            for (int a = 0; a < D; ++a) rel[a] = (R(kk[a]) - R(0.5) - f[a]) * d.dx;
+            acc.v[k][FI::M] += w * Q[0];
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+              R s = Q[1 + a];
+#pragma unroll
+              for (int b = 0; b < D; ++b) s += Q[1 + D + a * D + b] * rel[b];
+              acc.v[k][FI::MV + a] += w * s;
+            }
+            R sw = Z[1];
+#pragma unroll
+            for (int a = 0; a < D; ++a) sw += bW[a] * rel[a];
+            acc.v[k][FI::W] += w * Z[0];
+            acc.v[k][FI::WT] += w * sw;
+            acc.v[k][FI::E] += w * Z[2];
+            acc.v[k][FI::ET] += w * Z[3];
+            R g2 = 0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) g2 += g[a] * g[a];
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+              acc.v[k][FI::DG + a] += H[0] * g[a] * g[a] + H[1] * (R(0.5) * g2 + R(0.5) * g[a] * g[a]);
+            acc.v[k][FI::HD] += H[2] * g2 + H[3] * w * w;
+            acc.v[k][FI::HR] += H[4] * w;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // field chunks of 3 onto the region
+  R* reg = sm.pay;   // RN * 3 <= NT * PW
+  for (int f0 = 0; f0 < NF; f0 += 3) {
+    reduce_cells_to_region<D, R, NF, 3>(acc, f0, sm.cellpart, reg, lcell, lk0, lk1, lane_on);
+    for (int i = t; i < RN * 3; i += NT) {
+      int rn = i / 3, f = f0 + i % 3;
+      if (f < NF) tpart[((size_t)blockIdx.x * NF + f) * RN + rn] = reg[i];
+    }
+    __syncthreads();
+  }
+}
+
+// ======================================================================================
+// Merge: for every node of the active node tiles, sum the region partials of the <= 2^d
+// cell tiles that cover it (fixed order: cell tiles in lexicographic order).
+// ======================================================================================
+template <int D>
+struct MergeSrc {
+  int slot[8];
+  int rn[8];
+  int cnt;
+};
+
+template <int D>
+MPM_DEV void merge_sources(int node_tile, int local, int nt, const int* ctile_slot, MergeSrc<D>& ms) {
+  constexpr int E = TileGeo<D>::E, RE = TileGeo<D>::RE;
+  int i[3] = {0, 0, 0};
+  tiled_coords<D>(node_tile, local, nt, i);
+  int T[3] = {0, 0, 0}, l[3] = {0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < D; ++a) { T[a] = i[a] / E; l[a] = i[a] % E; }
+  int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    lo[a] = l[a] == 0 ? T[a] - 1 : T[a];
+    hi[a] = l[a] == E - 1 ? T[a] + 1 : T[a];
+    lo[a] = lo[a] < 0 ? 0 : lo[a];
+    hi[a] = hi[a] > nt - 1 ? nt - 1 : hi[a];
+  }
+  ms.cnt = 0;
+  for (int c2 = (D == 3 ? lo[2] : 0); c2 <= (D == 3 ? hi[2] : 0); ++c2)
+    for (int c1 = lo[1]; c1 <= hi[1]; ++c1)
+      for (int c0 = lo[0]; c0 <= hi[0]; ++c0) {
+        int ct = c0 + nt * (c1 + (D == 3 ? nt * c2 : 0));
+        int s = ctile_slot[ct];
+        if (s < 0) continue;
+        int C[3] = {c0, c1, c2};
+        int r[3] = {0, 0, 0};
+#pragma unroll
+        for (int a = 0; a < D; ++a) r[a] = i[a] - (E * C[a] - 1);
+        ms.slot[ms.cnt] = s;
+        ms.rn[ms.cnt] = r[0] + RE * (r[1] + (D == 3 ? RE * r[2] : 0));
+        ms.cnt++;
+      }
+}
+
+// Stress merge: NM_GRAD / NM_HESS node-level terms as in the node phase.
+template <int D, typename R>
+__global__ void __launch_bounds__(64) k_merge_stress(Dev<R> d, TileLists tl, const R* tpart, const R* u, R* out,
+                                                     int mode, double alpha, int mask_in, const int* done,
+                                                     int part_slot, int dot_slot) {
+  constexpr int RN = TileGeo<D>::RN;
+  __shared__ double sh[16];
+  if (done && *done) return;
+  const int tile = d.tile_list[blockIdx.x];
+  const int lane = threadIdx.x;
+  const int node = tile * kTileNodes + lane;
+  const int nn = d.nn;
+  MergeSrc<D> ms;
+  merge_sources<D>(tile, lane, d.nt, tl.ctile_slot, ms);
+  R acc[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) acc[a] = 0;
+  for (int j = 0; j < ms.cnt; ++j) {
+    const R* src = tpart + (size_t)ms.slot[j] * RN * D + ms.rn[j] * D;
+#pragma unroll
+    for (int a = 0; a < D; ++a) acc[a] += src[a];
+  }
+  uint8_t fr = d.gfree[node];
+  R m = d.gm[node];
+  double e = 0, dotv = 0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    bool fa = (fr >> a) & 1;
+    R ua = u ? u[a * nn + node] : R(0);
+    R o;
+    if (mode == NM_GRAD) {
+      R vn = d.gvn[a * nn + node];
+      o = acc[a] + m * (ua - vn) - d.dt * m * d.grav[a];
+      if (fr & 0x80) {
+        double dv = (double)ua - (double)vn;
+        e += 0.5 * (double)m * dv * dv - (double)d.dt * (double)m * (double)d.grav[a] * (double)ua;
+      }
+    } else {
+      R wa = (!mask_in || fa) ? ua : R(0);
+      o = acc[a] + R(alpha) * m * wa;
+      if (fa) dotv += (double)wa * (double)o;
+    }
+    o = fa ? o : R(0);
+    out[a * nn + node] = o;
+  }
+  if (mode == NM_GRAD && part_slot >= 0) {
+    double bs = block_sum(e, sh);
+    if (threadIdx.x == 0) d.part[part_slot * kPartSlot + blockIdx.x] = bs;
+  }
+  if (mode == NM_HESS && dot_slot >= 0) {
+    double bs = block_sum(dotv, sh);
+    if (threadIdx.x == 0) d.part[dot_slot * kPartSlot + blockIdx.x] = bs;
+  }
+}
+
+template <int D, typename R>
+__global__ void __launch_bounds__(64) k_merge_heat(Dev<R> d, TileLists tl, const R* tpart, const R* T, R* out,
+                                                   const int* done, int dot_slot) {
+  constexpr int RN = TileGeo<D>::RN;
+  __shared__ double sh[16];
+  if (done && *done) return;
+  const int tile = d.tile_list[blockIdx.x];
+  const int lane = threadIdx.x;
+  const int node = tile * kTileNodes + lane;
+  MergeSrc<D> ms;
+  merge_sources<D>(tile, lane, d.nt, tl.ctile_slot, ms);
+  R acc = 0;
+  for (int j = 0; j < ms.cnt; ++j) acc += tpart[(size_t)ms.slot[j] * RN + ms.rn[j]];
+  bool dof = d.gfree[node] & 0x80;
+  R Ti = T[node];
+  R o = dof ? d.cp / d.dt * d.gm[node] * Ti + acc : R(0);
+  out[node] = o;
+  if (dot_slot >= 0) {
+    double bs = block_sum(dof ? (double)Ti * (double)o : 0.0, sh);
+    if (threadIdx.x == 0) d.part[dot_slot * kPartSlot + blockIdx.x] = bs;
+  }
+}
+
+// P2G merge and grid set-up (degrees of freedom, v^n, T^n, constraints, diagonals, heat
+// right side).
+template <int D, typename R>
+__global__ void __launch_bounds__(64) k_merge_p2g(Dev<R> d, TileLists tl, const R* tpart) {
+  constexpr int RN = TileGeo<D>::RN;
+  using FI = P2GF<D>;
+  constexpr int NF = FI::NF;
+  const int tile = d.tile_list[blockIdx.x];
+  const int lane = threadIdx.x;
+  const int node = tile * kTileNodes + lane;
+  const int nn = d.nn;
+  int i[3] = {0, 0, 0};
+  tiled_coords<D>(tile, lane, d.nt, i);
+  MergeSrc<D> ms;
+  merge_sources<D>(tile, lane, d.nt, tl.ctile_slot, ms);
+  R v[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) v[f] = 0;
+  for (int j = 0; j < ms.cnt; ++j) {
+#pragma unroll
+    for (int f = 0; f < NF; ++f) v[f] += tpart[((size_t)ms.slot[j] * NF + f) * RN + ms.rn[j]];
+  }
+  const R m = v[FI::M], W = v[FI::W], WT = v[FI::WT], E = v[FI::E], ET = v[FI::ET];
+  const bool dof = m > R(0);
+  d.gm[node] = m; d.gW[node] = W; d.gWT[node] = WT; d.gE[node] = E; d.gET[node] = ET;
+  R Tn = W > R(0) ? WT / W : (E > R(0) ? ET / E : R(0));
+  d.gTn[node] = dof ? Tn : R(0);
+  uint8_t fr = dof ? 0x80 : 0;
+  R xi[3];
+#pragma unroll
+  for (int a = 0; a < D; ++a) xi[a] = (R(i[a]) + R(0.5)) * d.dx;
+  bool in_slab = d.slab != 0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) in_slab = in_slab && xi[a] >= d.slab_lo[a] && xi[a] < d.slab_hi[a];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    bool wall = d.wall > 0 && (i[a] < d.wall || i[a] >= d.n - d.wall);
+    bool fixed = wall || (in_slab && a == d.slab_axis);
+    bool fa = dof && !fixed;
+    if (fa) fr |= (uint8_t)(1u << a);
+    R mv = v[FI::MV + a];
+    d.gmv[a * nn + node] = mv;
+    d.gvn[a * nn + node] = dof ? mv / m : R(0);
+    d.gdiag[a * nn + node] = fa ? m + v[FI::DG + a] : R(1);
+  }
+  d.gfree[node] = fr;
+  R cm = d.cp / d.dt * m;
+  d.hdiag[node] = dof ? cm + v[FI::HD] : R(1);
+  d.hrhs[node] = dof ? cm * Tn + v[FI::HR] : R(0);
+}
+
+// Active cell tiles: tiles holding any point.
+template <int D, typename R>
+__global__ void k_flag_ctiles(Dev<R> d, int* flag, int ntile) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntile) return;
+  int cb = t * 64;
+  int cnt = d.p_start[cb + 64] - d.p_start[cb];
+  if (d.ns) cnt += (d.s_start[cb + 64] - d.s_start[cb]) + (d.b_start[cb + 64] - d.b_start[cb]);
+  flag[t] = cnt > 0;
+}
+
+__global__ void k_ctile_slots(const int* flag, const int* pos, int ntile, int* list, int* slot) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntile) return;
+  if (flag[t]) { list[pos[t]] = t; slot[t] = pos[t]; }
+  else slot[t] = -1;
+}
+
+}  // namespace mpm
