@@ -142,7 +142,8 @@ enum mpm_field {
   MPM_F_PARENT = 13,/* int32 [n_surf]: parent p(r) of each surface sample (input order) */
   MPM_F_COUNT = 14, /* int32 [n_part]: |Pi_p| (input order)                             */
   MPM_F_KSURF = 15, /* real [n_surf]: k_r (input order)                                 */
-  MPM_F_MOM_DIAG = 16 /* Jacobi diagonal of the Newton matrix  real [dim][n^dim]        */
+  MPM_F_MOM_DIAG = 16, /* Jacobi diagonal of the Newton matrix  real [dim][n^dim]       */
+  MPM_F_PERM = 17   /* int32 [n_part]: input index of the particle in each cell-order slot */
 };
 
 /* Kernel classes timed by mpm_timing (HIP events on the launch stream). */
@@ -217,9 +218,12 @@ int mpm_hessvec(mpm_ctx* ctx, const void* v_lin, const void* w, double alpha_mas
  * (L the particle conduction matrix, R the particle Robin matrix).  Requires mpm_p2g. */
 int mpm_heat_apply(mpm_ctx* ctx, const void* T_in, void* T_out, void* stream);
 
-/* Section 5: G2P with merge of split groups, then J_p and x_p advanced; writes v, A, T,
- * gradT, J, x of P in place (input order).  T_hat may be NULL: T and gradT are then left
- * unchanged.  Requires mpm_p2g on the same P and S. */
+/* Section 5: G2P with merge of split groups, then J_p and x_p advanced.  Writes the
+ * whole particle state (x, v, A, J, V0, m, T, gradT) of P back IN CELL ORDER: slot j then
+ * holds the particle whose index in the mpm_p2g input was perm[j] (MPM_F_PERM), so that
+ * the next step's binning finds the particles almost sorted and every access coalesces.
+ * T_hat may be NULL: T and gradT are then carried over unchanged.  Requires mpm_p2g on
+ * the same P and S. */
 int mpm_g2p(mpm_ctx* ctx, const void* v_hat, const void* T_hat, mpm_particles* P, void* stream);
 
 /* Momentum solve only (after mpm_p2g): Newton-CG on Phi; v^ lands in MPM_F_VHAT.

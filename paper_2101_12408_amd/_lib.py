@@ -12,7 +12,7 @@ STATUS_NAMES = {0: "MPM_OK", 1: "MPM_EINVAL", 2: "MPM_ENOMEM", 3: "MPM_EBUDGET",
                 5: "MPM_ENOCONV", 6: "MPM_ENONFINITE", 7: "MPM_EHIP"}
 MPM_FP64, MPM_MIXED = 0, 1
 (F_MASS, F_MOM, F_W, F_WT, F_E, F_ET, F_VN, F_TN, F_FREE, F_HEAT_RHS, F_HEAT_DIAG, F_VHAT, F_THAT,
- F_PARENT, F_COUNT, F_KSURF, F_MOM_DIAG) = range(17)
+ F_PARENT, F_COUNT, F_KSURF, F_MOM_DIAG, F_PERM) = range(18)
 
 
 class MpmParams(C.Structure):
@@ -85,6 +85,9 @@ def load(path=LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_2101_12408_amd.build`")
+    # torch ships its own HIP runtime; loading it first makes libmpm.so bind to that same
+    # runtime instead of pulling a second copy into the process.
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     for name, (res, args) in EXPORTS.items():
         f = getattr(lib, name)

@@ -258,7 +258,7 @@ class Scene:
             dt, shape = torch.uint8, (nn,)
         elif field == L.F_PARENT:
             dt, shape = torch.int32, (st["n_surf"],)
-        elif field == L.F_COUNT:
+        elif field in (L.F_COUNT, L.F_PERM):
             dt, shape = torch.int32, (st["n_part"],)
         elif field == L.F_KSURF:
             dt, shape = self.dtype, (st["n_surf"],)

@@ -172,6 +172,36 @@ MPM_DEV double block_sum(double v, double* sh) {
   return r;
 }
 
+// Deterministic grid reduction without a second launch.  Thread 0 of every block
+// publishes its partials with publish() (device-scope stores, written through to the
+// level shared by all XCDs), waits until its own stores are acknowledged and takes a
+// ticket; the block holding the last ticket reads all partials with device-scope loads
+// and sums them in index order, so the result does not depend on which block finishes
+// last.  No cache writeback or invalidate is issued: other blocks keep their L2 contents.
+// The counter returns to zero for the next use (kernel boundaries order the reuse).
+MPM_DEV void publish(double* p, double v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+
+MPM_DEV bool grid_last_block(unsigned* counter) {
+  __shared__ int last;
+  if (threadIdx.x == 0) {
+    __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    last = prev == gridDim.x - 1;
+    if (last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  return last != 0;
+}
+
+// Sum of part[0..nb) in fixed order by one block (result in thread 0); device-scope loads
+// see every block's published partial.
+MPM_DEV double block_sum_array(const double* part, int nb, double* sh) {
+  double v = 0;
+  for (int k = threadIdx.x; k < nb; k += blockDim.x)
+    v += __hip_atomic_load(part + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return block_sum(v, sh);
+}
+
 // Latched device status word bits.
 enum : int { ST_DOMAIN = 1, ST_NONFINITE = 2, ST_NOCONV = 4 };
 

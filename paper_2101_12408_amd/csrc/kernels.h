@@ -142,12 +142,29 @@ __global__ void k_cell_scatter(const int* key, int cnt, const int* start, int* c
   perm[slot] = i;
 }
 
-// Sort each segment [start[c], start[c+1]) of vals ascending (insertion sort; segments
-// hold a handful of items).  Makes the slot order independent of atomic arrival order.
+// Sort each segment [start[c], start[c+1]) of distinct values ascending.  Makes the slot
+// order independent of atomic arrival order.  Segments of up to 16 values are ranked in
+// registers (independent loads); longer ones use an insertion sort in memory.
+constexpr int kSegReg = 16;
 __global__ void k_segment_order(const int* start, int nseg, int* vals) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nseg) return;
   int b = start[c], e = start[c + 1];
+  int n = e - b;
+  if (n < 2) return;
+  if (n <= kSegReg) {
+    int v[kSegReg];
+#pragma unroll
+    for (int i = 0; i < kSegReg; ++i) v[i] = i < n ? vals[b + i] : 0x7fffffff;
+#pragma unroll
+    for (int i = 0; i < kSegReg; ++i) {
+      int r = 0;
+#pragma unroll
+      for (int j = 0; j < kSegReg; ++j) r += v[j] < v[i] ? 1 : 0;
+      if (i < n) vals[b + r] = v[i];
+    }
+    return;
+  }
   for (int i = b + 1; i < e; ++i) {
     int v = vals[i];
     int j = i - 1;
@@ -220,8 +237,9 @@ MPM_DEV double dist2_exact(const double* a, const double* b) {
 }
 
 // Nearest interior particle of each sample (Section 4.1.2); ties to the lower input
-// index.  Searches the cells within 2, then 3 cells of the sample; a winner closer than
-// the searched radius is exact.  Otherwise falls back to a scan of all particles.
+// index.  Searches the cells within 1, 2, then 3 cells of the sample; a winner closer
+// than the searched radius (rad * dx) is exact, since every particle outside the searched
+// block is at least that far.  Otherwise falls back to a scan of all particles.
 template <int D, typename R>
 __global__ void k_parents(Dev<R> d) {
   int r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -244,7 +262,7 @@ __global__ void k_parents(Dev<R> d) {
     if (d2 < best || (d2 == best && o < borig)) { best = d2; bk = k; borig = o; }
   };
   double dxd = (double)d.dx;
-  for (int rad = 2; rad <= 3; ++rad) {
+  for (int rad = 1; rad <= 3; ++rad) {
     int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
 #pragma unroll
     for (int a = 0; a < D; ++a) { lo[a] = max(c[a] - rad, 0); hi[a] = min(c[a] + rad, d.n - 1); }
@@ -476,81 +494,6 @@ __global__ void k_g2p_split(Dev<R> d, const R* vh) {
   }
 }
 
-template <int D, typename R>
-__global__ void k_g2p_particles(Dev<R> d, const R* vh, const R* Th, R* x, R* v, R* A, R* J, R* T, R* gT) {
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
-  const int N = d.np, S = d.ns;
-  if (k >= N) return;
-  R xp[D];
-#pragma unroll
-  for (int a = 0; a < D; ++a) xp[a] = d.px[a * N + k];
-  Stencil<D, R> st; bool bad = false;
-  make_stencil<D, R>(xp, d.n, d.fn, st, &bad);
-  R vq[D], tq[D][D], gTq[D];
-  R Tq = 0, div = 0;
-#pragma unroll
-  for (int a = 0; a < D; ++a) { vq[a] = 0; gTq[a] = 0; for (int b = 0; b < D; ++b) tq[a][b] = 0; }
-  for_stencil<D>([&](int k0, int k1, int k2) {
-    int kk[3] = {k0, k1, k2};
-    int nd[3] = {st.c[0] - 1 + k0, st.c[1] - 1 + k1, D == 3 ? st.c[2] - 1 + k2 : 0};
-    int node = (int)tiled_index<D>(nd, d.nt);
-    R g[D];
-    R Nw = node_weight<D, R>(st, k0, k1, k2, g);
-    R rel[D];
-#pragma unroll
-    for (int b = 0; b < D; ++b) rel[b] = (R(kk[b]) - R(0.5) - st.f[b]) * d.dx;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      R va = vh[a * d.nn + node];
-      R nv = Nw * va;
-      vq[a] += nv;
-      div += va * g[a];
-#pragma unroll
-      for (int b = 0; b < D; ++b) tq[a][b] += nv * rel[b];
-    }
-    if (Th) {
-      R Tj = Th[node];
-      Tq += Nw * Tj;
-#pragma unroll
-      for (int a = 0; a < D; ++a) gTq[a] += Tj * g[a];
-    }
-  });
-  R mt = d.pmt[k], mp = d.pm[k];
-  R mom[D], tt[D][D];
-#pragma unroll
-  for (int a = 0; a < D; ++a) {
-    mom[a] = mt * vq[a];
-#pragma unroll
-    for (int b = 0; b < D; ++b) tt[a][b] = mt * tq[a][b];
-  }
-  for (int j = d.grp_start[k]; j < d.grp_start[k + 1]; ++j) {
-    int r = d.grp[j];
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      mom[a] += mt * d.sc[a * S + r];
-#pragma unroll
-      for (int b = 0; b < D; ++b) tt[a][b] += mt * d.sc[(D + a * D + b) * S + r];
-    }
-  }
-  int i = d.p_perm[k];
-  R inv_m = R(1) / mp;
-  R cA = R(4) / (mp * d.dx * d.dx);
-#pragma unroll
-  for (int a = 0; a < D; ++a) {
-    R va = mom[a] * inv_m;
-    v[a * N + i] = va;
-    x[a * N + i] = xp[a] + d.dt * va;
-#pragma unroll
-    for (int b = 0; b < D; ++b) A[(a * D + b) * N + i] = cA * tt[a][b];
-  }
-  J[i] = (R(1) + d.dt * div) * d.pJ[k];
-  if (Th) {
-    T[i] = Tq;
-#pragma unroll
-    for (int a = 0; a < D; ++a) gT[a * N + i] = gTq[a];
-  }
-}
-
 // ======================================================================================
 // Krylov BLAS-1 over the nodes of the active tiles (ncomp components, dense arrays of nn
 // per component).  Grid-stride with a fixed grid, so the partial-sum partition depends
@@ -561,42 +504,27 @@ struct CgScal {
   int done, iters, maxit, breakdown;
 };
 
+// Reduction counters (one per reduction site; each returns to zero after use).
+enum : int { CTR_DOT = 0, CTR_MOM = 1, CTR_CGSTART = 2, CTR_MERGE = 3, CTR_CGUPD = 4, CTR_COUNT = 8 };
+
 MPM_DEV int elem_node(const int* tile_list, int e) { return tile_list[e >> 6] * kTileNodes + (e & 63); }
 
+// dst = sum over the active nodes of a . b (ncomp components), reduced in fixed order.
 template <typename R>
 __global__ void k_dot(const int* tl, int nelem, int nn, int ncomp, const R* a, const R* b, double* part,
-                      const int* done) {
+                      unsigned* ctr, double* dst) {
   __shared__ double sh[16];
-  if (done && *done) return;
   double s = 0;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nelem; e += gridDim.x * blockDim.x) {
     int node = elem_node(tl, e);
     for (int c = 0; c < ncomp; ++c) s += (double)a[c * nn + node] * (double)b[c * nn + node];
   }
   double t = block_sum(s, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = t;
-}
-
-__global__ void k_sum3(const double* a, double* out, double* out2) {
-  double v = a[0] + a[1] + a[2];
-  *out = v;
-  if (out2) *out2 = v;
-}
-
-// misc[2] += number of nodes with mass; misc[1] |= 1 if one of them has a fixed component.
-template <int D>
-__global__ void k_dof_flags(const int* tl, const uint8_t* fr, int* misc) {
-  __shared__ int cnt;
-  if (threadIdx.x == 0) cnt = 0;
-  __syncthreads();
-  uint8_t f = fr[tl[blockIdx.x] * kTileNodes + threadIdx.x];
-  const uint8_t all = (uint8_t)((1u << D) - 1);
-  if (f & 0x80) {
-    atomicAdd(&cnt, 1);
-    if ((f & all) != all) atomicOr(&misc[1], 1);
+  if (threadIdx.x == 0) publish(part + blockIdx.x, t);
+  if (grid_last_block(ctr)) {
+    double r = block_sum_array(part, gridDim.x, sh);
+    if (threadIdx.x == 0) *dst = r;
   }
-  __syncthreads();
-  if (threadIdx.x == 0 && cnt) atomicAdd(&misc[2], cnt);
 }
 
 // Sums nslot partial arrays of nb entries each (fixed order) into dst[0..nslot).
@@ -611,74 +539,58 @@ __global__ void k_finalize(const double* part, int nb, int nslot, double* dst) {
   }
 }
 
-// r = b, x = 0, z = r/diag, p = z; partials r.z, r.r (slots 0, 1).
-template <typename R>
-__global__ void k_cg_start(const int* tl, int nelem, int nn, int ncomp, const R* b, const R* diag, R* x,
-                           R* r, R* z, R* p, double* part, int zero_x) {
-  __shared__ double sh[16];
-  double rz = 0, rr = 0;
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nelem; e += gridDim.x * blockDim.x) {
-    int node = elem_node(tl, e);
-    for (int c = 0; c < ncomp; ++c) {
-      int j = c * nn + node;
-      R rv = b[j];
-      R zv = rv / diag[j];
-      if (zero_x) x[j] = 0;
-      r[j] = rv; z[j] = zv; p[j] = zv;
-      rz += (double)rv * (double)zv;
-      rr += (double)rv * (double)rv;
-    }
-  }
-  double t0 = block_sum(rz, sh);
-  double t1 = block_sum(rr, sh);
-  if (threadIdx.x == 0) { part[blockIdx.x] = t0; part[kPartSlot + blockIdx.x] = t1; }
-}
-
-// r = b - Ax (for a given initial guess), then as k_cg_start.
-template <typename R>
-__global__ void k_cg_start_x0(const int* tl, int nelem, int nn, int ncomp, const R* b, const R* Ax,
-                              const R* diag, R* r, R* z, R* p, double* part) {
-  __shared__ double sh[16];
-  double rz = 0, rr = 0;
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nelem; e += gridDim.x * blockDim.x) {
-    int node = elem_node(tl, e);
-    for (int c = 0; c < ncomp; ++c) {
-      int j = c * nn + node;
-      R rv = b[j] - Ax[j];
-      R zv = rv / diag[j];
-      r[j] = rv; z[j] = zv; p[j] = zv;
-      rz += (double)rv * (double)zv;
-      rr += (double)rv * (double)rv;
-    }
-  }
-  double t0 = block_sum(rz, sh);
-  double t1 = block_sum(rr, sh);
-  if (threadIdx.x == 0) { part[blockIdx.x] = t0; part[kPartSlot + blockIdx.x] = t1; }
-}
-
-__global__ void k_cg_init_scal(CgScal* s, const double* red, double tol2, int maxit) {
-  s->rz = red[0];
-  s->rr = red[1];
+// CG scalars from the sums r.z, r.r of the starting residual.
+MPM_DEV void cg_init(CgScal* s, double rz, double rr, double tol2, int maxit) {
+  s->rz = rz;
+  s->rr = rr;
   s->tol2 = tol2;
   s->maxit = maxit;
   s->iters = 0;
   s->breakdown = 0;
-  s->done = (red[1] <= tol2) || maxit <= 0;
-  if (!(red[1] == red[1]) || red[1] > 1e300) s->done = 1;
+  s->done = (rr <= tol2) || maxit <= 0 || !(rr == rr) || rr > 1e300;
 }
 
-// pAp from the reduction; stops on breakdown (non-positive curvature).
-__global__ void k_cg_pap(CgScal* s, const double* red) {
+// Start of a CG solve: r = b - A x0 (Ax = null: x0 = 0 and x is zeroed), z = r / diag,
+// p = z; the last block sets the scalars.  tol2 = tol2_host * (*tol2_scale) if given.
+template <typename R>
+__global__ void k_cg_start(const int* tl, int nelem, int nn, int ncomp, const R* b, const R* Ax, const R* diag,
+                           R* x, R* r, R* z, R* p, double* part, unsigned* ctr, CgScal* cs, double tol2_host,
+                           const double* tol2_scale, int maxit) {
+  __shared__ double sh[16];
+  double rz = 0, rr = 0;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nelem; e += gridDim.x * blockDim.x) {
+    int node = elem_node(tl, e);
+    for (int c = 0; c < ncomp; ++c) {
+      int j = c * nn + node;
+      R rv = Ax ? b[j] - Ax[j] : b[j];
+      R zv = rv / diag[j];
+      if (!Ax) x[j] = 0;
+      r[j] = rv; z[j] = zv; p[j] = zv;
+      rz += (double)rv * (double)zv;
+      rr += (double)rv * (double)rv;
+    }
+  }
+  double t0 = block_sum(rz, sh);
+  double t1 = block_sum(rr, sh);
+  if (threadIdx.x == 0) { publish(part + blockIdx.x, t0); publish(part + kPartSlot + blockIdx.x, t1); }
+  if (grid_last_block(ctr)) {
+    double srz = block_sum_array(part, gridDim.x, sh);
+    double srr = block_sum_array(part + kPartSlot, gridDim.x, sh);
+    if (threadIdx.x == 0) cg_init(cs, srz, srr, tol2_host * (tol2_scale ? *tol2_scale : 1.0), maxit);
+  }
+}
+
+// Called by the last block of the operator's merge with the sum p . A p.
+MPM_DEV void cg_set_alpha(CgScal* s, double pAp) {
   if (s->done) return;
-  double pAp = red[0];
   s->pAp = pAp;
   if (!(pAp > 0.0)) { s->done = 1; s->breakdown = 1; return; }
   s->alpha = s->rz / pAp;
 }
 
 template <typename R>
-__global__ void k_cg_update(const int* tl, int nelem, int nn, int ncomp, const CgScal* s, R* x, R* r, R* z,
-                            const R* p, const R* Ap, const R* diag, double* part) {
+__global__ void k_cg_update(const int* tl, int nelem, int nn, int ncomp, CgScal* s, R* x, R* r, R* z,
+                            const R* p, const R* Ap, const R* diag, double* part, unsigned* ctr) {
   __shared__ double sh[16];
   if (s->done) return;
   R alpha = (R)s->alpha;
@@ -697,23 +609,22 @@ __global__ void k_cg_update(const int* tl, int nelem, int nn, int ncomp, const C
   }
   double t0 = block_sum(rz, sh);
   double t1 = block_sum(rr, sh);
-  if (threadIdx.x == 0) { part[blockIdx.x] = t0; part[kPartSlot + blockIdx.x] = t1; }
-}
-
-__global__ void k_cg_scal_after(CgScal* s, const double* red) {
-  if (s->done) return;
-  double rz_new = red[0], rr = red[1];
-  s->beta = rz_new / s->rz;
-  s->rz = rz_new;
-  s->rr = rr;
-  s->iters += 1;
-  if (rr <= s->tol2 || s->iters >= s->maxit || !(rr == rr)) s->done = 1;
+  if (threadIdx.x == 0) { publish(part + blockIdx.x, t0); publish(part + kPartSlot + blockIdx.x, t1); }
+  if (grid_last_block(ctr)) {
+    double rz_new = block_sum_array(part, gridDim.x, sh);
+    double rrs = block_sum_array(part + kPartSlot, gridDim.x, sh);
+    if (threadIdx.x == 0) {
+      s->beta = rz_new / s->rz;
+      s->rz = rz_new;
+      s->rr = rrs;
+      s->iters += 1;
+      if (rrs <= s->tol2 || s->iters >= s->maxit || !(rrs == rrs)) s->done = 1;
+    }
+  }
 }
 
 template <typename R>
-__global__ void k_cg_p(const int* tl, int nelem, int nn, int ncomp, const CgScal* s, const R* z, R* p,
-                       int* done_flag) {
-  // runs even on the iteration that finished (harmless: p is not used afterwards)
+__global__ void k_cg_p(const int* tl, int nelem, int nn, int ncomp, const CgScal* s, const R* z, R* p) {
   if (s->done) return;
   R beta = (R)s->beta;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nelem; e += gridDim.x * blockDim.x) {
@@ -765,10 +676,10 @@ __global__ void k_neg(const int* tl, int nelem, int nn, int ncomp, const R* a, R
 }
 
 // Momentum sums over nodes with mass: slots 0..D-1 sum m (v^ - v^n), slot D sum m,
-// slots D+1..2D sum m v^.
+// slots D+1..2D sum m v^; the last block writes them to dst[0..2D].
 template <int D, typename R>
 __global__ void k_mom_sums(const int* tl, int nelem, int nn, const uint8_t* fr, const R* m, const R* vh,
-                           const R* vn, double* part) {
+                           const R* vn, double* part, unsigned* ctr, double* dst) {
   __shared__ double sh[16];
   double s[2 * D + 1];
   for (int k = 0; k < 2 * D + 1; ++k) s[k] = 0;
@@ -784,8 +695,15 @@ __global__ void k_mom_sums(const int* tl, int nelem, int nn, const uint8_t* fr, 
   }
   for (int k = 0; k < 2 * D + 1; ++k) {
     double t = block_sum(s[k], sh);
-    if (threadIdx.x == 0) part[k * kPartSlot + blockIdx.x] = t;
+    if (threadIdx.x == 0) publish(part + k * kPartSlot + blockIdx.x, t);
     __syncthreads();
+  }
+  if (grid_last_block(ctr)) {
+    for (int k = 0; k < 2 * D + 1; ++k) {
+      double r = block_sum_array(part + k * kPartSlot, gridDim.x, sh);
+      if (threadIdx.x == 0) dst[k] = r;
+      __syncthreads();
+    }
   }
 }
 
@@ -818,6 +736,23 @@ __global__ void k_explicit_update(const int* tl, int nelem, int nn, const uint8_
       vh[j] = ((fl >> a) & 1) ? vn[j] - f[j] / m[node] + dt * gg[a] : R(0);
     }
   }
+}
+
+// Counts the degrees of freedom (nodes with mass) into misc[2] and sets misc[1] when any
+// node with mass has a constrained component.
+template <int D>
+__global__ void k_dof_flags(const int* tl, const uint8_t* fr, int* misc) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  uint8_t f = fr[tl[blockIdx.x] * kTileNodes + threadIdx.x];
+  const uint8_t all = (uint8_t)((1u << D) - 1);
+  if (f & 0x80) {
+    atomicAdd(&cnt, 1);
+    if ((f & all) != all) atomicOr(&misc[1], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && cnt) atomicAdd(&misc[2], cnt);
 }
 
 }  // namespace mpm

@@ -81,6 +81,7 @@ struct mpm_ctx {
   int* ctile_pos = nullptr;
   int* ctile_list = nullptr;
   int* ctile_slot = nullptr;
+  int* ctile_rng = nullptr;
   void* tpart = nullptr;        // per-cell-tile region partials
   int nctile = 0;
   int* scan_bsum = nullptr;
@@ -88,13 +89,14 @@ struct mpm_ctx {
   double* part = nullptr;
   double* scal = nullptr;
   CgScal* cg = nullptr;
+  unsigned* ctr = nullptr;       // grid-reduction counters
   // pinned host mirror
   double* hbuf = nullptr;
   int* hint = nullptr;
   CgScal* hcg = nullptr;
   // state
   int np = 0, ns = 0, ntiles = 0, prev_ntiles = 0;
-  bool have_p2g = false, constrained = false;
+  bool have_p2g = false, constrained = false, mom_pending = false;
   int status = 0;
   mpm_stats stats{};
   std::string err;
@@ -162,6 +164,7 @@ size_t layout(mpm_ctx* c, char* base) {
   int* ctile_pos = b.take<int>(NT + 1);
   int* ctile_list = b.take<int>(NT);
   int* ctile_slot = b.take<int>(NT);
+  int* ctile_rng = b.take<int>(6 * NT);
   const int64_t nct_cap = std::min<int64_t>(NT, NP + 2 * NS);
   const int RNd = D == 3 ? TileGeo<3>::RN : TileGeo<2>::RN;
   const int NFmax = std::max(2 * D + 7, D);
@@ -185,6 +188,7 @@ size_t layout(mpm_ctx* c, char* base) {
   d.part = b.take<double>((size_t)kNumParts * kPartSlot);
   d.scal = b.take<double>(kScalDoubles);
   CgScal* cg = b.take<CgScal>(2);
+  unsigned* ctr = b.take<unsigned>(CTR_COUNT);
   d.status = misc;
   if (base) {
     c->vhat = vecs[0]; c->vtrial = vecs[1]; c->grad = vecs[2]; c->delta = vecs[3]; c->r = vecs[4];
@@ -192,8 +196,9 @@ size_t layout(mpm_ctx* c, char* base) {
     c->That = hvecs[0]; c->hr = hvecs[1]; c->hz = hvecs[2]; c->hp = hvecs[3]; c->hAp = hvecs[4];
     c->tile_pos = tile_pos; c->scan_bsum = scan_bsum; c->misc = misc;
     c->ctile_flag = ctile_flag; c->ctile_pos = ctile_pos; c->ctile_list = ctile_list; c->ctile_slot = ctile_slot;
+    c->ctile_rng = ctile_rng;
     c->tpart = tpart;
-    c->part = d.part; c->scal = d.scal; c->cg = cg;
+    c->part = d.part; c->scal = d.scal; c->cg = cg; c->ctr = ctr;
     if constexpr (sizeof(R) == 8) c->d64 = d; else c->d32 = d;
   }
   return b.off + 256;
@@ -259,6 +264,7 @@ TileLists tiles(mpm_ctx* c) {
   TileLists t;
   t.ctile_list = c->ctile_list;
   t.ctile_slot = c->ctile_slot;
+  t.ctile_rng = c->ctile_rng;
   t.nctile = c->nctile;
   return t;
 }
@@ -317,8 +323,9 @@ void do_p2g(mpm_ctx* c, const mpm_particles* P, const mpm_surface* S, hipStream_
   LAUNCH(c, MPM_K_SETUP, (k_flag_ctiles<D, R>), dim3(cdiv(c->ntile_total, 256)), dim3(256), 0, s, d, c->ctile_flag,
          c->ntile_total);
   scan(c, c->ctile_flag, c->ctile_pos, c->ntile_total, s);
-  LAUNCH(c, MPM_K_SETUP, k_ctile_slots, dim3(cdiv(c->ntile_total, 256)), dim3(256), 0, s, (const int*)c->ctile_flag,
-         (const int*)c->ctile_pos, c->ntile_total, c->ctile_list, c->ctile_slot);
+  LAUNCH(c, MPM_K_SETUP, (k_ctile_slots<R>), dim3(cdiv(c->ntile_total, 256)), dim3(256), 0, s, d,
+         (const int*)c->ctile_flag, (const int*)c->ctile_pos, c->ntile_total, c->ctile_list, c->ctile_slot,
+         c->ctile_rng);
   LAUNCH(c, MPM_K_SETUP, (k_mark_tiles<D, R>), dim3(cdiv(d.nn, 256)), dim3(256), 0, s, d);
   scan(c, d.tile_flag, c->tile_pos, c->ntile_total, s);
   LAUNCH(c, MPM_K_SETUP, k_compact_tiles, dim3(cdiv(c->ntile_total, 256)), dim3(256), 0, s, (const int*)d.tile_flag,
@@ -347,35 +354,26 @@ void do_p2g(mpm_ctx* c, const mpm_particles* P, const mpm_surface* S, hipStream_
   c->stats.n_tiles = c->ntiles;
 }
 
-// Reads the degree-of-freedom count and the constrained flag written by k_dof_flags.
-bool any_constrained(mpm_ctx* c, hipStream_t s) {
-  sync_read(c, s, c->misc, c->hint, 4 * sizeof(int));
-  c->stats.n_dof = c->hint[2];
-  c->status |= c->hint[0];
-  return c->hint[1] != 0;
-}
 
-// Phi(u) into scal[0] (and energy_dev if given), gradient into g.
+// Device scalar slots (doubles at ctx->scal).
+enum : int { SC_PHI = 0, SC_DOT = 1, SC_GN2 = 2, SC_SLOPE = 3, SC_PHIT = 4, SC_RHS2 = 5, SC_MOM = 8, SC_N = 16 };
+
+// Phi(u) into scal[phi_slot] (and energy_dev if given), projected gradient into g.
 template <int D, typename R>
-void do_energy_grad(mpm_ctx* c, const R* u, R* g, double* energy_dev, hipStream_t s) {
+void do_energy_grad(mpm_ctx* c, const R* u, R* g, double* energy_dev, int phi_slot, hipStream_t s) {
   Dev<R>& d = dev<R>(c);
   TileLists tl = tiles(c);
   if (c->nctile > 0)
     LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_ENERGY>), dim3(c->nctile), dim3(TileGeo<D>::NT), 0, s, d, tl,
            u, (R*)c->tpart, 0, (const int*)nullptr, 2);
-  else
-    LAUNCH(c, MPM_K_BLAS, k_fill_r<double>, dim3(1), dim3(1), 0, s, c->part + 2 * kPartSlot, 0.0, (int64_t)1);
-  if (c->ntiles > 0)
+  if (c->ntiles > 0) {
     LAUNCH(c, MPM_K_ENERGY_NODE, (k_merge_stress<D, R>), dim3(c->ntiles), dim3(64), 0, s, d, tl, (const R*)c->tpart,
-           u, g, (int)NM_GRAD, 0.0, 0, (const int*)nullptr, 4, -1);
-  else
-    LAUNCH(c, MPM_K_BLAS, k_fill_r<double>, dim3(1), dim3(1), 0, s, c->part + 4 * kPartSlot, 0.0, (int64_t)1);
-  LAUNCH(c, MPM_K_REDUCE, k_finalize, dim3(1), dim3(256), 0, s, c->part + 2 * kPartSlot, std::max(c->nctile, 1), 1,
-         c->scal + 8);
-  LAUNCH(c, MPM_K_REDUCE, k_fill_r<double>, dim3(1), dim3(1), 0, s, c->scal + 9, 0.0, (int64_t)1);
-  LAUNCH(c, MPM_K_REDUCE, k_finalize, dim3(1), dim3(256), 0, s, c->part + 4 * kPartSlot, std::max(c->ntiles, 1), 1,
-         c->scal + 10);
-  LAUNCH(c, MPM_K_REDUCE, k_sum3, dim3(1), dim3(1), 0, s, (const double*)(c->scal + 8), c->scal + 0, energy_dev);
+           u, g, (int)NM_GRAD, 0.0, 0, (const int*)nullptr, c->nctile > 0 ? (const double*)(c->part + 2 * kPartSlot) : nullptr,
+           c->nctile, c->part + 4 * kPartSlot, c->ctr + CTR_MERGE, c->scal + phi_slot, energy_dev, (CgScal*)nullptr);
+  } else {
+    LAUNCH(c, MPM_K_BLAS, k_fill_r<double>, dim3(1), dim3(1), 0, s, c->scal + phi_slot, 0.0, (int64_t)1);
+    if (energy_dev) LAUNCH(c, MPM_K_BLAS, k_fill_r<double>, dim3(1), dim3(1), 0, s, energy_dev, 0.0, (int64_t)1);
+  }
 }
 
 // Caches the surface linearization point F_r = I + dt grad v_lin(s_r).
@@ -386,9 +384,10 @@ void do_surface_lin(mpm_ctx* c, const R* vlin, hipStream_t s) {
     LAUNCH(c, MPM_K_HESS_SURF, (k_surface_F<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d, vlin);
 }
 
-// out = P(alpha M P w + H P w) with the surface term linearized at the cached F_r.
+// out = P(alpha M P w + H P w) with the surface term linearized at the cached F_r.  With cg
+// the merge also reduces w . out and sets the CG step length.
 template <int D, typename R>
-void do_hessvec(mpm_ctx* c, const R* w, double alpha, R* out, bool mask_in, const int* done, int dot_slot,
+void do_hessvec(mpm_ctx* c, const R* w, double alpha, R* out, bool mask_in, const int* done, CgScal* cg,
                 hipStream_t s) {
   Dev<R>& d = dev<R>(c);
   TileLists tl = tiles(c);
@@ -397,7 +396,8 @@ void do_hessvec(mpm_ctx* c, const R* w, double alpha, R* out, bool mask_in, cons
            (R*)c->tpart, (int)mask_in, done, -1);
   if (c->ntiles > 0)
     LAUNCH(c, MPM_K_HESS_NODE, (k_merge_stress<D, R>), dim3(c->ntiles), dim3(64), 0, s, d, tl, (const R*)c->tpart,
-           w, out, (int)NM_HESS, alpha, (int)mask_in, done, -1, dot_slot);
+           w, out, (int)NM_HESS, alpha, (int)mask_in, done, (const double*)nullptr, 0, c->part + 4 * kPartSlot,
+           c->ctr + CTR_MERGE, (double*)nullptr, (double*)nullptr, cg);
 }
 
 // Forces only (no inertia term): out = P sum_q S_q grad N_i for the stress of u.
@@ -410,11 +410,12 @@ void do_hessvec_force(mpm_ctx* c, const R* u, R* out, hipStream_t s) {
            u, (R*)c->tpart, 0, (const int*)nullptr, -1);
   if (c->ntiles > 0)
     LAUNCH(c, MPM_K_ENERGY_NODE, (k_merge_stress<D, R>), dim3(c->ntiles), dim3(64), 0, s, d, tl, (const R*)c->tpart,
-           u, out, (int)NM_HESS, 0.0, 0, (const int*)nullptr, -1, -1);
+           u, out, (int)NM_HESS, 0.0, 0, (const int*)nullptr, (const double*)nullptr, 0, c->part + 4 * kPartSlot,
+           c->ctr + CTR_MERGE, (double*)nullptr, (double*)nullptr, (CgScal*)nullptr);
 }
 
 template <int D, typename R>
-void do_heat_apply(mpm_ctx* c, const R* T, R* out, const int* done, int dot_slot, hipStream_t s) {
+void do_heat_apply(mpm_ctx* c, const R* T, R* out, const int* done, CgScal* cg, hipStream_t s) {
   Dev<R>& d = dev<R>(c);
   TileLists tl = tiles(c);
   if (c->nctile > 0)
@@ -422,7 +423,7 @@ void do_heat_apply(mpm_ctx* c, const R* T, R* out, const int* done, int dot_slot
            (R*)c->tpart, done);
   if (c->ntiles > 0)
     LAUNCH(c, MPM_K_HEAT_NODE, (k_merge_heat<D, R>), dim3(c->ntiles), dim3(64), 0, s, d, tl, (const R*)c->tpart, T,
-           out, done, dot_slot);
+           out, done, c->part + 4 * kPartSlot, c->ctr + CTR_MERGE, cg);
 }
 
 template <int D, typename R>
@@ -430,64 +431,70 @@ void do_g2p(mpm_ctx* c, const R* vh, const R* Th, mpm_particles* P, hipStream_t 
   Dev<R>& d = dev<R>(c);
   if (!P || P->n != c->np) throw ApiError{MPM_EINVAL, "g2p particle count differs from p2g"};
   if (c->ns > 0) LAUNCH(c, MPM_K_G2P_SPLIT, (k_g2p_split<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d, vh);
-  if (c->np > 0)
-    LAUNCH(c, MPM_K_G2P, (k_g2p_particles<D, R>), dim3(cdiv(c->np, 256)), dim3(256), 0, s, d, vh, Th, (R*)P->x,
-                       (R*)P->v, (R*)P->A, (R*)P->J, (R*)P->T, (R*)P->gradT);
+  if (c->nctile > 0)
+    LAUNCH(c, MPM_K_G2P, (k_tile_g2p<D, R>), dim3(c->nctile), dim3(256), 0, s, d, tiles(c), vh, Th,
+           (R*)P->x, (R*)P->v, (R*)P->A, (R*)P->J, (R*)P->V0, (R*)P->m, (R*)P->T, (R*)P->gradT);
 }
 
-// Scalar readback helpers -----------------------------------------------------------------
+// a . b over the active nodes into scal[slot] (asynchronous).
 template <typename R>
-double dot_sync(mpm_ctx* c, const R* a, const R* b, int ncomp, hipStream_t s) {
+void dot_async(mpm_ctx* c, const R* a, const R* b, int ncomp, int slot, hipStream_t s) {
   Dev<R>& d = dev<R>(c);
   int nelem = c->ntiles * 64, nb = krylov_blocks(nelem);
   LAUNCH(c, MPM_K_BLAS, k_dot<R>, dim3(nb), dim3(256), 0, s, (const int*)d.tile_list, nelem, d.nn, ncomp, a, b,
-                     c->part, (const int*)nullptr);
-  LAUNCH(c, MPM_K_REDUCE, k_finalize, dim3(1), dim3(256), 0, s, (const double*)c->part, nb, 1, c->scal + 16);
-  sync_read(c, s, c->scal + 16, c->hbuf, sizeof(double));
-  return c->hbuf[0];
+         c->part, c->ctr + CTR_DOT, c->scal + slot);
 }
 
-// Jacobi-preconditioned CG with device-side scalars; the host only polls the done flag
-// every `chunk` iterations.  apply(p, Ap, done, dot_slot) must write A p and the partial
-// sums of p . A p into dot_slot.
+// Momentum sums of vh into scal[SC_MOM..] (asynchronous).
+template <int D, typename R>
+void mom_sums_async(mpm_ctx* c, const R* vh, hipStream_t s) {
+  Dev<R>& d = dev<R>(c);
+  int nelem = c->ntiles * 64, nb = krylov_blocks(nelem);
+  LAUNCH(c, MPM_K_BLAS, (k_mom_sums<D, R>), dim3(nb), dim3(256), 0, s, (const int*)d.tile_list, nelem, d.nn,
+         (const uint8_t*)d.gfree, (const R*)d.gm, vh, (const R*)d.gvn, c->part, c->ctr + CTR_MOM, c->scal + SC_MOM);
+}
+
+// Reads the scalar block (and the misc words) in one synchronization.
+void read_scalars(mpm_ctx* c, hipStream_t s, bool misc = false) {
+  HIPCHK(hipMemcpyAsync(c->hbuf, c->scal, SC_N * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (misc) HIPCHK(hipMemcpyAsync(c->hint, c->misc, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (misc) {
+    c->status |= c->hint[0];
+    c->constrained = c->hint[1] != 0;
+    c->stats.n_dof = c->hint[2];
+  }
+}
+
+// Jacobi-preconditioned CG with device-side scalars: apply(p, Ap, done, cg) must write
+// A p and, when cg is given, set the step length from p . A p.  The host polls the done
+// flag after 2, 4, 8, ... iterations.
 template <typename R, class Apply>
 int cg_solve(mpm_ctx* c, Apply&& apply, const R* b, R* x, bool x0_given, const R* diag, R* r, R* z, R* p, R* Ap,
-             int ncomp, double tol_abs, int maxit, hipStream_t s) {
+             int ncomp, double tol2_host, const double* tol2_scale, int maxit, hipStream_t s) {
   Dev<R>& d = dev<R>(c);
   int nelem = c->ntiles * 64, nb = krylov_blocks(nelem);
   const int* tl = d.tile_list;
-  if (x0_given) {
-    apply(x, Ap, (const int*)nullptr, -1);
-    LAUNCH(c, MPM_K_BLAS, k_cg_start_x0<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, b, (const R*)Ap, diag,
-                       r, z, p, c->part);
-  } else {
-    LAUNCH(c, MPM_K_BLAS, k_cg_start<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, b, diag, x, r, z, p,
-                       c->part, 1);
-  }
-  LAUNCH(c, MPM_K_REDUCE, k_finalize, dim3(1), dim3(256), 0, s, (const double*)c->part, nb, 2, c->scal + 20);
-  LAUNCH(c, MPM_K_REDUCE, k_cg_init_scal, dim3(1), dim3(1), 0, s, c->cg, (const double*)(c->scal + 20),
-                     tol_abs * tol_abs, maxit);
+  if (x0_given) apply(x, Ap, (const int*)nullptr, (CgScal*)nullptr);
+  LAUNCH(c, MPM_K_BLAS, k_cg_start<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, b,
+         x0_given ? (const R*)Ap : (const R*)nullptr, diag, x, r, z, p, c->part, c->ctr + CTR_CGSTART, c->cg, tol2_host,
+         tol2_scale, maxit);
   const int* done = &c->cg->done;
-  int chunk = 4;
+  int chunk = 2;
   for (int it = 0; it < maxit + chunk; it += chunk) {
     for (int j = 0; j < chunk; ++j) {
-      apply(p, Ap, done, 0);
-      LAUNCH(c, MPM_K_REDUCE, k_finalize, dim3(1), dim3(256), 0, s, (const double*)c->part, std::max(c->ntiles, 1), 1,
-                         c->scal + 22);
-      LAUNCH(c, MPM_K_REDUCE, k_cg_pap, dim3(1), dim3(1), 0, s, c->cg, (const double*)(c->scal + 22));
-      LAUNCH(c, MPM_K_BLAS, k_cg_update<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, (const CgScal*)c->cg, x,
-                         r, z, (const R*)p, (const R*)Ap, diag, c->part);
-      LAUNCH(c, MPM_K_REDUCE, k_finalize, dim3(1), dim3(256), 0, s, (const double*)c->part, nb, 2, c->scal + 20);
-      LAUNCH(c, MPM_K_REDUCE, k_cg_scal_after, dim3(1), dim3(1), 0, s, c->cg, (const double*)(c->scal + 20));
+      apply(p, Ap, done, c->cg);
+      LAUNCH(c, MPM_K_BLAS, k_cg_update<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, c->cg, x, r, z,
+             (const R*)p, (const R*)Ap, diag, c->part, c->ctr + CTR_CGUPD);
       LAUNCH(c, MPM_K_BLAS, k_cg_p<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, (const CgScal*)c->cg,
-                         (const R*)z, p, (int*)nullptr);
+             (const R*)z, p);
     }
     sync_read(c, s, c->cg, c->hcg, sizeof(CgScal));
     if (c->hcg->done) break;
-    chunk = std::min(chunk * 2, 32);
+    chunk = std::min(chunk * 2, 16);
   }
   LAUNCH(c, MPM_K_BLAS, k_cg_fixup<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, (const CgScal*)c->cg, x,
-                     (const R*)z);
+         (const R*)z);
   if (!(c->hcg->rr == c->hcg->rr)) c->status |= ST_NONFINITE;
   return c->hcg->iters;
 }
@@ -504,28 +511,26 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
   R* g = (R*)c->grad;
   R* delta = (R*)c->delta;
   mpm_stats& st = c->stats;
-  c->constrained = any_constrained(c, s);
-  const bool fix = p.momentum_fix && !c->constrained;
-  // mass sum for the absolute floor and the translation correction
-  LAUNCH(c, MPM_K_BLAS, (k_mom_sums<D, R>), dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, (const uint8_t*)d.gfree,
-                     (const R*)d.gm, (const R*)d.gvn, (const R*)d.gvn, c->part);
-  LAUNCH(c, MPM_K_REDUCE, k_finalize, dim3(1), dim3(256), 0, s, (const double*)c->part, nb, 2 * D + 1, c->scal + 32);
-  sync_read(c, s, c->scal + 32, c->hbuf, sizeof(double) * (2 * D + 1));
-  double msum = c->hbuf[D];
-  double floor_abs = 1e-14 * msum * p.dx / p.dt;
+  // start: v^ = P v^n, mass sum, Phi and |g| in one round trip
   LAUNCH(c, MPM_K_BLAS, k_project_copy<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const uint8_t*)d.gfree,
-                     (const R*)d.gvn, vhat);
-  do_energy_grad<D, R>(c, vhat, g, nullptr, s);
-  double phi = 0;
-  sync_read(c, s, c->scal, &phi, sizeof(double));
-  double gn = std::sqrt(dot_sync<R>(c, g, g, D, s));
-  double g0 = gn;
+         (const R*)d.gvn, vhat);
+  mom_sums_async<D, R>(c, (const R*)d.gvn, s);
+  do_energy_grad<D, R>(c, vhat, g, nullptr, SC_PHI, s);
+  dot_async<R>(c, g, g, D, SC_GN2, s);
+  read_scalars(c, s, true);
+  const bool fix = p.momentum_fix && !c->constrained;
+  const double msum = c->hbuf[SC_MOM + D];
+  const double floor_abs = 1e-14 * msum * p.dx / p.dt;
+  double phi = c->hbuf[SC_PHI];
+  double gn = std::sqrt(std::max(c->hbuf[SC_GN2], 0.0));
+  const double g0 = gn;
   st.g0 = g0;
   st.energy_evals = 1;
   st.converged = 0;
-  auto apply = [&](const R* pv, R* Apv, const int* done, int slot) {
-    do_hessvec<D, R>(c, pv, 1.0, Apv, false, done, slot, s);
+  auto apply = [&](const R* pv, R* Apv, const int* done, CgScal* cg) {
+    do_hessvec<D, R>(c, pv, 1.0, Apv, false, done, cg, s);
   };
+  const double eps = sizeof(R) == 8 ? 2.220446049250313e-16 : 1.1920928955078125e-07;
   int it = 0;
   double gn_prev = 1e300;
   for (; it < p.newton_max; ++it) {
@@ -539,50 +544,56 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
     LAUNCH(c, MPM_K_BLAS, k_neg<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const R*)g, vtrial);
     double cg_tol = std::max(p.cg_rel * gn, 0.1 * p.newton_tol * g0);
     int cit = cg_solve<R>(c, apply, vtrial, delta, false, (const R*)d.gdiag, (R*)c->r, (R*)c->z, (R*)c->pp,
-                          (R*)c->Ap, D, cg_tol, p.cg_max, s);
+                          (R*)c->Ap, D, cg_tol * cg_tol, nullptr, p.cg_max, s);
     st.cg_iters += cit;
     st.hessvecs += cit;
-    double slope = dot_sync<R>(c, g, delta, D, s);
-    double alpha = 1.0, phit = phi;
-    for (int ls = 0; ls < std::max(p.ls_max, 1); ++ls) {
-      LAUNCH(c, MPM_K_BLAS, k_axpy_to<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const R*)vhat,
-                         (const R*)delta, alpha, vtrial);
-      do_energy_grad<D, R>(c, vtrial, (R*)c->gscratch, nullptr, s);
-      sync_read(c, s, c->scal, &phit, sizeof(double));
-      st.energy_evals++;
-      // Armijo with the round-off of Phi as allowance (8 eps |Phi|, eps of the arithmetic):
-      // near convergence the decrement is below it and the test would be decided by noise.
-      const double eps = sizeof(R) == 8 ? 2.220446049250313e-16 : 1.1920928955078125e-07;
+    // slope and the full step's energy in one round trip
+    dot_async<R>(c, g, delta, D, SC_SLOPE, s);
+    double alpha = 1.0;
+    LAUNCH(c, MPM_K_BLAS, k_axpy_to<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const R*)vhat,
+           (const R*)delta, alpha, vtrial);
+    do_energy_grad<D, R>(c, vtrial, (R*)c->gscratch, nullptr, SC_PHIT, s);
+    read_scalars(c, s);
+    st.energy_evals++;
+    const double slope = c->hbuf[SC_SLOPE];
+    double phit = c->hbuf[SC_PHIT];
+    // Armijo with the round-off of Phi as allowance (8 eps |Phi|, eps of the arithmetic):
+    // near convergence the decrement is below it and the test would be decided by noise.
+    for (int ls = 1; ls < std::max(p.ls_max, 1); ++ls) {
       const double noise = 8.0 * eps * std::max(std::fabs(phi), std::fabs(phit));
       if (phit <= phi + p.ls_c1 * alpha * slope + noise) break;
-      if (ls + 1 < std::max(p.ls_max, 1)) { alpha *= 0.5; st.line_search_halvings++; }
+      alpha *= 0.5;
+      st.line_search_halvings++;
+      LAUNCH(c, MPM_K_BLAS, k_axpy_to<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const R*)vhat,
+             (const R*)delta, alpha, vtrial);
+      do_energy_grad<D, R>(c, vtrial, (R*)c->gscratch, nullptr, SC_PHIT, s);
+      read_scalars(c, s);
+      st.energy_evals++;
+      phit = c->hbuf[SC_PHIT];
     }
     std::swap(c->vhat, c->vtrial);
     vhat = (R*)c->vhat;
     vtrial = (R*)c->vtrial;
     if (fix) {
-      LAUNCH(c, MPM_K_BLAS, (k_mom_sums<D, R>), dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, (const uint8_t*)d.gfree,
-                         (const R*)d.gm, (const R*)vhat, (const R*)d.gvn, c->part);
-      LAUNCH(c, MPM_K_REDUCE, k_finalize, dim3(1), dim3(256), 0, s, (const double*)c->part, nb, 2 * D + 1, c->scal + 32);
+      mom_sums_async<D, R>(c, (const R*)vhat, s);
       LAUNCH(c, MPM_K_BLAS, (k_mom_fix<D, R>), dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, (const uint8_t*)d.gfree,
-                         (const double*)(c->scal + 32), p.dt, p.gravity[0], p.gravity[1], p.gravity[2], vhat);
+             (const double*)(c->scal + SC_MOM), p.dt, p.gravity[0], p.gravity[1], p.gravity[2], vhat);
     }
-    do_energy_grad<D, R>(c, vhat, g, nullptr, s);
-    sync_read(c, s, c->scal, &phi, sizeof(double));
+    do_energy_grad<D, R>(c, vhat, g, nullptr, SC_PHI, s);
+    dot_async<R>(c, g, g, D, SC_GN2, s);
+    read_scalars(c, s);
     st.energy_evals++;
-    gn = std::sqrt(dot_sync<R>(c, g, g, D, s));
+    phi = c->hbuf[SC_PHI];
+    gn = std::sqrt(std::max(c->hbuf[SC_GN2], 0.0));
   }
   if (it == p.newton_max && gn <= std::max(p.newton_tol * g0, floor_abs)) st.converged = 1;
   st.newton_iters = it;
   st.gnorm = gn;
   st.phi = phi;
   if (!st.converged && !(c->status & ST_NONFINITE)) c->status |= ST_NOCONV;
-  // grid momentum after the solve
-  LAUNCH(c, MPM_K_BLAS, (k_mom_sums<D, R>), dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, (const uint8_t*)d.gfree,
-                     (const R*)d.gm, (const R*)vhat, (const R*)d.gvn, c->part);
-  LAUNCH(c, MPM_K_REDUCE, k_finalize, dim3(1), dim3(256), 0, s, (const double*)c->part, nb, 2 * D + 1, c->scal + 32);
-  sync_read(c, s, c->scal + 32, c->hbuf, sizeof(double) * (2 * D + 1));
-  for (int a = 0; a < 3; ++a) st.momentum[a] = a < D ? c->hbuf[D + 1 + a] : 0.0;
+  // grid momentum after the solve (read with the next status query)
+  mom_sums_async<D, R>(c, (const R*)vhat, s);
+  c->mom_pending = true;
 }
 
 template <int D, typename R>
@@ -595,7 +606,7 @@ void do_explicit(mpm_ctx* c, hipStream_t s) {
   R* f2 = (R*)c->gscratch;
   R* zero = (R*)c->zero;
   LAUNCH(c, MPM_K_BLAS, k_axpy_to<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const R*)d.gvn, (const R*)d.gvn,
-                     -1.0, zero);
+         -1.0, zero);
   Dev<R> saved = d;
   // J and surface terms at y = x (v^ = 0)
   d.term_mask = saved.term_mask & 3;
@@ -604,13 +615,16 @@ void do_explicit(mpm_ctx* c, hipStream_t s) {
   d.term_mask = saved.term_mask & 4;
   if (d.term_mask) {
     do_hessvec_force<D, R>(c, (const R*)d.gvn, f2, s);
-    LAUNCH(c, MPM_K_BLAS, k_axpy_to<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const R*)f, (const R*)f2, 1.0, f);
+    LAUNCH(c, MPM_K_BLAS, k_axpy_to<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const R*)f, (const R*)f2, 1.0,
+           f);
   }
   d = saved;
   LAUNCH(c, MPM_K_BLAS, (k_explicit_update<D, R>), dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, (const uint8_t*)d.gfree,
-                     (const R*)d.gm, (const R*)d.gvn, (const R*)f, (R)c->p.gravity[0], (R)c->p.gravity[1],
-                     (R)c->p.gravity[2], (R)c->p.dt, (R*)c->vhat);
+         (const R*)d.gm, (const R*)d.gvn, (const R*)f, (R)c->p.gravity[0], (R)c->p.gravity[1], (R)c->p.gravity[2],
+         (R)c->p.dt, (R*)c->vhat);
   c->stats.converged = 1;
+  mom_sums_async<D, R>(c, (const R*)c->vhat, s);
+  c->mom_pending = true;
 }
 
 template <int D, typename R>
@@ -621,11 +635,13 @@ void do_solve_heat(mpm_ctx* c, hipStream_t s) {
   const int* tl = d.tile_list;
   R* T = (R*)c->That;
   LAUNCH(c, MPM_K_BLAS, k_axpy_to<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, 1, (const R*)d.gTn, (const R*)d.gTn,
-                     0.0, T);
-  double bn = std::sqrt(dot_sync<R>(c, d.hrhs, d.hrhs, 1, s));
-  auto apply = [&](const R* pv, R* Apv, const int* done, int slot) { do_heat_apply<D, R>(c, pv, Apv, done, slot, s); };
+         0.0, T);
+  dot_async<R>(c, (const R*)d.hrhs, (const R*)d.hrhs, 1, SC_RHS2, s);
+  auto apply = [&](const R* pv, R* Apv, const int* done, CgScal* cg) {
+    do_heat_apply<D, R>(c, pv, Apv, done, cg, s);
+  };
   int it = cg_solve<R>(c, apply, d.hrhs, T, true, (const R*)d.hdiag, (R*)c->hr, (R*)c->hz, (R*)c->hp, (R*)c->hAp, 1,
-                       c->p.heat_tol * bn, c->p.heat_max, s);
+                       c->p.heat_tol * c->p.heat_tol, c->scal + SC_RHS2, c->p.heat_max, s);
   c->stats.heat_iters = it;
   c->stats.heat_res = std::sqrt(std::max(c->hcg->rr, 0.0));
   if (it >= c->p.heat_max && c->hcg->rr > c->hcg->tol2) c->status |= ST_NOCONV;
@@ -828,7 +844,7 @@ int mpm_energy_grad(mpm_ctx* ctx, const void* v_hat, double* energy_dev, void* g
     dispatch(ctx, [&](auto Dc, auto Rv) {
       constexpr int D = decltype(Dc)::value;
       using R = decltype(Rv);
-      do_energy_grad<D, R>(ctx, (const R*)v_hat, (R*)grad, energy_dev, s);
+      do_energy_grad<D, R>(ctx, (const R*)v_hat, (R*)grad, energy_dev, SC_PHI, s);
     });
   });
   return rc != MPM_OK ? rc : check_launch(ctx);
@@ -843,7 +859,7 @@ int mpm_hessvec(mpm_ctx* ctx, const void* v_lin, const void* w, double alpha_mas
       constexpr int D = decltype(Dc)::value;
       using R = decltype(Rv);
       do_surface_lin<D, R>(ctx, (const R*)v_lin, s);
-      do_hessvec<D, R>(ctx, (const R*)w, alpha_mass, (R*)out, true, nullptr, -1, s);
+      do_hessvec<D, R>(ctx, (const R*)w, alpha_mass, (R*)out, true, nullptr, (CgScal*)nullptr, s);
     });
   });
   return rc != MPM_OK ? rc : check_launch(ctx);
@@ -857,7 +873,7 @@ int mpm_heat_apply(mpm_ctx* ctx, const void* T_in, void* T_out, void* stream) {
     dispatch(ctx, [&](auto Dc, auto Rv) {
       constexpr int D = decltype(Dc)::value;
       using R = decltype(Rv);
-      do_heat_apply<D, R>(ctx, (const R*)T_in, (R*)T_out, nullptr, -1, s);
+      do_heat_apply<D, R>(ctx, (const R*)T_in, (R*)T_out, nullptr, (CgScal*)nullptr, s);
     });
   });
   return rc != MPM_OK ? rc : check_launch(ctx);
@@ -961,6 +977,7 @@ int mpm_grid_view(mpm_ctx* ctx, int32_t field, void** out_ptr) {
       case MPM_F_COUNT: p = d.pcnt_orig; break;
       case MPM_F_KSURF: p = d.sk_orig; break;
       case MPM_F_MOM_DIAG: p = d.gdiag; break;
+      case MPM_F_PERM: p = d.p_perm; break;
       default: p = nullptr;
     }
   };
@@ -997,7 +1014,17 @@ int mpm_scene_status(mpm_ctx* ctx, void* stream) {
   if (!ctx) return MPM_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   int rc = guarded(ctx, [&] {
-    sync_read(ctx, s, ctx->misc, ctx->hint, sizeof(int));
+    if (ctx->mom_pending) {
+      // grid momentum after the solve, read with the status word in one round trip
+      HIPCHK(hipMemcpyAsync(ctx->hbuf, ctx->scal, SC_N * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(ctx->hint, ctx->misc, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      const int D = ctx->p.dim;
+      for (int a = 0; a < 3; ++a) ctx->stats.momentum[a] = a < D ? ctx->hbuf[SC_MOM + D + 1 + a] : 0.0;
+      ctx->mom_pending = false;
+    } else {
+      sync_read(ctx, s, ctx->misc, ctx->hint, sizeof(int));
+    }
     ctx->status |= ctx->hint[0];
   });
   if (rc != MPM_OK) return rc;

@@ -17,6 +17,10 @@
 
 namespace mpm {
 
+// Tile kernels run 9-wave (3D) workgroups; two of them fit on a CU only when every SIMD
+// can hold 6 waves, i.e. at most 80 VGPRs per lane.
+#define MPM_TILE_KERNEL(NT) __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6)))
+
 template <int D> struct TileGeo;
 template <> struct TileGeo<3> {
   static constexpr int E = 4;          // cells per tile edge
@@ -37,6 +41,7 @@ template <> struct TileGeo<2> {
 struct TileLists {
   const int* ctile_list;   // active cell tiles (compact)
   const int* ctile_slot;   // cell tile -> slot in ctile_list, -1 when inactive
+  const int* ctile_rng;    // per slot: [interior begin, end, surface begin, end, balance begin, end]
   int nctile;
 };
 
@@ -250,32 +255,129 @@ MPM_DEV R surface_q(const R (&F)[D][D], const R* Nv, bool hess, const R (&G)[D][
 // ======================================================================================
 enum TileMode { TM_ENERGY = 0, TM_HESS = 1, TM_FORCE = 2 };
 
+// Per-point 1D weight table: w[a][k], dw[a][k] (dw per unit length) for the nodes
+// c_a - 1 + k of the point's stencil.
+template <int D, typename R>
+MPM_DEV void weight_table(const R* f, R fn, R (&w)[D][3], R (&dw)[D][3]) {
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    R x = f[a];
+    w[a][0] = R(0.5) * (R(1) - x) * (R(1) - x);
+    w[a][1] = R(0.75) - (x - R(0.5)) * (x - R(0.5));
+    w[a][2] = R(0.5) * x * x;
+    dw[a][0] = (x - R(1)) * fn;
+    dw[a][1] = (R(1) - R(2) * x) * fn;
+    dw[a][2] = x * fn;
+  }
+}
+
+// Gradient sum_k u_a[k] grad N_k of NC components staged on the region (u[rn*NC + a]) by
+// sum factorization over the axes (the tensor-product structure of N).
+template <int D, typename R, int NC>
+MPM_DEV void region_grad(const R* u, const int* lc, const R (&w)[D][3], const R (&dw)[D][3], R (&G)[NC][D],
+                         R* val) {
+  constexpr int RE = TileGeo<D>::RE;
+#pragma unroll
+  for (int a = 0; a < NC; ++a) {
+    val[a] = 0;
+#pragma unroll
+    for (int b = 0; b < D; ++b) G[a][b] = 0;
+  }
+  if constexpr (D == 3) {
+#pragma unroll
+    for (int k2 = 0; k2 < 3; ++k2) {
+      R A[NC], B[NC], Cc[NC], V[NC];
+#pragma unroll
+      for (int a = 0; a < NC; ++a) { A[a] = 0; B[a] = 0; Cc[a] = 0; V[a] = 0; }
+#pragma unroll
+      for (int k1 = 0; k1 < 3; ++k1) {
+        int base = lc[0] + RE * ((lc[1] + k1) + RE * (lc[2] + k2));
+#pragma unroll
+        for (int a = 0; a < NC; ++a) {
+          R u0 = u[(base + 0) * NC + a], u1 = u[(base + 1) * NC + a], u2 = u[(base + 2) * NC + a];
+          R s = u0 * w[0][0] + u1 * w[0][1] + u2 * w[0][2];
+          R sd = u0 * dw[0][0] + u1 * dw[0][1] + u2 * dw[0][2];
+          A[a] += sd * w[1][k1];
+          B[a] += s * dw[1][k1];
+          Cc[a] += s * w[1][k1];
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < NC; ++a) {
+        G[a][0] += A[a] * w[2][k2];
+        G[a][1] += B[a] * w[2][k2];
+        G[a][2] += Cc[a] * dw[2][k2];
+        val[a] += Cc[a] * w[2][k2];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) {
+      int base = lc[0] + RE * (lc[1] + k1);
+#pragma unroll
+      for (int a = 0; a < NC; ++a) {
+        R u0 = u[(base + 0) * NC + a], u1 = u[(base + 1) * NC + a], u2 = u[(base + 2) * NC + a];
+        R s = u0 * w[0][0] + u1 * w[0][1] + u2 * w[0][2];
+        R sd = u0 * dw[0][0] + u1 * dw[0][1] + u2 * dw[0][2];
+        G[a][0] += sd * w[1][k1];
+        G[a][1] += s * dw[1][k1];
+        val[a] += s * w[1][k1];
+      }
+    }
+  }
+}
+
+// Lane (cell, k0[, k1]) view of a point's weights: the weights and gradients of its 3
+// nodes k = 0..2 along the last axis.
+template <int D, typename R>
+MPM_DEV void lane_nodes(const R* W, const R* DW, int k0, int k1, R (&wn)[3], R (&gn)[3][D]) {
+  if constexpr (D == 3) {
+    R wx = W[0 * 3 + k0], dwx = DW[0 * 3 + k0], wy = W[1 * 3 + k1], dwy = DW[1 * 3 + k1];
+    R al = dwx * wy, be = wx * dwy, ga = wx * wy;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      R wz = W[2 * 3 + k], dwz = DW[2 * 3 + k];
+      wn[k] = ga * wz;
+      gn[k][0] = al * wz;
+      gn[k][1] = be * wz;
+      gn[k][2] = ga * dwz;
+    }
+  } else {
+    R wx = W[k0], dwx = DW[k0];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      R wy = W[3 + k], dwy = DW[3 + k];
+      wn[k] = wx * wy;
+      gn[k][0] = dwx * wy;
+      gn[k][1] = wx * dwy;
+    }
+  }
+}
+
 template <int D, typename R>
 struct StressLds {
   static constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
-  R u[RN * D];                 // input field on the node region
-  R pf[NT * D];                // point cell-relative positions
-  R pS[NT * D * D];            // point stresses
-  R cellpart[64 * 27 * D];     // per-cell partials (FC = D)
+  static constexpr int CH = sizeof(R) == 8 ? NT / 4 : NT / 2; // points per chunk (2 blocks per CU)
+  static constexpr int PW = 6 * D + D * D;                  // w, dw tables + stress
+  R u[RN * D];
+  R pt[CH * PW];
+  R cellpart[64 * 27 * D];
   double red[16];
 };
 
 template <int D, typename R, int MODE>
-__global__ void __launch_bounds__(TileGeo<D>::NT) k_tile_stress(Dev<R> d, TileLists tl, const R* u, R* tpart,
+__global__ void MPM_TILE_KERNEL(TileGeo<D>::NT) k_tile_stress(Dev<R> d, TileLists tl, const R* u, R* tpart,
                                                                 int mask_in, const int* done, int energy_slot) {
-  constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN, RE = TileGeo<D>::RE;
+  constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
+  constexpr int CH = StressLds<D, R>::CH, PW = StressLds<D, R>::PW;
   __shared__ StressLds<D, R> sm;
   if (done && *done) return;
   const int ct = tl.ctile_list[blockIdx.x];
   const int N = d.np, S = d.ns, nn = d.nn;
   const int t = threadIdx.x;
   const R dt = d.dt;
-  // region origin (global node coordinates of region node 0)
   int org[3] = {0, 0, 0};
   tiled_coords<D>(ct, 0, d.nt, org);
-#pragma unroll
-  for (int a = 0; a < D; ++a) org[a] -= 1;
-  // stage u on the region
   for (int rn = t; rn < RN; rn += NT) {
     int r[3];
     region_coords<D>(rn, r);
@@ -286,16 +388,16 @@ __global__ void __launch_bounds__(TileGeo<D>::NT) k_tile_stress(Dev<R> d, TileLi
       sm.u[rn * D + a] = (gnode >= 0 && ((fr >> a) & 1)) ? u[a * nn + gnode] : R(0);
   }
   const int cb = ct * 64;
-  const int pb = d.p_start[cb], pe = d.p_start[cb + 64];
   const bool surf = (d.term_mask & 2) && S > 0;
-  const int sb = surf ? d.s_start[cb] : 0, se = surf ? d.s_start[cb + 64] : 0;
   const bool vol = (d.term_mask & 5) != 0;
-  const int npi = vol ? pe - pb : 0;
+  const int* rg = tl.ctile_rng + 6 * blockIdx.x;
+  const int pb = rg[0], pe = vol ? rg[1] : pb;
+  const int sb = surf ? rg[2] : 0, se = surf ? rg[3] : 0;
+  const int npi = pe - pb;
   const int ntot = npi + (se - sb);
   int lcell, lk0, lk1;
   lane_map<D>(t, lcell, lk0, lk1);
   const bool lane_on = t < 64 * TileGeo<D>::LPC;
-  // the lane's cell ranges
   int cpb = 0, cpe = 0, csb = 0, cse = 0;
   if (lane_on) {
     if (vol) { cpb = d.p_start[cb + lcell] - pb; cpe = d.p_start[cb + lcell + 1] - pb; }
@@ -305,44 +407,26 @@ __global__ void __launch_bounds__(TileGeo<D>::NT) k_tile_stress(Dev<R> d, TileLi
   acc.zero();
   double e = 0;
   __syncthreads();
-  for (int q0 = 0; q0 < ntot; q0 += NT) {
-    // ---- point phase ----
+  for (int q0 = 0; q0 < ntot; q0 += CH) {
+    // ---- point phase: weights, gradient of u, stress ----
     int q = q0 + t;
-    if (q < ntot) {
-      R x[D];
+    if (t < CH && q < ntot) {
       bool interior = q < npi;
       int k = interior ? pb + q : sb + (q - npi);
-#pragma unroll
-      for (int a = 0; a < D; ++a) x[a] = interior ? d.px[a * N + k] : d.ss[a * S + k];
       R f[D];
-      int lc[3];
+      int lc[3] = {0, 0, 0};
 #pragma unroll
       for (int a = 0; a < D; ++a) {
-        R xs = x[a] * d.fn;
+        R xs = (interior ? d.px[a * N + k] : d.ss[a * S + k]) * d.fn;
         R cf = floor(xs);
         f[a] = xs - cf;
-        lc[a] = (int)cf - (org[a] + 1);
-        lc[a] = lc[a] < 0 ? 0 : (lc[a] > TileGeo<D>::E - 1 ? TileGeo<D>::E - 1 : lc[a]);   // clamped points only
+        int l = (int)cf - org[a];
+        lc[a] = l < 0 ? 0 : (l > TileGeo<D>::E - 1 ? TileGeo<D>::E - 1 : l);   // clamped points only
       }
-      // gradient of u at the point from the staged region (nodes lc + k in region coords)
-      R G[D][D];
-#pragma unroll
-      for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int b = 0; b < D; ++b) G[a][b] = 0;
-      for_stencil<D>([&](int k0, int k1, int k2) {
-        int kk[3] = {k0, k1, k2};
-        R g[D];
-        weight_from_cell<D, R>(kk, f, d.fn, g);
-        int rr[3] = {lc[0] + k0, lc[1] + k1, D == 3 ? lc[2] + k2 : 0};
-        int rn = region_index<D>(rr);
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-          R ua = sm.u[rn * D + a];
-#pragma unroll
-          for (int b = 0; b < D; ++b) G[a][b] += ua * g[b];
-        }
-      });
+      R w[D][3], dw[D][3];
+      weight_table<D, R>(f, d.fn, w, dw);
+      R G[D][D], val[D];
+      region_grad<D, R, D>(sm.u, lc, w, dw, G, val);
       R Sq[D][D];
 #pragma unroll
       for (int a = 0; a < D; ++a)
@@ -405,50 +489,47 @@ __global__ void __launch_bounds__(TileGeo<D>::NT) k_tile_stress(Dev<R> d, TileLi
 #pragma unroll
           for (int b = 0; b < D; ++b) Sq[a][b] = sc * Q[a][b];
       }
+      R* P = &sm.pt[t * PW];
 #pragma unroll
-      for (int a = 0; a < D; ++a) {
-        sm.pf[t * D + a] = f[a];
+      for (int a = 0; a < D; ++a)
 #pragma unroll
-        for (int b = 0; b < D; ++b) sm.pS[(t * D + a) * D + b] = Sq[a][b];
-      }
+        for (int kk = 0; kk < 3; ++kk) { P[a * 3 + kk] = w[a][kk]; P[3 * D + a * 3 + kk] = dw[a][kk]; }
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = 0; b < D; ++b) P[6 * D + a * D + b] = Sq[a][b];
     }
     __syncthreads();
     // ---- scatter phase: the lane's cell points inside this chunk ----
     if (lane_on) {
-      int lo = q0, hi = min(q0 + NT, ntot);
+      int lo = q0, hi = min(q0 + CH, ntot);
       for (int pass = 0; pass < 2; ++pass) {
-        int b0 = pass == 0 ? cpb : csb, b1 = pass == 0 ? cpe : cse;
-        b0 = max(b0, lo);
-        b1 = min(b1, hi);
+        int b0 = max(pass == 0 ? cpb : csb, lo), b1 = min(pass == 0 ? cpe : cse, hi);
         for (int qq = b0; qq < b1; ++qq) {
-          int sl = qq - q0;
-          R f[D];
-#pragma unroll
-          for (int a = 0; a < D; ++a) f[a] = sm.pf[sl * D + a];
+          const R* P = &sm.pt[(qq - q0) * PW];
+          R wn[3], gn[3][D];
+          lane_nodes<D, R>(P, P + 3 * D, lk0, lk1, wn, gn);
           R Sq[D][D];
 #pragma unroll
           for (int a = 0; a < D; ++a)
 #pragma unroll
-            for (int b = 0; b < D; ++b) Sq[a][b] = sm.pS[(sl * D + a) * D + b];
+            for (int b = 0; b < D; ++b) Sq[a][b] = P[6 * D + a * D + b];
 #pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            R g[D];
-            lane_weight<D, R>(f, lk0, lk1, k, d.fn, g);
+          for (int kk = 0; kk < 3; ++kk)
 #pragma unroll
             for (int a = 0; a < D; ++a) {
-              R s = 0;
+              R s = acc.v[kk][a];
 #pragma unroll
-              for (int b = 0; b < D; ++b) s += Sq[a][b] * g[b];
-              acc.v[k][a] += s;
+              for (int b = 0; b < D; ++b) s += Sq[a][b] * gn[kk][b];
+              acc.v[kk][a] = s;
             }
-          }
         }
       }
     }
     __syncthreads();
   }
   // ---- reduce onto the region and write the tile partial ----
-  R* reg = reinterpret_cast<R*>(sm.pS);        // reuse (RN * D <= NT * D * D)
+  R* reg = sm.pt;        // RN * D <= CH * PW
   reduce_cells_to_region<D, R, D, D>(acc, 0, sm.cellpart, reg, lcell, lk0, lk1, lane_on);
   R* dst = tpart + (size_t)blockIdx.x * RN * D;
   for (int i = t; i < RN * D; i += NT) dst[i] = reg[i];
@@ -484,16 +565,16 @@ __global__ void k_surface_F(Dev<R> d, const R* vlin) {
 template <int D, typename R>
 struct HeatLds {
   static constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
+  static constexpr int PW = 6 * D + 1 + D;    // w, dw tables + c + q
   R u[RN];
-  R pf[NT * D];
-  R pq[NT * (D + 1)];
+  R pt[NT * PW];
   R cellpart[64 * 27];
 };
 
 template <int D, typename R>
-__global__ void __launch_bounds__(TileGeo<D>::NT) k_tile_heat(Dev<R> d, TileLists tl, const R* T, R* tpart,
+__global__ void MPM_TILE_KERNEL(TileGeo<D>::NT) k_tile_heat(Dev<R> d, TileLists tl, const R* T, R* tpart,
                                                               const int* done) {
-  constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
+  constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN, PW = HeatLds<D, R>::PW;
   __shared__ HeatLds<D, R> sm;
   if (done && *done) return;
   const int ct = tl.ctile_list[blockIdx.x];
@@ -501,8 +582,6 @@ __global__ void __launch_bounds__(TileGeo<D>::NT) k_tile_heat(Dev<R> d, TileList
   const int t = threadIdx.x;
   int org[3] = {0, 0, 0};
   tiled_coords<D>(ct, 0, d.nt, org);
-#pragma unroll
-  for (int a = 0; a < D; ++a) org[a] -= 1;
   for (int rn = t; rn < RN; rn += NT) {
     int r[3];
     region_coords<D>(rn, r);
@@ -510,8 +589,9 @@ __global__ void __launch_bounds__(TileGeo<D>::NT) k_tile_heat(Dev<R> d, TileList
     sm.u[rn] = gnode >= 0 ? T[gnode] : R(0);
   }
   const int cb = ct * 64;
-  const int pb = d.p_start[cb], pe = d.p_start[cb + 64];
-  const int sb = S ? d.s_start[cb] : 0, se = S ? d.s_start[cb + 64] : 0;
+  const int* rg = tl.ctile_rng + 6 * blockIdx.x;
+  const int pb = rg[0], pe = rg[1];
+  const int sb = S ? rg[2] : 0, se = S ? rg[3] : 0;
   const int npi = pe - pb, ntot = npi + (se - sb);
   int lcell, lk0, lk1;
   lane_map<D>(t, lcell, lk0, lk1);
@@ -529,44 +609,37 @@ __global__ void __launch_bounds__(TileGeo<D>::NT) k_tile_heat(Dev<R> d, TileList
     if (q < ntot) {
       bool interior = q < npi;
       int k = interior ? pb + q : sb + (q - npi);
-      R x[D], f[D];
+      R f[D];
       int lc[3] = {0, 0, 0};
 #pragma unroll
       for (int a = 0; a < D; ++a) {
-        x[a] = interior ? d.px[a * N + k] : d.ss[a * S + k];
-        R xs = x[a] * d.fn;
+        R xs = (interior ? d.px[a * N + k] : d.ss[a * S + k]) * d.fn;
         R cf = floor(xs);
         f[a] = xs - cf;
-        lc[a] = (int)cf - (org[a] + 1);
-        lc[a] = lc[a] < 0 ? 0 : (lc[a] > TileGeo<D>::E - 1 ? TileGeo<D>::E - 1 : lc[a]);
+        int l = (int)cf - org[a];
+        lc[a] = l < 0 ? 0 : (l > TileGeo<D>::E - 1 ? TileGeo<D>::E - 1 : l);
       }
-      R gT[D], Tq = 0;
+      R w[D][3], dw[D][3];
+      weight_table<D, R>(f, d.fn, w, dw);
+      R G[1][D], val[1];
+      region_grad<D, R, 1>(sm.u, lc, w, dw, G, val);
+      R* P = &sm.pt[t * PW];
 #pragma unroll
-      for (int a = 0; a < D; ++a) gT[a] = 0;
-      for_stencil<D>([&](int k0, int k1, int k2) {
-        int kk[3] = {k0, k1, k2};
-        R g[D];
-        R w = weight_from_cell<D, R>(kk, f, d.fn, g);
-        int rr[3] = {lc[0] + k0, lc[1] + k1, D == 3 ? lc[2] + k2 : 0};
-        R Tj = sm.u[region_index<D>(rr)];
-        Tq += w * Tj;
+      for (int a = 0; a < D; ++a)
 #pragma unroll
-        for (int a = 0; a < D; ++a) gT[a] += Tj * g[a];
-      });
-#pragma unroll
-      for (int a = 0; a < D; ++a) sm.pf[t * D + a] = f[a];
+        for (int kk = 0; kk < 3; ++kk) { P[a * 3 + kk] = w[a][kk]; P[3 * D + a * 3 + kk] = dw[a][kk]; }
       if (interior) {
         R c = d.K * d.pVn[k];
-        sm.pq[t * (D + 1)] = 0;
+        P[6 * D] = 0;
 #pragma unroll
-        for (int a = 0; a < D; ++a) sm.pq[t * (D + 1) + 1 + a] = c * gT[a];
+        for (int a = 0; a < D; ++a) P[6 * D + 1 + a] = c * G[0][a];
       } else {
         R area = 0;
 #pragma unroll
         for (int a = 0; a < D; ++a) area += d.sdA[a * S + k] * d.sdA[a * S + k];
-        sm.pq[t * (D + 1)] = d.h * sqrt(area) * Tq;
+        P[6 * D] = d.h * sqrt(area) * val[0];
 #pragma unroll
-        for (int a = 0; a < D; ++a) sm.pq[t * (D + 1) + 1 + a] = 0;
+        for (int a = 0; a < D; ++a) P[6 * D + 1 + a] = 0;
       }
     }
     __syncthreads();
@@ -575,29 +648,23 @@ __global__ void __launch_bounds__(TileGeo<D>::NT) k_tile_heat(Dev<R> d, TileList
       for (int pass = 0; pass < 2; ++pass) {
         int b0 = max(pass == 0 ? cpb : csb, lo), b1 = min(pass == 0 ? cpe : cse, hi);
         for (int qq = b0; qq < b1; ++qq) {
-          int sl = qq - q0;
-          R f[D];
+          const R* P = &sm.pt[(qq - q0) * PW];
+          R wn[3], gn[3][D];
+          lane_nodes<D, R>(P, P + 3 * D, lk0, lk1, wn, gn);
+          R c = P[6 * D];
 #pragma unroll
-          for (int a = 0; a < D; ++a) f[a] = sm.pf[sl * D + a];
-          R c = sm.pq[sl * (D + 1)];
-          R qv[D];
+          for (int kk = 0; kk < 3; ++kk) {
+            R s = c * wn[kk];
 #pragma unroll
-          for (int a = 0; a < D; ++a) qv[a] = sm.pq[sl * (D + 1) + 1 + a];
-#pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            R g[D];
-            R w = lane_weight<D, R>(f, lk0, lk1, k, d.fn, g);
-            R s = c * w;
-#pragma unroll
-            for (int a = 0; a < D; ++a) s += qv[a] * g[a];
-            acc.v[k][0] += s;
+            for (int a = 0; a < D; ++a) s += P[6 * D + 1 + a] * gn[kk][a];
+            acc.v[kk][0] += s;
           }
         }
       }
     }
     __syncthreads();
   }
-  R* reg = sm.pf;   // RN <= NT * D
+  R* reg = sm.pt;   // RN <= NT * PW
   reduce_cells_to_region<D, R, 1, 1>(acc, 0, sm.cellpart, reg, lcell, lk0, lk1, lane_on);
   R* dst = tpart + (size_t)blockIdx.x * RN;
   for (int i = t; i < RN; i += NT) dst[i] = reg[i];
@@ -777,6 +844,158 @@ __global__ void __launch_bounds__(TileGeo<D>::NT) k_tile_p2g(Dev<R> d, TileLists
 }
 
 // ======================================================================================
+// G2P with merge (Section 5), one workgroup per cell tile: v^ (and T^) staged on the
+// tile's node region, one lane per interior particle, stencil sums by sum factorization.
+// The particle's own share is m~ [v(x_p), sum_i N_i v^_i (x_i - x_p)^T]; the split members'
+// shares come from k_g2p_split.  The state is written back in cell order.
+// ======================================================================================
+// sum_k N_k u_a (k_b) over the 3^D stencil: first moments of the staged field, from which
+// sum_i N_i u_a (x_i - x_p)_b = dx [mom_ab - (f_b + 1/2) val_a] (x_i - x_p = (k - 1/2 - f) dx).
+template <int D, typename R, int NC>
+MPM_DEV void region_moments(const R* u, const int* lc, const R (&w)[D][3], R (&val)[NC], R (&mom)[NC][D]) {
+  constexpr int RE = TileGeo<D>::RE;
+#pragma unroll
+  for (int a = 0; a < NC; ++a) {
+    val[a] = 0;
+#pragma unroll
+    for (int b = 0; b < D; ++b) mom[a][b] = 0;
+  }
+  if constexpr (D == 3) {
+#pragma unroll
+    for (int k2 = 0; k2 < 3; ++k2) {
+      R V[NC], M0[NC], M1[NC];
+#pragma unroll
+      for (int a = 0; a < NC; ++a) { V[a] = 0; M0[a] = 0; M1[a] = 0; }
+#pragma unroll
+      for (int k1 = 0; k1 < 3; ++k1) {
+        int base = lc[0] + RE * ((lc[1] + k1) + RE * (lc[2] + k2));
+#pragma unroll
+        for (int a = 0; a < NC; ++a) {
+          R u0 = u[(base + 0) * NC + a], u1 = u[(base + 1) * NC + a], u2 = u[(base + 2) * NC + a];
+          R s = u0 * w[0][0] + u1 * w[0][1] + u2 * w[0][2];
+          R s1 = u1 * w[0][1] + R(2) * u2 * w[0][2];          // sum_k0 u w0 k0
+          V[a] += s * w[1][k1];
+          M0[a] += s1 * w[1][k1];
+          M1[a] += s * w[1][k1] * R(k1);
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < NC; ++a) {
+        val[a] += V[a] * w[2][k2];
+        mom[a][0] += M0[a] * w[2][k2];
+        mom[a][1] += M1[a] * w[2][k2];
+        mom[a][2] += V[a] * w[2][k2] * R(k2);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) {
+      int base = lc[0] + RE * (lc[1] + k1);
+#pragma unroll
+      for (int a = 0; a < NC; ++a) {
+        R u0 = u[(base + 0) * NC + a], u1 = u[(base + 1) * NC + a], u2 = u[(base + 2) * NC + a];
+        R s = u0 * w[0][0] + u1 * w[0][1] + u2 * w[0][2];
+        R s1 = u1 * w[0][1] + R(2) * u2 * w[0][2];
+        val[a] += s * w[1][k1];
+        mom[a][0] += s1 * w[1][k1];
+        mom[a][1] += s * w[1][k1] * R(k1);
+      }
+    }
+  }
+}
+
+template <int D, typename R>
+struct G2PLds {
+  static constexpr int RN = TileGeo<D>::RN;
+  R u[RN * D];
+  R T[RN];
+};
+
+template <int D, typename R>
+__global__ void __launch_bounds__(256) k_tile_g2p(Dev<R> d, TileLists tl, const R* vh, const R* Th, R* x, R* v,
+                                                  R* A, R* J, R* V0, R* m, R* T, R* gT) {
+  constexpr int NT = 256, RN = TileGeo<D>::RN;
+  __shared__ G2PLds<D, R> sm;
+  const int ct = tl.ctile_list[blockIdx.x];
+  const int* rg = tl.ctile_rng + 6 * blockIdx.x;
+  const int pb = rg[0], pe = rg[1];
+  const int N = d.np, S = d.ns, nn = d.nn;
+  const int t = threadIdx.x;
+  int org[3] = {0, 0, 0};
+  tiled_coords<D>(ct, 0, d.nt, org);
+  for (int rn = t; rn < RN; rn += NT) {
+    int r[3];
+    region_coords<D>(rn, r);
+    int gnode = region_node_global<D>(ct, r, d.n, d.nt);
+#pragma unroll
+    for (int a = 0; a < D; ++a) sm.u[rn * D + a] = gnode >= 0 ? vh[a * nn + gnode] : R(0);
+    sm.T[rn] = (gnode >= 0 && Th) ? Th[gnode] : R(0);
+  }
+  __syncthreads();
+  for (int k = pb + t; k < pe; k += NT) {
+    R xp[D], f[D];
+    int lc[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      xp[a] = d.px[a * N + k];
+      R xs = xp[a] * d.fn;
+      R cf = floor(xs);
+      f[a] = xs - cf;
+      int l = (int)cf - org[a];
+      lc[a] = l < 0 ? 0 : (l > TileGeo<D>::E - 1 ? TileGeo<D>::E - 1 : l);
+    }
+    R w[D][3], dw[D][3];
+    weight_table<D, R>(f, d.fn, w, dw);
+    R G[D][D], val[D], mom[D][D];
+    region_grad<D, R, D>(sm.u, lc, w, dw, G, val);
+    region_moments<D, R, D>(sm.u, lc, w, val, mom);
+    R div = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) div += G[a][a];
+    const R mt = d.pmt[k], mp = d.pm[k];
+    R mo[D], tt[D][D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      mo[a] = mt * val[a];
+#pragma unroll
+      for (int b = 0; b < D; ++b) tt[a][b] = mt * d.dx * (mom[a][b] - (f[b] + R(0.5)) * val[a]);
+    }
+    for (int j = d.grp_start[k]; j < d.grp_start[k + 1]; ++j) {
+      int r = d.grp[j];
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        mo[a] += mt * d.sc[a * S + r];
+#pragma unroll
+        for (int b = 0; b < D; ++b) tt[a][b] += mt * d.sc[(D + a * D + b) * S + r];
+      }
+    }
+    const R inv_m = R(1) / mp, cA = R(4) / (mp * d.dx * d.dx);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      R va = mo[a] * inv_m;
+      v[a * N + k] = va;
+      x[a * N + k] = xp[a] + d.dt * va;
+#pragma unroll
+      for (int b = 0; b < D; ++b) A[(a * D + b) * N + k] = cA * tt[a][b];
+    }
+    J[k] = (R(1) + d.dt * div) * d.pJ[k];
+    V0[k] = d.pV0[k];
+    m[k] = mp;
+    if (Th) {
+      R GT[1][D], vT[1];
+      region_grad<D, R, 1>(sm.T, lc, w, dw, GT, vT);
+      T[k] = vT[0];
+#pragma unroll
+      for (int a = 0; a < D; ++a) gT[a * N + k] = GT[0][a];
+    } else {
+      T[k] = d.pT[k];
+#pragma unroll
+      for (int a = 0; a < D; ++a) gT[a * N + k] = d.pgT[a * N + k];
+    }
+  }
+}
+
+// ======================================================================================
 // Merge: for every node of the active node tiles, sum the region partials of the <= 2^d
 // cell tiles that cover it (fixed order: cell tiles in lexicographic order).
 // ======================================================================================
@@ -820,11 +1039,16 @@ MPM_DEV void merge_sources(int node_tile, int local, int nt, const int* ctile_sl
       }
 }
 
-// Stress merge: NM_GRAD / NM_HESS node-level terms as in the node phase.
+// Stress merge: node-level terms.
+//  NM_GRAD: out = P[acc + m (v^ - v^n) - dt m g]; the last block adds the tile energy
+//           partials (epart, nep entries) and the node terms into Phi (*phi, *phi2).
+//  NM_HESS: out = P[acc + alpha m w]; with cg the last block sets the CG step length from
+//           the sum of w . out.
 template <int D, typename R>
 __global__ void __launch_bounds__(64) k_merge_stress(Dev<R> d, TileLists tl, const R* tpart, const R* u, R* out,
                                                      int mode, double alpha, int mask_in, const int* done,
-                                                     int part_slot, int dot_slot) {
+                                                     const double* epart, int nep, double* npart, unsigned* ctr,
+                                                     double* phi, double* phi2, CgScal* cg) {
   constexpr int RN = TileGeo<D>::RN;
   __shared__ double sh[16];
   if (done && *done) return;
@@ -865,19 +1089,27 @@ __global__ void __launch_bounds__(64) k_merge_stress(Dev<R> d, TileLists tl, con
     o = fa ? o : R(0);
     out[a * nn + node] = o;
   }
-  if (mode == NM_GRAD && part_slot >= 0) {
-    double bs = block_sum(e, sh);
-    if (threadIdx.x == 0) d.part[part_slot * kPartSlot + blockIdx.x] = bs;
-  }
-  if (mode == NM_HESS && dot_slot >= 0) {
-    double bs = block_sum(dotv, sh);
-    if (threadIdx.x == 0) d.part[dot_slot * kPartSlot + blockIdx.x] = bs;
+  const bool want = (mode == NM_GRAD && phi) || (mode == NM_HESS && cg);
+  if (!want) return;
+  double bs = block_sum(mode == NM_GRAD ? e : dotv, sh);
+  if (threadIdx.x == 0) publish(npart + blockIdx.x, bs);
+  if (grid_last_block(ctr)) {
+    double tot = block_sum_array(npart, gridDim.x, sh);
+    if (mode == NM_GRAD) {
+      double te = epart ? block_sum_array(epart, nep, sh) : 0.0;
+      if (threadIdx.x == 0) {
+        *phi = te + tot;
+        if (phi2) *phi2 = te + tot;
+      }
+    } else if (threadIdx.x == 0) {
+      cg_set_alpha(cg, tot);
+    }
   }
 }
 
 template <int D, typename R>
 __global__ void __launch_bounds__(64) k_merge_heat(Dev<R> d, TileLists tl, const R* tpart, const R* T, R* out,
-                                                   const int* done, int dot_slot) {
+                                                   const int* done, double* npart, unsigned* ctr, CgScal* cg) {
   constexpr int RN = TileGeo<D>::RN;
   __shared__ double sh[16];
   if (done && *done) return;
@@ -892,9 +1124,12 @@ __global__ void __launch_bounds__(64) k_merge_heat(Dev<R> d, TileLists tl, const
   R Ti = T[node];
   R o = dof ? d.cp / d.dt * d.gm[node] * Ti + acc : R(0);
   out[node] = o;
-  if (dot_slot >= 0) {
-    double bs = block_sum(dof ? (double)Ti * (double)o : 0.0, sh);
-    if (threadIdx.x == 0) d.part[dot_slot * kPartSlot + blockIdx.x] = bs;
+  if (!cg) return;
+  double bs = block_sum(dof ? (double)Ti * (double)o : 0.0, sh);
+  if (threadIdx.x == 0) publish(npart + blockIdx.x, bs);
+  if (grid_last_block(ctr)) {
+    double tot = block_sum_array(npart, gridDim.x, sh);
+    if (threadIdx.x == 0) cg_set_alpha(cg, tot);
   }
 }
 
@@ -960,11 +1195,21 @@ __global__ void k_flag_ctiles(Dev<R> d, int* flag, int ntile) {
   flag[t] = cnt > 0;
 }
 
-__global__ void k_ctile_slots(const int* flag, const int* pos, int ntile, int* list, int* slot) {
+template <typename R>
+__global__ void k_ctile_slots(Dev<R> d, const int* flag, const int* pos, int ntile, int* list, int* slot, int* rng) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= ntile) return;
-  if (flag[t]) { list[pos[t]] = t; slot[t] = pos[t]; }
-  else slot[t] = -1;
+  if (flag[t]) {
+    int s = pos[t], cb = t * 64;
+    list[s] = t;
+    slot[t] = s;
+    int* r = rng + 6 * s;
+    r[0] = d.p_start[cb]; r[1] = d.p_start[cb + 64];
+    r[2] = d.ns ? d.s_start[cb] : 0; r[3] = d.ns ? d.s_start[cb + 64] : 0;
+    r[4] = d.ns ? d.b_start[cb] : 0; r[5] = d.ns ? d.b_start[cb + 64] : 0;
+  } else {
+    slot[t] = -1;
+  }
 }
 
 }  // namespace mpm

@@ -151,11 +151,18 @@ def test_g2p_parity(kind, dim, seed, precision):
         Th = Th.astype(np.float32).astype(np.float64)
     ref = transfer_g2p(o, vh, Th)
     g.scene.g2p(g.from_natural(vh), g.from_natural(Th), g.Pd)
+    from paper_2101_12408_amd import _lib as L
+    perm = g.scene.view(L.F_PERM).cpu().numpy()
     N = len(P["m"])
     d = dim
+    # the library writes particles back in cell order: slot j holds input particle perm[j]
     got = dict(x=g.Pd["x"].cpu().numpy().T, v=g.Pd["v"].cpu().numpy().T,
                A=g.Pd["A"].cpu().numpy().T.reshape(N, d, d), J=g.Pd["J"].cpu().numpy(),
                T=g.Pd["T"].cpu().numpy(), gradT=g.Pd["gradT"].cpu().numpy().T)
+    assert np.array_equal(np.sort(perm), np.arange(N))
+    assert np.array_equal(g.Pd["m"].cpu().numpy(), P["m"][perm].astype(g.Pd["m"].cpu().numpy().dtype))
+    ref = {k: v[perm] for k, v in ref.items() if isinstance(v, np.ndarray) and len(v) == N}
+    P = {k: v[perm] for k, v in P.items()}
     tol = TOL_FP64 if precision == "fp64" else 1e-4
     for k in ("v", "A", "J", "T", "gradT", "x"):
         if k == "x" and precision == "fp64":

@@ -21,10 +21,15 @@ def _gpu_step(P, surf, p, precision="fp64", implicit=True):
     Pd, Sd = s.to_device(P, surf)
     rc = s.step(Pd, Sd, implicit=implicit, check=False)
     N, d = len(P["m"]), p["dim"]
-    out = dict(x=Pd["x"].cpu().numpy().T.astype(np.float64), v=Pd["v"].cpu().numpy().T.astype(np.float64),
-               A=Pd["A"].cpu().numpy().T.reshape(N, d, d).astype(np.float64),
-               J=Pd["J"].cpu().numpy().astype(np.float64), T=Pd["T"].cpu().numpy().astype(np.float64),
-               gradT=Pd["gradT"].cpu().numpy().T.astype(np.float64), m=P["m"], V0=P["V0"])
+    from paper_2101_12408_amd import _lib as L
+    perm = s.view(L.F_PERM).cpu().numpy()
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(N)           # back to input order for the comparison
+    out = dict(x=Pd["x"].cpu().numpy().T.astype(np.float64)[inv], v=Pd["v"].cpu().numpy().T.astype(np.float64)[inv],
+               A=Pd["A"].cpu().numpy().T.reshape(N, d, d).astype(np.float64)[inv],
+               J=Pd["J"].cpu().numpy().astype(np.float64)[inv], T=Pd["T"].cpu().numpy().astype(np.float64)[inv],
+               gradT=Pd["gradT"].cpu().numpy().T.astype(np.float64)[inv], m=P["m"], V0=P["V0"])
+    assert np.array_equal(Pd["m"].cpu().numpy().astype(np.float64)[inv], P["m"].astype(Pd["m"].cpu().numpy().dtype))
     return out, s.stats(), rc
 
 
@@ -100,7 +105,7 @@ def test_explicit_steps_conserve_on_gpu():
         surf = api.sample_surface(xh, p, step=k)
         Sd = s.to_device(S=surf)
         s.step(Pd, Sd, implicit=False)
-        Q = dict(m=P["m"], x=Pd["x"].cpu().numpy().T, v=Pd["v"].cpu().numpy().T,
+        Q = dict(m=Pd["m"].cpu().numpy(), x=Pd["x"].cpu().numpy().T, v=Pd["v"].cpu().numpy().T,
                  A=Pd["A"].cpu().numpy().T.reshape(-1, 2, 2))
         hist.append(_momenta(Q, p["dx"]))
     scale = np.abs(P["m"][:, None] * Q["v"]).sum()
@@ -125,7 +130,7 @@ def test_implicit_momentum_fix_conserves():
         surf = api.sample_surface(Pd["x"].cpu().numpy().T.copy(), p, step=k)
         s.step(Pd, s.to_device(S=surf), implicit=True)
     v = Pd["v"].cpu().numpy().T
-    mom = (P["m"][:, None] * v).sum(0)
+    mom = (Pd["m"].cpu().numpy()[:, None] * v).sum(0)
     log(f"  momentum {mom0} -> {mom}")
     assert np.allclose(mom, mom0, rtol=0, atol=1e-14 * np.abs(P["m"][:, None] * v).sum())
 
