@@ -27,9 +27,6 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0
-FP32_PEAK_TFLOPS = 157.3
-FP64_PEAK_TFLOPS = 78.6
 
 
 def log(msg):
@@ -84,7 +81,22 @@ def run_gpu(scene_fn, precision, steps, warmup, want_timing):
     return dict(N=N, elapsed=elapsed, stats=stats, timing=timing, S=len(surf0["s"]), params=p)
 
 
-def cpu_baseline(max_seconds=60.0):
+def cpu_baseline():
+    """Runs the oracle timing in a child process pinned to one BLAS/OpenMP thread, so the
+    reported core count is the number of threads actually used."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
+               HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
+    code = "import json, bench; print(json.dumps(bench._cpu_baseline_inproc()))"
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True,
+                       timeout=600)
+    if r.returncode != 0:
+        log(f"cpu baseline failed: {r.stderr[-500:]}")
+        return None
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def _cpu_baseline_inproc():
     """The oracle, timed on the host on a bounded sample: one full implicit step of the
     same Marangoni scene at the same grid (128^3), particle density and parameters, with
     a droplet of radius 0.1 instead of 0.2 (1/8 of the particles)."""
@@ -103,45 +115,107 @@ def cpu_baseline(max_seconds=60.0):
                        f"cg {info['cg']}, heat cg {info.get('heat_cg')}): {dt:.1f} s single-threaded numpy")
 
 
-# Algorithmic traffic and arithmetic per launch of each timed kernel class (MIXED: 4-byte
-# reals).  N interior particles, S surface samples, G nodes of the active tiles.
-def algorithmic(cls, N, S, G, dim=3):
-    R = 4
-    d2 = dim * dim
-    if cls == "hess_int":      # read x, V0, J (+mu V), w at the stencil nodes; write S_p
-        return dict(bytes=N * (dim + 2) * R + N * d2 * R, flops=N * 420)
-    if cls == "hess_node":     # read S_p and x of every point, w, m, mask; write out
-        return dict(bytes=N * (dim + d2) * R + S * (dim + d2) * R + G * (2 * dim + 1) * R + G, flops=(N + S) * 27 * 24)
-    if cls == "energy_int":
-        return dict(bytes=N * (dim + 2) * R + N * d2 * R, flops=N * 440)
-    if cls == "energy_node":
-        return dict(bytes=N * (dim + d2) * R + S * (dim + d2) * R + G * (3 * dim + 1) * R + G, flops=(N + S) * 27 * 24)
-    if cls == "p2g":           # read the particle state once; write the grid fields
-        return dict(bytes=N * (dim + dim + d2 + 8) * R + 2 * S * (dim + 1) * R + S * dim * R + G * 17 * R + G,
-                    flops=(N + 2 * S) * 27 * 40)
-    if cls == "g2p":           # read x, J, m, m~, v^ stencil; write v, A, T, grad T, J, x
-        return dict(bytes=N * (dim + 3) * R + N * (dim + d2 + 1 + dim + 1 + dim) * R + G * (dim + 1) * R,
-                    flops=N * 27 * 30)
+# Algorithmic bytes and flops per launch of each timed kernel class: the minimum the
+# method moves (each needed particle field read once, each output written once, each
+# active node's fields read or written once), R bytes per real (4 in MIXED, 8 in FP64),
+# 4 per int32.  N interior particles, S surface samples (each with its balance point),
+# G nodes of the active tiles.  Flop counts are per-point estimates of the arithmetic
+# of the method (not of this implementation).
+def algorithmic(cls, N, S, G, R, dim=3):
+    d, d2, I = dim, dim * dim, 4
+    if cls == "p2g":           # read x v A m T gradT + group count; s + parent; write m mv W WT E ET
+        return dict(bytes=N * ((3 * d + d2 + 2) * R + I) + S * (d * R + I) + G * (d + 5) * R,
+                    flops=(N + 2 * S) * 700)
+    if cls == "energy_int":    # read x J V0 muV, s dA k, v^ at the nodes; energy partials
+        return dict(bytes=N * (d + 3) * R + S * (2 * d + 1) * R + G * d * R, flops=N * 500 + S * 1500)
+    if cls == "hess_int":      # read x cJ muV, s dA k + cached F (d^2), w at the nodes
+        return dict(bytes=N * (d + 2) * R + S * (2 * d + 1 + d2) * R + G * d * R, flops=N * 450 + S * 1500)
+    if cls in ("energy_node", "hess_node"):   # read w/v^, v^n, m, flags; write out
+        return dict(bytes=G * ((2 * d + 1) * R + 1 + d * R), flops=G * 8 * d)
+    if cls == "heat_pt":       # read x KV, s h|dA|, T at the nodes
+        return dict(bytes=N * (d + 1) * R + S * (d + 1) * R + G * R, flops=(N + S) * 400)
     if cls == "heat_node":
-        return dict(bytes=(N + S) * (dim + dim) * R + G * 4 * R, flops=(N + S) * 27 * 12)
-    if cls == "heat_pt":
-        return dict(bytes=N * (dim + 1 + dim) * R + S * (2 * dim + 1) * R, flops=(N + S) * 27 * 10)
+        return dict(bytes=G * (3 * R + 1), flops=G * 4)
+    if cls == "g2p":           # read x J count, s + parent, v^ T^; write v A T gradT x J
+        return dict(bytes=N * ((d + 1) * R + I) + N * (d + d2 + 1 + d + d + 1) * R + S * (d * R + I) + G * (d + 1) * R,
+                    flops=N * 750)
     return None
+
+
+HBM_PEAK = 8000.0      # GB/s
+VALU_PEAK = {4: 157.3, 8: 78.6}   # TFLOP/s, vector FP32 / FP64
+
+
+def roofline_of(cls, tm, N, S, G, R, K, traffic):
+    ms, launches = tm[cls]
+    avg_s = ms / launches * 1e-3
+    alg = algorithmic(cls, N, S, G, R)
+    gbs = alg["bytes"] / avg_s / 1e9
+    tfl = alg["flops"] / avg_s / 1e12
+    t_hbm = alg["bytes"] / (HBM_PEAK * 1e9)
+    t_alu = alg["flops"] / (VALU_PEAK[R] * 1e12)
+    common = dict(kernel=cls, avg_launch_us=round(avg_s * 1e6, 2), launches_per_step=round(launches / K, 2),
+                  alg_bytes=int(alg["bytes"]), alg_flops=int(alg["flops"]),
+                  hbm_frac=round(gbs / HBM_PEAK, 4), valu_frac=round(tfl / VALU_PEAK[R], 4))
+    if t_hbm >= t_alu:
+        r = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK, unit="GB/s", frac=round(gbs / HBM_PEAK, 4))
+    else:
+        r = dict(bound="alu", achieved=round(tfl, 3), peak=VALU_PEAK[R], unit="TFLOP/s",
+                 frac=round(tfl / VALU_PEAK[R], 4))
+    r["traffic"] = traffic
+    r.update(common)
+    return r
+
+
+def kernel_sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("common.h", "kernels.h", "tiles.h", "mpm.hip"):
+        with open(os.path.join(ROOT, "paper_2101_12408_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(cls, precision):
+    """HBM bytes per launch from the committed PMC summary, if it was taken on the current
+    kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    e = t.get(f"{cls}:{precision}")
+    if not e or e.get("sources") != kernel_sources_digest():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def copy_calibration(mib=512, reps=5):
+    """A plain device copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    a = torch.empty(mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copy calibration: {reps} copies of {mib} MiB")
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--fp64-steps", type=int, default=3, help="steps of the FP64 GPU comparison run (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 512 MiB device copy (PMC traffic calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md for how the "
-              "step would shard); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path; run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
@@ -149,6 +223,8 @@ def main():
         sys.exit(2)
     import mpm_scenes as sc
     scene_fn = sc.marangoni3d
+    if args.copy_calibration:
+        copy_calibration()
     main_run = run_gpu(scene_fn, args.precision, args.steps, args.warmup, not args.no_timing)
     N, K = main_run["N"], args.steps
     value = N * K / main_run["elapsed"]
@@ -159,25 +235,16 @@ def main():
     S = int(np.mean([s["n_surf"] for s in st]))
     out_extra = {}
     roofline = None
+    R = 4 if args.precision == "mixed" else 8
     if main_run["timing"]:
         tm = main_run["timing"]
         total = sum(v[0] for v in tm.values())
-        breakdown = {k: round(v[0] / K, 4) for k, v in tm.items() if v[1]}
-        out_extra["kernel_ms_per_step"] = breakdown
-        cand = [k for k in tm if tm[k][1] and algorithmic(k, N, S, G)]
+        out_extra["kernel_ms_per_step"] = {k: round(v[0] / K, 4) for k, v in tm.items() if v[1]}
+        cand = [k for k in tm if tm[k][1] and algorithmic(k, N, S, G, R)]
         dom = max(cand, key=lambda k: tm[k][0])
-        avg_s = tm[dom][0] / tm[dom][1] * 1e-3
-        alg = algorithmic(dom, N, S, G)
-        gbs = alg["bytes"] / avg_s / 1e9
-        tfl = alg["flops"] / avg_s / 1e12
-        if gbs / HBM_PEAK_GBS >= tfl / FP32_PEAK_TFLOPS:
-            roofline = dict(kernel=dom, bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                            frac=round(gbs / HBM_PEAK_GBS, 4), traffic=None,
-                            avg_launch_us=round(avg_s * 1e6, 2), launches=tm[dom][1])
-        else:
-            roofline = dict(kernel=dom, bound="alu", achieved=round(tfl, 3), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
-                            frac=round(tfl / FP32_PEAK_TFLOPS, 4), traffic=None,
-                            avg_launch_us=round(avg_s * 1e6, 2), launches=tm[dom][1])
+        roofline = roofline_of(dom, tm, N, S, G, R, K, measured_traffic(dom, args.precision))
+        out_extra["kernel_rooflines"] = {k: {kk: roofline_of(k, tm, N, S, G, R, K, None)[kk]
+                                             for kk in ("avg_launch_us", "hbm_frac", "valu_frac")} for k in cand}
         out_extra["kernel_time_share"] = round(total / (main_run["elapsed"] * 1e3), 3)
     fp64 = None
     if args.fp64_steps > 0 and args.precision != "fp64":

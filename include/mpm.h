@@ -150,7 +150,7 @@ enum mpm_field {
 enum mpm_kernel_class {
   MPM_K_SORT = 0,        /* cell keys, scans, slot scatter, per-cell order              */
   MPM_K_SETUP = 1,       /* staging, parents, split, balance points, tiles, k_r         */
-  MPM_K_P2G = 2,         /* P2G node gather with the grid set-up                        */
+  MPM_K_P2G = 2,         /* P2G cell-tile scatter into per-tile partial fields          */
   MPM_K_ENERGY_INT = 3,  /* energy/gradient point phase, interior particles             */
   MPM_K_ENERGY_SURF = 4, /* energy/gradient point phase, surface samples                */
   MPM_K_ENERGY_NODE = 5, /* energy/gradient node phase                                  */
@@ -162,7 +162,7 @@ enum mpm_kernel_class {
   MPM_K_G2P_SPLIT = 11,  /* G2P moments of surface and balance points                   */
   MPM_K_G2P = 12,        /* G2P with merge and advection                                */
   MPM_K_BLAS = 13,       /* Krylov vector updates and dot products                      */
-  MPM_K_REDUCE = 14,     /* single-block final reductions and scalar updates            */
+  MPM_K_P2G_NODE = 14,   /* P2G node phase: partial merge and the grid set-up           */
   MPM_K_COUNT = 15
 };
 

@@ -19,6 +19,6 @@ of the n^d cell-centred grid has linear index i_0 + n*(i_1 + n*i_2) and position
   solve     Newton-CG momentum solve, implicit heat solve           (Sections 4.3.1-4.3.2)
   step      one full time step                                      (Section 4 list of steps)
 
-Readings of points the paper leaves open are listed in the design doc and cited per function.
+Where the paper leaves a point open, the function's docstring states the reading it takes.
 """
 from . import bspline, sampler, resample, transfer, energy, solve, step  # noqa: F401

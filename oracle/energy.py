@@ -3,8 +3,8 @@
 
 With y = x + dt v^ (x the unmoved node positions) the discrete potential is
     e(y) = sum_p lambda/2 (J_p(y) - 1)^2 V^0_p  +  sum_r k_r |J^_r F^_r^{-T} dA_r|
-where, in displacement form (reading R6, identical to the printed form because
-sum_i x_i (x) grad N_i = I),
+where, in displacement form (identical to the printed form in exact arithmetic because
+sum_i x_i (x) grad N_i = I, and four digits more accurate in FP32),
     J_p(y) = (1 + dt sum_i v^_i . grad N_i(x_p)) J^n_p,     F^_r = I + dt sum_i v^_i (x) grad N_i(s_r),
 and J^ F^^{-T} = cof(F^) (the cofactor matrix, det(F) F^{-T}).  The linear viscous force
 of eq. disc_force, -mu sum_p eps(v^; x_p) grad N_i(x_p) V^n_p with eps the symmetric
@@ -16,7 +16,7 @@ condition of
 whose gradient and Hessian (M + dt^2 d2e/dy2 + dt C) drive Newton's method.
 
 Surface term: f(G) = |cof(G) N| with N = dA_r.  Its first derivative (the force of
-eq. fe, evaluated at the surface sample s_r, reading R4) and second derivative are
+eq. fe, read as evaluated at the surface sample s_r, the quadrature point of e_sigma) and second derivative are
 written with the cross-product form of the cofactor (3D: column m of cof(G) is
 g_{m+1} x g_{m+2}) or the rotated normal (2D: |cof(G) N| = |G tau|, tau = (N_1, -N_0)).
 The second derivative splits into a positive semidefinite part Q1 (the change of the

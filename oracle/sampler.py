@@ -8,7 +8,7 @@ Steps, in the order the section gives them:
      square-root barycentric map), each carrying the area-weighted outward normal
      dA_r = n_t * area_t / count_t, so that sum |dA_r| equals the mesh area.
 
-Readings (listed in the design doc): phi is evaluated exactly at the grid nodes; the
+Choices where the section is silent: phi is evaluated exactly at the grid nodes; the
 isocontour is extracted by marching tetrahedra (six tets around each cube's main
 diagonal) in 3D and marching triangles (two per square) in 2D, which have no ambiguous
 cases; the per-triangle count is max(1, floor(rho_s * area + u)) with u uniform, and the

@@ -2,7 +2,7 @@
 
 Momentum (Section 4.3.1): backward Euler solved with Newton's method.  The paper names
 Newton's method and defers the linear algebra to earlier work, so the solver details are
-readings (R9): Jacobi-preconditioned CG on the projected Newton system, Armijo
+chosen here: Jacobi-preconditioned CG on the projected Newton system, Armijo
 backtracking on Phi (a trial is accepted when Phi does not exceed the Armijo bound by
 more than the round-off of Phi, 8 eps |Phi|, eps the unit round-off of the arithmetic:
 near convergence the Newton decrement falls below that round-off and the comparison
@@ -15,8 +15,8 @@ term and interior particles as quadrature points of the conduction term,
     [c_p/dt diag(m) + L + R] T^ = c_p/dt m o T^n + sum_r N_i(s_r)(h T_amb + b)|dA_r|
                                   + sum_p N_i(x_p) H V^n_p
     L_ij = sum_p K V^n_p grad N_i(x_p) . grad N_j(x_p),   R_ij = sum_r h |dA_r| N_i(s_r) N_j(s_r)
-over the nodes with mass (reading R3; the stray factor h on the source term is dropped,
-reading R2).  Solved with Jacobi-preconditioned CG from the initial guess T^n.
+over the nodes with mass (the heat mass is the momentum mass m_i, split mass included;
+the stray factor h printed on the source term is dropped).  Solved with Jacobi-preconditioned CG from the initial guess T^n.
 """
 from __future__ import annotations
 

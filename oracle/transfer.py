@@ -23,7 +23,7 @@ G2P with merge (Section 5): for every interior particle,
     v_p  = (1/m_p) sum_i p_ip
     t_p  = sum_i p_ip (x_i - x_p)^T,   A_p = 4 / (m_p dx^2) t_p
     T_p  = sum_i N_i(x_p) T^_i,   grad T_p = sum_i T^_i grad N_i(x_p)
-and (reading R8) J_p <- (1 + dt sum_i v^_i . grad N_i(x_p)) J_p, x_p <- x_p + dt v_p.
+and (not stated in the paper, read as the trace form at the solution) J_p <- (1 + dt sum_i v^_i . grad N_i(x_p)) J_p, x_p <- x_p + dt v_p.
 """
 from __future__ import annotations
 

@@ -73,7 +73,7 @@ EXPORTS = {
 }
 
 KERNEL_CLASSES = ["sort", "setup", "p2g", "energy_int", "energy_surf", "energy_node", "hess_int",
-                  "hess_surf", "hess_node", "heat_pt", "heat_node", "g2p_split", "g2p", "blas", "reduce"]
+                  "hess_surf", "hess_node", "heat_pt", "heat_node", "g2p_split", "g2p", "blas", "p2g_node"]
 
 _lib = None
 

@@ -172,34 +172,88 @@ MPM_DEV double block_sum(double v, double* sh) {
   return r;
 }
 
-// Deterministic grid reduction without a second launch.  Thread 0 of every block
-// publishes its partials with publish() (device-scope stores, written through to the
-// level shared by all XCDs), waits until its own stores are acknowledged and takes a
-// ticket; the block holding the last ticket reads all partials with device-scope loads
-// and sums them in index order, so the result does not depend on which block finishes
-// last.  No cache writeback or invalidate is issued: other blocks keep their L2 contents.
-// The counter returns to zero for the next use (kernel boundaries order the reuse).
+// ---- deterministic grid reduction without a second launch ----------------------------
+// Thread 0 of every block publishes its NV partials with device-scope stores (written
+// through to the level shared by all XCDs), waits until they are acknowledged and takes a
+// ticket of its group of kRedGroup blocks.  The last block of a group sums the group's
+// partials in index order, publishes the group sum and takes a ticket of the grid; the
+// last group sums the group sums in index order.  The result therefore does not depend
+// on which blocks finish first.  Same-address atomics serialize (tens of ns each across
+// XCDs), so two levels keep the serial chain at kRedGroup + groups tickets instead of one
+// per block; the counters sit on separate 128-byte lines.  No cache writeback or
+// invalidate is issued.  Counters return to zero for the next use.
+//   part: partial v of block b at part[v * kRedSlot + b], group sums at kRedGroupOff + g;
+//   ctr:  kCtrSite unsigned counters of this reduction site.
+constexpr int kRedSlot = 1 << 18;
+constexpr int kRedGroup = 64;
+constexpr int kRedGroupOff = 1 << 17;                  // max blocks of a reducing grid
+constexpr int kMaxRedGroups = kRedGroupOff / kRedGroup;
+constexpr int kCtrStride = 32;
+constexpr int kCtrSite = (1 + kMaxRedGroups) * kCtrStride;
+
 MPM_DEV void publish(double* p, double v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 
-MPM_DEV bool grid_last_block(unsigned* counter) {
-  __shared__ int last;
-  if (threadIdx.x == 0) {
-    __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    last = prev == gridDim.x - 1;
-    if (last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  __syncthreads();
-  return last != 0;
+MPM_DEV unsigned take_ticket(unsigned* c) {
+  __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wave's published stores are acknowledged
+  return __hip_atomic_fetch_add(c, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+
+MPM_DEV void reset_ticket(unsigned* c) { __hip_atomic_store(c, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 
 // Sum of part[0..nb) in fixed order by one block (result in thread 0); device-scope loads
 // see every block's published partial.
 MPM_DEV double block_sum_array(const double* part, int nb, double* sh) {
+  constexpr int U = 8;   // loads in flight per thread
   double v = 0;
-  for (int k = threadIdx.x; k < nb; k += blockDim.x)
-    v += __hip_atomic_load(part + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int k0 = threadIdx.x; k0 < nb; k0 += U * blockDim.x) {
+    double t[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      int k = k0 + u * blockDim.x;
+      t[u] = k < nb ? __hip_atomic_load(part + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) v += t[u];
+  }
   return block_sum(v, sh);
+}
+
+// vals: the block's NV sums (read in thread 0).  Returns true in the one block that holds
+// the grid sums, in out[0..NV) of thread 0.  Every thread of every block must call it.
+template <int NV>
+MPM_DEV bool grid_reduce(const double* vals, double* part, unsigned* ctr, double* sh, double* out) {
+  __shared__ int flag;
+  const int b = blockIdx.x, nb = gridDim.x;
+  const int g = b / kRedGroup, ng = (nb + kRedGroup - 1) / kRedGroup;
+  const int gsz = min(kRedGroup, nb - g * kRedGroup);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) publish(part + (size_t)v * kRedSlot + b, vals[v]);
+    unsigned* gc = ctr + (size_t)(1 + g) * kCtrStride;
+    bool last = take_ticket(gc) == (unsigned)(gsz - 1);
+    if (last) reset_ticket(gc);
+    flag = last;
+  }
+  __syncthreads();
+  if (!flag) return false;
+  double gs[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) gs[v] = block_sum_array(part + (size_t)v * kRedSlot + g * kRedGroup, gsz, sh);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) publish(part + (size_t)v * kRedSlot + kRedGroupOff + g, gs[v]);
+    bool last = take_ticket(ctr) == (unsigned)(ng - 1);
+    if (last) reset_ticket(ctr);
+    flag = last;
+  }
+  __syncthreads();
+  if (!flag) return false;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    double r = block_sum_array(part + (size_t)v * kRedSlot + kRedGroupOff, ng, sh);
+    if (threadIdx.x == 0) out[v] = r;
+  }
+  return true;
 }
 
 // Latched device status word bits.

@@ -44,7 +44,7 @@ struct Dev {
   double* scal;
 };
 
-constexpr int kPartSlot = 1 << 18;  // partial sums per reduction slot
+constexpr int kPartSlot = kRedSlot;  // partial sums per reduction slot
 
 // ======================================================================================
 // Cell sort: keys, counts, slots, per-cell order fix-up.
@@ -142,14 +142,13 @@ __global__ void k_cell_scatter(const int* key, int cnt, const int* start, int* c
   perm[slot] = i;
 }
 
-// Sort each segment [start[c], start[c+1]) of distinct values ascending.  Makes the slot
-// order independent of atomic arrival order.  Segments of up to 16 values are ranked in
-// registers (independent loads); longer ones use an insertion sort in memory.
+// Sort each segment of distinct values ascending; the segments are the runs of equal
+// key[vals[s]] in vals[0..cnt), starting at start[key].  Makes the slot order independent
+// of atomic arrival order.  One thread per slot: only a segment's first slot works, so
+// the launch scales with the number of points, not of cells.  Segments of up to 16 values
+// are ranked in registers (independent loads); longer ones use an insertion sort in memory.
 constexpr int kSegReg = 16;
-__global__ void k_segment_order(const int* start, int nseg, int* vals) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= nseg) return;
-  int b = start[c], e = start[c + 1];
+MPM_DEV void sort_segment(int b, int e, int* vals) {
   int n = e - b;
   if (n < 2) return;
   if (n <= kSegReg) {
@@ -171,6 +170,22 @@ __global__ void k_segment_order(const int* start, int nseg, int* vals) {
     while (j >= b && vals[j] > v) { vals[j + 1] = vals[j]; --j; }
     vals[j + 1] = v;
   }
+}
+
+// Segments given by keys (cell sort): key of slot s is key[vals[s]].
+__global__ void k_segment_order_keys(const int* key, const int* start, int cnt, int* vals) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= cnt) return;
+  int k = key[vals[s]];
+  if (start[k] != s) return;
+  sort_segment(s, start[k + 1], vals);
+}
+
+// Segments given directly: [start[c], start[c+1]) for c < nseg.
+__global__ void k_segment_order(const int* start, int nseg, int* vals) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nseg) return;
+  sort_segment(start[c], start[c + 1], vals);
 }
 
 __global__ void k_fill_i32(int* p, int v, int64_t len) {
@@ -262,6 +277,11 @@ __global__ void k_parents(Dev<R> d) {
     if (d2 < best || (d2 == best && o < borig)) { best = d2; bk = k; borig = o; }
   };
   double dxd = (double)d.dx;
+  // own cell first, so that the box test below prunes most neighbours
+  {
+    int ci = (int)tiled_index<D>(c, d.nt);
+    for (int k = d.p_start[ci]; k < d.p_start[ci + 1]; ++k) visit(k);
+  }
   for (int rad = 1; rad <= 3; ++rad) {
     int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
 #pragma unroll
@@ -270,6 +290,20 @@ __global__ void k_parents(Dev<R> d) {
       for (int y = lo[1]; y <= hi[1]; ++y)
         for (int x = lo[0]; x <= hi[0]; ++x) {
           int cc[3] = {x, y, z};
+          // shell rad only: inner cells were searched by the smaller radii
+          int ring = 0;
+          double bd2 = 0;
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            ring = max(ring, abs(cc[a] - c[a]));
+            double lo_a = cc[a] * dxd, hi_a = (cc[a] + 1) * dxd;
+            double g = sd[a] < lo_a ? lo_a - sd[a] : (sd[a] > hi_a ? sd[a] - hi_a : 0.0);
+            bd2 += g * g;
+          }
+          if (ring != rad) continue;
+          // no point of the cell can be closer than its box; the margin keeps the test
+          // conservative against the rounding of both distances (ties must be visited)
+          if (bd2 > best * (1.0 + 1e-9)) continue;
           int ci = (int)tiled_index<D>(cc, d.nt);
           for (int k = d.p_start[ci]; k < d.p_start[ci + 1]; ++k) visit(k);
         }
@@ -519,12 +553,8 @@ __global__ void k_dot(const int* tl, int nelem, int nn, int ncomp, const R* a, c
     int node = elem_node(tl, e);
     for (int c = 0; c < ncomp; ++c) s += (double)a[c * nn + node] * (double)b[c * nn + node];
   }
-  double t = block_sum(s, sh);
-  if (threadIdx.x == 0) publish(part + blockIdx.x, t);
-  if (grid_last_block(ctr)) {
-    double r = block_sum_array(part, gridDim.x, sh);
-    if (threadIdx.x == 0) *dst = r;
-  }
+  double t = block_sum(s, sh), r;
+  if (grid_reduce<1>(&t, part, ctr, sh, &r) && threadIdx.x == 0) *dst = r;
 }
 
 // Sums nslot partial arrays of nb entries each (fixed order) into dst[0..nslot).
@@ -570,14 +600,11 @@ __global__ void k_cg_start(const int* tl, int nelem, int nn, int ncomp, const R*
       rr += (double)rv * (double)rv;
     }
   }
-  double t0 = block_sum(rz, sh);
-  double t1 = block_sum(rr, sh);
-  if (threadIdx.x == 0) { publish(part + blockIdx.x, t0); publish(part + kPartSlot + blockIdx.x, t1); }
-  if (grid_last_block(ctr)) {
-    double srz = block_sum_array(part, gridDim.x, sh);
-    double srr = block_sum_array(part + kPartSlot, gridDim.x, sh);
-    if (threadIdx.x == 0) cg_init(cs, srz, srr, tol2_host * (tol2_scale ? *tol2_scale : 1.0), maxit);
-  }
+  double t[2], sum[2];
+  t[0] = block_sum(rz, sh);
+  t[1] = block_sum(rr, sh);
+  if (grid_reduce<2>(t, part, ctr, sh, sum) && threadIdx.x == 0)
+    cg_init(cs, sum[0], sum[1], tol2_host * (tol2_scale ? *tol2_scale : 1.0), maxit);
 }
 
 // Called by the last block of the operator's merge with the sum p . A p.
@@ -607,12 +634,11 @@ __global__ void k_cg_update(const int* tl, int nelem, int nn, int ncomp, CgScal*
       rr += (double)rv * (double)rv;
     }
   }
-  double t0 = block_sum(rz, sh);
-  double t1 = block_sum(rr, sh);
-  if (threadIdx.x == 0) { publish(part + blockIdx.x, t0); publish(part + kPartSlot + blockIdx.x, t1); }
-  if (grid_last_block(ctr)) {
-    double rz_new = block_sum_array(part, gridDim.x, sh);
-    double rrs = block_sum_array(part + kPartSlot, gridDim.x, sh);
+  double t[2], sum[2];
+  t[0] = block_sum(rz, sh);
+  t[1] = block_sum(rr, sh);
+  if (grid_reduce<2>(t, part, ctr, sh, sum)) {
+    const double rz_new = sum[0], rrs = sum[1];
     if (threadIdx.x == 0) {
       s->beta = rz_new / s->rz;
       s->rz = rz_new;
@@ -693,24 +719,18 @@ __global__ void k_mom_sums(const int* tl, int nelem, int nn, const uint8_t* fr, 
       s[D + 1 + a] += mm * (double)vh[a * nn + node];
     }
   }
-  for (int k = 0; k < 2 * D + 1; ++k) {
-    double t = block_sum(s[k], sh);
-    if (threadIdx.x == 0) publish(part + k * kPartSlot + blockIdx.x, t);
-    __syncthreads();
-  }
-  if (grid_last_block(ctr)) {
-    for (int k = 0; k < 2 * D + 1; ++k) {
-      double r = block_sum_array(part + k * kPartSlot, gridDim.x, sh);
-      if (threadIdx.x == 0) dst[k] = r;
-      __syncthreads();
-    }
-  }
+  double t[2 * D + 1], r[2 * D + 1];
+  for (int k = 0; k < 2 * D + 1; ++k) t[k] = block_sum(s[k], sh);
+  if (grid_reduce<2 * D + 1>(t, part, ctr, sh, r) && threadIdx.x == 0)
+    for (int k = 0; k < 2 * D + 1; ++k) dst[k] = r[k];
 }
 
-// v^ -= c on nodes with mass, c_a = [sum m (v^-v^n) - dt g_a sum m] / sum m.
+// Exact minimization of Phi along rigid translations: v^ -= c on nodes with mass,
+// c_a = [sum m (v^ - v^n) - dt g_a sum m] / sum m.  e and D are translation invariant, so
+// the projected gradient moves by exactly -m c (grad may be null).
 template <int D, typename R>
-__global__ void k_mom_fix(const int* tl, int nelem, int nn, const uint8_t* fr, const double* red, double dt,
-                          double g0, double g1, double g2, R* vh) {
+__global__ void k_mom_fix(const int* tl, int nelem, int nn, const uint8_t* fr, const R* m, const double* red,
+                          double dt, double g0, double g1, double g2, R* vh, R* grad) {
   double msum = red[D];
   double gg[3] = {g0, g1, g2};
   R c[D];
@@ -718,7 +738,11 @@ __global__ void k_mom_fix(const int* tl, int nelem, int nn, const uint8_t* fr, c
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nelem; e += gridDim.x * blockDim.x) {
     int node = elem_node(tl, e);
     if (!(fr[node] & 0x80)) continue;
-    for (int a = 0; a < D; ++a) vh[a * nn + node] -= c[a];
+    R mm = m[node];
+    for (int a = 0; a < D; ++a) {
+      vh[a * nn + node] -= c[a];
+      if (grad) grad[a * nn + node] -= mm * c[a];
+    }
   }
 }
 
@@ -739,20 +763,29 @@ __global__ void k_explicit_update(const int* tl, int nelem, int nn, const uint8_
 }
 
 // Counts the degrees of freedom (nodes with mass) into misc[2] and sets misc[1] when any
-// node with mass has a constrained component.
+// node with mass has a constrained component.  Grid-stride over the active nodes with one
+// atomic pair per block (same-address atomics serialize across the grid).
 template <int D>
-__global__ void k_dof_flags(const int* tl, const uint8_t* fr, int* misc) {
-  __shared__ int cnt;
-  if (threadIdx.x == 0) cnt = 0;
-  __syncthreads();
-  uint8_t f = fr[tl[blockIdx.x] * kTileNodes + threadIdx.x];
+__global__ void k_dof_flags(const int* tl, int nelem, const uint8_t* fr, int* misc) {
+  int cnt = 0, con = 0;
   const uint8_t all = (uint8_t)((1u << D) - 1);
-  if (f & 0x80) {
-    atomicAdd(&cnt, 1);
-    if ((f & all) != all) atomicOr(&misc[1], 1);
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nelem; e += gridDim.x * blockDim.x) {
+    uint8_t f = fr[elem_node(tl, e)];
+    if (f & 0x80) {
+      cnt += 1;
+      con |= (f & all) != all;
+    }
   }
+  __shared__ int scnt, scon;
+  if (threadIdx.x == 0) { scnt = 0; scon = 0; }
   __syncthreads();
-  if (threadIdx.x == 0 && cnt) atomicAdd(&misc[2], cnt);
+  if (cnt) atomicAdd(&scnt, cnt);
+  if (con) atomicOr(&scon, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (scnt) atomicAdd(&misc[2], scnt);
+    if (scon) atomicOr(&misc[1], 1);
+  }
 }
 
 }  // namespace mpm

@@ -188,7 +188,7 @@ size_t layout(mpm_ctx* c, char* base) {
   d.part = b.take<double>((size_t)kNumParts * kPartSlot);
   d.scal = b.take<double>(kScalDoubles);
   CgScal* cg = b.take<CgScal>(2);
-  unsigned* ctr = b.take<unsigned>(CTR_COUNT);
+  unsigned* ctr = b.take<unsigned>((size_t)CTR_COUNT * kCtrSite);
   d.status = misc;
   if (base) {
     c->vhat = vecs[0]; c->vtrial = vecs[1]; c->grad = vecs[2]; c->delta = vecs[3]; c->r = vecs[4];
@@ -252,7 +252,8 @@ void cell_sort(mpm_ctx* c, Dev<R>& d, const R* pos, int cnt, int* key, int* perm
   if (cnt > 0) {
     LAUNCH(c, MPM_K_SORT, k_cell_scatter, dim3(cdiv(cnt, 256)), dim3(256), 0, s, (const int*)key, cnt,
                        (const int*)start, d.ccount, perm);
-    LAUNCH(c, MPM_K_SORT, k_segment_order, dim3(cdiv(d.nn, 256)), dim3(256), 0, s, (const int*)start, d.nn, perm);
+    LAUNCH(c, MPM_K_SORT, k_segment_order_keys, dim3(cdiv(cnt, 256)), dim3(256), 0, s, (const int*)key,
+           (const int*)start, cnt, perm);
   }
 }
 
@@ -270,6 +271,7 @@ TileLists tiles(mpm_ctx* c) {
 }
 
 int krylov_blocks(int nelem) { return std::max(1, std::min(1024, cdiv(nelem, 256))); }
+int merge_blocks(const mpm_ctx* c) { return cdiv(c->ntiles, kMergeTiles); }
 
 void sync_read(mpm_ctx* c, hipStream_t s, const void* src, void* dst, size_t bytes) {
   HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
@@ -341,12 +343,12 @@ void do_p2g(mpm_ctx* c, const mpm_particles* P, const mpm_surface* S, hipStream_
   if (c->nctile > 0)
     LAUNCH(c, MPM_K_P2G, (k_tile_p2g<D, R>), dim3(c->nctile), dim3(TileGeo<D>::NT), 0, s, d, tl, (R*)c->tpart);
   if (c->ntiles > 0)
-    LAUNCH(c, MPM_K_P2G, (k_merge_p2g<D, R>), dim3(c->ntiles), dim3(64), 0, s, d, tl, (const R*)c->tpart);
+    LAUNCH(c, MPM_K_P2G_NODE, (k_merge_p2g<D, R>), dim3(c->ntiles), dim3(64), 0, s, d, tl, (const R*)c->tpart);
   if (c->ns > 0) LAUNCH(c, MPM_K_SETUP, (k_surface_k<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d);
   // degrees of freedom and whether any of them has a fixed component
   if (c->ntiles > 0)
-    LAUNCH(c, MPM_K_SETUP, (k_dof_flags<D>), dim3(c->ntiles), dim3(64), 0, s, (const int*)d.tile_list,
-           (const uint8_t*)d.gfree, c->misc);
+    LAUNCH(c, MPM_K_SETUP, (k_dof_flags<D>), dim3(std::min(128, cdiv(c->ntiles, 4))), dim3(256), 0, s,
+           (const int*)d.tile_list, c->ntiles * 64, (const uint8_t*)d.gfree, c->misc);
   c->have_p2g = true;
   c->stats = mpm_stats{};
   c->stats.n_part = c->np;
@@ -367,9 +369,10 @@ void do_energy_grad(mpm_ctx* c, const R* u, R* g, double* energy_dev, int phi_sl
     LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_ENERGY>), dim3(c->nctile), dim3(TileGeo<D>::NT), 0, s, d, tl,
            u, (R*)c->tpart, 0, (const int*)nullptr, 2);
   if (c->ntiles > 0) {
-    LAUNCH(c, MPM_K_ENERGY_NODE, (k_merge_stress<D, R>), dim3(c->ntiles), dim3(64), 0, s, d, tl, (const R*)c->tpart,
+    LAUNCH(c, MPM_K_ENERGY_NODE, (k_merge_stress<D, R>), dim3(merge_blocks(c)), dim3(64 * kMergeTiles), 0, s, d, tl, c->ntiles,
+           (const R*)c->tpart,
            u, g, (int)NM_GRAD, 0.0, 0, (const int*)nullptr, c->nctile > 0 ? (const double*)(c->part + 2 * kPartSlot) : nullptr,
-           c->nctile, c->part + 4 * kPartSlot, c->ctr + CTR_MERGE, c->scal + phi_slot, energy_dev, (CgScal*)nullptr);
+           c->nctile, c->part + 4 * kPartSlot, c->ctr + (size_t)CTR_MERGE * kCtrSite, c->scal + phi_slot, energy_dev, (CgScal*)nullptr);
   } else {
     LAUNCH(c, MPM_K_BLAS, k_fill_r<double>, dim3(1), dim3(1), 0, s, c->scal + phi_slot, 0.0, (int64_t)1);
     if (energy_dev) LAUNCH(c, MPM_K_BLAS, k_fill_r<double>, dim3(1), dim3(1), 0, s, energy_dev, 0.0, (int64_t)1);
@@ -395,9 +398,10 @@ void do_hessvec(mpm_ctx* c, const R* w, double alpha, R* out, bool mask_in, cons
     LAUNCH(c, MPM_K_HESS_INT, (k_tile_stress<D, R, TM_HESS>), dim3(c->nctile), dim3(TileGeo<D>::NT), 0, s, d, tl, w,
            (R*)c->tpart, (int)mask_in, done, -1);
   if (c->ntiles > 0)
-    LAUNCH(c, MPM_K_HESS_NODE, (k_merge_stress<D, R>), dim3(c->ntiles), dim3(64), 0, s, d, tl, (const R*)c->tpart,
+    LAUNCH(c, MPM_K_HESS_NODE, (k_merge_stress<D, R>), dim3(merge_blocks(c)), dim3(64 * kMergeTiles), 0, s, d, tl, c->ntiles,
+           (const R*)c->tpart,
            w, out, (int)NM_HESS, alpha, (int)mask_in, done, (const double*)nullptr, 0, c->part + 4 * kPartSlot,
-           c->ctr + CTR_MERGE, (double*)nullptr, (double*)nullptr, cg);
+           c->ctr + (size_t)CTR_MERGE * kCtrSite, (double*)nullptr, (double*)nullptr, cg);
 }
 
 // Forces only (no inertia term): out = P sum_q S_q grad N_i for the stress of u.
@@ -409,9 +413,10 @@ void do_hessvec_force(mpm_ctx* c, const R* u, R* out, hipStream_t s) {
     LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_FORCE>), dim3(c->nctile), dim3(TileGeo<D>::NT), 0, s, d, tl,
            u, (R*)c->tpart, 0, (const int*)nullptr, -1);
   if (c->ntiles > 0)
-    LAUNCH(c, MPM_K_ENERGY_NODE, (k_merge_stress<D, R>), dim3(c->ntiles), dim3(64), 0, s, d, tl, (const R*)c->tpart,
+    LAUNCH(c, MPM_K_ENERGY_NODE, (k_merge_stress<D, R>), dim3(merge_blocks(c)), dim3(64 * kMergeTiles), 0, s, d, tl, c->ntiles,
+           (const R*)c->tpart,
            u, out, (int)NM_HESS, 0.0, 0, (const int*)nullptr, (const double*)nullptr, 0, c->part + 4 * kPartSlot,
-           c->ctr + CTR_MERGE, (double*)nullptr, (double*)nullptr, (CgScal*)nullptr);
+           c->ctr + (size_t)CTR_MERGE * kCtrSite, (double*)nullptr, (double*)nullptr, (CgScal*)nullptr);
 }
 
 template <int D, typename R>
@@ -422,8 +427,9 @@ void do_heat_apply(mpm_ctx* c, const R* T, R* out, const int* done, CgScal* cg, 
     LAUNCH(c, MPM_K_HEAT_PT, (k_tile_heat<D, R>), dim3(c->nctile), dim3(TileGeo<D>::NT), 0, s, d, tl, T,
            (R*)c->tpart, done);
   if (c->ntiles > 0)
-    LAUNCH(c, MPM_K_HEAT_NODE, (k_merge_heat<D, R>), dim3(c->ntiles), dim3(64), 0, s, d, tl, (const R*)c->tpart, T,
-           out, done, c->part + 4 * kPartSlot, c->ctr + CTR_MERGE, cg);
+    LAUNCH(c, MPM_K_HEAT_NODE, (k_merge_heat<D, R>), dim3(merge_blocks(c)), dim3(64 * kMergeTiles), 0, s, d, tl, c->ntiles,
+           (const R*)c->tpart, T,
+           out, done, c->part + 4 * kPartSlot, c->ctr + (size_t)CTR_MERGE * kCtrSite, cg);
 }
 
 template <int D, typename R>
@@ -442,7 +448,7 @@ void dot_async(mpm_ctx* c, const R* a, const R* b, int ncomp, int slot, hipStrea
   Dev<R>& d = dev<R>(c);
   int nelem = c->ntiles * 64, nb = krylov_blocks(nelem);
   LAUNCH(c, MPM_K_BLAS, k_dot<R>, dim3(nb), dim3(256), 0, s, (const int*)d.tile_list, nelem, d.nn, ncomp, a, b,
-         c->part, c->ctr + CTR_DOT, c->scal + slot);
+         c->part, c->ctr + (size_t)CTR_DOT * kCtrSite, c->scal + slot);
 }
 
 // Momentum sums of vh into scal[SC_MOM..] (asynchronous).
@@ -451,7 +457,7 @@ void mom_sums_async(mpm_ctx* c, const R* vh, hipStream_t s) {
   Dev<R>& d = dev<R>(c);
   int nelem = c->ntiles * 64, nb = krylov_blocks(nelem);
   LAUNCH(c, MPM_K_BLAS, (k_mom_sums<D, R>), dim3(nb), dim3(256), 0, s, (const int*)d.tile_list, nelem, d.nn,
-         (const uint8_t*)d.gfree, (const R*)d.gm, vh, (const R*)d.gvn, c->part, c->ctr + CTR_MOM, c->scal + SC_MOM);
+         (const uint8_t*)d.gfree, (const R*)d.gm, vh, (const R*)d.gvn, c->part, c->ctr + (size_t)CTR_MOM * kCtrSite, c->scal + SC_MOM);
 }
 
 // Reads the scalar block (and the misc words) in one synchronization.
@@ -477,7 +483,7 @@ int cg_solve(mpm_ctx* c, Apply&& apply, const R* b, R* x, bool x0_given, const R
   const int* tl = d.tile_list;
   if (x0_given) apply(x, Ap, (const int*)nullptr, (CgScal*)nullptr);
   LAUNCH(c, MPM_K_BLAS, k_cg_start<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, b,
-         x0_given ? (const R*)Ap : (const R*)nullptr, diag, x, r, z, p, c->part, c->ctr + CTR_CGSTART, c->cg, tol2_host,
+         x0_given ? (const R*)Ap : (const R*)nullptr, diag, x, r, z, p, c->part, c->ctr + (size_t)CTR_CGSTART * kCtrSite, c->cg, tol2_host,
          tol2_scale, maxit);
   const int* done = &c->cg->done;
   int chunk = 2;
@@ -485,7 +491,7 @@ int cg_solve(mpm_ctx* c, Apply&& apply, const R* b, R* x, bool x0_given, const R
     for (int j = 0; j < chunk; ++j) {
       apply(p, Ap, done, c->cg);
       LAUNCH(c, MPM_K_BLAS, k_cg_update<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, c->cg, x, r, z,
-             (const R*)p, (const R*)Ap, diag, c->part, c->ctr + CTR_CGUPD);
+             (const R*)p, (const R*)Ap, diag, c->part, c->ctr + (size_t)CTR_CGUPD * kCtrSite);
       LAUNCH(c, MPM_K_BLAS, k_cg_p<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, (const CgScal*)c->cg,
              (const R*)z, p);
     }
@@ -547,14 +553,26 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
                           (R*)c->Ap, D, cg_tol * cg_tol, nullptr, p.cg_max, s);
     st.cg_iters += cit;
     st.hessvecs += cit;
-    // slope and the full step's energy in one round trip
+    // slope, then the full step: its energy, gradient and (speculatively, harmless if the
+    // trial is rejected because the next trial overwrites it) the translation correction
+    // and |g|^2 at the corrected point, all read in one round trip.
     dot_async<R>(c, g, delta, D, SC_SLOPE, s);
     double alpha = 1.0;
-    LAUNCH(c, MPM_K_BLAS, k_axpy_to<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const R*)vhat,
-           (const R*)delta, alpha, vtrial);
-    do_energy_grad<D, R>(c, vtrial, (R*)c->gscratch, nullptr, SC_PHIT, s);
-    read_scalars(c, s);
-    st.energy_evals++;
+    auto trial = [&](double a) {
+      LAUNCH(c, MPM_K_BLAS, k_axpy_to<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const R*)vhat,
+             (const R*)delta, a, vtrial);
+      do_energy_grad<D, R>(c, vtrial, (R*)c->gscratch, nullptr, SC_PHIT, s);
+      if (fix) {
+        mom_sums_async<D, R>(c, (const R*)vtrial, s);
+        LAUNCH(c, MPM_K_BLAS, (k_mom_fix<D, R>), dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, (const uint8_t*)d.gfree,
+               (const R*)d.gm, (const double*)(c->scal + SC_MOM), p.dt, p.gravity[0], p.gravity[1], p.gravity[2],
+               vtrial, (R*)c->gscratch);
+      }
+      dot_async<R>(c, (const R*)c->gscratch, (const R*)c->gscratch, D, SC_GN2, s);
+      read_scalars(c, s);
+      st.energy_evals++;
+    };
+    trial(alpha);
     const double slope = c->hbuf[SC_SLOPE];
     double phit = c->hbuf[SC_PHIT];
     // Armijo with the round-off of Phi as allowance (8 eps |Phi|, eps of the arithmetic):
@@ -564,26 +582,27 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
       if (phit <= phi + p.ls_c1 * alpha * slope + noise) break;
       alpha *= 0.5;
       st.line_search_halvings++;
-      LAUNCH(c, MPM_K_BLAS, k_axpy_to<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const R*)vhat,
-             (const R*)delta, alpha, vtrial);
-      do_energy_grad<D, R>(c, vtrial, (R*)c->gscratch, nullptr, SC_PHIT, s);
-      read_scalars(c, s);
-      st.energy_evals++;
+      trial(alpha);
       phit = c->hbuf[SC_PHIT];
     }
+    // accept the last trial: its (corrected) point and gradient become the iterate
     std::swap(c->vhat, c->vtrial);
+    std::swap(c->grad, c->gscratch);
     vhat = (R*)c->vhat;
     vtrial = (R*)c->vtrial;
+    g = (R*)c->grad;
+    phi = phit;
     if (fix) {
-      mom_sums_async<D, R>(c, (const R*)vhat, s);
-      LAUNCH(c, MPM_K_BLAS, (k_mom_fix<D, R>), dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, (const uint8_t*)d.gfree,
-             (const double*)(c->scal + SC_MOM), p.dt, p.gravity[0], p.gravity[1], p.gravity[2], vhat);
+      // Phi(v^ - c) = Phi(v^) - 1/2 |c|^2 sum m for the minimizing translation c
+      const double* red = c->hbuf + SC_MOM;
+      const double M = red[D];
+      double c2 = 0;
+      for (int a2 = 0; a2 < D; ++a2) {
+        double ca = (red[a2] - p.dt * p.gravity[a2] * M) / M;
+        c2 += ca * ca;
+      }
+      phi -= 0.5 * M * c2;
     }
-    do_energy_grad<D, R>(c, vhat, g, nullptr, SC_PHI, s);
-    dot_async<R>(c, g, g, D, SC_GN2, s);
-    read_scalars(c, s);
-    st.energy_evals++;
-    phi = c->hbuf[SC_PHI];
     gn = std::sqrt(std::max(c->hbuf[SC_GN2], 0.0));
   }
   if (it == p.newton_max && gn <= std::max(p.newton_tol * g0, floor_abs)) st.converged = 1;

@@ -1001,136 +1001,157 @@ __global__ void __launch_bounds__(256) k_tile_g2p(Dev<R> d, TileLists tl, const 
 // ======================================================================================
 template <int D>
 struct MergeSrc {
-  int slot[8];
-  int rn[8];
-  int cnt;
+  int slot[1 << D];   // partial slot of candidate j, -1 if absent
+  int rn[1 << D];     // node's index in that tile's region
 };
 
+// The cell tiles whose 6^3 (10^2) node regions contain a node: its own tile and, on a
+// tile face, the neighbour across it.  Candidate j (0 <= j < 2^D, axis a taking the
+// bit k_a of j, higher axes outer) is the tile base_a + k_a per axis; the candidates are
+// visited in increasing tile coordinates, which fixes the summation order.  Every
+// index is a compile-time constant after unrolling, so the arrays stay in registers and
+// all slot lookups and partial loads can be in flight together.
 template <int D>
 MPM_DEV void merge_sources(int node_tile, int local, int nt, const int* ctile_slot, MergeSrc<D>& ms) {
   constexpr int E = TileGeo<D>::E, RE = TileGeo<D>::RE;
   int i[3] = {0, 0, 0};
   tiled_coords<D>(node_tile, local, nt, i);
-  int T[3] = {0, 0, 0}, l[3] = {0, 0, 0};
-#pragma unroll
-  for (int a = 0; a < D; ++a) { T[a] = i[a] / E; l[a] = i[a] % E; }
-  int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  int base[3] = {0, 0, 0}, two[3] = {0, 0, 0};
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    lo[a] = l[a] == 0 ? T[a] - 1 : T[a];
-    hi[a] = l[a] == E - 1 ? T[a] + 1 : T[a];
-    lo[a] = lo[a] < 0 ? 0 : lo[a];
-    hi[a] = hi[a] > nt - 1 ? nt - 1 : hi[a];
+    const int T = i[a] / E, l = i[a] % E;
+    base[a] = l == 0 ? T - 1 : T;
+    two[a] = (l == 0 || l == E - 1) ? 1 : 0;
   }
-  ms.cnt = 0;
-  for (int c2 = (D == 3 ? lo[2] : 0); c2 <= (D == 3 ? hi[2] : 0); ++c2)
-    for (int c1 = lo[1]; c1 <= hi[1]; ++c1)
-      for (int c0 = lo[0]; c0 <= hi[0]; ++c0) {
-        int ct = c0 + nt * (c1 + (D == 3 ? nt * c2 : 0));
-        int s = ctile_slot[ct];
-        if (s < 0) continue;
-        int C[3] = {c0, c1, c2};
-        int r[3] = {0, 0, 0};
 #pragma unroll
-        for (int a = 0; a < D; ++a) r[a] = i[a] - (E * C[a] - 1);
-        ms.slot[ms.cnt] = s;
-        ms.rn[ms.cnt] = r[0] + RE * (r[1] + (D == 3 ? RE * r[2] : 0));
-        ms.cnt++;
-      }
+  for (int j = 0; j < (1 << D); ++j) {
+    int C[3] = {0, 0, 0};
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const int k = (j >> a) & 1;
+      C[a] = base[a] + k;
+      ok = ok && (k == 0 || two[a]) && C[a] >= 0 && C[a] < nt;
+    }
+    const int ct = C[0] + nt * (C[1] + (D == 3 ? nt * C[2] : 0));
+    const int s = ok ? ctile_slot[ct] : -1;
+    int r[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < D; ++a) r[a] = i[a] - (E * C[a] - 1);
+    ms.slot[j] = s;
+    ms.rn[j] = r[0] + RE * (r[1] + (D == 3 ? RE * r[2] : 0));
+  }
 }
 
+// Node kernels of the operators: one wave per node tile, kMergeTiles tiles per block.
+constexpr int kMergeTiles = 4;
+
 // Stress merge: node-level terms.
-//  NM_GRAD: out = P[acc + m (v^ - v^n) - dt m g]; the last block adds the tile energy
-//           partials (epart, nep entries) and the node terms into Phi (*phi, *phi2).
-//  NM_HESS: out = P[acc + alpha m w]; with cg the last block sets the CG step length from
-//           the sum of w . out.
+//  NM_GRAD: out = P[acc + m (v^ - v^n) - dt m g]; the blocks also sum the tile energy
+//           partials (epart, nep entries) and the grid sum goes to Phi (*phi, *phi2).
+//  NM_HESS: out = P[acc + alpha m w]; with cg the grid sum of w . out sets the CG step.
 template <int D, typename R>
-__global__ void __launch_bounds__(64) k_merge_stress(Dev<R> d, TileLists tl, const R* tpart, const R* u, R* out,
-                                                     int mode, double alpha, int mask_in, const int* done,
-                                                     const double* epart, int nep, double* npart, unsigned* ctr,
-                                                     double* phi, double* phi2, CgScal* cg) {
+__global__ void __launch_bounds__(64 * kMergeTiles) k_merge_stress(
+    Dev<R> d, TileLists tl, int ntiles, const R* tpart, const R* u, R* out, int mode, double alpha, int mask_in,
+    const int* done, const double* epart, int nep, double* npart, unsigned* ctr, double* phi, double* phi2,
+    CgScal* cg) {
   constexpr int RN = TileGeo<D>::RN;
   __shared__ double sh[16];
   if (done && *done) return;
-  const int tile = d.tile_list[blockIdx.x];
-  const int lane = threadIdx.x;
-  const int node = tile * kTileNodes + lane;
-  const int nn = d.nn;
-  MergeSrc<D> ms;
-  merge_sources<D>(tile, lane, d.nt, tl.ctile_slot, ms);
-  R acc[D];
-#pragma unroll
-  for (int a = 0; a < D; ++a) acc[a] = 0;
-  for (int j = 0; j < ms.cnt; ++j) {
-    const R* src = tpart + (size_t)ms.slot[j] * RN * D + ms.rn[j] * D;
-#pragma unroll
-    for (int a = 0; a < D; ++a) acc[a] += src[a];
-  }
-  uint8_t fr = d.gfree[node];
-  R m = d.gm[node];
+  const int ti = blockIdx.x * kMergeTiles + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   double e = 0, dotv = 0;
+  if (ti < ntiles) {
+    const int tile = d.tile_list[ti];
+    const int node = tile * kTileNodes + lane;
+    const int nn = d.nn;
+    MergeSrc<D> ms;
+    merge_sources<D>(tile, lane, d.nt, tl.ctile_slot, ms);
+    R acc[D];
 #pragma unroll
-  for (int a = 0; a < D; ++a) {
-    bool fa = (fr >> a) & 1;
-    R ua = u ? u[a * nn + node] : R(0);
-    R o;
-    if (mode == NM_GRAD) {
-      R vn = d.gvn[a * nn + node];
-      o = acc[a] + m * (ua - vn) - d.dt * m * d.grav[a];
-      if (fr & 0x80) {
-        double dv = (double)ua - (double)vn;
-        e += 0.5 * (double)m * dv * dv - (double)d.dt * (double)m * (double)d.grav[a] * (double)ua;
-      }
-    } else {
-      R wa = (!mask_in || fa) ? ua : R(0);
-      o = acc[a] + R(alpha) * m * wa;
-      if (fa) dotv += (double)wa * (double)o;
+    for (int a = 0; a < D; ++a) acc[a] = 0;
+    R val[1 << D][D];
+#pragma unroll
+    for (int j = 0; j < (1 << D); ++j) {
+      const R* src = tpart + (size_t)(ms.slot[j] < 0 ? 0 : ms.slot[j]) * RN * D + ms.rn[j] * D;
+#pragma unroll
+      for (int a = 0; a < D; ++a) val[j][a] = ms.slot[j] >= 0 ? src[a] : R(0);
     }
-    o = fa ? o : R(0);
-    out[a * nn + node] = o;
+#pragma unroll
+    for (int j = 0; j < (1 << D); ++j)
+#pragma unroll
+      for (int a = 0; a < D; ++a) acc[a] += val[j][a];
+    uint8_t fr = d.gfree[node];
+    R m = d.gm[node];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      bool fa = (fr >> a) & 1;
+      R ua = u ? u[a * nn + node] : R(0);
+      R o;
+      if (mode == NM_GRAD) {
+        R vn = d.gvn[a * nn + node];
+        o = acc[a] + m * (ua - vn) - d.dt * m * d.grav[a];
+        if (fr & 0x80) {
+          double dv = (double)ua - (double)vn;
+          e += 0.5 * (double)m * dv * dv - (double)d.dt * (double)m * (double)d.grav[a] * (double)ua;
+        }
+      } else {
+        R wa = (!mask_in || fa) ? ua : R(0);
+        o = acc[a] + R(alpha) * m * wa;
+        if (fa) dotv += (double)wa * (double)o;
+      }
+      o = fa ? o : R(0);
+      out[a * nn + node] = o;
+    }
   }
   const bool want = (mode == NM_GRAD && phi) || (mode == NM_HESS && cg);
   if (!want) return;
-  double bs = block_sum(mode == NM_GRAD ? e : dotv, sh);
-  if (threadIdx.x == 0) publish(npart + blockIdx.x, bs);
-  if (grid_last_block(ctr)) {
-    double tot = block_sum_array(npart, gridDim.x, sh);
+  if (mode == NM_GRAD && epart) {
+    // this block also sums the tile-kernel energy partials k = blockIdx.x (mod gridDim.x)
+    for (int k = blockIdx.x + threadIdx.x * gridDim.x; k < nep; k += blockDim.x * gridDim.x) e += epart[k];
+  }
+  double bs = block_sum(mode == NM_GRAD ? e : dotv, sh), tot;
+  if (grid_reduce<1>(&bs, npart, ctr, sh, &tot) && threadIdx.x == 0) {
     if (mode == NM_GRAD) {
-      double te = epart ? block_sum_array(epart, nep, sh) : 0.0;
-      if (threadIdx.x == 0) {
-        *phi = te + tot;
-        if (phi2) *phi2 = te + tot;
-      }
-    } else if (threadIdx.x == 0) {
+      *phi = tot;
+      if (phi2) *phi2 = tot;
+    } else {
       cg_set_alpha(cg, tot);
     }
   }
 }
 
 template <int D, typename R>
-__global__ void __launch_bounds__(64) k_merge_heat(Dev<R> d, TileLists tl, const R* tpart, const R* T, R* out,
-                                                   const int* done, double* npart, unsigned* ctr, CgScal* cg) {
+__global__ void __launch_bounds__(64 * kMergeTiles) k_merge_heat(Dev<R> d, TileLists tl, int ntiles,
+                                                                 const R* tpart, const R* T, R* out, const int* done,
+                                                                 double* npart, unsigned* ctr, CgScal* cg) {
   constexpr int RN = TileGeo<D>::RN;
   __shared__ double sh[16];
   if (done && *done) return;
-  const int tile = d.tile_list[blockIdx.x];
-  const int lane = threadIdx.x;
-  const int node = tile * kTileNodes + lane;
-  MergeSrc<D> ms;
-  merge_sources<D>(tile, lane, d.nt, tl.ctile_slot, ms);
-  R acc = 0;
-  for (int j = 0; j < ms.cnt; ++j) acc += tpart[(size_t)ms.slot[j] * RN + ms.rn[j]];
-  bool dof = d.gfree[node] & 0x80;
-  R Ti = T[node];
-  R o = dof ? d.cp / d.dt * d.gm[node] * Ti + acc : R(0);
-  out[node] = o;
-  if (!cg) return;
-  double bs = block_sum(dof ? (double)Ti * (double)o : 0.0, sh);
-  if (threadIdx.x == 0) publish(npart + blockIdx.x, bs);
-  if (grid_last_block(ctr)) {
-    double tot = block_sum_array(npart, gridDim.x, sh);
-    if (threadIdx.x == 0) cg_set_alpha(cg, tot);
+  const int ti = blockIdx.x * kMergeTiles + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  double dotv = 0;
+  if (ti < ntiles) {
+    const int tile = d.tile_list[ti];
+    const int node = tile * kTileNodes + lane;
+    MergeSrc<D> ms;
+    merge_sources<D>(tile, lane, d.nt, tl.ctile_slot, ms);
+    R acc = 0;
+    R val[1 << D];
+#pragma unroll
+    for (int j = 0; j < (1 << D); ++j)
+      val[j] = ms.slot[j] >= 0 ? tpart[(size_t)ms.slot[j] * RN + ms.rn[j]] : R(0);
+#pragma unroll
+    for (int j = 0; j < (1 << D); ++j) acc += val[j];
+    bool dof = d.gfree[node] & 0x80;
+    R Ti = T[node];
+    R o = dof ? d.cp / d.dt * d.gm[node] * Ti + acc : R(0);
+    out[node] = o;
+    if (dof) dotv = (double)Ti * (double)o;
   }
+  if (!cg) return;
+  double bs = block_sum(dotv, sh), tot;
+  if (grid_reduce<1>(&bs, npart, ctr, sh, &tot) && threadIdx.x == 0) cg_set_alpha(cg, tot);
 }
 
 // P2G merge and grid set-up (degrees of freedom, v^n, T^n, constraints, diagonals, heat
@@ -1151,9 +1172,14 @@ __global__ void __launch_bounds__(64) k_merge_p2g(Dev<R> d, TileLists tl, const 
   R v[NF];
 #pragma unroll
   for (int f = 0; f < NF; ++f) v[f] = 0;
-  for (int j = 0; j < ms.cnt; ++j) {
 #pragma unroll
-    for (int f = 0; f < NF; ++f) v[f] += tpart[((size_t)ms.slot[j] * NF + f) * RN + ms.rn[j]];
+  for (int j = 0; j < (1 << D); ++j) {
+    if (ms.slot[j] < 0) continue;
+    R t[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) t[f] = tpart[((size_t)ms.slot[j] * NF + f) * RN + ms.rn[j]];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) v[f] += t[f];
   }
   const R m = v[FI::M], W = v[FI::W], WT = v[FI::WT], E = v[FI::E], ET = v[FI::ET];
   const bool dof = m > R(0);
