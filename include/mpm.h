@@ -232,12 +232,19 @@ int mpm_solve_momentum(mpm_ctx* ctx, void* stream);
 /* Heat solve only (after mpm_p2g): CG on the heat system; T^ lands in MPM_F_THAT. */
 int mpm_solve_heat(mpm_ctx* ctx, void* stream);
 
-/* One full step for each of n_scenes scenes: p2g, momentum solve (implicit = 1:
- * backward Euler with Newton; implicit = 0: explicit, forces at y = x), heat solve when
- * enabled, g2p.  Particles are updated in place.  Synchronizes the stream.  Returns the
- * first non-OK status; per-scene status is in mpm_stats. */
+/* One full step for each of n_scenes scenes (Section 4, its list of steps): p2g,
+ * momentum solve (implicit = 1: backward Euler with Newton; implicit = 0: explicit,
+ * forces at y = x), heat solve when enabled, g2p.  Particles are updated in place.
+ * With more than one scene the scenes run concurrently: up to mpm_batch_config()
+ * scenes at a time, each on a worker thread with its own non-blocking stream (default
+ * priority) that waits for the work already queued on `stream`; the call returns when
+ * every scene is done and `stream` is ordered after them.  A scene's results do not
+ * depend on the batch it runs in (bitwise).  The contexts must be distinct.  Returns the
+ * first non-OK status in scene order; per-scene status is in mpm_stats. */
 int mpm_step(mpm_ctx* const* ctxs, mpm_particles* const* P, const mpm_surface* const* S,
              int32_t n_scenes, int32_t implicit, void* stream);
+/* Maximum number of scenes mpm_step advances at once (1..64, default 8; process-wide). */
+int mpm_batch_config(int32_t max_concurrent);
 
 /* Device pointer of a grid field of the last mpm_p2g / solve (see mpm_field). */
 int mpm_grid_view(mpm_ctx* ctx, int32_t field, void** out_ptr);

@@ -279,9 +279,16 @@ def mpm_step(scenes, Ps, Ss, implicit=True, check=True):
     parr = (C.POINTER(L.MpmParticles) * n)(*[C.pointer(p) for p in pstructs])
     sarr = (C.POINTER(L.MpmSurface) * n)(*[C.pointer(p) for p in sstructs])
     rc = lib.mpm_step(ctxs, parr, sarr, n, 1 if implicit else 0, scenes[0].stream())
-    if check:
-        _check(rc, lib, scenes[0].ctx if n == 1 else None)
+    if check and rc != L.MPM_OK:
+        bad = next((s for s in scenes if s.stats()["status"] != L.MPM_OK), scenes[0])
+        _check(rc, lib, bad.ctx)
     return rc
+
+
+def batch_config(max_concurrent):
+    """Maximum number of scenes mpm_step advances at once (process-wide)."""
+    lib = L.load()
+    _check(lib.mpm_batch_config(int(max_concurrent)), lib)
 
 
 # C-named functional aliases

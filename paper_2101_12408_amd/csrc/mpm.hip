@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <thread>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -100,6 +102,10 @@ struct mpm_ctx {
   int status = 0;
   mpm_stats stats{};
   std::string err;
+  // batch execution: the device the context lives on, its own stream and done event
+  int device = 0;
+  hipStream_t own = nullptr;
+  hipEvent_t own_done = nullptr;
 };
 
 namespace {
@@ -796,6 +802,7 @@ int mpm_ctx_create(const mpm_params* p, void* workspace, size_t ws_bytes, int64_
       layout<float>(c, c->ws);
       fill_params(c->d32, *p, c->nt);
     }
+    HIPCHK(hipGetDevice(&c->device));
     HIPCHK(hipHostMalloc((void**)&c->hbuf, 64 * sizeof(double), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&c->hint, 64 * sizeof(int), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&c->hcg, sizeof(CgScal), hipHostMallocDefault));
@@ -820,6 +827,11 @@ int mpm_ctx_create(const mpm_params* p, void* workspace, size_t ws_bytes, int64_
 int mpm_ctx_destroy(mpm_ctx* ctx) {
   if (!ctx) return MPM_EINVAL;
   for (hipEvent_t e : ctx->prof.ev) hipEventDestroy(e);
+  if (ctx->own) {
+    hipStreamSynchronize(ctx->own);
+    hipStreamDestroy(ctx->own);
+  }
+  if (ctx->own_done) hipEventDestroy(ctx->own_done);
   if (ctx->hbuf) hipHostFree(ctx->hbuf);
   if (ctx->hint) hipHostFree(ctx->hint);
   if (ctx->hcg) hipHostFree(ctx->hcg);
@@ -944,34 +956,84 @@ int mpm_solve_heat(mpm_ctx* ctx, void* stream) {
   return mpm_scene_status(ctx, stream);
 }
 
+}  // extern "C"
+
+namespace {
+
+std::atomic<int> g_batch_concurrency{8};
+
+int step_one(mpm_ctx* c, mpm_particles* P, const mpm_surface* S, int implicit, hipStream_t s) {
+  int rc = mpm_p2g(c, P, S, s);
+  if (rc == MPM_OK) {
+    rc = guarded(c, [&] {
+      dispatch(c, [&](auto Dc, auto Rv) {
+        constexpr int D = decltype(Dc)::value;
+        using R = decltype(Rv);
+        if (implicit) do_solve_momentum<D, R>(c, s);
+        else do_explicit<D, R>(c, s);
+        if (c->p.heat) do_solve_heat<D, R>(c, s);
+        do_g2p<D, R>(c, (const R*)c->vhat, c->p.heat ? (const R*)c->That : nullptr, P, s);
+      });
+    });
+  }
+  if (rc == MPM_OK) rc = check_launch(c);
+  int st = mpm_scene_status(c, s);
+  if (rc == MPM_OK) rc = st;
+  c->stats.status = rc;
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mpm_batch_config(int32_t max_concurrent) {
+  if (max_concurrent < 1 || max_concurrent > 64) return MPM_EINVAL;
+  g_batch_concurrency = max_concurrent;
+  return MPM_OK;
+}
+
 int mpm_step(mpm_ctx* const* ctxs, mpm_particles* const* P, const mpm_surface* const* S, int32_t n_scenes,
              int32_t implicit, void* stream) {
   if (!ctxs || !P || n_scenes < 0) return MPM_EINVAL;
+  for (int k = 0; k < n_scenes; ++k)
+    if (!ctxs[k] || !P[k]) return MPM_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  int first = MPM_OK;
-  for (int k = 0; k < n_scenes; ++k) {
-    mpm_ctx* c = ctxs[k];
-    if (!c) { if (first == MPM_OK) first = MPM_EINVAL; continue; }
-    int rc = mpm_p2g(c, P[k], S ? S[k] : nullptr, stream);
-    if (rc == MPM_OK) {
-      rc = guarded(c, [&] {
-        dispatch(c, [&](auto Dc, auto Rv) {
-          constexpr int D = decltype(Dc)::value;
-          using R = decltype(Rv);
-          if (implicit) do_solve_momentum<D, R>(c, s);
-          else do_explicit<D, R>(c, s);
-          if (c->p.heat) do_solve_heat<D, R>(c, s);
-          do_g2p<D, R>(c, (const R*)c->vhat, c->p.heat ? (const R*)c->That : nullptr, P[k], s);
+  std::vector<int> rcs(n_scenes, MPM_OK);
+  const int workers = std::min<int>(g_batch_concurrency.load(), n_scenes);
+  if (workers <= 1) {
+    for (int k = 0; k < n_scenes; ++k) rcs[k] = step_one(ctxs[k], P[k], S ? S[k] : nullptr, implicit, s);
+  } else {
+    // every scene's stream starts after the work already queued on the caller's stream
+    hipEvent_t ready = nullptr;
+    if (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess) return MPM_EHIP;
+    if (hipEventRecord(ready, s) != hipSuccess) { hipEventDestroy(ready); return MPM_EHIP; }
+    std::atomic<int> next{0};
+    auto work = [&]() {
+      for (int k = next.fetch_add(1); k < n_scenes; k = next.fetch_add(1)) {
+        mpm_ctx* c = ctxs[k];
+        int rc = guarded(c, [&] {
+          HIPCHK(hipSetDevice(c->device));
+          if (!c->own) HIPCHK(hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking));
+          if (!c->own_done) HIPCHK(hipEventCreateWithFlags(&c->own_done, hipEventDisableTiming));
+          HIPCHK(hipStreamWaitEvent(c->own, ready, 0));
         });
-      });
-    }
-    if (rc == MPM_OK) rc = check_launch(c);
-    int st = mpm_scene_status(c, stream);
-    if (rc == MPM_OK) rc = st;
-    c->stats.status = rc;
-    if (first == MPM_OK && rc != MPM_OK) first = rc;
+        if (rc == MPM_OK) rc = step_one(c, P[k], S ? S[k] : nullptr, implicit, c->own);
+        if (rc != MPM_EHIP && hipEventRecord(c->own_done, c->own) != hipSuccess) rc = MPM_EHIP;
+        rcs[k] = rc;
+      }
+    };
+    std::vector<std::thread> pool;
+    for (int w = 1; w < workers; ++w) pool.emplace_back(work);
+    work();
+    for (auto& t : pool) t.join();
+    for (int k = 0; k < n_scenes; ++k)
+      if (ctxs[k]->own_done) hipStreamWaitEvent(s, ctxs[k]->own_done, 0);
+    hipEventDestroy(ready);
   }
-  return first;
+  for (int k = 0; k < n_scenes; ++k)
+    if (rcs[k] != MPM_OK) return rcs[k];
+  return MPM_OK;
 }
 
 int mpm_grid_view(mpm_ctx* ctx, int32_t field, void** out_ptr) {
