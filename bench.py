@@ -201,6 +201,41 @@ def copy_calibration(mib=512, reps=5):
     log(f"copy calibration: {reps} copies of {mib} MiB")
 
 
+def run_serving(count, rate, precision, concurrency, budget_bytes):
+    """The serving stream (Poisson arrivals at `rate`, droplets on n in {16,...,96}, one
+    implicit step each) through the native serving runtime.  Latency is measured from
+    each request's scheduled arrival to its completion (host sampling, admission,
+    upload, step, download)."""
+    import mpm_scenes as sc
+    from paper_2101_12408_amd import api
+    reqs = sc.serving_stream(count=count, rate=rate, seed=5)
+    si = sc.ServingInputs()
+    inputs = [(si.params(r), si.soa(r)) for r in reqs]       # kept alive: the server borrows them
+    srv = api.Server(budget_bytes, max_concurrent=concurrency)
+    clock = api.Server.clock
+    t0 = clock() + 0.05
+    for i, (r, (p, soa)) in enumerate(zip(reqs, inputs)):
+        wait = t0 + r["arrival"] - clock()
+        if wait > 0:
+            time.sleep(wait)
+        srv.submit(i, p, soa=soa, borrow=True, precision=precision)
+    srv.wait(-1.0)
+    comps = srv.poll(cap=count + 16)
+    info = srv.info()
+    srv.close()
+    lat = np.array([c["t_done"] - (t0 + reqs[c["id"]]["arrival"]) for c in comps]) * 1e3
+    done = max(c["t_done"] for c in comps)
+    ps = sum(c["n_part"] * c["steps_done"] for c in comps)
+    failed = sum(1 for c in comps if c["status"] != 0)
+    log(f"serving {precision} x{concurrency}: {count} requests, p50 {np.percentile(lat, 50):.1f} ms, "
+        f"p99 {np.percentile(lat, 99):.1f} ms, {ps / (done - t0):.3e} particle-steps/s, failed {failed}")
+    return dict(requests=count, arrival_rate_per_s=rate, precision=precision, max_concurrent=concurrency,
+                budget_gb=round(budget_bytes / 2 ** 30, 2), p50_ms=round(float(np.percentile(lat, 50)), 2),
+                p99_ms=round(float(np.percentile(lat, 99)), 2), mean_ms=round(float(lat.mean()), 2),
+                particle_steps_per_s=round(ps / (done - t0), 1), makespan_s=round(done - t0, 3),
+                peak_running=info["peak_running"], peak_gb=round(info["peak_bytes"] / 2 ** 30, 3), failed=failed)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -210,6 +245,9 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=3, help="steps of the FP64 GPU comparison run (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=512,
+                    help="requests of the serving stream (0: skip the serving measurement)")
+    ap.add_argument("--serving-concurrency", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (PMC traffic calibration)")
     args = ap.parse_args()
@@ -252,6 +290,15 @@ def main():
         v64 = r64["N"] * args.fp64_steps / r64["elapsed"]
         fp64 = dict(value=round(v64, 1), unit="particle-steps/s", steps=args.fp64_steps,
                     speedup_mixed_over_fp64=round(value / v64, 3))
+    serving = None
+    if args.serving_requests > 0:
+        free, _ = torch.cuda.mem_get_info()
+        budget = int(min(0.8 * free, 64 * 2 ** 30))
+        mixed = run_serving(args.serving_requests, 200.0, "mixed", args.serving_concurrency, budget)
+        base = run_serving(args.serving_requests, 200.0, "fp64", 1, budget)
+        serving = dict(batched=mixed, one_at_a_time_fp64=base,
+                       throughput_speedup=round(mixed["particle_steps_per_s"] / base["particle_steps_per_s"], 3),
+                       p99_speedup=round(base["p99_ms"] / mixed["p99_ms"], 3))
     cpu = None if args.no_cpu_baseline else cpu_baseline()
     if cpu:
         cpu["value"] = round(cpu["value"], 1)
@@ -278,6 +325,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fp64_gpu": fp64,
+        "serving": serving,
     }
     line.update(out_extra)
     print(json.dumps(line), flush=True)

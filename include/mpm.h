@@ -271,6 +271,72 @@ int mpm_sample_surface(int32_t dim, int32_t n, const double* x, int64_t n_part, 
                        const double* label_hi, double* s, double* dA, int32_t* label, int64_t cap,
                        int64_t* out_n);
 
+/* ---- Serving: continuous batching of step requests -------------------------------
+ * A server owns max_concurrent worker threads, each with its own non-blocking stream
+ * (default priority), and sub-allocates a caller-provided device arena (256-byte
+ * aligned; the library allocates no device memory).  Requests are admitted strictly in
+ * arrival order, each as soon as a worker is free and the arena holds its context
+ * workspace, particle and surface buffers; a request larger than the whole arena
+ * completes with MPM_EBUDGET.  A worker draws each step's surface samples on the host
+ * (mpm_sample_surface), runs the steps with mpm_step, downloads the final particle state
+ * (in the request's particle order) and frees the memory.  Several admitted requests run
+ * at once and their work overlaps on the device; each result is bitwise the same as
+ * stepping the scene alone.  All entry points are host calls and thread-safe. */
+typedef struct mpm_server mpm_server;
+
+typedef struct mpm_request {
+  int64_t id;               /* caller's id (unique among results not yet fetched)          */
+  mpm_params params;
+  int32_t n_steps;          /* steps to advance (>= 1)                                     */
+  int32_t implicit;         /* 1: implicit steps, 0: explicit                              */
+  int32_t keep_result;      /* 1: keep the final state for mpm_server_result               */
+  int32_t borrow;           /* 1: read the host arrays in place (the caller keeps them
+                               unchanged until the request completes); 0: copy at submit  */
+  int64_t n_part;
+  uint64_t seed;            /* sampler seed; step k of the request draws with step index   */
+  uint64_t first_step;      /* first_step + k                                              */
+  double ls_radius;         /* sampler radius and density (<= 0: the defaults of           */
+  double sample_density;    /* mpm_sample_surface)                                          */
+  double label_lo[3], label_hi[3];
+  /* host particle state, double, SoA [comp][n_part] (x, v, gradT: dim; A: dim*dim; the
+   * rest 1); copied by mpm_server_submit unless borrow */
+  const double *x, *v, *A, *J, *V0, *m, *T, *gradT;
+} mpm_request;
+
+typedef struct mpm_completion {
+  int64_t id;
+  int32_t status;           /* MPM_OK or the request's first error                         */
+  int32_t steps_done;
+  double t_submit, t_admit, t_done;   /* mpm_server_clock() seconds                        */
+  int64_t n_part, n_surf;   /* n_surf of the last step                                     */
+  int64_t bytes;            /* arena bytes held while resident                             */
+  int32_t newton_iters, cg_iters;     /* summed over the request's steps                   */
+} mpm_completion;
+
+typedef struct mpm_server_info {
+  int64_t submitted, completed, rejected, queued, running;
+  int64_t arena_bytes, bytes_in_use, peak_bytes;
+  int32_t peak_running, pad_;
+} mpm_server_info;
+
+/* Seconds of a monotonic clock (the time base of mpm_completion). */
+double mpm_server_clock(void);
+int mpm_server_create(void* arena, size_t arena_bytes, int32_t max_concurrent, mpm_server** out);
+/* Queues a request (copies its host state unless borrow); returns at once. */
+int mpm_server_submit(mpm_server* srv, const mpm_request* req);
+/* Completions since the last poll, oldest first (at most cap; *n_out receives the count). */
+int mpm_server_poll(mpm_server* srv, mpm_completion* out, int32_t cap, int32_t* n_out);
+/* Blocks until nothing is queued or running (timeout_s < 0: no limit; MPM_ENOCONV on
+ * timeout). */
+int mpm_server_wait(mpm_server* srv, double timeout_s);
+/* Final state of a completed request kept with keep_result (host double, SoA, request
+ * particle order; any pointer may be NULL); releases it.  Returns the request's status. */
+int mpm_server_result(mpm_server* srv, int64_t id, double* x, double* v, double* A, double* J,
+                      double* T, double* gradT);
+int mpm_server_info_get(mpm_server* srv, mpm_server_info* out);
+/* Finishes every queued request, then stops the workers. */
+int mpm_server_destroy(mpm_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

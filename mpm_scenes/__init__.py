@@ -182,6 +182,37 @@ def droplet3d(n, seed, gamma0, grad, radius=0.24, dt=5e-4):
                 name=f"droplet{n}", steps=1)
 
 
+class ServingInputs:
+    """Inputs of a serving stream without rebuilding a lattice per request: one droplet
+    lattice per grid size (seed = n), and per request its own parameters (gamma0, sampler
+    seed) and linear temperature field.  soa(req) returns the host SoA double arrays
+    (x, v, A, J, V0, m shared per size; T, gradT per request)."""
+
+    def __init__(self, radius=0.24):
+        self.radius = radius
+        self.base = {}
+
+    def _lattice(self, n):
+        if n not in self.base:
+            S = droplet3d(n, n, 0.05, [0.0, 0.0, 0.0], radius=self.radius)
+            P = S["particles"]
+            N = len(P["m"])
+            self.base[n] = dict(x=np.ascontiguousarray(P["x"].T), v=np.zeros((3, N)), A=np.zeros((9, N)),
+                                J=np.ones(N), V0=np.ascontiguousarray(P["V0"]), m=np.ascontiguousarray(P["m"]))
+        return self.base[n]
+
+    def params(self, req):
+        return make_params(dim=3, n=req["n"], dt=5e-4, bulk=1e4, g0=req["gamma0"], g1=-1.5e-4, gT0=300.0,
+                           heat=1, cp=1.0, K=0.1, h=0.0, b=0.0, T_amb=300.0, seed=req["seed"])
+
+    def soa(self, req):
+        b = self._lattice(req["n"])
+        grad = np.asarray(req["grad"], np.float64)
+        T = 300.0 + (b["x"] - 0.5).T @ grad
+        gT = np.ascontiguousarray(np.repeat(grad[:, None], b["x"].shape[1], axis=1))
+        return dict(b, T=np.ascontiguousarray(T), gradT=gT)
+
+
 def serving_stream(count=512, rate=200.0, seed=5, sizes=(16, 32, 48, 64, 96)):
     """Request stream: exponential inter-arrival times (mean 1/rate), grid edge uniform
     in sizes, gamma0 ~ U[0.02,0.08], temperature gradient = random direction x U[0,125]."""

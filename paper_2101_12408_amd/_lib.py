@@ -45,6 +45,26 @@ class MpmStats(C.Structure):
         ("n_tiles", C.c_int64)]
 
 
+class MpmRequest(C.Structure):
+    _fields_ = [("id", C.c_int64), ("params", MpmParams), ("n_steps", C.c_int32), ("implicit", C.c_int32),
+                ("keep_result", C.c_int32), ("borrow", C.c_int32), ("n_part", C.c_int64), ("seed", C.c_uint64),
+                ("first_step", C.c_uint64), ("ls_radius", C.c_double), ("sample_density", C.c_double),
+                ("label_lo", C.c_double * 3), ("label_hi", C.c_double * 3)] + [
+        (k, C.c_void_p) for k in ("x", "v", "A", "J", "V0", "m", "T", "gradT")]
+
+
+class MpmCompletion(C.Structure):
+    _fields_ = [("id", C.c_int64), ("status", C.c_int32), ("steps_done", C.c_int32), ("t_submit", C.c_double),
+                ("t_admit", C.c_double), ("t_done", C.c_double), ("n_part", C.c_int64), ("n_surf", C.c_int64),
+                ("bytes", C.c_int64), ("newton_iters", C.c_int32), ("cg_iters", C.c_int32)]
+
+
+class MpmServerInfo(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in ("submitted", "completed", "rejected", "queued", "running", "arena_bytes",
+                                         "bytes_in_use", "peak_bytes")] + [("peak_running", C.c_int32),
+                                                                          ("pad_", C.c_int32)]
+
+
 EXPORTS = {
     "mpm_params_default": (C.c_int, [C.POINTER(MpmParams), C.c_int32, C.c_int32]),
     "mpm_workspace_bytes": (C.c_int, [C.POINTER(MpmParams), C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]),
@@ -68,6 +88,14 @@ EXPORTS = {
     "mpm_timing": (C.c_int, [C.c_void_p, C.c_int32]),
     "mpm_timing_read": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "mpm_scene_status": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "mpm_server_clock": (C.c_double, []),
+    "mpm_server_create": (C.c_int, [C.c_void_p, C.c_size_t, C.c_int32, C.POINTER(C.c_void_p)]),
+    "mpm_server_submit": (C.c_int, [C.c_void_p, C.POINTER(MpmRequest)]),
+    "mpm_server_poll": (C.c_int, [C.c_void_p, C.POINTER(MpmCompletion), C.c_int32, C.POINTER(C.c_int32)]),
+    "mpm_server_wait": (C.c_int, [C.c_void_p, C.c_double]),
+    "mpm_server_result": (C.c_int, [C.c_void_p, C.c_int64] + [C.c_void_p] * 6),
+    "mpm_server_info_get": (C.c_int, [C.c_void_p, C.POINTER(MpmServerInfo)]),
+    "mpm_server_destroy": (C.c_int, [C.c_void_p]),
     "mpm_sample_surface": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_int64, C.c_double, C.c_double,
                                      C.c_uint64, C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]),

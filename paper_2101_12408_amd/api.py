@@ -76,7 +76,7 @@ def sample_surface(x, params, step=0):
     radius = float(params.get("ls_radius") or 0.0)
     density = float(params.get("sample_density") or 0.0)
     seed = int(params.get("seed", 0))
-    cap = max(16, int(64 * N) + 1024)
+    cap = max(16, 2 * N + 4096)    # grown to the exact count if the first call overflows
     for _ in range(3):
         s = np.zeros((dim, cap))
         dA = np.zeros((dim, cap))
@@ -310,3 +310,93 @@ def mpm_heat_apply(scene, T, out):
 
 def mpm_g2p(scene, vhat, That, P):
     return scene.g2p(vhat, That, P)
+
+
+class Server:
+    """Serving runtime (mpm_server_*): continuous batching of step requests over a device
+    arena of budget_bytes; max_concurrent requests run at once on their own streams."""
+
+    def __init__(self, budget_bytes, max_concurrent=8, device="cuda"):
+        import torch
+        self.lib = L.load()
+        self.arena = torch.empty(int(budget_bytes) + 256, dtype=torch.uint8, device=device)
+        base = self.arena.data_ptr()
+        base += (-base) % 256
+        srv = C.c_void_p()
+        _check(self.lib.mpm_server_create(C.c_void_p(base), int(budget_bytes), int(max_concurrent), C.byref(srv)),
+               self.lib)
+        self.srv = srv
+
+    @staticmethod
+    def clock():
+        return L.load().mpm_server_clock()
+
+    @staticmethod
+    def soa(P, dim):
+        """Host particle dict (x (N,d), v, A (N,d,d), J, V0, m, T, gradT) as the contiguous
+        SoA double arrays a request reads."""
+        N, d = len(P["m"]), dim
+        soa = dict(x=np.asarray(P["x"], np.float64).reshape(N, d).T, v=np.asarray(P["v"], np.float64).reshape(N, d).T,
+                   A=np.asarray(P["A"], np.float64).reshape(N, d * d).T, J=np.asarray(P["J"], np.float64),
+                   V0=np.asarray(P["V0"], np.float64), m=np.asarray(P["m"], np.float64),
+                   T=np.asarray(P["T"], np.float64), gradT=np.asarray(P["gradT"], np.float64).reshape(N, d).T)
+        return {k: np.ascontiguousarray(v) for k, v in soa.items()}
+
+    def submit(self, rid, params, P=None, n_steps=1, precision="mixed", implicit=True, keep_result=False,
+               first_step=0, soa=None, borrow=False):
+        """Queues one request.  P: host particle dict, or soa: arrays from Server.soa().
+        borrow: the server reads soa in place; the caller keeps the arrays alive and
+        unchanged until the request completes."""
+        p = make_params(params, precision)
+        d = int(p.dim)
+        if soa is None:
+            soa = self.soa(P, d)
+            borrow = False
+        N = len(soa["m"])
+        r = L.MpmRequest()
+        r.id, r.params, r.n_steps, r.implicit, r.keep_result = int(rid), p, int(n_steps), int(bool(implicit)), \
+            int(bool(keep_result))
+        r.borrow = int(bool(borrow))
+        r.n_part, r.seed, r.first_step = N, int(params.get("seed", 0)), int(first_step)
+        r.ls_radius = float(params.get("ls_radius") or 0.0)
+        r.sample_density = float(params.get("sample_density") or 0.0)
+        lo = list(params.get("label_lo", (0, 0, 0)))[:3] + [0.0] * 3
+        hi = list(params.get("label_hi", (0, 0, 0)))[:3] + [0.0] * 3
+        r.label_lo = (C.c_double * 3)(*lo[:3])
+        r.label_hi = (C.c_double * 3)(*hi[:3])
+        for k, v in soa.items():
+            setattr(r, k, v.ctypes.data)
+        _check(self.lib.mpm_server_submit(self.srv, C.byref(r)), self.lib)   # copies the arrays
+
+    def poll(self, cap=4096):
+        out = (L.MpmCompletion * cap)()
+        n = C.c_int32(0)
+        _check(self.lib.mpm_server_poll(self.srv, out, cap, C.byref(n)), self.lib)
+        return [{f: getattr(out[k], f) for f, _ in L.MpmCompletion._fields_} for k in range(n.value)]
+
+    def wait(self, timeout=-1.0):
+        return self.lib.mpm_server_wait(self.srv, float(timeout))
+
+    def result(self, rid, N, dim):
+        x, v = np.zeros((dim, N)), np.zeros((dim, N))
+        A, gT = np.zeros((dim * dim, N)), np.zeros((dim, N))
+        J, T = np.zeros(N), np.zeros(N)
+        rc = self.lib.mpm_server_result(self.srv, int(rid), x.ctypes.data, v.ctypes.data, A.ctypes.data,
+                                        J.ctypes.data, T.ctypes.data, gT.ctypes.data)
+        return rc, dict(x=x.T.copy(), v=v.T.copy(), A=A.T.reshape(N, dim, dim).copy(), J=J, T=T, gradT=gT.T.copy())
+
+    def info(self):
+        i = L.MpmServerInfo()
+        _check(self.lib.mpm_server_info_get(self.srv, C.byref(i)), self.lib)
+        return {f: getattr(i, f) for f, _ in L.MpmServerInfo._fields_ if f != "pad_"}
+
+    def close(self):
+        if self.srv:
+            self.lib.mpm_server_destroy(self.srv)
+            self.srv = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -26,7 +26,7 @@ def hipcc():
 
 
 def build(verbose=False):
-    srcs = [os.path.join(CSRC, "mpm.hip"), os.path.join(CSRC, "sampler.cpp")]
+    srcs = [os.path.join(CSRC, "mpm.hip"), os.path.join(CSRC, "sampler.cpp"), os.path.join(CSRC, "serve.cpp")]
     tmp = OUT + ".tmp"
     cmd = [hipcc(), "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-shared",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

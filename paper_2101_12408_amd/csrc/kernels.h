@@ -50,7 +50,7 @@ constexpr int kPartSlot = kRedSlot;  // partial sums per reduction slot
 // Cell sort: keys, counts, slots, per-cell order fix-up.
 // ======================================================================================
 template <int D, typename R>
-__global__ void k_cell_keys(const R* pos, int cnt, int n, int nt, R fn, int* key, int* ccount,
+__global__ void k_cell_keys(const R* pos, int cnt, int n, int nt, R fn, int* key, int* iota, int* ccount,
                             int* status) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= cnt) return;
@@ -62,13 +62,15 @@ __global__ void k_cell_keys(const R* pos, int cnt, int n, int nt, R fn, int* key
   if (bad) flag_status(status, ST_DOMAIN);
   int k = (int)tiled_index<D>(c, nt);
   key[i] = k;
+  iota[i] = i;
   atomicAdd(&ccount[k], 1);
 }
 
 constexpr int kScanT = 256, kScanI = 16, kScanBlock = kScanT * kScanI;
 
-// Exclusive scan of in[0,len) into out[0,len), block totals into bsum.
-__global__ void k_scan_local(const int* in, int* out, int len, int* bsum) {
+// Exclusive scan of in[0,len) into out[0,len), block totals into bsum; with zero_in the
+// input is cleared as it is read (the cell counters start the next sort at zero).
+__global__ void k_scan_local(int* in, int* out, int len, int* bsum, int zero_in) {
   __shared__ int sh[kScanT];
   int base = blockIdx.x * kScanBlock + threadIdx.x * kScanI;
   int v[kScanI];
@@ -78,6 +80,11 @@ __global__ void k_scan_local(const int* in, int* out, int len, int* bsum) {
     int idx = base + k;
     v[k] = idx < len ? in[idx] : 0;
     s += v[k];
+  }
+  if (zero_in) {
+#pragma unroll
+    for (int k = 0; k < kScanI; ++k)
+      if (base + k < len && v[k]) in[base + k] = 0;
   }
   sh[threadIdx.x] = s;
   __syncthreads();
@@ -133,20 +140,10 @@ __global__ void k_scan_add(int* out, int len, const int* bsum) {
   out[idx] += bsum[idx / kScanBlock];
 }
 
-// slot = start[key] + (remaining count - 1); leaves ccount at zero.
-__global__ void k_cell_scatter(const int* key, int cnt, const int* start, int* ccount, int* perm) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= cnt) return;
-  int k = key[i];
-  int slot = start[k] + atomicSub(&ccount[k], 1) - 1;
-  perm[slot] = i;
-}
-
-// Sort each segment of distinct values ascending; the segments are the runs of equal
-// key[vals[s]] in vals[0..cnt), starting at start[key].  Makes the slot order independent
-// of atomic arrival order.  One thread per slot: only a segment's first slot works, so
-// the launch scales with the number of points, not of cells.  Segments of up to 16 values
-// are ranked in registers (independent loads); longer ones use an insertion sort in memory.
+// Sort a segment of distinct values ascending (the group lists of the split, filled by
+// atomics, are put in sample order so that nothing depends on atomic arrival order).
+// Segments of up to 16 values are ranked in registers (independent loads); longer ones use
+// an insertion sort in memory.
 constexpr int kSegReg = 16;
 MPM_DEV void sort_segment(int b, int e, int* vals) {
   int n = e - b;
@@ -170,15 +167,6 @@ MPM_DEV void sort_segment(int b, int e, int* vals) {
     while (j >= b && vals[j] > v) { vals[j + 1] = vals[j]; --j; }
     vals[j + 1] = v;
   }
-}
-
-// Segments given by keys (cell sort): key of slot s is key[vals[s]].
-__global__ void k_segment_order_keys(const int* key, const int* start, int cnt, int* vals) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= cnt) return;
-  int k = key[vals[s]];
-  if (start[k] != s) return;
-  sort_segment(s, start[k + 1], vals);
 }
 
 // Segments given directly: [start[c], start[c+1]) for c < nseg.

@@ -11,6 +11,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprim/device/device_radix_sort.hpp>
+
 #include "tiles.h"
 
 using namespace mpm;
@@ -92,6 +94,11 @@ struct mpm_ctx {
   double* scal = nullptr;
   CgScal* cg = nullptr;
   unsigned* ctr = nullptr;       // grid-reduction counters
+  // radix sort: alternate key / value buffers and scratch
+  int* sort_kalt = nullptr;
+  int* sort_valt = nullptr;
+  void* sort_tmp = nullptr;
+  size_t sort_tmp_bytes = 0;
   // pinned host mirror
   double* hbuf = nullptr;
   int* hint = nullptr;
@@ -151,6 +158,11 @@ void prof_collect(mpm_ctx* c) {
     }                                                             \
   } while (0)
 
+// Scratch reserved for the radix sort of n pairs (histograms and look-back state; the
+// key/value ping-pong buffers are separate).  Checked against the sort's own query when
+// a context is created.
+size_t sort_scratch_bytes(int64_t n) { return ((size_t)1 << 20) + (size_t)n * 2; }
+
 template <typename R>
 size_t layout(mpm_ctx* c, char* base) {
   Bump b{base};
@@ -195,6 +207,11 @@ size_t layout(mpm_ctx* c, char* base) {
   d.scal = b.take<double>(kScalDoubles);
   CgScal* cg = b.take<CgScal>(2);
   unsigned* ctr = b.take<unsigned>((size_t)CTR_COUNT * kCtrSite);
+  const int64_t NMX = std::max(NP, NS);
+  int* sort_kalt = b.take<int>(NMX);
+  int* sort_valt = b.take<int>(NMX);
+  const size_t sort_tmp_bytes = sort_scratch_bytes(NMX);
+  void* sort_tmp = b.take<char>(sort_tmp_bytes);
   d.status = misc;
   if (base) {
     c->vhat = vecs[0]; c->vtrial = vecs[1]; c->grad = vecs[2]; c->delta = vecs[3]; c->r = vecs[4];
@@ -205,6 +222,7 @@ size_t layout(mpm_ctx* c, char* base) {
     c->ctile_rng = ctile_rng;
     c->tpart = tpart;
     c->part = d.part; c->scal = d.scal; c->cg = cg; c->ctr = ctr;
+    c->sort_kalt = sort_kalt; c->sort_valt = sort_valt; c->sort_tmp = sort_tmp; c->sort_tmp_bytes = sort_tmp_bytes;
     if constexpr (sizeof(R) == 8) c->d64 = d; else c->d32 = d;
   }
   return b.off + 256;
@@ -239,27 +257,40 @@ void check_params(const mpm_params* p) {
 }
 
 // ---- exclusive scan of len ints: out[0..len) and out[len] = total ----------------------
-void scan(mpm_ctx* c, const int* in, int* out, int len, hipStream_t s) {
+void scan(mpm_ctx* c, int* in, int* out, int len, hipStream_t s, bool zero_in = false) {
   int nb = cdiv(len, kScanBlock);
   if (nb > kScanBlock) throw ApiError{MPM_EINVAL, "scan length above 2^24"};
-  if (len > 0) LAUNCH(c, MPM_K_SORT, k_scan_local, dim3(nb), dim3(kScanT), 0, s, in, out, len, c->scan_bsum);
+  if (len > 0)
+    LAUNCH(c, MPM_K_SORT, k_scan_local, dim3(nb), dim3(kScanT), 0, s, in, out, len, c->scan_bsum, (int)zero_in);
   else LAUNCH(c, MPM_K_SORT, k_fill_i32, dim3(1), dim3(1), 0, s, c->scan_bsum, 0, (int64_t)1);
   LAUNCH(c, MPM_K_SORT, k_scan_sums, dim3(1), dim3(kScanT), 0, s, c->scan_bsum, std::max(nb, 1), out + len);
   if (len > 0) LAUNCH(c, MPM_K_SORT, k_scan_add, dim3(cdiv(len, 256)), dim3(256), 0, s, out, len, (const int*)c->scan_bsum);
 }
 
-// Stable cell sort of cnt points: perm (sorted slot -> input index) and start[nn+1].
+int key_bits(int64_t nn) {
+  int b = 1;
+  while ((int64_t(1) << b) < nn) ++b;
+  return b;
+}
+
+// Stable cell sort of cnt points: perm (sorted slot -> input index) and start[nn+1].  The
+// cell counts give the dense cell starts; a stable LSD radix sort of (cell key, input
+// index) gives the order, so points of one cell stay in input order.
 template <int D, typename R>
 void cell_sort(mpm_ctx* c, Dev<R>& d, const R* pos, int cnt, int* key, int* perm, int* start, hipStream_t s) {
   if (cnt > 0)
     LAUNCH(c, MPM_K_SORT, (k_cell_keys<D, R>), dim3(cdiv(cnt, 256)), dim3(256), 0, s, pos, cnt, d.n, d.nt, d.fn, key,
-                       d.ccount, d.status);
-  scan(c, d.ccount, start, d.nn, s);
-  if (cnt > 0) {
-    LAUNCH(c, MPM_K_SORT, k_cell_scatter, dim3(cdiv(cnt, 256)), dim3(256), 0, s, (const int*)key, cnt,
-                       (const int*)start, d.ccount, perm);
-    LAUNCH(c, MPM_K_SORT, k_segment_order_keys, dim3(cdiv(cnt, 256)), dim3(256), 0, s, (const int*)key,
-           (const int*)start, cnt, perm);
+           perm, d.ccount, d.status);
+  scan(c, d.ccount, start, d.nn, s, true);
+  if (cnt > 1) {
+    rocprim::double_buffer<int> kb(key, c->sort_kalt), vb(perm, c->sort_valt);
+    size_t bytes = c->sort_tmp_bytes;
+    hipEvent_t stop = nullptr;
+    if (c->prof.on) prof_begin(c, MPM_K_SORT, s, &stop);
+    HIPCHK(rocprim::radix_sort_pairs(c->sort_tmp, bytes, kb, vb, (size_t)cnt, 0, key_bits(d.nn), s));
+    if (stop) HIPCHK(hipEventRecord(stop, s));
+    if (vb.current() != perm)
+      HIPCHK(hipMemcpyAsync(perm, vb.current(), (size_t)cnt * sizeof(int), hipMemcpyDeviceToDevice, s));
   }
 }
 
@@ -803,6 +834,16 @@ int mpm_ctx_create(const mpm_params* p, void* workspace, size_t ws_bytes, int64_
       fill_params(c->d32, *p, c->nt);
     }
     HIPCHK(hipGetDevice(&c->device));
+    {
+      // the reserved sort scratch must cover what the sort asks for at full capacity
+      size_t need_sort = 0;
+      const int64_t nmx = std::max<int64_t>(std::max<int64_t>(cap_part, cap_surf), 1);
+      rocprim::double_buffer<int> kb(c->sort_kalt, c->sort_kalt), vb(c->sort_valt, c->sort_valt);
+      HIPCHK(rocprim::radix_sort_pairs(nullptr, need_sort, kb, vb, (size_t)nmx, 0, key_bits(c->nn), (hipStream_t)0));
+      if (need_sort > c->sort_tmp_bytes)
+        throw ApiError{MPM_ENOMEM, "radix sort scratch (" + std::to_string(need_sort) + " B) above the reserve (" +
+                                       std::to_string(c->sort_tmp_bytes) + " B)"};
+    }
     HIPCHK(hipHostMalloc((void**)&c->hbuf, 64 * sizeof(double), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&c->hint, 64 * sizeof(int), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&c->hcg, sizeof(CgScal), hipHostMallocDefault));

@@ -63,28 +63,42 @@ void bin(Grid& g) {
   for (int64_t p = 0; p < g.np; ++p) g.order[cur[key[p]]++] = (int)p;
 }
 
-// Exact nearest-particle distance of node i (valid when a particle lies within 2.5 dx).
+// Exact nearest-particle distance of node i over the particles in the cells within 3
+// cells of the node's cell (the level set is only needed near the particles).  Searched
+// in shells of growing Chebyshev radius R: every particle outside the shells searched so
+// far is at least (R + 1/2) dx away (the node sits at its cell's centre), so the search
+// stops once the best distance is within that bound; the minimum is the same as the
+// full 7^d search.
 double node_dist(const Grid& g, const int* i) {
-  double pos[3];
+  double pos[3] = {0, 0, 0};
   for (int a = 0; a < g.dim; ++a) pos[a] = (i[a] + 0.5) * g.dx;
   double best = 1e300;
-  int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-  for (int a = 0; a < g.dim; ++a) { lo[a] = std::max(i[a] - 3, 0); hi[a] = std::min(i[a] + 3, g.n - 1); }
-  for (int z = lo[2]; z <= hi[2]; ++z)
-    for (int y = lo[1]; y <= hi[1]; ++y)
-      for (int x = lo[0]; x <= hi[0]; ++x) {
-        int c[3] = {x, y, z};
-        int64_t ci = g.cell(c);
-        for (int k = g.start[ci]; k < g.start[ci + 1]; ++k) {
-          int p = g.order[k];
-          double d2 = 0;
-          for (int a = 0; a < g.dim; ++a) {
-            double t = pos[a] - g.x[a * g.np + p];
-            d2 += t * t;
-          }
-          best = std::min(best, d2);
-        }
+  auto visit_cell = [&](const int* c) {
+    int64_t ci = g.cell(c);
+    for (int k = g.start[ci]; k < g.start[ci + 1]; ++k) {
+      int p = g.order[k];
+      double d2 = 0;
+      for (int a = 0; a < g.dim; ++a) {
+        double t = pos[a] - g.x[a * g.np + p];
+        d2 += t * t;
       }
+      best = std::min(best, d2);
+    }
+  };
+  for (int R = 0; R <= 3; ++R) {
+    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int a = 0; a < g.dim; ++a) { lo[a] = std::max(i[a] - R, 0); hi[a] = std::min(i[a] + R, g.n - 1); }
+    for (int z = lo[2]; z <= hi[2]; ++z)
+      for (int y = lo[1]; y <= hi[1]; ++y)
+        for (int x = lo[0]; x <= hi[0]; ++x) {
+          int c[3] = {x, y, z};
+          int ring = 0;
+          for (int a = 0; a < g.dim; ++a) ring = std::max(ring, std::abs(c[a] - i[a]));
+          if (ring == R) visit_cell(c);
+        }
+    const double bound = (R + 0.5) * g.dx;
+    if (best <= bound * bound) break;
+  }
   return std::sqrt(best);
 }
 

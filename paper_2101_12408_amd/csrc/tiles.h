@@ -354,15 +354,24 @@ MPM_DEV void lane_nodes(const R* W, const R* DW, int k0, int k1, R (&wn)[3], R (
   }
 }
 
+// LDS of the tile kernels: the point payloads of a chunk and the buffers of the final
+// cell-to-region reduction are never live together, so they share storage.  Keeping a
+// 9-wave block near 1/3 of the 160 KB lets three blocks (27 of the CU's 32 wave slots)
+// reside per CU.
 template <int D, typename R>
 struct StressLds {
   static constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
-  static constexpr int CH = sizeof(R) == 8 ? NT / 4 : NT / 2; // points per chunk (2 blocks per CU)
+  static constexpr int CH = sizeof(R) == 8 ? NT / 4 : NT / 2; // points per chunk
   static constexpr int PW = 6 * D + D * D;                  // w, dw tables + stress
   R u[RN * D];
-  R pt[CH * PW];
-  R cellpart[64 * 27 * D];
-  double red[16];
+  union {
+    R pt[CH * PW];
+    struct {
+      R cellpart[64 * 27 * D];
+      R reg[RN * D];
+    } red;
+  } x;
+  double bsum[16];
 };
 
 template <int D, typename R, int MODE>
@@ -489,7 +498,7 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT) k_tile_stress(Dev<R> d, TileList
 #pragma unroll
           for (int b = 0; b < D; ++b) Sq[a][b] = sc * Q[a][b];
       }
-      R* P = &sm.pt[t * PW];
+      R* P = &sm.x.pt[t * PW];
 #pragma unroll
       for (int a = 0; a < D; ++a)
 #pragma unroll
@@ -506,7 +515,7 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT) k_tile_stress(Dev<R> d, TileList
       for (int pass = 0; pass < 2; ++pass) {
         int b0 = max(pass == 0 ? cpb : csb, lo), b1 = min(pass == 0 ? cpe : cse, hi);
         for (int qq = b0; qq < b1; ++qq) {
-          const R* P = &sm.pt[(qq - q0) * PW];
+          const R* P = &sm.x.pt[(qq - q0) * PW];
           R wn[3], gn[3][D];
           lane_nodes<D, R>(P, P + 3 * D, lk0, lk1, wn, gn);
           R Sq[D][D];
@@ -529,12 +538,12 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT) k_tile_stress(Dev<R> d, TileList
     __syncthreads();
   }
   // ---- reduce onto the region and write the tile partial ----
-  R* reg = sm.pt;        // RN * D <= CH * PW
-  reduce_cells_to_region<D, R, D, D>(acc, 0, sm.cellpart, reg, lcell, lk0, lk1, lane_on);
+  R* reg = sm.x.red.reg;
+  reduce_cells_to_region<D, R, D, D>(acc, 0, sm.x.red.cellpart, reg, lcell, lk0, lk1, lane_on);
   R* dst = tpart + (size_t)blockIdx.x * RN * D;
   for (int i = t; i < RN * D; i += NT) dst[i] = reg[i];
   if (MODE == TM_ENERGY && energy_slot >= 0) {
-    double bs = block_sum(e, sm.red);
+    double bs = block_sum(e, sm.bsum);
     if (t == 0) d.part[energy_slot * kPartSlot + blockIdx.x] = bs;
   }
 }
@@ -565,16 +574,22 @@ __global__ void k_surface_F(Dev<R> d, const R* vlin) {
 template <int D, typename R>
 struct HeatLds {
   static constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
+  static constexpr int CH = sizeof(R) == 8 ? NT / 4 : NT / 2; // points per chunk
   static constexpr int PW = 6 * D + 1 + D;    // w, dw tables + c + q
   R u[RN];
-  R pt[NT * PW];
-  R cellpart[64 * 27];
+  union {
+    R pt[CH * PW];
+    struct {
+      R cellpart[64 * 27];
+      R reg[RN];
+    } red;
+  } x;
 };
 
 template <int D, typename R>
 __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT) k_tile_heat(Dev<R> d, TileLists tl, const R* T, R* tpart,
                                                               const int* done) {
-  constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN, PW = HeatLds<D, R>::PW;
+  constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN, PW = HeatLds<D, R>::PW, CH = HeatLds<D, R>::CH;
   __shared__ HeatLds<D, R> sm;
   if (done && *done) return;
   const int ct = tl.ctile_list[blockIdx.x];
@@ -604,9 +619,9 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT) k_tile_heat(Dev<R> d, TileLists 
   LaneAcc<D, R, 1> acc;
   acc.zero();
   __syncthreads();
-  for (int q0 = 0; q0 < ntot; q0 += NT) {
+  for (int q0 = 0; q0 < ntot; q0 += CH) {
     int q = q0 + t;
-    if (q < ntot) {
+    if (t < CH && q < ntot) {
       bool interior = q < npi;
       int k = interior ? pb + q : sb + (q - npi);
       R f[D];
@@ -623,7 +638,7 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT) k_tile_heat(Dev<R> d, TileLists 
       weight_table<D, R>(f, d.fn, w, dw);
       R G[1][D], val[1];
       region_grad<D, R, 1>(sm.u, lc, w, dw, G, val);
-      R* P = &sm.pt[t * PW];
+      R* P = &sm.x.pt[t * PW];
 #pragma unroll
       for (int a = 0; a < D; ++a)
 #pragma unroll
@@ -644,11 +659,11 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT) k_tile_heat(Dev<R> d, TileLists 
     }
     __syncthreads();
     if (lane_on) {
-      int lo = q0, hi = min(q0 + NT, ntot);
+      int lo = q0, hi = min(q0 + CH, ntot);
       for (int pass = 0; pass < 2; ++pass) {
         int b0 = max(pass == 0 ? cpb : csb, lo), b1 = min(pass == 0 ? cpe : cse, hi);
         for (int qq = b0; qq < b1; ++qq) {
-          const R* P = &sm.pt[(qq - q0) * PW];
+          const R* P = &sm.x.pt[(qq - q0) * PW];
           R wn[3], gn[3][D];
           lane_nodes<D, R>(P, P + 3 * D, lk0, lk1, wn, gn);
           R c = P[6 * D];
@@ -664,8 +679,8 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT) k_tile_heat(Dev<R> d, TileLists 
     }
     __syncthreads();
   }
-  R* reg = sm.pt;   // RN <= NT * PW
-  reduce_cells_to_region<D, R, 1, 1>(acc, 0, sm.cellpart, reg, lcell, lk0, lk1, lane_on);
+  R* reg = sm.x.red.reg;
+  reduce_cells_to_region<D, R, 1, 1>(acc, 0, sm.x.red.cellpart, reg, lcell, lk0, lk1, lane_on);
   R* dst = tpart + (size_t)blockIdx.x * RN;
   for (int i = t; i < RN; i += NT) dst[i] = reg[i];
 }
@@ -687,11 +702,16 @@ template <int D> struct P2GF {
 
 template <int D, typename R>
 struct P2GLds {
-  static constexpr int NT = TileGeo<D>::NT;
-  static constexpr int CH = sizeof(R) == 8 ? NT / 2 : NT;   // points per chunk (LDS budget)
+  static constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
+  static constexpr int CH = sizeof(R) == 8 ? NT / 4 : NT / 2;   // points per chunk
   static constexpr int PW = D + P2GF<D>::PL;    // f + payload
-  R pay[CH * PW];
-  R cellpart[64 * 27 * 3];                      // field chunks of 3
+  union {
+    R pay[CH * PW];
+    struct {
+      R cellpart[64 * 27 * 3];                  // field chunks of 3
+      R reg[RN * 3];
+    } red;
+  } x;
 };
 
 template <int D, typename R>
@@ -732,7 +752,7 @@ __global__ void __launch_bounds__(TileGeo<D>::NT) k_tile_p2g(Dev<R> d, TileLists
     if (t < CH && q < ntot) {
       // payload: f[D] | m~ | m~ v[D] | m~ A[D*D] | c_W | c_WT | c_E | c_ET | m grad T[D] |
       //          cJ | cV | cK (|grad N|^2 heat term) | cR (N^2 Robin term) | cS (N heat right side)
-      R* P = &sm.pay[t * PW];
+      R* P = &sm.x.pay[t * PW];
       int type = q < n1 ? 0 : (q < n2 ? 1 : 2);
       int k, p;
       R x[D];
@@ -786,7 +806,7 @@ __global__ void __launch_bounds__(TileGeo<D>::NT) k_tile_p2g(Dev<R> d, TileLists
       for (int pass = 0; pass < 3; ++pass) {
         int b0 = max(rb[pass], lo), b1 = min(re[pass], hi);
         for (int qq = b0; qq < b1; ++qq) {
-          const R* P = &sm.pay[(qq - q0) * PW];
+          const R* P = &sm.x.pay[(qq - q0) * PW];
           R f[D];
 #pragma unroll
           for (int a = 0; a < D; ++a) f[a] = P[a];
@@ -832,9 +852,9 @@ __global__ void __launch_bounds__(TileGeo<D>::NT) k_tile_p2g(Dev<R> d, TileLists
     __syncthreads();
   }
   // field chunks of 3 onto the region
-  R* reg = sm.pay;   // RN * 3 <= NT * PW
+  R* reg = sm.x.red.reg;
   for (int f0 = 0; f0 < NF; f0 += 3) {
-    reduce_cells_to_region<D, R, NF, 3>(acc, f0, sm.cellpart, reg, lcell, lk0, lk1, lane_on);
+    reduce_cells_to_region<D, R, NF, 3>(acc, f0, sm.x.red.cellpart, reg, lcell, lk0, lk1, lane_on);
     for (int i = t; i < RN * 3; i += NT) {
       int rn = i / 3, f = f0 + i % 3;
       if (f < NF) tpart[((size_t)blockIdx.x * NF + f) * RN + rn] = reg[i];

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_functions():
     src = open(os.path.join(ROOT, "include", "mpm.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"^\s*(?:int|const char\*)\s+(mpm_\w+)\s*\(", src, flags=re.M)
+    names = re.findall(r"^\s*(?:int|double|const char\*)\s+(mpm_\w+)\s*\(", src, flags=re.M)
     return sorted(set(names))
 
 
@@ -89,3 +89,32 @@ def test_host_sampler_matches_oracle(case):
     assert np.array_equal(got["label"], ref["label"])
     if case == "contact3d":
         assert 0 < ref["label"].sum() < len(ref["label"])
+
+
+def test_struct_layouts_match_c_compiler(tmp_path):
+    """sizeof / offsetof of every ABI struct as the C compiler lays it out, against the
+    ctypes declarations of the binding."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if not cc:
+        pytest.skip("no C compiler")
+    structs = {"mpm_params": L.MpmParams, "mpm_particles": L.MpmParticles, "mpm_surface": L.MpmSurface,
+               "mpm_stats": L.MpmStats, "mpm_request": L.MpmRequest, "mpm_completion": L.MpmCompletion,
+               "mpm_server_info": L.MpmServerInfo}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mpm.h"', 'int main(void) {']
+    for cname, ct in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in ct._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, ct in structs.items():
+        assert got[(cname, "size")] == C.sizeof(ct), cname
+        for f, _ in ct._fields_:
+            assert got[(cname, f)] == getattr(ct, f).offset, (cname, f)
