@@ -17,9 +17,15 @@
 
 namespace mpm {
 
-// Tile kernels run 9-wave (3D) workgroups; two of them fit on a CU only when every SIMD
-// can hold 6 waves, i.e. at most 80 VGPRs per lane.
-#define MPM_TILE_KERNEL(NT) __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6)))
+// Tile kernels run 9-wave (3D) workgroups.  The dispatcher places three waves of every
+// such workgroup on one SIMD, so k resident workgroups need 3k wave slots on that SIMD:
+// two per CU fit at most 85 VGPRs (80 allocated), three need at most 56.  P2G keeps 96
+// (one workgroup per CU): squeezing it to 80 spills enough to be slower.  FP64 kernels
+// need about twice the registers and keep lower targets.
+#define MPM_TILE_KERNEL(NT, W) __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(W)))
+template <typename R> struct TileOcc;
+template <> struct TileOcc<float> { static constexpr int STRESS = 6, HEAT = 6, P2G = 5; };
+template <> struct TileOcc<double> { static constexpr int STRESS = 6, HEAT = 6, P2G = 3; };
 
 template <int D> struct TileGeo;
 template <> struct TileGeo<3> {
@@ -374,19 +380,70 @@ struct StressLds {
   double bsum[16];
 };
 
+// A point's inputs to the stress scatter, loaded one chunk ahead so that the loads are in
+// flight while the previous chunk is scattered (and, for the first chunk, while the node
+// region is staged).  Interior: x, J^n, V0, mu V^n.  Surface: x, k_r, dA (and the cached
+// F_r for the Hessian).
 template <int D, typename R, int MODE>
-__global__ void MPM_TILE_KERNEL(TileGeo<D>::NT) k_tile_stress(Dev<R> d, TileLists tl, const R* u, R* tpart,
+struct StressIn {
+  static constexpr int NV = D + 1 + D + (MODE == TM_HESS ? D * D : 0);
+  R v[NV];
+  int k = -1;            // point index (sorted order), -1: none
+  bool interior = true;
+};
+
+template <int D, typename R, int MODE>
+MPM_DEV void stress_fetch(const Dev<R>& d, int q, int ntot, int npi, int pb, int sb, bool visc, StressIn<D, R, MODE>& in) {
+  in.k = -1;
+  if (q >= ntot) return;
+  const int N = d.np, S = d.ns;
+  in.interior = q < npi;
+  const int k = in.interior ? pb + q : sb + (q - npi);
+  in.k = k;
+  if (in.interior) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) in.v[a] = d.px[a * N + k];
+    in.v[D] = d.pJ[k];
+    in.v[D + 1] = d.pV0[k];
+    if (D >= 2) in.v[D + 2] = visc ? d.pmu[k] * d.pVn[k] : R(0);
+  } else {
+#pragma unroll
+    for (int a = 0; a < D; ++a) in.v[a] = d.ss[a * S + k];
+    in.v[D] = d.sk[k];
+#pragma unroll
+    for (int a = 0; a < D; ++a) in.v[D + 1 + a] = d.sdA[a * S + k];
+    if constexpr (MODE == TM_HESS) {
+#pragma unroll
+      for (int ab = 0; ab < D * D; ++ab) in.v[2 * D + 1 + ab] = d.sF[ab * S + k];
+    }
+  }
+}
+
+template <int D, typename R, int MODE>
+__global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stress(Dev<R> d, TileLists tl, const R* u, R* tpart,
                                                                 int mask_in, const int* done, int energy_slot) {
   constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
   constexpr int CH = StressLds<D, R>::CH, PW = StressLds<D, R>::PW;
   __shared__ StressLds<D, R> sm;
   if (done && *done) return;
   const int ct = tl.ctile_list[blockIdx.x];
-  const int N = d.np, S = d.ns, nn = d.nn;
+  const int S = d.ns, nn = d.nn;
   const int t = threadIdx.x;
   const R dt = d.dt;
   int org[3] = {0, 0, 0};
   tiled_coords<D>(ct, 0, d.nt, org);
+  const int cb = ct * 64;
+  const bool surf = (d.term_mask & 2) && S > 0;
+  const bool vol = (d.term_mask & 5) != 0;
+  const bool visc = (d.term_mask & 4) != 0;
+  const int* rg = tl.ctile_rng + 6 * blockIdx.x;
+  const int pb = rg[0], pe = vol ? rg[1] : pb;
+  const int sb = surf ? rg[2] : 0, se = surf ? rg[3] : 0;
+  const int npi = pe - pb;
+  const int ntot = npi + (se - sb);
+  // first chunk's point inputs, issued together with the node staging below
+  StressIn<D, R, MODE> in;
+  if (t < CH) stress_fetch<D, R, MODE>(d, t, ntot, npi, pb, sb, visc, in);
   for (int rn = t; rn < RN; rn += NT) {
     int r[3];
     region_coords<D>(rn, r);
@@ -396,14 +453,6 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT) k_tile_stress(Dev<R> d, TileList
     for (int a = 0; a < D; ++a)
       sm.u[rn * D + a] = (gnode >= 0 && ((fr >> a) & 1)) ? u[a * nn + gnode] : R(0);
   }
-  const int cb = ct * 64;
-  const bool surf = (d.term_mask & 2) && S > 0;
-  const bool vol = (d.term_mask & 5) != 0;
-  const int* rg = tl.ctile_rng + 6 * blockIdx.x;
-  const int pb = rg[0], pe = vol ? rg[1] : pb;
-  const int sb = surf ? rg[2] : 0, se = surf ? rg[3] : 0;
-  const int npi = pe - pb;
-  const int ntot = npi + (se - sb);
   int lcell, lk0, lk1;
   lane_map<D>(t, lcell, lk0, lk1);
   const bool lane_on = t < 64 * TileGeo<D>::LPC;
@@ -418,15 +467,13 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT) k_tile_stress(Dev<R> d, TileList
   __syncthreads();
   for (int q0 = 0; q0 < ntot; q0 += CH) {
     // ---- point phase: weights, gradient of u, stress ----
-    int q = q0 + t;
-    if (t < CH && q < ntot) {
-      bool interior = q < npi;
-      int k = interior ? pb + q : sb + (q - npi);
+    if (t < CH && in.k >= 0) {
+      const bool interior = in.interior;
       R f[D];
       int lc[3] = {0, 0, 0};
 #pragma unroll
       for (int a = 0; a < D; ++a) {
-        R xs = (interior ? d.px[a * N + k] : d.ss[a * S + k]) * d.fn;
+        R xs = in.v[a] * d.fn;
         R cf = floor(xs);
         f[a] = xs - cf;
         int l = (int)cf - org[a];
@@ -445,7 +492,7 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT) k_tile_stress(Dev<R> d, TileList
         R tr = 0;
 #pragma unroll
         for (int a = 0; a < D; ++a) tr += G[a][a];
-        const R Jn = d.pJ[k], V0 = d.pV0[k];
+        const R Jn = in.v[D], V0 = in.v[D + 1];
         if (d.term_mask & 1) {
           R s;
           if (MODE == TM_HESS) {
@@ -458,8 +505,8 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT) k_tile_stress(Dev<R> d, TileList
 #pragma unroll
           for (int a = 0; a < D; ++a) Sq[a][a] += s;
         }
-        if (d.term_mask & 4) {
-          R cV = dt * d.pmu[k] * d.pVn[k];
+        if (visc) {
+          R cV = dt * in.v[D + 2];
           R ee = 0;
 #pragma unroll
           for (int a = 0; a < D; ++a)
@@ -473,14 +520,14 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT) k_tile_stress(Dev<R> d, TileList
         }
       } else {
         R Nv[D], F[D][D];
-        const R kr = d.sk[k];
+        const R kr = in.v[D];
 #pragma unroll
-        for (int a = 0; a < D; ++a) Nv[a] = d.sdA[a * S + k];
-        if (MODE == TM_HESS) {
+        for (int a = 0; a < D; ++a) Nv[a] = in.v[D + 1 + a];
+        if constexpr (MODE == TM_HESS) {
 #pragma unroll
           for (int a = 0; a < D; ++a)
 #pragma unroll
-            for (int b = 0; b < D; ++b) F[a][b] = d.sF[(a * D + b) * S + k];
+            for (int b = 0; b < D; ++b) F[a][b] = in.v[2 * D + 1 + a * D + b];
         } else {
 #pragma unroll
           for (int a = 0; a < D; ++a) {
@@ -509,6 +556,8 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT) k_tile_stress(Dev<R> d, TileList
         for (int b = 0; b < D; ++b) P[6 * D + a * D + b] = Sq[a][b];
     }
     __syncthreads();
+    // next chunk's inputs: in flight during this chunk's scatter
+    if (t < CH) stress_fetch<D, R, MODE>(d, q0 + CH + t, ntot, npi, pb, sb, visc, in);
     // ---- scatter phase: the lane's cell points inside this chunk ----
     if (lane_on) {
       int lo = q0, hi = min(q0 + CH, ntot);
@@ -587,7 +636,7 @@ struct HeatLds {
 };
 
 template <int D, typename R>
-__global__ void MPM_TILE_KERNEL(TileGeo<D>::NT) k_tile_heat(Dev<R> d, TileLists tl, const R* T, R* tpart,
+__global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::HEAT) k_tile_heat(Dev<R> d, TileLists tl, const R* T, R* tpart,
                                                               const int* done) {
   constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN, PW = HeatLds<D, R>::PW, CH = HeatLds<D, R>::CH;
   __shared__ HeatLds<D, R> sm;
@@ -715,7 +764,7 @@ struct P2GLds {
 };
 
 template <int D, typename R>
-__global__ void __launch_bounds__(TileGeo<D>::NT) k_tile_p2g(Dev<R> d, TileLists tl, R* tpart) {
+__global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::P2G) k_tile_p2g(Dev<R> d, TileLists tl, R* tpart) {
   constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
   using FI = P2GF<D>;
   constexpr int NF = FI::NF, PW = P2GLds<D, R>::PW, CH = P2GLds<D, R>::CH;
