@@ -59,26 +59,37 @@ def run_gpu(scene_fn, precision, steps, warmup, want_timing):
         scene.step(Pd, Sd)
     log(f"{precision}: recorded {warmup + steps} steps in {time.perf_counter() - t0:.1f} s "
         f"(N={N}, S~{len(surf0['s'])})")
-    # replay: warmup steps untimed, then the timed region
-    for k, v in init.items():
-        Pd[k].copy_(v)
-    for k in range(warmup):
-        scene.step(Pd, surfs[k])
-    torch.cuda.synchronize()
+    def replay(timed_events):
+        for k, v in init.items():
+            Pd[k].copy_(v)
+        for k in range(warmup):
+            scene.step(Pd, surfs[k])
+        torch.cuda.synchronize()
+        if timed_events:
+            scene.timing(True)
+        stats = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(warmup, warmup + steps):
+            scene.step(Pd, surfs[k])
+            stats.append(scene.stats())
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        timing = None
+        if timed_events:
+            timing = scene.timing_read()
+            scene.timing(False)
+        return elapsed, stats, timing
+
+    # the timed region carries no profiling events; a second replay of the same steps
+    # records per-kernel HIP events for the breakdown and the roofline
+    elapsed, stats, _ = replay(False)
+    timing, elapsed_ev = None, None
     if want_timing:
-        scene.timing(True)
-    stats = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(warmup, warmup + steps):
-        scene.step(Pd, surfs[k])
-        stats.append(scene.stats())
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    timing = scene.timing_read() if want_timing else None
-    if want_timing:
-        scene.timing(False)
-    return dict(N=N, elapsed=elapsed, stats=stats, timing=timing, S=len(surf0["s"]), params=p)
+        elapsed_ev, _, timing = replay(True)
+        log(f"{precision}: {1e3 * elapsed / steps:.3f} ms/step, with per-launch events {1e3 * elapsed_ev / steps:.3f}")
+    return dict(N=N, elapsed=elapsed, elapsed_events=elapsed_ev, stats=stats, timing=timing, S=len(surf0["s"]),
+                params=p)
 
 
 def cpu_baseline():
@@ -283,7 +294,8 @@ def main():
         roofline = roofline_of(dom, tm, N, S, G, R, K, measured_traffic(dom, args.precision))
         out_extra["kernel_rooflines"] = {k: {kk: roofline_of(k, tm, N, S, G, R, K, None)[kk]
                                              for kk in ("avg_launch_us", "hbm_frac", "valu_frac")} for k in cand}
-        out_extra["kernel_time_share"] = round(total / (main_run["elapsed"] * 1e3), 3)
+        out_extra["kernel_time_share"] = round(total / (main_run["elapsed_events"] * 1e3), 3)
+        out_extra["ms_per_step_with_events"] = round(1e3 * main_run["elapsed_events"] / K, 3)
     fp64 = None
     if args.fp64_steps > 0 and args.precision != "fp64":
         r64 = run_gpu(scene_fn, "fp64", args.fp64_steps, 1, False)

@@ -106,6 +106,8 @@ struct mpm_ctx {
   // state
   int np = 0, ns = 0, ntiles = 0, prev_ntiles = 0;
   bool have_p2g = false, constrained = false, mom_pending = false;
+  // Krylov launch schedule learned from the previous solves (first chunk sizes)
+  int cg_hint_mom = 2, cg_hint_heat = 2;
   int status = 0;
   mpm_stats stats{};
   std::string err;
@@ -510,36 +512,112 @@ void read_scalars(mpm_ctx* c, hipStream_t s, bool misc = false) {
 }
 
 // Jacobi-preconditioned CG with device-side scalars: apply(p, Ap, done, cg) must write
-// A p and, when cg is given, set the step length from p . A p.  The host polls the done
-// flag after 2, 4, 8, ... iterations.
+// A p and, when cg is given, set the step length from p . A p.  The kernels return at
+// once after the done flag is set, so chunks of iterations can be queued ahead of the
+// host's check: cg_begin queues the start and the first two iterations, cg_finish (after
+// the host has read the scalars into hcg) queues further chunks of 4, 8, 16, ... until the
+// flag is seen set, then the fix-up of a first-iteration breakdown.
+struct CgRun {
+  int chunk = 2;
+  int launched = 0;
+};
+
+// First chunk of a solve: the iteration count of the previous solve of the same kind
+// (2..32).  Iterations queued past convergence return at once, while a chunk that is
+// too short costs a host round trip, so the schedule follows the last count.
+inline int first_chunk(int hint) { return std::max(2, std::min(hint, 32)); }
+
 template <typename R, class Apply>
-int cg_solve(mpm_ctx* c, Apply&& apply, const R* b, R* x, bool x0_given, const R* diag, R* r, R* z, R* p, R* Ap,
-             int ncomp, double tol2_host, const double* tol2_scale, int maxit, hipStream_t s) {
+void cg_iterate(mpm_ctx* c, Apply&& apply, R* x, const R* diag, R* r, R* z, R* p, R* Ap, int ncomp, int n,
+                hipStream_t s, CgRun& run) {
+  Dev<R>& d = dev<R>(c);
+  int nelem = c->ntiles * 64, nb = krylov_blocks(nelem);
+  const int* tl = d.tile_list;
+  const int* done = &c->cg->done;
+  for (int j = 0; j < n; ++j) {
+    apply(p, Ap, done, c->cg);
+    LAUNCH(c, MPM_K_BLAS, k_cg_update<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, c->cg, x, r, z,
+           (const R*)p, (const R*)Ap, diag, c->part, c->ctr + (size_t)CTR_CGUPD * kCtrSite);
+    LAUNCH(c, MPM_K_BLAS, k_cg_p<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, (const CgScal*)c->cg,
+           (const R*)z, p);
+  }
+  run.launched += n;
+}
+
+template <typename R, class Apply>
+void cg_begin(mpm_ctx* c, Apply&& apply, const R* b, R* x, bool x0_given, const R* diag, R* r, R* z, R* p, R* Ap,
+              int ncomp, double tol2_host, const double* tol2_scale, int maxit, hipStream_t s, CgRun& run,
+              int first = 2) {
   Dev<R>& d = dev<R>(c);
   int nelem = c->ntiles * 64, nb = krylov_blocks(nelem);
   const int* tl = d.tile_list;
   if (x0_given) apply(x, Ap, (const int*)nullptr, (CgScal*)nullptr);
   LAUNCH(c, MPM_K_BLAS, k_cg_start<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, b,
-         x0_given ? (const R*)Ap : (const R*)nullptr, diag, x, r, z, p, c->part, c->ctr + (size_t)CTR_CGSTART * kCtrSite, c->cg, tol2_host,
-         tol2_scale, maxit);
-  const int* done = &c->cg->done;
-  int chunk = 2;
-  for (int it = 0; it < maxit + chunk; it += chunk) {
-    for (int j = 0; j < chunk; ++j) {
-      apply(p, Ap, done, c->cg);
-      LAUNCH(c, MPM_K_BLAS, k_cg_update<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, c->cg, x, r, z,
-             (const R*)p, (const R*)Ap, diag, c->part, c->ctr + (size_t)CTR_CGUPD * kCtrSite);
-      LAUNCH(c, MPM_K_BLAS, k_cg_p<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, (const CgScal*)c->cg,
-             (const R*)z, p);
-    }
+         x0_given ? (const R*)Ap : (const R*)nullptr, diag, x, r, z, p, c->part, c->ctr + (size_t)CTR_CGSTART * kCtrSite,
+         c->cg, tol2_host, tol2_scale, maxit);
+  run = CgRun{};
+  run.chunk = std::min(first, std::max(maxit, 1));
+  cg_iterate<R>(c, apply, x, diag, r, z, p, Ap, ncomp, run.chunk, s, run);
+}
+
+// Returns true when it changed x after the scalars in hcg were read (more iterations, or
+// the breakdown fix-up), i.e. when work queued behind that read used an unfinished x.
+template <typename R, class Apply>
+bool cg_finish(mpm_ctx* c, Apply&& apply, R* x, const R* diag, R* r, R* z, R* p, R* Ap, int ncomp, int maxit,
+               hipStream_t s, CgRun& run) {
+  Dev<R>& d = dev<R>(c);
+  int nelem = c->ntiles * 64, nb = krylov_blocks(nelem);
+  const int* tl = d.tile_list;
+  bool changed = false;
+  while (!c->hcg->done && run.launched < maxit + 32) {
+    run.chunk = std::min(run.chunk * 2, 16);
+    cg_iterate<R>(c, apply, x, diag, r, z, p, Ap, ncomp, run.chunk, s, run);
     sync_read(c, s, c->cg, c->hcg, sizeof(CgScal));
-    if (c->hcg->done) break;
-    chunk = std::min(chunk * 2, 16);
+    changed = true;
   }
   LAUNCH(c, MPM_K_BLAS, k_cg_fixup<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, (const CgScal*)c->cg, x,
          (const R*)z);
+  if (c->hcg->breakdown && c->hcg->iters == 0) changed = true;
   if (!(c->hcg->rr == c->hcg->rr)) c->status |= ST_NONFINITE;
+  return changed;
+}
+
+template <typename R, class Apply>
+int cg_solve(mpm_ctx* c, Apply&& apply, const R* b, R* x, bool x0_given, const R* diag, R* r, R* z, R* p, R* Ap,
+             int ncomp, double tol2_host, const double* tol2_scale, int maxit, hipStream_t s) {
+  CgRun run;
+  cg_begin<R>(c, apply, b, x, x0_given, diag, r, z, p, Ap, ncomp, tol2_host, tol2_scale, maxit, s, run);
+  sync_read(c, s, c->cg, c->hcg, sizeof(CgScal));
+  cg_finish<R>(c, apply, x, diag, r, z, p, Ap, ncomp, maxit, s, run);
   return c->hcg->iters;
+}
+
+int status_code(int bits) {
+  if (bits & ST_DOMAIN) return MPM_EDOMAIN;
+  if (bits & ST_NONFINITE) return MPM_ENONFINITE;
+  if (bits & ST_NOCONV) return MPM_ENOCONV;
+  return MPM_OK;
+}
+
+// Status code of the latched status word (already read) with its message.
+int status_code_of(mpm_ctx* c) {
+  int code = status_code(c->status);
+  if (code == MPM_EDOMAIN) c->err = "point outside [dx, 1-dx)^dim";
+  else if (code == MPM_ENONFINITE) c->err = "non-finite residual or energy";
+  else if (code == MPM_ENOCONV) c->err = "iteration cap reached";
+  return code;
+}
+
+// Reads the scalar block, the CG scalars and (optionally) the misc words in one sync.
+void read_all(mpm_ctx* c, hipStream_t s, bool cg, bool misc) {
+  HIPCHK(hipMemcpyAsync(c->hbuf, c->scal, SC_N * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (cg) HIPCHK(hipMemcpyAsync(c->hcg, c->cg, sizeof(CgScal), hipMemcpyDeviceToHost, s));
+  if (misc) HIPCHK(hipMemcpyAsync(c->hint, c->misc, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (misc) {
+    c->status |= c->hint[0];
+    c->constrained = c->hint[1] != 0;
+  }
 }
 
 template <int D, typename R>
@@ -586,16 +664,20 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
     do_surface_lin<D, R>(c, vhat, s);
     LAUNCH(c, MPM_K_BLAS, k_neg<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const R*)g, vtrial);
     double cg_tol = std::max(p.cg_rel * gn, 0.1 * p.newton_tol * g0);
-    int cit = cg_solve<R>(c, apply, vtrial, delta, false, (const R*)d.gdiag, (R*)c->r, (R*)c->z, (R*)c->pp,
-                          (R*)c->Ap, D, cg_tol * cg_tol, nullptr, p.cg_max, s);
-    st.cg_iters += cit;
-    st.hessvecs += cit;
-    // slope, then the full step: its energy, gradient and (speculatively, harmless if the
-    // trial is rejected because the next trial overwrites it) the translation correction
-    // and |g|^2 at the corrected point, all read in one round trip.
-    dot_async<R>(c, g, delta, D, SC_SLOPE, s);
+    R* cr = (R*)c->r;
+    R* cz = (R*)c->z;
+    R* cp = (R*)c->pp;
+    R* cAp = (R*)c->Ap;
+    CgRun run;
+    cg_begin<R>(c, apply, vtrial, delta, false, (const R*)d.gdiag, cr, cz, cp, cAp, D, cg_tol * cg_tol, nullptr,
+                p.cg_max, s, run, first_chunk(c->cg_hint_mom));
+    // slope, then the full step: its energy, gradient and the translation correction with
+    // |g|^2 at the corrected point.  Queued behind the first CG chunk on the guess that
+    // it converges there; the CG scalars and the trial's scalars come back in one read.
+    // A trial that is rejected is overwritten by the next one, so the correction applied
+    // speculatively is harmless.
     double alpha = 1.0;
-    auto trial = [&](double a) {
+    auto trial_launch = [&](double a) {
       LAUNCH(c, MPM_K_BLAS, k_axpy_to<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const R*)vhat,
              (const R*)delta, a, vtrial);
       do_energy_grad<D, R>(c, vtrial, (R*)c->gscratch, nullptr, SC_PHIT, s);
@@ -606,10 +688,21 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
                vtrial, (R*)c->gscratch);
       }
       dot_async<R>(c, (const R*)c->gscratch, (const R*)c->gscratch, D, SC_GN2, s);
-      read_scalars(c, s);
       st.energy_evals++;
     };
-    trial(alpha);
+    dot_async<R>(c, g, delta, D, SC_SLOPE, s);
+    trial_launch(alpha);
+    read_all(c, s, true, false);
+    if (cg_finish<R>(c, apply, delta, (const R*)d.gdiag, cr, cz, cp, cAp, D, p.cg_max, s, run)) {
+      // the guess failed: the trial used an unfinished delta
+      dot_async<R>(c, g, delta, D, SC_SLOPE, s);
+      trial_launch(alpha);
+      read_all(c, s, false, false);
+    }
+    const int cit = c->hcg->iters;
+    c->cg_hint_mom = cit;
+    st.cg_iters += cit;
+    st.hessvecs += cit;
     const double slope = c->hbuf[SC_SLOPE];
     double phit = c->hbuf[SC_PHIT];
     // Armijo with the round-off of Phi as allowance (8 eps |Phi|, eps of the arithmetic):
@@ -619,7 +712,8 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
       if (phit <= phi + p.ls_c1 * alpha * slope + noise) break;
       alpha *= 0.5;
       st.line_search_halvings++;
-      trial(alpha);
+      trial_launch(alpha);
+      read_all(c, s, false, false);
       phit = c->hbuf[SC_PHIT];
     }
     // accept the last trial: its (corrected) point and gradient become the iterate
@@ -683,8 +777,12 @@ void do_explicit(mpm_ctx* c, hipStream_t s) {
   c->mom_pending = true;
 }
 
+// Heat solve, split so that work can be queued behind its first CG chunk: heat_begin
+// queues T = T^n, |rhs|^2 and the CG start with two iterations; heat_end (after hcg has
+// been read) finishes the CG and records the statistics, returning true when it changed
+// T^ after that read.
 template <int D, typename R>
-void do_solve_heat(mpm_ctx* c, hipStream_t s) {
+void heat_begin(mpm_ctx* c, hipStream_t s, CgRun& run) {
   if (!c->have_p2g) throw ApiError{MPM_EINVAL, "mpm_p2g must run first"};
   Dev<R>& d = dev<R>(c);
   int nelem = c->ntiles * 64, nb = krylov_blocks(nelem);
@@ -693,14 +791,31 @@ void do_solve_heat(mpm_ctx* c, hipStream_t s) {
   LAUNCH(c, MPM_K_BLAS, k_axpy_to<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, 1, (const R*)d.gTn, (const R*)d.gTn,
          0.0, T);
   dot_async<R>(c, (const R*)d.hrhs, (const R*)d.hrhs, 1, SC_RHS2, s);
-  auto apply = [&](const R* pv, R* Apv, const int* done, CgScal* cg) {
-    do_heat_apply<D, R>(c, pv, Apv, done, cg, s);
-  };
-  int it = cg_solve<R>(c, apply, d.hrhs, T, true, (const R*)d.hdiag, (R*)c->hr, (R*)c->hz, (R*)c->hp, (R*)c->hAp, 1,
-                       c->p.heat_tol * c->p.heat_tol, c->scal + SC_RHS2, c->p.heat_max, s);
+  auto apply = [&](const R* pv, R* Apv, const int* done, CgScal* cg) { do_heat_apply<D, R>(c, pv, Apv, done, cg, s); };
+  cg_begin<R>(c, apply, d.hrhs, T, true, (const R*)d.hdiag, (R*)c->hr, (R*)c->hz, (R*)c->hp, (R*)c->hAp, 1,
+              c->p.heat_tol * c->p.heat_tol, c->scal + SC_RHS2, c->p.heat_max, s, run, first_chunk(c->cg_hint_heat));
+}
+
+template <int D, typename R>
+bool heat_end(mpm_ctx* c, hipStream_t s, CgRun& run) {
+  Dev<R>& d = dev<R>(c);
+  auto apply = [&](const R* pv, R* Apv, const int* done, CgScal* cg) { do_heat_apply<D, R>(c, pv, Apv, done, cg, s); };
+  bool changed = cg_finish<R>(c, apply, (R*)c->That, (const R*)d.hdiag, (R*)c->hr, (R*)c->hz, (R*)c->hp, (R*)c->hAp, 1,
+                              c->p.heat_max, s, run);
+  const int it = c->hcg->iters;
+  c->cg_hint_heat = it;
   c->stats.heat_iters = it;
   c->stats.heat_res = std::sqrt(std::max(c->hcg->rr, 0.0));
   if (it >= c->p.heat_max && c->hcg->rr > c->hcg->tol2) c->status |= ST_NOCONV;
+  return changed;
+}
+
+template <int D, typename R>
+void do_solve_heat(mpm_ctx* c, hipStream_t s) {
+  CgRun run;
+  heat_begin<D, R>(c, s, run);
+  sync_read(c, s, c->cg, c->hcg, sizeof(CgScal));
+  heat_end<D, R>(c, s, run);
 }
 
 // ---- dispatch ----------------------------------------------------------------------------
@@ -713,13 +828,6 @@ void dispatch(mpm_ctx* c, F&& f) {
     if (c->fp64) f(std::integral_constant<int, 2>{}, double{});
     else f(std::integral_constant<int, 2>{}, float{});
   }
-}
-
-int status_code(int bits) {
-  if (bits & ST_DOMAIN) return MPM_EDOMAIN;
-  if (bits & ST_NONFINITE) return MPM_ENONFINITE;
-  if (bits & ST_NOCONV) return MPM_ENOCONV;
-  return MPM_OK;
 }
 
 // Message of the last failure that had no context to hold it (mpm_last_error(NULL)).
@@ -1005,6 +1113,7 @@ std::atomic<int> g_batch_concurrency{8};
 
 int step_one(mpm_ctx* c, mpm_particles* P, const mpm_surface* S, int implicit, hipStream_t s) {
   int rc = mpm_p2g(c, P, S, s);
+  bool synced = false;   // true when the final read covered all queued work and the status
   if (rc == MPM_OK) {
     rc = guarded(c, [&] {
       dispatch(c, [&](auto Dc, auto Rv) {
@@ -1012,13 +1121,27 @@ int step_one(mpm_ctx* c, mpm_particles* P, const mpm_surface* S, int implicit, h
         using R = decltype(Rv);
         if (implicit) do_solve_momentum<D, R>(c, s);
         else do_explicit<D, R>(c, s);
-        if (c->p.heat) do_solve_heat<D, R>(c, s);
-        do_g2p<D, R>(c, (const R*)c->vhat, c->p.heat ? (const R*)c->That : nullptr, P, s);
+        const bool heat = c->p.heat != 0;
+        CgRun run;
+        if (heat) heat_begin<D, R>(c, s, run);
+        // G2P is queued behind the first heat CG chunk; it reads only staged data, so if
+        // the heat solve needs more iterations it is simply queued again afterwards
+        do_g2p<D, R>(c, (const R*)c->vhat, heat ? (const R*)c->That : nullptr, P, s);
+        read_all(c, s, heat, true);
+        if (c->mom_pending) {
+          for (int a = 0; a < 3; ++a) c->stats.momentum[a] = a < D ? c->hbuf[SC_MOM + D + 1 + a] : 0.0;
+          c->mom_pending = false;
+        }
+        synced = true;
+        if (heat && heat_end<D, R>(c, s, run)) {
+          do_g2p<D, R>(c, (const R*)c->vhat, (const R*)c->That, P, s);
+          synced = false;
+        }
       });
     });
   }
   if (rc == MPM_OK) rc = check_launch(c);
-  int st = mpm_scene_status(c, s);
+  int st = synced ? status_code_of(c) : mpm_scene_status(c, s);
   if (rc == MPM_OK) rc = st;
   c->stats.status = rc;
   return rc;
@@ -1150,11 +1273,7 @@ int mpm_scene_status(mpm_ctx* ctx, void* stream) {
     ctx->status |= ctx->hint[0];
   });
   if (rc != MPM_OK) return rc;
-  int code = status_code(ctx->status);
-  if (code == MPM_EDOMAIN) ctx->err = "point outside [dx, 1-dx)^dim";
-  else if (code == MPM_ENONFINITE) ctx->err = "non-finite residual or energy";
-  else if (code == MPM_ENOCONV) ctx->err = "iteration cap reached";
-  return code;
+  return status_code_of(ctx);
 }
 
 }  // extern "C"
