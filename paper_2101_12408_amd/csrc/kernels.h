@@ -50,8 +50,7 @@ constexpr int kPartSlot = kRedSlot;  // partial sums per reduction slot
 // Cell sort: keys, counts, slots, per-cell order fix-up.
 // ======================================================================================
 template <int D, typename R>
-__global__ void k_cell_keys(const R* pos, int cnt, int n, int nt, R fn, int* key, int* iota, int* ccount,
-                            int* status) {
+__global__ void k_cell_keys(const R* pos, int cnt, int n, int nt, R fn, int* key, int* ccount, int* status) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= cnt) return;
   R x[D];
@@ -62,15 +61,13 @@ __global__ void k_cell_keys(const R* pos, int cnt, int n, int nt, R fn, int* key
   if (bad) flag_status(status, ST_DOMAIN);
   int k = (int)tiled_index<D>(c, nt);
   key[i] = k;
-  iota[i] = i;
   atomicAdd(&ccount[k], 1);
 }
 
 constexpr int kScanT = 256, kScanI = 16, kScanBlock = kScanT * kScanI;
 
-// Exclusive scan of in[0,len) into out[0,len), block totals into bsum; with zero_in the
-// input is cleared as it is read (the cell counters start the next sort at zero).
-__global__ void k_scan_local(int* in, int* out, int len, int* bsum, int zero_in) {
+// Exclusive scan of in[0,len) into out[0,len), block totals into bsum.
+__global__ void k_scan_local(const int* in, int* out, int len, int* bsum) {
   __shared__ int sh[kScanT];
   int base = blockIdx.x * kScanBlock + threadIdx.x * kScanI;
   int v[kScanI];
@@ -80,11 +77,6 @@ __global__ void k_scan_local(int* in, int* out, int len, int* bsum, int zero_in)
     int idx = base + k;
     v[k] = idx < len ? in[idx] : 0;
     s += v[k];
-  }
-  if (zero_in) {
-#pragma unroll
-    for (int k = 0; k < kScanI; ++k)
-      if (base + k < len && v[k]) in[base + k] = 0;
   }
   sh[threadIdx.x] = s;
   __syncthreads();
@@ -140,40 +132,56 @@ __global__ void k_scan_add(int* out, int len, const int* bsum) {
   out[idx] += bsum[idx / kScanBlock];
 }
 
-// Sort a segment of distinct values ascending (the group lists of the split, filled by
-// atomics, are put in sample order so that nothing depends on atomic arrival order).
-// Segments of up to 16 values are ranked in registers (independent loads); longer ones use
-// an insertion sort in memory.
+// slot = start[key] + (remaining count - 1); leaves the cell counter at zero.
+__global__ void k_cell_scatter(const int* key, int cnt, const int* start, int* ccount, int* perm) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  int k = key[i];
+  int slot = start[k] + atomicSub(&ccount[k], 1) - 1;
+  perm[slot] = i;
+}
+
+// Segment ordering after an atomic scatter: the segment of slot s is the run of slots
+// whose values v have the same key[v]; it starts at start[key[v]].  Sorting each segment
+// by value (the input index) puts it in input order, independent of the order in which
+// the atomics were served.  Short segments (up to 16) are ranked in registers by their
+// first slot's thread; in longer ones every thread ranks its own value by counting the
+// smaller ones (independent loads) into tmp, and k_segment_copy_long moves them back.
+// (Threads may read a slot while its short segment is being reordered: any value there
+// belongs to the same segment, so they still compute the same key and bounds.)
 constexpr int kSegReg = 16;
-MPM_DEV void sort_segment(int b, int e, int* vals) {
-  int n = e - b;
+
+__global__ void k_segment_rank(const int* key, const int* start, int cnt, int* vals, int* tmp) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= cnt) return;
+  const int v = vals[s];
+  const int k = key[v];
+  const int b = start[k], e = start[k + 1], n = e - b;
   if (n < 2) return;
-  if (n <= kSegReg) {
-    int v[kSegReg];
-#pragma unroll
-    for (int i = 0; i < kSegReg; ++i) v[i] = i < n ? vals[b + i] : 0x7fffffff;
-#pragma unroll
-    for (int i = 0; i < kSegReg; ++i) {
-      int r = 0;
-#pragma unroll
-      for (int j = 0; j < kSegReg; ++j) r += v[j] < v[i] ? 1 : 0;
-      if (i < n) vals[b + r] = v[i];
-    }
+  if (n > kSegReg) {
+    int r = 0;
+    for (int j = b; j < e; ++j) r += vals[j] < v ? 1 : 0;
+    tmp[b + r] = v;
     return;
   }
-  for (int i = b + 1; i < e; ++i) {
-    int v = vals[i];
-    int j = i - 1;
-    while (j >= b && vals[j] > v) { vals[j + 1] = vals[j]; --j; }
-    vals[j + 1] = v;
+  if (s != b) return;
+  int w[kSegReg];
+#pragma unroll
+  for (int i = 0; i < kSegReg; ++i) w[i] = i < n ? vals[b + i] : 0x7fffffff;
+#pragma unroll
+  for (int i = 0; i < kSegReg; ++i) {
+    int r = 0;
+#pragma unroll
+    for (int j = 0; j < kSegReg; ++j) r += w[j] < w[i] ? 1 : 0;
+    if (i < n) vals[b + r] = w[i];
   }
 }
 
-// Segments given directly: [start[c], start[c+1]) for c < nseg.
-__global__ void k_segment_order(const int* start, int nseg, int* vals) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= nseg) return;
-  sort_segment(start[c], start[c + 1], vals);
+__global__ void k_segment_copy_long(const int* key, const int* start, int cnt, int* vals, const int* tmp) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= cnt) return;
+  const int k = key[vals[s]];
+  if (start[k + 1] - start[k] > kSegReg) vals[s] = tmp[s];
 }
 
 __global__ void k_fill_i32(int* p, int v, int64_t len) {
@@ -568,19 +576,20 @@ MPM_DEV void cg_init(CgScal* s, double rz, double rr, double tol2, int maxit) {
   s->done = (rr <= tol2) || maxit <= 0 || !(rr == rr) || rr > 1e300;
 }
 
-// Start of a CG solve: r = b - A x0 (Ax = null: x0 = 0 and x is zeroed), z = r / diag,
+// Start of a CG solve for the right side bscale * b: r = bscale b - A x0 (Ax = null: x0 = 0
+// and x is zeroed), z = r / diag,
 // p = z; the last block sets the scalars.  tol2 = tol2_host * (*tol2_scale) if given.
 template <typename R>
-__global__ void k_cg_start(const int* tl, int nelem, int nn, int ncomp, const R* b, const R* Ax, const R* diag,
-                           R* x, R* r, R* z, R* p, double* part, unsigned* ctr, CgScal* cs, double tol2_host,
-                           const double* tol2_scale, int maxit) {
+__global__ void k_cg_start(const int* tl, int nelem, int nn, int ncomp, const R* b, R bscale, const R* Ax,
+                           const R* diag, R* x, R* r, R* z, R* p, double* part, unsigned* ctr, CgScal* cs,
+                           double tol2_host, const double* tol2_scale, int maxit) {
   __shared__ double sh[16];
   double rz = 0, rr = 0;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nelem; e += gridDim.x * blockDim.x) {
     int node = elem_node(tl, e);
     for (int c = 0; c < ncomp; ++c) {
       int j = c * nn + node;
-      R rv = Ax ? b[j] - Ax[j] : b[j];
+      R rv = Ax ? bscale * b[j] - Ax[j] : bscale * b[j];
       R zv = rv / diag[j];
       if (!Ax) x[j] = 0;
       r[j] = rv; z[j] = zv; p[j] = zv;
@@ -715,23 +724,33 @@ __global__ void k_mom_sums(const int* tl, int nelem, int nn, const uint8_t* fr, 
 
 // Exact minimization of Phi along rigid translations: v^ -= c on nodes with mass,
 // c_a = [sum m (v^ - v^n) - dt g_a sum m] / sum m.  e and D are translation invariant, so
-// the projected gradient moves by exactly -m c (grad may be null).
+// the projected gradient moves by exactly -m c; the grid sum of |grad|^2 after the move
+// goes to *gn2.
 template <int D, typename R>
 __global__ void k_mom_fix(const int* tl, int nelem, int nn, const uint8_t* fr, const R* m, const double* red,
-                          double dt, double g0, double g1, double g2, R* vh, R* grad) {
+                          double dt, double g0, double g1, double g2, R* vh, R* grad, double* part, unsigned* ctr,
+                          double* gn2) {
+  __shared__ double sh[16];
   double msum = red[D];
   double gg[3] = {g0, g1, g2};
   R c[D];
   for (int a = 0; a < D; ++a) c[a] = (R)((red[a] - dt * gg[a] * msum) / msum);
+  double s = 0;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nelem; e += gridDim.x * blockDim.x) {
     int node = elem_node(tl, e);
-    if (!(fr[node] & 0x80)) continue;
-    R mm = m[node];
+    uint8_t f = fr[node];
     for (int a = 0; a < D; ++a) {
-      vh[a * nn + node] -= c[a];
-      if (grad) grad[a * nn + node] -= mm * c[a];
+      R gv = grad[a * nn + node];
+      if (f & 0x80) {
+        vh[a * nn + node] -= c[a];
+        gv -= m[node] * c[a];
+        grad[a * nn + node] = gv;
+      }
+      s += (double)gv * (double)gv;
     }
   }
+  double t = block_sum(s, sh), r;
+  if (grid_reduce<1>(&t, part, ctr, sh, &r) && threadIdx.x == 0) *gn2 = r;
 }
 
 // Explicit update (q^ = 0): v^ = P[v^n - f/m + dt g] with f = dPsi/dv^ evaluated by the

@@ -11,16 +11,17 @@
 #include <string>
 #include <vector>
 
-#include <rocprim/device/device_radix_sort.hpp>
-
 #include "tiles.h"
 
 using namespace mpm;
 
 namespace {
 
-constexpr int kNumParts = 8;
+constexpr int kNumParts = 16;   // partial-sum slots (the gradient merge reduces 2D+3 values from slot 4)
 constexpr int kScalDoubles = 64;
+// Device scalars the host reads back, in one block so that every read is one copy:
+// [0, 512) FP64 scalar slots, [512, 672) the two CG scalar sets, [768, 1024) status words.
+constexpr int kMirrorBytes = 1024, kMirrorCg = 512, kMirrorMisc = 768, kMirrorRead = 800;
 
 struct HipError {
   hipError_t e;
@@ -94,12 +95,9 @@ struct mpm_ctx {
   double* scal = nullptr;
   CgScal* cg = nullptr;
   unsigned* ctr = nullptr;       // grid-reduction counters
-  // radix sort: alternate key / value buffers and scratch
-  int* sort_kalt = nullptr;
-  int* sort_valt = nullptr;
-  void* sort_tmp = nullptr;
-  size_t sort_tmp_bytes = 0;
-  // pinned host mirror
+  int* sort_tmp = nullptr;       // segment-order scratch (max(cap_part, cap_surf) ints)
+  // pinned host mirror of the device scalar block (hbuf, hcg, hint point into it)
+  char* hmirror = nullptr;
   double* hbuf = nullptr;
   int* hint = nullptr;
   CgScal* hcg = nullptr;
@@ -160,11 +158,6 @@ void prof_collect(mpm_ctx* c) {
     }                                                             \
   } while (0)
 
-// Scratch reserved for the radix sort of n pairs (histograms and look-back state; the
-// key/value ping-pong buffers are separate).  Checked against the sort's own query when
-// a context is created.
-size_t sort_scratch_bytes(int64_t n) { return ((size_t)1 << 20) + (size_t)n * 2; }
-
 template <typename R>
 size_t layout(mpm_ctx* c, char* base) {
   Bump b{base};
@@ -190,7 +183,8 @@ size_t layout(mpm_ctx* c, char* base) {
   const int NFmax = std::max(2 * D + 7, D);
   void* tpart = b.take<R>((size_t)nct_cap * RNd * NFmax);
   int* scan_bsum = b.take<int>(kScanBlock + 1);
-  int* misc = b.take<int>(64);
+  char* mirror = b.take<char>(kMirrorBytes);
+  int* misc = (int*)(mirror + kMirrorMisc);
   d.px = b.take<R>(D * NP); d.pv = b.take<R>(D * NP); d.pA = b.take<R>(D * D * NP);
   d.pm = b.take<R>(NP); d.pmt = b.take<R>(NP); d.pJ = b.take<R>(NP); d.pV0 = b.take<R>(NP);
   d.pT = b.take<R>(NP); d.pgT = b.take<R>(D * NP); d.pmu = b.take<R>(NP); d.pVn = b.take<R>(NP);
@@ -206,14 +200,13 @@ size_t layout(mpm_ctx* c, char* base) {
   void* hvecs[5];
   for (int k = 0; k < 5; ++k) hvecs[k] = b.take<R>(NN);
   d.part = b.take<double>((size_t)kNumParts * kPartSlot);
-  d.scal = b.take<double>(kScalDoubles);
-  CgScal* cg = b.take<CgScal>(2);
+  d.scal = (double*)mirror;
+  CgScal* cg = (CgScal*)(mirror + kMirrorCg);
+  static_assert(kScalDoubles * sizeof(double) <= kMirrorCg && kMirrorCg + 2 * sizeof(CgScal) <= kMirrorMisc &&
+                    kMirrorMisc + 8 * sizeof(int) <= kMirrorRead && kMirrorRead <= kMirrorBytes,
+                "mirror layout");
   unsigned* ctr = b.take<unsigned>((size_t)CTR_COUNT * kCtrSite);
-  const int64_t NMX = std::max(NP, NS);
-  int* sort_kalt = b.take<int>(NMX);
-  int* sort_valt = b.take<int>(NMX);
-  const size_t sort_tmp_bytes = sort_scratch_bytes(NMX);
-  void* sort_tmp = b.take<char>(sort_tmp_bytes);
+  int* sort_tmp = b.take<int>(std::max(NP, NS));
   d.status = misc;
   if (base) {
     c->vhat = vecs[0]; c->vtrial = vecs[1]; c->grad = vecs[2]; c->delta = vecs[3]; c->r = vecs[4];
@@ -224,7 +217,7 @@ size_t layout(mpm_ctx* c, char* base) {
     c->ctile_rng = ctile_rng;
     c->tpart = tpart;
     c->part = d.part; c->scal = d.scal; c->cg = cg; c->ctr = ctr;
-    c->sort_kalt = sort_kalt; c->sort_valt = sort_valt; c->sort_tmp = sort_tmp; c->sort_tmp_bytes = sort_tmp_bytes;
+    c->sort_tmp = sort_tmp;
     if constexpr (sizeof(R) == 8) c->d64 = d; else c->d32 = d;
   }
   return b.off + 256;
@@ -259,40 +252,39 @@ void check_params(const mpm_params* p) {
 }
 
 // ---- exclusive scan of len ints: out[0..len) and out[len] = total ----------------------
-void scan(mpm_ctx* c, int* in, int* out, int len, hipStream_t s, bool zero_in = false) {
+void scan(mpm_ctx* c, const int* in, int* out, int len, hipStream_t s) {
   int nb = cdiv(len, kScanBlock);
   if (nb > kScanBlock) throw ApiError{MPM_EINVAL, "scan length above 2^24"};
   if (len > 0)
-    LAUNCH(c, MPM_K_SORT, k_scan_local, dim3(nb), dim3(kScanT), 0, s, in, out, len, c->scan_bsum, (int)zero_in);
+    LAUNCH(c, MPM_K_SORT, k_scan_local, dim3(nb), dim3(kScanT), 0, s, in, out, len, c->scan_bsum);
   else LAUNCH(c, MPM_K_SORT, k_fill_i32, dim3(1), dim3(1), 0, s, c->scan_bsum, 0, (int64_t)1);
   LAUNCH(c, MPM_K_SORT, k_scan_sums, dim3(1), dim3(kScanT), 0, s, c->scan_bsum, std::max(nb, 1), out + len);
   if (len > 0) LAUNCH(c, MPM_K_SORT, k_scan_add, dim3(cdiv(len, 256)), dim3(256), 0, s, out, len, (const int*)c->scan_bsum);
 }
 
-int key_bits(int64_t nn) {
-  int b = 1;
-  while ((int64_t(1) << b) < nn) ++b;
-  return b;
+// Puts every segment of vals[0, cnt) (runs of equal key[value], starting at start[key])
+// in ascending value order.
+void segment_order(mpm_ctx* c, const int* key, const int* start, int cnt, int* vals, hipStream_t s) {
+  if (cnt <= 0) return;
+  LAUNCH(c, MPM_K_SORT, k_segment_rank, dim3(cdiv(cnt, 256)), dim3(256), 0, s, key, start, cnt, vals, c->sort_tmp);
+  LAUNCH(c, MPM_K_SORT, k_segment_copy_long, dim3(cdiv(cnt, 256)), dim3(256), 0, s, key, start, cnt, vals,
+         (const int*)c->sort_tmp);
 }
 
-// Stable cell sort of cnt points: perm (sorted slot -> input index) and start[nn+1].  The
-// cell counts give the dense cell starts; a stable LSD radix sort of (cell key, input
-// index) gives the order, so points of one cell stay in input order.
+// Stable cell sort of cnt points: perm (sorted slot -> input index) and start[nn+1].
+// Dense cell counts give the cell starts; an atomic scatter places the points, and each
+// cell's segment is then put in input order, so the result does not depend on the order
+// in which the atomics were served.
 template <int D, typename R>
 void cell_sort(mpm_ctx* c, Dev<R>& d, const R* pos, int cnt, int* key, int* perm, int* start, hipStream_t s) {
   if (cnt > 0)
     LAUNCH(c, MPM_K_SORT, (k_cell_keys<D, R>), dim3(cdiv(cnt, 256)), dim3(256), 0, s, pos, cnt, d.n, d.nt, d.fn, key,
-           perm, d.ccount, d.status);
-  scan(c, d.ccount, start, d.nn, s, true);
-  if (cnt > 1) {
-    rocprim::double_buffer<int> kb(key, c->sort_kalt), vb(perm, c->sort_valt);
-    size_t bytes = c->sort_tmp_bytes;
-    hipEvent_t stop = nullptr;
-    if (c->prof.on) prof_begin(c, MPM_K_SORT, s, &stop);
-    HIPCHK(rocprim::radix_sort_pairs(c->sort_tmp, bytes, kb, vb, (size_t)cnt, 0, key_bits(d.nn), s));
-    if (stop) HIPCHK(hipEventRecord(stop, s));
-    if (vb.current() != perm)
-      HIPCHK(hipMemcpyAsync(perm, vb.current(), (size_t)cnt * sizeof(int), hipMemcpyDeviceToDevice, s));
+           d.ccount, d.status);
+  scan(c, d.ccount, start, d.nn, s);
+  if (cnt > 0) {
+    LAUNCH(c, MPM_K_SORT, k_cell_scatter, dim3(cdiv(cnt, 256)), dim3(256), 0, s, (const int*)key, cnt,
+           (const int*)start, d.ccount, perm);
+    segment_order(c, key, start, cnt, perm, s);
   }
 }
 
@@ -355,8 +347,7 @@ void do_p2g(mpm_ctx* c, const mpm_particles* P, const mpm_surface* S, hipStream_
   scan(c, d.pcnt, d.grp_start, c->np, s);
   if (c->ns > 0) {
     LAUNCH(c, MPM_K_SETUP, (k_balance<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d);
-    LAUNCH(c, MPM_K_SORT, k_segment_order, dim3(cdiv(c->np, 256)), dim3(256), 0, s, (const int*)d.grp_start, c->np,
-                       d.grp);
+    segment_order(c, (const int*)d.spar, (const int*)d.grp_start, c->ns, d.grp, s);
     cell_sort<D, R>(c, d, (const R*)d.bx_unsorted, c->ns, d.b_key, d.b_src, d.b_start, s);
     LAUNCH(c, MPM_K_SETUP, (k_gather_balance<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d);
   }
@@ -397,23 +388,27 @@ void do_p2g(mpm_ctx* c, const mpm_particles* P, const mpm_surface* S, hipStream_
 
 
 // Device scalar slots (doubles at ctx->scal).
-enum : int { SC_PHI = 0, SC_DOT = 1, SC_GN2 = 2, SC_SLOPE = 3, SC_PHIT = 4, SC_RHS2 = 5, SC_MOM = 8, SC_N = 16 };
+// SC_G0 / SC_GT: the gradient merge's sums (see k_merge_stress) at the iterate and at the
+// line-search trial: [0] Phi, [1..D] sum m (v^ - v^n), [D+1] sum m, [D+2..2D+1] sum m v^,
+// [2D+2] |g|^2.
+enum : int { SC_DOT = 1, SC_SLOPE = 3, SC_RHS2 = 5, SC_MOM = 8, SC_G0 = 16, SC_GT = 32, SC_N = 48 };
 
-// Phi(u) into scal[phi_slot] (and energy_dev if given), projected gradient into g.
+// Phi(u), the momentum sums and |g|^2 into scal[red_slot ..] (Phi also into energy_dev if
+// given), projected gradient into g.
 template <int D, typename R>
-void do_energy_grad(mpm_ctx* c, const R* u, R* g, double* energy_dev, int phi_slot, hipStream_t s) {
+void do_energy_grad(mpm_ctx* c, const R* u, R* g, double* energy_dev, int red_slot, hipStream_t s) {
   Dev<R>& d = dev<R>(c);
   TileLists tl = tiles(c);
   if (c->nctile > 0)
     LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_ENERGY>), dim3(c->nctile), dim3(TileGeo<D>::NT), 0, s, d, tl,
            u, (R*)c->tpart, 0, (const int*)nullptr, 2);
   if (c->ntiles > 0) {
-    LAUNCH(c, MPM_K_ENERGY_NODE, (k_merge_stress<D, R>), dim3(merge_blocks(c)), dim3(64 * kMergeTiles), 0, s, d, tl, c->ntiles,
-           (const R*)c->tpart,
-           u, g, (int)NM_GRAD, 0.0, 0, (const int*)nullptr, c->nctile > 0 ? (const double*)(c->part + 2 * kPartSlot) : nullptr,
-           c->nctile, c->part + 4 * kPartSlot, c->ctr + (size_t)CTR_MERGE * kCtrSite, c->scal + phi_slot, energy_dev, (CgScal*)nullptr);
+    LAUNCH(c, MPM_K_ENERGY_NODE, (k_merge_stress<D, R>), dim3(merge_blocks(c)), dim3(64 * kMergeTiles), 0, s, d, tl,
+           c->ntiles, (const R*)c->tpart, u, g, (int)NM_GRAD, 0.0, 0, (const int*)nullptr,
+           c->nctile > 0 ? (const double*)(c->part + 2 * kPartSlot) : nullptr, c->nctile, c->part + 4 * kPartSlot,
+           c->ctr + (size_t)CTR_MERGE * kCtrSite, c->scal + red_slot, energy_dev, (CgScal*)nullptr);
   } else {
-    LAUNCH(c, MPM_K_BLAS, k_fill_r<double>, dim3(1), dim3(1), 0, s, c->scal + phi_slot, 0.0, (int64_t)1);
+    LAUNCH(c, MPM_K_BLAS, k_fill_r<double>, dim3(1), dim3(64), 0, s, c->scal + red_slot, 0.0, (int64_t)(2 * D + 3));
     if (energy_dev) LAUNCH(c, MPM_K_BLAS, k_fill_r<double>, dim3(1), dim3(1), 0, s, energy_dev, 0.0, (int64_t)1);
   }
 }
@@ -499,16 +494,14 @@ void mom_sums_async(mpm_ctx* c, const R* vh, hipStream_t s) {
          (const uint8_t*)d.gfree, (const R*)d.gm, vh, (const R*)d.gvn, c->part, c->ctr + (size_t)CTR_MOM * kCtrSite, c->scal + SC_MOM);
 }
 
-// Reads the scalar block (and the misc words) in one synchronization.
-void read_scalars(mpm_ctx* c, hipStream_t s, bool misc = false) {
-  HIPCHK(hipMemcpyAsync(c->hbuf, c->scal, SC_N * sizeof(double), hipMemcpyDeviceToHost, s));
-  if (misc) HIPCHK(hipMemcpyAsync(c->hint, c->misc, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+// Reads the device scalar block (scalars, CG scalars, status words) in one copy and
+// updates the latched status from it.
+void read_mirror(mpm_ctx* c, hipStream_t s) {
+  HIPCHK(hipMemcpyAsync(c->hmirror, (const char*)c->scal, kMirrorRead, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  if (misc) {
-    c->status |= c->hint[0];
-    c->constrained = c->hint[1] != 0;
-    c->stats.n_dof = c->hint[2];
-  }
+  c->status |= c->hint[0];
+  c->constrained = c->hint[1] != 0;
+  c->stats.n_dof = c->hint[2];
 }
 
 // Jacobi-preconditioned CG with device-side scalars: apply(p, Ap, done, cg) must write
@@ -545,14 +538,14 @@ void cg_iterate(mpm_ctx* c, Apply&& apply, R* x, const R* diag, R* r, R* z, R* p
 }
 
 template <typename R, class Apply>
-void cg_begin(mpm_ctx* c, Apply&& apply, const R* b, R* x, bool x0_given, const R* diag, R* r, R* z, R* p, R* Ap,
-              int ncomp, double tol2_host, const double* tol2_scale, int maxit, hipStream_t s, CgRun& run,
-              int first = 2) {
+void cg_begin(mpm_ctx* c, Apply&& apply, const R* b, double bscale, R* x, bool x0_given, const R* diag, R* r, R* z,
+              R* p, R* Ap, int ncomp, double tol2_host, const double* tol2_scale, int maxit, hipStream_t s,
+              CgRun& run, int first = 2) {
   Dev<R>& d = dev<R>(c);
   int nelem = c->ntiles * 64, nb = krylov_blocks(nelem);
   const int* tl = d.tile_list;
   if (x0_given) apply(x, Ap, (const int*)nullptr, (CgScal*)nullptr);
-  LAUNCH(c, MPM_K_BLAS, k_cg_start<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, b,
+  LAUNCH(c, MPM_K_BLAS, k_cg_start<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, b, (R)bscale,
          x0_given ? (const R*)Ap : (const R*)nullptr, diag, x, r, z, p, c->part, c->ctr + (size_t)CTR_CGSTART * kCtrSite,
          c->cg, tol2_host, tol2_scale, maxit);
   run = CgRun{};
@@ -572,12 +565,14 @@ bool cg_finish(mpm_ctx* c, Apply&& apply, R* x, const R* diag, R* r, R* z, R* p,
   while (!c->hcg->done && run.launched < maxit + 32) {
     run.chunk = std::min(run.chunk * 2, 16);
     cg_iterate<R>(c, apply, x, diag, r, z, p, Ap, ncomp, run.chunk, s, run);
-    sync_read(c, s, c->cg, c->hcg, sizeof(CgScal));
+    read_mirror(c, s);
     changed = true;
   }
-  LAUNCH(c, MPM_K_BLAS, k_cg_fixup<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, (const CgScal*)c->cg, x,
-         (const R*)z);
-  if (c->hcg->breakdown && c->hcg->iters == 0) changed = true;
+  if (c->hcg->breakdown && c->hcg->iters == 0) {
+    LAUNCH(c, MPM_K_BLAS, k_cg_fixup<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, (const CgScal*)c->cg, x,
+           (const R*)z);
+    changed = true;
+  }
   if (!(c->hcg->rr == c->hcg->rr)) c->status |= ST_NONFINITE;
   return changed;
 }
@@ -586,8 +581,8 @@ template <typename R, class Apply>
 int cg_solve(mpm_ctx* c, Apply&& apply, const R* b, R* x, bool x0_given, const R* diag, R* r, R* z, R* p, R* Ap,
              int ncomp, double tol2_host, const double* tol2_scale, int maxit, hipStream_t s) {
   CgRun run;
-  cg_begin<R>(c, apply, b, x, x0_given, diag, r, z, p, Ap, ncomp, tol2_host, tol2_scale, maxit, s, run);
-  sync_read(c, s, c->cg, c->hcg, sizeof(CgScal));
+  cg_begin<R>(c, apply, b, 1.0, x, x0_given, diag, r, z, p, Ap, ncomp, tol2_host, tol2_scale, maxit, s, run);
+  read_mirror(c, s);
   cg_finish<R>(c, apply, x, diag, r, z, p, Ap, ncomp, maxit, s, run);
   return c->hcg->iters;
 }
@@ -608,18 +603,6 @@ int status_code_of(mpm_ctx* c) {
   return code;
 }
 
-// Reads the scalar block, the CG scalars and (optionally) the misc words in one sync.
-void read_all(mpm_ctx* c, hipStream_t s, bool cg, bool misc) {
-  HIPCHK(hipMemcpyAsync(c->hbuf, c->scal, SC_N * sizeof(double), hipMemcpyDeviceToHost, s));
-  if (cg) HIPCHK(hipMemcpyAsync(c->hcg, c->cg, sizeof(CgScal), hipMemcpyDeviceToHost, s));
-  if (misc) HIPCHK(hipMemcpyAsync(c->hint, c->misc, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  if (misc) {
-    c->status |= c->hint[0];
-    c->constrained = c->hint[1] != 0;
-  }
-}
-
 template <int D, typename R>
 void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
   if (!c->have_p2g) throw ApiError{MPM_EINVAL, "mpm_p2g must run first"};
@@ -632,18 +615,16 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
   R* g = (R*)c->grad;
   R* delta = (R*)c->delta;
   mpm_stats& st = c->stats;
-  // start: v^ = P v^n, mass sum, Phi and |g| in one round trip
+  // start: v^ = P v^n; Phi, the mass sum and |g| come from the gradient merge
   LAUNCH(c, MPM_K_BLAS, k_project_copy<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const uint8_t*)d.gfree,
          (const R*)d.gvn, vhat);
-  mom_sums_async<D, R>(c, (const R*)d.gvn, s);
-  do_energy_grad<D, R>(c, vhat, g, nullptr, SC_PHI, s);
-  dot_async<R>(c, g, g, D, SC_GN2, s);
-  read_scalars(c, s, true);
+  do_energy_grad<D, R>(c, vhat, g, nullptr, SC_G0, s);
+  read_mirror(c, s);
   const bool fix = p.momentum_fix && !c->constrained;
-  const double msum = c->hbuf[SC_MOM + D];
+  const double msum = c->hbuf[SC_G0 + 1 + D];
   const double floor_abs = 1e-14 * msum * p.dx / p.dt;
-  double phi = c->hbuf[SC_PHI];
-  double gn = std::sqrt(std::max(c->hbuf[SC_GN2], 0.0));
+  double phi = c->hbuf[SC_G0];
+  double gn = std::sqrt(std::max(c->hbuf[SC_G0 + 2 * D + 2], 0.0));
   const double g0 = gn;
   st.g0 = g0;
   st.energy_evals = 1;
@@ -662,15 +643,14 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
     if (sizeof(R) == 4 && gn <= 1e-4 * g0 && gn > 0.5 * gn_prev) { st.converged = 2; break; }
     gn_prev = gn;
     do_surface_lin<D, R>(c, vhat, s);
-    LAUNCH(c, MPM_K_BLAS, k_neg<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const R*)g, vtrial);
     double cg_tol = std::max(p.cg_rel * gn, 0.1 * p.newton_tol * g0);
     R* cr = (R*)c->r;
     R* cz = (R*)c->z;
     R* cp = (R*)c->pp;
     R* cAp = (R*)c->Ap;
     CgRun run;
-    cg_begin<R>(c, apply, vtrial, delta, false, (const R*)d.gdiag, cr, cz, cp, cAp, D, cg_tol * cg_tol, nullptr,
-                p.cg_max, s, run, first_chunk(c->cg_hint_mom));
+    cg_begin<R>(c, apply, (const R*)g, -1.0, delta, false, (const R*)d.gdiag, cr, cz, cp, cAp, D, cg_tol * cg_tol,
+                nullptr, p.cg_max, s, run, first_chunk(c->cg_hint_mom));
     // slope, then the full step: its energy, gradient and the translation correction with
     // |g|^2 at the corrected point.  Queued behind the first CG chunk on the guess that
     // it converges there; the CG scalars and the trial's scalars come back in one read.
@@ -680,31 +660,28 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
     auto trial_launch = [&](double a) {
       LAUNCH(c, MPM_K_BLAS, k_axpy_to<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const R*)vhat,
              (const R*)delta, a, vtrial);
-      do_energy_grad<D, R>(c, vtrial, (R*)c->gscratch, nullptr, SC_PHIT, s);
-      if (fix) {
-        mom_sums_async<D, R>(c, (const R*)vtrial, s);
+      do_energy_grad<D, R>(c, vtrial, (R*)c->gscratch, nullptr, SC_GT, s);
+      if (fix)
         LAUNCH(c, MPM_K_BLAS, (k_mom_fix<D, R>), dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, (const uint8_t*)d.gfree,
-               (const R*)d.gm, (const double*)(c->scal + SC_MOM), p.dt, p.gravity[0], p.gravity[1], p.gravity[2],
-               vtrial, (R*)c->gscratch);
-      }
-      dot_async<R>(c, (const R*)c->gscratch, (const R*)c->gscratch, D, SC_GN2, s);
+               (const R*)d.gm, (const double*)(c->scal + SC_GT + 1), p.dt, p.gravity[0], p.gravity[1], p.gravity[2],
+               vtrial, (R*)c->gscratch, c->part, c->ctr + (size_t)CTR_MOM * kCtrSite, c->scal + SC_GT + 2 * D + 2);
       st.energy_evals++;
     };
     dot_async<R>(c, g, delta, D, SC_SLOPE, s);
     trial_launch(alpha);
-    read_all(c, s, true, false);
+    read_mirror(c, s);
     if (cg_finish<R>(c, apply, delta, (const R*)d.gdiag, cr, cz, cp, cAp, D, p.cg_max, s, run)) {
       // the guess failed: the trial used an unfinished delta
       dot_async<R>(c, g, delta, D, SC_SLOPE, s);
       trial_launch(alpha);
-      read_all(c, s, false, false);
+      read_mirror(c, s);
     }
     const int cit = c->hcg->iters;
     c->cg_hint_mom = cit;
     st.cg_iters += cit;
     st.hessvecs += cit;
     const double slope = c->hbuf[SC_SLOPE];
-    double phit = c->hbuf[SC_PHIT];
+    double phit = c->hbuf[SC_GT];
     // Armijo with the round-off of Phi as allowance (8 eps |Phi|, eps of the arithmetic):
     // near convergence the decrement is below it and the test would be decided by noise.
     for (int ls = 1; ls < std::max(p.ls_max, 1); ++ls) {
@@ -713,8 +690,8 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
       alpha *= 0.5;
       st.line_search_halvings++;
       trial_launch(alpha);
-      read_all(c, s, false, false);
-      phit = c->hbuf[SC_PHIT];
+      read_mirror(c, s);
+      phit = c->hbuf[SC_GT];
     }
     // accept the last trial: its (corrected) point and gradient become the iterate
     std::swap(c->vhat, c->vtrial);
@@ -725,7 +702,7 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
     phi = phit;
     if (fix) {
       // Phi(v^ - c) = Phi(v^) - 1/2 |c|^2 sum m for the minimizing translation c
-      const double* red = c->hbuf + SC_MOM;
+      const double* red = c->hbuf + SC_GT + 1;
       const double M = red[D];
       double c2 = 0;
       for (int a2 = 0; a2 < D; ++a2) {
@@ -734,7 +711,7 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
       }
       phi -= 0.5 * M * c2;
     }
-    gn = std::sqrt(std::max(c->hbuf[SC_GN2], 0.0));
+    gn = std::sqrt(std::max(c->hbuf[SC_GT + 2 * D + 2], 0.0));
   }
   if (it == p.newton_max && gn <= std::max(p.newton_tol * g0, floor_abs)) st.converged = 1;
   st.newton_iters = it;
@@ -792,7 +769,7 @@ void heat_begin(mpm_ctx* c, hipStream_t s, CgRun& run) {
          0.0, T);
   dot_async<R>(c, (const R*)d.hrhs, (const R*)d.hrhs, 1, SC_RHS2, s);
   auto apply = [&](const R* pv, R* Apv, const int* done, CgScal* cg) { do_heat_apply<D, R>(c, pv, Apv, done, cg, s); };
-  cg_begin<R>(c, apply, d.hrhs, T, true, (const R*)d.hdiag, (R*)c->hr, (R*)c->hz, (R*)c->hp, (R*)c->hAp, 1,
+  cg_begin<R>(c, apply, d.hrhs, 1.0, T, true, (const R*)d.hdiag, (R*)c->hr, (R*)c->hz, (R*)c->hp, (R*)c->hAp, 1,
               c->p.heat_tol * c->p.heat_tol, c->scal + SC_RHS2, c->p.heat_max, s, run, first_chunk(c->cg_hint_heat));
 }
 
@@ -814,7 +791,7 @@ template <int D, typename R>
 void do_solve_heat(mpm_ctx* c, hipStream_t s) {
   CgRun run;
   heat_begin<D, R>(c, s, run);
-  sync_read(c, s, c->cg, c->hcg, sizeof(CgScal));
+  read_mirror(c, s);
   heat_end<D, R>(c, s, run);
 }
 
@@ -942,19 +919,10 @@ int mpm_ctx_create(const mpm_params* p, void* workspace, size_t ws_bytes, int64_
       fill_params(c->d32, *p, c->nt);
     }
     HIPCHK(hipGetDevice(&c->device));
-    {
-      // the reserved sort scratch must cover what the sort asks for at full capacity
-      size_t need_sort = 0;
-      const int64_t nmx = std::max<int64_t>(std::max<int64_t>(cap_part, cap_surf), 1);
-      rocprim::double_buffer<int> kb(c->sort_kalt, c->sort_kalt), vb(c->sort_valt, c->sort_valt);
-      HIPCHK(rocprim::radix_sort_pairs(nullptr, need_sort, kb, vb, (size_t)nmx, 0, key_bits(c->nn), (hipStream_t)0));
-      if (need_sort > c->sort_tmp_bytes)
-        throw ApiError{MPM_ENOMEM, "radix sort scratch (" + std::to_string(need_sort) + " B) above the reserve (" +
-                                       std::to_string(c->sort_tmp_bytes) + " B)"};
-    }
-    HIPCHK(hipHostMalloc((void**)&c->hbuf, 64 * sizeof(double), hipHostMallocDefault));
-    HIPCHK(hipHostMalloc((void**)&c->hint, 64 * sizeof(int), hipHostMallocDefault));
-    HIPCHK(hipHostMalloc((void**)&c->hcg, sizeof(CgScal), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&c->hmirror, kMirrorBytes, hipHostMallocDefault));
+    c->hbuf = (double*)c->hmirror;
+    c->hcg = (CgScal*)(c->hmirror + kMirrorCg);
+    c->hint = (int*)(c->hmirror + kMirrorMisc);
     // zero the workspace once (fill kernels; the cell counters must start at zero)
     hipLaunchKernelGGL(k_fill_i32, dim3(cdiv((int64_t)(need / 4), 256)), dim3(256), 0, 0, (int*)c->ws, 0,
                        (int64_t)(need / 4));
@@ -963,9 +931,7 @@ int mpm_ctx_create(const mpm_params* p, void* workspace, size_t ws_bytes, int64_
   });
   if (rc != MPM_OK) {
     g_last_error = c->err;
-    if (c->hbuf) hipHostFree(c->hbuf);
-    if (c->hint) hipHostFree(c->hint);
-    if (c->hcg) hipHostFree(c->hcg);
+    if (c->hmirror) hipHostFree(c->hmirror);
     delete c;
     return rc;
   }
@@ -981,9 +947,7 @@ int mpm_ctx_destroy(mpm_ctx* ctx) {
     hipStreamDestroy(ctx->own);
   }
   if (ctx->own_done) hipEventDestroy(ctx->own_done);
-  if (ctx->hbuf) hipHostFree(ctx->hbuf);
-  if (ctx->hint) hipHostFree(ctx->hint);
-  if (ctx->hcg) hipHostFree(ctx->hcg);
+  if (ctx->hmirror) hipHostFree(ctx->hmirror);
   delete ctx;
   return MPM_OK;
 }
@@ -1024,7 +988,7 @@ int mpm_energy_grad(mpm_ctx* ctx, const void* v_hat, double* energy_dev, void* g
     dispatch(ctx, [&](auto Dc, auto Rv) {
       constexpr int D = decltype(Dc)::value;
       using R = decltype(Rv);
-      do_energy_grad<D, R>(ctx, (const R*)v_hat, (R*)grad, energy_dev, SC_PHI, s);
+      do_energy_grad<D, R>(ctx, (const R*)v_hat, (R*)grad, energy_dev, SC_G0, s);
     });
   });
   return rc != MPM_OK ? rc : check_launch(ctx);
@@ -1127,7 +1091,7 @@ int step_one(mpm_ctx* c, mpm_particles* P, const mpm_surface* S, int implicit, h
         // G2P is queued behind the first heat CG chunk; it reads only staged data, so if
         // the heat solve needs more iterations it is simply queued again afterwards
         do_g2p<D, R>(c, (const R*)c->vhat, heat ? (const R*)c->That : nullptr, P, s);
-        read_all(c, s, heat, true);
+        read_mirror(c, s);
         if (c->mom_pending) {
           for (int a = 0; a < 3; ++a) c->stats.momentum[a] = a < D ? c->hbuf[SC_MOM + D + 1 + a] : 0.0;
           c->mom_pending = false;
@@ -1259,18 +1223,12 @@ int mpm_scene_status(mpm_ctx* ctx, void* stream) {
   if (!ctx) return MPM_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   int rc = guarded(ctx, [&] {
+    read_mirror(ctx, s);
     if (ctx->mom_pending) {
-      // grid momentum after the solve, read with the status word in one round trip
-      HIPCHK(hipMemcpyAsync(ctx->hbuf, ctx->scal, SC_N * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpyAsync(ctx->hint, ctx->misc, sizeof(int), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
       const int D = ctx->p.dim;
       for (int a = 0; a < 3; ++a) ctx->stats.momentum[a] = a < D ? ctx->hbuf[SC_MOM + D + 1 + a] : 0.0;
       ctx->mom_pending = false;
-    } else {
-      sync_read(ctx, s, ctx->misc, ctx->hint, sizeof(int));
     }
-    ctx->status |= ctx->hint[0];
   });
   if (rc != MPM_OK) return rc;
   return status_code_of(ctx);

@@ -1116,20 +1116,26 @@ MPM_DEV void merge_sources(int node_tile, int local, int nt, const int* ctile_sl
 constexpr int kMergeTiles = 4;
 
 // Stress merge: node-level terms.
-//  NM_GRAD: out = P[acc + m (v^ - v^n) - dt m g]; the blocks also sum the tile energy
-//           partials (epart, nep entries) and the grid sum goes to Phi (*phi, *phi2).
+//  NM_GRAD: out = P[acc + m (v^ - v^n) - dt m g]; with phi the blocks also sum the tile
+//           energy partials (epart, nep entries) and the grid sums go to red: red[0] = Phi,
+//           red[1..D] = sum m (v^ - v^n), red[D+1] = sum m, red[D+2..2D+1] = sum m v^ (nodes
+//           with mass), red[2D+2] = |out|^2.
 //  NM_HESS: out = P[acc + alpha m w]; with cg the grid sum of w . out sets the CG step.
 template <int D, typename R>
 __global__ void __launch_bounds__(64 * kMergeTiles) k_merge_stress(
     Dev<R> d, TileLists tl, int ntiles, const R* tpart, const R* u, R* out, int mode, double alpha, int mask_in,
-    const int* done, const double* epart, int nep, double* npart, unsigned* ctr, double* phi, double* phi2,
+    const int* done, const double* epart, int nep, double* npart, unsigned* ctr, double* red, double* phi2,
     CgScal* cg) {
   constexpr int RN = TileGeo<D>::RN;
+  constexpr int NV = 2 * D + 3;
   __shared__ double sh[16];
   if (done && *done) return;
   const int ti = blockIdx.x * kMergeTiles + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  double e = 0, dotv = 0;
+  double vals[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) vals[k] = 0;
+  double dotv = 0;
   if (ti < ntiles) {
     const int tile = d.tile_list[ti];
     const int node = tile * kTileNodes + lane;
@@ -1152,6 +1158,8 @@ __global__ void __launch_bounds__(64 * kMergeTiles) k_merge_stress(
       for (int a = 0; a < D; ++a) acc[a] += val[j][a];
     uint8_t fr = d.gfree[node];
     R m = d.gm[node];
+    const bool dof = fr & 0x80;
+    if (dof && mode == NM_GRAD) vals[D + 1] = (double)m;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       bool fa = (fr >> a) & 1;
@@ -1160,9 +1168,11 @@ __global__ void __launch_bounds__(64 * kMergeTiles) k_merge_stress(
       if (mode == NM_GRAD) {
         R vn = d.gvn[a * nn + node];
         o = acc[a] + m * (ua - vn) - d.dt * m * d.grav[a];
-        if (fr & 0x80) {
+        if (dof) {
           double dv = (double)ua - (double)vn;
-          e += 0.5 * (double)m * dv * dv - (double)d.dt * (double)m * (double)d.grav[a] * (double)ua;
+          vals[0] += 0.5 * (double)m * dv * dv - (double)d.dt * (double)m * (double)d.grav[a] * (double)ua;
+          vals[1 + a] = (double)m * dv;
+          vals[D + 2 + a] = (double)m * (double)ua;
         }
       } else {
         R wa = (!mask_in || fa) ? ua : R(0);
@@ -1171,22 +1181,27 @@ __global__ void __launch_bounds__(64 * kMergeTiles) k_merge_stress(
       }
       o = fa ? o : R(0);
       out[a * nn + node] = o;
+      vals[2 * D + 2] += (double)o * (double)o;
     }
   }
-  const bool want = (mode == NM_GRAD && phi) || (mode == NM_HESS && cg);
+  const bool want = (mode == NM_GRAD && red) || (mode == NM_HESS && cg);
   if (!want) return;
-  if (mode == NM_GRAD && epart) {
-    // this block also sums the tile-kernel energy partials k = blockIdx.x (mod gridDim.x)
-    for (int k = blockIdx.x + threadIdx.x * gridDim.x; k < nep; k += blockDim.x * gridDim.x) e += epart[k];
-  }
-  double bs = block_sum(mode == NM_GRAD ? e : dotv, sh), tot;
-  if (grid_reduce<1>(&bs, npart, ctr, sh, &tot) && threadIdx.x == 0) {
-    if (mode == NM_GRAD) {
-      *phi = tot;
-      if (phi2) *phi2 = tot;
-    } else {
-      cg_set_alpha(cg, tot);
+  if (mode == NM_GRAD) {
+    if (epart) {
+      // this block also sums the tile-kernel energy partials k = blockIdx.x (mod gridDim.x)
+      for (int k = blockIdx.x + threadIdx.x * gridDim.x; k < nep; k += blockDim.x * gridDim.x) vals[0] += epart[k];
     }
+    double t[NV], r[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) t[k] = block_sum(vals[k], sh);
+    if (grid_reduce<NV>(t, npart, ctr, sh, r) && threadIdx.x == 0) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) red[k] = r[k];
+      if (phi2) *phi2 = r[0];
+    }
+  } else {
+    double bs = block_sum(dotv, sh), tot;
+    if (grid_reduce<1>(&bs, npart, ctr, sh, &tot) && threadIdx.x == 0) cg_set_alpha(cg, tot);
   }
 }
 
