@@ -190,6 +190,7 @@ constexpr int kRedGroupOff = 1 << 17;                  // max blocks of a reduci
 constexpr int kMaxRedGroups = kRedGroupOff / kRedGroup;
 constexpr int kCtrStride = 32;
 constexpr int kCtrSite = (1 + kMaxRedGroups) * kCtrStride;
+constexpr int kRedSh = 64;   // LDS doubles of a reducing block: NV values x waves (<= 16 waves, NV <= 4; or 4 waves, NV <= 16)
 
 MPM_DEV void publish(double* p, double v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 
@@ -218,6 +219,45 @@ MPM_DEV double block_sum_array(const double* part, int nb, double* sh) {
   return block_sum(v, sh);
 }
 
+// NV block sums at once (each lane's v[k]; results in thread 0's out[k]): wave shuffles
+// per value, then one exchange through LDS (sh must hold NV * waves doubles).  Fixed
+// order: lanes by shuffle tree, then waves in index order.
+template <int NV>
+MPM_DEV void block_sum_n(const double* v, double* sh, double* out) {
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int nw = (blockDim.x + kWave - 1) / kWave;
+  double w[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) w[k] = wave_sum(v[k]);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sh[wid * NV + k] = w[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double r = 0;
+      for (int q = 0; q < nw; ++q) r += sh[q * NV + k];
+      out[k] = r;
+    }
+  }
+}
+
+// Sums of NV published arrays part[v * kRedSlot + (0..nb)] in fixed order (thread 0's out).
+template <int NV>
+MPM_DEV void block_sum_arrays(const double* part, int nb, double* sh, double* out) {
+  double v[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = 0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] += __hip_atomic_load(part + (size_t)k * kRedSlot + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  block_sum_n<NV>(v, sh, out);
+}
+
 // vals: the block's NV sums (read in thread 0).  Returns true in the one block that holds
 // the grid sums, in out[0..NV) of thread 0.  Every thread of every block must call it.
 template <int NV>
@@ -237,8 +277,7 @@ MPM_DEV bool grid_reduce(const double* vals, double* part, unsigned* ctr, double
   __syncthreads();
   if (!flag) return false;
   double gs[NV];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) gs[v] = block_sum_array(part + (size_t)v * kRedSlot + g * kRedGroup, gsz, sh);
+  block_sum_arrays<NV>(part + (size_t)g * kRedGroup, gsz, sh, gs);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) publish(part + (size_t)v * kRedSlot + kRedGroupOff + g, gs[v]);
@@ -248,11 +287,7 @@ MPM_DEV bool grid_reduce(const double* vals, double* part, unsigned* ctr, double
   }
   __syncthreads();
   if (!flag) return false;
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    double r = block_sum_array(part + (size_t)v * kRedSlot + kRedGroupOff, ng, sh);
-    if (threadIdx.x == 0) out[v] = r;
-  }
+  block_sum_arrays<NV>(part + kRedGroupOff, ng, sh, out);
   return true;
 }
 

@@ -543,7 +543,7 @@ MPM_DEV int elem_node(const int* tile_list, int e) { return tile_list[e >> 6] * 
 template <typename R>
 __global__ void k_dot(const int* tl, int nelem, int nn, int ncomp, const R* a, const R* b, double* part,
                       unsigned* ctr, double* dst) {
-  __shared__ double sh[16];
+  __shared__ double sh[kRedSh];
   double s = 0;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nelem; e += gridDim.x * blockDim.x) {
     int node = elem_node(tl, e);
@@ -555,7 +555,7 @@ __global__ void k_dot(const int* tl, int nelem, int nn, int ncomp, const R* a, c
 
 // Sums nslot partial arrays of nb entries each (fixed order) into dst[0..nslot).
 __global__ void k_finalize(const double* part, int nb, int nslot, double* dst) {
-  __shared__ double sh[16];
+  __shared__ double sh[kRedSh];
   for (int s = 0; s < nslot; ++s) {
     double v = 0;
     for (int k = threadIdx.x; k < nb; k += blockDim.x) v += part[s * kPartSlot + k];
@@ -583,7 +583,7 @@ template <typename R>
 __global__ void k_cg_start(const int* tl, int nelem, int nn, int ncomp, const R* b, R bscale, const R* Ax,
                            const R* diag, R* x, R* r, R* z, R* p, double* part, unsigned* ctr, CgScal* cs,
                            double tol2_host, const double* tol2_scale, int maxit) {
-  __shared__ double sh[16];
+  __shared__ double sh[kRedSh];
   double rz = 0, rr = 0;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nelem; e += gridDim.x * blockDim.x) {
     int node = elem_node(tl, e);
@@ -615,7 +615,7 @@ MPM_DEV void cg_set_alpha(CgScal* s, double pAp) {
 template <typename R>
 __global__ void k_cg_update(const int* tl, int nelem, int nn, int ncomp, CgScal* s, R* x, R* r, R* z,
                             const R* p, const R* Ap, const R* diag, double* part, unsigned* ctr) {
-  __shared__ double sh[16];
+  __shared__ double sh[kRedSh];
   if (s->done) return;
   R alpha = (R)s->alpha;
   double rz = 0, rr = 0;
@@ -703,7 +703,7 @@ __global__ void k_neg(const int* tl, int nelem, int nn, int ncomp, const R* a, R
 template <int D, typename R>
 __global__ void k_mom_sums(const int* tl, int nelem, int nn, const uint8_t* fr, const R* m, const R* vh,
                            const R* vn, double* part, unsigned* ctr, double* dst) {
-  __shared__ double sh[16];
+  __shared__ double sh[kRedSh];
   double s[2 * D + 1];
   for (int k = 0; k < 2 * D + 1; ++k) s[k] = 0;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nelem; e += gridDim.x * blockDim.x) {
@@ -717,7 +717,7 @@ __global__ void k_mom_sums(const int* tl, int nelem, int nn, const uint8_t* fr, 
     }
   }
   double t[2 * D + 1], r[2 * D + 1];
-  for (int k = 0; k < 2 * D + 1; ++k) t[k] = block_sum(s[k], sh);
+  block_sum_n<2 * D + 1>(s, sh, t);
   if (grid_reduce<2 * D + 1>(t, part, ctr, sh, r) && threadIdx.x == 0)
     for (int k = 0; k < 2 * D + 1; ++k) dst[k] = r[k];
 }
@@ -730,7 +730,7 @@ template <int D, typename R>
 __global__ void k_mom_fix(const int* tl, int nelem, int nn, const uint8_t* fr, const R* m, const double* red,
                           double dt, double g0, double g1, double g2, R* vh, R* grad, double* part, unsigned* ctr,
                           double* gn2) {
-  __shared__ double sh[16];
+  __shared__ double sh[kRedSh];
   double msum = red[D];
   double gg[3] = {g0, g1, g2};
   R c[D];

@@ -1128,7 +1128,7 @@ __global__ void __launch_bounds__(64 * kMergeTiles) k_merge_stress(
     CgScal* cg) {
   constexpr int RN = TileGeo<D>::RN;
   constexpr int NV = 2 * D + 3;
-  __shared__ double sh[16];
+  __shared__ double sh[kRedSh];
   if (done && *done) return;
   const int ti = blockIdx.x * kMergeTiles + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -1192,8 +1192,7 @@ __global__ void __launch_bounds__(64 * kMergeTiles) k_merge_stress(
       for (int k = blockIdx.x + threadIdx.x * gridDim.x; k < nep; k += blockDim.x * gridDim.x) vals[0] += epart[k];
     }
     double t[NV], r[NV];
-#pragma unroll
-    for (int k = 0; k < NV; ++k) t[k] = block_sum(vals[k], sh);
+    block_sum_n<NV>(vals, sh, t);
     if (grid_reduce<NV>(t, npart, ctr, sh, r) && threadIdx.x == 0) {
 #pragma unroll
       for (int k = 0; k < NV; ++k) red[k] = r[k];
@@ -1210,7 +1209,7 @@ __global__ void __launch_bounds__(64 * kMergeTiles) k_merge_heat(Dev<R> d, TileL
                                                                  const R* tpart, const R* T, R* out, const int* done,
                                                                  double* npart, unsigned* ctr, CgScal* cg) {
   constexpr int RN = TileGeo<D>::RN;
-  __shared__ double sh[16];
+  __shared__ double sh[kRedSh];
   if (done && *done) return;
   const int ti = blockIdx.x * kMergeTiles + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
