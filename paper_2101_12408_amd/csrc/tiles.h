@@ -382,11 +382,11 @@ struct StressLds {
 
 // A point's inputs to the stress scatter, loaded one chunk ahead so that the loads are in
 // flight while the previous chunk is scattered (and, for the first chunk, while the node
-// region is staged).  Interior: x, J^n, V0, mu V^n.  Surface: x, k_r, dA (and the cached
-// F_r for the Hessian).
+// region is staged).  Interior: x, J^n, V0, mu V^n.  Surface: x, k_r, dA (the cached F_r
+// of the Hessian is loaded in the point phase: holding it across the scatter spills).
 template <int D, typename R, int MODE>
 struct StressIn {
-  static constexpr int NV = D + 1 + D + (MODE == TM_HESS ? D * D : 0);
+  static constexpr int NV = D + 1 + D;
   R v[NV];
   int k = -1;            // point index (sorted order), -1: none
   bool interior = true;
@@ -412,10 +412,6 @@ MPM_DEV void stress_fetch(const Dev<R>& d, int q, int ntot, int npi, int pb, int
     in.v[D] = d.sk[k];
 #pragma unroll
     for (int a = 0; a < D; ++a) in.v[D + 1 + a] = d.sdA[a * S + k];
-    if constexpr (MODE == TM_HESS) {
-#pragma unroll
-      for (int ab = 0; ab < D * D; ++ab) in.v[2 * D + 1 + ab] = d.sF[ab * S + k];
-    }
   }
 }
 
@@ -527,7 +523,7 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
 #pragma unroll
           for (int a = 0; a < D; ++a)
 #pragma unroll
-            for (int b = 0; b < D; ++b) F[a][b] = in.v[2 * D + 1 + a * D + b];
+            for (int b = 0; b < D; ++b) F[a][b] = d.sF[(a * D + b) * d.ns + in.k];
         } else {
 #pragma unroll
           for (int a = 0; a < D; ++a) {

@@ -59,3 +59,68 @@ def test_fullsize_operators(full_case, precision):
     e = rel(g.to_natural(out1)[dof], o.heat.apply(T)[dof])
     log(f"  heat_apply rel {e:.3e}")
     assert e < (1e-10 if precision == "fp64" else 1e-5)
+
+
+def _sum64(t):
+    return t.double().sum(dim=-1).cpu().numpy()
+
+
+@pytest.mark.parametrize("case,precision", [("contact3d", "mixed"), ("meltslab3d", "fp64")])
+def test_fullsize_step_properties(case, precision):
+    """The contact-angle scene (192^3) and the melting slab (256^3, ~9.7M particles) at full
+    size, where the oracle cannot run whole: properties that hold at any size.  P2G
+    conserves mass and momentum, Newton converges, G2P returns the grid momentum to the
+    particles exactly, and (slab) the heat update satisfies the Robin balance law
+    sum_i c_p m_i (T^_i - T^n_i) / dt = sum_r |dA_r| (h (T_amb - T^(s_r)) + b)."""
+    import torch
+    from oracle import bspline
+    from paper_2101_12408_amd import _lib as L
+    from paper_2101_12408_amd import api
+    S = sc.contact3d() if case == "contact3d" else sc.meltslab3d()
+    P, p = S["particles"], S["params"]
+    rng = np.random.default_rng(7)
+    P["v"] = rng.normal(size=P["v"].shape) * 0.01
+    surf = api.sample_surface(P["x"], p)
+    N, Ns = len(P["m"]), len(surf["s"])
+    log(f"case fullsize {case} {precision}: N={N} S={Ns} n={p['n']}")
+    s = api.Scene(p, cap_part=N, cap_surf=Ns, precision=precision)
+    Pd, Sd = s.to_device(P, surf)
+    s.p2g(Pd, Sd)
+    m_grid = float(s.view(L.F_MASS).double().sum())
+    mv_grid = _sum64(s.view(L.F_MOM))
+    m_p = P["m"].astype(np.float64)
+    tol = 1e-12 if precision == "fp64" else 2e-5
+    log(f"  mass {m_grid:.9e} vs {m_p.sum():.9e}")
+    assert abs(m_grid - m_p.sum()) <= tol * m_p.sum()
+    mom_p = (m_p[:, None] * P["v"]).sum(0)
+    scale = (m_p[:, None] * np.abs(P["v"])).sum()
+    log(f"  momentum {mv_grid} vs {mom_p}")
+    assert np.all(np.abs(mv_grid - mom_p) <= tol * scale)
+    rc = s.step(Pd, Sd, check=False)
+    st = s.stats()
+    log(f"  step rc {rc}: newton {st['newton_iters']} ({st['converged']}), cg {st['cg_iters']}, heat {st['heat_iters']}")
+    assert rc == 0 and st["converged"] in (1, 2)
+    # G2P: particle momentum = grid momentum sum_i m_i v^_i (exact in arithmetic)
+    v_new = Pd["v"].double().cpu().numpy()
+    m_new = Pd["m"].double().cpu().numpy()
+    mom_new = (m_new[None, :] * v_new).sum(1)
+    gmom = np.asarray(st["momentum"][:3])
+    scale = (m_new[None, :] * np.abs(v_new)).sum()
+    log(f"  particle momentum {mom_new} vs grid {gmom}")
+    assert np.all(np.abs(mom_new - gmom) <= (1e-11 if precision == "fp64" else 1e-5) * scale)
+    assert np.all(np.isfinite(Pd["x"].cpu().numpy())) and np.all(np.isfinite(Pd["T"].cpu().numpy()))
+    if p["heat"] and p["h"] > 0:
+        nat = torch.as_tensor(api.tiled_index(3, p["n"]), device=Pd["x"].device)
+        m = s.view(L.F_MASS).double()[nat].cpu().numpy()
+        Th = s.view(L.F_THAT).double()[nat].cpu().numpy()
+        Tn = s.view(L.F_TN).double()[nat].cpu().numpy()
+        dof = m > 0
+        lhs_terms = p["cp"] * m[dof] * (Th[dof] - Tn[dof]) / p["dt"]
+        idx, Nw, _ = bspline.stencil(surf["s"], p["dx"], p["n"])
+        Ts = (Nw * Th[idx]).sum(1)
+        area = np.linalg.norm(surf["dA"], axis=1)
+        rhs_terms = area * (p["h"] * (p["T_amb"] - Ts) + p["b"])
+        lhs, rhs = lhs_terms.sum(), rhs_terms.sum()
+        scale = np.abs(lhs_terms).sum() + np.abs(rhs_terms).sum()
+        log(f"  heat balance: {lhs:.9e} vs {rhs:.9e} (scale {scale:.3e})")
+        assert abs(lhs - rhs) <= 1e-7 * scale
