@@ -749,12 +749,13 @@ template <int D, typename R>
 struct P2GLds {
   static constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
   static constexpr int CH = sizeof(R) == 8 ? NT / 4 : NT / 2;   // points per chunk
-  static constexpr int PW = D + P2GF<D>::PL;    // f + payload
+  static constexpr int FC = sizeof(R) == 8 ? 3 : 7;             // fields per reduction round
+  static constexpr int PW = D + 6 * D + P2GF<D>::PL;            // f, w/dw tables, payload
   union {
     R pay[CH * PW];
     struct {
-      R cellpart[64 * 27 * 3];                  // field chunks of 3
-      R reg[RN * 3];
+      R cellpart[64 * 27 * FC];
+      R reg[RN * FC];
     } red;
   } x;
 };
@@ -763,7 +764,7 @@ template <int D, typename R>
 __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::P2G) k_tile_p2g(Dev<R> d, TileLists tl, R* tpart) {
   constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
   using FI = P2GF<D>;
-  constexpr int NF = FI::NF, PW = P2GLds<D, R>::PW, CH = P2GLds<D, R>::CH;
+  constexpr int NF = FI::NF, PW = P2GLds<D, R>::PW, CH = P2GLds<D, R>::CH, FC = P2GLds<D, R>::FC;
   __shared__ P2GLds<D, R> sm;
   const int ct = tl.ctile_list[blockIdx.x];
   const int N = d.np, S = d.ns;
@@ -795,8 +796,9 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::P2G) k_tile_p2g(Dev<
   for (int q0 = 0; q0 < ntot; q0 += CH) {
     int q = q0 + t;
     if (t < CH && q < ntot) {
-      // payload: f[D] | m~ | m~ v[D] | m~ A[D*D] | c_W | c_WT | c_E | c_ET | m grad T[D] |
-      //          cJ | cV | cK (|grad N|^2 heat term) | cR (N^2 Robin term) | cS (N heat right side)
+      // payload: f[D] | w[D][3] | dw[D][3] | m~ | m~ v[D] | m~ A[D*D] | c_W | c_WT | c_E | c_ET |
+      //          m grad T[D] | cJ | cV | cK (|grad N|^2 heat term) | cR (N^2 Robin term) |
+      //          cS (N heat right side)
       R* P = &sm.x.pay[t * PW];
       int type = q < n1 ? 0 : (q < n2 ? 1 : 2);
       int k, p;
@@ -804,12 +806,22 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::P2G) k_tile_p2g(Dev<
       if (type == 0) { k = pb + q; p = k; for (int a = 0; a < D; ++a) x[a] = d.px[a * N + k]; }
       else if (type == 1) { k = sb + (q - n1); p = d.spar[k]; for (int a = 0; a < D; ++a) x[a] = d.ss[a * S + k]; }
       else { k = bb + (q - n2); p = d.spar[d.b_src[k]]; for (int a = 0; a < D; ++a) x[a] = d.bx[a * S + k]; }
+      R fq[D];
 #pragma unroll
       for (int a = 0; a < D; ++a) {
         R xs = x[a] * d.fn;
-        P[a] = xs - floor(xs);
+        fq[a] = xs - floor(xs);
+        P[a] = fq[a];
       }
-      R* Q = P + D;
+      {
+        R w[D][3], dw[D][3];
+        weight_table<D, R>(fq, d.fn, w, dw);
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+          for (int kk = 0; kk < 3; ++kk) { P[D + a * 3 + kk] = w[a][kk]; P[4 * D + a * 3 + kk] = dw[a][kk]; }
+      }
+      R* Q = P + 7 * D;
       R mt = d.pmt[p];
       Q[0] = mt;
 #pragma unroll
@@ -855,14 +867,16 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::P2G) k_tile_p2g(Dev<
           R f[D];
 #pragma unroll
           for (int a = 0; a < D; ++a) f[a] = P[a];
-          const R* Q = P + D;
+          R wn[3], gn[3][D];
+          lane_nodes<D, R>(P + D, P + 4 * D, lk0, lk1, wn, gn);
+          const R* Q = P + 7 * D;
           const R* Z = Q + 1 + D + D * D;
           const R* bW = Z + 4;
           const R* H = bW + D;
 #pragma unroll
           for (int k = 0; k < 3; ++k) {
-            R g[D];
-            R w = lane_weight<D, R>(f, lk0, lk1, k, d.fn, g);
+            const R* g = gn[k];
+            const R w = wn[k];
             int kk[3] = {lk0, D == 3 ? lk1 : k, D == 3 ? k : 0};
             R rel[D];
 #pragma unroll
@@ -896,12 +910,12 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::P2G) k_tile_p2g(Dev<
     }
     __syncthreads();
   }
-  // field chunks of 3 onto the region
+  // field chunks of FC onto the region
   R* reg = sm.x.red.reg;
-  for (int f0 = 0; f0 < NF; f0 += 3) {
-    reduce_cells_to_region<D, R, NF, 3>(acc, f0, sm.x.red.cellpart, reg, lcell, lk0, lk1, lane_on);
-    for (int i = t; i < RN * 3; i += NT) {
-      int rn = i / 3, f = f0 + i % 3;
+  for (int f0 = 0; f0 < NF; f0 += FC) {
+    reduce_cells_to_region<D, R, NF, FC>(acc, f0, sm.x.red.cellpart, reg, lcell, lk0, lk1, lane_on);
+    for (int i = t; i < RN * FC; i += NT) {
+      int rn = i / FC, f = f0 + i % FC;
       if (f < NF) tpart[((size_t)blockIdx.x * NF + f) * RN + rn] = reg[i];
     }
     __syncthreads();
