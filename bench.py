@@ -126,30 +126,37 @@ def _cpu_baseline_inproc():
                        f"cg {info['cg']}, heat cg {info.get('heat_cg')}): {dt:.1f} s single-threaded numpy")
 
 
-# Algorithmic bytes and flops per launch of each timed kernel class: the minimum the
-# method moves (each needed particle field read once, each output written once, each
-# active node's fields read or written once), R bytes per real (4 in MIXED, 8 in FP64),
-# 4 per int32.  N interior particles, S surface samples (each with its balance point),
-# G nodes of the active tiles.  Flop counts are per-point estimates of the arithmetic
-# of the method (not of this implementation).
+# Algorithmic bytes and flops per launch of each timed kernel class.  Bytes: the minimum
+# the method moves (each needed particle field read once, each output written once, each
+# active node's fields read or written once), R bytes per real (4 in MIXED, 8 in FP64), 4
+# per int32.  Flops: the method's arithmetic in direct tensor-product form over the 3^d
+# stencil (3D counts): per point the 1D weight tables and the 27 node weights and
+# gradients (252), then per node what the kernel accumulates, e.g. the gradient gather
+# sum_i u_i (x) grad N_i (9 FMA = 18 flops) and the stress scatter S grad N_i (18 flops).
+#   energy / Hessian, interior: 252 + 486 + ~15 + 486 = ~1240; surface: ~1350 / ~1420
+#   heat operator: interior 252 + 162 + 162 = ~580; surface (value only) ~360
+#   P2G: interior ~62 per node (~1930); surface and balance points ~42 per node (~1390)
+#   G2P: interior ~38 per node (~1280); each surface and balance member ~24 per node (~900)
+# N interior particles, S surface samples (each with its balance point), G nodes of the
+# active tiles.
 def algorithmic(cls, N, S, G, R, dim=3):
     d, d2, I = dim, dim * dim, 4
     if cls == "p2g":           # read x v A m T gradT + group count; s + parent; write m mv W WT E ET
         return dict(bytes=N * ((3 * d + d2 + 2) * R + I) + S * (d * R + I) + G * (d + 5) * R,
-                    flops=(N + 2 * S) * 700)
-    if cls == "energy_int":    # read x J V0 muV, s dA k, v^ at the nodes; energy partials
-        return dict(bytes=N * (d + 3) * R + S * (2 * d + 1) * R + G * d * R, flops=N * 500 + S * 1500)
+                    flops=N * 1930 + 2 * S * 1390)
+    if cls == "energy_int":    # read x J V0 muV, s dA k, v^ at the nodes
+        return dict(bytes=N * (d + 3) * R + S * (2 * d + 1) * R + G * d * R, flops=N * 1240 + S * 1350)
     if cls == "hess_int":      # read x cJ muV, s dA k + cached F (d^2), w at the nodes
-        return dict(bytes=N * (d + 2) * R + S * (2 * d + 1 + d2) * R + G * d * R, flops=N * 450 + S * 1500)
+        return dict(bytes=N * (d + 2) * R + S * (2 * d + 1 + d2) * R + G * d * R, flops=N * 1240 + S * 1420)
     if cls in ("energy_node", "hess_node"):   # read w/v^, v^n, m, flags; write out
         return dict(bytes=G * ((2 * d + 1) * R + 1 + d * R), flops=G * 8 * d)
     if cls == "heat_pt":       # read x KV, s h|dA|, T at the nodes
-        return dict(bytes=N * (d + 1) * R + S * (d + 1) * R + G * R, flops=(N + S) * 400)
+        return dict(bytes=N * (d + 1) * R + S * (d + 1) * R + G * R, flops=N * 580 + S * 360)
     if cls == "heat_node":
         return dict(bytes=G * (3 * R + 1), flops=G * 4)
     if cls == "g2p":           # read x J count, s + parent, v^ T^; write v A T gradT x J
         return dict(bytes=N * ((d + 1) * R + I) + N * (d + d2 + 1 + d + d + 1) * R + S * (d * R + I) + G * (d + 1) * R,
-                    flops=N * 750)
+                    flops=N * 1280 + 2 * S * 900)
     return None
 
 

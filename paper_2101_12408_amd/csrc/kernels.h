@@ -263,14 +263,19 @@ __global__ void k_parents(Dev<R> d) {
   int c[D]; R f[D]; bool bad = false;
   locate<D, R>(sr, d.n, d.fn, c, f, &bad);
   double best = 1e300;
-  int bk = -1, borig = 0x7fffffff;
+  int bk = -1, borig = -1;   // borig: input index of bk, loaded only when a tie needs it
   auto visit = [&](int k) {
     double xp[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) xp[a] = (double)d.px[a * N + k];
     double d2 = dist2_exact<D>(sd, xp);
-    int o = d.p_perm[k];
-    if (d2 < best || (d2 == best && o < borig)) { best = d2; bk = k; borig = o; }
+    if (d2 < best) {
+      best = d2; bk = k; borig = -1;
+    } else if (d2 == best) {
+      if (borig < 0) borig = d.p_perm[bk];
+      int o = d.p_perm[k];
+      if (o < borig) { bk = k; borig = o; }
+    }
   };
   double dxd = (double)d.dx;
   // own cell first, so that the box test below prunes most neighbours
@@ -305,11 +310,12 @@ __global__ void k_parents(Dev<R> d) {
         }
     if (best < (rad * dxd) * (rad * dxd)) break;
     if (rad == 3) {
-      best = 1e300; bk = -1; borig = 0x7fffffff;
+      best = 1e300; bk = -1; borig = -1;
       for (int k = 0; k < N; ++k) visit(k);
     }
   }
-  if (bk < 0) { flag_status(d.status, ST_DOMAIN); bk = 0; borig = d.p_perm[0]; }
+  if (bk < 0) { flag_status(d.status, ST_DOMAIN); bk = 0; }
+  if (borig < 0) borig = d.p_perm[bk];
   d.spar[r] = bk;
   d.s_parent_orig[d.s_perm[r]] = borig;
   atomicAdd(&d.pcnt[bk], 1);

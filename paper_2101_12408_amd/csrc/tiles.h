@@ -131,21 +131,41 @@ MPM_DEV void reduce_cells_to_region(const LaneAcc<D, R, NF>& acc, int f0, R* cel
     R s[FC];
 #pragma unroll
     for (int f = 0; f < FC; ++f) s[f] = 0;
-    // cells c = r - k in [0, E)
-    for (int k2 = (D == 3 ? 0 : 0); k2 < (D == 3 ? 3 : 1); ++k2) {
-      int c2 = D == 3 ? r[2] - k2 : 0;
-      if (c2 < 0 || c2 >= (D == 3 ? E : 1)) continue;
-      for (int k1 = 0; k1 < 3; ++k1) {
-        int c1 = r[1] - k1;
-        if (c1 < 0 || c1 >= E) continue;
-        for (int k0 = 0; k0 < 3; ++k0) {
-          int c0 = r[0] - k0;
-          if (c0 < 0 || c0 >= E) continue;
-          int cc[3] = {c0, c1, c2};
-          int lc = (int)tiled_index<D>(cc, 1) & 63;
-          int base = (((lc * 3 + (D == 3 ? k2 : 0)) * 3 + k1) * 3 + k0) * FC;
+    // cells c = r - k in [0, E), visited in (k2, k1, k0) order.  A single field is summed
+    // fully unrolled with predicated reads (all reads in flight together); wider field
+    // chunks keep the loop, since unrolling them costs more registers than it saves.
+    if constexpr (FC == 1) {
 #pragma unroll
-          for (int f = 0; f < FC; ++f) s[f] += cellpart[base + f];
+      for (int k2 = 0; k2 < (D == 3 ? 3 : 1); ++k2) {
+#pragma unroll
+        for (int k1 = 0; k1 < 3; ++k1) {
+#pragma unroll
+          for (int k0 = 0; k0 < 3; ++k0) {
+            const int c0 = r[0] - k0, c1 = r[1] - k1, c2 = D == 3 ? r[2] - k2 : 0;
+            const bool in = c0 >= 0 && c0 < E && c1 >= 0 && c1 < E && c2 >= 0 && c2 < (D == 3 ? E : 1);
+            int cc[3] = {in ? c0 : 0, in ? c1 : 0, in ? c2 : 0};
+            const int lc = (int)tiled_index<D>(cc, 1) & 63;
+            const int base = ((lc * 3 + (D == 3 ? k2 : 0)) * 3 + k1) * 3 + k0;
+            s[0] += in ? cellpart[base] : R(0);
+          }
+        }
+      }
+    } else {
+      for (int k2 = 0; k2 < (D == 3 ? 3 : 1); ++k2) {
+        int c2 = D == 3 ? r[2] - k2 : 0;
+        if (c2 < 0 || c2 >= (D == 3 ? E : 1)) continue;
+        for (int k1 = 0; k1 < 3; ++k1) {
+          int c1 = r[1] - k1;
+          if (c1 < 0 || c1 >= E) continue;
+          for (int k0 = 0; k0 < 3; ++k0) {
+            int c0 = r[0] - k0;
+            if (c0 < 0 || c0 >= E) continue;
+            int cc[3] = {c0, c1, c2};
+            int lc = (int)tiled_index<D>(cc, 1) & 63;
+            int base = (((lc * 3 + (D == 3 ? k2 : 0)) * 3 + k1) * 3 + k0) * FC;
+#pragma unroll
+            for (int f = 0; f < FC; ++f) s[f] += cellpart[base + f];
+          }
         }
       }
     }
