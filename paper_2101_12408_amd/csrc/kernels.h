@@ -541,7 +541,12 @@ struct CgScal {
 };
 
 // Reduction counters (one per reduction site; each returns to zero after use).
-enum : int { CTR_DOT = 0, CTR_MOM = 1, CTR_CGSTART = 2, CTR_MERGE = 3, CTR_CGUPD = 4, CTR_COUNT = 8 };
+// Reduction counter sites.  The heat solve has its own sites (CTR_H*) so that it can run
+// on a second stream concurrently with the momentum solve.
+enum : int {
+  CTR_DOT = 0, CTR_MOM = 1, CTR_CGSTART = 2, CTR_MERGE = 3, CTR_CGUPD = 4,
+  CTR_HSTART = 5, CTR_HUPD = 6, CTR_HMERGE = 7, CTR_HDOT = 8, CTR_COUNT = 12
+};
 
 MPM_DEV int elem_node(const int* tile_list, int e) { return tile_list[e >> 6] * kTileNodes + (e & 63); }
 

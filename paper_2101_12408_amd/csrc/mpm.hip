@@ -17,7 +17,7 @@ using namespace mpm;
 
 namespace {
 
-constexpr int kNumParts = 16;   // partial-sum slots (the gradient merge reduces 2D+3 values from slot 4)
+constexpr int kNumParts = 20;   // partial-sum slots: momentum 0..12 (gradient merge: 2D+3 from slot 4), heat 16..19
 constexpr int kScalDoubles = 64;
 // Device scalars the host reads back, in one block so that every read is one copy:
 // [0, 512) FP64 scalar slots, [512, 672) the two CG scalar sets, [768, 1024) status words.
@@ -88,6 +88,7 @@ struct mpm_ctx {
   int* ctile_slot = nullptr;
   int* ctile_rng = nullptr;
   void* tpart = nullptr;        // per-cell-tile region partials
+  void* tpart_heat = nullptr;   // the heat operator's (separate: it may run concurrently)
   int nctile = 0;
   int* scan_bsum = nullptr;
   int* misc = nullptr;          // [0] status, [1] constrained flag, [2] tile count
@@ -113,6 +114,9 @@ struct mpm_ctx {
   int device = 0;
   hipStream_t own = nullptr;
   hipEvent_t own_done = nullptr;
+  // second stream of a step: the heat solve runs beside the momentum solve
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace {
@@ -182,6 +186,7 @@ size_t layout(mpm_ctx* c, char* base) {
   const int RNd = D == 3 ? TileGeo<3>::RN : TileGeo<2>::RN;
   const int NFmax = std::max(2 * D + 7, D);
   void* tpart = b.take<R>((size_t)nct_cap * RNd * NFmax);
+  void* tpart_heat = b.take<R>((size_t)nct_cap * RNd);
   int* scan_bsum = b.take<int>(kScanBlock + 1);
   char* mirror = b.take<char>(kMirrorBytes);
   int* misc = (int*)(mirror + kMirrorMisc);
@@ -216,6 +221,7 @@ size_t layout(mpm_ctx* c, char* base) {
     c->ctile_flag = ctile_flag; c->ctile_pos = ctile_pos; c->ctile_list = ctile_list; c->ctile_slot = ctile_slot;
     c->ctile_rng = ctile_rng;
     c->tpart = tpart;
+    c->tpart_heat = tpart_heat;
     c->part = d.part; c->scal = d.scal; c->cg = cg; c->ctr = ctr;
     c->sort_tmp = sort_tmp;
     if constexpr (sizeof(R) == 8) c->d64 = d; else c->d32 = d;
@@ -453,17 +459,19 @@ void do_hessvec_force(mpm_ctx* c, const R* u, R* out, hipStream_t s) {
            c->ctr + (size_t)CTR_MERGE * kCtrSite, (double*)nullptr, (double*)nullptr, (CgScal*)nullptr);
 }
 
+// Uses only the heat solve's scratch (tile partials, partial slots 18.., counters CTR_H*),
+// so that it can run beside the momentum solve.
 template <int D, typename R>
 void do_heat_apply(mpm_ctx* c, const R* T, R* out, const int* done, CgScal* cg, hipStream_t s) {
   Dev<R>& d = dev<R>(c);
   TileLists tl = tiles(c);
   if (c->nctile > 0)
     LAUNCH(c, MPM_K_HEAT_PT, (k_tile_heat<D, R>), dim3(c->nctile), dim3(TileGeo<D>::NT), 0, s, d, tl, T,
-           (R*)c->tpart, done);
+           (R*)c->tpart_heat, done);
   if (c->ntiles > 0)
-    LAUNCH(c, MPM_K_HEAT_NODE, (k_merge_heat<D, R>), dim3(merge_blocks(c)), dim3(64 * kMergeTiles), 0, s, d, tl, c->ntiles,
-           (const R*)c->tpart, T,
-           out, done, c->part + 4 * kPartSlot, c->ctr + (size_t)CTR_MERGE * kCtrSite, cg);
+    LAUNCH(c, MPM_K_HEAT_NODE, (k_merge_heat<D, R>), dim3(merge_blocks(c)), dim3(64 * kMergeTiles), 0, s, d, tl,
+           c->ntiles, (const R*)c->tpart_heat, T, out, done, c->part + 18 * kPartSlot,
+           c->ctr + (size_t)CTR_HMERGE * kCtrSite, cg);
 }
 
 template <int D, typename R>
@@ -476,13 +484,15 @@ void do_g2p(mpm_ctx* c, const R* vh, const R* Th, mpm_particles* P, hipStream_t 
            (R*)P->x, (R*)P->v, (R*)P->A, (R*)P->J, (R*)P->V0, (R*)P->m, (R*)P->T, (R*)P->gradT);
 }
 
-// a . b over the active nodes into scal[slot] (asynchronous).
+// a . b over the active nodes into scal[slot] (asynchronous).  heat: use the heat solve's
+// partial slot and counter.
 template <typename R>
-void dot_async(mpm_ctx* c, const R* a, const R* b, int ncomp, int slot, hipStream_t s) {
+void dot_async(mpm_ctx* c, const R* a, const R* b, int ncomp, int slot, hipStream_t s, bool heat = false) {
   Dev<R>& d = dev<R>(c);
   int nelem = c->ntiles * 64, nb = krylov_blocks(nelem);
   LAUNCH(c, MPM_K_BLAS, k_dot<R>, dim3(nb), dim3(256), 0, s, (const int*)d.tile_list, nelem, d.nn, ncomp, a, b,
-         c->part, c->ctr + (size_t)CTR_DOT * kCtrSite, c->scal + slot);
+         c->part + (heat ? 19 * kPartSlot : 0), c->ctr + (size_t)(heat ? CTR_HDOT : CTR_DOT) * kCtrSite,
+         c->scal + slot);
 }
 
 // Momentum sums of vh into scal[SC_MOM..] (asynchronous).
@@ -515,76 +525,84 @@ struct CgRun {
   int launched = 0;
 };
 
+// Device scratch of one CG solve: its scalars (and their host mirror), partial slots and
+// reduction counters.  Momentum and heat have separate sets.
+struct KrySet {
+  CgScal* cg;
+  CgScal* hcg;
+  double* part;
+  unsigned* ctr_start;
+  unsigned* ctr_upd;
+};
+
+inline KrySet kry_momentum(mpm_ctx* c) {
+  return KrySet{c->cg, c->hcg, c->part, c->ctr + (size_t)CTR_CGSTART * kCtrSite, c->ctr + (size_t)CTR_CGUPD * kCtrSite};
+}
+inline KrySet kry_heat(mpm_ctx* c) {
+  return KrySet{c->cg + 1, c->hcg + 1, c->part + 16 * kPartSlot, c->ctr + (size_t)CTR_HSTART * kCtrSite,
+                c->ctr + (size_t)CTR_HUPD * kCtrSite};
+}
+
 // First chunk of a solve: the iteration count of the previous solve of the same kind
 // (2..32).  Iterations queued past convergence return at once, while a chunk that is
 // too short costs a host round trip, so the schedule follows the last count.
 inline int first_chunk(int hint) { return std::max(2, std::min(hint, 32)); }
 
 template <typename R, class Apply>
-void cg_iterate(mpm_ctx* c, Apply&& apply, R* x, const R* diag, R* r, R* z, R* p, R* Ap, int ncomp, int n,
-                hipStream_t s, CgRun& run) {
+void cg_iterate(mpm_ctx* c, const KrySet& k, Apply&& apply, R* x, const R* diag, R* r, R* z, R* p, R* Ap, int ncomp,
+                int n, hipStream_t s, CgRun& run) {
   Dev<R>& d = dev<R>(c);
   int nelem = c->ntiles * 64, nb = krylov_blocks(nelem);
   const int* tl = d.tile_list;
-  const int* done = &c->cg->done;
+  const int* done = &k.cg->done;
   for (int j = 0; j < n; ++j) {
-    apply(p, Ap, done, c->cg);
-    LAUNCH(c, MPM_K_BLAS, k_cg_update<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, c->cg, x, r, z,
-           (const R*)p, (const R*)Ap, diag, c->part, c->ctr + (size_t)CTR_CGUPD * kCtrSite);
-    LAUNCH(c, MPM_K_BLAS, k_cg_p<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, (const CgScal*)c->cg,
+    apply(p, Ap, done, k.cg);
+    LAUNCH(c, MPM_K_BLAS, k_cg_update<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, k.cg, x, r, z,
+           (const R*)p, (const R*)Ap, diag, k.part, k.ctr_upd);
+    LAUNCH(c, MPM_K_BLAS, k_cg_p<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, (const CgScal*)k.cg,
            (const R*)z, p);
   }
   run.launched += n;
 }
 
 template <typename R, class Apply>
-void cg_begin(mpm_ctx* c, Apply&& apply, const R* b, double bscale, R* x, bool x0_given, const R* diag, R* r, R* z,
-              R* p, R* Ap, int ncomp, double tol2_host, const double* tol2_scale, int maxit, hipStream_t s,
-              CgRun& run, int first = 2) {
+void cg_begin(mpm_ctx* c, const KrySet& k, Apply&& apply, const R* b, double bscale, R* x, bool x0_given,
+              const R* diag, R* r, R* z, R* p, R* Ap, int ncomp, double tol2_host, const double* tol2_scale, int maxit,
+              hipStream_t s, CgRun& run, int first = 2) {
   Dev<R>& d = dev<R>(c);
   int nelem = c->ntiles * 64, nb = krylov_blocks(nelem);
   const int* tl = d.tile_list;
   if (x0_given) apply(x, Ap, (const int*)nullptr, (CgScal*)nullptr);
   LAUNCH(c, MPM_K_BLAS, k_cg_start<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, b, (R)bscale,
-         x0_given ? (const R*)Ap : (const R*)nullptr, diag, x, r, z, p, c->part, c->ctr + (size_t)CTR_CGSTART * kCtrSite,
-         c->cg, tol2_host, tol2_scale, maxit);
+         x0_given ? (const R*)Ap : (const R*)nullptr, diag, x, r, z, p, k.part, k.ctr_start, k.cg, tol2_host,
+         tol2_scale, maxit);
   run = CgRun{};
   run.chunk = std::min(first, std::max(maxit, 1));
-  cg_iterate<R>(c, apply, x, diag, r, z, p, Ap, ncomp, run.chunk, s, run);
+  cg_iterate<R>(c, k, apply, x, diag, r, z, p, Ap, ncomp, run.chunk, s, run);
 }
 
 // Returns true when it changed x after the scalars in hcg were read (more iterations, or
 // the breakdown fix-up), i.e. when work queued behind that read used an unfinished x.
 template <typename R, class Apply>
-bool cg_finish(mpm_ctx* c, Apply&& apply, R* x, const R* diag, R* r, R* z, R* p, R* Ap, int ncomp, int maxit,
-               hipStream_t s, CgRun& run) {
+bool cg_finish(mpm_ctx* c, const KrySet& k, Apply&& apply, R* x, const R* diag, R* r, R* z, R* p, R* Ap, int ncomp,
+               int maxit, hipStream_t s, CgRun& run) {
   Dev<R>& d = dev<R>(c);
   int nelem = c->ntiles * 64, nb = krylov_blocks(nelem);
   const int* tl = d.tile_list;
   bool changed = false;
-  while (!c->hcg->done && run.launched < maxit + 32) {
+  while (!k.hcg->done && run.launched < maxit + 32) {
     run.chunk = std::min(run.chunk * 2, 16);
-    cg_iterate<R>(c, apply, x, diag, r, z, p, Ap, ncomp, run.chunk, s, run);
+    cg_iterate<R>(c, k, apply, x, diag, r, z, p, Ap, ncomp, run.chunk, s, run);
     read_mirror(c, s);
     changed = true;
   }
-  if (c->hcg->breakdown && c->hcg->iters == 0) {
-    LAUNCH(c, MPM_K_BLAS, k_cg_fixup<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, (const CgScal*)c->cg, x,
+  if (k.hcg->breakdown && k.hcg->iters == 0) {
+    LAUNCH(c, MPM_K_BLAS, k_cg_fixup<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, (const CgScal*)k.cg, x,
            (const R*)z);
     changed = true;
   }
-  if (!(c->hcg->rr == c->hcg->rr)) c->status |= ST_NONFINITE;
+  if (!(k.hcg->rr == k.hcg->rr)) c->status |= ST_NONFINITE;
   return changed;
-}
-
-template <typename R, class Apply>
-int cg_solve(mpm_ctx* c, Apply&& apply, const R* b, R* x, bool x0_given, const R* diag, R* r, R* z, R* p, R* Ap,
-             int ncomp, double tol2_host, const double* tol2_scale, int maxit, hipStream_t s) {
-  CgRun run;
-  cg_begin<R>(c, apply, b, 1.0, x, x0_given, diag, r, z, p, Ap, ncomp, tol2_host, tol2_scale, maxit, s, run);
-  read_mirror(c, s);
-  cg_finish<R>(c, apply, x, diag, r, z, p, Ap, ncomp, maxit, s, run);
-  return c->hcg->iters;
 }
 
 int status_code(int bits) {
@@ -649,7 +667,8 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
     R* cp = (R*)c->pp;
     R* cAp = (R*)c->Ap;
     CgRun run;
-    cg_begin<R>(c, apply, (const R*)g, -1.0, delta, false, (const R*)d.gdiag, cr, cz, cp, cAp, D, cg_tol * cg_tol,
+    const KrySet km = kry_momentum(c);
+    cg_begin<R>(c, km, apply, (const R*)g, -1.0, delta, false, (const R*)d.gdiag, cr, cz, cp, cAp, D, cg_tol * cg_tol,
                 nullptr, p.cg_max, s, run, first_chunk(c->cg_hint_mom));
     // slope, then the full step: its energy, gradient and the translation correction with
     // |g|^2 at the corrected point.  Queued behind the first CG chunk on the guess that
@@ -670,13 +689,13 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
     dot_async<R>(c, g, delta, D, SC_SLOPE, s);
     trial_launch(alpha);
     read_mirror(c, s);
-    if (cg_finish<R>(c, apply, delta, (const R*)d.gdiag, cr, cz, cp, cAp, D, p.cg_max, s, run)) {
+    if (cg_finish<R>(c, km, apply, delta, (const R*)d.gdiag, cr, cz, cp, cAp, D, p.cg_max, s, run)) {
       // the guess failed: the trial used an unfinished delta
       dot_async<R>(c, g, delta, D, SC_SLOPE, s);
       trial_launch(alpha);
       read_mirror(c, s);
     }
-    const int cit = c->hcg->iters;
+    const int cit = km.hcg->iters;
     c->cg_hint_mom = cit;
     st.cg_iters += cit;
     st.hessvecs += cit;
@@ -755,9 +774,11 @@ void do_explicit(mpm_ctx* c, hipStream_t s) {
 }
 
 // Heat solve, split so that work can be queued behind its first CG chunk: heat_begin
-// queues T = T^n, |rhs|^2 and the CG start with two iterations; heat_end (after hcg has
-// been read) finishes the CG and records the statistics, returning true when it changed
-// T^ after that read.
+// queues T = T^n, |rhs|^2 and the CG start with its first iterations; heat_end (after
+// the scalars have been read into the host mirror) finishes the CG and records the
+// statistics, returning true when it changed T^ after that read.  The heat solve uses
+// only its own scratch (kry_heat, its tile partials), so it may run on a second stream
+// beside the momentum solve.
 template <int D, typename R>
 void heat_begin(mpm_ctx* c, hipStream_t s, CgRun& run) {
   if (!c->have_p2g) throw ApiError{MPM_EINVAL, "mpm_p2g must run first"};
@@ -767,23 +788,25 @@ void heat_begin(mpm_ctx* c, hipStream_t s, CgRun& run) {
   R* T = (R*)c->That;
   LAUNCH(c, MPM_K_BLAS, k_axpy_to<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, 1, (const R*)d.gTn, (const R*)d.gTn,
          0.0, T);
-  dot_async<R>(c, (const R*)d.hrhs, (const R*)d.hrhs, 1, SC_RHS2, s);
+  dot_async<R>(c, (const R*)d.hrhs, (const R*)d.hrhs, 1, SC_RHS2, s, true);
   auto apply = [&](const R* pv, R* Apv, const int* done, CgScal* cg) { do_heat_apply<D, R>(c, pv, Apv, done, cg, s); };
-  cg_begin<R>(c, apply, d.hrhs, 1.0, T, true, (const R*)d.hdiag, (R*)c->hr, (R*)c->hz, (R*)c->hp, (R*)c->hAp, 1,
-              c->p.heat_tol * c->p.heat_tol, c->scal + SC_RHS2, c->p.heat_max, s, run, first_chunk(c->cg_hint_heat));
+  cg_begin<R>(c, kry_heat(c), apply, d.hrhs, 1.0, T, true, (const R*)d.hdiag, (R*)c->hr, (R*)c->hz, (R*)c->hp,
+              (R*)c->hAp, 1, c->p.heat_tol * c->p.heat_tol, c->scal + SC_RHS2, c->p.heat_max, s, run,
+              first_chunk(c->cg_hint_heat));
 }
 
 template <int D, typename R>
 bool heat_end(mpm_ctx* c, hipStream_t s, CgRun& run) {
   Dev<R>& d = dev<R>(c);
+  const KrySet kh = kry_heat(c);
   auto apply = [&](const R* pv, R* Apv, const int* done, CgScal* cg) { do_heat_apply<D, R>(c, pv, Apv, done, cg, s); };
-  bool changed = cg_finish<R>(c, apply, (R*)c->That, (const R*)d.hdiag, (R*)c->hr, (R*)c->hz, (R*)c->hp, (R*)c->hAp, 1,
-                              c->p.heat_max, s, run);
-  const int it = c->hcg->iters;
+  bool changed = cg_finish<R>(c, kh, apply, (R*)c->That, (const R*)d.hdiag, (R*)c->hr, (R*)c->hz, (R*)c->hp,
+                              (R*)c->hAp, 1, c->p.heat_max, s, run);
+  const int it = kh.hcg->iters;
   c->cg_hint_heat = it;
   c->stats.heat_iters = it;
-  c->stats.heat_res = std::sqrt(std::max(c->hcg->rr, 0.0));
-  if (it >= c->p.heat_max && c->hcg->rr > c->hcg->tol2) c->status |= ST_NOCONV;
+  c->stats.heat_res = std::sqrt(std::max(kh.hcg->rr, 0.0));
+  if (it >= c->p.heat_max && kh.hcg->rr > kh.hcg->tol2) c->status |= ST_NOCONV;
   return changed;
 }
 
@@ -947,6 +970,12 @@ int mpm_ctx_destroy(mpm_ctx* ctx) {
     hipStreamDestroy(ctx->own);
   }
   if (ctx->own_done) hipEventDestroy(ctx->own_done);
+  if (ctx->aux) {
+    hipStreamSynchronize(ctx->aux);
+    hipStreamDestroy(ctx->aux);
+  }
+  if (ctx->ev_fork) hipEventDestroy(ctx->ev_fork);
+  if (ctx->ev_join) hipEventDestroy(ctx->ev_join);
   if (ctx->hmirror) hipHostFree(ctx->hmirror);
   delete ctx;
   return MPM_OK;
@@ -1083,13 +1112,26 @@ int step_one(mpm_ctx* c, mpm_particles* P, const mpm_surface* S, int implicit, h
       dispatch(c, [&](auto Dc, auto Rv) {
         constexpr int D = decltype(Dc)::value;
         using R = decltype(Rv);
-        if (implicit) do_solve_momentum<D, R>(c, s);
-        else do_explicit<D, R>(c, s);
         const bool heat = c->p.heat != 0;
         CgRun run;
-        if (heat) heat_begin<D, R>(c, s, run);
-        // G2P is queued behind the first heat CG chunk; it reads only staged data, so if
-        // the heat solve needs more iterations it is simply queued again afterwards
+        if (heat) {
+          // the heat solve needs only the grid set-up: it runs on a second stream beside
+          // the momentum solve
+          if (!c->aux) HIPCHK(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+          if (!c->ev_fork) HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+          if (!c->ev_join) HIPCHK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+          HIPCHK(hipEventRecord(c->ev_fork, s));
+          HIPCHK(hipStreamWaitEvent(c->aux, c->ev_fork, 0));
+          heat_begin<D, R>(c, c->aux, run);
+        }
+        if (implicit) do_solve_momentum<D, R>(c, s);
+        else do_explicit<D, R>(c, s);
+        if (heat) {
+          read_mirror(c, c->aux);
+          heat_end<D, R>(c, c->aux, run);
+          HIPCHK(hipEventRecord(c->ev_join, c->aux));
+          HIPCHK(hipStreamWaitEvent(s, c->ev_join, 0));
+        }
         do_g2p<D, R>(c, (const R*)c->vhat, heat ? (const R*)c->That : nullptr, P, s);
         read_mirror(c, s);
         if (c->mom_pending) {
@@ -1097,10 +1139,6 @@ int step_one(mpm_ctx* c, mpm_particles* P, const mpm_surface* S, int implicit, h
           c->mom_pending = false;
         }
         synced = true;
-        if (heat && heat_end<D, R>(c, s, run)) {
-          do_g2p<D, R>(c, (const R*)c->vhat, (const R*)c->That, P, s);
-          synced = false;
-        }
       });
     });
   }
