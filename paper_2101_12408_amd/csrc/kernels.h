@@ -576,8 +576,24 @@ __global__ void k_finalize(const double* part, int nb, int nslot, double* dst) {
   }
 }
 
+// Fused direction update of CG: an operator applied to the direction p first forms
+// p = z + beta p (beta from the CG scalars; 0 before the first update, when p = z), and
+// its node kernel stores the new p.  z == nullptr: no update.
+template <typename R>
+struct PUpd {
+  R* p;
+  const R* z;
+  const CgScal* cg;
+};
+
+// The new direction z + beta p, contracted explicitly so that the operator's two kernels
+// form it bitwise alike.
+MPM_DEV float cg_dir(float z, float beta, float p) { return __builtin_fmaf(beta, p, z); }
+MPM_DEV double cg_dir(double z, double beta, double p) { return __builtin_fma(beta, p, z); }
+
 // CG scalars from the sums r.z, r.r of the starting residual.
 MPM_DEV void cg_init(CgScal* s, double rz, double rr, double tol2, int maxit) {
+  s->beta = 0;
   s->rz = rz;
   s->rr = rr;
   s->tol2 = tol2;
@@ -653,19 +669,6 @@ __global__ void k_cg_update(const int* tl, int nelem, int nn, int ncomp, CgScal*
       s->rr = rrs;
       s->iters += 1;
       if (rrs <= s->tol2 || s->iters >= s->maxit || !(rrs == rrs)) s->done = 1;
-    }
-  }
-}
-
-template <typename R>
-__global__ void k_cg_p(const int* tl, int nelem, int nn, int ncomp, const CgScal* s, const R* z, R* p) {
-  if (s->done) return;
-  R beta = (R)s->beta;
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nelem; e += gridDim.x * blockDim.x) {
-    int node = elem_node(tl, e);
-    for (int c = 0; c < ncomp; ++c) {
-      int j = c * nn + node;
-      p[j] = z[j] + beta * p[j];
     }
   }
 }

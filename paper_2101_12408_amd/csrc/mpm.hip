@@ -407,12 +407,12 @@ void do_energy_grad(mpm_ctx* c, const R* u, R* g, double* energy_dev, int red_sl
   TileLists tl = tiles(c);
   if (c->nctile > 0)
     LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_ENERGY>), dim3(c->nctile), dim3(TileGeo<D>::NT), 0, s, d, tl,
-           u, (R*)c->tpart, 0, (const int*)nullptr, 2);
+           u, (R*)c->tpart, 0, (const int*)nullptr, 2, PUpd<R>{});
   if (c->ntiles > 0) {
     LAUNCH(c, MPM_K_ENERGY_NODE, (k_merge_stress<D, R>), dim3(merge_blocks(c)), dim3(64 * kMergeTiles), 0, s, d, tl,
            c->ntiles, (const R*)c->tpart, u, g, (int)NM_GRAD, 0.0, 0, (const int*)nullptr,
            c->nctile > 0 ? (const double*)(c->part + 2 * kPartSlot) : nullptr, c->nctile, c->part + 4 * kPartSlot,
-           c->ctr + (size_t)CTR_MERGE * kCtrSite, c->scal + red_slot, energy_dev, (CgScal*)nullptr);
+           c->ctr + (size_t)CTR_MERGE * kCtrSite, c->scal + red_slot, energy_dev, (CgScal*)nullptr, PUpd<R>{});
   } else {
     LAUNCH(c, MPM_K_BLAS, k_fill_r<double>, dim3(1), dim3(64), 0, s, c->scal + red_slot, 0.0, (int64_t)(2 * D + 3));
     if (energy_dev) LAUNCH(c, MPM_K_BLAS, k_fill_r<double>, dim3(1), dim3(1), 0, s, energy_dev, 0.0, (int64_t)1);
@@ -428,20 +428,21 @@ void do_surface_lin(mpm_ctx* c, const R* vlin, hipStream_t s) {
 }
 
 // out = P(alpha M P w + H P w) with the surface term linearized at the cached F_r.  With cg
-// the merge also reduces w . out and sets the CG step length.
+// the merge also reduces w . out and sets the CG step length.  With z (a CG direction w):
+// w is first replaced by z + beta w, which the merge stores.
 template <int D, typename R>
 void do_hessvec(mpm_ctx* c, const R* w, double alpha, R* out, bool mask_in, const int* done, CgScal* cg,
-                hipStream_t s) {
+                hipStream_t s, PUpd<R> pu = PUpd<R>{}) {
   Dev<R>& d = dev<R>(c);
   TileLists tl = tiles(c);
   if (c->nctile > 0)
     LAUNCH(c, MPM_K_HESS_INT, (k_tile_stress<D, R, TM_HESS>), dim3(c->nctile), dim3(TileGeo<D>::NT), 0, s, d, tl, w,
-           (R*)c->tpart, (int)mask_in, done, -1);
+           (R*)c->tpart, (int)mask_in, done, -1, pu);
   if (c->ntiles > 0)
     LAUNCH(c, MPM_K_HESS_NODE, (k_merge_stress<D, R>), dim3(merge_blocks(c)), dim3(64 * kMergeTiles), 0, s, d, tl, c->ntiles,
            (const R*)c->tpart,
            w, out, (int)NM_HESS, alpha, (int)mask_in, done, (const double*)nullptr, 0, c->part + 4 * kPartSlot,
-           c->ctr + (size_t)CTR_MERGE * kCtrSite, (double*)nullptr, (double*)nullptr, cg);
+           c->ctr + (size_t)CTR_MERGE * kCtrSite, (double*)nullptr, (double*)nullptr, cg, pu);
 }
 
 // Forces only (no inertia term): out = P sum_q S_q grad N_i for the stress of u.
@@ -451,27 +452,28 @@ void do_hessvec_force(mpm_ctx* c, const R* u, R* out, hipStream_t s) {
   TileLists tl = tiles(c);
   if (c->nctile > 0)
     LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_FORCE>), dim3(c->nctile), dim3(TileGeo<D>::NT), 0, s, d, tl,
-           u, (R*)c->tpart, 0, (const int*)nullptr, -1);
+           u, (R*)c->tpart, 0, (const int*)nullptr, -1, PUpd<R>{});
   if (c->ntiles > 0)
     LAUNCH(c, MPM_K_ENERGY_NODE, (k_merge_stress<D, R>), dim3(merge_blocks(c)), dim3(64 * kMergeTiles), 0, s, d, tl, c->ntiles,
            (const R*)c->tpart,
            u, out, (int)NM_HESS, 0.0, 0, (const int*)nullptr, (const double*)nullptr, 0, c->part + 4 * kPartSlot,
-           c->ctr + (size_t)CTR_MERGE * kCtrSite, (double*)nullptr, (double*)nullptr, (CgScal*)nullptr);
+           c->ctr + (size_t)CTR_MERGE * kCtrSite, (double*)nullptr, (double*)nullptr, (CgScal*)nullptr, PUpd<R>{});
 }
 
 // Uses only the heat solve's scratch (tile partials, partial slots 18.., counters CTR_H*),
 // so that it can run beside the momentum solve.
 template <int D, typename R>
-void do_heat_apply(mpm_ctx* c, const R* T, R* out, const int* done, CgScal* cg, hipStream_t s) {
+void do_heat_apply(mpm_ctx* c, const R* T, R* out, const int* done, CgScal* cg, hipStream_t s,
+                   PUpd<R> pu = PUpd<R>{}) {
   Dev<R>& d = dev<R>(c);
   TileLists tl = tiles(c);
   if (c->nctile > 0)
     LAUNCH(c, MPM_K_HEAT_PT, (k_tile_heat<D, R>), dim3(c->nctile), dim3(TileGeo<D>::NT), 0, s, d, tl, T,
-           (R*)c->tpart_heat, done);
+           (R*)c->tpart_heat, done, pu);
   if (c->ntiles > 0)
     LAUNCH(c, MPM_K_HEAT_NODE, (k_merge_heat<D, R>), dim3(merge_blocks(c)), dim3(64 * kMergeTiles), 0, s, d, tl,
            c->ntiles, (const R*)c->tpart_heat, T, out, done, c->part + 18 * kPartSlot,
-           c->ctr + (size_t)CTR_HMERGE * kCtrSite, cg);
+           c->ctr + (size_t)CTR_HMERGE * kCtrSite, cg, pu);
 }
 
 template <int D, typename R>
@@ -555,12 +557,12 @@ void cg_iterate(mpm_ctx* c, const KrySet& k, Apply&& apply, R* x, const R* diag,
   int nelem = c->ntiles * 64, nb = krylov_blocks(nelem);
   const int* tl = d.tile_list;
   const int* done = &k.cg->done;
+  // each operator application first forms the direction p = z + beta p (beta = 0 on the
+  // first, which leaves p = z from the start)
   for (int j = 0; j < n; ++j) {
-    apply(p, Ap, done, k.cg);
+    apply(p, Ap, done, k.cg, PUpd<R>{p, z, k.cg});
     LAUNCH(c, MPM_K_BLAS, k_cg_update<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, k.cg, x, r, z,
            (const R*)p, (const R*)Ap, diag, k.part, k.ctr_upd);
-    LAUNCH(c, MPM_K_BLAS, k_cg_p<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, (const CgScal*)k.cg,
-           (const R*)z, p);
   }
   run.launched += n;
 }
@@ -572,7 +574,7 @@ void cg_begin(mpm_ctx* c, const KrySet& k, Apply&& apply, const R* b, double bsc
   Dev<R>& d = dev<R>(c);
   int nelem = c->ntiles * 64, nb = krylov_blocks(nelem);
   const int* tl = d.tile_list;
-  if (x0_given) apply(x, Ap, (const int*)nullptr, (CgScal*)nullptr);
+  if (x0_given) apply(x, Ap, (const int*)nullptr, (CgScal*)nullptr, PUpd<R>{});
   LAUNCH(c, MPM_K_BLAS, k_cg_start<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, b, (R)bscale,
          x0_given ? (const R*)Ap : (const R*)nullptr, diag, x, r, z, p, k.part, k.ctr_start, k.cg, tol2_host,
          tol2_scale, maxit);
@@ -647,8 +649,8 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
   st.g0 = g0;
   st.energy_evals = 1;
   st.converged = 0;
-  auto apply = [&](const R* pv, R* Apv, const int* done, CgScal* cg) {
-    do_hessvec<D, R>(c, pv, 1.0, Apv, false, done, cg, s);
+  auto apply = [&](const R* pv, R* Apv, const int* done, CgScal* cg, PUpd<R> pu) {
+    do_hessvec<D, R>(c, pv, 1.0, Apv, false, done, cg, s, pu);
   };
   const double eps = sizeof(R) == 8 ? 2.220446049250313e-16 : 1.1920928955078125e-07;
   int it = 0;
@@ -789,7 +791,9 @@ void heat_begin(mpm_ctx* c, hipStream_t s, CgRun& run) {
   LAUNCH(c, MPM_K_BLAS, k_axpy_to<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, 1, (const R*)d.gTn, (const R*)d.gTn,
          0.0, T);
   dot_async<R>(c, (const R*)d.hrhs, (const R*)d.hrhs, 1, SC_RHS2, s, true);
-  auto apply = [&](const R* pv, R* Apv, const int* done, CgScal* cg) { do_heat_apply<D, R>(c, pv, Apv, done, cg, s); };
+  auto apply = [&](const R* pv, R* Apv, const int* done, CgScal* cg, PUpd<R> pu) {
+    do_heat_apply<D, R>(c, pv, Apv, done, cg, s, pu);
+  };
   cg_begin<R>(c, kry_heat(c), apply, d.hrhs, 1.0, T, true, (const R*)d.hdiag, (R*)c->hr, (R*)c->hz, (R*)c->hp,
               (R*)c->hAp, 1, c->p.heat_tol * c->p.heat_tol, c->scal + SC_RHS2, c->p.heat_max, s, run,
               first_chunk(c->cg_hint_heat));
@@ -799,7 +803,9 @@ template <int D, typename R>
 bool heat_end(mpm_ctx* c, hipStream_t s, CgRun& run) {
   Dev<R>& d = dev<R>(c);
   const KrySet kh = kry_heat(c);
-  auto apply = [&](const R* pv, R* Apv, const int* done, CgScal* cg) { do_heat_apply<D, R>(c, pv, Apv, done, cg, s); };
+  auto apply = [&](const R* pv, R* Apv, const int* done, CgScal* cg, PUpd<R> pu) {
+    do_heat_apply<D, R>(c, pv, Apv, done, cg, s, pu);
+  };
   bool changed = cg_finish<R>(c, kh, apply, (R*)c->That, (const R*)d.hdiag, (R*)c->hr, (R*)c->hz, (R*)c->hp,
                               (R*)c->hAp, 1, c->p.heat_max, s, run);
   const int it = kh.hcg->iters;

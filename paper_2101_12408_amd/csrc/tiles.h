@@ -437,7 +437,8 @@ MPM_DEV void stress_fetch(const Dev<R>& d, int q, int ntot, int npi, int pb, int
 
 template <int D, typename R, int MODE>
 __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stress(Dev<R> d, TileLists tl, const R* u, R* tpart,
-                                                                int mask_in, const int* done, int energy_slot) {
+                                                                int mask_in, const int* done, int energy_slot,
+                                                                PUpd<R> pu) {
   constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
   constexpr int CH = StressLds<D, R>::CH, PW = StressLds<D, R>::PW;
   __shared__ StressLds<D, R> sm;
@@ -460,14 +461,21 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
   // first chunk's point inputs, issued together with the node staging below
   StressIn<D, R, MODE> in;
   if (t < CH) stress_fetch<D, R, MODE>(d, t, ntot, npi, pb, sb, visc, in);
+  const R beta = pu.z ? (R)pu.cg->beta : R(0);
   for (int rn = t; rn < RN; rn += NT) {
     int r[3];
     region_coords<D>(rn, r);
     int gnode = region_node_global<D>(ct, r, d.n, d.nt);
     uint8_t fr = (gnode >= 0 && mask_in) ? d.gfree[gnode] : 0xff;
 #pragma unroll
-    for (int a = 0; a < D; ++a)
-      sm.u[rn * D + a] = (gnode >= 0 && ((fr >> a) & 1)) ? u[a * nn + gnode] : R(0);
+    for (int a = 0; a < D; ++a) {
+      R val = R(0);
+      if (gnode >= 0 && ((fr >> a) & 1)) {
+        val = u[a * nn + gnode];
+        if (pu.z) val = cg_dir(pu.z[a * nn + gnode], beta, val);
+      }
+      sm.u[rn * D + a] = val;
+    }
   }
   int lcell, lk0, lk1;
   lane_map<D>(t, lcell, lk0, lk1);
@@ -653,7 +661,7 @@ struct HeatLds {
 
 template <int D, typename R>
 __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::HEAT) k_tile_heat(Dev<R> d, TileLists tl, const R* T, R* tpart,
-                                                              const int* done) {
+                                                              const int* done, PUpd<R> pu) {
   constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN, PW = HeatLds<D, R>::PW, CH = HeatLds<D, R>::CH;
   __shared__ HeatLds<D, R> sm;
   if (done && *done) return;
@@ -662,11 +670,17 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::HEAT) k_tile_heat(De
   const int t = threadIdx.x;
   int org[3] = {0, 0, 0};
   tiled_coords<D>(ct, 0, d.nt, org);
+  const R beta = pu.z ? (R)pu.cg->beta : R(0);
   for (int rn = t; rn < RN; rn += NT) {
     int r[3];
     region_coords<D>(rn, r);
     int gnode = region_node_global<D>(ct, r, d.n, d.nt);
-    sm.u[rn] = gnode >= 0 ? T[gnode] : R(0);
+    R val = R(0);
+    if (gnode >= 0) {
+      val = T[gnode];
+      if (pu.z) val = cg_dir(pu.z[gnode], beta, val);
+    }
+    sm.u[rn] = val;
   }
   const int cb = ct * 64;
   const int* rg = tl.ctile_rng + 6 * blockIdx.x;
@@ -1155,7 +1169,7 @@ template <int D, typename R>
 __global__ void __launch_bounds__(64 * kMergeTiles) k_merge_stress(
     Dev<R> d, TileLists tl, int ntiles, const R* tpart, const R* u, R* out, int mode, double alpha, int mask_in,
     const int* done, const double* epart, int nep, double* npart, unsigned* ctr, double* red, double* phi2,
-    CgScal* cg) {
+    CgScal* cg, PUpd<R> pu) {
   constexpr int RN = TileGeo<D>::RN;
   constexpr int NV = 2 * D + 3;
   __shared__ double sh[kRedSh];
@@ -1190,10 +1204,15 @@ __global__ void __launch_bounds__(64 * kMergeTiles) k_merge_stress(
     R m = d.gm[node];
     const bool dof = fr & 0x80;
     if (dof && mode == NM_GRAD) vals[D + 1] = (double)m;
+    const R beta = pu.z ? (R)pu.cg->beta : R(0);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       bool fa = (fr >> a) & 1;
       R ua = u ? u[a * nn + node] : R(0);
+      if (pu.z) {
+        ua = cg_dir(pu.z[a * nn + node], beta, ua);
+        pu.p[a * nn + node] = ua;
+      }
       R o;
       if (mode == NM_GRAD) {
         R vn = d.gvn[a * nn + node];
@@ -1237,7 +1256,8 @@ __global__ void __launch_bounds__(64 * kMergeTiles) k_merge_stress(
 template <int D, typename R>
 __global__ void __launch_bounds__(64 * kMergeTiles) k_merge_heat(Dev<R> d, TileLists tl, int ntiles,
                                                                  const R* tpart, const R* T, R* out, const int* done,
-                                                                 double* npart, unsigned* ctr, CgScal* cg) {
+                                                                 double* npart, unsigned* ctr, CgScal* cg,
+                                                                 PUpd<R> pu) {
   constexpr int RN = TileGeo<D>::RN;
   __shared__ double sh[kRedSh];
   if (done && *done) return;
@@ -1258,6 +1278,10 @@ __global__ void __launch_bounds__(64 * kMergeTiles) k_merge_heat(Dev<R> d, TileL
     for (int j = 0; j < (1 << D); ++j) acc += val[j];
     bool dof = d.gfree[node] & 0x80;
     R Ti = T[node];
+    if (pu.z) {
+      Ti = cg_dir(pu.z[node], (R)pu.cg->beta, Ti);
+      pu.p[node] = Ti;
+    }
     R o = dof ? d.cp / d.dt * d.gm[node] * Ti + acc : R(0);
     out[node] = o;
     if (dof) dotv = (double)Ti * (double)o;
