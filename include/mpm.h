@@ -53,7 +53,7 @@ enum mpm_status {
   MPM_EDOMAIN = 4,    /* a point's stencil leaves the grid (not in [dx, 1-dx)^dim)   */
   MPM_ENOCONV = 5,    /* Newton or a Krylov solve hit its iteration cap              */
   MPM_ENONFINITE = 6, /* a residual norm or energy became NaN or Inf                 */
-  MPM_EHIP = 7        /* a HIP runtime call failed                                   */
+  MPM_EHIP = 7        /* a HIP runtime call failed, or a bounded device wait gave up */
 };
 
 enum mpm_precision { MPM_FP64 = 0, MPM_MIXED = 1 };

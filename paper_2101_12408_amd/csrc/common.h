@@ -292,7 +292,9 @@ MPM_DEV bool grid_reduce(const double* vals, double* part, unsigned* ctr, double
 }
 
 // Latched device status word bits.
-enum : int { ST_DOMAIN = 1, ST_NONFINITE = 2, ST_NOCONV = 4 };
+// ST_STALL: a bounded device-side wait gave up; ST_INTERNAL: a consistency check failed
+// (results of the step are invalid in both cases).
+enum : int { ST_DOMAIN = 1, ST_NONFINITE = 2, ST_NOCONV = 4, ST_STALL = 8, ST_INTERNAL = 16 };
 
 MPM_DEV void flag_status(int* st, int bit) { atomicOr(st, bit); }
 

@@ -49,96 +49,180 @@ constexpr int kPartSlot = kRedSlot;  // partial sums per reduction slot
 // ======================================================================================
 // Cell sort: keys, counts, slots, per-cell order fix-up.
 // ======================================================================================
+// Runs of equal keys among the consecutive lanes of a wave (lanes with act form a prefix
+// of the wave): the lane of the run's first element and the run's length.  Points come
+// in nearly cell order, so one atomic per run replaces one per point.
+MPM_DEV void wave_run(int key, bool act, int& head, int& len) {
+  const int lane = __lane_id();
+  const int prev = __shfl_up(key, 1, kWave);
+  const uint64_t heads = __ballot(act && (lane == 0 || prev != key));
+  const uint64_t nact = __popcll(__ballot(act));
+  const uint64_t upto = (2ull << lane) - 1;   // lanes 0..lane (all ones for lane 63)
+  head = 0;
+  len = 0;
+  if (act) {
+    head = 63 - __builtin_clzll(heads & upto);
+    const uint64_t after = heads & ~upto;
+    len = (after ? __builtin_ctzll(after) : (int)nact) - head;
+  }
+}
+
 template <int D, typename R>
 __global__ void k_cell_keys(const R* pos, int cnt, int n, int nt, R fn, int* key, int* ccount, int* status) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= cnt) return;
-  R x[D];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool act = i < cnt;
+  int k = 0;
+  if (act) {
+    R x[D];
 #pragma unroll
-  for (int a = 0; a < D; ++a) x[a] = pos[(int64_t)a * cnt + i];
-  int c[D]; R f[D]; bool bad = false;
-  locate<D, R>(x, n, fn, c, f, &bad);
-  if (bad) flag_status(status, ST_DOMAIN);
-  int k = (int)tiled_index<D>(c, nt);
-  key[i] = k;
-  atomicAdd(&ccount[k], 1);
+    for (int a = 0; a < D; ++a) x[a] = pos[(int64_t)a * cnt + i];
+    int c[D]; R f[D]; bool bad = false;
+    locate<D, R>(x, n, fn, c, f, &bad);
+    if (bad) flag_status(status, ST_DOMAIN);
+    k = (int)tiled_index<D>(c, nt);
+    key[i] = k;
+  }
+  int head, len;
+  wave_run(k, act, head, len);
+  if (act && __lane_id() == head) atomicAdd(&ccount[k], len);
 }
 
 constexpr int kScanT = 256, kScanI = 16, kScanBlock = kScanT * kScanI;
+constexpr int kScanSpin = 1 << 22;   // polls of one look-back window before giving up
 
-// Exclusive scan of in[0,len) into out[0,len), block totals into bsum.
-__global__ void k_scan_local(const int* in, int* out, int len, int* bsum) {
-  __shared__ int sh[kScanT];
-  int base = blockIdx.x * kScanBlock + threadIdx.x * kScanI;
+// Status word of a scan block: value | state << 32 | epoch << 34, state 1 = the block's
+// own sum, 2 = its inclusive prefix.  Words of an earlier scan carry another epoch.
+MPM_DEV uint64_t scan_word(unsigned epoch, unsigned state, unsigned value) {
+  return (uint64_t)value | ((uint64_t)state << 32) | ((uint64_t)epoch << 34);
+}
+
+// Sum over the wave, in every lane.
+MPM_DEV int wave_sum_all(int v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// Single-pass exclusive scan of in[0,len) into out[0,len), out[len] = total.  Block b
+// scans kScanBlock elements; it publishes its sum at once, then wave 0 reads the status
+// words of up to 64 predecessors at a time, going back until it meets an inclusive prefix
+// (block 0 publishes one at once), and publishes its own.  Workgroups start in index order,
+// so every predecessor is running or done and each wait ends; the wait is still bounded:
+// after kScanSpin polls without progress the block flags ST_STALL and the scan is invalid.
+__global__ void __launch_bounds__(kScanT) k_scan(const int* in, int* out, int len, uint64_t* flags, unsigned epoch,
+                                                 int* status) {
+  __shared__ int wsum[kScanT / kWave];
+  __shared__ int excl;
+  const int b = blockIdx.x, t = threadIdx.x, lane = t & (kWave - 1), wid = t / kWave;
+  const int base = b * kScanBlock + t * kScanI;
   int v[kScanI];
+  if (base + kScanI <= len) {
+    const int4* p4 = (const int4*)(in + base);
+#pragma unroll
+    for (int q = 0; q < kScanI / 4; ++q) {
+      int4 x = p4[q];
+      v[4 * q] = x.x; v[4 * q + 1] = x.y; v[4 * q + 2] = x.z; v[4 * q + 3] = x.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kScanI; ++k) v[k] = base + k < len ? in[base + k] : 0;
+  }
   int s = 0;
 #pragma unroll
-  for (int k = 0; k < kScanI; ++k) {
-    int idx = base + k;
-    v[k] = idx < len ? in[idx] : 0;
-    s += v[k];
+  for (int k = 0; k < kScanI; ++k) s += v[k];
+  int incl = s;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    int y = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += y;
   }
-  sh[threadIdx.x] = s;
+  if (lane == kWave - 1) wsum[wid] = incl;
   __syncthreads();
-  for (int off = 1; off < kScanT; off <<= 1) {      // Hillis-Steele inclusive scan
-    int t = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
-    __syncthreads();
-    sh[threadIdx.x] += t;
-    __syncthreads();
-  }
-  int run = sh[threadIdx.x] - s;
+  int woff = 0, total = 0;
 #pragma unroll
-  for (int k = 0; k < kScanI; ++k) {
-    int idx = base + k;
-    if (idx < len) out[idx] = run;
-    run += v[k];
+  for (int w = 0; w < kScanT / kWave; ++w) {
+    int x = wsum[w];
+    woff += w < wid ? x : 0;
+    total += x;
   }
-  if (threadIdx.x == kScanT - 1) bsum[blockIdx.x] = sh[kScanT - 1];
-}
-
-// Single block: exclusive scan of bsum[0,nb) in place; total -> *total.
-__global__ void k_scan_sums(int* bsum, int nb, int* total) {
-  __shared__ int sh[kScanT];
-  int base = threadIdx.x * kScanI;
-  int v[kScanI];
-  int s = 0;
-#pragma unroll
-  for (int k = 0; k < kScanI; ++k) {
-    int idx = base + k;
-    v[k] = idx < nb ? bsum[idx] : 0;
-    s += v[k];
+  if (wid == 0) {
+    if (b == 0) {
+      if (lane == 0) {
+        __hip_atomic_store(flags, scan_word(epoch, 2, (unsigned)total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        excl = 0;
+      }
+    } else {
+      if (lane == 0)
+        __hip_atomic_store(flags + b, scan_word(epoch, 1, (unsigned)total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int prefix = 0, top = b - 1, spins = 0;
+      bool stalled = false;
+      for (;;) {
+        const int idx = top - lane;
+        uint64_t w = idx >= 0 ? __hip_atomic_load(flags + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+        const unsigned st = (unsigned)(w >> 32) & 3u;
+        const bool ready = idx < 0 || ((unsigned)(w >> 34) == epoch && st != 0);
+        const uint64_t waiting = __ballot(!ready);
+        const uint64_t pref = __ballot(idx >= 0 && ready && st == 2);
+        const int pl = pref ? __builtin_ctzll(pref) : kWave;             // nearest prefix
+        const uint64_t upto = pl == kWave ? ~0ull : (2ull << pl) - 1;   // lanes 0..pl
+        if ((waiting & upto) == 0) {
+          prefix += wave_sum_all(lane <= pl && idx >= 0 ? (int)(unsigned)w : 0);
+          if (pl < kWave) break;
+          top -= kWave;
+          spins = 0;
+          continue;
+        }
+        if (++spins > kScanSpin) { stalled = true; break; }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      if (lane == 0) {
+        if (stalled) flag_status(status, ST_STALL);
+        __hip_atomic_store(flags + b, scan_word(epoch, 2, (unsigned)(prefix + total)), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        excl = prefix;
+      }
+    }
   }
-  sh[threadIdx.x] = s;
   __syncthreads();
-  for (int off = 1; off < kScanT; off <<= 1) {
-    int t = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
-    __syncthreads();
-    sh[threadIdx.x] += t;
-    __syncthreads();
-  }
-  int run = sh[threadIdx.x] - s;
+  int run = excl + woff + incl - s;
+  if (base + kScanI <= len) {
+    int4* o4 = (int4*)(out + base);
 #pragma unroll
-  for (int k = 0; k < kScanI; ++k) {
-    int idx = base + k;
-    if (idx < nb) bsum[idx] = run;
-    run += v[k];
+    for (int q = 0; q < kScanI / 4; ++q) {
+      int4 x;
+      x.x = run; run += v[4 * q];
+      x.y = run; run += v[4 * q + 1];
+      x.z = run; run += v[4 * q + 2];
+      x.w = run; run += v[4 * q + 3];
+      o4[q] = x;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kScanI; ++k) {
+      if (base + k < len) out[base + k] = run;
+      run += v[k];
+    }
   }
-  if (threadIdx.x == kScanT - 1) *total = sh[kScanT - 1];
+  if (b == (int)gridDim.x - 1 && t == kScanT - 1) out[len] = excl + total;
 }
 
-__global__ void k_scan_add(int* out, int len, const int* bsum) {
-  int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= len) return;
-  out[idx] += bsum[idx / kScanBlock];
-}
-
-// slot = start[key] + (remaining count - 1); leaves the cell counter at zero.
-__global__ void k_cell_scatter(const int* key, int cnt, const int* start, int* ccount, int* perm) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= cnt) return;
-  int k = key[i];
-  int slot = start[k] + atomicSub(&ccount[k], 1) - 1;
-  perm[slot] = i;
+// Slots from the remaining cell count: a run of len equal keys takes the len slots below
+// start[key] + (count before its atomic), in input order.  Leaves the counters at zero.
+__global__ void k_cell_scatter(const int* key, int cnt, const int* start, int* ccount, int* perm, int* status) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool act = i < cnt;
+  const int k = act ? key[i] : 0;
+  int head, len;
+  wave_run(k, act, head, len);
+  const int lane = __lane_id();
+  int rem = 0;
+  if (act && lane == head) rem = atomicSub(&ccount[k], len);
+  rem = __shfl(rem, head, kWave);
+  if (act) {
+    const int slot = start[k] + rem - len + (lane - head);
+    if (slot >= 0 && slot < cnt) perm[slot] = i;
+    else flag_status(status, ST_INTERNAL);
+  }
 }
 
 // Segment ordering after an atomic scatter: the segment of slot s is the run of slots
@@ -743,8 +827,9 @@ __global__ void k_mom_sums(const int* tl, int nelem, int nn, const uint8_t* fr, 
 template <int D, typename R>
 __global__ void k_mom_fix(const int* tl, int nelem, int nn, const uint8_t* fr, const R* m, const double* red,
                           double dt, double g0, double g1, double g2, R* vh, R* grad, double* part, unsigned* ctr,
-                          double* gn2) {
+                          double* gn2, const int* skip) {
   __shared__ double sh[kRedSh];
+  if (*skip) return;   // a constrained component: no translation correction (uniform in the grid)
   double msum = red[D];
   double gg[3] = {g0, g1, g2};
   R c[D];

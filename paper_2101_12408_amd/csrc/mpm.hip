@@ -22,6 +22,9 @@ constexpr int kScalDoubles = 64;
 // Device scalars the host reads back, in one block so that every read is one copy:
 // [0, 512) FP64 scalar slots, [512, 672) the two CG scalar sets, [768, 1024) status words.
 constexpr int kMirrorBytes = 1024, kMirrorCg = 512, kMirrorMisc = 768, kMirrorRead = 800;
+// Host-only slot of the pinned mirror (past the part that read_mirror copies): the heat
+// solve's CG scalars, read on their own stream.
+constexpr int kMirrorHeatHost = 896;
 
 struct HipError {
   hipError_t e;
@@ -90,7 +93,13 @@ struct mpm_ctx {
   void* tpart = nullptr;        // per-cell-tile region partials
   void* tpart_heat = nullptr;   // the heat operator's (separate: it may run concurrently)
   int nctile = 0;
-  int* scan_bsum = nullptr;
+  uint64_t* scan_flags = nullptr;   // status words of the single-pass scan (kScanBlock)
+  unsigned scan_epoch = 0;
+  // the same sort scratch for the surface-sample sort on the second stream
+  int* ccount_aux = nullptr;
+  int* sort_tmp_aux = nullptr;
+  uint64_t* scan_flags_aux = nullptr;
+  unsigned scan_epoch_aux = 0;
   int* misc = nullptr;          // [0] status, [1] constrained flag, [2] tile count
   double* part = nullptr;
   double* scal = nullptr;
@@ -103,7 +112,7 @@ struct mpm_ctx {
   int* hint = nullptr;
   CgScal* hcg = nullptr;
   // state
-  int np = 0, ns = 0, ntiles = 0, prev_ntiles = 0;
+  int np = 0, ns = 0, ntiles = 0, prev_ntiles = 0, prev_nctile = 0;
   bool have_p2g = false, constrained = false, mom_pending = false;
   // Krylov launch schedule learned from the previous solves (first chunk sizes)
   int cg_hint_mom = 2, cg_hint_heat = 2;
@@ -116,7 +125,8 @@ struct mpm_ctx {
   hipEvent_t own_done = nullptr;
   // second stream of a step: the heat solve runs beside the momentum solve
   hipStream_t aux = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_hread = nullptr, ev_counts = nullptr, ev_sfork = nullptr,
+             ev_sjoin = nullptr;
 };
 
 namespace {
@@ -187,7 +197,7 @@ size_t layout(mpm_ctx* c, char* base) {
   const int NFmax = std::max(2 * D + 7, D);
   void* tpart = b.take<R>((size_t)nct_cap * RNd * NFmax);
   void* tpart_heat = b.take<R>((size_t)nct_cap * RNd);
-  int* scan_bsum = b.take<int>(kScanBlock + 1);
+  uint64_t* scan_flags = b.take<uint64_t>(kScanBlock);
   char* mirror = b.take<char>(kMirrorBytes);
   int* misc = (int*)(mirror + kMirrorMisc);
   d.px = b.take<R>(D * NP); d.pv = b.take<R>(D * NP); d.pA = b.take<R>(D * D * NP);
@@ -208,22 +218,27 @@ size_t layout(mpm_ctx* c, char* base) {
   d.scal = (double*)mirror;
   CgScal* cg = (CgScal*)(mirror + kMirrorCg);
   static_assert(kScalDoubles * sizeof(double) <= kMirrorCg && kMirrorCg + 2 * sizeof(CgScal) <= kMirrorMisc &&
-                    kMirrorMisc + 8 * sizeof(int) <= kMirrorRead && kMirrorRead <= kMirrorBytes,
+                    kMirrorMisc + 8 * sizeof(int) <= kMirrorRead && kMirrorRead <= kMirrorHeatHost &&
+                    kMirrorHeatHost + sizeof(CgScal) <= kMirrorBytes,
                 "mirror layout");
   unsigned* ctr = b.take<unsigned>((size_t)CTR_COUNT * kCtrSite);
   int* sort_tmp = b.take<int>(std::max(NP, NS));
+  int* ccount_aux = b.take<int>(NN);
+  int* sort_tmp_aux = b.take<int>(NS);
+  uint64_t* scan_flags_aux = b.take<uint64_t>(kScanBlock);
   d.status = misc;
   if (base) {
     c->vhat = vecs[0]; c->vtrial = vecs[1]; c->grad = vecs[2]; c->delta = vecs[3]; c->r = vecs[4];
     c->z = vecs[5]; c->pp = vecs[6]; c->Ap = vecs[7]; c->zero = vecs[8]; c->gscratch = vecs[9];
     c->That = hvecs[0]; c->hr = hvecs[1]; c->hz = hvecs[2]; c->hp = hvecs[3]; c->hAp = hvecs[4];
-    c->tile_pos = tile_pos; c->scan_bsum = scan_bsum; c->misc = misc;
+    c->tile_pos = tile_pos; c->scan_flags = scan_flags; c->misc = misc;
     c->ctile_flag = ctile_flag; c->ctile_pos = ctile_pos; c->ctile_list = ctile_list; c->ctile_slot = ctile_slot;
     c->ctile_rng = ctile_rng;
     c->tpart = tpart;
     c->tpart_heat = tpart_heat;
     c->part = d.part; c->scal = d.scal; c->cg = cg; c->ctr = ctr;
     c->sort_tmp = sort_tmp;
+    c->ccount_aux = ccount_aux; c->sort_tmp_aux = sort_tmp_aux; c->scan_flags_aux = scan_flags_aux;
     if constexpr (sizeof(R) == 8) c->d64 = d; else c->d32 = d;
   }
   return b.off + 256;
@@ -257,24 +272,46 @@ void check_params(const mpm_params* p) {
   if (p->slab_axis < 0 || p->slab_axis >= p->dim) throw ApiError{MPM_EINVAL, "bad slab_axis"};
 }
 
+// Scratch of one cell sort: cell counters (zero between sorts), the scan's status words
+// with their epoch, segment-order scratch.  The surface-sample sort runs on the second
+// stream beside the particle sort with a set of its own.
+struct SortRes {
+  int* ccount;
+  uint64_t* flags;
+  unsigned* epoch;
+  int* tmp;
+};
+template <typename R>
+SortRes sort_res(mpm_ctx* c, Dev<R>& d, bool aux) {
+  return aux ? SortRes{c->ccount_aux, c->scan_flags_aux, &c->scan_epoch_aux, c->sort_tmp_aux}
+             : SortRes{d.ccount, c->scan_flags, &c->scan_epoch, c->sort_tmp};
+}
+
 // ---- exclusive scan of len ints: out[0..len) and out[len] = total ----------------------
-void scan(mpm_ctx* c, const int* in, int* out, int len, hipStream_t s) {
+void scan(mpm_ctx* c, const int* in, int* out, int len, hipStream_t s, uint64_t* flags, unsigned* epoch) {
   int nb = cdiv(len, kScanBlock);
   if (nb > kScanBlock) throw ApiError{MPM_EINVAL, "scan length above 2^24"};
-  if (len > 0)
-    LAUNCH(c, MPM_K_SORT, k_scan_local, dim3(nb), dim3(kScanT), 0, s, in, out, len, c->scan_bsum);
-  else LAUNCH(c, MPM_K_SORT, k_fill_i32, dim3(1), dim3(1), 0, s, c->scan_bsum, 0, (int64_t)1);
-  LAUNCH(c, MPM_K_SORT, k_scan_sums, dim3(1), dim3(kScanT), 0, s, c->scan_bsum, std::max(nb, 1), out + len);
-  if (len > 0) LAUNCH(c, MPM_K_SORT, k_scan_add, dim3(cdiv(len, 256)), dim3(256), 0, s, out, len, (const int*)c->scan_bsum);
+  if (((uintptr_t)in | (uintptr_t)out) % 16) throw ApiError{MPM_EINVAL, "scan buffers not 16-byte aligned"};
+  if (len == 0) {
+    LAUNCH(c, MPM_K_SORT, k_fill_i32, dim3(1), dim3(1), 0, s, out, 0, (int64_t)1);
+    return;
+  }
+  // the status words of one scan are told from older ones by the epoch (never 0, the
+  // value of the zeroed workspace)
+  *epoch = *epoch % ((1u << 30) - 1) + 1;
+  LAUNCH(c, MPM_K_SORT, k_scan, dim3(nb), dim3(kScanT), 0, s, in, out, len, flags, *epoch, c->misc);
+}
+void scan(mpm_ctx* c, const int* in, int* out, int len, hipStream_t s) {
+  scan(c, in, out, len, s, c->scan_flags, &c->scan_epoch);
 }
 
 // Puts every segment of vals[0, cnt) (runs of equal key[value], starting at start[key])
 // in ascending value order.
-void segment_order(mpm_ctx* c, const int* key, const int* start, int cnt, int* vals, hipStream_t s) {
+void segment_order(mpm_ctx* c, const int* key, const int* start, int cnt, int* vals, hipStream_t s, int* tmp) {
   if (cnt <= 0) return;
-  LAUNCH(c, MPM_K_SORT, k_segment_rank, dim3(cdiv(cnt, 256)), dim3(256), 0, s, key, start, cnt, vals, c->sort_tmp);
+  LAUNCH(c, MPM_K_SORT, k_segment_rank, dim3(cdiv(cnt, 256)), dim3(256), 0, s, key, start, cnt, vals, tmp);
   LAUNCH(c, MPM_K_SORT, k_segment_copy_long, dim3(cdiv(cnt, 256)), dim3(256), 0, s, key, start, cnt, vals,
-         (const int*)c->sort_tmp);
+         (const int*)tmp);
 }
 
 // Stable cell sort of cnt points: perm (sorted slot -> input index) and start[nn+1].
@@ -282,15 +319,16 @@ void segment_order(mpm_ctx* c, const int* key, const int* start, int cnt, int* v
 // cell's segment is then put in input order, so the result does not depend on the order
 // in which the atomics were served.
 template <int D, typename R>
-void cell_sort(mpm_ctx* c, Dev<R>& d, const R* pos, int cnt, int* key, int* perm, int* start, hipStream_t s) {
+void cell_sort(mpm_ctx* c, Dev<R>& d, const R* pos, int cnt, int* key, int* perm, int* start, hipStream_t s,
+               const SortRes& r) {
   if (cnt > 0)
     LAUNCH(c, MPM_K_SORT, (k_cell_keys<D, R>), dim3(cdiv(cnt, 256)), dim3(256), 0, s, pos, cnt, d.n, d.nt, d.fn, key,
-           d.ccount, d.status);
-  scan(c, d.ccount, start, d.nn, s);
+           r.ccount, d.status);
+  scan(c, r.ccount, start, d.nn, s, r.flags, r.epoch);
   if (cnt > 0) {
     LAUNCH(c, MPM_K_SORT, k_cell_scatter, dim3(cdiv(cnt, 256)), dim3(256), 0, s, (const int*)key, cnt,
-           (const int*)start, d.ccount, perm);
-    segment_order(c, key, start, cnt, perm, s);
+           (const int*)start, r.ccount, perm, d.status);
+    segment_order(c, key, start, cnt, perm, s, r.tmp);
   }
 }
 
@@ -315,6 +353,31 @@ void sync_read(mpm_ctx* c, hipStream_t s, const void* src, void* dst, size_t byt
   HIPCHK(hipStreamSynchronize(s));
 }
 
+// The second stream's share of the binning (on stream s): clears the previous step's
+// tiles, then bins the surface samples by cell and stages them in cell order.
+template <int D, typename R>
+void front_aux(mpm_ctx* c, Dev<R>& d, const mpm_surface* S, hipStream_t s) {
+  if (c->prev_ntiles > 0)
+    LAUNCH(c, MPM_K_SETUP, (k_clear_tiles<D, R>), dim3(c->prev_ntiles), dim3(64), 0, s, d, (const int*)d.tile_list,
+           (R* const*)nullptr, 0, 0);
+  if (c->ns > 0) {
+    cell_sort<D, R>(c, d, (const R*)S->s, c->ns, d.s_key, d.s_perm, d.s_start, s, sort_res(c, d, true));
+    LAUNCH(c, MPM_K_SETUP, (k_gather_surface<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d, (const R*)S->s,
+           (const R*)S->dA, S->label);
+  }
+}
+
+// Active node tiles (hold a stencil node of a point), compacted into the tile list, and
+// the count copied to the host (on stream s).
+template <int D, typename R>
+void node_tiles(mpm_ctx* c, Dev<R>& d, hipStream_t s) {
+  LAUNCH(c, MPM_K_SETUP, (k_mark_tiles<D, R>), dim3(cdiv(d.nn, 256)), dim3(256), 0, s, d);
+  scan(c, d.tile_flag, c->tile_pos, c->ntile_total, s, c->scan_flags_aux, &c->scan_epoch_aux);
+  LAUNCH(c, MPM_K_SETUP, k_compact_tiles, dim3(cdiv(c->ntile_total, 256)), dim3(256), 0, s, (const int*)d.tile_flag,
+         (const int*)c->tile_pos, c->ntile_total, d.tile_list);
+  HIPCHK(hipMemcpyAsync(c->hint, c->tile_pos + c->ntile_total, sizeof(int), hipMemcpyDeviceToHost, s));
+}
+
 // ---------------------------------------------------------------------------------------
 template <int D, typename R>
 void do_p2g(mpm_ctx* c, const mpm_particles* P, const mpm_surface* S, hipStream_t s) {
@@ -330,54 +393,65 @@ void do_p2g(mpm_ctx* c, const mpm_particles* P, const mpm_surface* S, hipStream_
   c->ns = (int)ns;
   d.np = c->np;
   d.ns = c->ns;
-  // clear the previous step's tiles so that views read zero outside the new active set
-  if (c->prev_ntiles > 0) {
-    LAUNCH(c, MPM_K_SETUP, (k_clear_tiles<D, R>), dim3(c->prev_ntiles), dim3(64), 0, s, d, (const int*)d.tile_list,
-                       (R* const*)nullptr, 0, 0);
-  }
   LAUNCH(c, MPM_K_SORT, k_fill_i32, dim3(1), dim3(64), 0, s, c->misc, 0, (int64_t)8);
-  // A0: bin interior particles by cell and stage them in cell order
-  cell_sort<D, R>(c, d, (const R*)P->x, c->np, d.p_key, d.p_perm, d.p_start, s);
+  // Independent chains go to the second stream: the clearing of the previous step's
+  // tiles (views read zero outside the new active set) and the binning of the surface
+  // samples, beside the binning of the interior particles on this stream.
+  if (!c->aux) HIPCHK(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+  if (!c->ev_sfork) HIPCHK(hipEventCreateWithFlags(&c->ev_sfork, hipEventDisableTiming));
+  if (!c->ev_sjoin) HIPCHK(hipEventCreateWithFlags(&c->ev_sjoin, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(c->ev_sfork, s));
+  HIPCHK(hipStreamWaitEvent(c->aux, c->ev_sfork, 0));
+  front_aux<D, R>(c, d, S, c->aux);
+  HIPCHK(hipEventRecord(c->ev_sjoin, c->aux));
+  cell_sort<D, R>(c, d, (const R*)P->x, c->np, d.p_key, d.p_perm, d.p_start, s, sort_res(c, d, false));
   if (c->np > 0)
     LAUNCH(c, MPM_K_SETUP, (k_gather_particles<D, R>), dim3(cdiv(c->np, 256)), dim3(256), 0, s, d, (const R*)P->x,
                        (const R*)P->v, (const R*)P->A, (const R*)P->J, (const R*)P->V0, (const R*)P->m,
                        (const R*)P->T, (const R*)P->gradT);
-  // A1: surface samples, parents, split masses, balance points, groups
-  if (c->ns > 0) {
-    cell_sort<D, R>(c, d, (const R*)S->s, c->ns, d.s_key, d.s_perm, d.s_start, s);
-    LAUNCH(c, MPM_K_SETUP, (k_gather_surface<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d, (const R*)S->s,
-                       (const R*)S->dA, S->label);
-    LAUNCH(c, MPM_K_SETUP, (k_parents<D, R>), dim3(cdiv(c->ns, 64)), dim3(64), 0, s, d);
-  }
+  HIPCHK(hipStreamWaitEvent(s, c->ev_sjoin, 0));
+  // A1: parents, split masses, balance points, groups
+  if (c->ns > 0) LAUNCH(c, MPM_K_SETUP, (k_parents<D, R>), dim3(cdiv(c->ns, 64)), dim3(64), 0, s, d);
   if (c->np > 0) LAUNCH(c, MPM_K_SETUP, (k_split_mass<R>), dim3(cdiv(c->np, 256)), dim3(256), 0, s, d);
   scan(c, d.pcnt, d.grp_start, c->np, s);
   if (c->ns > 0) {
     LAUNCH(c, MPM_K_SETUP, (k_balance<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d);
-    segment_order(c, (const int*)d.spar, (const int*)d.grp_start, c->ns, d.grp, s);
-    cell_sort<D, R>(c, d, (const R*)d.bx_unsorted, c->ns, d.b_key, d.b_src, d.b_start, s);
+    segment_order(c, (const int*)d.spar, (const int*)d.grp_start, c->ns, d.grp, s, c->sort_tmp);
+    cell_sort<D, R>(c, d, (const R*)d.bx_unsorted, c->ns, d.b_key, d.b_src, d.b_start, s, sort_res(c, d, false));
     LAUNCH(c, MPM_K_SETUP, (k_gather_balance<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d);
   }
-  // active cell tiles (hold points) and node tiles (hold a stencil node of a point)
+  // active cell tiles (hold points) on this stream, node tiles on the second
+  HIPCHK(hipEventRecord(c->ev_sfork, s));
+  HIPCHK(hipStreamWaitEvent(c->aux, c->ev_sfork, 0));
+  node_tiles<D, R>(c, d, c->aux);
+  HIPCHK(hipEventRecord(c->ev_sjoin, c->aux));
   LAUNCH(c, MPM_K_SETUP, (k_flag_ctiles<D, R>), dim3(cdiv(c->ntile_total, 256)), dim3(256), 0, s, d, c->ctile_flag,
          c->ntile_total);
   scan(c, c->ctile_flag, c->ctile_pos, c->ntile_total, s);
   LAUNCH(c, MPM_K_SETUP, (k_ctile_slots<R>), dim3(cdiv(c->ntile_total, 256)), dim3(256), 0, s, d,
          (const int*)c->ctile_flag, (const int*)c->ctile_pos, c->ntile_total, c->ctile_list, c->ctile_slot,
          c->ctile_rng);
-  LAUNCH(c, MPM_K_SETUP, (k_mark_tiles<D, R>), dim3(cdiv(d.nn, 256)), dim3(256), 0, s, d);
-  scan(c, d.tile_flag, c->tile_pos, c->ntile_total, s);
-  LAUNCH(c, MPM_K_SETUP, k_compact_tiles, dim3(cdiv(c->ntile_total, 256)), dim3(256), 0, s, (const int*)d.tile_flag,
-         (const int*)c->tile_pos, c->ntile_total, d.tile_list);
-  HIPCHK(hipMemcpyAsync(c->hint, c->tile_pos + c->ntile_total, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(c->hint + 1, c->ctile_pos + c->ntile_total, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipStreamWaitEvent(s, c->ev_sjoin, 0));
+  if (!c->ev_counts) HIPCHK(hipEventCreateWithFlags(&c->ev_counts, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(c->ev_counts, s));
+  // A2: the cell-tile scatter goes out before the host has the tile counts, sized by the
+  // previous step's count (the kernel reads the true count); the host waits for the
+  // counts while it runs and covers any further tiles with a second launch
+  const int* nct_dev = c->ctile_pos + c->ntile_total;
+  const int est = (int)std::min<int64_t>(c->ntile_total, c->prev_nctile + c->prev_nctile / 8 + 64);
+  LAUNCH(c, MPM_K_P2G, (k_tile_p2g<D, R>), dim3(cdiv(est, 8) * 16), dim3(TileGeo<D>::NT), 0, s, d, tiles(c),
+         (R*)c->tpart, nct_dev, 0);
+  HIPCHK(hipEventSynchronize(c->ev_counts));
   c->ntiles = c->hint[0];
   c->nctile = c->hint[1];
   c->prev_ntiles = c->ntiles;
-  // A2/A3: P2G (cell-tile scatter, merge) and grid set-up
+  c->prev_nctile = c->nctile;
+  if (c->nctile > est)
+    LAUNCH(c, MPM_K_P2G, (k_tile_p2g<D, R>), dim3(cdiv(c->nctile - est, 8) * 16), dim3(TileGeo<D>::NT), 0, s, d,
+           tiles(c), (R*)c->tpart, nct_dev, est);
+  // A2/A3: node merge of the scatter and grid set-up
   TileLists tl = tiles(c);
-  if (c->nctile > 0)
-    LAUNCH(c, MPM_K_P2G, (k_tile_p2g<D, R>), dim3(c->nctile), dim3(TileGeo<D>::NT), 0, s, d, tl, (R*)c->tpart);
   if (c->ntiles > 0)
     LAUNCH(c, MPM_K_P2G_NODE, (k_merge_p2g<D, R>), dim3(c->ntiles), dim3(64), 0, s, d, tl, (const R*)c->tpart);
   if (c->ns > 0) LAUNCH(c, MPM_K_SETUP, (k_surface_k<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d);
@@ -529,20 +603,38 @@ struct CgRun {
 
 // Device scratch of one CG solve: its scalars (and their host mirror), partial slots and
 // reduction counters.  Momentum and heat have separate sets.
+// own_read: its host copy is a slot of its own, filled by kry_read (not by read_mirror).
 struct KrySet {
   CgScal* cg;
   CgScal* hcg;
   double* part;
   unsigned* ctr_start;
   unsigned* ctr_upd;
+  bool own_read;
 };
 
 inline KrySet kry_momentum(mpm_ctx* c) {
-  return KrySet{c->cg, c->hcg, c->part, c->ctr + (size_t)CTR_CGSTART * kCtrSite, c->ctr + (size_t)CTR_CGUPD * kCtrSite};
+  return KrySet{c->cg, c->hcg, c->part, c->ctr + (size_t)CTR_CGSTART * kCtrSite, c->ctr + (size_t)CTR_CGUPD * kCtrSite,
+                false};
 }
 inline KrySet kry_heat(mpm_ctx* c) {
-  return KrySet{c->cg + 1, c->hcg + 1, c->part + 16 * kPartSlot, c->ctr + (size_t)CTR_HSTART * kCtrSite,
-                c->ctr + (size_t)CTR_HUPD * kCtrSite};
+  return KrySet{c->cg + 1, (CgScal*)(c->hmirror + kMirrorHeatHost), c->part + 16 * kPartSlot,
+                c->ctr + (size_t)CTR_HSTART * kCtrSite, c->ctr + (size_t)CTR_HUPD * kCtrSite, true};
+}
+
+// Queues the copy of the solve's scalars to the host (with the whole mirror for the
+// momentum solve); kry_read also waits for it.
+void kry_copy(mpm_ctx* c, const KrySet& k, hipStream_t s) {
+  if (k.own_read) HIPCHK(hipMemcpyAsync(k.hcg, k.cg, sizeof(CgScal), hipMemcpyDeviceToHost, s));
+  else HIPCHK(hipMemcpyAsync(c->hmirror, (const char*)c->scal, kMirrorRead, hipMemcpyDeviceToHost, s));
+}
+void kry_read(mpm_ctx* c, const KrySet& k, hipStream_t s) {
+  if (!k.own_read) {
+    read_mirror(c, s);
+    return;
+  }
+  kry_copy(c, k, s);
+  HIPCHK(hipStreamSynchronize(s));
 }
 
 // First chunk of a solve: the iteration count of the previous solve of the same kind
@@ -595,7 +687,7 @@ bool cg_finish(mpm_ctx* c, const KrySet& k, Apply&& apply, R* x, const R* diag, 
   while (!k.hcg->done && run.launched < maxit + 32) {
     run.chunk = std::min(run.chunk * 2, 16);
     cg_iterate<R>(c, k, apply, x, diag, r, z, p, Ap, ncomp, run.chunk, s, run);
-    read_mirror(c, s);
+    kry_read(c, k, s);
     changed = true;
   }
   if (k.hcg->breakdown && k.hcg->iters == 0) {
@@ -608,6 +700,7 @@ bool cg_finish(mpm_ctx* c, const KrySet& k, Apply&& apply, R* x, const R* diag, 
 }
 
 int status_code(int bits) {
+  if (bits & (ST_STALL | ST_INTERNAL)) return MPM_EHIP;
   if (bits & ST_DOMAIN) return MPM_EDOMAIN;
   if (bits & ST_NONFINITE) return MPM_ENONFINITE;
   if (bits & ST_NOCONV) return MPM_ENOCONV;
@@ -620,6 +713,7 @@ int status_code_of(mpm_ctx* c) {
   if (code == MPM_EDOMAIN) c->err = "point outside [dx, 1-dx)^dim";
   else if (code == MPM_ENONFINITE) c->err = "non-finite residual or energy";
   else if (code == MPM_ENOCONV) c->err = "iteration cap reached";
+  else if (code == MPM_EHIP) c->err = "a bounded device-side wait gave up or a device consistency check failed";
   return code;
 }
 
@@ -635,18 +729,29 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
   R* g = (R*)c->grad;
   R* delta = (R*)c->delta;
   mpm_stats& st = c->stats;
-  // start: v^ = P v^n; Phi, the mass sum and |g| come from the gradient merge
+  // start: v^ = P v^n; Phi, the mass sum and |g| come from the gradient merge.  The host
+  // reads them together with the first iteration's CG and trial scalars: the first CG
+  // chunk takes its tolerance from |g|^2 on the device, and the translation correction
+  // tests the constrained flag on the device.  When the start already satisfies the
+  // stopping test, that queued work is dropped (it writes only the CG and trial buffers).
   LAUNCH(c, MPM_K_BLAS, k_project_copy<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const uint8_t*)d.gfree,
          (const R*)d.gvn, vhat);
   do_energy_grad<D, R>(c, vhat, g, nullptr, SC_G0, s);
-  read_mirror(c, s);
-  const bool fix = p.momentum_fix && !c->constrained;
-  const double msum = c->hbuf[SC_G0 + 1 + D];
-  const double floor_abs = 1e-14 * msum * p.dx / p.dt;
-  double phi = c->hbuf[SC_G0];
-  double gn = std::sqrt(std::max(c->hbuf[SC_G0 + 2 * D + 2], 0.0));
-  const double g0 = gn;
-  st.g0 = g0;
+  bool fix = false;
+  double msum = 0, floor_abs = 0, phi = 0, gn = 0, g0 = 0;
+  auto start_values = [&] {   // from a read that covers the start's gradient merge
+    fix = p.momentum_fix && !c->constrained;
+    msum = c->hbuf[SC_G0 + 1 + D];
+    floor_abs = 1e-14 * msum * p.dx / p.dt;
+    phi = c->hbuf[SC_G0];
+    gn = std::sqrt(std::max(c->hbuf[SC_G0 + 2 * D + 2], 0.0));
+    g0 = gn;
+    st.g0 = g0;
+  };
+  if (p.newton_max <= 0) {
+    read_mirror(c, s);
+    start_values();
+  }
   st.energy_evals = 1;
   st.converged = 0;
   auto apply = [&](const R* pv, R* Apv, const int* done, CgScal* cg, PUpd<R> pu) {
@@ -656,22 +761,31 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
   int it = 0;
   double gn_prev = 1e300;
   for (; it < p.newton_max; ++it) {
-    if (!(gn == gn) || !(phi == phi)) { c->status |= ST_NONFINITE; break; }
-    if (gn <= std::max(p.newton_tol * g0, floor_abs)) { st.converged = 1; break; }
-    // MIXED: the FP32 gradient cannot fall below its own round-off; once |g| is small
-    // (1e-4 |g0|) and a Newton step no longer halves it, the solve has reached that floor.
-    if (sizeof(R) == 4 && gn <= 1e-4 * g0 && gn > 0.5 * gn_prev) { st.converged = 2; break; }
+    if (it > 0) {
+      if (!(gn == gn) || !(phi == phi)) { c->status |= ST_NONFINITE; break; }
+      if (gn <= std::max(p.newton_tol * g0, floor_abs)) { st.converged = 1; break; }
+      // MIXED: the FP32 gradient cannot fall below its own round-off; once |g| is small
+      // (1e-4 |g0|) and a Newton step no longer halves it, the solve has reached that floor.
+      if (sizeof(R) == 4 && gn <= 1e-4 * g0 && gn > 0.5 * gn_prev) { st.converged = 2; break; }
+    }
     gn_prev = gn;
     do_surface_lin<D, R>(c, vhat, s);
-    double cg_tol = std::max(p.cg_rel * gn, 0.1 * p.newton_tol * g0);
     R* cr = (R*)c->r;
     R* cz = (R*)c->z;
     R* cp = (R*)c->pp;
     R* cAp = (R*)c->Ap;
     CgRun run;
     const KrySet km = kry_momentum(c);
-    cg_begin<R>(c, km, apply, (const R*)g, -1.0, delta, false, (const R*)d.gdiag, cr, cz, cp, cAp, D, cg_tol * cg_tol,
-                nullptr, p.cg_max, s, run, first_chunk(c->cg_hint_mom));
+    if (it == 0) {
+      // tolerance max(cg_rel |g|, 0.1 newton_tol |g0|) with g0 = |g|
+      const double f = std::max(p.cg_rel, 0.1 * p.newton_tol);
+      cg_begin<R>(c, km, apply, (const R*)g, -1.0, delta, false, (const R*)d.gdiag, cr, cz, cp, cAp, D, f * f,
+                  c->scal + SC_G0 + 2 * D + 2, p.cg_max, s, run, first_chunk(c->cg_hint_mom));
+    } else {
+      const double cg_tol = std::max(p.cg_rel * gn, 0.1 * p.newton_tol * g0);
+      cg_begin<R>(c, km, apply, (const R*)g, -1.0, delta, false, (const R*)d.gdiag, cr, cz, cp, cAp, D,
+                  cg_tol * cg_tol, nullptr, p.cg_max, s, run, first_chunk(c->cg_hint_mom));
+    }
     // slope, then the full step: its energy, gradient and the translation correction with
     // |g|^2 at the corrected point.  Queued behind the first CG chunk on the guess that
     // it converges there; the CG scalars and the trial's scalars come back in one read.
@@ -682,15 +796,21 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
       LAUNCH(c, MPM_K_BLAS, k_axpy_to<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const R*)vhat,
              (const R*)delta, a, vtrial);
       do_energy_grad<D, R>(c, vtrial, (R*)c->gscratch, nullptr, SC_GT, s);
-      if (fix)
+      if (p.momentum_fix)
         LAUNCH(c, MPM_K_BLAS, (k_mom_fix<D, R>), dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, (const uint8_t*)d.gfree,
                (const R*)d.gm, (const double*)(c->scal + SC_GT + 1), p.dt, p.gravity[0], p.gravity[1], p.gravity[2],
-               vtrial, (R*)c->gscratch, c->part, c->ctr + (size_t)CTR_MOM * kCtrSite, c->scal + SC_GT + 2 * D + 2);
+               vtrial, (R*)c->gscratch, c->part, c->ctr + (size_t)CTR_MOM * kCtrSite, c->scal + SC_GT + 2 * D + 2,
+               (const int*)(c->misc + 1));
       st.energy_evals++;
     };
     dot_async<R>(c, g, delta, D, SC_SLOPE, s);
     trial_launch(alpha);
     read_mirror(c, s);
+    if (it == 0) {
+      start_values();
+      if (!(gn == gn) || !(phi == phi)) { c->status |= ST_NONFINITE; st.energy_evals--; break; }
+      if (gn <= std::max(p.newton_tol * g0, floor_abs)) { st.converged = 1; st.energy_evals--; break; }
+    }
     if (cg_finish<R>(c, km, apply, delta, (const R*)d.gdiag, cr, cz, cp, cAp, D, p.cg_max, s, run)) {
       // the guess failed: the trial used an unfinished delta
       dot_async<R>(c, g, delta, D, SC_SLOPE, s);
@@ -776,11 +896,11 @@ void do_explicit(mpm_ctx* c, hipStream_t s) {
 }
 
 // Heat solve, split so that work can be queued behind its first CG chunk: heat_begin
-// queues T = T^n, |rhs|^2 and the CG start with its first iterations; heat_end (after
-// the scalars have been read into the host mirror) finishes the CG and records the
-// statistics, returning true when it changed T^ after that read.  The heat solve uses
-// only its own scratch (kry_heat, its tile partials), so it may run on a second stream
-// beside the momentum solve.
+// queues T = T^n, |rhs|^2, the CG start with its first iterations and the copy of the CG
+// scalars to their host slot; heat_end waits for that copy, finishes the CG and records
+// the statistics, returning true when it changed T^ after the copy.  The heat solve uses
+// only its own scratch (kry_heat, its tile partials, its host slot), so it may run on a
+// second stream beside the momentum solve.
 template <int D, typename R>
 void heat_begin(mpm_ctx* c, hipStream_t s, CgRun& run) {
   if (!c->have_p2g) throw ApiError{MPM_EINVAL, "mpm_p2g must run first"};
@@ -794,15 +914,21 @@ void heat_begin(mpm_ctx* c, hipStream_t s, CgRun& run) {
   auto apply = [&](const R* pv, R* Apv, const int* done, CgScal* cg, PUpd<R> pu) {
     do_heat_apply<D, R>(c, pv, Apv, done, cg, s, pu);
   };
-  cg_begin<R>(c, kry_heat(c), apply, d.hrhs, 1.0, T, true, (const R*)d.hdiag, (R*)c->hr, (R*)c->hz, (R*)c->hp,
+  const KrySet kh = kry_heat(c);
+  cg_begin<R>(c, kh, apply, d.hrhs, 1.0, T, true, (const R*)d.hdiag, (R*)c->hr, (R*)c->hz, (R*)c->hp,
               (R*)c->hAp, 1, c->p.heat_tol * c->p.heat_tol, c->scal + SC_RHS2, c->p.heat_max, s, run,
               first_chunk(c->cg_hint_heat));
+  // the scalars after the first chunk go to the host at once; heat_end waits for them
+  if (!c->ev_hread) HIPCHK(hipEventCreateWithFlags(&c->ev_hread, hipEventDisableTiming));
+  kry_copy(c, kh, s);
+  HIPCHK(hipEventRecord(c->ev_hread, s));
 }
 
 template <int D, typename R>
 bool heat_end(mpm_ctx* c, hipStream_t s, CgRun& run) {
   Dev<R>& d = dev<R>(c);
   const KrySet kh = kry_heat(c);
+  HIPCHK(hipEventSynchronize(c->ev_hread));
   auto apply = [&](const R* pv, R* Apv, const int* done, CgScal* cg, PUpd<R> pu) {
     do_heat_apply<D, R>(c, pv, Apv, done, cg, s, pu);
   };
@@ -820,7 +946,6 @@ template <int D, typename R>
 void do_solve_heat(mpm_ctx* c, hipStream_t s) {
   CgRun run;
   heat_begin<D, R>(c, s, run);
-  read_mirror(c, s);
   heat_end<D, R>(c, s, run);
 }
 
@@ -982,6 +1107,10 @@ int mpm_ctx_destroy(mpm_ctx* ctx) {
   }
   if (ctx->ev_fork) hipEventDestroy(ctx->ev_fork);
   if (ctx->ev_join) hipEventDestroy(ctx->ev_join);
+  if (ctx->ev_hread) hipEventDestroy(ctx->ev_hread);
+  if (ctx->ev_counts) hipEventDestroy(ctx->ev_counts);
+  if (ctx->ev_sfork) hipEventDestroy(ctx->ev_sfork);
+  if (ctx->ev_sjoin) hipEventDestroy(ctx->ev_sjoin);
   if (ctx->hmirror) hipHostFree(ctx->hmirror);
   delete ctx;
   return MPM_OK;
@@ -1133,7 +1262,6 @@ int step_one(mpm_ctx* c, mpm_particles* P, const mpm_surface* S, int implicit, h
         if (implicit) do_solve_momentum<D, R>(c, s);
         else do_explicit<D, R>(c, s);
         if (heat) {
-          read_mirror(c, c->aux);
           heat_end<D, R>(c, c->aux, run);
           HIPCHK(hipEventRecord(c->ev_join, c->aux));
           HIPCHK(hipStreamWaitEvent(s, c->ev_join, 0));

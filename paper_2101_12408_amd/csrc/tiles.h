@@ -24,8 +24,8 @@ namespace mpm {
 // need about twice the registers and keep lower targets.
 #define MPM_TILE_KERNEL(NT, W) __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(W)))
 template <typename R> struct TileOcc;
-template <> struct TileOcc<float> { static constexpr int STRESS = 6, HEAT = 6, P2G = 5; };
-template <> struct TileOcc<double> { static constexpr int STRESS = 6, HEAT = 6, P2G = 3; };
+template <> struct TileOcc<float> { static constexpr int STRESS = 6, HEAT = 6, P2G = 6; };
+template <> struct TileOcc<double> { static constexpr int STRESS = 6, HEAT = 6, P2G = 4; };
 
 template <int D> struct TileGeo;
 template <> struct TileGeo<3> {
@@ -50,6 +50,50 @@ struct TileLists {
   const int* ctile_rng;    // per slot: [interior begin, end, surface begin, end, balance begin, end]
   int nctile;
 };
+
+template <int D>
+struct MergeSrc {
+  int slot[1 << D];   // partial slot of candidate j, -1 if absent
+  int rn[1 << D];     // node's index in that tile's region
+};
+
+// The cell tiles whose 6^3 (10^2) node regions contain a node: its own tile and, on a
+// tile face, the neighbour across it.  Candidate j (0 <= j < 2^D, axis a taking the
+// bit k_a of j, higher axes outer) is the tile base_a + k_a per axis; the candidates are
+// visited in increasing tile coordinates, which fixes the summation order.  Every
+// index is a compile-time constant after unrolling, so the arrays stay in registers and
+// all slot lookups and partial loads can be in flight together.
+template <int D>
+MPM_DEV void merge_sources(int node_tile, int local, int nt, const int* ctile_slot, MergeSrc<D>& ms) {
+  constexpr int E = TileGeo<D>::E, RE = TileGeo<D>::RE;
+  int i[3] = {0, 0, 0};
+  tiled_coords<D>(node_tile, local, nt, i);
+  int base[3] = {0, 0, 0}, two[3] = {0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const int T = i[a] / E, l = i[a] % E;
+    base[a] = l == 0 ? T - 1 : T;
+    two[a] = (l == 0 || l == E - 1) ? 1 : 0;
+  }
+#pragma unroll
+  for (int j = 0; j < (1 << D); ++j) {
+    int C[3] = {0, 0, 0};
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const int k = (j >> a) & 1;
+      C[a] = base[a] + k;
+      ok = ok && (k == 0 || two[a]) && C[a] >= 0 && C[a] < nt;
+    }
+    const int ct = C[0] + nt * (C[1] + (D == 3 ? nt * C[2] : 0));
+    const int s = ok ? ctile_slot[ct] : -1;
+    int r[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < D; ++a) r[a] = i[a] - (E * C[a] - 1);
+    ms.slot[j] = s;
+    ms.rn[j] = r[0] + RE * (r[1] + (D == 3 ? RE * r[2] : 0));
+  }
+}
 
 // Local coordinates of cell lc (tile-local tiled order) and of region node rn.
 template <int D>
@@ -125,52 +169,30 @@ MPM_DEV void reduce_cells_to_region(const LaneAcc<D, R, NF>& acc, int f0, R* cel
       }
   }
   __syncthreads();
-  for (int rn = threadIdx.x; rn < RN; rn += NT) {
+  // one (node, field) item per thread: the cells c = r - k in [0, E) are visited in (k2,
+  // k1, k0) order with predicated reads, all in flight together
+  for (int i = threadIdx.x; i < RN * FC; i += NT) {
+    const int rn = i / FC, f = i - rn * FC;
+    if (f0 + f >= NF) continue;
     int r[3];
     region_coords<D>(rn, r);
-    R s[FC];
+    R s = 0;
 #pragma unroll
-    for (int f = 0; f < FC; ++f) s[f] = 0;
-    // cells c = r - k in [0, E), visited in (k2, k1, k0) order.  A single field is summed
-    // fully unrolled with predicated reads (all reads in flight together); wider field
-    // chunks keep the loop, since unrolling them costs more registers than it saves.
-    if constexpr (FC == 1) {
+    for (int k2 = 0; k2 < (D == 3 ? 3 : 1); ++k2) {
 #pragma unroll
-      for (int k2 = 0; k2 < (D == 3 ? 3 : 1); ++k2) {
+      for (int k1 = 0; k1 < 3; ++k1) {
 #pragma unroll
-        for (int k1 = 0; k1 < 3; ++k1) {
-#pragma unroll
-          for (int k0 = 0; k0 < 3; ++k0) {
-            const int c0 = r[0] - k0, c1 = r[1] - k1, c2 = D == 3 ? r[2] - k2 : 0;
-            const bool in = c0 >= 0 && c0 < E && c1 >= 0 && c1 < E && c2 >= 0 && c2 < (D == 3 ? E : 1);
-            int cc[3] = {in ? c0 : 0, in ? c1 : 0, in ? c2 : 0};
-            const int lc = (int)tiled_index<D>(cc, 1) & 63;
-            const int base = ((lc * 3 + (D == 3 ? k2 : 0)) * 3 + k1) * 3 + k0;
-            s[0] += in ? cellpart[base] : R(0);
-          }
-        }
-      }
-    } else {
-      for (int k2 = 0; k2 < (D == 3 ? 3 : 1); ++k2) {
-        int c2 = D == 3 ? r[2] - k2 : 0;
-        if (c2 < 0 || c2 >= (D == 3 ? E : 1)) continue;
-        for (int k1 = 0; k1 < 3; ++k1) {
-          int c1 = r[1] - k1;
-          if (c1 < 0 || c1 >= E) continue;
-          for (int k0 = 0; k0 < 3; ++k0) {
-            int c0 = r[0] - k0;
-            if (c0 < 0 || c0 >= E) continue;
-            int cc[3] = {c0, c1, c2};
-            int lc = (int)tiled_index<D>(cc, 1) & 63;
-            int base = (((lc * 3 + (D == 3 ? k2 : 0)) * 3 + k1) * 3 + k0) * FC;
-#pragma unroll
-            for (int f = 0; f < FC; ++f) s[f] += cellpart[base + f];
-          }
+        for (int k0 = 0; k0 < 3; ++k0) {
+          const int c0 = r[0] - k0, c1 = r[1] - k1, c2 = D == 3 ? r[2] - k2 : 0;
+          const bool in = c0 >= 0 && c0 < E && c1 >= 0 && c1 < E && c2 >= 0 && c2 < (D == 3 ? E : 1);
+          int cc[3] = {in ? c0 : 0, in ? c1 : 0, in ? c2 : 0};
+          const int lc = (int)tiled_index<D>(cc, 1) & 63;
+          const int base = ((lc * 3 + (D == 3 ? k2 : 0)) * 3 + k1) * 3 + k0;
+          s += in ? cellpart[base * FC + f] : R(0);
         }
       }
     }
-#pragma unroll
-    for (int f = 0; f < FC; ++f) reg[rn * FC + f] = s[f];
+    reg[rn * FC + f] = s;
   }
   __syncthreads();
 }
@@ -389,9 +411,10 @@ struct StressLds {
   static constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
   static constexpr int CH = sizeof(R) == 8 ? NT / 4 : NT / 2; // points per chunk
   static constexpr int PW = 6 * D + D * D;                  // w, dw tables + stress
+  static constexpr int PS = PW | 1;                         // odd payload stride
   R u[RN * D];
   union {
-    R pt[CH * PW];
+    R pt[CH * PS];
     struct {
       R cellpart[64 * 27 * D];
       R reg[RN * D];
@@ -440,7 +463,7 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
                                                                 int mask_in, const int* done, int energy_slot,
                                                                 PUpd<R> pu) {
   constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
-  constexpr int CH = StressLds<D, R>::CH, PW = StressLds<D, R>::PW;
+  constexpr int CH = StressLds<D, R>::CH, PS = StressLds<D, R>::PS;
   __shared__ StressLds<D, R> sm;
   if (done && *done) return;
   const int ct = tl.ctile_list[blockIdx.x];
@@ -569,7 +592,7 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
 #pragma unroll
           for (int b = 0; b < D; ++b) Sq[a][b] = sc * Q[a][b];
       }
-      R* P = &sm.x.pt[t * PW];
+      R* P = &sm.x.pt[t * PS];
 #pragma unroll
       for (int a = 0; a < D; ++a)
 #pragma unroll
@@ -588,7 +611,7 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
       for (int pass = 0; pass < 2; ++pass) {
         int b0 = max(pass == 0 ? cpb : csb, lo), b1 = min(pass == 0 ? cpe : cse, hi);
         for (int qq = b0; qq < b1; ++qq) {
-          const R* P = &sm.x.pt[(qq - q0) * PW];
+          const R* P = &sm.x.pt[(qq - q0) * PS];
           R wn[3], gn[3][D];
           lane_nodes<D, R>(P, P + 3 * D, lk0, lk1, wn, gn);
           R Sq[D][D];
@@ -649,9 +672,10 @@ struct HeatLds {
   static constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
   static constexpr int CH = sizeof(R) == 8 ? NT / 4 : NT / 2; // points per chunk
   static constexpr int PW = 6 * D + 1 + D;    // w, dw tables + c + q
+  static constexpr int PS = PW | 1;           // odd payload stride (distinct banks per cell)
   R u[RN];
   union {
-    R pt[CH * PW];
+    R pt[CH * PS];
     struct {
       R cellpart[64 * 27];
       R reg[RN];
@@ -662,7 +686,7 @@ struct HeatLds {
 template <int D, typename R>
 __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::HEAT) k_tile_heat(Dev<R> d, TileLists tl, const R* T, R* tpart,
                                                               const int* done, PUpd<R> pu) {
-  constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN, PW = HeatLds<D, R>::PW, CH = HeatLds<D, R>::CH;
+  constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN, PS = HeatLds<D, R>::PS, CH = HeatLds<D, R>::CH;
   __shared__ HeatLds<D, R> sm;
   if (done && *done) return;
   const int ct = tl.ctile_list[blockIdx.x];
@@ -717,7 +741,7 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::HEAT) k_tile_heat(De
       weight_table<D, R>(f, d.fn, w, dw);
       R G[1][D], val[1];
       region_grad<D, R, 1>(sm.u, lc, w, dw, G, val);
-      R* P = &sm.x.pt[t * PW];
+      R* P = &sm.x.pt[t * PS];
 #pragma unroll
       for (int a = 0; a < D; ++a)
 #pragma unroll
@@ -742,7 +766,7 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::HEAT) k_tile_heat(De
       for (int pass = 0; pass < 2; ++pass) {
         int b0 = max(pass == 0 ? cpb : csb, lo), b1 = min(pass == 0 ? cpe : cse, hi);
         for (int qq = b0; qq < b1; ++qq) {
-          const R* P = &sm.x.pt[(qq - q0) * PW];
+          const R* P = &sm.x.pt[(qq - q0) * PS];
           R wn[3], gn[3][D];
           lane_nodes<D, R>(P, P + 3 * D, lk0, lk1, wn, gn);
           R c = P[6 * D];
@@ -776,17 +800,28 @@ template <int D> struct P2GF {
   static constexpr int NF = 2 * D + 7;
   static constexpr int M = 0, MV = 1, W = D + 1, WT = D + 2, E = D + 3, ET = D + 4, DG = D + 5, HD = 2 * D + 5,
                        HR = 2 * D + 6;
-  static constexpr int PL = 1 + D + D * D + 4 + D + 5;   // payload per point (see k_tile_p2g)
+  // The fields go in two groups, each transferred by its own workgroup of one launch:
+  // group 0 (fields [0, G1)) needs the weights only, group 1 (fields [G1, NF)) the weight
+  // gradients too.  Payload per point of group 0: m~, m~ v, m~ A, c_W, c_WT, c_E, c_ET,
+  // m grad T; of group 1: cJ, cV, cK (|grad N|^2 heat term), cR (N^2 Robin term), cS (N
+  // heat right side).
+  static constexpr int G1 = D + 5;
+  static constexpr int PL0 = 1 + D + D * D + 4 + D, PL1 = 5;
+  static constexpr int PW0 = D + 3 * D + PL0;        // f, w table, payload
+  static constexpr int PW1 = D + 6 * D + PL1;        // f, w and dw tables, payload
+  static constexpr int PW = PW0 > PW1 ? PW0 : PW1;
 };
 
+// LDS of the P2G tile kernel.  The payload stride is odd, so that the points that the
+// cells of a wave read at one time fall in distinct banks.
 template <int D, typename R>
 struct P2GLds {
   static constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
   static constexpr int CH = sizeof(R) == 8 ? NT / 4 : NT / 2;   // points per chunk
-  static constexpr int FC = sizeof(R) == 8 ? 3 : 7;             // fields per reduction round
-  static constexpr int PW = D + 6 * D + P2GF<D>::PL;            // f, w/dw tables, payload
+  static constexpr int FC = sizeof(R) == 8 ? 3 : 5;             // fields per reduction round
+  static constexpr int PS = P2GF<D>::PW | 1;                     // payload stride
   union {
-    R pay[CH * PW];
+    R pay[CH * PS];
     struct {
       R cellpart[64 * 27 * FC];
       R reg[RN * FC];
@@ -794,25 +829,39 @@ struct P2GLds {
   } x;
 };
 
+// Weights of the lane's three nodes (the weight factor of lane_nodes alone).
 template <int D, typename R>
-__global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::P2G) k_tile_p2g(Dev<R> d, TileLists tl, R* tpart) {
+MPM_DEV void lane_weights(const R* W, int k0, int k1, R (&wn)[3]) {
+  if constexpr (D == 3) {
+    R ga = W[0 * 3 + k0] * W[1 * 3 + k1];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) wn[k] = ga * W[2 * 3 + k];
+  } else {
+    R wx = W[k0];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) wn[k] = wx * W[3 + k];
+  }
+}
+
+// One field group G of the P2G transfer for cell tile ti (position in the cell-tile list).
+template <int D, typename R, int G>
+MPM_DEV void p2g_group(const Dev<R>& d, const TileLists& tl, int ti, R* tpart, P2GLds<D, R>& sm) {
   constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
   using FI = P2GF<D>;
-  constexpr int NF = FI::NF, PW = P2GLds<D, R>::PW, CH = P2GLds<D, R>::CH, FC = P2GLds<D, R>::FC;
-  __shared__ P2GLds<D, R> sm;
-  const int ct = tl.ctile_list[blockIdx.x];
+  constexpr int F0 = G == 0 ? 0 : FI::G1, NFG = G == 0 ? FI::G1 : FI::NF - FI::G1;
+  constexpr int PS = P2GLds<D, R>::PS, CH = P2GLds<D, R>::CH, FC = P2GLds<D, R>::FC;
+  const int ct = tl.ctile_list[ti];
   const int N = d.np, S = d.ns;
   const int t = threadIdx.x;
   const R dt = d.dt;
-  int org[3] = {0, 0, 0};
-  tiled_coords<D>(ct, 0, d.nt, org);
-#pragma unroll
-  for (int a = 0; a < D; ++a) org[a] -= 1;
   const int cb = ct * 64;
   const int pb = d.p_start[cb], pe = d.p_start[cb + 64];
   const int sb = S ? d.s_start[cb] : 0, se = S ? d.s_start[cb + 64] : 0;
   const int bb = S ? d.b_start[cb] : 0, be = S ? d.b_start[cb + 64] : 0;
-  const int n1 = pe - pb, n2 = n1 + (se - sb), ntot = n2 + (be - bb);
+  const int n1 = pe - pb, n2 = n1 + (se - sb);
+  // group 1 has nothing from balance particles (all of its payload terms vanish for them)
+  const int ntot = G == 0 ? n2 + (be - bb) : n2;
+  constexpr int NPASS = G == 0 ? 3 : 2;
   int lcell, lk0, lk1;
   lane_map<D>(t, lcell, lk0, lk1);
   const bool lane_on = t < 64 * TileGeo<D>::LPC;
@@ -825,15 +874,12 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::P2G) k_tile_p2g(Dev<
     }
   }
   const bool useJ = d.term_mask & 1, useV = d.term_mask & 4;
-  LaneAcc<D, R, NF> acc;
+  LaneAcc<D, R, NFG> acc;
   acc.zero();
   for (int q0 = 0; q0 < ntot; q0 += CH) {
     int q = q0 + t;
     if (t < CH && q < ntot) {
-      // payload: f[D] | w[D][3] | dw[D][3] | m~ | m~ v[D] | m~ A[D*D] | c_W | c_WT | c_E | c_ET |
-      //          m grad T[D] | cJ | cV | cK (|grad N|^2 heat term) | cR (N^2 Robin term) |
-      //          cS (N heat right side)
-      R* P = &sm.x.pay[t * PW];
+      R* P = &sm.x.pay[t * PS];
       int type = q < n1 ? 0 : (q < n2 ? 1 : 2);
       int k, p;
       R x[D];
@@ -853,39 +899,46 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::P2G) k_tile_p2g(Dev<
 #pragma unroll
         for (int a = 0; a < D; ++a)
 #pragma unroll
-          for (int kk = 0; kk < 3; ++kk) { P[D + a * 3 + kk] = w[a][kk]; P[4 * D + a * 3 + kk] = dw[a][kk]; }
+          for (int kk = 0; kk < 3; ++kk) {
+            P[D + a * 3 + kk] = w[a][kk];
+            if (G == 1) P[4 * D + a * 3 + kk] = dw[a][kk];
+          }
       }
-      R* Q = P + 7 * D;
-      R mt = d.pmt[p];
-      Q[0] = mt;
+      if constexpr (G == 0) {
+        R* Q = P + 4 * D;                   // m~, m~ v, m~ A
+        R mt = d.pmt[p];
+        Q[0] = mt;
 #pragma unroll
-      for (int a = 0; a < D; ++a) Q[1 + a] = mt * d.pv[a * N + p];
+        for (int a = 0; a < D; ++a) Q[1 + a] = mt * d.pv[a * N + p];
 #pragma unroll
-      for (int a = 0; a < D * D; ++a) Q[1 + D + a] = mt * d.pA[a * N + p];
-      R* Z = Q + 1 + D + D * D;          // c_W, c_WT, c_E, c_ET
-      R* bW = Z + 4;                      // bWT[D]
-      R* H = bW + D;                      // cJ, cV, cK, cR, cS
-      if (type == 0) {
-        R mp = d.pm[k];
-        Z[0] = mp; Z[1] = mp * d.pT[k]; Z[2] = 0; Z[3] = 0;
+        for (int a = 0; a < D * D; ++a) Q[1 + D + a] = mt * d.pA[a * N + p];
+        R* Z = Q + 1 + D + D * D;           // c_W, c_WT, c_E, c_ET
+        R* bW = Z + 4;                      // m grad T
+        if (type == 0) {
+          R mp = d.pm[k];
+          Z[0] = mp; Z[1] = mp * d.pT[k]; Z[2] = 0; Z[3] = 0;
 #pragma unroll
-        for (int a = 0; a < D; ++a) bW[a] = mp * d.pgT[a * N + k];
-        R Jn = d.pJ[k], Vn = d.pVn[k];
-        H[0] = useJ ? dt * dt * d.lam * d.pV0[k] * Jn * Jn : R(0);
-        H[1] = useV ? dt * d.pmu[k] * Vn : R(0);
-        H[2] = d.K * Vn;
-        H[3] = 0;
-        H[4] = d.H * Vn;
+          for (int a = 0; a < D; ++a) bW[a] = mp * d.pgT[a * N + k];
+        } else {
+          Z[0] = 0; Z[1] = 0; Z[2] = mt; Z[3] = mt * d.pT[p];
+#pragma unroll
+          for (int a = 0; a < D; ++a) bW[a] = 0;
+        }
       } else {
-        Z[0] = 0; Z[1] = 0; Z[2] = mt; Z[3] = mt * d.pT[p];
-#pragma unroll
-        for (int a = 0; a < D; ++a) bW[a] = 0;
-        H[0] = 0; H[1] = 0; H[2] = 0; H[3] = 0; H[4] = 0;
-        if (type == 1) {
+        R* H = P + 7 * D;                   // cJ, cV, cK, cR, cS
+        if (type == 0) {
+          R Jn = d.pJ[k], Vn = d.pVn[k];
+          H[0] = useJ ? dt * dt * d.lam * d.pV0[k] * Jn * Jn : R(0);
+          H[1] = useV ? dt * d.pmu[k] * Vn : R(0);
+          H[2] = d.K * Vn;
+          H[3] = 0;
+          H[4] = d.H * Vn;
+        } else {
           R area = 0;
 #pragma unroll
           for (int a = 0; a < D; ++a) area += d.sdA[a * S + k] * d.sdA[a * S + k];
           area = sqrt(area);
+          H[0] = 0; H[1] = 0; H[2] = 0;
           H[3] = d.h * area;
           H[4] = (d.h * d.T_amb + d.b) * area;
         }
@@ -894,66 +947,92 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::P2G) k_tile_p2g(Dev<
     __syncthreads();
     if (lane_on) {
       int lo = q0, hi = min(q0 + CH, ntot);
-      for (int pass = 0; pass < 3; ++pass) {
+      for (int pass = 0; pass < NPASS; ++pass) {
         int b0 = max(rb[pass], lo), b1 = min(re[pass], hi);
         for (int qq = b0; qq < b1; ++qq) {
-          const R* P = &sm.x.pay[(qq - q0) * PW];
-          R f[D];
+          const R* P = &sm.x.pay[(qq - q0) * PS];
+          if constexpr (G == 0) {
+            R f[D];
 #pragma unroll
-          for (int a = 0; a < D; ++a) f[a] = P[a];
-          R wn[3], gn[3][D];
-          lane_nodes<D, R>(P + D, P + 4 * D, lk0, lk1, wn, gn);
-          const R* Q = P + 7 * D;
-          const R* Z = Q + 1 + D + D * D;
-          const R* bW = Z + 4;
-          const R* H = bW + D;
+            for (int a = 0; a < D; ++a) f[a] = P[a];
+            R wn[3];
+            lane_weights<D, R>(P + D, lk0, lk1, wn);
+            const R* Q = P + 4 * D;
+            const R* Z = Q + 1 + D + D * D;
+            const R* bW = Z + 4;
 #pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            const R* g = gn[k];
-            const R w = wn[k];
-            int kk[3] = {lk0, D == 3 ? lk1 : k, D == 3 ? k : 0};
-            R rel[D];
+            for (int k = 0; k < 3; ++k) {
+              const R w = wn[k];
+              int kk[3] = {lk0, D == 3 ? lk1 : k, D == 3 ? k : 0};
+              R rel[D];
 #pragma unroll
-            for (int a = 0; a < D; ++a) rel[a] = (R(kk[a]) - R(0.5) - f[a]) * d.dx;
-            acc.v[k][FI::M] += w * Q[0];
+              for (int a = 0; a < D; ++a) rel[a] = (R(kk[a]) - R(0.5) - f[a]) * d.dx;
+              acc.v[k][FI::M] += w * Q[0];
 #pragma unroll
-            for (int a = 0; a < D; ++a) {
-              R s = Q[1 + a];
+              for (int a = 0; a < D; ++a) {
+                R s = Q[1 + a];
 #pragma unroll
-              for (int b = 0; b < D; ++b) s += Q[1 + D + a * D + b] * rel[b];
-              acc.v[k][FI::MV + a] += w * s;
+                for (int b = 0; b < D; ++b) s += Q[1 + D + a * D + b] * rel[b];
+                acc.v[k][FI::MV + a] += w * s;
+              }
+              R sw = Z[1];
+#pragma unroll
+              for (int a = 0; a < D; ++a) sw += bW[a] * rel[a];
+              acc.v[k][FI::W] += w * Z[0];
+              acc.v[k][FI::WT] += w * sw;
+              acc.v[k][FI::E] += w * Z[2];
+              acc.v[k][FI::ET] += w * Z[3];
             }
-            R sw = Z[1];
+          } else {
+            R wn[3], gn[3][D];
+            lane_nodes<D, R>(P + D, P + 4 * D, lk0, lk1, wn, gn);
+            const R* H = P + 7 * D;
 #pragma unroll
-            for (int a = 0; a < D; ++a) sw += bW[a] * rel[a];
-            acc.v[k][FI::W] += w * Z[0];
-            acc.v[k][FI::WT] += w * sw;
-            acc.v[k][FI::E] += w * Z[2];
-            acc.v[k][FI::ET] += w * Z[3];
-            R g2 = 0;
+            for (int k = 0; k < 3; ++k) {
+              const R* g = gn[k];
+              const R w = wn[k];
+              R g2 = 0;
 #pragma unroll
-            for (int a = 0; a < D; ++a) g2 += g[a] * g[a];
+              for (int a = 0; a < D; ++a) g2 += g[a] * g[a];
 #pragma unroll
-            for (int a = 0; a < D; ++a)
-              acc.v[k][FI::DG + a] += H[0] * g[a] * g[a] + H[1] * (R(0.5) * g2 + R(0.5) * g[a] * g[a]);
-            acc.v[k][FI::HD] += H[2] * g2 + H[3] * w * w;
-            acc.v[k][FI::HR] += H[4] * w;
+              for (int a = 0; a < D; ++a)
+                acc.v[k][FI::DG - F0 + a] += H[0] * g[a] * g[a] + H[1] * (R(0.5) * g2 + R(0.5) * g[a] * g[a]);
+              acc.v[k][FI::HD - F0] += H[2] * g2 + H[3] * w * w;
+              acc.v[k][FI::HR - F0] += H[4] * w;
+            }
           }
         }
       }
     }
     __syncthreads();
   }
-  // field chunks of FC onto the region
+  // field rounds of FC onto the region
   R* reg = sm.x.red.reg;
-  for (int f0 = 0; f0 < NF; f0 += FC) {
-    reduce_cells_to_region<D, R, NF, FC>(acc, f0, sm.x.red.cellpart, reg, lcell, lk0, lk1, lane_on);
+#pragma unroll
+  for (int f0 = 0; f0 < NFG; f0 += FC) {
+    reduce_cells_to_region<D, R, NFG, FC>(acc, f0, sm.x.red.cellpart, reg, lcell, lk0, lk1, lane_on);
     for (int i = t; i < RN * FC; i += NT) {
       int rn = i / FC, f = f0 + i % FC;
-      if (f < NF) tpart[((size_t)blockIdx.x * NF + f) * RN + rn] = reg[i];
+      if (f < NFG) tpart[((size_t)ti * FI::NF + F0 + f) * RN + rn] = reg[i];
     }
     __syncthreads();
   }
+}
+
+// P2G scatter, two workgroups per cell tile (one per field group).  Workgroups are handed
+// to the XCDs in turn, so ids 16j + i and 16j + 8 + i (i < 8), which share an XCD and its
+// L2, take the two groups of cell tile t0 + 8j + i.  The count of active cell tiles is
+// read on the device (*nct), so that the launch can be sized before the host knows it:
+// workgroups past it return at once, and a second launch with t0 > 0 covers the rest.
+template <int D, typename R>
+__global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::P2G) k_tile_p2g(Dev<R> d, TileLists tl, R* tpart,
+                                                             const int* nct, int t0) {
+  __shared__ P2GLds<D, R> sm;
+  const int b = blockIdx.x;
+  const int ti = t0 + (b >> 4) * 8 + (b & 7);
+  if (ti >= *nct) return;
+  if (b & 8) p2g_group<D, R, 1>(d, tl, ti, tpart, sm);
+  else p2g_group<D, R, 0>(d, tl, ti, tpart, sm);
 }
 
 // ======================================================================================
@@ -1112,49 +1191,6 @@ __global__ void __launch_bounds__(256) k_tile_g2p(Dev<R> d, TileLists tl, const 
 // Merge: for every node of the active node tiles, sum the region partials of the <= 2^d
 // cell tiles that cover it (fixed order: cell tiles in lexicographic order).
 // ======================================================================================
-template <int D>
-struct MergeSrc {
-  int slot[1 << D];   // partial slot of candidate j, -1 if absent
-  int rn[1 << D];     // node's index in that tile's region
-};
-
-// The cell tiles whose 6^3 (10^2) node regions contain a node: its own tile and, on a
-// tile face, the neighbour across it.  Candidate j (0 <= j < 2^D, axis a taking the
-// bit k_a of j, higher axes outer) is the tile base_a + k_a per axis; the candidates are
-// visited in increasing tile coordinates, which fixes the summation order.  Every
-// index is a compile-time constant after unrolling, so the arrays stay in registers and
-// all slot lookups and partial loads can be in flight together.
-template <int D>
-MPM_DEV void merge_sources(int node_tile, int local, int nt, const int* ctile_slot, MergeSrc<D>& ms) {
-  constexpr int E = TileGeo<D>::E, RE = TileGeo<D>::RE;
-  int i[3] = {0, 0, 0};
-  tiled_coords<D>(node_tile, local, nt, i);
-  int base[3] = {0, 0, 0}, two[3] = {0, 0, 0};
-#pragma unroll
-  for (int a = 0; a < D; ++a) {
-    const int T = i[a] / E, l = i[a] % E;
-    base[a] = l == 0 ? T - 1 : T;
-    two[a] = (l == 0 || l == E - 1) ? 1 : 0;
-  }
-#pragma unroll
-  for (int j = 0; j < (1 << D); ++j) {
-    int C[3] = {0, 0, 0};
-    bool ok = true;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      const int k = (j >> a) & 1;
-      C[a] = base[a] + k;
-      ok = ok && (k == 0 || two[a]) && C[a] >= 0 && C[a] < nt;
-    }
-    const int ct = C[0] + nt * (C[1] + (D == 3 ? nt * C[2] : 0));
-    const int s = ok ? ctile_slot[ct] : -1;
-    int r[3] = {0, 0, 0};
-#pragma unroll
-    for (int a = 0; a < D; ++a) r[a] = i[a] - (E * C[a] - 1);
-    ms.slot[j] = s;
-    ms.rn[j] = r[0] + RE * (r[1] + (D == 3 ? RE * r[2] : 0));
-  }
-}
 
 // Node kernels of the operators: one wave per node tile, kMergeTiles tiles per block.
 constexpr int kMergeTiles = 4;
