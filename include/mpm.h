@@ -120,7 +120,8 @@ typedef struct mpm_stats {
   int32_t newton_iters, cg_iters, heat_iters, line_search_halvings;
   int32_t energy_evals, hessvecs, converged, status;
   double g0, gnorm, phi, heat_res;
-  double momentum[3];     /* sum_i m_i v^_i over the grid after the solve (FP64)        */
+  double momentum[3];     /* sum_i m_i v^_i over the grid after the solve (FP64); after
+                             an implicit mpm_step, set by the next mpm_scene_status      */
   int64_t n_part, n_surf, n_dof, n_tiles;
 } mpm_stats;
 
@@ -240,7 +241,10 @@ int mpm_solve_heat(mpm_ctx* ctx, void* stream);
  * priority) that waits for the work already queued on `stream`; the call returns when
  * every scene is done and `stream` is ordered after them.  A scene's results do not
  * depend on the batch it runs in (bitwise).  The contexts must be distinct.  Returns the
- * first non-OK status in scene order; per-scene status is in mpm_stats. */
+ * first non-OK status in scene order; per-scene status is in mpm_stats.  An implicit step
+ * returns once its last host check is done, while its G2P may still run on the stream
+ * (work queued after it is ordered behind it); the status it returns covers the whole
+ * step.  Its grid momentum (mpm_stats.momentum) is read by the next mpm_scene_status. */
 int mpm_step(mpm_ctx* const* ctxs, mpm_particles* const* P, const mpm_surface* const* S,
              int32_t n_scenes, int32_t implicit, void* stream);
 /* Maximum number of scenes mpm_step advances at once (1..64, default 8; process-wide). */

@@ -1267,11 +1267,17 @@ int step_one(mpm_ctx* c, mpm_particles* P, const mpm_surface* S, int implicit, h
           HIPCHK(hipStreamWaitEvent(s, c->ev_join, 0));
         }
         do_g2p<D, R>(c, (const R*)c->vhat, heat ? (const R*)c->That : nullptr, P, s);
-        read_mirror(c, s);
-        if (c->mom_pending) {
-          for (int a = 0; a < 3; ++a) c->stats.momentum[a] = a < D ? c->hbuf[SC_MOM + D + 1 + a] : 0.0;
-          c->mom_pending = false;
+        if (!implicit) {
+          // an explicit step has read nothing since the binning flagged the status word
+          read_mirror(c, s);
+          if (c->mom_pending) {
+            for (int a = 0; a < 3; ++a) c->stats.momentum[a] = a < D ? c->hbuf[SC_MOM + D + 1 + a] : 0.0;
+            c->mom_pending = false;
+          }
         }
+        // An implicit step's Newton reads came after every kernel that flags the status
+        // word, so it returns without waiting for G2P (the next step queues behind it);
+        // its grid momentum is read by the next mpm_scene_status.
         synced = true;
       });
     });

@@ -97,6 +97,7 @@ def test_fullsize_step_properties(case, precision):
     log(f"  momentum {mv_grid} vs {mom_p}")
     assert np.all(np.abs(mv_grid - mom_p) <= tol * scale)
     rc = s.step(Pd, Sd, check=False)
+    assert s.status() == rc             # synchronizes and reads the grid momentum
     st = s.stats()
     log(f"  step rc {rc}: newton {st['newton_iters']} ({st['converged']}), cg {st['cg_iters']}, heat {st['heat_iters']}")
     assert rc == 0 and st["converged"] in (1, 2)
