@@ -660,14 +660,19 @@ __global__ void k_finalize(const double* part, int nb, int nslot, double* dst) {
   }
 }
 
-// Fused direction update of CG: an operator applied to the direction p first forms
-// p = z + beta p (beta from the CG scalars; 0 before the first update, when p = z), and
-// its node kernel stores the new p.  z == nullptr: no update.
+// Input update fused into an operator application: the operator is applied to z + beta u
+// instead of u (its tile kernel forms the values it stages, its node kernel forms its
+// nodes' values and stores them in p).  Used for the CG direction p = z + beta p (p == u,
+// beta from the CG scalars, 0 before the first update so that p = z) and for the line-
+// search trial v^ + alpha delta (u = delta, beta = alpha given by the host, p = the trial
+// point).  z == nullptr: no update.
 template <typename R>
 struct PUpd {
   R* p;
   const R* z;
-  const CgScal* cg;
+  const CgScal* cg;   // beta = cg->beta; nullptr: beta = beta_h
+  R beta_h;
+  MPM_DEV R beta() const { return z ? (cg ? (R)cg->beta : beta_h) : R(0); }
 };
 
 // The new direction z + beta p, contracted explicitly so that the operator's two kernels

@@ -470,25 +470,29 @@ void do_p2g(mpm_ctx* c, const mpm_particles* P, const mpm_surface* S, hipStream_
 // Device scalar slots (doubles at ctx->scal).
 // SC_G0 / SC_GT: the gradient merge's sums (see k_merge_stress) at the iterate and at the
 // line-search trial: [0] Phi, [1..D] sum m (v^ - v^n), [D+1] sum m, [D+2..2D+1] sum m v^,
-// [2D+2] |g|^2.
-enum : int { SC_DOT = 1, SC_SLOPE = 3, SC_RHS2 = 5, SC_MOM = 8, SC_G0 = 16, SC_GT = 32, SC_N = 48 };
+// [2D+2] |g|^2, [2D+3] the trial's slope g . delta.
+enum : int { SC_DOT = 1, SC_RHS2 = 5, SC_MOM = 8, SC_G0 = 16, SC_GT = 32, SC_N = 48 };
 
 // Phi(u), the momentum sums and |g|^2 into scal[red_slot ..] (Phi also into energy_dev if
 // given), projected gradient into g.
 template <int D, typename R>
-void do_energy_grad(mpm_ctx* c, const R* u, R* g, double* energy_dev, int red_slot, hipStream_t s) {
+//
+// With pu (z = v^, beta = alpha, p = the trial point) the point is v^ + alpha u, formed in
+// the kernels and stored in pu.p; with slope_g the sums also hold slope_g . u.
+void do_energy_grad(mpm_ctx* c, const R* u, R* g, double* energy_dev, int red_slot, hipStream_t s,
+                    PUpd<R> pu = PUpd<R>{}, const R* slope_g = nullptr) {
   Dev<R>& d = dev<R>(c);
   TileLists tl = tiles(c);
   if (c->nctile > 0)
     LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_ENERGY>), dim3(c->nctile), dim3(TileGeo<D>::NT), 0, s, d, tl,
-           u, (R*)c->tpart, 0, (const int*)nullptr, 2, PUpd<R>{});
+           u, (R*)c->tpart, 0, (const int*)nullptr, 2, pu);
   if (c->ntiles > 0) {
     LAUNCH(c, MPM_K_ENERGY_NODE, (k_merge_stress<D, R>), dim3(merge_blocks(c)), dim3(64 * kMergeTiles), 0, s, d, tl,
            c->ntiles, (const R*)c->tpart, u, g, (int)NM_GRAD, 0.0, 0, (const int*)nullptr,
            c->nctile > 0 ? (const double*)(c->part + 2 * kPartSlot) : nullptr, c->nctile, c->part + 4 * kPartSlot,
-           c->ctr + (size_t)CTR_MERGE * kCtrSite, c->scal + red_slot, energy_dev, (CgScal*)nullptr, PUpd<R>{});
+           c->ctr + (size_t)CTR_MERGE * kCtrSite, c->scal + red_slot, energy_dev, (CgScal*)nullptr, pu, slope_g);
   } else {
-    LAUNCH(c, MPM_K_BLAS, k_fill_r<double>, dim3(1), dim3(64), 0, s, c->scal + red_slot, 0.0, (int64_t)(2 * D + 3));
+    LAUNCH(c, MPM_K_BLAS, k_fill_r<double>, dim3(1), dim3(64), 0, s, c->scal + red_slot, 0.0, (int64_t)(2 * D + 4));
     if (energy_dev) LAUNCH(c, MPM_K_BLAS, k_fill_r<double>, dim3(1), dim3(1), 0, s, energy_dev, 0.0, (int64_t)1);
   }
 }
@@ -516,7 +520,7 @@ void do_hessvec(mpm_ctx* c, const R* w, double alpha, R* out, bool mask_in, cons
     LAUNCH(c, MPM_K_HESS_NODE, (k_merge_stress<D, R>), dim3(merge_blocks(c)), dim3(64 * kMergeTiles), 0, s, d, tl, c->ntiles,
            (const R*)c->tpart,
            w, out, (int)NM_HESS, alpha, (int)mask_in, done, (const double*)nullptr, 0, c->part + 4 * kPartSlot,
-           c->ctr + (size_t)CTR_MERGE * kCtrSite, (double*)nullptr, (double*)nullptr, cg, pu);
+           c->ctr + (size_t)CTR_MERGE * kCtrSite, (double*)nullptr, (double*)nullptr, cg, pu, (const R*)nullptr);
 }
 
 // Forces only (no inertia term): out = P sum_q S_q grad N_i for the stress of u.
@@ -531,7 +535,8 @@ void do_hessvec_force(mpm_ctx* c, const R* u, R* out, hipStream_t s) {
     LAUNCH(c, MPM_K_ENERGY_NODE, (k_merge_stress<D, R>), dim3(merge_blocks(c)), dim3(64 * kMergeTiles), 0, s, d, tl, c->ntiles,
            (const R*)c->tpart,
            u, out, (int)NM_HESS, 0.0, 0, (const int*)nullptr, (const double*)nullptr, 0, c->part + 4 * kPartSlot,
-           c->ctr + (size_t)CTR_MERGE * kCtrSite, (double*)nullptr, (double*)nullptr, (CgScal*)nullptr, PUpd<R>{});
+           c->ctr + (size_t)CTR_MERGE * kCtrSite, (double*)nullptr, (double*)nullptr, (CgScal*)nullptr, PUpd<R>{},
+           (const R*)nullptr);
 }
 
 // Uses only the heat solve's scratch (tile partials, partial slots 18.., counters CTR_H*),
@@ -786,16 +791,16 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
       cg_begin<R>(c, km, apply, (const R*)g, -1.0, delta, false, (const R*)d.gdiag, cr, cz, cp, cAp, D,
                   cg_tol * cg_tol, nullptr, p.cg_max, s, run, first_chunk(c->cg_hint_mom));
     }
-    // slope, then the full step: its energy, gradient and the translation correction with
+    // the full step: the trial point v^ + alpha delta (formed in the energy kernels), its
+    // energy and gradient with the slope g . delta, and the translation correction with
     // |g|^2 at the corrected point.  Queued behind the first CG chunk on the guess that
     // it converges there; the CG scalars and the trial's scalars come back in one read.
     // A trial that is rejected is overwritten by the next one, so the correction applied
     // speculatively is harmless.
     double alpha = 1.0;
     auto trial_launch = [&](double a) {
-      LAUNCH(c, MPM_K_BLAS, k_axpy_to<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const R*)vhat,
-             (const R*)delta, a, vtrial);
-      do_energy_grad<D, R>(c, vtrial, (R*)c->gscratch, nullptr, SC_GT, s);
+      do_energy_grad<D, R>(c, (const R*)delta, (R*)c->gscratch, nullptr, SC_GT, s,
+                           PUpd<R>{vtrial, (const R*)vhat, nullptr, (R)a}, (const R*)g);
       if (p.momentum_fix)
         LAUNCH(c, MPM_K_BLAS, (k_mom_fix<D, R>), dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, (const uint8_t*)d.gfree,
                (const R*)d.gm, (const double*)(c->scal + SC_GT + 1), p.dt, p.gravity[0], p.gravity[1], p.gravity[2],
@@ -803,7 +808,6 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
                (const int*)(c->misc + 1));
       st.energy_evals++;
     };
-    dot_async<R>(c, g, delta, D, SC_SLOPE, s);
     trial_launch(alpha);
     read_mirror(c, s);
     if (it == 0) {
@@ -813,7 +817,6 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
     }
     if (cg_finish<R>(c, km, apply, delta, (const R*)d.gdiag, cr, cz, cp, cAp, D, p.cg_max, s, run)) {
       // the guess failed: the trial used an unfinished delta
-      dot_async<R>(c, g, delta, D, SC_SLOPE, s);
       trial_launch(alpha);
       read_mirror(c, s);
     }
@@ -821,7 +824,7 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
     c->cg_hint_mom = cit;
     st.cg_iters += cit;
     st.hessvecs += cit;
-    const double slope = c->hbuf[SC_SLOPE];
+    const double slope = c->hbuf[SC_GT + 2 * D + 3];
     double phit = c->hbuf[SC_GT];
     // Armijo with the round-off of Phi as allowance (8 eps |Phi|, eps of the arithmetic):
     // near convergence the decrement is below it and the test would be decided by noise.

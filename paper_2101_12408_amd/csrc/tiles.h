@@ -484,7 +484,7 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
   // first chunk's point inputs, issued together with the node staging below
   StressIn<D, R, MODE> in;
   if (t < CH) stress_fetch<D, R, MODE>(d, t, ntot, npi, pb, sb, visc, in);
-  const R beta = pu.z ? (R)pu.cg->beta : R(0);
+  const R beta = pu.beta();
   for (int rn = t; rn < RN; rn += NT) {
     int r[3];
     region_coords<D>(rn, r);
@@ -694,7 +694,7 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::HEAT) k_tile_heat(De
   const int t = threadIdx.x;
   int org[3] = {0, 0, 0};
   tiled_coords<D>(ct, 0, d.nt, org);
-  const R beta = pu.z ? (R)pu.cg->beta : R(0);
+  const R beta = pu.beta();
   for (int rn = t; rn < RN; rn += NT) {
     int r[3];
     region_coords<D>(rn, r);
@@ -1199,15 +1199,16 @@ constexpr int kMergeTiles = 4;
 //  NM_GRAD: out = P[acc + m (v^ - v^n) - dt m g]; with phi the blocks also sum the tile
 //           energy partials (epart, nep entries) and the grid sums go to red: red[0] = Phi,
 //           red[1..D] = sum m (v^ - v^n), red[D+1] = sum m, red[D+2..2D+1] = sum m v^ (nodes
-//           with mass), red[2D+2] = |out|^2.
+//           with mass), red[2D+2] = |out|^2, red[2D+3] = slope_g . u (u before the input
+//           update; 0 without slope_g).
 //  NM_HESS: out = P[acc + alpha m w]; with cg the grid sum of w . out sets the CG step.
 template <int D, typename R>
 __global__ void __launch_bounds__(64 * kMergeTiles) k_merge_stress(
     Dev<R> d, TileLists tl, int ntiles, const R* tpart, const R* u, R* out, int mode, double alpha, int mask_in,
     const int* done, const double* epart, int nep, double* npart, unsigned* ctr, double* red, double* phi2,
-    CgScal* cg, PUpd<R> pu) {
+    CgScal* cg, PUpd<R> pu, const R* slope_g) {
   constexpr int RN = TileGeo<D>::RN;
-  constexpr int NV = 2 * D + 3;
+  constexpr int NV = 2 * D + 4;
   __shared__ double sh[kRedSh];
   if (done && *done) return;
   const int ti = blockIdx.x * kMergeTiles + (threadIdx.x >> 6);
@@ -1240,11 +1241,12 @@ __global__ void __launch_bounds__(64 * kMergeTiles) k_merge_stress(
     R m = d.gm[node];
     const bool dof = fr & 0x80;
     if (dof && mode == NM_GRAD) vals[D + 1] = (double)m;
-    const R beta = pu.z ? (R)pu.cg->beta : R(0);
+    const R beta = pu.beta();
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       bool fa = (fr >> a) & 1;
       R ua = u ? u[a * nn + node] : R(0);
+      if (slope_g) vals[2 * D + 3] += (double)slope_g[a * nn + node] * (double)ua;
       if (pu.z) {
         ua = cg_dir(pu.z[a * nn + node], beta, ua);
         pu.p[a * nn + node] = ua;
@@ -1315,7 +1317,7 @@ __global__ void __launch_bounds__(64 * kMergeTiles) k_merge_heat(Dev<R> d, TileL
     bool dof = d.gfree[node] & 0x80;
     R Ti = T[node];
     if (pu.z) {
-      Ti = cg_dir(pu.z[node], (R)pu.cg->beta, Ti);
+      Ti = cg_dir(pu.z[node], pu.beta(), Ti);
       pu.p[node] = Ti;
     }
     R o = dof ? d.cp / d.dt * d.gm[node] * Ti + acc : R(0);
