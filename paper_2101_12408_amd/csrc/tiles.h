@@ -19,9 +19,10 @@ namespace mpm {
 
 // Tile kernels run 9-wave (3D) workgroups.  The dispatcher places three waves of every
 // such workgroup on one SIMD, so k resident workgroups need 3k wave slots on that SIMD:
-// two per CU fit at most 85 VGPRs (80 allocated), three need at most 56.  P2G keeps 96
-// (one workgroup per CU): squeezing it to 80 spills enough to be slower.  FP64 kernels
-// need about twice the registers and keep lower targets.
+// two per CU fit at most 85 VGPRs (80 allocated), three need at most 56.  The kernels
+// ask for W waves per SIMD; the compiler honours that only while its own LDS estimate
+// allows W, so the LDS of a block stays under a third of the CU's 160 KB.  P2G fits 73
+// (MIXED) by itself; FP64 kernels need about twice the registers.
 #define MPM_TILE_KERNEL(NT, W) __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(W)))
 template <typename R> struct TileOcc;
 template <> struct TileOcc<float> { static constexpr int STRESS = 6, HEAT = 6, P2G = 6; };
@@ -402,6 +403,70 @@ MPM_DEV void lane_nodes(const R* W, const R* DW, int k0, int k1, R (&wn)[3], R (
   }
 }
 
+// Derivative (per dx) of the 1D weight of stencil node k at cell-relative x, as in
+// weight_table.
+template <typename R>
+MPM_DEV R bs_dw_fn(int k, R x, R fn) {
+  return k == 0 ? (x - R(1)) * fn : (k == 1 ? (R(1) - R(2) * x) * fn : x * fn);
+}
+
+// acc[k][a] += sum_b S[a][b] dN_k/dx_b over the lane's three nodes k (k2 = k in 3D, k1 = k
+// in 2D), from the point's cell-relative position F and weight table W.  The node
+// gradients share the lane's factors (3D: (al wz_k, be wz_k, ga dwz_k) with al = dwx wy,
+// be = wx dwy, ga = wx wy), so S g_k = wz_k (al S_.0 + be S_.1) + dwz_k (ga S_.2): 2 FMAs
+// per node and component after a per-point set-up.
+template <int D, typename R>
+MPM_DEV void lane_scatter_grad(const R* F, const R* W, R fn, int k0, int k1, const R (&S)[D][D],
+                               R (&acc)[3][D]) {
+  if constexpr (D == 3) {
+    const R wx = W[k0], dwx = bs_dw_fn<R>(k0, F[0], fn), wy = W[3 + k1], dwy = bs_dw_fn<R>(k1, F[1], fn);
+    const R al = dwx * wy, be = wx * dwy, ga = wx * wy;
+    R Pa[3], Qa[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      Pa[a] = al * S[a][0] + be * S[a][1];
+      Qa[a] = ga * S[a][2];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const R wz = W[6 + k], dwz = bs_dw_fn<R>(k, F[2], fn);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) acc[k][a] += wz * Pa[a] + dwz * Qa[a];
+    }
+  } else {
+    const R wx = W[k0], dwx = bs_dw_fn<R>(k0, F[0], fn);
+    R Pa[2], Qa[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      Pa[a] = dwx * S[a][0];
+      Qa[a] = wx * S[a][1];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const R wy = W[3 + k], dwy = bs_dw_fn<R>(k, F[1], fn);
+#pragma unroll
+      for (int a = 0; a < 2; ++a) acc[k][a] += wy * Pa[a] + dwy * Qa[a];
+    }
+  }
+}
+
+// acc[k][0] += c N_k + q . grad N_k over the lane's three nodes, factored as above.
+template <int D, typename R>
+MPM_DEV void lane_scatter_heat(const R* F, const R* W, R fn, int k0, int k1, R c, const R* q, R (&acc)[3][1]) {
+  if constexpr (D == 3) {
+    const R wx = W[k0], dwx = bs_dw_fn<R>(k0, F[0], fn), wy = W[3 + k1], dwy = bs_dw_fn<R>(k1, F[1], fn);
+    const R al = dwx * wy, be = wx * dwy, ga = wx * wy;
+    const R Pv = c * ga + al * q[0] + be * q[1], Qv = ga * q[2];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) acc[k][0] += W[6 + k] * Pv + bs_dw_fn<R>(k, F[2], fn) * Qv;
+  } else {
+    const R wx = W[k0], dwx = bs_dw_fn<R>(k0, F[0], fn);
+    const R Pv = c * wx + dwx * q[0], Qv = wx * q[1];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) acc[k][0] += W[3 + k] * Pv + bs_dw_fn<R>(k, F[1], fn) * Qv;
+  }
+}
+
 // LDS of the tile kernels: the point payloads of a chunk and the buffers of the final
 // cell-to-region reduction are never live together, so they share storage.  Keeping a
 // 9-wave block near 1/3 of the 160 KB lets three blocks (27 of the CU's 32 wave slots)
@@ -409,8 +474,8 @@ MPM_DEV void lane_nodes(const R* W, const R* DW, int k0, int k1, R (&wn)[3], R (
 template <int D, typename R>
 struct StressLds {
   static constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
-  static constexpr int CH = sizeof(R) == 8 ? NT / 4 : NT / 2; // points per chunk
-  static constexpr int PW = 6 * D + D * D;                  // w, dw tables + stress
+  static constexpr int CH = sizeof(R) == 8 ? NT / 4 : NT;     // points per chunk
+  static constexpr int PW = 4 * D + D * D;                  // f, w table, stress
   static constexpr int PS = PW | 1;                         // odd payload stride
   R u[RN * D];
   union {
@@ -594,13 +659,15 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
       }
       R* P = &sm.x.pt[t * PS];
 #pragma unroll
+      for (int a = 0; a < D; ++a) {
+        P[a] = f[a];
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) P[D + a * 3 + kk] = w[a][kk];
+      }
+#pragma unroll
       for (int a = 0; a < D; ++a)
 #pragma unroll
-        for (int kk = 0; kk < 3; ++kk) { P[a * 3 + kk] = w[a][kk]; P[3 * D + a * 3 + kk] = dw[a][kk]; }
-#pragma unroll
-      for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int b = 0; b < D; ++b) P[6 * D + a * D + b] = Sq[a][b];
+        for (int b = 0; b < D; ++b) P[4 * D + a * D + b] = Sq[a][b];
     }
     __syncthreads();
     // next chunk's inputs: in flight during this chunk's scatter
@@ -612,22 +679,12 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
         int b0 = max(pass == 0 ? cpb : csb, lo), b1 = min(pass == 0 ? cpe : cse, hi);
         for (int qq = b0; qq < b1; ++qq) {
           const R* P = &sm.x.pt[(qq - q0) * PS];
-          R wn[3], gn[3][D];
-          lane_nodes<D, R>(P, P + 3 * D, lk0, lk1, wn, gn);
           R Sq[D][D];
 #pragma unroll
           for (int a = 0; a < D; ++a)
 #pragma unroll
-            for (int b = 0; b < D; ++b) Sq[a][b] = P[6 * D + a * D + b];
-#pragma unroll
-          for (int kk = 0; kk < 3; ++kk)
-#pragma unroll
-            for (int a = 0; a < D; ++a) {
-              R s = acc.v[kk][a];
-#pragma unroll
-              for (int b = 0; b < D; ++b) s += Sq[a][b] * gn[kk][b];
-              acc.v[kk][a] = s;
-            }
+            for (int b = 0; b < D; ++b) Sq[a][b] = P[4 * D + a * D + b];
+          lane_scatter_grad<D, R>(P, P + D, d.fn, lk0, lk1, Sq, acc.v);
         }
       }
     }
@@ -670,8 +727,8 @@ __global__ void k_surface_F(Dev<R> d, const R* vlin) {
 template <int D, typename R>
 struct HeatLds {
   static constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
-  static constexpr int CH = sizeof(R) == 8 ? NT / 4 : NT / 2; // points per chunk
-  static constexpr int PW = 6 * D + 1 + D;    // w, dw tables + c + q
+  static constexpr int CH = sizeof(R) == 8 ? NT / 4 : NT;     // points per chunk
+  static constexpr int PW = 4 * D + 1 + D;    // f, w table, c, q
   static constexpr int PS = PW | 1;           // odd payload stride (distinct banks per cell)
   R u[RN];
   union {
@@ -743,21 +800,23 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::HEAT) k_tile_heat(De
       region_grad<D, R, 1>(sm.u, lc, w, dw, G, val);
       R* P = &sm.x.pt[t * PS];
 #pragma unroll
-      for (int a = 0; a < D; ++a)
+      for (int a = 0; a < D; ++a) {
+        P[a] = f[a];
 #pragma unroll
-        for (int kk = 0; kk < 3; ++kk) { P[a * 3 + kk] = w[a][kk]; P[3 * D + a * 3 + kk] = dw[a][kk]; }
+        for (int kk = 0; kk < 3; ++kk) P[D + a * 3 + kk] = w[a][kk];
+      }
       if (interior) {
         R c = d.K * d.pVn[k];
-        P[6 * D] = 0;
+        P[4 * D] = 0;
 #pragma unroll
-        for (int a = 0; a < D; ++a) P[6 * D + 1 + a] = c * G[0][a];
+        for (int a = 0; a < D; ++a) P[4 * D + 1 + a] = c * G[0][a];
       } else {
         R area = 0;
 #pragma unroll
         for (int a = 0; a < D; ++a) area += d.sdA[a * S + k] * d.sdA[a * S + k];
-        P[6 * D] = d.h * sqrt(area) * val[0];
+        P[4 * D] = d.h * sqrt(area) * val[0];
 #pragma unroll
-        for (int a = 0; a < D; ++a) P[6 * D + 1 + a] = 0;
+        for (int a = 0; a < D; ++a) P[4 * D + 1 + a] = 0;
       }
     }
     __syncthreads();
@@ -767,16 +826,7 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::HEAT) k_tile_heat(De
         int b0 = max(pass == 0 ? cpb : csb, lo), b1 = min(pass == 0 ? cpe : cse, hi);
         for (int qq = b0; qq < b1; ++qq) {
           const R* P = &sm.x.pt[(qq - q0) * PS];
-          R wn[3], gn[3][D];
-          lane_nodes<D, R>(P, P + 3 * D, lk0, lk1, wn, gn);
-          R c = P[6 * D];
-#pragma unroll
-          for (int kk = 0; kk < 3; ++kk) {
-            R s = c * wn[kk];
-#pragma unroll
-            for (int a = 0; a < D; ++a) s += P[6 * D + 1 + a] * gn[kk][a];
-            acc.v[kk][0] += s;
-          }
+          lane_scatter_heat<D, R>(P, P + D, d.fn, lk0, lk1, P[4 * D], P + 4 * D + 1, acc.v);
         }
       }
     }
