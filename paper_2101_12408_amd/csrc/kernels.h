@@ -331,21 +331,14 @@ MPM_DEV double dist2_exact(const double* a, const double* b) {
   return acc;
 }
 
-// Nearest interior particle of each sample (Section 4.1.2); ties to the lower input
-// index.  Searches the cells within 1, 2, then 3 cells of the sample; a winner closer
-// than the searched radius (rad * dx) is exact, since every particle outside the searched
-// block is at least that far.  Otherwise falls back to a scan of all particles.
+// Nearest interior particle of sample r (Section 4.1.2); ties to the lower input index.
+// Searches the cells within 1, 2, then 3 cells of the sample; a winner closer than the
+// searched radius (rad * dx) is exact, since every particle outside the searched block
+// is at least that far.  Otherwise falls back to a scan of all particles.  Returns the
+// sorted index and its input index.
 template <int D, typename R>
-__global__ void k_parents(Dev<R> d) {
-  int r = blockIdx.x * blockDim.x + threadIdx.x;
-  int S = d.ns, N = d.np;
-  if (r >= S) return;
-  double sd[D];
-  R sr[D];
-#pragma unroll
-  for (int a = 0; a < D; ++a) { sr[a] = d.ss[a * S + r]; sd[a] = (double)sr[a]; }
-  int c[D]; R f[D]; bool bad = false;
-  locate<D, R>(sr, d.n, d.fn, c, f, &bad);
+MPM_DEV int parent_search(const Dev<R>& d, const double* sd, const int* c, int& borig_out) {
+  const int N = d.np;
   double best = 1e300;
   int bk = -1, borig = -1;   // borig: input index of bk, loaded only when a tie needs it
   auto visit = [&](int k) {
@@ -398,6 +391,101 @@ __global__ void k_parents(Dev<R> d) {
       for (int k = 0; k < N; ++k) visit(k);
     }
   }
+  if (bk >= 0 && borig < 0) borig = d.p_perm[bk];
+  borig_out = borig;
+  return bk;
+}
+
+// Parents of the samples, a group of kParGroup lanes per sample, ring by ring as in
+// parent_search: the lanes share the particles of the sample's own cell, then the cells
+// of ring 1 and, if needed, ring 2 (cells at Chebyshev distance 1, 2 from the sample's
+// cell), each skipped when its box is farther than the group's best so far (the cells the
+// sequential search prunes).  The group takes the minimum of (distance, input index), a
+// total order, so the result is the sequential search's.  After ring rad a winner closer
+// than rad dx is exact; past ring 2 the group's first lane runs the sequential search.
+constexpr int kParGroup = 8;
+
+template <int D>
+MPM_DEV void par_min(double& best, int& bk, const int* perm) {
+#pragma unroll
+  for (int o = kParGroup / 2; o > 0; o >>= 1) {
+    const double ob = __shfl_xor(best, o, kParGroup);
+    const int ok = __shfl_xor(bk, o, kParGroup);
+    bool take = ob < best;
+    if (!take && ob == best && ok >= 0 && bk >= 0 && ok != bk) take = perm[ok] < perm[bk];
+    if (take) { best = ob; bk = ok; }
+  }
+}
+
+template <int D, typename R>
+__global__ void __launch_bounds__(256) k_parents(Dev<R> d) {
+  const int lane = threadIdx.x & (kParGroup - 1);
+  const int r = blockIdx.x * (256 / kParGroup) + threadIdx.x / kParGroup;
+  const int S = d.ns, N = d.np;
+  const bool live = r < S;
+  double sd[D];
+  int c[D];
+  if (live) {
+    R sr[D], f[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) { sr[a] = d.ss[a * S + r]; sd[a] = (double)sr[a]; }
+    bool bad = false;
+    locate<D, R>(sr, d.n, d.fn, c, f, &bad);
+  } else {
+#pragma unroll
+    for (int a = 0; a < D; ++a) { sd[a] = 0; c[a] = 0; }
+  }
+  double best = 1e300;
+  int bk = -1, bo = -1;
+  auto visit = [&](int k) {
+    double xp[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) xp[a] = (double)d.px[a * N + k];
+    const double d2 = dist2_exact<D>(sd, xp);
+    if (d2 < best) {
+      best = d2; bk = k; bo = -1;
+    } else if (d2 == best) {
+      if (bo < 0) bo = d.p_perm[bk];
+      const int o = d.p_perm[k];
+      if (o < bo) { bk = k; bo = o; }
+    }
+  };
+  if (live) {
+    const int ci = (int)tiled_index<D>(c, d.nt);
+    for (int k = d.p_start[ci] + lane; k < d.p_start[ci + 1]; k += kParGroup) visit(k);
+  }
+  par_min<D>(best, bk, d.p_perm);
+  const double dxd = (double)d.dx;
+  bool done = false;
+  for (int rad = 1; rad <= 2 && !done; ++rad) {
+    constexpr int W = 5;                                  // offsets -2..2 per axis
+    constexpr int NB = D == 3 ? W * W * W : W * W;
+    const double cut = best * (1.0 + 1e-9);                // ties must be visited
+    for (int j = lane; live && j < NB; j += kParGroup) {
+      const int o0 = j % W - 2, o1 = (j / W) % W - 2, o2 = D == 3 ? j / (W * W) - 2 : 0;
+      const int ring = max(abs(o0), max(abs(o1), abs(o2)));
+      if (ring != rad) continue;
+      int cc[3] = {c[0] + o0, c[1] + o1, D == 3 ? c[2] + o2 : 0};
+      bool in = true;
+      double bd2 = 0;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        in = in && cc[a] >= 0 && cc[a] < d.n;
+        const double lo_a = cc[a] * dxd, hi_a = (cc[a] + 1) * dxd;
+        const double g = sd[a] < lo_a ? lo_a - sd[a] : (sd[a] > hi_a ? sd[a] - hi_a : 0.0);
+        bd2 += g * g;
+      }
+      if (in && !(bd2 > cut)) {
+        const int ci = (int)tiled_index<D>(cc, d.nt);
+        for (int k = d.p_start[ci]; k < d.p_start[ci + 1]; ++k) visit(k);
+      }
+    }
+    par_min<D>(best, bk, d.p_perm);
+    done = bk >= 0 && best < (rad * dxd) * (rad * dxd);
+  }
+  if (!live || lane != 0) return;
+  int borig = -1;
+  if (!done) bk = parent_search<D, R>(d, sd, c, borig);
   if (bk < 0) { flag_status(d.status, ST_DOMAIN); bk = 0; }
   if (borig < 0) borig = d.p_perm[bk];
   d.spar[r] = bk;

@@ -411,7 +411,8 @@ void do_p2g(mpm_ctx* c, const mpm_particles* P, const mpm_surface* S, hipStream_
                        (const R*)P->T, (const R*)P->gradT);
   HIPCHK(hipStreamWaitEvent(s, c->ev_sjoin, 0));
   // A1: parents, split masses, balance points, groups
-  if (c->ns > 0) LAUNCH(c, MPM_K_SETUP, (k_parents<D, R>), dim3(cdiv(c->ns, 64)), dim3(64), 0, s, d);
+  if (c->ns > 0)
+    LAUNCH(c, MPM_K_SETUP, (k_parents<D, R>), dim3(cdiv(c->ns, 256 / kParGroup)), dim3(256), 0, s, d);
   if (c->np > 0) LAUNCH(c, MPM_K_SETUP, (k_split_mass<R>), dim3(cdiv(c->np, 256)), dim3(256), 0, s, d);
   scan(c, d.pcnt, d.grp_start, c->np, s);
   if (c->ns > 0) {
