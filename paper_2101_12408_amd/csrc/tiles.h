@@ -1063,7 +1063,7 @@ MPM_DEV void p2g_group(const Dev<R>& d, const TileLists& tl, int ti, R* tpart, P
     reduce_cells_to_region<D, R, NFG, FC>(acc, f0, sm.x.red.cellpart, reg, lcell, lk0, lk1, lane_on);
     for (int i = t; i < RN * FC; i += NT) {
       int rn = i / FC, f = f0 + i % FC;
-      if (f < NFG) tpart[((size_t)ti * FI::NF + F0 + f) * RN + rn] = reg[i];
+      if (f < NFG) tpart[((size_t)ti * RN + rn) * FI::NF + F0 + f] = reg[i];
     }
     __syncthreads();
   }
@@ -1402,7 +1402,7 @@ __global__ void __launch_bounds__(64) k_merge_p2g(Dev<R> d, TileLists tl, const 
     if (ms.slot[j] < 0) continue;
     R t[NF];
 #pragma unroll
-    for (int f = 0; f < NF; ++f) t[f] = tpart[((size_t)ms.slot[j] * NF + f) * RN + ms.rn[j]];
+    for (int f = 0; f < NF; ++f) t[f] = tpart[((size_t)ms.slot[j] * RN + ms.rn[j]) * NF + f];
 #pragma unroll
     for (int f = 0; f < NF; ++f) v[f] += t[f];
   }
