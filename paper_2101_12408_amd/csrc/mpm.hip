@@ -470,8 +470,8 @@ void do_p2g(mpm_ctx* c, const mpm_particles* P, const mpm_surface* S, hipStream_
 
 // Device scalar slots (doubles at ctx->scal).
 // SC_G0 / SC_GT: the gradient merge's sums (see k_merge_stress) at the iterate and at the
-// line-search trial: [0] Phi, [1..D] sum m (v^ - v^n), [D+1] sum m, [D+2..2D+1] sum m v^,
-// [2D+2] |g|^2, [2D+3] the trial's slope g . delta.
+// line-search trial: [0] Phi, [1..D] sum m (v^ - v^n), [D+1] sum m, [D+2] |g|^2, [D+3]
+// the trial's slope g . delta.
 enum : int { SC_DOT = 1, SC_RHS2 = 5, SC_MOM = 8, SC_G0 = 16, SC_GT = 32, SC_N = 48 };
 
 // Phi(u), the momentum sums and |g|^2 into scal[red_slot ..] (Phi also into energy_dev if
@@ -493,7 +493,7 @@ void do_energy_grad(mpm_ctx* c, const R* u, R* g, double* energy_dev, int red_sl
            c->nctile > 0 ? (const double*)(c->part + 2 * kPartSlot) : nullptr, c->nctile, c->part + 4 * kPartSlot,
            c->ctr + (size_t)CTR_MERGE * kCtrSite, c->scal + red_slot, energy_dev, (CgScal*)nullptr, pu, slope_g);
   } else {
-    LAUNCH(c, MPM_K_BLAS, k_fill_r<double>, dim3(1), dim3(64), 0, s, c->scal + red_slot, 0.0, (int64_t)(2 * D + 4));
+    LAUNCH(c, MPM_K_BLAS, k_fill_r<double>, dim3(1), dim3(64), 0, s, c->scal + red_slot, 0.0, (int64_t)(D + 4));
     if (energy_dev) LAUNCH(c, MPM_K_BLAS, k_fill_r<double>, dim3(1), dim3(1), 0, s, energy_dev, 0.0, (int64_t)1);
   }
 }
@@ -750,7 +750,7 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
     msum = c->hbuf[SC_G0 + 1 + D];
     floor_abs = 1e-14 * msum * p.dx / p.dt;
     phi = c->hbuf[SC_G0];
-    gn = std::sqrt(std::max(c->hbuf[SC_G0 + 2 * D + 2], 0.0));
+    gn = std::sqrt(std::max(c->hbuf[SC_G0 + D + 2], 0.0));
     g0 = gn;
     st.g0 = g0;
   };
@@ -786,7 +786,7 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
       // tolerance max(cg_rel |g|, 0.1 newton_tol |g0|) with g0 = |g|
       const double f = std::max(p.cg_rel, 0.1 * p.newton_tol);
       cg_begin<R>(c, km, apply, (const R*)g, -1.0, delta, false, (const R*)d.gdiag, cr, cz, cp, cAp, D, f * f,
-                  c->scal + SC_G0 + 2 * D + 2, p.cg_max, s, run, first_chunk(c->cg_hint_mom));
+                  c->scal + SC_G0 + D + 2, p.cg_max, s, run, first_chunk(c->cg_hint_mom));
     } else {
       const double cg_tol = std::max(p.cg_rel * gn, 0.1 * p.newton_tol * g0);
       cg_begin<R>(c, km, apply, (const R*)g, -1.0, delta, false, (const R*)d.gdiag, cr, cz, cp, cAp, D,
@@ -805,7 +805,7 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
       if (p.momentum_fix)
         LAUNCH(c, MPM_K_BLAS, (k_mom_fix<D, R>), dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, (const uint8_t*)d.gfree,
                (const R*)d.gm, (const double*)(c->scal + SC_GT + 1), p.dt, p.gravity[0], p.gravity[1], p.gravity[2],
-               vtrial, (R*)c->gscratch, c->part, c->ctr + (size_t)CTR_MOM * kCtrSite, c->scal + SC_GT + 2 * D + 2,
+               vtrial, (R*)c->gscratch, c->part, c->ctr + (size_t)CTR_MOM * kCtrSite, c->scal + SC_GT + D + 2,
                (const int*)(c->misc + 1));
       st.energy_evals++;
     };
@@ -825,7 +825,7 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
     c->cg_hint_mom = cit;
     st.cg_iters += cit;
     st.hessvecs += cit;
-    const double slope = c->hbuf[SC_GT + 2 * D + 3];
+    const double slope = c->hbuf[SC_GT + D + 3];
     double phit = c->hbuf[SC_GT];
     // Armijo with the round-off of Phi as allowance (8 eps |Phi|, eps of the arithmetic):
     // near convergence the decrement is below it and the test would be decided by noise.
@@ -856,7 +856,7 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
       }
       phi -= 0.5 * M * c2;
     }
-    gn = std::sqrt(std::max(c->hbuf[SC_GT + 2 * D + 2], 0.0));
+    gn = std::sqrt(std::max(c->hbuf[SC_GT + D + 2], 0.0));
   }
   if (it == p.newton_max && gn <= std::max(p.newton_tol * g0, floor_abs)) st.converged = 1;
   st.newton_iters = it;

@@ -1248,9 +1248,8 @@ constexpr int kMergeTiles = 4;
 // Stress merge: node-level terms.
 //  NM_GRAD: out = P[acc + m (v^ - v^n) - dt m g]; with phi the blocks also sum the tile
 //           energy partials (epart, nep entries) and the grid sums go to red: red[0] = Phi,
-//           red[1..D] = sum m (v^ - v^n), red[D+1] = sum m, red[D+2..2D+1] = sum m v^ (nodes
-//           with mass), red[2D+2] = |out|^2, red[2D+3] = slope_g . u (u before the input
-//           update; 0 without slope_g).
+//           red[1..D] = sum m (v^ - v^n), red[D+1] = sum m (nodes with mass), red[D+2] =
+//           |out|^2, red[D+3] = slope_g . u (u before the input update; 0 without slope_g).
 //  NM_HESS: out = P[acc + alpha m w]; with cg the grid sum of w . out sets the CG step.
 template <int D, typename R>
 __global__ void __launch_bounds__(64 * kMergeTiles) k_merge_stress(
@@ -1258,7 +1257,7 @@ __global__ void __launch_bounds__(64 * kMergeTiles) k_merge_stress(
     const int* done, const double* epart, int nep, double* npart, unsigned* ctr, double* red, double* phi2,
     CgScal* cg, PUpd<R> pu, const R* slope_g) {
   constexpr int RN = TileGeo<D>::RN;
-  constexpr int NV = 2 * D + 4;
+  constexpr int NV = D + 4;
   __shared__ double sh[kRedSh];
   if (done && *done) return;
   const int ti = blockIdx.x * kMergeTiles + (threadIdx.x >> 6);
@@ -1296,7 +1295,7 @@ __global__ void __launch_bounds__(64 * kMergeTiles) k_merge_stress(
     for (int a = 0; a < D; ++a) {
       bool fa = (fr >> a) & 1;
       R ua = u ? u[a * nn + node] : R(0);
-      if (slope_g) vals[2 * D + 3] += (double)slope_g[a * nn + node] * (double)ua;
+      if (slope_g) vals[D + 3] += (double)slope_g[a * nn + node] * (double)ua;
       if (pu.z) {
         ua = cg_dir(pu.z[a * nn + node], beta, ua);
         pu.p[a * nn + node] = ua;
@@ -1309,7 +1308,6 @@ __global__ void __launch_bounds__(64 * kMergeTiles) k_merge_stress(
           double dv = (double)ua - (double)vn;
           vals[0] += 0.5 * (double)m * dv * dv - (double)d.dt * (double)m * (double)d.grav[a] * (double)ua;
           vals[1 + a] = (double)m * dv;
-          vals[D + 2 + a] = (double)m * (double)ua;
         }
       } else {
         R wa = (!mask_in || fa) ? ua : R(0);
@@ -1318,7 +1316,7 @@ __global__ void __launch_bounds__(64 * kMergeTiles) k_merge_stress(
       }
       o = fa ? o : R(0);
       out[a * nn + node] = o;
-      vals[2 * D + 2] += (double)o * (double)o;
+      vals[D + 2] += (double)o * (double)o;
     }
   }
   const bool want = (mode == NM_GRAD && red) || (mode == NM_HESS && cg);
