@@ -98,6 +98,7 @@ struct mpm_ctx {
   // the same sort scratch for the surface-sample sort on the second stream
   int* ccount_aux = nullptr;
   int* sort_tmp_aux = nullptr;
+  void* sF_alt = nullptr;        // surface F_r at the line-search trial (swapped with d.sF)
   uint64_t* scan_flags_aux = nullptr;
   unsigned scan_epoch_aux = 0;
   int* misc = nullptr;          // [0] status, [1] constrained flag, [2] tile count
@@ -225,6 +226,7 @@ size_t layout(mpm_ctx* c, char* base) {
   int* sort_tmp = b.take<int>(std::max(NP, NS));
   int* ccount_aux = b.take<int>(NN);
   int* sort_tmp_aux = b.take<int>(NS);
+  void* sF_alt = b.take<R>(D * D * NS);
   uint64_t* scan_flags_aux = b.take<uint64_t>(kScanBlock);
   d.status = misc;
   if (base) {
@@ -239,6 +241,7 @@ size_t layout(mpm_ctx* c, char* base) {
     c->part = d.part; c->scal = d.scal; c->cg = cg; c->ctr = ctr;
     c->sort_tmp = sort_tmp;
     c->ccount_aux = ccount_aux; c->sort_tmp_aux = sort_tmp_aux; c->scan_flags_aux = scan_flags_aux;
+    c->sF_alt = sF_alt;
     if constexpr (sizeof(R) == 8) c->d64 = d; else c->d32 = d;
   }
   return b.off + 256;
@@ -479,14 +482,15 @@ enum : int { SC_DOT = 1, SC_RHS2 = 5, SC_MOM = 8, SC_G0 = 16, SC_GT = 32, SC_N =
 template <int D, typename R>
 //
 // With pu (z = v^, beta = alpha, p = the trial point) the point is v^ + alpha u, formed in
-// the kernels and stored in pu.p; with slope_g the sums also hold slope_g . u.
+// the kernels and stored in pu.p; with slope_g the sums also hold slope_g . u; with fout
+// the surface samples' F_r = I + dt grad v (the Hessian's linearization at this point).
 void do_energy_grad(mpm_ctx* c, const R* u, R* g, double* energy_dev, int red_slot, hipStream_t s,
-                    PUpd<R> pu = PUpd<R>{}, const R* slope_g = nullptr) {
+                    PUpd<R> pu = PUpd<R>{}, const R* slope_g = nullptr, R* fout = nullptr) {
   Dev<R>& d = dev<R>(c);
   TileLists tl = tiles(c);
   if (c->nctile > 0)
     LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_ENERGY>), dim3(c->nctile), dim3(TileGeo<D>::NT), 0, s, d, tl,
-           u, (R*)c->tpart, 0, (const int*)nullptr, 2, pu);
+           u, (R*)c->tpart, 0, (const int*)nullptr, 2, pu, fout);
   if (c->ntiles > 0) {
     LAUNCH(c, MPM_K_ENERGY_NODE, (k_merge_stress<D, R>), dim3(merge_blocks(c)), dim3(64 * kMergeTiles), 0, s, d, tl,
            c->ntiles, (const R*)c->tpart, u, g, (int)NM_GRAD, 0.0, 0, (const int*)nullptr,
@@ -516,7 +520,7 @@ void do_hessvec(mpm_ctx* c, const R* w, double alpha, R* out, bool mask_in, cons
   TileLists tl = tiles(c);
   if (c->nctile > 0)
     LAUNCH(c, MPM_K_HESS_INT, (k_tile_stress<D, R, TM_HESS>), dim3(c->nctile), dim3(TileGeo<D>::NT), 0, s, d, tl, w,
-           (R*)c->tpart, (int)mask_in, done, -1, pu);
+           (R*)c->tpart, (int)mask_in, done, -1, pu, (R*)nullptr);
   if (c->ntiles > 0)
     LAUNCH(c, MPM_K_HESS_NODE, (k_merge_stress<D, R>), dim3(merge_blocks(c)), dim3(64 * kMergeTiles), 0, s, d, tl, c->ntiles,
            (const R*)c->tpart,
@@ -531,7 +535,7 @@ void do_hessvec_force(mpm_ctx* c, const R* u, R* out, hipStream_t s) {
   TileLists tl = tiles(c);
   if (c->nctile > 0)
     LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_FORCE>), dim3(c->nctile), dim3(TileGeo<D>::NT), 0, s, d, tl,
-           u, (R*)c->tpart, 0, (const int*)nullptr, -1, PUpd<R>{});
+           u, (R*)c->tpart, 0, (const int*)nullptr, -1, PUpd<R>{}, (R*)nullptr);
   if (c->ntiles > 0)
     LAUNCH(c, MPM_K_ENERGY_NODE, (k_merge_stress<D, R>), dim3(merge_blocks(c)), dim3(64 * kMergeTiles), 0, s, d, tl, c->ntiles,
            (const R*)c->tpart,
@@ -742,7 +746,9 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
   // stopping test, that queued work is dropped (it writes only the CG and trial buffers).
   LAUNCH(c, MPM_K_BLAS, k_project_copy<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const uint8_t*)d.gfree,
          (const R*)d.gvn, vhat);
-  do_energy_grad<D, R>(c, vhat, g, nullptr, SC_G0, s);
+  // the start's energy evaluation also caches the surface linearization F_r at v^; each
+  // trial's goes to sF_alt, which becomes the cache when the trial is accepted
+  do_energy_grad<D, R>(c, vhat, g, nullptr, SC_G0, s, PUpd<R>{}, nullptr, (d.term_mask & 2) ? d.sF : nullptr);
   bool fix = false;
   double msum = 0, floor_abs = 0, phi = 0, gn = 0, g0 = 0;
   auto start_values = [&] {   // from a read that covers the start's gradient merge
@@ -775,7 +781,6 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
       if (sizeof(R) == 4 && gn <= 1e-4 * g0 && gn > 0.5 * gn_prev) { st.converged = 2; break; }
     }
     gn_prev = gn;
-    do_surface_lin<D, R>(c, vhat, s);
     R* cr = (R*)c->r;
     R* cz = (R*)c->z;
     R* cp = (R*)c->pp;
@@ -801,7 +806,8 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
     double alpha = 1.0;
     auto trial_launch = [&](double a) {
       do_energy_grad<D, R>(c, (const R*)delta, (R*)c->gscratch, nullptr, SC_GT, s,
-                           PUpd<R>{vtrial, (const R*)vhat, nullptr, (R)a}, (const R*)g);
+                           PUpd<R>{vtrial, (const R*)vhat, nullptr, (R)a}, (const R*)g,
+                           (d.term_mask & 2) ? (R*)c->sF_alt : nullptr);
       if (p.momentum_fix)
         LAUNCH(c, MPM_K_BLAS, (k_mom_fix<D, R>), dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, (const uint8_t*)d.gfree,
                (const R*)d.gm, (const double*)(c->scal + SC_GT + 1), p.dt, p.gravity[0], p.gravity[1], p.gravity[2],
@@ -840,6 +846,11 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
     }
     // accept the last trial: its (corrected) point and gradient become the iterate
     std::swap(c->vhat, c->vtrial);
+    {
+      R* f_acc = (R*)c->sF_alt;
+      c->sF_alt = d.sF;
+      d.sF = f_acc;
+    }
     std::swap(c->grad, c->gscratch);
     vhat = (R*)c->vhat;
     vtrial = (R*)c->vtrial;

@@ -526,7 +526,7 @@ MPM_DEV void stress_fetch(const Dev<R>& d, int q, int ntot, int npi, int pb, int
 template <int D, typename R, int MODE>
 __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stress(Dev<R> d, TileLists tl, const R* u, R* tpart,
                                                                 int mask_in, const int* done, int energy_slot,
-                                                                PUpd<R> pu) {
+                                                                PUpd<R> pu, R* fout) {
   constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
   constexpr int CH = StressLds<D, R>::CH, PS = StressLds<D, R>::PS;
   __shared__ StressLds<D, R> sm;
@@ -646,6 +646,13 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
 #pragma unroll
             for (int b = 0; b < D; ++b) F[a][b] = dt * G[a][b];
             F[a][a] += R(1);
+          }
+          // the surface linearization point of a Hessian at this velocity
+          if (fout) {
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+#pragma unroll
+              for (int b = 0; b < D; ++b) fout[(a * D + b) * d.ns + in.k] = F[a][b];
           }
         }
         R Q[D][D];
