@@ -786,8 +786,9 @@ MPM_DEV void cg_init(CgScal* s, double rz, double rr, double tol2, int maxit) {
 template <typename R>
 __global__ void k_cg_start(const int* tl, int nelem, int nn, int ncomp, const R* b, R bscale, const R* Ax,
                            const R* diag, R* x, R* r, R* z, R* p, double* part, unsigned* ctr, CgScal* cs,
-                           double tol2_host, const double* tol2_scale, int maxit) {
+                           double tol2_host, const double* tol2_scale, int maxit, const double* gate) {
   __shared__ double sh[kRedSh];
+  if (gate && *gate == 0.0) return;   // a speculative start that was called off
   double rz = 0, rr = 0;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nelem; e += gridDim.x * blockDim.x) {
     int node = elem_node(tl, e);
@@ -806,6 +807,37 @@ __global__ void k_cg_start(const int* tl, int nelem, int nn, int ncomp, const R*
   t[1] = block_sum(rr, sh);
   if (grid_reduce<2>(t, part, ctr, sh, sum) && threadIdx.x == 0)
     cg_init(cs, sum[0], sum[1], tol2_host * (tol2_scale ? *tol2_scale : 1.0), maxit);
+}
+
+// Whether the Newton iteration after the current trial follows at once, decided on the
+// device from the trial's sums with the host's tests (the Armijo test at alpha = 1 with
+// its round-off allowance, then the stopping tests at the new iterate): writes 1 or 0 to
+// scal[go_slot], and the CG tolerance max(cg_rel |g|, 0.1 newton_tol |g0|)^2 of that
+// iteration to scal[tol_slot]; when it does not follow, the next CG's scalars are marked
+// done so that a CG queued for it returns at once.  from_start: the current iterate is
+// the start, whose values come from the start's sums at scal[g0_slot] instead of the
+// host's.  One thread.
+__global__ void k_newton_decide(double* scal, int dim, int gt_slot, int g0_slot, int from_start, double phi_h,
+                                double g0_h, double floor_h, double gcur_h, double c1, double eps8, int armijo,
+                                double newton_tol, double cg_rel, int mixed, double dx_over_dt, CgScal* next,
+                                int go_slot, int tol_slot) {
+  double phi = phi_h, g0 = g0_h, floor_abs = floor_h, gcur = gcur_h;
+  if (from_start) {
+    phi = scal[g0_slot];
+    g0 = sqrt(fmax(scal[g0_slot + dim + 2], 0.0));
+    floor_abs = 1e-14 * scal[g0_slot + 1 + dim] * dx_over_dt;
+    gcur = g0;
+  }
+  const double phit = scal[gt_slot], slope = scal[gt_slot + dim + 3];
+  const double gn = sqrt(fmax(scal[gt_slot + dim + 2], 0.0));
+  const bool start_ok = g0 == g0 && phi == phi && !(g0 <= fmax(newton_tol * g0, floor_abs));
+  const bool accept = !armijo || phit <= phi + c1 * slope + eps8 * fmax(fabs(phi), fabs(phit));
+  const bool go = start_ok && accept && gn == gn && phit == phit && !(gn <= fmax(newton_tol * g0, floor_abs)) &&
+                  !(mixed && gn <= 1e-4 * g0 && gn > 0.5 * gcur);
+  const double t = fmax(cg_rel * gn, 0.1 * newton_tol * g0);
+  scal[go_slot] = go ? 1.0 : 0.0;
+  scal[tol_slot] = t * t;
+  if (!go) next->done = 1;
 }
 
 // Called by the last block of the operator's merge with the sum p . A p.

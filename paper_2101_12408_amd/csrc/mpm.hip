@@ -83,6 +83,9 @@ struct mpm_ctx {
   // real-typed vectors (void* so both precisions share the host code)
   void *vhat = nullptr, *vtrial = nullptr, *grad = nullptr, *delta = nullptr, *r = nullptr, *z = nullptr,
        *pp = nullptr, *Ap = nullptr, *zero = nullptr, *gscratch = nullptr;
+  // a second set of momentum-CG vectors (delta, r, z, p, Ap): Newton iterations alternate
+  // sets, so that the next iteration's CG can be queued before the current one is judged
+  void* cg2[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   void *That = nullptr, *hr = nullptr, *hz = nullptr, *hp = nullptr, *hAp = nullptr;
   int* tile_pos = nullptr;
   int* ctile_flag = nullptr;
@@ -127,7 +130,7 @@ struct mpm_ctx {
   // second stream of a step: the heat solve runs beside the momentum solve
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_hread = nullptr, ev_counts = nullptr, ev_sfork = nullptr,
-             ev_sjoin = nullptr;
+             ev_sjoin = nullptr, ev_mread = nullptr;
 };
 
 namespace {
@@ -211,14 +214,14 @@ size_t layout(mpm_ctx* c, char* base) {
   d.gET = b.take<R>(NN); d.gTn = b.take<R>(NN); d.hdiag = b.take<R>(NN); d.hrhs = b.take<R>(NN);
   d.gmv = b.take<R>(D * NN); d.gvn = b.take<R>(D * NN); d.gdiag = b.take<R>(D * NN);
   d.gfree = b.take<uint8_t>(NN);
-  void* vecs[10];
-  for (int k = 0; k < 10; ++k) vecs[k] = b.take<R>(D * NN);
+  void* vecs[15];
+  for (int k = 0; k < 15; ++k) vecs[k] = b.take<R>(D * NN);
   void* hvecs[5];
   for (int k = 0; k < 5; ++k) hvecs[k] = b.take<R>(NN);
   d.part = b.take<double>((size_t)kNumParts * kPartSlot);
   d.scal = (double*)mirror;
   CgScal* cg = (CgScal*)(mirror + kMirrorCg);
-  static_assert(kScalDoubles * sizeof(double) <= kMirrorCg && kMirrorCg + 2 * sizeof(CgScal) <= kMirrorMisc &&
+  static_assert(kScalDoubles * sizeof(double) <= kMirrorCg && kMirrorCg + 3 * sizeof(CgScal) <= kMirrorMisc &&
                     kMirrorMisc + 8 * sizeof(int) <= kMirrorRead && kMirrorRead <= kMirrorHeatHost &&
                     kMirrorHeatHost + sizeof(CgScal) <= kMirrorBytes,
                 "mirror layout");
@@ -232,6 +235,7 @@ size_t layout(mpm_ctx* c, char* base) {
   if (base) {
     c->vhat = vecs[0]; c->vtrial = vecs[1]; c->grad = vecs[2]; c->delta = vecs[3]; c->r = vecs[4];
     c->z = vecs[5]; c->pp = vecs[6]; c->Ap = vecs[7]; c->zero = vecs[8]; c->gscratch = vecs[9];
+    for (int k = 0; k < 5; ++k) c->cg2[k] = vecs[10 + k];
     c->That = hvecs[0]; c->hr = hvecs[1]; c->hz = hvecs[2]; c->hp = hvecs[3]; c->hAp = hvecs[4];
     c->tile_pos = tile_pos; c->scan_flags = scan_flags; c->misc = misc;
     c->ctile_flag = ctile_flag; c->ctile_pos = ctile_pos; c->ctile_list = ctile_list; c->ctile_slot = ctile_slot;
@@ -475,7 +479,8 @@ void do_p2g(mpm_ctx* c, const mpm_particles* P, const mpm_surface* S, hipStream_
 // SC_G0 / SC_GT: the gradient merge's sums (see k_merge_stress) at the iterate and at the
 // line-search trial: [0] Phi, [1..D] sum m (v^ - v^n), [D+1] sum m, [D+2] |g|^2, [D+3]
 // the trial's slope g . delta.
-enum : int { SC_DOT = 1, SC_RHS2 = 5, SC_MOM = 8, SC_G0 = 16, SC_GT = 32, SC_N = 48 };
+// SC_GO / SC_TOL2: the device's decision on the next Newton iteration (k_newton_decide).
+enum : int { SC_DOT = 1, SC_RHS2 = 5, SC_MOM = 8, SC_G0 = 16, SC_GT = 32, SC_GO = 40, SC_TOL2 = 41, SC_N = 48 };
 
 // Phi(u), the momentum sums and |g|^2 into scal[red_slot ..] (Phi also into energy_dev if
 // given), projected gradient into g.
@@ -513,14 +518,17 @@ void do_surface_lin(mpm_ctx* c, const R* vlin, hipStream_t s) {
 // out = P(alpha M P w + H P w) with the surface term linearized at the cached F_r.  With cg
 // the merge also reduces w . out and sets the CG step length.  With z (a CG direction w):
 // w is first replaced by z + beta w, which the merge stores.
+// f_lin: the surface linearization to use instead of the cached one.
 template <int D, typename R>
 void do_hessvec(mpm_ctx* c, const R* w, double alpha, R* out, bool mask_in, const int* done, CgScal* cg,
-                hipStream_t s, PUpd<R> pu = PUpd<R>{}) {
+                hipStream_t s, PUpd<R> pu = PUpd<R>{}, R* f_lin = nullptr) {
   Dev<R>& d = dev<R>(c);
   TileLists tl = tiles(c);
+  Dev<R> dh = d;
+  if (f_lin) dh.sF = f_lin;
   if (c->nctile > 0)
-    LAUNCH(c, MPM_K_HESS_INT, (k_tile_stress<D, R, TM_HESS>), dim3(c->nctile), dim3(TileGeo<D>::NT), 0, s, d, tl, w,
-           (R*)c->tpart, (int)mask_in, done, -1, pu, (R*)nullptr);
+    LAUNCH(c, MPM_K_HESS_INT, (k_tile_stress<D, R, TM_HESS>), dim3(c->nctile), dim3(TileGeo<D>::NT), 0, s, dh, tl,
+           w, (R*)c->tpart, (int)mask_in, done, -1, pu, (R*)nullptr);
   if (c->ntiles > 0)
     LAUNCH(c, MPM_K_HESS_NODE, (k_merge_stress<D, R>), dim3(merge_blocks(c)), dim3(64 * kMergeTiles), 0, s, d, tl, c->ntiles,
            (const R*)c->tpart,
@@ -600,6 +608,20 @@ void read_mirror(mpm_ctx* c, hipStream_t s) {
   c->stats.n_dof = c->hint[2];
 }
 
+// read_mirror in two halves, so that work can be queued behind the copy before the host
+// waits for it.
+void mirror_copy(mpm_ctx* c, hipStream_t s) {
+  if (!c->ev_mread) HIPCHK(hipEventCreateWithFlags(&c->ev_mread, hipEventDisableTiming));
+  HIPCHK(hipMemcpyAsync(c->hmirror, (const char*)c->scal, kMirrorRead, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipEventRecord(c->ev_mread, s));
+}
+void mirror_wait(mpm_ctx* c) {
+  HIPCHK(hipEventSynchronize(c->ev_mread));
+  c->status |= c->hint[0];
+  c->constrained = c->hint[1] != 0;
+  c->stats.n_dof = c->hint[2];
+}
+
 // Jacobi-preconditioned CG with device-side scalars: apply(p, Ap, done, cg) must write
 // A p and, when cg is given, set the step length from p . A p.  The kernels return at
 // once after the done flag is set, so chunks of iterations can be queued ahead of the
@@ -623,9 +645,10 @@ struct KrySet {
   bool own_read;
 };
 
-inline KrySet kry_momentum(mpm_ctx* c) {
-  return KrySet{c->cg, c->hcg, c->part, c->ctr + (size_t)CTR_CGSTART * kCtrSite, c->ctr + (size_t)CTR_CGUPD * kCtrSite,
-                false};
+// Momentum CG scalars: slot 0 for vector set 0, slot 2 for set 1 (slot 1 is the heat CG's).
+inline KrySet kry_momentum(mpm_ctx* c, int set = 0) {
+  return KrySet{c->cg + (set ? 2 : 0), c->hcg + (set ? 2 : 0), c->part, c->ctr + (size_t)CTR_CGSTART * kCtrSite,
+                c->ctr + (size_t)CTR_CGUPD * kCtrSite, false};
 }
 inline KrySet kry_heat(mpm_ctx* c) {
   return KrySet{c->cg + 1, (CgScal*)(c->hmirror + kMirrorHeatHost), c->part + 16 * kPartSlot,
@@ -672,14 +695,14 @@ void cg_iterate(mpm_ctx* c, const KrySet& k, Apply&& apply, R* x, const R* diag,
 template <typename R, class Apply>
 void cg_begin(mpm_ctx* c, const KrySet& k, Apply&& apply, const R* b, double bscale, R* x, bool x0_given,
               const R* diag, R* r, R* z, R* p, R* Ap, int ncomp, double tol2_host, const double* tol2_scale, int maxit,
-              hipStream_t s, CgRun& run, int first = 2) {
+              hipStream_t s, CgRun& run, int first = 2, const double* gate = nullptr) {
   Dev<R>& d = dev<R>(c);
   int nelem = c->ntiles * 64, nb = krylov_blocks(nelem);
   const int* tl = d.tile_list;
   if (x0_given) apply(x, Ap, (const int*)nullptr, (CgScal*)nullptr, PUpd<R>{});
   LAUNCH(c, MPM_K_BLAS, k_cg_start<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, b, (R)bscale,
          x0_given ? (const R*)Ap : (const R*)nullptr, diag, x, r, z, p, k.part, k.ctr_start, k.cg, tol2_host,
-         tol2_scale, maxit);
+         tol2_scale, maxit, gate);
   run = CgRun{};
   run.chunk = std::min(first, std::max(maxit, 1));
   cg_iterate<R>(c, k, apply, x, diag, r, z, p, Ap, ncomp, run.chunk, s, run);
@@ -737,7 +760,6 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
   R* vhat = (R*)c->vhat;
   R* vtrial = (R*)c->vtrial;
   R* g = (R*)c->grad;
-  R* delta = (R*)c->delta;
   mpm_stats& st = c->stats;
   // start: v^ = P v^n; Phi, the mass sum and |g| come from the gradient merge.  The host
   // reads them together with the first iteration's CG and trial scalars: the first CG
@@ -770,8 +792,13 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
     do_hessvec<D, R>(c, pv, 1.0, Apv, false, done, cg, s, pu);
   };
   const double eps = sizeof(R) == 8 ? 2.220446049250313e-16 : 1.1920928955078125e-07;
+  // CG vectors of the two sets (delta, r, z, p, Ap); iteration it uses set it % 2
+  R* cgv[2][5] = {{(R*)c->delta, (R*)c->r, (R*)c->z, (R*)c->pp, (R*)c->Ap},
+                  {(R*)c->cg2[0], (R*)c->cg2[1], (R*)c->cg2[2], (R*)c->cg2[3], (R*)c->cg2[4]}};
   int it = 0;
   double gn_prev = 1e300;
+  bool have_next = false;   // this iteration's CG start and first chunk are already queued
+  CgRun next_run;
   for (; it < p.newton_max; ++it) {
     if (it > 0) {
       if (!(gn == gn) || !(phi == phi)) { c->status |= ST_NONFINITE; break; }
@@ -781,13 +808,23 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
       if (sizeof(R) == 4 && gn <= 1e-4 * g0 && gn > 0.5 * gn_prev) { st.converged = 2; break; }
     }
     gn_prev = gn;
-    R* cr = (R*)c->r;
-    R* cz = (R*)c->z;
-    R* cp = (R*)c->pp;
-    R* cAp = (R*)c->Ap;
+    const int set = it & 1;
+    R* delta = cgv[set][0];
+    R* cr = cgv[set][1];
+    R* cz = cgv[set][2];
+    R* cp = cgv[set][3];
+    R* cAp = cgv[set][4];
     CgRun run;
-    const KrySet km = kry_momentum(c);
-    if (it == 0) {
+    const KrySet km = kry_momentum(c, set);
+    if (have_next) {
+      // the queued start and first iteration, completed to the usual first chunk
+      run = next_run;
+      const int more = std::min(first_chunk(c->cg_hint_mom), std::max(p.cg_max, 1)) - run.launched;
+      if (more > 0) {
+        cg_iterate<R>(c, km, apply, delta, (const R*)d.gdiag, cr, cz, cp, cAp, D, more, s, run);
+        run.chunk = run.launched;
+      }
+    } else if (it == 0) {
       // tolerance max(cg_rel |g|, 0.1 newton_tol |g0|) with g0 = |g|
       const double f = std::max(p.cg_rel, 0.1 * p.newton_tol);
       cg_begin<R>(c, km, apply, (const R*)g, -1.0, delta, false, (const R*)d.gdiag, cr, cz, cp, cAp, D, f * f,
@@ -816,16 +853,43 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
       st.energy_evals++;
     };
     trial_launch(alpha);
-    read_mirror(c, s);
+    // The next iteration's CG start and first iteration (other vector set) are queued
+    // behind the read, on the guess that the full step is accepted and the solve goes on:
+    // the right side is the trial's gradient and the Hessian the trial's surface
+    // linearization.  They keep the GPU busy while the host decides.  The device decides
+    // with the host's tests whether they run (k_newton_decide); the host uses them only
+    // when its own decision agrees and the trial stands as queued, else it starts the CG
+    // afresh.
+    const bool spec = it + 1 < p.newton_max;
+    if (spec)
+      LAUNCH(c, MPM_K_BLAS, k_newton_decide, dim3(1), dim3(1), 0, s, c->scal, D, (int)SC_GT, (int)SC_G0,
+             it == 0 ? 1 : 0, phi, g0, floor_abs, gn, p.ls_c1, 8.0 * eps, p.ls_max > 1 ? 1 : 0, p.newton_tol, p.cg_rel,
+             sizeof(R) == 4 ? 1 : 0, p.dx / p.dt, kry_momentum(c, set ^ 1).cg, (int)SC_GO, (int)SC_TOL2);
+    mirror_copy(c, s);
+    if (spec) {
+      R* const* nv = cgv[set ^ 1];
+      R* f_next = (d.term_mask & 2) ? (R*)c->sF_alt : nullptr;
+      auto apply_next = [&](const R* pv, R* Apv, const int* done, CgScal* cg, PUpd<R> pu) {
+        do_hessvec<D, R>(c, pv, 1.0, Apv, false, done, cg, s, pu, f_next);
+      };
+      cg_begin<R>(c, kry_momentum(c, set ^ 1), apply_next, (const R*)c->gscratch, -1.0, nv[0], false,
+                  (const R*)d.gdiag, nv[1], nv[2], nv[3], nv[4], D, 1.0, c->scal + SC_TOL2, p.cg_max, s, next_run,
+                  1, c->scal + SC_GO);
+    }
+    mirror_wait(c);
+    const bool dev_go = c->hbuf[SC_GO] != 0.0;
+    have_next = false;
     if (it == 0) {
       start_values();
       if (!(gn == gn) || !(phi == phi)) { c->status |= ST_NONFINITE; st.energy_evals--; break; }
       if (gn <= std::max(p.newton_tol * g0, floor_abs)) { st.converged = 1; st.energy_evals--; break; }
     }
+    bool stands = true;   // the trial read above is the one accepted, at alpha = 1
     if (cg_finish<R>(c, km, apply, delta, (const R*)d.gdiag, cr, cz, cp, cAp, D, p.cg_max, s, run)) {
       // the guess failed: the trial used an unfinished delta
       trial_launch(alpha);
       read_mirror(c, s);
+      stands = false;
     }
     const int cit = km.hcg->iters;
     c->cg_hint_mom = cit;
@@ -843,7 +907,9 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
       trial_launch(alpha);
       read_mirror(c, s);
       phit = c->hbuf[SC_GT];
+      stands = false;
     }
+    have_next = spec && dev_go && stands;
     // accept the last trial: its (corrected) point and gradient become the iterate
     std::swap(c->vhat, c->vtrial);
     {
@@ -1126,6 +1192,7 @@ int mpm_ctx_destroy(mpm_ctx* ctx) {
   if (ctx->ev_counts) hipEventDestroy(ctx->ev_counts);
   if (ctx->ev_sfork) hipEventDestroy(ctx->ev_sfork);
   if (ctx->ev_sjoin) hipEventDestroy(ctx->ev_sjoin);
+  if (ctx->ev_mread) hipEventDestroy(ctx->ev_mread);
   if (ctx->hmirror) hipHostFree(ctx->hmirror);
   delete ctx;
   return MPM_OK;
