@@ -164,15 +164,19 @@ HBM_PEAK = 8000.0      # GB/s
 VALU_PEAK = {4: 157.3, 8: 78.6}   # TFLOP/s, vector FP32 / FP64
 
 
-def roofline_of(cls, tm, N, S, G, R, K, traffic):
+def roofline_of(cls, tm, N, S, G, R, K, traffic, hessvecs=None):
+    """Roofline of one kernel class.  The Hessian classes are averaged over the operator
+    applications that did work (hessvecs): a CG queued ahead of a Newton decision that
+    the device then calls off still launches, and its kernels return at once."""
     ms, launches = tm[cls]
-    avg_s = ms / launches * 1e-3
+    work = hessvecs if (hessvecs and cls in ("hess_int", "hess_node")) else launches
+    avg_s = ms / work * 1e-3
     alg = algorithmic(cls, N, S, G, R)
     gbs = alg["bytes"] / avg_s / 1e9
     tfl = alg["flops"] / avg_s / 1e12
     t_hbm = alg["bytes"] / (HBM_PEAK * 1e9)
     t_alu = alg["flops"] / (VALU_PEAK[R] * 1e12)
-    common = dict(kernel=cls, avg_launch_us=round(avg_s * 1e6, 2), launches_per_step=round(launches / K, 2),
+    common = dict(kernel=cls, avg_launch_us=round(avg_s * 1e6, 2), launches_per_step=round(work / K, 2),
                   alg_bytes=int(alg["bytes"]), alg_flops=int(alg["flops"]),
                   hbm_frac=round(gbs / HBM_PEAK, 4), valu_frac=round(tfl / VALU_PEAK[R], 4))
     if t_hbm >= t_alu:
@@ -298,8 +302,8 @@ def main():
         out_extra["kernel_ms_per_step"] = {k: round(v[0] / K, 4) for k, v in tm.items() if v[1]}
         cand = [k for k in tm if tm[k][1] and algorithmic(k, N, S, G, R)]
         dom = max(cand, key=lambda k: tm[k][0])
-        roofline = roofline_of(dom, tm, N, S, G, R, K, measured_traffic(dom, args.precision))
-        out_extra["kernel_rooflines"] = {k: {kk: roofline_of(k, tm, N, S, G, R, K, None)[kk]
+        roofline = roofline_of(dom, tm, N, S, G, R, K, measured_traffic(dom, args.precision), hv)
+        out_extra["kernel_rooflines"] = {k: {kk: roofline_of(k, tm, N, S, G, R, K, None, hv)[kk]
                                              for kk in ("avg_launch_us", "hbm_frac", "valu_frac")} for k in cand}
         out_extra["kernel_time_share"] = round(total / (main_run["elapsed_events"] * 1e3), 3)
         out_extra["ms_per_step_with_events"] = round(1e3 * main_run["elapsed_events"] / K, 3)
