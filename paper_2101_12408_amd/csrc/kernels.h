@@ -225,47 +225,42 @@ __global__ void k_cell_scatter(const int* key, int cnt, const int* start, int* c
   }
 }
 
-// Segment ordering after an atomic scatter: the segment of slot s is the run of slots
-// whose values v have the same key[v]; it starts at start[key[v]].  Sorting each segment
-// by value (the input index) puts it in input order, independent of the order in which
-// the atomics were served.  Short segments (up to 16) are ranked in registers by their
-// first slot's thread; in longer ones every thread ranks its own value by counting the
-// smaller ones (independent loads) into tmp, and k_segment_copy_long moves them back.
-// (Threads may read a slot while its short segment is being reordered: any value there
-// belongs to the same segment, so they still compute the same key and bounds.)
+// Segment ordering after an atomic scatter, from src into dst: the segment of slot s is
+// the run of slots whose values v have the same key[v]; it starts at start[key[v]].
+// Sorting each segment by value (the input index) puts it in input order, independent of
+// the order in which the atomics were served.  Short segments (up to 16) are ranked in
+// registers by their first slot's thread; in longer ones every thread ranks its own value
+// by counting the smaller ones (independent loads).  src is only read, so every thread
+// sees the scatter's output.
 constexpr int kSegReg = 16;
 
-__global__ void k_segment_rank(const int* key, const int* start, int cnt, int* vals, int* tmp) {
+__global__ void k_segment_order(const int* key, const int* start, int cnt, const int* src, int* dst) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= cnt) return;
-  const int v = vals[s];
+  const int v = src[s];
   const int k = key[v];
   const int b = start[k], e = start[k + 1], n = e - b;
-  if (n < 2) return;
+  if (n < 2) {
+    dst[s] = v;
+    return;
+  }
   if (n > kSegReg) {
     int r = 0;
-    for (int j = b; j < e; ++j) r += vals[j] < v ? 1 : 0;
-    tmp[b + r] = v;
+    for (int j = b; j < e; ++j) r += src[j] < v ? 1 : 0;
+    dst[b + r] = v;
     return;
   }
   if (s != b) return;
   int w[kSegReg];
 #pragma unroll
-  for (int i = 0; i < kSegReg; ++i) w[i] = i < n ? vals[b + i] : 0x7fffffff;
+  for (int i = 0; i < kSegReg; ++i) w[i] = i < n ? src[b + i] : 0x7fffffff;
 #pragma unroll
   for (int i = 0; i < kSegReg; ++i) {
     int r = 0;
 #pragma unroll
     for (int j = 0; j < kSegReg; ++j) r += w[j] < w[i] ? 1 : 0;
-    if (i < n) vals[b + r] = w[i];
+    if (i < n) dst[b + r] = w[i];
   }
-}
-
-__global__ void k_segment_copy_long(const int* key, const int* start, int cnt, int* vals, const int* tmp) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= cnt) return;
-  const int k = key[vals[s]];
-  if (start[k + 1] - start[k] > kSegReg) vals[s] = tmp[s];
 }
 
 __global__ void k_fill_i32(int* p, int v, int64_t len) {
@@ -504,9 +499,10 @@ __global__ void k_split_mass(Dev<R> d) {
   d.pcnt_orig[d.p_perm[k]] = c;
 }
 
-// Balance point b_r = s_r + 2 (x_p(r) - s_r) (eq. pbal), in sample order; group slots.
+// Balance point b_r = s_r + 2 (x_p(r) - s_r) (eq. pbal), in sample order; group slots
+// (each group in atomic order, put in sample order by k_segment_order).
 template <int D, typename R>
-__global__ void k_balance(Dev<R> d) {
+__global__ void k_balance(Dev<R> d, int* grp_unordered) {
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   int S = d.ns, N = d.np;
   if (r >= S) return;
@@ -517,7 +513,7 @@ __global__ void k_balance(Dev<R> d) {
     d.bx_unsorted[a * S + r] = s + R(2) * (d.px[a * N + p] - s);
   }
   int slot = d.grp_start[p] + atomicSub(&d.gcur[p], 1) - 1;
-  d.grp[slot] = r;
+  grp_unordered[slot] = r;
 }
 
 template <int D, typename R>

@@ -312,13 +312,11 @@ void scan(mpm_ctx* c, const int* in, int* out, int len, hipStream_t s) {
   scan(c, in, out, len, s, c->scan_flags, &c->scan_epoch);
 }
 
-// Puts every segment of vals[0, cnt) (runs of equal key[value], starting at start[key])
-// in ascending value order.
-void segment_order(mpm_ctx* c, const int* key, const int* start, int cnt, int* vals, hipStream_t s, int* tmp) {
+// Copies src[0, cnt) to dst with every segment (run of equal key[value], starting at
+// start[key]) in ascending value order.
+void segment_order(mpm_ctx* c, const int* key, const int* start, int cnt, const int* src, int* dst, hipStream_t s) {
   if (cnt <= 0) return;
-  LAUNCH(c, MPM_K_SORT, k_segment_rank, dim3(cdiv(cnt, 256)), dim3(256), 0, s, key, start, cnt, vals, tmp);
-  LAUNCH(c, MPM_K_SORT, k_segment_copy_long, dim3(cdiv(cnt, 256)), dim3(256), 0, s, key, start, cnt, vals,
-         (const int*)tmp);
+  LAUNCH(c, MPM_K_SORT, k_segment_order, dim3(cdiv(cnt, 256)), dim3(256), 0, s, key, start, cnt, src, dst);
 }
 
 // Stable cell sort of cnt points: perm (sorted slot -> input index) and start[nn+1].
@@ -334,8 +332,8 @@ void cell_sort(mpm_ctx* c, Dev<R>& d, const R* pos, int cnt, int* key, int* perm
   scan(c, r.ccount, start, d.nn, s, r.flags, r.epoch);
   if (cnt > 0) {
     LAUNCH(c, MPM_K_SORT, k_cell_scatter, dim3(cdiv(cnt, 256)), dim3(256), 0, s, (const int*)key, cnt,
-           (const int*)start, r.ccount, perm, d.status);
-    segment_order(c, key, start, cnt, perm, s, r.tmp);
+           (const int*)start, r.ccount, r.tmp, d.status);
+    segment_order(c, key, start, cnt, (const int*)r.tmp, perm, s);
   }
 }
 
@@ -423,8 +421,8 @@ void do_p2g(mpm_ctx* c, const mpm_particles* P, const mpm_surface* S, hipStream_
   if (c->np > 0) LAUNCH(c, MPM_K_SETUP, (k_split_mass<R>), dim3(cdiv(c->np, 256)), dim3(256), 0, s, d);
   scan(c, d.pcnt, d.grp_start, c->np, s);
   if (c->ns > 0) {
-    LAUNCH(c, MPM_K_SETUP, (k_balance<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d);
-    segment_order(c, (const int*)d.spar, (const int*)d.grp_start, c->ns, d.grp, s, c->sort_tmp);
+    LAUNCH(c, MPM_K_SETUP, (k_balance<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d, c->sort_tmp);
+    segment_order(c, (const int*)d.spar, (const int*)d.grp_start, c->ns, (const int*)c->sort_tmp, d.grp, s);
     cell_sort<D, R>(c, d, (const R*)d.bx_unsorted, c->ns, d.b_key, d.b_src, d.b_start, s, sort_res(c, d, false));
     LAUNCH(c, MPM_K_SETUP, (k_gather_balance<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d);
   }
