@@ -67,15 +67,12 @@ MPM_DEV void wave_run(int key, bool act, int& head, int& len) {
   }
 }
 
+// Cell key of point i at x (stored in key[i]) and its count in ccount, one atomic per run
+// of equal keys in the wave.  Every lane of the wave calls it (act: the lane has a point).
 template <int D, typename R>
-__global__ void k_cell_keys(const R* pos, int cnt, int n, int nt, R fn, int* key, int* ccount, int* status) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool act = i < cnt;
+MPM_DEV void cell_key_count(const R* x, bool act, int i, int n, int nt, R fn, int* key, int* ccount, int* status) {
   int k = 0;
   if (act) {
-    R x[D];
-#pragma unroll
-    for (int a = 0; a < D; ++a) x[a] = pos[(int64_t)a * cnt + i];
     int c[D]; R f[D]; bool bad = false;
     locate<D, R>(x, n, fn, c, f, &bad);
     if (bad) flag_status(status, ST_DOMAIN);
@@ -85,6 +82,16 @@ __global__ void k_cell_keys(const R* pos, int cnt, int n, int nt, R fn, int* key
   int head, len;
   wave_run(k, act, head, len);
   if (act && __lane_id() == head) atomicAdd(&ccount[k], len);
+}
+
+template <int D, typename R>
+__global__ void k_cell_keys(const R* pos, int cnt, int n, int nt, R fn, int* key, int* ccount, int* status) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool act = i < cnt;
+  R x[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) x[a] = act ? pos[(int64_t)a * cnt + i] : R(0);
+  cell_key_count<D, R>(x, act, i, n, nt, fn, key, ccount, status);
 }
 
 constexpr int kScanT = 256, kScanI = 16, kScanBlock = kScanT * kScanI;
@@ -499,21 +506,29 @@ __global__ void k_split_mass(Dev<R> d) {
   d.pcnt_orig[d.p_perm[k]] = c;
 }
 
-// Balance point b_r = s_r + 2 (x_p(r) - s_r) (eq. pbal), in sample order; group slots
-// (each group in atomic order, put in sample order by k_segment_order).
+// Balance point b_r = s_r + 2 (x_p(r) - s_r) (eq. pbal), in sample order, with its cell
+// key and count (the first step of its cell sort); group slots (each group in atomic
+// order, put in sample order by k_segment_order).
 template <int D, typename R>
 __global__ void k_balance(Dev<R> d, int* grp_unordered) {
-  int r = blockIdx.x * blockDim.x + threadIdx.x;
-  int S = d.ns, N = d.np;
-  if (r >= S) return;
-  int p = d.spar[r];
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int S = d.ns, N = d.np;
+  const bool act = r < S;
+  R b[D];
 #pragma unroll
-  for (int a = 0; a < D; ++a) {
-    R s = d.ss[a * S + r];
-    d.bx_unsorted[a * S + r] = s + R(2) * (d.px[a * N + p] - s);
+  for (int a = 0; a < D; ++a) b[a] = R(0);
+  if (act) {
+    const int p = d.spar[r];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const R s = d.ss[a * S + r];
+      b[a] = s + R(2) * (d.px[a * N + p] - s);
+      d.bx_unsorted[a * S + r] = b[a];
+    }
+    const int slot = d.grp_start[p] + atomicSub(&d.gcur[p], 1) - 1;
+    grp_unordered[slot] = r;
   }
-  int slot = d.grp_start[p] + atomicSub(&d.gcur[p], 1) - 1;
-  grp_unordered[slot] = r;
+  cell_key_count<D, R>(b, act, r, d.n, d.nt, d.fn, d.b_key, d.ccount, d.status);
 }
 
 template <int D, typename R>

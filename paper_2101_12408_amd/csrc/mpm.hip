@@ -323,10 +323,11 @@ void segment_order(mpm_ctx* c, const int* key, const int* start, int cnt, const 
 // Dense cell counts give the cell starts; an atomic scatter places the points, and each
 // cell's segment is then put in input order, so the result does not depend on the order
 // in which the atomics were served.
+// counted: keys and counts are already in key and r.ccount.
 template <int D, typename R>
 void cell_sort(mpm_ctx* c, Dev<R>& d, const R* pos, int cnt, int* key, int* perm, int* start, hipStream_t s,
-               const SortRes& r) {
-  if (cnt > 0)
+               const SortRes& r, bool counted = false) {
+  if (cnt > 0 && !counted)
     LAUNCH(c, MPM_K_SORT, (k_cell_keys<D, R>), dim3(cdiv(cnt, 256)), dim3(256), 0, s, pos, cnt, d.n, d.nt, d.fn, key,
            r.ccount, d.status);
   scan(c, r.ccount, start, d.nn, s, r.flags, r.epoch);
@@ -423,7 +424,8 @@ void do_p2g(mpm_ctx* c, const mpm_particles* P, const mpm_surface* S, hipStream_
   if (c->ns > 0) {
     LAUNCH(c, MPM_K_SETUP, (k_balance<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d, c->sort_tmp);
     segment_order(c, (const int*)d.spar, (const int*)d.grp_start, c->ns, (const int*)c->sort_tmp, d.grp, s);
-    cell_sort<D, R>(c, d, (const R*)d.bx_unsorted, c->ns, d.b_key, d.b_src, d.b_start, s, sort_res(c, d, false));
+    cell_sort<D, R>(c, d, (const R*)d.bx_unsorted, c->ns, d.b_key, d.b_src, d.b_start, s, sort_res(c, d, false),
+                    true);
     LAUNCH(c, MPM_K_SETUP, (k_gather_balance<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d);
   }
   // active cell tiles (hold points) on this stream, node tiles on the second
