@@ -1004,7 +1004,12 @@ MPM_DEV void p2g_group(const Dev<R>& d, const TileLists& tl, int ti, R* tpart, P
     __syncthreads();
     if (lane_on) {
       int lo = q0, hi = min(q0 + CH, ntot);
+      // pass 0: interior particles, 1: surface samples, 2: balance points.  Each type
+      // leaves some fields at zero (interior: E, ET and the Robin term; samples and balance
+      // points: W, WT and the Hessian diagonal), so the passes skip them.
+#pragma unroll
       for (int pass = 0; pass < NPASS; ++pass) {
+        const bool interior = pass == 0;
         int b0 = max(rb[pass], lo), b1 = min(re[pass], hi);
         for (int qq = b0; qq < b1; ++qq) {
           const R* P = &sm.x.pay[(qq - q0) * PS];
@@ -1032,30 +1037,43 @@ MPM_DEV void p2g_group(const Dev<R>& d, const TileLists& tl, int ti, R* tpart, P
                 for (int b = 0; b < D; ++b) s += Q[1 + D + a * D + b] * rel[b];
                 acc.v[k][FI::MV + a] += w * s;
               }
-              R sw = Z[1];
+              if (interior) {
+                R sw = Z[1];
 #pragma unroll
-              for (int a = 0; a < D; ++a) sw += bW[a] * rel[a];
-              acc.v[k][FI::W] += w * Z[0];
-              acc.v[k][FI::WT] += w * sw;
-              acc.v[k][FI::E] += w * Z[2];
-              acc.v[k][FI::ET] += w * Z[3];
+                for (int a = 0; a < D; ++a) sw += bW[a] * rel[a];
+                acc.v[k][FI::W] += w * Z[0];
+                acc.v[k][FI::WT] += w * sw;
+              } else {
+                acc.v[k][FI::E] += w * Z[2];
+                acc.v[k][FI::ET] += w * Z[3];
+              }
             }
           } else {
-            R wn[3], gn[3][D];
-            lane_nodes<D, R>(P + D, P + 4 * D, lk0, lk1, wn, gn);
             const R* H = P + 7 * D;
+            if (interior) {
+              R wn[3], gn[3][D];
+              lane_nodes<D, R>(P + D, P + 4 * D, lk0, lk1, wn, gn);
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-              const R* g = gn[k];
-              const R w = wn[k];
-              R g2 = 0;
+              for (int k = 0; k < 3; ++k) {
+                const R* g = gn[k];
+                const R w = wn[k];
+                R g2 = 0;
 #pragma unroll
-              for (int a = 0; a < D; ++a) g2 += g[a] * g[a];
+                for (int a = 0; a < D; ++a) g2 += g[a] * g[a];
 #pragma unroll
-              for (int a = 0; a < D; ++a)
-                acc.v[k][FI::DG - F0 + a] += H[0] * g[a] * g[a] + H[1] * (R(0.5) * g2 + R(0.5) * g[a] * g[a]);
-              acc.v[k][FI::HD - F0] += H[2] * g2 + H[3] * w * w;
-              acc.v[k][FI::HR - F0] += H[4] * w;
+                for (int a = 0; a < D; ++a)
+                  acc.v[k][FI::DG - F0 + a] += H[0] * g[a] * g[a] + H[1] * (R(0.5) * g2 + R(0.5) * g[a] * g[a]);
+                acc.v[k][FI::HD - F0] += H[2] * g2;
+                acc.v[k][FI::HR - F0] += H[4] * w;
+              }
+            } else {
+              R wn[3];
+              lane_weights<D, R>(P + D, lk0, lk1, wn);
+#pragma unroll
+              for (int k = 0; k < 3; ++k) {
+                acc.v[k][FI::HD - F0] += H[3] * wn[k] * wn[k];
+                acc.v[k][FI::HR - F0] += H[4] * wn[k];
+              }
             }
           }
         }
