@@ -190,7 +190,7 @@ constexpr int kRedGroupOff = 1 << 17;                  // max blocks of a reduci
 constexpr int kMaxRedGroups = kRedGroupOff / kRedGroup;
 constexpr int kCtrStride = 32;
 constexpr int kCtrSite = (1 + kMaxRedGroups) * kCtrStride;
-constexpr int kRedSh = 64;   // LDS doubles of a reducing block: NV values x waves (<= 16 waves, NV <= 4; or 4 waves, NV <= 16)
+constexpr int kRedSh = 64;   // LDS doubles of a block that reduces single values (grid_reduce needs NV <= kRedSh)
 
 MPM_DEV void publish(double* p, double v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 
@@ -219,43 +219,79 @@ MPM_DEV double block_sum_array(const double* part, int nb, double* sh) {
   return block_sum(v, sh);
 }
 
-// NV block sums at once (each lane's v[k]; results in thread 0's out[k]): wave shuffles
-// per value, then one exchange through LDS (sh must hold NV * waves doubles).  Fixed
-// order: lanes by shuffle tree, then waves in index order.
+// Lanes that sum one value in the transposed block sums below: the largest power of two
+// up to a wave with nv * L <= nt.
+MPM_DEV int red_lanes(int nv, int nt) {
+  int l = kWave;
+  while (l > 1 && nv * l > nt) l >>= 1;
+  return l;
+}
+
+// Shuffle tree over aligned groups of L lanes (L a power of two dividing the wave): the
+// first lane of each group gets the group's sum.  Every lane of the wave takes part.
+MPM_DEV double group_sum(double p, int L) {
+  for (int o = L / 2; o > 0; o >>= 1) p += __shfl_down(p, o, kWave);
+  return p;
+}
+
+// NV block sums at once (each thread's v[k]; results in thread 0's out[k]), transposed:
+// the values go to LDS (sh must hold NV * blockDim doubles), and value k is summed by the
+// L = red_lanes(NV, blockDim) lanes k L .. k L + L - 1, lane q over the entries q, q + L,
+// ... in index order, then by a shuffle tree over the L lanes.  The order is fixed.  All
+// values share one tree of log2(L) steps (one tree per value serializes on the LDS
+// counter).
 template <int NV>
 MPM_DEV void block_sum_n(const double* v, double* sh, double* out) {
-  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  const int nw = (blockDim.x + kWave - 1) / kWave;
-  double w[NV];
-#pragma unroll
-  for (int k = 0; k < NV; ++k) w[k] = wave_sum(v[k]);
+  const int nt = blockDim.x, t = threadIdx.x;
+  const int L = red_lanes(NV, nt);
   __syncthreads();
-  if (lane == 0) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) sh[wid * NV + k] = w[k];
-  }
+  for (int k = 0; k < NV; ++k) sh[k * nt + t] = v[k];
   __syncthreads();
-  if (threadIdx.x == 0) {
+  const int k = t / L, q = t % L;
+  double p = 0;
+  if (k < NV)
+    for (int i = q; i < nt; i += L) p += sh[k * nt + i];
+  p = group_sum(p, L);
+  __syncthreads();
+  if (k < NV && q == 0) sh[k] = p;
+  __syncthreads();
+  if (t == 0) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      double r = 0;
-      for (int q = 0; q < nw; ++q) r += sh[q * NV + k];
-      out[k] = r;
-    }
+    for (int j = 0; j < NV; ++j) out[j] = sh[j];
   }
 }
 
-// Sums of NV published arrays part[v * kRedSlot + (0..nb)] in fixed order (thread 0's out).
+// Sums of NV published arrays part[v * kRedSlot + (0..nb)] in fixed order (thread 0's
+// out), transposed as in block_sum_n, straight from the device-scope loads (sh must hold
+// NV doubles).
 template <int NV>
 MPM_DEV void block_sum_arrays(const double* part, int nb, double* sh, double* out) {
-  double v[NV];
+  constexpr int U = 4;   // loads in flight per lane
+  const int t = threadIdx.x, L = red_lanes(NV, blockDim.x);
+  const int k = t / L, q = t % L;
+  double p = 0;
+  if (k < NV) {
+    const double* src = part + (size_t)k * kRedSlot;
+    for (int i0 = q; i0 < nb; i0 += U * L) {
+      double x[U];
 #pragma unroll
-  for (int k = 0; k < NV; ++k) v[k] = 0;
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * L;
+        x[u] = i < nb ? __hip_atomic_load(src + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0;
+      }
 #pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] += __hip_atomic_load(part + (size_t)k * kRedSlot + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (int u = 0; u < U; ++u) p += x[u];
+    }
   }
-  block_sum_n<NV>(v, sh, out);
+  p = group_sum(p, L);
+  __syncthreads();
+  if (k < NV && q == 0) sh[k] = p;
+  __syncthreads();
+  if (t == 0) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) out[j] = sh[j];
+  }
 }
 
 // vals: the block's NV sums (read in thread 0).  Returns true in the one block that holds

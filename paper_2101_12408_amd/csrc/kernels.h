@@ -733,6 +733,15 @@ enum : int {
 
 MPM_DEV int elem_node(const int* tile_list, int e) { return tile_list[e >> 6] * kTileNodes + (e & 63); }
 
+// Most components of a node vector (D velocity components, or 1 temperature).  The node
+// kernels load all of a node's components before they store any: for the compiler a
+// store may alias a later load, which would otherwise wait for it.
+constexpr int kMaxComp = 3;
+
+// Threads of a block of the node kernels below (their multi-value block sums hold
+// NV x kNodeThreads doubles of LDS).
+constexpr int kNodeThreads = 256;
+
 // dst = sum over the active nodes of a . b (ncomp components), reduced in fixed order.
 template <typename R>
 __global__ void k_dot(const int* tl, int nelem, int nn, int ncomp, const R* a, const R* b, double* part,
@@ -798,24 +807,34 @@ template <typename R>
 __global__ void k_cg_start(const int* tl, int nelem, int nn, int ncomp, const R* b, R bscale, const R* Ax,
                            const R* diag, R* x, R* r, R* z, R* p, double* part, unsigned* ctr, CgScal* cs,
                            double tol2_host, const double* tol2_scale, int maxit, const double* gate) {
-  __shared__ double sh[kRedSh];
+  __shared__ double sh[2 * kNodeThreads];
   if (gate && *gate == 0.0) return;   // a speculative start that was called off
   double rz = 0, rr = 0;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nelem; e += gridDim.x * blockDim.x) {
     int node = elem_node(tl, e);
-    for (int c = 0; c < ncomp; ++c) {
-      int j = c * nn + node;
-      R rv = Ax ? bscale * b[j] - Ax[j] : bscale * b[j];
-      R zv = rv / diag[j];
+    R bv[kMaxComp], av[kMaxComp], dv[kMaxComp];
+#pragma unroll
+    for (int c = 0; c < kMaxComp; ++c) {
+      if (c >= ncomp) break;
+      const int j = c * nn + node;
+      bv[c] = b[j];
+      av[c] = Ax ? Ax[j] : R(0);
+      dv[c] = diag[j];
+    }
+#pragma unroll
+    for (int c = 0; c < kMaxComp; ++c) {
+      if (c >= ncomp) break;
+      const int j = c * nn + node;
+      R rv = Ax ? bscale * bv[c] - av[c] : bscale * bv[c];
+      R zv = rv / dv[c];
       if (!Ax) x[j] = 0;
       r[j] = rv; z[j] = zv; p[j] = zv;
       rz += (double)rv * (double)zv;
       rr += (double)rv * (double)rv;
     }
   }
-  double t[2], sum[2];
-  t[0] = block_sum(rz, sh);
-  t[1] = block_sum(rr, sh);
+  double v[2] = {rz, rr}, t[2], sum[2];
+  block_sum_n<2>(v, sh, t);
   if (grid_reduce<2>(t, part, ctr, sh, sum) && threadIdx.x == 0)
     cg_init(cs, sum[0], sum[1], tol2_host * (tol2_scale ? *tol2_scale : 1.0), maxit);
 }
@@ -824,31 +843,46 @@ __global__ void k_cg_start(const int* tl, int nelem, int nn, int ncomp, const R*
 // device from the trial's sums with the host's tests (the Armijo test at alpha = 1 with
 // its round-off allowance, then the stopping tests at the new iterate): writes 1 or 0 to
 // scal[go_slot], and the CG tolerance max(cg_rel |g|, 0.1 newton_tol |g0|)^2 of that
-// iteration to scal[tol_slot]; when it does not follow, the next CG's scalars are marked
-// done so that a CG queued for it returns at once.  from_start: the current iterate is
-// the start, whose values come from the start's sums at scal[g0_slot] instead of the
-// host's.  One thread.
-__global__ void k_newton_decide(double* scal, int dim, int gt_slot, int g0_slot, int from_start, double phi_h,
-                                double g0_h, double floor_h, double gcur_h, double c1, double eps8, int armijo,
-                                double newton_tol, double cg_rel, int mixed, double dx_over_dt, CgScal* next,
-                                int go_slot, int tol_slot) {
-  double phi = phi_h, g0 = g0_h, floor_abs = floor_h, gcur = gcur_h;
-  if (from_start) {
-    phi = scal[g0_slot];
-    g0 = sqrt(fmax(scal[g0_slot + dim + 2], 0.0));
-    floor_abs = 1e-14 * scal[g0_slot + 1 + dim] * dx_over_dt;
+// iteration to scal[tol_slot].  from_start: the current iterate is the start, whose
+// values come from the start's sums at scal[g0_slot] instead of the host's.
+// scal == nullptr: no decision.
+struct NewtonDecide {
+  double* scal;
+  int dim, gt_slot, g0_slot, from_start;
+  double phi_h, g0_h, floor_h, gcur_h, c1, eps8;
+  int armijo;
+  double newton_tol, cg_rel;
+  int mixed;
+  double dx_over_dt;
+  int go_slot, tol_slot;
+};
+
+MPM_DEV bool newton_decide(const NewtonDecide& a) {
+  double* scal = a.scal;
+  const int dim = a.dim;
+  double phi = a.phi_h, g0 = a.g0_h, floor_abs = a.floor_h, gcur = a.gcur_h;
+  if (a.from_start) {
+    phi = scal[a.g0_slot];
+    g0 = sqrt(fmax(scal[a.g0_slot + dim + 2], 0.0));
+    floor_abs = 1e-14 * scal[a.g0_slot + 1 + dim] * a.dx_over_dt;
     gcur = g0;
   }
-  const double phit = scal[gt_slot], slope = scal[gt_slot + dim + 3];
-  const double gn = sqrt(fmax(scal[gt_slot + dim + 2], 0.0));
-  const bool start_ok = g0 == g0 && phi == phi && !(g0 <= fmax(newton_tol * g0, floor_abs));
-  const bool accept = !armijo || phit <= phi + c1 * slope + eps8 * fmax(fabs(phi), fabs(phit));
-  const bool go = start_ok && accept && gn == gn && phit == phit && !(gn <= fmax(newton_tol * g0, floor_abs)) &&
-                  !(mixed && gn <= 1e-4 * g0 && gn > 0.5 * gcur);
-  const double t = fmax(cg_rel * gn, 0.1 * newton_tol * g0);
-  scal[go_slot] = go ? 1.0 : 0.0;
-  scal[tol_slot] = t * t;
-  if (!go) next->done = 1;
+  const double phit = scal[a.gt_slot], slope = scal[a.gt_slot + dim + 3];
+  const double gn = sqrt(fmax(scal[a.gt_slot + dim + 2], 0.0));
+  const bool start_ok = g0 == g0 && phi == phi && !(g0 <= fmax(a.newton_tol * g0, floor_abs));
+  const bool accept = !a.armijo || phit <= phi + a.c1 * slope + a.eps8 * fmax(fabs(phi), fabs(phit));
+  const bool go = start_ok && accept && gn == gn && phit == phit && !(gn <= fmax(a.newton_tol * g0, floor_abs)) &&
+                  !(a.mixed && gn <= 1e-4 * g0 && gn > 0.5 * gcur);
+  const double t = fmax(a.cg_rel * gn, 0.1 * a.newton_tol * g0);
+  scal[a.go_slot] = go ? 1.0 : 0.0;
+  scal[a.tol_slot] = t * t;
+  return go;
+}
+
+// The decision alone (one thread); when the iteration does not follow, the next CG's
+// scalars are marked done so that a CG queued for it returns at once.
+__global__ void k_newton_decide(NewtonDecide a, CgScal* next) {
+  if (!newton_decide(a)) next->done = 1;
 }
 
 // Called by the last block of the operator's merge with the sum p . A p.
@@ -862,25 +896,33 @@ MPM_DEV void cg_set_alpha(CgScal* s, double pAp) {
 template <typename R>
 __global__ void k_cg_update(const int* tl, int nelem, int nn, int ncomp, CgScal* s, R* x, R* r, R* z,
                             const R* p, const R* Ap, const R* diag, double* part, unsigned* ctr) {
-  __shared__ double sh[kRedSh];
+  __shared__ double sh[2 * kNodeThreads];
   if (s->done) return;
   R alpha = (R)s->alpha;
   double rz = 0, rr = 0;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nelem; e += gridDim.x * blockDim.x) {
     int node = elem_node(tl, e);
-    for (int c = 0; c < ncomp; ++c) {
-      int j = c * nn + node;
-      x[j] += alpha * p[j];
-      R rv = r[j] - alpha * Ap[j];
-      R zv = rv / diag[j];
+    R xv[kMaxComp], pv[kMaxComp], rv0[kMaxComp], av[kMaxComp], dv[kMaxComp];
+#pragma unroll
+    for (int c = 0; c < kMaxComp; ++c) {
+      if (c >= ncomp) break;
+      const int j = c * nn + node;
+      xv[c] = x[j]; pv[c] = p[j]; rv0[c] = r[j]; av[c] = Ap[j]; dv[c] = diag[j];
+    }
+#pragma unroll
+    for (int c = 0; c < kMaxComp; ++c) {
+      if (c >= ncomp) break;
+      const int j = c * nn + node;
+      x[j] = xv[c] + alpha * pv[c];
+      R rv = rv0[c] - alpha * av[c];
+      R zv = rv / dv[c];
       r[j] = rv; z[j] = zv;
       rz += (double)rv * (double)zv;
       rr += (double)rv * (double)rv;
     }
   }
-  double t[2], sum[2];
-  t[0] = block_sum(rz, sh);
-  t[1] = block_sum(rr, sh);
+  double v[2] = {rz, rr}, t[2], sum[2];
+  block_sum_n<2>(v, sh, t);
   if (grid_reduce<2>(t, part, ctr, sh, sum)) {
     const double rz_new = sum[0], rrs = sum[1];
     if (threadIdx.x == 0) {
@@ -909,7 +951,13 @@ __global__ void k_axpy_to(const int* tl, int nelem, int nn, int ncomp, const R* 
                           R* y) {
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nelem; e += gridDim.x * blockDim.x) {
     int node = elem_node(tl, e);
-    for (int c = 0; c < ncomp; ++c) y[c * nn + node] = a[c * nn + node] + (R)sh * b[c * nn + node];
+    R av[kMaxComp], bv[kMaxComp];
+#pragma unroll
+    for (int c = 0; c < kMaxComp; ++c)
+      if (c < ncomp) { av[c] = a[c * nn + node]; bv[c] = b[c * nn + node]; }
+#pragma unroll
+    for (int c = 0; c < kMaxComp; ++c)
+      if (c < ncomp) y[c * nn + node] = av[c] + (R)sh * bv[c];
   }
 }
 
@@ -920,7 +968,13 @@ __global__ void k_project_copy(const int* tl, int nelem, int nn, int ncomp, cons
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nelem; e += gridDim.x * blockDim.x) {
     int node = elem_node(tl, e);
     uint8_t f = fr[node];
-    for (int c = 0; c < ncomp; ++c) y[c * nn + node] = ((f >> c) & 1) ? a[c * nn + node] : R(0);
+    R av[kMaxComp];
+#pragma unroll
+    for (int c = 0; c < kMaxComp; ++c)
+      if (c < ncomp) av[c] = a[c * nn + node];
+#pragma unroll
+    for (int c = 0; c < kMaxComp; ++c)
+      if (c < ncomp) y[c * nn + node] = ((f >> c) & 1) ? av[c] : R(0);
   }
 }
 
@@ -937,7 +991,7 @@ __global__ void k_neg(const int* tl, int nelem, int nn, int ncomp, const R* a, R
 template <int D, typename R>
 __global__ void k_mom_sums(const int* tl, int nelem, int nn, const uint8_t* fr, const R* m, const R* vh,
                            const R* vn, double* part, unsigned* ctr, double* dst) {
-  __shared__ double sh[kRedSh];
+  __shared__ double sh[(2 * D + 1) * kNodeThreads];
   double s[2 * D + 1];
   for (int k = 0; k < 2 * D + 1; ++k) s[k] = 0;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nelem; e += gridDim.x * blockDim.x) {
@@ -956,36 +1010,99 @@ __global__ void k_mom_sums(const int* tl, int nelem, int nn, const uint8_t* fr, 
     for (int k = 0; k < 2 * D + 1; ++k) dst[k] = r[k];
 }
 
+// The start of the next Newton iteration's CG, fused into the translation correction of
+// the trial that precedes it: r = -g at the corrected trial point, z = r / diag, p = z,
+// x = 0 (the start of a CG for the right side -g, as k_cg_start forms it), and its
+// scalars with the tolerance of the device's Newton decision, marked done when the
+// iteration does not follow.  x == nullptr: none.
+template <typename R>
+struct NextCgStart {
+  R* x;
+  R* r;
+  R* z;
+  R* p;
+  const R* diag;
+  CgScal* cs;
+  int maxit;
+};
+
 // Exact minimization of Phi along rigid translations: v^ -= c on nodes with mass,
 // c_a = [sum m (v^ - v^n) - dt g_a sum m] / sum m.  e and D are translation invariant, so
 // the projected gradient moves by exactly -m c; the grid sum of |grad|^2 after the move
-// goes to *gn2.
+// goes to *gn2.  skip (a constrained component; uniform in the grid): no correction, and
+// *gn2 keeps the merge's sum.  Also forms, in the same pass and with the same per-node
+// arithmetic and summation order as k_mom_sums, the momentum sums of the (corrected)
+// point into mom[0..2D], and the next CG's start (nx) after the Newton decision (nd).
 template <int D, typename R>
 __global__ void k_mom_fix(const int* tl, int nelem, int nn, const uint8_t* fr, const R* m, const double* red,
                           double dt, double g0, double g1, double g2, R* vh, R* grad, double* part, unsigned* ctr,
-                          double* gn2, const int* skip) {
-  __shared__ double sh[kRedSh];
-  if (*skip) return;   // a constrained component: no translation correction (uniform in the grid)
+                          double* gn2, const int* skip, const R* vn, double* mom, NextCgStart<R> nx,
+                          NewtonDecide nd) {
+  constexpr int NV = 2 * D + 4;   // |g|^2, r.z, r.r, momentum sums
+  __shared__ double sh[NV * kNodeThreads];
+  const bool fix = !*skip;
   double msum = red[D];
   double gg[3] = {g0, g1, g2};
   R c[D];
-  for (int a = 0; a < D; ++a) c[a] = (R)((red[a] - dt * gg[a] * msum) / msum);
-  double s = 0;
+  for (int a = 0; a < D; ++a) c[a] = fix ? (R)((red[a] - dt * gg[a] * msum) / msum) : R(0);
+  double v[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = 0;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nelem; e += gridDim.x * blockDim.x) {
     int node = elem_node(tl, e);
-    uint8_t f = fr[node];
+    // every load of the node first: the stores below may alias them for the compiler
+    const uint8_t f = fr[node];
+    const bool dof = f & 0x80;
+    const R mn = m[node];
+    R vv[D], gv[D], vnv[D], dg[D];
+#pragma unroll
     for (int a = 0; a < D; ++a) {
-      R gv = grad[a * nn + node];
-      if (f & 0x80) {
-        vh[a * nn + node] -= c[a];
-        gv -= m[node] * c[a];
-        grad[a * nn + node] = gv;
+      const int j = a * nn + node;
+      gv[a] = grad[j];
+      vv[a] = vh[j];
+      vnv[a] = vn[j];
+      dg[a] = nx.x ? nx.diag[j] : R(1);
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const int j = a * nn + node;
+      if (fix && dof) {
+        vv[a] -= c[a];
+        vh[j] = vv[a];
+        gv[a] -= mn * c[a];
+        grad[j] = gv[a];
       }
-      s += (double)gv * (double)gv;
+      v[0] += (double)gv[a] * (double)gv[a];
+      if (nx.x) {
+        R rv = R(-1) * gv[a];
+        R zv = rv / dg[a];
+        nx.x[j] = 0;
+        nx.r[j] = rv; nx.z[j] = zv; nx.p[j] = zv;
+        v[1] += (double)rv * (double)zv;
+        v[2] += (double)rv * (double)rv;
+      }
+    }
+    if (dof) {
+      double mm = mn;
+      v[3 + D] += mm;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        v[3 + a] += mm * ((double)vv[a] - (double)vnv[a]);
+        v[3 + D + 1 + a] += mm * (double)vv[a];
+      }
     }
   }
-  double t = block_sum(s, sh), r;
-  if (grid_reduce<1>(&t, part, ctr, sh, &r) && threadIdx.x == 0) *gn2 = r;
+  double t[NV], r[NV];
+  block_sum_n<NV>(v, sh, t);
+  if (grid_reduce<NV>(t, part, ctr, sh, r) && threadIdx.x == 0) {
+    if (fix) *gn2 = r[0];
+    for (int k = 0; k < 2 * D + 1; ++k) mom[k] = r[3 + k];
+    if (nx.x) {
+      const bool go = nd.scal ? newton_decide(nd) : true;
+      cg_init(nx.cs, r[1], r[2], nd.scal ? nd.scal[nd.tol_slot] : 0.0, nx.maxit);
+      if (!go) nx.cs->done = 1;
+    }
+  }
 }
 
 // Explicit update (q^ = 0): v^ = P[v^n - f/m + dt g] with f = dPsi/dv^ evaluated by the

@@ -17,7 +17,7 @@ using namespace mpm;
 
 namespace {
 
-constexpr int kNumParts = 20;   // partial-sum slots: momentum 0..12 (gradient merge: 2D+3 from slot 4), heat 16..19
+constexpr int kNumParts = 20;   // partial-sum slots: momentum 0..15 (merge: D+4 from slot 4; correction: 2D+4 from 0), heat 16..19
 constexpr int kScalDoubles = 64;
 // Device scalars the host reads back, in one block so that every read is one copy:
 // [0, 512) FP64 scalar slots, [512, 672) the two CG scalar sets, [768, 1024) status words.
@@ -351,7 +351,7 @@ TileLists tiles(mpm_ctx* c) {
   return t;
 }
 
-int krylov_blocks(int nelem) { return std::max(1, std::min(1024, cdiv(nelem, 256))); }
+int krylov_blocks(int nelem) { return std::max(1, std::min(1024, cdiv(nelem, kNodeThreads))); }
 int merge_blocks(const mpm_ctx* c) { return cdiv(c->ntiles, kMergeTiles); }
 
 void sync_read(mpm_ctx* c, hipStream_t s, const void* src, void* dst, size_t bytes) {
@@ -479,7 +479,7 @@ void do_p2g(mpm_ctx* c, const mpm_particles* P, const mpm_surface* S, hipStream_
 // SC_G0 / SC_GT: the gradient merge's sums (see k_merge_stress) at the iterate and at the
 // line-search trial: [0] Phi, [1..D] sum m (v^ - v^n), [D+1] sum m, [D+2] |g|^2, [D+3]
 // the trial's slope g . delta.
-// SC_GO / SC_TOL2: the device's decision on the next Newton iteration (k_newton_decide).
+// SC_GO / SC_TOL2: the device's decision on the next Newton iteration (newton_decide).
 enum : int { SC_DOT = 1, SC_RHS2 = 5, SC_MOM = 8, SC_G0 = 16, SC_GT = 32, SC_GO = 40, SC_TOL2 = 41, SC_N = 48 };
 
 // Phi(u), the momentum sums and |g|^2 into scal[red_slot ..] (Phi also into energy_dev if
@@ -594,7 +594,7 @@ template <int D, typename R>
 void mom_sums_async(mpm_ctx* c, const R* vh, hipStream_t s) {
   Dev<R>& d = dev<R>(c);
   int nelem = c->ntiles * 64, nb = krylov_blocks(nelem);
-  LAUNCH(c, MPM_K_BLAS, (k_mom_sums<D, R>), dim3(nb), dim3(256), 0, s, (const int*)d.tile_list, nelem, d.nn,
+  LAUNCH(c, MPM_K_BLAS, (k_mom_sums<D, R>), dim3(nb), dim3(kNodeThreads), 0, s, (const int*)d.tile_list, nelem, d.nn,
          (const uint8_t*)d.gfree, (const R*)d.gm, vh, (const R*)d.gvn, c->part, c->ctr + (size_t)CTR_MOM * kCtrSite, c->scal + SC_MOM);
 }
 
@@ -686,7 +686,7 @@ void cg_iterate(mpm_ctx* c, const KrySet& k, Apply&& apply, R* x, const R* diag,
   // first, which leaves p = z from the start)
   for (int j = 0; j < n; ++j) {
     apply(p, Ap, done, k.cg, PUpd<R>{p, z, k.cg});
-    LAUNCH(c, MPM_K_BLAS, k_cg_update<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, k.cg, x, r, z,
+    LAUNCH(c, MPM_K_BLAS, k_cg_update<R>, dim3(nb), dim3(kNodeThreads), 0, s, tl, nelem, d.nn, ncomp, k.cg, x, r, z,
            (const R*)p, (const R*)Ap, diag, k.part, k.ctr_upd);
   }
   run.launched += n;
@@ -700,7 +700,7 @@ void cg_begin(mpm_ctx* c, const KrySet& k, Apply&& apply, const R* b, double bsc
   int nelem = c->ntiles * 64, nb = krylov_blocks(nelem);
   const int* tl = d.tile_list;
   if (x0_given) apply(x, Ap, (const int*)nullptr, (CgScal*)nullptr, PUpd<R>{});
-  LAUNCH(c, MPM_K_BLAS, k_cg_start<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, ncomp, b, (R)bscale,
+  LAUNCH(c, MPM_K_BLAS, k_cg_start<R>, dim3(nb), dim3(kNodeThreads), 0, s, tl, nelem, d.nn, ncomp, b, (R)bscale,
          x0_given ? (const R*)Ap : (const R*)nullptr, diag, x, r, z, p, k.part, k.ctr_start, k.cg, tol2_host,
          tol2_scale, maxit, gate);
   run = CgRun{};
@@ -798,6 +798,7 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
   int it = 0;
   double gn_prev = 1e300;
   bool have_next = false;   // this iteration's CG start and first chunk are already queued
+  bool mom_formed = false;  // the momentum sums of v^ are in place (formed with its correction)
   CgRun next_run;
   for (; it < p.newton_max; ++it) {
     if (it > 0) {
@@ -841,40 +842,55 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
     // A trial that is rejected is overwritten by the next one, so the correction applied
     // speculatively is harmless.
     double alpha = 1.0;
-    auto trial_launch = [&](double a) {
-      do_energy_grad<D, R>(c, (const R*)delta, (R*)c->gscratch, nullptr, SC_GT, s,
-                           PUpd<R>{vtrial, (const R*)vhat, nullptr, (R)a}, (const R*)g,
-                           (d.term_mask & 2) ? (R*)c->sF_alt : nullptr);
-      if (p.momentum_fix)
-        LAUNCH(c, MPM_K_BLAS, (k_mom_fix<D, R>), dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, (const uint8_t*)d.gfree,
-               (const R*)d.gm, (const double*)(c->scal + SC_GT + 1), p.dt, p.gravity[0], p.gravity[1], p.gravity[2],
-               vtrial, (R*)c->gscratch, c->part, c->ctr + (size_t)CTR_MOM * kCtrSite, c->scal + SC_GT + D + 2,
-               (const int*)(c->misc + 1));
-      st.energy_evals++;
-    };
-    trial_launch(alpha);
     // The next iteration's CG start and first iteration (other vector set) are queued
     // behind the read, on the guess that the full step is accepted and the solve goes on:
     // the right side is the trial's gradient and the Hessian the trial's surface
     // linearization.  They keep the GPU busy while the host decides.  The device decides
-    // with the host's tests whether they run (k_newton_decide); the host uses them only
+    // with the host's tests whether they run (newton_decide); the host uses them only
     // when its own decision agrees and the trial stands as queued, else it starts the CG
-    // afresh.
+    // afresh.  With the translation correction, the decision and the CG start are formed
+    // by the correction's kernel.
     const bool spec = it + 1 < p.newton_max;
-    if (spec)
-      LAUNCH(c, MPM_K_BLAS, k_newton_decide, dim3(1), dim3(1), 0, s, c->scal, D, (int)SC_GT, (int)SC_G0,
-             it == 0 ? 1 : 0, phi, g0, floor_abs, gn, p.ls_c1, 8.0 * eps, p.ls_max > 1 ? 1 : 0, p.newton_tol, p.cg_rel,
-             sizeof(R) == 4 ? 1 : 0, p.dx / p.dt, kry_momentum(c, set ^ 1).cg, (int)SC_GO, (int)SC_TOL2);
+    R* const* nv = cgv[set ^ 1];
+    const NewtonDecide nd{c->scal, D, (int)SC_GT, (int)SC_G0, it == 0 ? 1 : 0, phi, g0, floor_abs, gn, p.ls_c1,
+                          8.0 * eps, p.ls_max > 1 ? 1 : 0, p.newton_tol, p.cg_rel, sizeof(R) == 4 ? 1 : 0,
+                          p.dx / p.dt, (int)SC_GO, (int)SC_TOL2};
+    auto trial_launch = [&](double a, bool first) {
+      do_energy_grad<D, R>(c, (const R*)delta, (R*)c->gscratch, nullptr, SC_GT, s,
+                           PUpd<R>{vtrial, (const R*)vhat, nullptr, (R)a}, (const R*)g,
+                           (d.term_mask & 2) ? (R*)c->sF_alt : nullptr);
+      if (p.momentum_fix) {
+        const bool fuse = first && spec;
+        LAUNCH(c, MPM_K_BLAS, (k_mom_fix<D, R>), dim3(nb), dim3(kNodeThreads), 0, s, tl, nelem, d.nn, (const uint8_t*)d.gfree,
+               (const R*)d.gm, (const double*)(c->scal + SC_GT + 1), p.dt, p.gravity[0], p.gravity[1], p.gravity[2],
+               vtrial, (R*)c->gscratch, c->part, c->ctr + (size_t)CTR_MOM * kCtrSite, c->scal + SC_GT + D + 2,
+               (const int*)(c->misc + 1), (const R*)d.gvn, c->scal + SC_MOM,
+               fuse ? NextCgStart<R>{nv[0], nv[1], nv[2], nv[3], (const R*)d.gdiag, kry_momentum(c, set ^ 1).cg,
+                                     p.cg_max}
+                    : NextCgStart<R>{},
+               fuse ? nd : NewtonDecide{});
+      }
+      st.energy_evals++;
+    };
+    trial_launch(alpha, true);
+    if (spec && !p.momentum_fix)
+      LAUNCH(c, MPM_K_BLAS, k_newton_decide, dim3(1), dim3(1), 0, s, nd, kry_momentum(c, set ^ 1).cg);
     mirror_copy(c, s);
     if (spec) {
-      R* const* nv = cgv[set ^ 1];
       R* f_next = (d.term_mask & 2) ? (R*)c->sF_alt : nullptr;
       auto apply_next = [&](const R* pv, R* Apv, const int* done, CgScal* cg, PUpd<R> pu) {
         do_hessvec<D, R>(c, pv, 1.0, Apv, false, done, cg, s, pu, f_next);
       };
-      cg_begin<R>(c, kry_momentum(c, set ^ 1), apply_next, (const R*)c->gscratch, -1.0, nv[0], false,
-                  (const R*)d.gdiag, nv[1], nv[2], nv[3], nv[4], D, 1.0, c->scal + SC_TOL2, p.cg_max, s, next_run,
-                  1, c->scal + SC_GO);
+      if (p.momentum_fix) {
+        next_run = CgRun{};
+        next_run.chunk = 1;
+        cg_iterate<R>(c, kry_momentum(c, set ^ 1), apply_next, nv[0], (const R*)d.gdiag, nv[1], nv[2], nv[3], nv[4],
+                      D, 1, s, next_run);
+      } else {
+        cg_begin<R>(c, kry_momentum(c, set ^ 1), apply_next, (const R*)c->gscratch, -1.0, nv[0], false,
+                    (const R*)d.gdiag, nv[1], nv[2], nv[3], nv[4], D, 1.0, c->scal + SC_TOL2, p.cg_max, s, next_run,
+                    1, c->scal + SC_GO);
+      }
     }
     mirror_wait(c);
     const bool dev_go = c->hbuf[SC_GO] != 0.0;
@@ -887,7 +903,7 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
     bool stands = true;   // the trial read above is the one accepted, at alpha = 1
     if (cg_finish<R>(c, km, apply, delta, (const R*)d.gdiag, cr, cz, cp, cAp, D, p.cg_max, s, run)) {
       // the guess failed: the trial used an unfinished delta
-      trial_launch(alpha);
+      trial_launch(alpha, false);
       read_mirror(c, s);
       stands = false;
     }
@@ -904,13 +920,15 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
       if (phit <= phi + p.ls_c1 * alpha * slope + noise) break;
       alpha *= 0.5;
       st.line_search_halvings++;
-      trial_launch(alpha);
+      trial_launch(alpha, false);
       read_mirror(c, s);
       phit = c->hbuf[SC_GT];
       stands = false;
     }
     have_next = spec && dev_go && stands;
-    // accept the last trial: its (corrected) point and gradient become the iterate
+    // accept the last trial: its (corrected) point and gradient become the iterate; its
+    // momentum sums, when the correction's kernel formed them, are the solve's
+    mom_formed = p.momentum_fix;
     std::swap(c->vhat, c->vtrial);
     {
       R* f_acc = (R*)c->sF_alt;
@@ -941,7 +959,7 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
   st.phi = phi;
   if (!st.converged && !(c->status & ST_NONFINITE)) c->status |= ST_NOCONV;
   // grid momentum after the solve (read with the next status query)
-  mom_sums_async<D, R>(c, (const R*)vhat, s);
+  if (!mom_formed) mom_sums_async<D, R>(c, (const R*)vhat, s);
   c->mom_pending = true;
 }
 

@@ -1283,7 +1283,7 @@ __global__ void __launch_bounds__(64 * kMergeTiles) k_merge_stress(
     CgScal* cg, PUpd<R> pu, const R* slope_g) {
   constexpr int RN = TileGeo<D>::RN;
   constexpr int NV = D + 4;
-  __shared__ double sh[kRedSh];
+  __shared__ double sh[NV * 64 * kMergeTiles];
   if (done && *done) return;
   const int ti = blockIdx.x * kMergeTiles + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -1316,18 +1316,27 @@ __global__ void __launch_bounds__(64 * kMergeTiles) k_merge_stress(
     const bool dof = fr & 0x80;
     if (dof && mode == NM_GRAD) vals[D + 1] = (double)m;
     const R beta = pu.beta();
+    // the node's loads before its stores (a store may alias a later load for the compiler)
+    R uv[D], sgv[D], zv[D], vnv[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      uv[a] = u ? u[a * nn + node] : R(0);
+      sgv[a] = slope_g ? slope_g[a * nn + node] : R(0);
+      zv[a] = pu.z ? pu.z[a * nn + node] : R(0);
+      vnv[a] = mode == NM_GRAD ? d.gvn[a * nn + node] : R(0);
+    }
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       bool fa = (fr >> a) & 1;
-      R ua = u ? u[a * nn + node] : R(0);
-      if (slope_g) vals[D + 3] += (double)slope_g[a * nn + node] * (double)ua;
+      R ua = uv[a];
+      if (slope_g) vals[D + 3] += (double)sgv[a] * (double)ua;
       if (pu.z) {
-        ua = cg_dir(pu.z[a * nn + node], beta, ua);
+        ua = cg_dir(zv[a], beta, ua);
         pu.p[a * nn + node] = ua;
       }
       R o;
       if (mode == NM_GRAD) {
-        R vn = d.gvn[a * nn + node];
+        R vn = vnv[a];
         o = acc[a] + m * (ua - vn) - d.dt * m * d.grav[a];
         if (dof) {
           double dv = (double)ua - (double)vn;
@@ -1389,11 +1398,12 @@ __global__ void __launch_bounds__(64 * kMergeTiles) k_merge_heat(Dev<R> d, TileL
     for (int j = 0; j < (1 << D); ++j) acc += val[j];
     bool dof = d.gfree[node] & 0x80;
     R Ti = T[node];
+    const R mn = d.gm[node];   // loaded before the store below, which may alias it for the compiler
     if (pu.z) {
       Ti = cg_dir(pu.z[node], pu.beta(), Ti);
       pu.p[node] = Ti;
     }
-    R o = dof ? d.cp / d.dt * d.gm[node] * Ti + acc : R(0);
+    R o = dof ? d.cp / d.dt * mn * Ti + acc : R(0);
     out[node] = o;
     if (dof) dotv = (double)Ti * (double)o;
   }
