@@ -191,8 +191,8 @@ size_t layout(mpm_ctx* c, char* base) {
   d.ccount = b.take<int>(NN);
   d.tile_flag = b.take<int>(NT); d.tile_list = b.take<int>(NT);
   int* tile_pos = b.take<int>(NT + 1);
-  int* ctile_flag = b.take<int>(NT);
-  int* ctile_pos = b.take<int>(NT + 1);
+  int* ctile_flag = b.take<int>(2 * NT);
+  int* ctile_pos = b.take<int>(2 * NT + 1);
   int* ctile_list = b.take<int>(NT);
   int* ctile_slot = b.take<int>(NT);
   int* ctile_rng = b.take<int>(6 * NT);
@@ -435,18 +435,18 @@ void do_p2g(mpm_ctx* c, const mpm_particles* P, const mpm_surface* S, hipStream_
   HIPCHK(hipEventRecord(c->ev_sjoin, c->aux));
   LAUNCH(c, MPM_K_SETUP, (k_flag_ctiles<D, R>), dim3(cdiv(c->ntile_total, 256)), dim3(256), 0, s, d, c->ctile_flag,
          c->ntile_total);
-  scan(c, c->ctile_flag, c->ctile_pos, c->ntile_total, s);
+  scan(c, c->ctile_flag, c->ctile_pos, 2 * c->ntile_total, s);
   LAUNCH(c, MPM_K_SETUP, (k_ctile_slots<R>), dim3(cdiv(c->ntile_total, 256)), dim3(256), 0, s, d,
          (const int*)c->ctile_flag, (const int*)c->ctile_pos, c->ntile_total, c->ctile_list, c->ctile_slot,
          c->ctile_rng);
-  HIPCHK(hipMemcpyAsync(c->hint + 1, c->ctile_pos + c->ntile_total, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(c->hint + 1, c->ctile_pos + 2 * c->ntile_total, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamWaitEvent(s, c->ev_sjoin, 0));
   if (!c->ev_counts) HIPCHK(hipEventCreateWithFlags(&c->ev_counts, hipEventDisableTiming));
   HIPCHK(hipEventRecord(c->ev_counts, s));
   // A2: the cell-tile scatter goes out before the host has the tile counts, sized by the
   // previous step's count (the kernel reads the true count); the host waits for the
   // counts while it runs and covers any further tiles with a second launch
-  const int* nct_dev = c->ctile_pos + c->ntile_total;
+  const int* nct_dev = c->ctile_pos + 2 * c->ntile_total;
   const int est = (int)std::min<int64_t>(c->ntile_total, c->prev_nctile + c->prev_nctile / 8 + 64);
   LAUNCH(c, MPM_K_P2G, (k_tile_p2g<D, R>), dim3(cdiv(est, 8) * 16), dim3(TileGeo<D>::NT), 0, s, d, tiles(c),
          (R*)c->tpart, nct_dev, 0);

@@ -1468,23 +1468,34 @@ __global__ void __launch_bounds__(64) k_merge_p2g(Dev<R> d, TileLists tl, const 
   d.hrhs[node] = dof ? cm * Tn + v[FI::HR] : R(0);
 }
 
-// Active cell tiles: tiles holding any point.
+// Active cell tiles (tiles holding any point), in two classes: flag[t] marks the tiles
+// with surface samples, flag[ntile + t] the others.  One scan of the 2 ntile flags then
+// numbers the tiles with samples first.  Workgroups of the tile kernels start in slot
+// order, and the tiles with samples are the costly ones (their samples take the surface
+// terms), so this order leaves the cheap tiles to fill the end of a launch.
 template <int D, typename R>
 __global__ void k_flag_ctiles(Dev<R> d, int* flag, int ntile) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= ntile) return;
   int cb = t * 64;
   int cnt = d.p_start[cb + 64] - d.p_start[cb];
-  if (d.ns) cnt += (d.s_start[cb + 64] - d.s_start[cb]) + (d.b_start[cb + 64] - d.b_start[cb]);
-  flag[t] = cnt > 0;
+  int ns = 0;
+  if (d.ns) {
+    ns = d.s_start[cb + 64] - d.s_start[cb];
+    cnt += ns + (d.b_start[cb + 64] - d.b_start[cb]);
+  }
+  flag[t] = cnt > 0 && ns > 0;
+  flag[ntile + t] = cnt > 0 && ns == 0;
 }
 
+// Slots of the active tiles from the scan of k_flag_ctiles' flags (pos over 2 ntile + 1).
 template <typename R>
 __global__ void k_ctile_slots(Dev<R> d, const int* flag, const int* pos, int ntile, int* list, int* slot, int* rng) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= ntile) return;
-  if (flag[t]) {
-    int s = pos[t], cb = t * 64;
+  const bool first = flag[t];
+  if (first || flag[ntile + t]) {
+    int s = first ? pos[t] : pos[ntile + t], cb = t * 64;
     list[s] = t;
     slot[t] = s;
     int* r = rng + 6 * s;
