@@ -93,6 +93,7 @@ struct mpm_ctx {
   int* ctile_list = nullptr;
   int* ctile_slot = nullptr;
   int* ctile_rng = nullptr;
+  int* nbr_slot = nullptr;
   void* tpart = nullptr;        // per-cell-tile region partials
   void* tpart_heat = nullptr;   // the heat operator's (separate: it may run concurrently)
   int nctile = 0;
@@ -196,6 +197,7 @@ size_t layout(mpm_ctx* c, char* base) {
   int* ctile_list = b.take<int>(NT);
   int* ctile_slot = b.take<int>(NT);
   int* ctile_rng = b.take<int>(6 * NT);
+  int* nbr_slot = b.take<int>((size_t)kNbr * NT);
   const int64_t nct_cap = std::min<int64_t>(NT, NP + 2 * NS);
   const int RNd = D == 3 ? TileGeo<3>::RN : TileGeo<2>::RN;
   const int NFmax = std::max(2 * D + 7, D);
@@ -240,6 +242,7 @@ size_t layout(mpm_ctx* c, char* base) {
     c->tile_pos = tile_pos; c->scan_flags = scan_flags; c->misc = misc;
     c->ctile_flag = ctile_flag; c->ctile_pos = ctile_pos; c->ctile_list = ctile_list; c->ctile_slot = ctile_slot;
     c->ctile_rng = ctile_rng;
+    c->nbr_slot = nbr_slot;
     c->tpart = tpart;
     c->tpart_heat = tpart_heat;
     c->part = d.part; c->scal = d.scal; c->cg = cg; c->ctr = ctr;
@@ -347,6 +350,7 @@ TileLists tiles(mpm_ctx* c) {
   t.ctile_list = c->ctile_list;
   t.ctile_slot = c->ctile_slot;
   t.ctile_rng = c->ctile_rng;
+  t.nbr = c->nbr_slot;
   t.nctile = c->nctile;
   return t;
 }
@@ -461,7 +465,8 @@ void do_p2g(mpm_ctx* c, const mpm_particles* P, const mpm_surface* S, hipStream_
   // A2/A3: node merge of the scatter and grid set-up
   TileLists tl = tiles(c);
   if (c->ntiles > 0)
-    LAUNCH(c, MPM_K_P2G_NODE, (k_merge_p2g<D, R>), dim3(c->ntiles), dim3(64), 0, s, d, tl, (const R*)c->tpart);
+    LAUNCH(c, MPM_K_P2G_NODE, (k_merge_p2g<D, R>), dim3(c->ntiles), dim3(64), 0, s, d, tl, (const R*)c->tpart,
+           c->nbr_slot);
   if (c->ns > 0) LAUNCH(c, MPM_K_SETUP, (k_surface_k<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d);
   // degrees of freedom and whether any of them has a fixed component
   if (c->ntiles > 0)

@@ -49,8 +49,11 @@ struct TileLists {
   const int* ctile_list;   // active cell tiles (compact)
   const int* ctile_slot;   // cell tile -> slot in ctile_list, -1 when inactive
   const int* ctile_rng;    // per slot: [interior begin, end, surface begin, end, balance begin, end]
+  const int* nbr;          // per active node tile ti: slots of the cell tiles at offsets -1..1 (kNbr)
   int nctile;
 };
+
+constexpr int kNbr = 27;   // neighbour slots per node tile (3^D used)
 
 template <int D>
 struct MergeSrc {
@@ -92,6 +95,33 @@ MPM_DEV void merge_sources(int node_tile, int local, int nt, const int* ctile_sl
 #pragma unroll
     for (int a = 0; a < D; ++a) r[a] = i[a] - (E * C[a] - 1);
     ms.slot[j] = s;
+    ms.rn[j] = r[0] + RE * (r[1] + (D == 3 ? RE * r[2] : 0));
+  }
+}
+
+// merge_sources from the table of neighbour slots of the node tile (tl.nbr, written by
+// k_merge_p2g): the candidates and their region indices follow from the node's place in
+// its tile alone (offset -1 on a low face, +1 on a high face), so the slot loads need not
+// wait for the tile's index.  Same candidates, order and values as merge_sources.
+template <int D>
+MPM_DEV void merge_sources_tab(int ti, int local, const int* nbr, MergeSrc<D>& ms) {
+  constexpr int E = TileGeo<D>::E, RE = TileGeo<D>::RE, L = Tiling<D>::LOG;
+  const int l[3] = {local & (E - 1), D == 3 ? (local >> L) & (E - 1) : (local >> L), D == 3 ? (local >> (2 * L)) : 0};
+#pragma unroll
+  for (int j = 0; j < (1 << D); ++j) {
+    int off[3] = {0, 0, 0};
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const int k = (j >> a) & 1;
+      off[a] = (l[a] == 0 ? -1 : 0) + k;
+      ok = ok && (k == 0 || l[a] == 0 || l[a] == E - 1);
+    }
+    const int idx = (off[0] + 1) + 3 * ((off[1] + 1) + (D == 3 ? 3 * (off[2] + 1) : 0));
+    ms.slot[j] = ok ? nbr[ti * kNbr + idx] : -1;
+    int r[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < D; ++a) r[a] = l[a] - E * off[a] + 1;
     ms.rn[j] = r[0] + RE * (r[1] + (D == 3 ? RE * r[2] : 0));
   }
 }
@@ -1296,7 +1326,7 @@ __global__ void __launch_bounds__(64 * kMergeTiles) k_merge_stress(
     const int node = tile * kTileNodes + lane;
     const int nn = d.nn;
     MergeSrc<D> ms;
-    merge_sources<D>(tile, lane, d.nt, tl.ctile_slot, ms);
+    merge_sources_tab<D>(ti, lane, tl.nbr, ms);
     R acc[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) acc[a] = 0;
@@ -1388,7 +1418,7 @@ __global__ void __launch_bounds__(64 * kMergeTiles) k_merge_heat(Dev<R> d, TileL
     const int tile = d.tile_list[ti];
     const int node = tile * kTileNodes + lane;
     MergeSrc<D> ms;
-    merge_sources<D>(tile, lane, d.nt, tl.ctile_slot, ms);
+    merge_sources_tab<D>(ti, lane, tl.nbr, ms);
     R acc = 0;
     R val[1 << D];
 #pragma unroll
@@ -1415,7 +1445,7 @@ __global__ void __launch_bounds__(64 * kMergeTiles) k_merge_heat(Dev<R> d, TileL
 // P2G merge and grid set-up (degrees of freedom, v^n, T^n, constraints, diagonals, heat
 // right side).
 template <int D, typename R>
-__global__ void __launch_bounds__(64) k_merge_p2g(Dev<R> d, TileLists tl, const R* tpart) {
+__global__ void __launch_bounds__(64) k_merge_p2g(Dev<R> d, TileLists tl, const R* tpart, int* nbr_out) {
   constexpr int RN = TileGeo<D>::RN;
   using FI = P2GF<D>;
   constexpr int NF = FI::NF;
@@ -1427,6 +1457,22 @@ __global__ void __launch_bounds__(64) k_merge_p2g(Dev<R> d, TileLists tl, const 
   tiled_coords<D>(tile, lane, d.nt, i);
   MergeSrc<D> ms;
   merge_sources<D>(tile, lane, d.nt, tl.ctile_slot, ms);
+  // this node tile's row of the neighbour-slot table, for the later merges of the step
+  if (lane < (D == 3 ? 27 : 9)) {
+    const int o[3] = {lane % 3 - 1, (lane / 3) % 3 - 1, lane / 9 - 1};
+    int T[3] = {0, 0, 0};
+    tiled_coords<D>(tile, 0, d.nt, T);
+    bool in = true;
+    int ct = 0, mul = 1;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const int C = T[a] / TileGeo<D>::E + o[a];
+      in = in && C >= 0 && C < d.nt;
+      ct += mul * C;
+      mul *= d.nt;
+    }
+    nbr_out[(size_t)blockIdx.x * kNbr + lane] = in ? tl.ctile_slot[ct] : -1;
+  }
   R v[NF];
 #pragma unroll
   for (int f = 0; f < NF; ++f) v[f] = 0;
