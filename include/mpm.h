@@ -147,7 +147,7 @@ enum mpm_field {
   MPM_F_PERM = 17   /* int32 [n_part]: input index of the particle in each cell-order slot */
 };
 
-/* Kernel classes timed by mpm_timing (HIP events on the launch stream). */
+/* Kernel classes timed by mpm_timing (HIP events stamped by the launches themselves). */
 enum mpm_kernel_class {
   MPM_K_SORT = 0,        /* cell keys, scans, slot scatter, per-cell order              */
   MPM_K_SETUP = 1,       /* staging, parents, split, balance points, tiles, k_r         */
@@ -254,7 +254,8 @@ int mpm_batch_config(int32_t max_concurrent);
 int mpm_grid_view(mpm_ctx* ctx, int32_t field, void** out_ptr);
 int mpm_get_stats(const mpm_ctx* ctx, mpm_stats* out);
 /* Timing of the context's kernels by class: enable = 1 starts (and resets) recording of a
- * HIP event pair around every launch on the call's stream, 0 stops it.  Host only. */
+ * HIP event pair for every launch on the call's stream, stamped with the kernel's own
+ * begin and end (hipExtLaunchKernel), 0 stops it.  Host only. */
 int mpm_timing(mpm_ctx* ctx, int32_t enable);
 /* Synchronizes on the recorded events and returns, per kernel class, the summed
  * duration in milliseconds (ms[MPM_K_COUNT]) and the number of launches. */

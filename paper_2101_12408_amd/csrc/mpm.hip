@@ -1,6 +1,7 @@
 // Host side of the MPM hot-path library: workspace layout, contexts, the step pipeline
 // and the C ABI declared in include/mpm.h.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <atomic>
@@ -59,7 +60,7 @@ struct Bump {
 
 }  // namespace
 
-// Per-kernel-class timing with HIP events recorded on the launch stream.
+// Per-kernel-class timing with HIP events stamped by the launches themselves.
 struct Prof {
   bool on = false;
   std::vector<hipEvent_t> ev;      // pairs (start, stop)
@@ -136,7 +137,10 @@ struct mpm_ctx {
 
 namespace {
 
-void prof_begin(mpm_ctx* c, int cls, hipStream_t s, hipEvent_t* stop) {
+// The start and stop events of the next timed launch.  They are given to the launch
+// itself (hipExtLaunchKernelGGL), which stamps them with the kernel's own begin and end,
+// so the elapsed time is the kernel's, without the time of separate event markers.
+void prof_slot(mpm_ctx* c, int cls, hipEvent_t* start, hipEvent_t* stop) {
   Prof& pr = c->prof;
   if (pr.used * 2 + 2 > pr.ev.size()) {
     hipEvent_t a, b;
@@ -147,7 +151,7 @@ void prof_begin(mpm_ctx* c, int cls, hipStream_t s, hipEvent_t* stop) {
     pr.cls.push_back(0);
   }
   pr.cls[pr.used] = cls;
-  HIPCHK(hipEventRecord(pr.ev[2 * pr.used], s));
+  *start = pr.ev[2 * pr.used];
   *stop = pr.ev[2 * pr.used + 1];
   pr.used++;
 }
@@ -165,16 +169,15 @@ void prof_collect(mpm_ctx* c) {
 }
 
 // Launch on stream s (in scope), timed as kernel class cls when timing is on.
-#define LAUNCH(c, cls, ...)                                       \
-  do {                                                            \
-    if ((c)->prof.on) {                                           \
-      hipEvent_t stop_;                                           \
-      prof_begin((c), (cls), s, &stop_);                          \
-      hipLaunchKernelGGL(__VA_ARGS__);                            \
-      HIPCHK(hipEventRecord(stop_, s));                           \
-    } else {                                                      \
-      hipLaunchKernelGGL(__VA_ARGS__);                            \
-    }                                                             \
+#define LAUNCH(c, cls, K, G, B, SH, S, ...)                                   \
+  do {                                                                        \
+    if ((c)->prof.on) {                                                       \
+      hipEvent_t start_, stop_;                                               \
+      prof_slot((c), (cls), &start_, &stop_);                                 \
+      hipExtLaunchKernelGGL(K, G, B, SH, S, start_, stop_, 0, ##__VA_ARGS__); \
+    } else {                                                                  \
+      hipLaunchKernelGGL(K, G, B, SH, S, ##__VA_ARGS__);                      \
+    }                                                                         \
   } while (0)
 
 template <typename R>
