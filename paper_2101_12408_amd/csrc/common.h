@@ -149,6 +149,10 @@ MPM_DEV R weight_from_cell(const int* k, const R* f, R fn, R* g) {
   }
 }
 
+// Fused multiply-add, one rounding.
+MPM_DEV float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+MPM_DEV double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // ---- deterministic reductions -------------------------------------------------------
 MPM_DEV double wave_sum(double v) {
 #pragma unroll

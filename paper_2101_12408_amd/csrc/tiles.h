@@ -440,16 +440,26 @@ MPM_DEV R bs_dw_fn(int k, R x, R fn) {
   return k == 0 ? (x - R(1)) * fn : (k == 1 ? (R(1) - R(2) * x) * fn : x * fn);
 }
 
+// bs_dw_fn for a node number k that varies across the lanes, without branches: the
+// derivative is (x b_k + a_k) fn with (a_k, b_k) = (-1, 1), (1, -2), (0, 1), taken once per
+// lane (LaneDw).  One FMA rounds x - 1, 1 - 2x and x exactly as bs_dw_fn's forms do.
+template <typename R>
+struct LaneDw {
+  R a, b;
+  MPM_DEV explicit LaneDw(int k) : a(k == 0 ? R(-1) : (k == 1 ? R(1) : R(0))), b(k == 1 ? R(-2) : R(1)) {}
+  MPM_DEV R operator()(R x, R fn) const { return fma_r(x, b, a) * fn; }
+};
+
 // acc[k][a] += sum_b S[a][b] dN_k/dx_b over the lane's three nodes k (k2 = k in 3D, k1 = k
 // in 2D), from the point's cell-relative position F and weight table W.  The node
 // gradients share the lane's factors (3D: (al wz_k, be wz_k, ga dwz_k) with al = dwx wy,
 // be = wx dwy, ga = wx wy), so S g_k = wz_k (al S_.0 + be S_.1) + dwz_k (ga S_.2): 2 FMAs
 // per node and component after a per-point set-up.
 template <int D, typename R>
-MPM_DEV void lane_scatter_grad(const R* F, const R* W, R fn, int k0, int k1, const R (&S)[D][D],
-                               R (&acc)[3][D]) {
+MPM_DEV void lane_scatter_grad(const R* F, const R* W, R fn, int k0, int k1, const LaneDw<R>& d0, const LaneDw<R>& d1,
+                               const R (&S)[D][D], R (&acc)[3][D]) {
   if constexpr (D == 3) {
-    const R wx = W[k0], dwx = bs_dw_fn<R>(k0, F[0], fn), wy = W[3 + k1], dwy = bs_dw_fn<R>(k1, F[1], fn);
+    const R wx = W[k0], dwx = d0(F[0], fn), wy = W[3 + k1], dwy = d1(F[1], fn);
     const R al = dwx * wy, be = wx * dwy, ga = wx * wy;
     R Pa[3], Qa[3];
 #pragma unroll
@@ -464,7 +474,7 @@ MPM_DEV void lane_scatter_grad(const R* F, const R* W, R fn, int k0, int k1, con
       for (int a = 0; a < 3; ++a) acc[k][a] += wz * Pa[a] + dwz * Qa[a];
     }
   } else {
-    const R wx = W[k0], dwx = bs_dw_fn<R>(k0, F[0], fn);
+    const R wx = W[k0], dwx = d0(F[0], fn);
     R Pa[2], Qa[2];
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
@@ -482,15 +492,16 @@ MPM_DEV void lane_scatter_grad(const R* F, const R* W, R fn, int k0, int k1, con
 
 // acc[k][0] += c N_k + q . grad N_k over the lane's three nodes, factored as above.
 template <int D, typename R>
-MPM_DEV void lane_scatter_heat(const R* F, const R* W, R fn, int k0, int k1, R c, const R* q, R (&acc)[3][1]) {
+MPM_DEV void lane_scatter_heat(const R* F, const R* W, R fn, int k0, int k1, const LaneDw<R>& d0, const LaneDw<R>& d1,
+                               R c, const R* q, R (&acc)[3][1]) {
   if constexpr (D == 3) {
-    const R wx = W[k0], dwx = bs_dw_fn<R>(k0, F[0], fn), wy = W[3 + k1], dwy = bs_dw_fn<R>(k1, F[1], fn);
+    const R wx = W[k0], dwx = d0(F[0], fn), wy = W[3 + k1], dwy = d1(F[1], fn);
     const R al = dwx * wy, be = wx * dwy, ga = wx * wy;
     const R Pv = c * ga + al * q[0] + be * q[1], Qv = ga * q[2];
 #pragma unroll
     for (int k = 0; k < 3; ++k) acc[k][0] += W[6 + k] * Pv + bs_dw_fn<R>(k, F[2], fn) * Qv;
   } else {
-    const R wx = W[k0], dwx = bs_dw_fn<R>(k0, F[0], fn);
+    const R wx = W[k0], dwx = d0(F[0], fn);
     const R Pv = c * wx + dwx * q[0], Qv = wx * q[1];
 #pragma unroll
     for (int k = 0; k < 3; ++k) acc[k][0] += W[3 + k] * Pv + bs_dw_fn<R>(k, F[1], fn) * Qv;
@@ -597,6 +608,7 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
   }
   int lcell, lk0, lk1;
   lane_map<D>(t, lcell, lk0, lk1);
+  const LaneDw<R> ldw0(lk0), ldw1(lk1);
   const bool lane_on = t < 64 * TileGeo<D>::LPC;
   int cpb = 0, cpe = 0, csb = 0, cse = 0;
   if (lane_on) {
@@ -721,7 +733,7 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
           for (int a = 0; a < D; ++a)
 #pragma unroll
             for (int b = 0; b < D; ++b) Sq[a][b] = P[4 * D + a * D + b];
-          lane_scatter_grad<D, R>(P, P + D, d.fn, lk0, lk1, Sq, acc.v);
+          lane_scatter_grad<D, R>(P, P + D, d.fn, lk0, lk1, ldw0, ldw1, Sq, acc.v);
         }
       }
     }
@@ -807,6 +819,7 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::HEAT) k_tile_heat(De
   const int npi = pe - pb, ntot = npi + (se - sb);
   int lcell, lk0, lk1;
   lane_map<D>(t, lcell, lk0, lk1);
+  const LaneDw<R> ldw0(lk0), ldw1(lk1);
   const bool lane_on = t < 64 * TileGeo<D>::LPC;
   int cpb = 0, cpe = 0, csb = 0, cse = 0;
   if (lane_on) {
@@ -863,7 +876,7 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::HEAT) k_tile_heat(De
         int b0 = max(pass == 0 ? cpb : csb, lo), b1 = min(pass == 0 ? cpe : cse, hi);
         for (int qq = b0; qq < b1; ++qq) {
           const R* P = &sm.x.pt[(qq - q0) * PS];
-          lane_scatter_heat<D, R>(P, P + D, d.fn, lk0, lk1, P[4 * D], P + 4 * D + 1, acc.v);
+          lane_scatter_heat<D, R>(P, P + D, d.fn, lk0, lk1, ldw0, ldw1, P[4 * D], P + 4 * D + 1, acc.v);
         }
       }
     }
