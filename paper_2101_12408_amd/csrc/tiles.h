@@ -454,7 +454,7 @@ struct LaneDw {
 // in 2D), from the point's cell-relative position F and weight table W.  The node
 // gradients share the lane's factors (3D: (al wz_k, be wz_k, ga dwz_k) with al = dwx wy,
 // be = wx dwy, ga = wx wy), so S g_k = wz_k (al S_.0 + be S_.1) + dwz_k (ga S_.2): 2 FMAs
-// per node and component after a per-point set-up.
+// per node and component, chained into the accumulator, after a per-point set-up.
 template <int D, typename R>
 MPM_DEV void lane_scatter_grad(const R* F, const R* W, R fn, int k0, int k1, const LaneDw<R>& d0, const LaneDw<R>& d1,
                                const R (&S)[D][D], R (&acc)[3][D]) {
@@ -471,7 +471,7 @@ MPM_DEV void lane_scatter_grad(const R* F, const R* W, R fn, int k0, int k1, con
     for (int k = 0; k < 3; ++k) {
       const R wz = W[6 + k], dwz = bs_dw_fn<R>(k, F[2], fn);
 #pragma unroll
-      for (int a = 0; a < 3; ++a) acc[k][a] += wz * Pa[a] + dwz * Qa[a];
+      for (int a = 0; a < 3; ++a) acc[k][a] = fma_r(dwz, Qa[a], fma_r(wz, Pa[a], acc[k][a]));
     }
   } else {
     const R wx = W[k0], dwx = d0(F[0], fn);
@@ -485,7 +485,7 @@ MPM_DEV void lane_scatter_grad(const R* F, const R* W, R fn, int k0, int k1, con
     for (int k = 0; k < 3; ++k) {
       const R wy = W[3 + k], dwy = bs_dw_fn<R>(k, F[1], fn);
 #pragma unroll
-      for (int a = 0; a < 2; ++a) acc[k][a] += wy * Pa[a] + dwy * Qa[a];
+      for (int a = 0; a < 2; ++a) acc[k][a] = fma_r(dwy, Qa[a], fma_r(wy, Pa[a], acc[k][a]));
     }
   }
 }
@@ -499,12 +499,12 @@ MPM_DEV void lane_scatter_heat(const R* F, const R* W, R fn, int k0, int k1, con
     const R al = dwx * wy, be = wx * dwy, ga = wx * wy;
     const R Pv = c * ga + al * q[0] + be * q[1], Qv = ga * q[2];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) acc[k][0] += W[6 + k] * Pv + bs_dw_fn<R>(k, F[2], fn) * Qv;
+    for (int k = 0; k < 3; ++k) acc[k][0] = fma_r(bs_dw_fn<R>(k, F[2], fn), Qv, fma_r(W[6 + k], Pv, acc[k][0]));
   } else {
     const R wx = W[k0], dwx = d0(F[0], fn);
     const R Pv = c * wx + dwx * q[0], Qv = wx * q[1];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) acc[k][0] += W[3 + k] * Pv + bs_dw_fn<R>(k, F[1], fn) * Qv;
+    for (int k = 0; k < 3; ++k) acc[k][0] = fma_r(bs_dw_fn<R>(k, F[1], fn), Qv, fma_r(W[3 + k], Pv, acc[k][0]));
   }
 }
 
