@@ -440,14 +440,18 @@ MPM_DEV R bs_dw_fn(int k, R x, R fn) {
   return k == 0 ? (x - R(1)) * fn : (k == 1 ? (R(1) - R(2) * x) * fn : x * fn);
 }
 
-// bs_dw_fn for a node number k that varies across the lanes, without branches: the
-// derivative is (x b_k + a_k) fn with (a_k, b_k) = (-1, 1), (1, -2), (0, 1), taken once per
-// lane (LaneDw).  One FMA rounds x - 1, 1 - 2x and x exactly as bs_dw_fn's forms do.
+// bs_dw_fn for a node number k that varies across the lanes, without branches: all three
+// forms (x - 1, 1 - 2x, x) are formed and the lane's is selected, each rounded as in
+// bs_dw_fn.  Held per lane as the two comparisons of k (lane masks in scalar registers),
+// so that it takes no vector registers across the scatter loop.
 template <typename R>
 struct LaneDw {
-  R a, b;
-  MPM_DEV explicit LaneDw(int k) : a(k == 0 ? R(-1) : (k == 1 ? R(1) : R(0))), b(k == 1 ? R(-2) : R(1)) {}
-  MPM_DEV R operator()(R x, R fn) const { return fma_r(x, b, a) * fn; }
+  bool k0, k1;
+  MPM_DEV explicit LaneDw(int k) : k0(k == 0), k1(k == 1) {}
+  MPM_DEV R operator()(R x, R fn) const {
+    const R t = k0 ? x - R(1) : (k1 ? fma_r(x, R(-2), R(1)) : x);
+    return t * fn;
+  }
 };
 
 // acc[k][a] += sum_b S[a][b] dN_k/dx_b over the lane's three nodes k (k2 = k in 3D, k1 = k
