@@ -553,12 +553,16 @@ MPM_DEV void stress_fetch(const Dev<R>& d, int q, int ntot, int npi, int pb, int
   in.interior = q < npi;
   const int k = in.interior ? pb + q : sb + (q - npi);
   in.k = k;
+  // every slot is written on both paths (constant indices), so that the array stays in
+  // registers
   if (in.interior) {
 #pragma unroll
     for (int a = 0; a < D; ++a) in.v[a] = d.px[a * N + k];
     in.v[D] = d.pJ[k];
     in.v[D + 1] = d.pV0[k];
-    if (D >= 2) in.v[D + 2] = visc ? d.pmu[k] * d.pVn[k] : R(0);
+    in.v[D + 2] = visc ? d.pmu[k] * d.pVn[k] : R(0);
+#pragma unroll
+    for (int a = 2; a < D; ++a) in.v[D + 1 + a] = R(0);
   } else {
 #pragma unroll
     for (int a = 0; a < D; ++a) in.v[a] = d.ss[a * S + k];
