@@ -63,6 +63,25 @@ def test_implicit_step_matches_oracle_fp64(case):
         assert e < 1e-7, k
 
 
+def test_implicit_step_without_translation_correction():
+    """With the translation correction off, the Newton decision and the next CG's start run
+    as kernels of their own (not inside the correction's pass): FP64 step against the
+    oracle at the same bar."""
+    S = sc.marangoni3d(n=32, radius=0.25)
+    P, p = S["particles"], dict(S["params"], momentum_fix=0, **TIGHT)
+    surf = sampler.sample_surface(P["x"], p)
+    ref, info = ostep.step(P, p, surf)
+    got, st, rc = _gpu_step(P, surf, p)
+    log(f"  no correction: gpu newton {st['newton_iters']} cg {st['cg_iters']}; oracle newton {info['newton']} "
+        f"cg {info['cg']}")
+    assert rc == 0
+    assert st["newton_iters"] >= 2   # the queued next-iteration CG was taken at least once
+    for k in ("v", "A", "J", "x", "T"):
+        e = rel(got[k] - P[k], ref[k] - P[k]) if k in ("x", "J") else rel(got[k], ref[k])
+        log(f"  {k}: rel {e:.3e}")
+        assert e < 1e-7, k
+
+
 def test_mixed_step_error_report():
     """MIXED mode step against the FP64 oracle: reported, bounded at the FP32 level."""
     S = sc.marangoni3d(n=32, radius=0.25)
