@@ -181,11 +181,11 @@ struct LaneAcc {
 };
 
 // Writes the lane accumulators to the per-cell LDS partial buffer (fields f0..f0+FC) and
-// reduces them onto the node region: reg[rn][f] = sum over cells c, offsets k with
-// c + k = rn (fixed order).  Caller synchronizes around.
-template <int D, typename R, int NF, int FC>
-MPM_DEV void reduce_cells_to_region(const LaneAcc<D, R, NF>& acc, int f0, R* cellpart, R* reg, int lane_cell,
-                                    int lane_k0, int lane_k1, bool lane_on) {
+// reduces them onto the node region: out(rn, f, sum over cells c, offsets k with c + k =
+// rn), in a fixed order.  Caller synchronizes around.
+template <int D, typename R, int NF, int FC, class Out>
+MPM_DEV void reduce_cells_to_region_out(const LaneAcc<D, R, NF>& acc, int f0, R* cellpart, int lane_cell, int lane_k0,
+                                        int lane_k1, bool lane_on, Out&& out) {
   constexpr int RN = TileGeo<D>::RN, NT = TileGeo<D>::NT, E = TileGeo<D>::E;
   // cellpart layout: [cell 64][k2 3][k1 3][k0 3][FC]  (3D)  /  [cell 64][k1 3][k0 3][FC] (2D)
   if (lane_on) {
@@ -223,9 +223,17 @@ MPM_DEV void reduce_cells_to_region(const LaneAcc<D, R, NF>& acc, int f0, R* cel
         }
       }
     }
-    reg[rn * FC + f] = s;
+    out(rn, f, s);
   }
   __syncthreads();
+}
+
+// reduce_cells_to_region_out into an LDS buffer: reg[rn][f].
+template <int D, typename R, int NF, int FC>
+MPM_DEV void reduce_cells_to_region(const LaneAcc<D, R, NF>& acc, int f0, R* cellpart, R* reg, int lane_cell,
+                                    int lane_k0, int lane_k1, bool lane_on) {
+  reduce_cells_to_region_out<D, R, NF, FC>(acc, f0, cellpart, lane_cell, lane_k0, lane_k1, lane_on,
+                                           [&](int rn, int f, R v) { reg[rn * FC + f] = v; });
 }
 
 // Lane mapping of the scatter phase.
@@ -906,15 +914,17 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::HEAT) k_tile_heat(De
 // ======================================================================================
 template <int D> struct P2GF {
   static constexpr int NF = 2 * D + 7;
-  static constexpr int M = 0, MV = 1, W = D + 1, WT = D + 2, E = D + 3, ET = D + 4, DG = D + 5, HD = 2 * D + 5,
+  static constexpr int M = 0, MV = 1, WT = D + 1, E = D + 2, ET = D + 3, W = D + 4, DG = D + 5, HD = 2 * D + 5,
                        HR = 2 * D + 6;
   // The fields go in two groups, each transferred by its own workgroup of one launch:
-  // group 0 (fields [0, G1)) needs the weights only, group 1 (fields [G1, NF)) the weight
-  // gradients too.  Payload per point of group 0: m~, m~ v, m~ A, c_W, c_WT, c_E, c_ET,
-  // m grad T; of group 1: cJ, cV, cK (|grad N|^2 heat term), cR (N^2 Robin term), cS (N
-  // heat right side).
-  static constexpr int G1 = D + 5;
-  static constexpr int PL0 = 1 + D + D * D + 4 + D, PL1 = 5;
+  // group 0 (fields [0, G1)) needs the weights only; group 1 (fields [G1, NF)) the weight
+  // gradients for all but W, which joins it because, like the gradient terms, it comes
+  // from the interior particles alone (with 7 fields per reduction round in FP32, both
+  // groups then reduce in one round).  Payload per point of group 0: m~, m~ v, m~ A, c_W
+  // (unused), c_WT, c_E, c_ET, m grad T; of group 1: cJ, cV, cK (|grad N|^2 heat term), cR
+  // (N^2 Robin term), cS (N heat right side), c_W.
+  static constexpr int G1 = D + 4;
+  static constexpr int PL0 = 1 + D + D * D + 4 + D, PL1 = 6;
   static constexpr int PW0 = D + 3 * D + PL0;        // f, w table, payload
   static constexpr int PW1 = D + 6 * D + PL1;        // f, w and dw tables, payload
   static constexpr int PW = PW0 > PW1 ? PW0 : PW1;
@@ -926,13 +936,12 @@ template <int D, typename R>
 struct P2GLds {
   static constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
   static constexpr int CH = sizeof(R) == 8 ? NT / 4 : NT / 2;   // points per chunk
-  static constexpr int FC = sizeof(R) == 8 ? 3 : 5;             // fields per reduction round
+  static constexpr int FC = sizeof(R) == 8 ? 3 : 7;             // fields per reduction round
   static constexpr int PS = P2GF<D>::PW | 1;                     // payload stride
   union {
     R pay[CH * PS];
     struct {
-      R cellpart[64 * 27 * FC];
-      R reg[RN * FC];
+      R cellpart[64 * 27 * FC];   // the region sums go straight to the tile partial
     } red;
   } x;
 };
@@ -1041,6 +1050,7 @@ MPM_DEV void p2g_group(const Dev<R>& d, const TileLists& tl, int ti, R* tpart, P
           H[2] = d.K * Vn;
           H[3] = 0;
           H[4] = d.H * Vn;
+          H[5] = d.pm[k];
         } else {
           R area = 0;
 #pragma unroll
@@ -1049,6 +1059,7 @@ MPM_DEV void p2g_group(const Dev<R>& d, const TileLists& tl, int ti, R* tpart, P
           H[0] = 0; H[1] = 0; H[2] = 0;
           H[3] = d.h * area;
           H[4] = (d.h * d.T_amb + d.b) * area;
+          H[5] = 0;
         }
       }
     }
@@ -1092,7 +1103,6 @@ MPM_DEV void p2g_group(const Dev<R>& d, const TileLists& tl, int ti, R* tpart, P
                 R sw = Z[1];
 #pragma unroll
                 for (int a = 0; a < D; ++a) sw += bW[a] * rel[a];
-                acc.v[k][FI::W] += w * Z[0];
                 acc.v[k][FI::WT] += w * sw;
               } else {
                 acc.v[k][FI::E] += w * Z[2];
@@ -1116,6 +1126,7 @@ MPM_DEV void p2g_group(const Dev<R>& d, const TileLists& tl, int ti, R* tpart, P
                   acc.v[k][FI::DG - F0 + a] += H[0] * g[a] * g[a] + H[1] * (R(0.5) * g2 + R(0.5) * g[a] * g[a]);
                 acc.v[k][FI::HD - F0] += H[2] * g2;
                 acc.v[k][FI::HR - F0] += H[4] * w;
+                acc.v[k][FI::W - F0] += w * H[5];
               }
             } else {
               R wn[3];
@@ -1132,16 +1143,13 @@ MPM_DEV void p2g_group(const Dev<R>& d, const TileLists& tl, int ti, R* tpart, P
     }
     __syncthreads();
   }
-  // field rounds of FC onto the region
-  R* reg = sm.x.red.reg;
+  // field rounds of FC onto the region, written to the tile partial
 #pragma unroll
   for (int f0 = 0; f0 < NFG; f0 += FC) {
-    reduce_cells_to_region<D, R, NFG, FC>(acc, f0, sm.x.red.cellpart, reg, lcell, lk0, lk1, lane_on);
-    for (int i = t; i < RN * FC; i += NT) {
-      int rn = i / FC, f = f0 + i % FC;
-      if (f < NFG) tpart[((size_t)ti * RN + rn) * FI::NF + F0 + f] = reg[i];
-    }
-    __syncthreads();
+    reduce_cells_to_region_out<D, R, NFG, FC>(acc, f0, sm.x.red.cellpart, lcell, lk0, lk1, lane_on,
+                                              [&](int rn, int f, R v) {
+                                                tpart[((size_t)ti * RN + rn) * FI::NF + F0 + f0 + f] = v;
+                                              });
   }
 }
 
