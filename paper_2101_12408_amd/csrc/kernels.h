@@ -407,6 +407,29 @@ MPM_DEV int parent_search(const Dev<R>& d, const double* sd, const int* c, int& 
 // than rad dx is exact; past ring 2 the group's first lane runs the sequential search.
 constexpr int kParGroup = 8;
 
+// The cells of rings 1 and 2 around a cell (Chebyshev distance 1, then 2), each as its
+// index j in the 5^D block of offsets -2..2 (offset a = j / 5^a % 5 - 2): ring 1 in
+// off[0, n1), ring 2 in off[n1, n1 + n2).
+template <int D>
+struct RingCells {
+  int n1 = 0, n2 = 0;
+  int off[D == 3 ? 124 : 24] = {};
+  constexpr RingCells() {
+    const int nb = D == 3 ? 125 : 25;
+    for (int ring = 1; ring <= 2; ++ring)
+      for (int j = 0; j < nb; ++j) {
+        const int o0 = j % 5 - 2, o1 = (j / 5) % 5 - 2, o2 = D == 3 ? j / 25 - 2 : 0;
+        const int a0 = o0 < 0 ? -o0 : o0, a1 = o1 < 0 ? -o1 : o1, a2 = o2 < 0 ? -o2 : o2;
+        const int r = a0 > a1 ? (a0 > a2 ? a0 : a2) : (a1 > a2 ? a1 : a2);
+        if (r != ring) continue;
+        if (ring == 1) off[n1++] = j;
+        else off[n1 + n2++] = j;
+      }
+  }
+};
+__constant__ RingCells<2> kRing2 = RingCells<2>();
+__constant__ RingCells<3> kRing3 = RingCells<3>();
+
 template <int D>
 MPM_DEV void par_min(double& best, int& bk, const int* perm) {
 #pragma unroll
@@ -459,14 +482,14 @@ __global__ void __launch_bounds__(256) k_parents(Dev<R> d) {
   par_min<D>(best, bk, d.p_perm);
   const double dxd = (double)d.dx;
   bool done = false;
+  const RingCells<D>& rings = *(D == 3 ? (const RingCells<D>*)&kRing3 : (const RingCells<D>*)&kRing2);
   for (int rad = 1; rad <= 2 && !done; ++rad) {
     constexpr int W = 5;                                  // offsets -2..2 per axis
-    constexpr int NB = D == 3 ? W * W * W : W * W;
     const double cut = best * (1.0 + 1e-9);                // ties must be visited
-    for (int j = lane; live && j < NB; j += kParGroup) {
+    const int q0 = rad == 1 ? 0 : rings.n1, q1 = rad == 1 ? rings.n1 : rings.n1 + rings.n2;
+    for (int q = q0 + lane; live && q < q1; q += kParGroup) {
+      const int j = rings.off[q];
       const int o0 = j % W - 2, o1 = (j / W) % W - 2, o2 = D == 3 ? j / (W * W) - 2 : 0;
-      const int ring = max(abs(o0), max(abs(o1), abs(o2)));
-      if (ring != rad) continue;
       int cc[3] = {c[0] + o0, c[1] + o1, D == 3 ? c[2] + o2 : 0};
       bool in = true;
       double bd2 = 0;
