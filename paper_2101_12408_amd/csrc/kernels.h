@@ -235,11 +235,9 @@ __global__ void k_cell_scatter(const int* key, int cnt, const int* start, int* c
 // Segment ordering after an atomic scatter, from src into dst: the segment of slot s is
 // the run of slots whose values v have the same key[v]; it starts at start[key[v]].
 // Sorting each segment by value (the input index) puts it in input order, independent of
-// the order in which the atomics were served.  Short segments (up to 16) are ranked in
-// registers by their first slot's thread; in longer ones every thread ranks its own value
-// by counting the smaller ones (independent loads).  src is only read, so every thread
-// sees the scatter's output.
-constexpr int kSegReg = 16;
+// the order in which the atomics were served.  Every thread ranks its own value by
+// counting the smaller ones in its segment (independent loads; the values are distinct).
+// src is only read, so every thread sees the scatter's output.
 
 __global__ void k_segment_order(const int* key, const int* start, int cnt, const int* src, int* dst) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -251,23 +249,10 @@ __global__ void k_segment_order(const int* key, const int* start, int cnt, const
     dst[s] = v;
     return;
   }
-  if (n > kSegReg) {
-    int r = 0;
-    for (int j = b; j < e; ++j) r += src[j] < v ? 1 : 0;
-    dst[b + r] = v;
-    return;
-  }
-  if (s != b) return;
-  int w[kSegReg];
-#pragma unroll
-  for (int i = 0; i < kSegReg; ++i) w[i] = i < n ? src[b + i] : 0x7fffffff;
-#pragma unroll
-  for (int i = 0; i < kSegReg; ++i) {
-    int r = 0;
-#pragma unroll
-    for (int j = 0; j < kSegReg; ++j) r += w[j] < w[i] ? 1 : 0;
-    if (i < n) dst[b + r] = w[i];
-  }
+  // the rank of v among its segment's (distinct) values, found by this thread alone
+  int r = 0;
+  for (int j = b; j < e; ++j) r += src[j] < v ? 1 : 0;
+  dst[b + r] = v;
 }
 
 __global__ void k_fill_i32(int* p, int v, int64_t len) {
