@@ -22,11 +22,13 @@ namespace mpm {
 // two per CU fit at most 85 VGPRs (80 allocated), three need at most 56.  The kernels
 // ask for W waves per SIMD; the compiler honours that only while its own LDS estimate
 // allows W, so the LDS of a block stays under a third of the CU's 160 KB.  P2G fits 73
-// (MIXED) by itself; FP64 kernels need about twice the registers.
+// (MIXED) by itself.  FP64 kernels need about twice the registers: at one workgroup per
+// CU they ask for 3 or 4 waves per SIMD (up to 168 or 128 VGPRs); held to 80, the FP64
+// stress and heat kernels spilled over 300 bytes per lane.
 #define MPM_TILE_KERNEL(NT, W) __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(W)))
 template <typename R> struct TileOcc;
 template <> struct TileOcc<float> { static constexpr int STRESS = 6, HEAT = 6, P2G = 6; };
-template <> struct TileOcc<double> { static constexpr int STRESS = 6, HEAT = 6, P2G = 4; };
+template <> struct TileOcc<double> { static constexpr int STRESS = 3, HEAT = 3, P2G = 4; };
 
 template <int D> struct TileGeo;
 template <> struct TileGeo<3> {
