@@ -529,7 +529,7 @@ MPM_DEV void lane_scatter_heat(const R* F, const R* W, R fn, int k0, int k1, con
 template <int D, typename R>
 struct StressLds {
   static constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
-  static constexpr int CH = sizeof(R) == 8 ? NT / 4 : NT;     // points per chunk
+  static constexpr int CH = NT;                             // points per chunk
   static constexpr int PW = 4 * D + D * D;                  // f, w table, stress
   static constexpr int PS = PW | 1;                         // odd payload stride
   R u[RN * D];
@@ -794,7 +794,7 @@ __global__ void k_surface_F(Dev<R> d, const R* vlin) {
 template <int D, typename R>
 struct HeatLds {
   static constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
-  static constexpr int CH = sizeof(R) == 8 ? NT / 4 : NT;     // points per chunk
+  static constexpr int CH = NT;                             // points per chunk
   static constexpr int PW = 4 * D + 1 + D;    // f, w table, c, q
   static constexpr int PS = PW | 1;           // odd payload stride (distinct banks per cell)
   R u[RN];
