@@ -937,8 +937,8 @@ template <int D> struct P2GF {
 template <int D, typename R>
 struct P2GLds {
   static constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
-  static constexpr int CH = sizeof(R) == 8 ? NT / 4 : NT / 2;   // points per chunk
-  static constexpr int FC = sizeof(R) == 8 ? 3 : 7;             // fields per reduction round
+  static constexpr int CH = NT / 2;                              // points per chunk
+  static constexpr int FC = 7;                                   // fields per reduction round
   static constexpr int PS = P2GF<D>::PW | 1;                     // payload stride
   union {
     R pay[CH * PS];
