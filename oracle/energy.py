@@ -25,7 +25,9 @@ refers to is read as dropping Q2 (hess_mode PSD).  EXACT keeps it.
 
 Parity pins: central finite differences of Phi and of grad Phi, Hessian symmetry,
 translation/rotation invariance of the forces, the closed form at F^ = I
-(tests/test_oracle_energy.py).
+(tests/test_oracle_energy.py); each term's value and first moment of its force under an
+affine velocity field, which fixes the scale of e_J, e_sigma and D and the
+symmetrization of the strain rate (tests/test_oracle_pins.py).
 """
 from __future__ import annotations
 

@@ -9,7 +9,7 @@
   each split member (x_p, s_r, b_r for r in Pi_p) carries m~_p, v_p and A_p.
 
 Parity pins: group mass = m_p and group centre of mass = x_p (eq. cons_mom), brute-force
-nearest search on small inputs (tests/test_oracle_resample.py).
+nearest search on small inputs, exact dyadic ties (tests/test_oracle_transfer.py).
 """
 from __future__ import annotations
 

@@ -17,6 +17,11 @@ term and interior particles as quadrature points of the conduction term,
     L_ij = sum_p K V^n_p grad N_i(x_p) . grad N_j(x_p),   R_ij = sum_r h |dA_r| N_i(s_r) N_j(s_r)
 over the nodes with mass (the heat mass is the momentum mass m_i, split mass included;
 the stray factor h printed on the source term is dropped).  Solved with Jacobi-preconditioned CG from the initial guess T^n.
+
+Parity pins: symmetry and definiteness of the heat operator, the ambient fixed point,
+the balance law, Newton stationarity, explicit conservation (tests/test_oracle_solve.py);
+the scale of L and R and of the right side's sources against a linear temperature
+(tests/test_oracle_pins.py).
 """
 from __future__ import annotations
 

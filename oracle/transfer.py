@@ -24,6 +24,13 @@ G2P with merge (Section 5): for every interior particle,
     t_p  = sum_i p_ip (x_i - x_p)^T,   A_p = 4 / (m_p dx^2) t_p
     T_p  = sum_i N_i(x_p) T^_i,   grad T_p = sum_i T^_i grad N_i(x_p)
 and (not stated in the paper, read as the trace form at the solution) J_p <- (1 + dt sum_i v^_i . grad N_i(x_p)) J_p, x_p <- x_p + dt v_p.
+
+Parity pins: conservation of mass, momentum and APIC angular momentum through P2G and
+G2P with split groups, the unsplit splat written out per particle, linear temperature
+reproduction (tests/test_oracle_transfer.py); k_r of a linear temperature field, G2P of
+an affine grid velocity in closed form (v, A with the split groups' second moments, J,
+x), the slip-wall and slab masks and the label table on enumerated grids
+(tests/test_oracle_pins.py).
 """
 from __future__ import annotations
 
