@@ -144,22 +144,23 @@ def contact3d(seed=3, n=192, radius=0.15):
     return dict(params=p, particles=particles_from_positions(x, 3, dx), name="contact3d", steps=50)
 
 
-def meltslab3d(seed=4, n=256, ppc_axis=2):
-    """3D wax slab x,z in [0.2,0.8], y in [2dx, 2dx+0.2], T0 290 K heated by a 400 K
-    ambient through the Robin term (h 20, b 0, K 0.25, c_p 1), mu(T) = 1e3 exp(-0.05
-    (T-290)), gamma(T) as in marangoni3d, gravity -9.8, slip floor (two node layers)."""
+def meltslab3d(seed=4, n=256, ppc_axis=2, lo=0.2, hi=0.8, height=0.2):
+    """3D wax slab x,z in [lo,hi] (default [0.2,0.8]), y in [2dx, 2dx+height] (default 0.2),
+    T0 290 K heated by a 400 K ambient through the Robin term (h 20, b 0, K 0.25, c_p 1),
+    mu(T) = 1e3 exp(-0.05 (T-290)), gamma(T) as in marangoni3d, gravity -9.8, slip floor
+    (two node layers)."""
     dx = 1.0 / n
     p = make_params(dim=3, n=n, dt=1e-3, bulk=1e4, gravity=(0.0, -9.8, 0.0),
                     mu0=1e3, mu_k=0.05, mu_T0=290.0,
                     g0=0.072, g1=-1.5e-4, gT0=300.0,
                     heat=1, cp=1.0, K=0.25, h=20.0, b=0.0, T_amb=400.0,
                     wall_layers=2, momentum_fix=0, seed=seed)
-    y0, y1 = 2 * dx, 2 * dx + 0.2
-    inside = lambda q: (np.all((q[:, [0, 2]] >= 0.2) & (q[:, [0, 2]] < 0.8), axis=1)
+    y0, y1 = 2 * dx, 2 * dx + height
+    inside = lambda q: (np.all((q[:, [0, 2]] >= lo) & (q[:, [0, 2]] < hi), axis=1)
                         & (q[:, 1] >= y0) & (q[:, 1] < y1))
-    lo = np.array([int(0.2 * n) - 1, 2, int(0.2 * n) - 1])
-    hi = np.array([int(0.8 * n) + 2, int(y1 * n) + 2, int(0.8 * n) + 2])
-    x = lattice(n, 3, inside, seed, ppc_axis=ppc_axis, lo=lo, hi=hi)
+    clo = np.array([int(lo * n) - 1, 2, int(lo * n) - 1])
+    chi = np.array([int(hi * n) + 2, int(y1 * n) + 2, int(hi * n) + 2])
+    x = lattice(n, 3, inside, seed, ppc_axis=ppc_axis, lo=clo, hi=chi)
     T = np.full(x.shape[0], 290.0)
     return dict(params=p, particles=particles_from_positions(x, 3, dx, ppc=ppc_axis ** 3, T=T),
                 name="meltslab3d", steps=20)

@@ -26,6 +26,24 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(nb, 1e-300))
 
 
+def rel_max(a, b):
+    """Worst element: max_i |a_i - b_i| / max_i |b_i| (a norm-wise bound lets one element of
+    a large array be off by sqrt(size) times the tolerance)."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    if b.size == 0:
+        return 0.0
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def check(name, got, ref, tol, tol_max=None):
+    """Norm-wise and element-wise relative error of got against ref, both below tol."""
+    e, m = rel(got, ref), rel_max(got, ref)
+    log(f"  {name}: rel {e:.3e}, worst element {m:.3e}")
+    assert e < tol and m < (tol if tol_max is None else tol_max), (name, e, m)
+    return e, m
+
+
 def round_inputs(P, surf, precision):
     if precision == "fp64":
         return P, surf

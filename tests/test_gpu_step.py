@@ -36,7 +36,7 @@ def _gpu_step(P, surf, p, precision="fp64", implicit=True):
 TIGHT = dict(newton_tol=1e-12, cg_rel=1e-3, heat_tol=1e-13)
 
 
-@pytest.mark.parametrize("case", ["square2d", "marangoni3d_small", "meltslab_small"])
+@pytest.mark.parametrize("case", ["square2d", "marangoni3d_small", "meltslab_small", "contact_small"])
 def test_implicit_step_matches_oracle_fp64(case):
     log(f"case step {case}")
     if case == "square2d":
@@ -45,6 +45,9 @@ def test_implicit_step_matches_oracle_fp64(case):
         S["particles"]["v"] = rng.normal(size=S["particles"]["v"].shape) * 0.05
     elif case == "marangoni3d_small":
         S = sc.marangoni3d(n=32, radius=0.25)
+    elif case == "contact_small":
+        # label table k_r, slab constraint on v_y, gravity, no translation correction
+        S = sc.contact3d(n=48, radius=0.12)
     else:
         S = sc.meltslab3d(n=32)
     P, p = S["particles"], dict(S["params"], **TIGHT)
@@ -136,22 +139,61 @@ def test_explicit_steps_conserve_on_gpu():
         assert np.allclose(com, hist[0][2], rtol=0, atol=1e-13)
 
 
-def test_implicit_momentum_fix_conserves():
+EPS32 = 2.0 ** -24
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_implicit_momentum_fix_conserves(precision):
+    """Implicit steps with the translation correction and no constraint conserve the total
+    linear momentum to round-off of the arithmetic: 1e-14 of sum |m v| in FP64, 16 eps32
+    of it in MIXED (particle state in FP32, the sums and the correction in FP64)."""
     from paper_2101_12408_amd import api
     S = sc.square2d(n=32)
     P, p = S["particles"], S["params"]
     rng = np.random.default_rng(2)
     P["v"] = rng.normal(size=P["v"].shape) * 0.05
+    if precision == "mixed":
+        P = {k: v.astype(np.float32).astype(np.float64) for k, v in P.items()}
     mom0 = (P["m"][:, None] * P["v"]).sum(0)
-    s = api.Scene(p, cap_part=len(P["m"]), cap_surf=20 * len(P["m"]))
+    s = api.Scene(p, cap_part=len(P["m"]), cap_surf=20 * len(P["m"]), precision=precision)
     Pd = s.to_device(P)
     for k in range(3):
-        surf = api.sample_surface(Pd["x"].cpu().numpy().T.copy(), p, step=k)
+        surf = api.sample_surface(Pd["x"].double().cpu().numpy().T.copy(), p, step=k)
         s.step(Pd, s.to_device(S=surf), implicit=True)
-    v = Pd["v"].cpu().numpy().T
-    mom = (Pd["m"].cpu().numpy()[:, None] * v).sum(0)
-    log(f"  momentum {mom0} -> {mom}")
-    assert np.allclose(mom, mom0, rtol=0, atol=1e-14 * np.abs(P["m"][:, None] * v).sum())
+    v = Pd["v"].double().cpu().numpy().T
+    mom = (Pd["m"].double().cpu().numpy()[:, None] * v).sum(0)
+    scale = np.abs(P["m"][:, None] * v).sum()
+    bound = (1e-14 if precision == "fp64" else 16 * EPS32) * scale
+    log(f"  {precision}: momentum {mom0} -> {mom}, drift {np.abs(mom - mom0).max():.3e} (bound {bound:.3e})")
+    assert np.all(np.abs(mom - mom0) <= bound)
+
+
+def test_mixed_batched_steps_conserve_momentum():
+    """Three droplets of uneven size stepped together through mpm_step in MIXED precision:
+    each keeps its linear momentum to FP32 round-off (16 eps32 of sum |m v|) over two steps."""
+    from paper_2101_12408_amd import api
+    specs = [(16, 51, 0.05, [40, 0, 0]), (32, 52, 0.03, [0, 30, 10]), (24, 53, 0.07, [0, 0, 90])]
+    objs, Ps, mom0, Ph = [], [], [], []
+    rng = np.random.default_rng(5)
+    for n, seed, g0, grad in specs:
+        S = sc.droplet3d(n, seed, g0, grad)
+        P, p = S["particles"], S["params"]
+        P["v"] = (rng.normal(size=P["v"].shape) * 0.05).astype(np.float32).astype(np.float64)
+        s = api.Scene(p, cap_part=len(P["m"]), cap_surf=20 * len(P["m"]), precision="mixed")
+        objs.append(s)
+        Ps.append(s.to_device(P))
+        mom0.append((P["m"].astype(np.float32).astype(np.float64)[:, None] * P["v"]).sum(0))
+    for k in range(2):
+        Ss = [s.to_device(S=api.sample_surface(Pd["x"].double().cpu().numpy().T.copy(), s.params, step=k))
+              for s, Pd in zip(objs, Ps)]
+        assert api.mpm_step(objs, Ps, Ss) == 0
+    for s, Pd, m0 in zip(objs, Ps, mom0):
+        v = Pd["v"].double().cpu().numpy().T
+        m = Pd["m"].double().cpu().numpy()
+        mom = (m[:, None] * v).sum(0)
+        scale = np.abs(m[:, None] * v).sum()
+        log(f"  n={s.n}: drift {np.abs(mom - m0).max():.3e} of scale {scale:.3e}")
+        assert np.all(np.abs(mom - m0) <= 16 * EPS32 * scale)
 
 
 def test_batch_invariance_bitwise():

@@ -1,11 +1,13 @@
-"""Parity at the full size of the 3D Marangoni droplet (128^3 grid, ~560k particles, the
-benchmark workload): every operator against the vectorized oracle on the same inputs,
-in the precision and launch configuration the benchmark uses (MIXED) and in FP64."""
+"""Parity at full size: the 3D Marangoni droplet (128^3 grid, ~560k particles), every
+operator and G2P against the vectorized oracle on the same inputs, in MIXED and FP64;
+the contact-angle scene (192^3) and the melting slab (256^3, ~9.7M particles) through
+properties that hold at any size; and MIXED at 256^3 from unrounded FP64 inputs against
+the FP64 oracle, which measures what the absolute FP32 positions cost at that grid."""
 import numpy as np
 import pytest
 
 import mpm_scenes as sc
-from gpu_cases import GpuState, OracleState, log, rel, round_inputs
+from gpu_cases import GpuState, OracleState, check, log, rel, round_inputs
 
 pytestmark = pytest.mark.gpu
 
@@ -31,10 +33,8 @@ def test_fullsize_operators(full_case, precision):
     from paper_2101_12408_amd import _lib as L
     tolf = 1e-10 if precision == "fp64" else 2e-5
     assert np.array_equal(g.scene.view(L.F_PARENT).cpu().numpy(), o.split["parent"])
-    for f, ref in ((L.F_MASS, o.grid["m"]), (L.F_MOM, o.grid["mv"]), (L.F_TN, o.setup["Tn"])):
-        e = rel(g.to_natural(g.scene.view(f)), ref)
-        log(f"  field {f}: rel {e:.3e}")
-        assert e < tolf
+    for name, f, ref in (("m", L.F_MASS, o.grid["m"]), ("mv", L.F_MOM, o.grid["mv"]), ("Tn", L.F_TN, o.setup["Tn"])):
+        check(name, g.to_natural(g.scene.view(f)), ref, tolf)
     rng = np.random.default_rng(3)
     dof = o.setup["dof"]
     v = o.setup["vn"] + rng.normal(size=o.ctx.vn.shape) * 0.01 * dof[:, None]
@@ -42,30 +42,65 @@ def test_fullsize_operators(full_case, precision):
         v = v.astype(np.float32).astype(np.float64)
     grad = g.scene.grid_vector()
     g.scene.energy_grad(g.from_natural(v), grad)
-    e = rel(g.to_natural(grad)[dof], o.ctx.project(o.ctx.grad_Phi(v))[dof])
-    log(f"  energy_grad rel {e:.3e}")
-    assert e < (1e-10 if precision == "fp64" else 1e-4)
+    check("energy_grad", g.to_natural(grad)[dof], o.ctx.project(o.ctx.grad_Phi(v))[dof],
+          1e-10 if precision == "fp64" else 1e-4)
     w = rng.normal(size=o.ctx.vn.shape) * dof[:, None]
     if precision != "fp64":
         w = w.astype(np.float32).astype(np.float64)
     out = g.scene.grid_vector()
     g.scene.hessvec(g.from_natural(v), g.from_natural(w), 1.0, out)
-    e = rel(g.to_natural(out)[dof], o.ctx.project(o.ctx.hessvec(v, o.ctx.project(w), 1.0))[dof])
-    log(f"  hessvec rel {e:.3e}")
-    assert e < (1e-10 if precision == "fp64" else 1e-4)
+    check("hessvec", g.to_natural(out)[dof], o.ctx.project(o.ctx.hessvec(v, o.ctx.project(w), 1.0))[dof],
+          1e-10 if precision == "fp64" else 1e-4)
     T = (300 + rng.normal(size=o.setup["Tn"].shape)) * dof
+    if precision != "fp64":
+        T = T.astype(np.float32).astype(np.float64)
     out1 = g.scene.grid_vector(1)[0]
     g.scene.heat_apply(g.from_natural(T), out1)
-    e = rel(g.to_natural(out1)[dof], o.heat.apply(T)[dof])
-    log(f"  heat_apply rel {e:.3e}")
-    assert e < (1e-10 if precision == "fp64" else 1e-5)
+    check("heat_apply", g.to_natural(out1)[dof], o.heat.apply(T)[dof], 1e-10 if precision == "fp64" else 1e-5)
+    # G2P with merge and advection at full size (the launch configuration of the benchmark)
+    from test_gpu_parity import g2p_compare
+    vh = o.ctx.project(v)
+    g2p_compare(o, g, P, vh, T, precision, 3)
+
+
+def test_mixed_at_256_from_fp64_inputs():
+    """The melting slab's grid (256^3, dx = 1/256) with a small slab near x = 0.75, where the
+    FP32 spacing of absolute positions is largest (6e-8, 1.5e-5 dx): the MIXED path takes
+    the unrounded FP64 inputs (it stores them as FP32 itself) and is compared with the FP64
+    oracle.  Grid forces must stay within 1e-4, the MIXED force tolerance."""
+    import mpm_scenes as sc
+    from oracle import sampler
+    from paper_2101_12408_amd import _lib as L
+    S = sc.meltslab3d(n=256, lo=0.7, hi=0.78, height=0.04)
+    P, p = S["particles"], S["params"]
+    rng = np.random.default_rng(256)
+    P["v"] = rng.normal(size=P["v"].shape) * 0.01
+    surf = sampler.sample_surface(P["x"], p)
+    log(f"case 256^3 absolute FP32 positions: N={len(P['m'])} S={len(surf['s'])}; oracle set-up")
+    o = OracleState(P, surf, p)
+    g = GpuState(P, surf, p, "mixed")
+    par = g.scene.view(L.F_PARENT).cpu().numpy()
+    flips = int(np.sum(par != o.split["parent"]))
+    log(f"  parents that differ from the FP64 search: {flips} of {len(par)}")
+    assert flips <= len(par) // 1000
+    dof = o.setup["dof"]
+    for name, f, ref in (("m", L.F_MASS, o.grid["m"]), ("mv", L.F_MOM, o.grid["mv"]), ("Tn", L.F_TN, o.setup["Tn"])):
+        check(name, g.to_natural(g.scene.view(f)), ref, 1e-4)
+    v = o.setup["vn"] + rng.normal(size=o.ctx.vn.shape) * 0.01 * dof[:, None]
+    grad = g.scene.grid_vector()
+    g.scene.energy_grad(g.from_natural(v), grad)
+    check("energy_grad", g.to_natural(grad)[dof], o.ctx.project(o.ctx.grad_Phi(v))[dof], 1e-4)
+    w = rng.normal(size=o.ctx.vn.shape) * dof[:, None]
+    out = g.scene.grid_vector()
+    g.scene.hessvec(g.from_natural(v), g.from_natural(w), 1.0, out)
+    check("hessvec", g.to_natural(out)[dof], o.ctx.project(o.ctx.hessvec(v, o.ctx.project(w), 1.0))[dof], 1e-4)
 
 
 def _sum64(t):
     return t.double().sum(dim=-1).cpu().numpy()
 
 
-@pytest.mark.parametrize("case,precision", [("contact3d", "mixed"), ("meltslab3d", "fp64")])
+@pytest.mark.parametrize("case,precision", [("contact3d", "mixed"), ("meltslab3d", "fp64"), ("meltslab3d", "mixed")])
 def test_fullsize_step_properties(case, precision):
     """The contact-angle scene (192^3) and the melting slab (256^3, ~9.7M particles) at full
     size, where the oracle cannot run whole: properties that hold at any size.  P2G
