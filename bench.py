@@ -1,18 +1,28 @@
 """Benchmark of the implicit APIC MPM hot path on one MI355X.
 
-Workload: the 3D Marangoni droplet (128^3 grid on the unit cube, sphere r = 0.2 at 8
-particles per cell, ~562k particles, linear temperature 300-350 K, gamma(T) =
-0.072 - 1.5e-4 (T - 300), bulk 1e4, dt 5e-4, implicit heat solve), FP32 transfers and
-Hessian-vector products with FP64 reductions.
+Headline workload: the melting slab at the largest single-GPU size, 256^3 grid on the
+unit cube, box 0.6 x 0.2 x 0.6 at 8 particles per cell (9,663,637 particles, ~966k
+surface samples per step), T0 290 K heated by a 400 K ambient through the particle Robin
+term (h 20, K 0.25), viscosity mu(T) = 1e3 exp(-0.05 (T - 290)), gamma(T) = 0.072 -
+1.5e-4 (T - 300), gravity, slip floor, dt 1e-3, implicit Newton-CG momentum solve and
+implicit heat CG.  Precision MIXED (FP32 transfers, operators and Krylov vectors; FP64
+energies, dot products, norms and momentum sums), with the FP64 GPU path timed over the
+same number of steps beside it.
 
 A step is one full pass of the hot path: cell sort, parents / balance points / split,
 P2G with the grid set-up, the Newton-CG momentum solve, the heat CG solve, G2P with
-merge and advection.  The surface samples are an input of the step (the host sampler
-is the input stage); they are drawn for every step of the trajectory in an untimed
+merge and advection.  The surface samples are an input of the step (the host sampler is
+the input stage): they are drawn for every step of the trajectory in an untimed
 recording pass and kept in HBM, so the timed pass replays the same trajectory
-(bit-identical, the kernels are deterministic) with all inputs resident.
+(bit-identical, the kernels are deterministic) with all inputs resident.  The rate that
+includes the host sampler is reported beside (all_in).
 
-Prints one JSON line (metric, value, roofline of the dominant kernel, cpu_baseline).
+Also reported: the MIXED-vs-FP64 error of the grid forces and of one step's particle
+state on the headline workload; the other workloads (2D square droplet, Marangoni
+droplet, contact angle) in a secondary block; the serving stream; the roofline of the
+dominant kernel; the oracle on the host cores (one core and all cores).
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -28,7 +38,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 
-
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -37,28 +46,49 @@ def clone_state(P):
     return {k: v.clone() for k, v in P.items()}
 
 
-def run_gpu(scene_fn, precision, steps, warmup, want_timing):
+def free_gpu():
+    import gc
+    import torch
+    gc.collect()
+    torch.cuda.empty_cache()
+
+
+def run_gpu(scene_fn, precision, steps, warmup, want_timing, label):
+    """Records warmup + steps steps (host sampling of each step's surface, untimed), then
+    replays them with every input in HBM: the timed pass, and with want_timing a second
+    pass with per-launch HIP events for the per-class breakdown."""
     import torch
     from paper_2101_12408_amd import api
     S = scene_fn()
     P0, p = S["particles"], S["params"]
     N = len(P0["m"])
     t0 = time.perf_counter()
+    ts = time.perf_counter()
     surf0 = api.sample_surface(P0["x"], p, step=0)
+    sample_s = [time.perf_counter() - ts]
     cap_s = int(len(surf0["s"]) * 1.5) + 1024
     scene = api.Scene(p, cap_part=N, cap_surf=cap_s, precision=precision)
     Pd = scene.to_device(P0)
     init = clone_state(Pd)
-    # recording pass (untimed): warmup + steps, surface samples of every step kept in HBM
-    surfs = []
+    surfs, upload_s = [], []
     for k in range(warmup + steps):
-        xh = Pd["x"].double().cpu().numpy().T.copy()
-        surf = surf0 if k == 0 else api.sample_surface(xh, p, step=k)
+        if k > 0:
+            ts = time.perf_counter()
+            xh = Pd["x"].double().cpu().numpy().T.copy()
+            surf = api.sample_surface(xh, p, step=k)
+            sample_s.append(time.perf_counter() - ts)
+        else:
+            surf = surf0
+        torch.cuda.synchronize()
+        tu = time.perf_counter()
         Sd = scene.to_device(S=surf)
+        torch.cuda.synchronize()
+        upload_s.append(time.perf_counter() - tu)
         surfs.append(Sd)
         scene.step(Pd, Sd)
-    log(f"{precision}: recorded {warmup + steps} steps in {time.perf_counter() - t0:.1f} s "
-        f"(N={N}, S~{len(surf0['s'])})")
+    log(f"{label} {precision}: recorded {warmup + steps} steps in {time.perf_counter() - t0:.1f} s "
+        f"(N={N}, S~{len(surf0['s'])}, host sampling {np.mean(sample_s):.3f} s/step)")
+
     def replay(timed_events):
         for k, v in init.items():
             Pd[k].copy_(v)
@@ -77,7 +107,7 @@ def run_gpu(scene_fn, precision, steps, warmup, want_timing):
         elapsed = time.perf_counter() - t0
         timing = None
         if timed_events:
-            timing = scene.timing_read()
+            timing = dict(all=scene.timing_read(), work=scene.timing_read(work=True))
             scene.timing(False)
         return elapsed, stats, timing
 
@@ -87,91 +117,130 @@ def run_gpu(scene_fn, precision, steps, warmup, want_timing):
     timing, elapsed_ev = None, None
     if want_timing:
         elapsed_ev, _, timing = replay(True)
-        log(f"{precision}: {1e3 * elapsed / steps:.3f} ms/step, with per-launch events {1e3 * elapsed_ev / steps:.3f}")
-    return dict(N=N, elapsed=elapsed, elapsed_events=elapsed_ev, stats=stats, timing=timing, S=len(surf0["s"]),
-                params=p)
+    log(f"{label} {precision}: {1e3 * elapsed / steps:.3f} ms/step"
+        + (f", with per-launch events {1e3 * elapsed_ev / steps:.3f}" if want_timing else ""))
+    out = dict(N=N, elapsed=elapsed, elapsed_events=elapsed_ev, stats=stats, timing=timing, S=len(surf0["s"]),
+               params=p, sample_s=float(np.sum(sample_s[warmup:])), upload_s=float(np.sum(upload_s[warmup:])))
+    del scene, Pd, init, surfs
+    free_gpu()
+    return out
 
 
-def cpu_baseline():
-    """Runs the oracle timing in a child process pinned to one BLAS/OpenMP thread, so the
-    reported core count is the number of threads actually used."""
-    import subprocess
-    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
-               HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
-    code = "import json, bench; print(json.dumps(bench._cpu_baseline_inproc()))"
-    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True,
-                       timeout=600)
-    if r.returncode != 0:
-        log(f"cpu baseline failed: {r.stderr[-500:]}")
-        return None
-    return json.loads(r.stdout.strip().splitlines()[-1])
+def per_step(stats, key):
+    return round(float(np.mean([s[key] for s in stats])), 2)
 
 
-def _cpu_baseline_inproc():
-    """The oracle, timed on the host on a bounded sample: one full implicit step of the
-    same Marangoni scene at the same grid (128^3), particle density and parameters, with
-    a droplet of radius 0.1 instead of 0.2 (1/8 of the particles)."""
-    import mpm_scenes as sc
-    from oracle import sampler, step as ostep
-    S = sc.marangoni3d(radius=0.1)
+def summary(r, steps):
+    st = r["stats"]
+    return dict(value=round(r["N"] * steps / r["elapsed"], 1), unit="particle-steps/s",
+                ms_per_step=round(1e3 * r["elapsed"] / steps, 3), steps=steps, particles=r["N"],
+                surface_samples=r["S"], newton_iters_per_step=per_step(st, "newton_iters"),
+                cg_iters_per_step=per_step(st, "cg_iters"), heat_iters_per_step=per_step(st, "heat_iters"),
+                hessvec_per_s=round(sum(s["hessvecs"] for s in st) / r["elapsed"], 1),
+                converged=[int(s["converged"]) for s in st][:3] + (["..."] if len(st) > 3 else []))
+
+
+def mixed_vs_fp64(scene_fn):
+    """MIXED against FP64 on the same inputs (FP64 host state, one set of surface samples):
+    the grid forces P grad Phi at v^ = v^n of the FP64 grid, and the particle state after
+    one implicit step (v, T, and the updates of x and J), each as the norm-wise relative
+    error and the worst element relative to the largest FP64 value."""
+    import torch
+    from paper_2101_12408_amd import _lib as L
+    from paper_2101_12408_amd import api
+    S = scene_fn()
     P, p = S["particles"], S["params"]
-    surf = sampler.sample_surface(P["x"], p)
-    t0 = time.perf_counter()
-    _, info = ostep.step(P, p, surf)
-    dt = time.perf_counter() - t0
-    n = len(P["m"])
-    return dict(value=n / dt, unit="particle-steps/s", cores=1, kind="oracle",
-                sample=f"one implicit step of marangoni3d at 128^3 with droplet radius 0.1 "
-                       f"({n} particles, {len(surf['s'])} surface samples; newton {info['newton']}, "
-                       f"cg {info['cg']}, heat cg {info.get('heat_cg')}): {dt:.1f} s single-threaded numpy")
+    surf = api.sample_surface(P["x"], p, step=0)
+    N = len(P["m"])
+    res, grads, outs = {}, {}, {}
+    for prec in ("fp64", "mixed"):
+        s = api.Scene(p, cap_part=N, cap_surf=len(surf["s"]) + 1024, precision=prec)
+        Pd, Sd = s.to_device(P, surf)
+        s.p2g(Pd, Sd)
+        if prec == "fp64":
+            vref = s.view(L.F_VN).clone()
+        g = s.grid_vector()
+        s.energy_grad(vref.to(s.dtype), g)
+        grads[prec] = g.double().cpu().numpy()
+        x0 = Pd["x"].double().clone()
+        J0 = Pd["J"].double().clone()
+        s.step(Pd, Sd)
+        perm = s.view(L.F_PERM).long()
+        inv = torch.empty_like(perm)
+        inv[perm] = torch.arange(N, device=perm.device)
+        outs[prec] = dict(v=Pd["v"].double()[:, inv].cpu().numpy(), T=Pd["T"].double()[inv].cpu().numpy(),
+                          dx=(Pd["x"].double()[:, inv] - x0).cpu().numpy(), dJ=(Pd["J"].double()[inv] - J0).cpu().numpy())
+        del s, Pd, Sd
+        free_gpu()
+
+    def err(a, b):
+        return dict(rel=float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)),
+                    worst=float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)))
+
+    res["grid_forces"] = err(grads["mixed"], grads["fp64"])
+    for k in ("v", "T", "dx", "dJ"):
+        res[f"step_{k}"] = err(outs["mixed"][k], outs["fp64"][k])
+    log("mixed vs fp64: " + ", ".join(f"{k} {v['rel']:.2e}/{v['worst']:.2e}" for k, v in res.items()))
+    return {k: {kk: float(f"{vv:.3e}") for kk, vv in v.items()} for k, v in res.items()}
 
 
-# Algorithmic bytes and flops per launch of each timed kernel class.  Bytes: the minimum
-# the method moves (each needed particle field read once, each output written once, each
-# active node's fields read or written once), R bytes per real (4 in MIXED, 8 in FP64), 4
-# per int32.  Flops: the method's arithmetic in direct tensor-product form over the 3^d
-# stencil (3D counts): per point the 1D weight tables and the 27 node weights and
-# gradients (252), then per node what the kernel accumulates, e.g. the gradient gather
-# sum_i u_i (x) grad N_i (9 FMA = 18 flops) and the stress scatter S grad N_i (18 flops).
-#   energy / Hessian, interior: 252 + 486 + ~15 + 486 = ~1240; surface: ~1350 / ~1420
-#   heat operator: interior 252 + 162 + 162 = ~580; surface (value only) ~360
-#   P2G: interior ~62 per node (~1930); surface and balance points ~42 per node (~1390)
-#   G2P: interior ~38 per node (~1280); each surface and balance member ~24 per node (~900)
+# ---------------------------------------------------------------------------------------
+# Algorithmic bytes and flops per launch, per unit of work (3D; R bytes per real: 4 in
+# MIXED, 8 in FP64; 4 per int32).  Bytes: each needed particle field read once, each
+# output written once, each active node's fields read or written once.  Flops: the
+# method's arithmetic per point for the scene's own terms.
+#   Hessian-vector product, point kernel: interior x3 + c_J + mu V^n (5 reals), surface
+#     s3 dA3 k + cached F9 (16 reals), nodes: w3 read (the merge writes the output);
+#     flops J-only ~450 per interior particle, ~1100 with viscosity, ~1500 per surface
+#     sample.
+#   Energy / gradient, point kernel: interior x3 J V0 mu V^n (6), surface s3 dA3 k (7),
+#     nodes v^3; flops as the Hessian plus the energy, ~500 / ~1150 / ~1500.
+#   Heat operator, point kernel: interior x3 + K V^n (4), surface s3 + h|dA| (4), nodes T;
+#     ~400 per interior particle, ~200 per sample.
+#   P2G: x3 v3 A9 m T gradT3 + count (20 reals + int), surface s3 + parent, nodes m mv3
+#     W WT E ET written; ~700 per interior particle, ~400 per surface or balance point.
+#   G2P: x3 J + count read, v3 A9 T gradT3 x3 J written, surface s3 + parent, nodes v^3 T;
+#     ~750 per interior particle, ~300 per surface or balance point.
+#   Node merges: read the partials of each node's tiles and the node fields, write one
+#     vector; ~10 flops per node.
 # N interior particles, S surface samples (each with its balance point), G nodes of the
 # active tiles.
-def algorithmic(cls, N, S, G, R, dim=3):
+# ---------------------------------------------------------------------------------------
+def algorithmic(cls, N, S, G, R, visc, dim=3):
     d, d2, I = dim, dim * dim, 4
-    if cls == "p2g":           # read x v A m T gradT + group count; s + parent; write m mv W WT E ET
+    fi = 1100 if visc else 450
+    if cls == "hess_int":
+        return dict(bytes=N * (d + 2) * R + S * (2 * d + 1 + d2) * R + G * d * R, flops=N * fi + S * 1500)
+    if cls == "energy_int":
+        return dict(bytes=N * (d + 3) * R + S * (2 * d + 1) * R + G * d * R,
+                    flops=N * (fi + 50) + S * 1500)
+    if cls == "heat_pt":
+        return dict(bytes=N * (d + 1) * R + S * (d + 1) * R + G * R, flops=N * 400 + S * 200)
+    if cls == "p2g":
         return dict(bytes=N * ((3 * d + d2 + 2) * R + I) + S * (d * R + I) + G * (d + 5) * R,
-                    flops=N * 1930 + 2 * S * 1390)
-    if cls == "energy_int":    # read x J V0 muV, s dA k, v^ at the nodes
-        return dict(bytes=N * (d + 3) * R + S * (2 * d + 1) * R + G * d * R, flops=N * 1240 + S * 1350)
-    if cls == "hess_int":      # read x cJ muV, s dA k + cached F (d^2), w at the nodes
-        return dict(bytes=N * (d + 2) * R + S * (2 * d + 1 + d2) * R + G * d * R, flops=N * 1240 + S * 1420)
-    if cls in ("energy_node", "hess_node"):   # read w/v^, v^n, m, flags; write out
-        return dict(bytes=G * ((2 * d + 1) * R + 1 + d * R), flops=G * 8 * d)
-    if cls == "heat_pt":       # read x KV, s h|dA|, T at the nodes
-        return dict(bytes=N * (d + 1) * R + S * (d + 1) * R + G * R, flops=N * 580 + S * 360)
+                    flops=N * 700 + 2 * S * 400)
+    if cls == "g2p":
+        return dict(bytes=N * ((d + 1) * R + I) + N * (d + d2 + 1 + d + d + 1) * R + S * (d * R + I)
+                    + G * (d + 1) * R, flops=N * 750 + 2 * S * 300)
+    if cls in ("energy_node", "hess_node"):
+        return dict(bytes=G * ((2 * d + 1) * R + 1 + d * R), flops=G * 10)
     if cls == "heat_node":
         return dict(bytes=G * (3 * R + 1), flops=G * 4)
-    if cls == "g2p":           # read x J count, s + parent, v^ T^; write v A T gradT x J
-        return dict(bytes=N * ((d + 1) * R + I) + N * (d + d2 + 1 + d + d + 1) * R + S * (d * R + I) + G * (d + 1) * R,
-                    flops=N * 1280 + 2 * S * 900)
     return None
 
 
-HBM_PEAK = 8000.0      # GB/s
-VALU_PEAK = {4: 157.3, 8: 78.6}   # TFLOP/s, vector FP32 / FP64
+HBM_PEAK = 8000.0                    # GB/s, MI355X
+VALU_PEAK = {4: 157.3, 8: 78.6}      # TFLOP/s, MI355X vector FP32 (packed) / FP64
 
 
-def roofline_of(cls, tm, N, S, G, R, K, traffic, hessvecs=None):
-    """Roofline of one kernel class.  The Hessian classes are averaged over the operator
-    applications that did work (hessvecs): a CG queued ahead of a Newton decision that
-    the device then calls off still launches, and its kernels return at once."""
-    ms, launches = tm[cls]
-    work = hessvecs if (hessvecs and cls in ("hess_int", "hess_node")) else launches
+def roofline_of(cls, tm, N, S, G, R, K, visc, traffic):
+    """Roofline of one kernel class from its average launch time over the launches that
+    did work (tm: the work totals of the timing read): a CG queued ahead of a Newton
+    decision that the device then calls off still launches, and its kernels return at
+    once."""
+    ms, work = tm[cls]
     avg_s = ms / work * 1e-3
-    alg = algorithmic(cls, N, S, G, R)
+    alg = algorithmic(cls, N, S, G, R, visc)
     gbs = alg["bytes"] / avg_s / 1e9
     tfl = alg["flops"] / avg_s / 1e12
     t_hbm = alg["bytes"] / (HBM_PEAK * 1e9)
@@ -198,15 +267,15 @@ def kernel_sources_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(cls, precision):
+def measured_traffic(cls, precision, workload):
     """HBM bytes per launch from the committed PMC summary, if it was taken on the current
-    kernel sources (else None)."""
+    kernel sources and workload (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         t = json.load(fh)
-    e = t.get(f"{cls}:{precision}")
+    e = t.get(f"{workload}:{cls}:{precision}")
     if not e or e.get("sources") != kernel_sources_digest():
         return None
     return e.get("bytes_per_launch")
@@ -258,13 +327,201 @@ def run_serving(count, rate, precision, concurrency, budget_bytes):
                 peak_running=info["peak_running"], peak_gb=round(info["peak_bytes"] / 2 ** 30, 3), failed=failed)
 
 
+# ---------------------------------------------------------------------------------------
+# CPU baseline: the oracle (plain numpy FP64) on the host cores.  One implicit step of the
+# headline workload takes the oracle minutes even on a small part of the slab (its grids
+# are dense 256^3 arrays and the viscous system takes ~110 CG iterations per step), so the
+# sample is bounded: on a sub-slab of the same 256^3 grid, same density and physics, it
+# times P2G with the grid set-up, one energy-and-gradient evaluation, one iteration of the
+# Newton-CG, one iteration of the heat CG and G2P, and scales them to one step with the
+# per-step counts of the timed GPU run (energy evaluations, CG and heat CG iterations).
+# ---------------------------------------------------------------------------------------
+CPU_SAMPLE = dict(lo=0.44, hi=0.56, height=0.06)
+
+
+def _cpu_sample_inproc(seed, n_energy, n_cg, n_heat):
+    import mpm_scenes as sc
+    from oracle import energy, resample, sampler, solve, transfer
+    S = sc.meltslab3d(seed=seed, **CPU_SAMPLE)
+    P, p = S["particles"], S["params"]
+    surf = sampler.sample_surface(P["x"], p)
+    T = {}
+    t = time.perf_counter()
+    sp = resample.split(P, surf)
+    g = transfer.p2g(P, surf, sp, p)
+    st = transfer.grid_setup(P, surf, sp, g, p)
+    ctx = energy.Context(P, surf, g, st, p)
+    heat = solve.Heat(P, surf, g, st, p)
+    T["p2g_setup"] = time.perf_counter() - t
+    v = ctx.project(ctx.vn.copy())
+    t = time.perf_counter()
+    ctx.Phi(v)
+    gr = ctx.project(ctx.grad_Phi(v))
+    T["energy"] = time.perf_counter() - t
+    diag = ctx.jacobi_diag()
+    t = time.perf_counter()
+    solve.pcg(lambda w: ctx.project(ctx.hessvec(v, ctx.project(w))), -gr, diag, 0.0, 1)
+    T["cg_iter"] = time.perf_counter() - t
+    hd = heat.diag()
+    t = time.perf_counter()
+    solve.pcg(heat.apply, heat.rhs, hd, 0.0, 1, x0=heat.Tn.copy())
+    T["heat_iter"] = time.perf_counter() - t
+    t = time.perf_counter()
+    transfer.g2p(P, surf, sp, v, st["Tn"], p)
+    T["g2p"] = time.perf_counter() - t
+    step_s = T["p2g_setup"] + n_energy * T["energy"] + n_cg * T["cg_iter"] + n_heat * T["heat_iter"] + T["g2p"]
+    return dict(N=len(P["m"]), S=len(surf["s"]), parts={k: round(x, 3) for k, x in T.items()},
+                measured_s=sum(T.values()), step_s=step_s)
+
+
+def cpu_baseline(n_energy, n_cg, n_heat):
+    """The oracle timing: one child process pinned to one BLAS/OpenMP thread, then one
+    child per host core (each on its own seeded sub-slab) at the same time."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
+               HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
+
+    def launch(seed):
+        code = (f"import json, bench; print(json.dumps(bench._cpu_sample_inproc({seed}, {n_energy}, {n_cg}, "
+                f"{n_heat})))")
+        return subprocess.Popen([sys.executable, "-c", code], cwd=ROOT, env=env, stdout=subprocess.PIPE,
+                                stderr=subprocess.PIPE, text=True)
+
+    def collect(pr):
+        out, errs = pr.communicate(timeout=900)
+        if pr.returncode != 0:
+            log(f"cpu baseline child failed: {errs[-400:]}")
+            return None
+        return json.loads(out.strip().splitlines()[-1])
+
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
+    except Exception:
+        pass
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    one = collect(launch(100))
+    if one is None:
+        return None
+    rate1 = one["N"] / one["step_s"]
+    log(f"cpu oracle, 1 core: {rate1:.1f} particle-steps/s ({one['measured_s']:.1f} s measured; parts {one['parts']})")
+    # all cores: as many samples at once as cores (at most 16), each ~5 GB of host memory
+    k = max(1, min(cores, 16))
+    t0 = time.perf_counter()
+    runs = [collect(p) for p in [launch(100 + j) for j in range(k)]]
+    runs = [r for r in runs if r]
+    wall = time.perf_counter() - t0
+    rate_all = sum(r["N"] / r["step_s"] for r in runs)
+    log(f"cpu oracle, {len(runs)} cores: {rate_all:.1f} particle-steps/s (wall {wall:.1f} s)")
+    sample = (f"melting slab on the same 256^3 grid, sub-slab x,z in [{CPU_SAMPLE['lo']},{CPU_SAMPLE['hi']}], "
+              f"height {CPU_SAMPLE['height']}, 8 ppc ({one['N']} particles, {one['S']} surface samples): P2G with "
+              f"the grid set-up, 1 energy evaluation, 1 Newton-CG iteration, 1 heat-CG iteration and G2P timed "
+              f"({one['measured_s']:.1f} s), scaled to one step with the GPU run's per-step counts ({n_energy} "
+              f"energy evaluations, {n_cg} CG and {n_heat} heat-CG iterations); all cores: {len(runs)} such "
+              f"samples at once, one per process")
+    return dict(value=round(rate1, 1), unit="particle-steps/s", cores=1, kind="oracle", sample=sample,
+                all_cores=dict(value=round(rate_all, 1), cores=len(runs), wall_s=round(wall, 1)),
+                cpu_model=model, host_cores=cores, parts_1core=one["parts"])
+
+
+# ---------------------------------------------------------------------------------------
+# Summaries of rocprofv3 output (host only): the kernel-trace table and the PMC traffic
+# per launch that profiles/ holds.
+# ---------------------------------------------------------------------------------------
+KERNEL_CLASS_OF = {"k_tile_stress<3, float, 1>": "hess_int", "k_tile_stress<3, double, 1>": "hess_int",
+                   "k_tile_stress<3, float, 0>": "energy_int", "k_tile_stress<3, double, 0>": "energy_int",
+                   "k_tile_heat<3, float>": "heat_pt", "k_tile_heat<3, double>": "heat_pt",
+                   "k_tile_p2g<3, float>": "p2g", "k_tile_p2g<3, double>": "p2g",
+                   "k_tile_g2p<3, float>": "g2p", "k_tile_g2p<3, double>": "g2p",
+                   "k_merge_heat<3, float>": "heat_node", "k_merge_heat<3, double>": "heat_node"}
+
+
+def _short(name):
+    n = name.split("(")[0]
+    for pre in ("void ", "mpm::"):
+        n = n.replace(pre, "")
+    return n
+
+
+def _work_launches(vals):
+    """Launches that did work: a CG called off on the device still launches its kernels,
+    which return at once; they are left out (below a tenth of the 95th percentile)."""
+    v = np.asarray(vals, np.float64)
+    return v[v >= 0.1 * np.percentile(v, 95)] if len(v) else v
+
+
+def summarize_ktrace(d):
+    import csv
+    import glob
+    path = glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True)[0]
+    dur = {}
+    for r in csv.DictReader(open(path)):
+        dur.setdefault(_short(r["Kernel_Name"]), []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
+    total = sum(sum(v) for v in dur.values())
+    lines = [f"# {'kernel':58s} {'calls':>7s} {'avg_us':>10s} {'total_ms':>10s} {'pct':>6s} {'work_n':>7s} {'work_us':>9s}"]
+    for k, v in sorted(dur.items(), key=lambda kv: -sum(kv[1]))[:30]:
+        w = _work_launches(v)
+        lines.append(f"  {k[:58]:58s} {len(v):7d} {np.mean(v):10.2f} {sum(v) * 1e-3:10.3f} {100 * sum(v) / total:6.2f} "
+                     f"{len(w):7d} {np.mean(w):9.2f}")
+    return "\n".join(lines)
+
+
+def summarize_pmc(fetch_dir, write_dir, workload, precision):
+    """Per-launch HBM bytes of the tile kernels from a FETCH_SIZE pass and a WRITE_SIZE pass
+    (KiB per dispatch), each scaled by what the counter reads for the 512 MiB device copy
+    of --copy-calibration in the same run; written to profiles/traffic.json."""
+    import csv
+    import glob
+
+    def load(d, counter):
+        path = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
+        out = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] == counter:
+                out.setdefault(_short(r["Kernel_Name"]), []).append(float(r["Counter_Value"]) * 1024.0)
+        return out
+
+    fetch, write = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
+    copy = 512 * 2 ** 20
+
+    def factor(tab):
+        vals = [max(v) for k, v in tab.items() if "copyBuffer" in k or "copy" in k.lower()]
+        big = max(vals) if vals else 0.0
+        return copy / big if big > 0.25 * copy else 1.0
+
+    ff, fw = factor(fetch), factor(write)
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    table = json.load(open(path)) if os.path.exists(path) else {}
+    lines = [f"# copy kernel: factors fetch x{ff:.3f}, write x{fw:.3f}",
+             f"# {'kernel':40s} {'n':>5s} {'fetch_MB':>10s} {'write_MB':>10s} {'total_MB':>10s}"]
+    for k in sorted(fetch, key=lambda k: -sum(fetch[k])):
+        if k not in KERNEL_CLASS_OF:
+            continue
+        fv = _work_launches(fetch[k])
+        wv = _work_launches(write.get(k, [0.0]))
+        fb, wb = float(np.mean(fv)) * ff, float(np.mean(wv)) * fw
+        lines.append(f"  {k:40s} {len(fv):5d} {fb / 1e6:10.2f} {wb / 1e6:10.2f} {(fb + wb) / 1e6:10.2f}")
+        table[f"{workload}:{KERNEL_CLASS_OF[k]}:{precision}"] = dict(
+            kernel=k, bytes_per_launch=int(fb + wb), fetch_bytes=int(fb), write_bytes=int(wb),
+            fetch_factor=round(ff, 4), write_factor=round(fw, 4), sources=kernel_sources_digest())
+    with open(path, "w") as fh:
+        json.dump(table, fh, indent=1, sort_keys=True)
+    return "\n".join(lines)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
-    ap.add_argument("--fp64-steps", type=int, default=3, help="steps of the FP64 GPU comparison run (0: skip)")
+    ap.add_argument("--workload", default="meltslab3d", choices=["meltslab3d", "marangoni3d", "contact3d"],
+                    help="headline workload (default: the 256^3 melting slab)")
+    ap.add_argument("--fp64-steps", type=int, default=-1,
+                    help="steps of the FP64 GPU comparison run (-1: as --steps; 0: skip)")
+    ap.add_argument("--no-errors", action="store_true", help="skip the MIXED-vs-FP64 error report")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the other workloads")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=512,
@@ -272,7 +529,18 @@ def main():
     ap.add_argument("--serving-concurrency", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (PMC traffic calibration)")
+    ap.add_argument("--summarize-ktrace", metavar="DIR", help="print the kernel table of a rocprofv3 "
+                    "--kernel-trace output directory and exit (no GPU)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="update profiles/traffic.json from a FETCH_SIZE and a WRITE_SIZE rocprofv3 --pmc "
+                    "output directory of the workload and precision given, print the table and exit (no GPU)")
     args = ap.parse_args()
+    if args.summarize_ktrace:
+        print(summarize_ktrace(args.summarize_ktrace))
+        return
+    if args.summarize_pmc:
+        print(summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload, args.precision))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path; run with --gpus 1",
               file=sys.stderr)
@@ -282,39 +550,60 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     import mpm_scenes as sc
-    scene_fn = sc.marangoni3d
+    scene_fn = sc.CONFIGS[args.workload]
     if args.copy_calibration:
         copy_calibration()
-    main_run = run_gpu(scene_fn, args.precision, args.steps, args.warmup, not args.no_timing)
-    N, K = main_run["N"], args.steps
+    K = args.steps
+    main_run = run_gpu(scene_fn, args.precision, K, args.warmup, not args.no_timing, args.workload)
+    N = main_run["N"]
     value = N * K / main_run["elapsed"]
-    ms_per_step = 1e3 * main_run["elapsed"] / K
     st = main_run["stats"]
     hv = sum(s["hessvecs"] for s in st)
     G = int(np.mean([s["n_tiles"] for s in st])) * 64
     S = int(np.mean([s["n_surf"] for s in st]))
+    visc = main_run["params"]["mu0"] > 0 and (main_run["params"]["term_mask"] & 4)
     out_extra = {}
     roofline = None
     R = 4 if args.precision == "mixed" else 8
     if main_run["timing"]:
-        tm = main_run["timing"]
-        total = sum(v[0] for v in tm.values())
-        out_extra["kernel_ms_per_step"] = {k: round(v[0] / K, 4) for k, v in tm.items() if v[1]}
-        cand = [k for k in tm if tm[k][1] and algorithmic(k, N, S, G, R)]
-        dom = max(cand, key=lambda k: tm[k][0])
-        roofline = roofline_of(dom, tm, N, S, G, R, K, measured_traffic(dom, args.precision), hv)
-        out_extra["kernel_rooflines"] = {k: {kk: roofline_of(k, tm, N, S, G, R, K, None, hv)[kk]
+        tma, tm = main_run["timing"]["all"], main_run["timing"]["work"]
+        total = sum(v[0] for v in tma.values())
+        out_extra["kernel_ms_per_step"] = {k: round(v[0] / K, 4) for k, v in tma.items() if v[1]}
+        cand = [k for k in tm if tm[k][1] and algorithmic(k, N, S, G, R, visc)]
+        dom = max(cand, key=lambda k: tma[k][0])
+        roofline = roofline_of(dom, tm, N, S, G, R, K, visc, measured_traffic(dom, args.precision, args.workload))
+        out_extra["kernel_rooflines"] = {k: {kk: roofline_of(k, tm, N, S, G, R, K, visc, None)[kk]
                                              for kk in ("avg_launch_us", "hbm_frac", "valu_frac")} for k in cand}
         # summed kernel time of both streams per step over the event-free step time (above 1
         # where the heat solve's stream overlaps the momentum solve's)
         out_extra["kernel_sum_over_step"] = round(total / (main_run["elapsed"] * 1e3), 3)
         out_extra["ms_per_step_with_events"] = round(1e3 * main_run["elapsed_events"] / K, 3)
+    # the host sampler (input stage) and the upload of its samples included
+    all_in = N * K / (main_run["elapsed"] + main_run["sample_s"] + main_run["upload_s"])
     fp64 = None
-    if args.fp64_steps > 0 and args.precision != "fp64":
-        r64 = run_gpu(scene_fn, "fp64", args.fp64_steps, 1, False)
-        v64 = r64["N"] * args.fp64_steps / r64["elapsed"]
-        fp64 = dict(value=round(v64, 1), unit="particle-steps/s", steps=args.fp64_steps,
-                    speedup_mixed_over_fp64=round(value / v64, 3))
+    k64 = K if args.fp64_steps < 0 else args.fp64_steps
+    if k64 > 0 and args.precision != "fp64":
+        r64 = run_gpu(scene_fn, "fp64", k64, args.warmup, False, args.workload)
+        fp64 = summary(r64, k64)
+        fp64["speedup_mixed_over_fp64"] = round(value / fp64["value"], 3)
+    errors = None
+    if not args.no_errors and args.precision != "fp64":
+        errors = mixed_vs_fp64(scene_fn)
+    secondary = None
+    if not args.no_secondary:
+        secondary = {}
+        plan = [("square2d", ["fp64"], 5), ("marangoni3d", ["mixed", "fp64"], 20),
+                ("contact3d", ["mixed", "fp64"], 50)]
+        for name, precs, steps in plan:
+            if name == args.workload:
+                continue
+            secondary[name] = {}
+            for prec in precs:
+                r = run_gpu(sc.CONFIGS[name], prec, steps, 2, False, name)
+                secondary[name][prec] = summary(r, steps)
+            if len(precs) == 2:
+                secondary[name]["speedup_mixed_over_fp64"] = round(
+                    secondary[name]["mixed"]["value"] / secondary[name]["fp64"]["value"], 3)
     serving = None
     if args.serving_requests > 0:
         free, _ = torch.cuda.mem_get_info()
@@ -324,9 +613,19 @@ def main():
         serving = dict(batched=mixed, one_at_a_time_fp64=base,
                        throughput_speedup=round(mixed["particle_steps_per_s"] / base["particle_steps_per_s"], 3),
                        p99_speedup=round(base["p99_ms"] / mixed["p99_ms"], 3))
-    cpu = None if args.no_cpu_baseline else cpu_baseline()
-    if cpu:
-        cpu["value"] = round(cpu["value"], 1)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(max(1, round(np.mean([s["energy_evals"] for s in st]))),
+                           max(1, round(np.mean([s["cg_iters"] for s in st]))),
+                           max(1, round(np.mean([s["heat_iters"] for s in st]))))
+    p = main_run["params"]
+    wl = {"meltslab3d": f"meltslab3d: 256^3 grid, slab 0.6x0.2x0.6 at 8 ppc, {N} particles, ~{S} surface samples, "
+                        f"mu(T)=1e3 exp(-0.05(T-290)), Robin heating h=20 to 400 K, gravity, slip floor, dt 1e-3, "
+                        f"implicit Newton-CG + heat CG",
+          "marangoni3d": f"marangoni3d: 128^3 grid, sphere r=0.2 at 8 ppc, {N} particles, ~{S} surface samples, "
+                         f"dt 5e-4, implicit Newton-CG + heat CG",
+          "contact3d": f"contact3d: 192^3 grid, cap r=0.15 on a slab at 8 ppc, {N} particles, ~{S} surface samples, "
+                       f"dt 5e-4, implicit Newton-CG"}[args.workload]
     line = {
         "metric": "implicit MPM particle-steps/s",
         "value": round(value, 1),
@@ -334,22 +633,25 @@ def main():
         "n_gpus": 1,
         "steps": K,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": round(1e3 * main_run["elapsed"] / K, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32" if args.precision == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": "marangoni3d: 128^3 grid, sphere r=0.2 at 8 ppc, "
-                               f"{N} particles, ~{S} surface samples, dt 5e-4, implicit Newton-CG + heat CG",
-                   "precision": args.precision, "global_batch": N},
+        "config": {"workload": wl, "precision": args.precision, "global_batch": N, "dt": p["dt"], "n": p["n"]},
         "hessvec_per_s": round(hv / main_run["elapsed"], 1),
-        "newton_iters_per_step": round(np.mean([s["newton_iters"] for s in st]), 2),
-        "cg_iters_per_step": round(np.mean([s["cg_iters"] for s in st]), 2),
-        "heat_iters_per_step": round(np.mean([s["heat_iters"] for s in st]), 2),
+        "newton_iters_per_step": per_step(st, "newton_iters"),
+        "cg_iters_per_step": per_step(st, "cg_iters"),
+        "heat_iters_per_step": per_step(st, "heat_iters"),
+        "all_in": dict(value=round(all_in, 1), unit="particle-steps/s",
+                       host_sampling_s_per_step=round(main_run["sample_s"] / K, 4),
+                       upload_s_per_step=round(main_run["upload_s"] / K, 4)),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fp64_gpu": fp64,
+        "mixed_vs_fp64_error": errors,
+        "secondary": secondary,
         "serving": serving,
     }
     line.update(out_extra)

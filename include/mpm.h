@@ -258,8 +258,11 @@ int mpm_get_stats(const mpm_ctx* ctx, mpm_stats* out);
  * begin and end (hipExtLaunchKernel), 0 stops it.  Host only. */
 int mpm_timing(mpm_ctx* ctx, int32_t enable);
 /* Synchronizes on the recorded events and returns, per kernel class, the summed
- * duration in milliseconds (ms[MPM_K_COUNT]) and the number of launches. */
-int mpm_timing_read(mpm_ctx* ctx, double* ms, int64_t* launches);
+ * duration in milliseconds (ms[MPM_K_COUNT]) and the number of launches; work_ms and
+ * work_launches (each may be NULL) the same over the launches that did work (a CG that
+ * the device has called off still launches its kernels, which return at once: launches
+ * shorter than a tenth of the class's 95th-percentile duration are left out). */
+int mpm_timing_read(mpm_ctx* ctx, double* ms, int64_t* launches, double* work_ms, int64_t* work_launches);
 /* Latched device status of the context (synchronizes the stream). */
 int mpm_scene_status(mpm_ctx* ctx, void* stream);
 

@@ -86,7 +86,7 @@ EXPORTS = {
     "mpm_grid_view": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]),
     "mpm_get_stats": (C.c_int, [C.c_void_p, C.POINTER(MpmStats)]),
     "mpm_timing": (C.c_int, [C.c_void_p, C.c_int32]),
-    "mpm_timing_read": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mpm_timing_read": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mpm_scene_status": (C.c_int, [C.c_void_p, C.c_void_p]),
     "mpm_server_clock": (C.c_double, []),
     "mpm_server_create": (C.c_int, [C.c_void_p, C.c_size_t, C.c_int32, C.POINTER(C.c_void_p)]),

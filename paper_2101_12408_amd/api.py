@@ -237,11 +237,17 @@ class Scene:
         """Starts (and resets) or stops per-kernel-class HIP-event timing."""
         _check(self.lib.mpm_timing(self.ctx, 1 if enable else 0), self.lib, self.ctx)
 
-    def timing_read(self):
-        """{kernel class: (total ms, launches)} since timing was enabled."""
-        ms = (C.c_double * len(L.KERNEL_CLASSES))()
-        cnt = (C.c_int64 * len(L.KERNEL_CLASSES))()
-        _check(self.lib.mpm_timing_read(self.ctx, C.cast(ms, C.c_void_p), C.cast(cnt, C.c_void_p)), self.lib, self.ctx)
+    def timing_read(self, work=False):
+        """{kernel class: (total ms, launches)} since timing was enabled; with work=True
+        (total ms, launches) over the launches that did work (a called-off CG's launches,
+        which return at once, left out)."""
+        n = len(L.KERNEL_CLASSES)
+        ms, cnt = (C.c_double * n)(), (C.c_int64 * n)()
+        wms, wcnt = (C.c_double * n)(), (C.c_int64 * n)()
+        _check(self.lib.mpm_timing_read(self.ctx, C.cast(ms, C.c_void_p), C.cast(cnt, C.c_void_p),
+                                        C.cast(wms, C.c_void_p), C.cast(wcnt, C.c_void_p)), self.lib, self.ctx)
+        if work:
+            return {k: (wms[i], wcnt[i]) for i, k in enumerate(L.KERNEL_CLASSES)}
         return {k: (ms[i], cnt[i]) for i, k in enumerate(L.KERNEL_CLASSES)}
 
     def view(self, field, count=None):

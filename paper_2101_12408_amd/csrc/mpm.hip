@@ -68,6 +68,7 @@ struct Prof {
   size_t used = 0;
   double ms[MPM_K_COUNT] = {};
   int64_t launches[MPM_K_COUNT] = {};
+  std::vector<float> dur[MPM_K_COUNT];   // every launch's duration (ms)
 };
 
 struct mpm_ctx {
@@ -164,8 +165,23 @@ void prof_collect(mpm_ctx* c) {
     HIPCHK(hipEventElapsedTime(&ms, pr.ev[2 * k], pr.ev[2 * k + 1]));
     pr.ms[pr.cls[k]] += ms;
     pr.launches[pr.cls[k]] += 1;
+    pr.dur[pr.cls[k]].push_back(ms);
   }
   pr.used = 0;
+}
+
+// Launches of class k that did work: a CG called off on the device still launches its
+// kernels, which return at once.  Those below a tenth of the class's 95th-percentile
+// duration are left out.
+void prof_work(const Prof& pr, int k, double* ms, int64_t* n) {
+  std::vector<float> v = pr.dur[k];
+  *ms = 0;
+  *n = 0;
+  if (v.empty()) return;
+  std::sort(v.begin(), v.end());
+  const double p95 = v[(size_t)std::floor(0.95 * (double)(v.size() - 1))];
+  for (float x : v)
+    if (x >= 0.1 * p95) { *ms += x; ++*n; }
 }
 
 // Launch on stream s (in scope), timed as kernel class cls when timing is on.
@@ -1486,16 +1502,28 @@ int mpm_timing(mpm_ctx* ctx, int32_t enable) {
   if (!ctx) return MPM_EINVAL;
   return guarded(ctx, [&] {
     prof_collect(ctx);
-    for (int k = 0; k < MPM_K_COUNT; ++k) { ctx->prof.ms[k] = 0; ctx->prof.launches[k] = 0; }
+    for (int k = 0; k < MPM_K_COUNT; ++k) {
+      ctx->prof.ms[k] = 0;
+      ctx->prof.launches[k] = 0;
+      ctx->prof.dur[k].clear();
+    }
     ctx->prof.on = enable != 0;
   });
 }
 
-int mpm_timing_read(mpm_ctx* ctx, double* ms, int64_t* launches) {
+int mpm_timing_read(mpm_ctx* ctx, double* ms, int64_t* launches, double* work_ms, int64_t* work_launches) {
   if (!ctx || !ms || !launches) return MPM_EINVAL;
   return guarded(ctx, [&] {
     prof_collect(ctx);
-    for (int k = 0; k < MPM_K_COUNT; ++k) { ms[k] = ctx->prof.ms[k]; launches[k] = ctx->prof.launches[k]; }
+    for (int k = 0; k < MPM_K_COUNT; ++k) {
+      ms[k] = ctx->prof.ms[k];
+      launches[k] = ctx->prof.launches[k];
+      double wm = 0;
+      int64_t wn = 0;
+      prof_work(ctx->prof, k, &wm, &wn);
+      if (work_ms) work_ms[k] = wm;
+      if (work_launches) work_launches[k] = wn;
+    }
   });
 }
 
