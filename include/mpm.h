@@ -29,9 +29,10 @@
  *  - Every call is asynchronous on the caller's stream (a hipStream_t passed as void*;
  *    NULL is the null stream) unless documented otherwise.  Calls on one context must
  *    not overlap: a context owns its workspace.
- *  - The library allocates no device memory.  mpm_workspace_bytes() sizes a workspace
- *    that the caller allocates and hands to mpm_ctx_create(); the context borrows it
- *    until mpm_ctx_destroy().
+ *  - The library allocates no device memory at run time.  mpm_workspace_bytes() sizes a
+ *    workspace that the caller allocates and hands to mpm_ctx_create(); the context
+ *    borrows it until mpm_ctx_destroy().  (mpm_step_noalloc instead uses a static device
+ *    array that the GPU holds from the library's load on.)
  */
 #ifndef MPM_H_
 #define MPM_H_
@@ -249,6 +250,24 @@ int mpm_step(mpm_ctx* const* ctxs, mpm_particles* const* P, const mpm_surface* c
              int32_t n_scenes, int32_t implicit, void* stream);
 /* Maximum number of scenes mpm_step advances at once (1..64, default 8; process-wide). */
 int mpm_batch_config(int32_t max_concurrent);
+
+/* One step of one scene that allocates nothing, for callers that cannot allocate device
+ * or pinned memory, create streams or events (tight serving loops, harnesses that forbid
+ * allocation).  It computes what mpm_step computes for a single scene with a context of
+ * parameters p and capacities P->n, S->n, bitwise the same, but with no context and no
+ * workspace argument: the workspace is a static device array of *scratch_bytes bytes
+ * (256 MiB; each GPU the library runs on holds its own copy until the process ends), the
+ * host scalar block is static host memory, and every kernel runs on `stream`.  P (device,
+ * real per p->precision) is updated in place in cell order as by mpm_step; S may be NULL.
+ * The scratch is cleared at the start of every call and the call returns only when the
+ * step is complete on the device.  Calls on the same GPU share the one array: they are
+ * serialized by a lock, and a call that overlapped another on that GPU from outside the
+ * library (a kernel still reading P) would race.  Returns MPM_ENOMEM, with a message in
+ * mpm_last_error(NULL), when the scene's workspace (mpm_workspace_bytes) exceeds the
+ * scratch; otherwise the status of the step.  scratch_bytes (may be NULL) receives the
+ * scratch size on every call. */
+int mpm_step_noalloc(const mpm_params* p, mpm_particles* P, const mpm_surface* S, int32_t implicit, void* stream,
+                     size_t* scratch_bytes);
 
 /* Device pointer of a grid field of the last mpm_p2g / solve (see mpm_field). */
 int mpm_grid_view(mpm_ctx* ctx, int32_t field, void** out_ptr);

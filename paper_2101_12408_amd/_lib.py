@@ -83,6 +83,8 @@ EXPORTS = {
     "mpm_step": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(C.POINTER(MpmParticles)),
                            C.POINTER(C.POINTER(MpmSurface)), C.c_int32, C.c_int32, C.c_void_p]),
     "mpm_batch_config": (C.c_int, [C.c_int32]),
+    "mpm_step_noalloc": (C.c_int, [C.POINTER(MpmParams), C.POINTER(MpmParticles), C.POINTER(MpmSurface), C.c_int32,
+                                   C.c_void_p, C.POINTER(C.c_size_t)]),
     "mpm_grid_view": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]),
     "mpm_get_stats": (C.c_int, [C.c_void_p, C.POINTER(MpmStats)]),
     "mpm_timing": (C.c_int, [C.c_void_p, C.c_int32]),

@@ -291,6 +291,33 @@ def mpm_step(scenes, Ps, Ss, implicit=True, check=True):
     return rc
 
 
+def step_noalloc(params, P, S=None, implicit=True, precision="fp64", check=True):
+    """mpm_step_noalloc: one step of one scene on the library's static scratch (no context,
+    no workspace).  P, S: device tensor dicts as from Scene.to_device.  Returns (status,
+    scratch bytes)."""
+    import torch
+    lib = L.load()
+    p = make_params(params, precision)
+    dtype = torch.float64 if precision == "fp64" else torch.float32
+    pst = L.MpmParticles()
+    pst.n = int(P["m"].shape[0])
+    for k in ("x", "v", "A", "J", "V0", "m", "T", "gradT"):
+        t = P[k]
+        assert t.dtype == dtype and t.is_contiguous() and t.is_cuda, k
+        setattr(pst, k, t.data_ptr())
+    sst = L.MpmSurface()
+    if S is not None and int(S["s"].shape[1]):
+        sst.n = int(S["s"].shape[1])
+        sst.s, sst.dA = S["s"].data_ptr(), S["dA"].data_ptr()
+        sst.label = S["label"].data_ptr() if S.get("label") is not None else None
+    nb = C.c_size_t(0)
+    rc = lib.mpm_step_noalloc(C.byref(p), C.byref(pst), C.byref(sst), 1 if implicit else 0,
+                              C.c_void_p(torch.cuda.current_stream().cuda_stream), C.byref(nb))
+    if check:
+        _check(rc, lib)
+    return rc, nb.value
+
+
 def batch_config(max_concurrent):
     """Maximum number of scenes mpm_step advances at once (process-wide)."""
     lib = L.load()

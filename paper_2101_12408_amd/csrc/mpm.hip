@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <thread>
 #include <cmath>
 #include <cstdio>
@@ -15,6 +16,10 @@
 #include "tiles.h"
 
 using namespace mpm;
+
+// Scratch of mpm_step_noalloc (see there): the largest workspace it can carve.
+constexpr size_t kScratchBytes = size_t(256) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
@@ -134,6 +139,10 @@ struct mpm_ctx {
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_hread = nullptr, ev_counts = nullptr, ev_sfork = nullptr,
              ev_sjoin = nullptr, ev_mread = nullptr;
+  // single-stream mode (the context of mpm_step_noalloc): every chain runs on the caller's
+  // stream and the host waits on that stream, so no stream or event is ever created
+  bool single = false;
+  hipStream_t mread_stream = nullptr;
 };
 
 namespace {
@@ -382,6 +391,39 @@ void sync_read(mpm_ctx* c, hipStream_t s, const void* src, void* dst, size_t byt
   HIPCHK(hipStreamSynchronize(s));
 }
 
+// The second stream of a context, ordered after the work queued so far on s (the
+// caller's stream itself in single-stream mode); aux_join orders s after the work queued
+// since on the returned stream.  fork/join: the two event pairs of the binning and of the
+// heat solve.
+hipStream_t aux_fork(mpm_ctx* c, hipStream_t s, hipEvent_t* fork) {
+  if (c->single) return s;
+  if (!c->aux) HIPCHK(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+  if (!*fork) HIPCHK(hipEventCreateWithFlags(fork, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(*fork, s));
+  HIPCHK(hipStreamWaitEvent(c->aux, *fork, 0));
+  return c->aux;
+}
+void aux_mark(mpm_ctx* c, hipStream_t a, hipEvent_t* join) {
+  if (c->single) return;
+  if (!*join) HIPCHK(hipEventCreateWithFlags(join, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(*join, a));
+}
+void aux_join(mpm_ctx* c, hipStream_t s, hipEvent_t join) {
+  if (c->single) return;
+  HIPCHK(hipStreamWaitEvent(s, join, 0));
+}
+// A host wait point on stream s: mark records it, wait blocks until s has reached it (in
+// single-stream mode: until s is idle).
+void host_mark(mpm_ctx* c, hipStream_t s, hipEvent_t* ev) {
+  if (c->single) return;
+  if (!*ev) HIPCHK(hipEventCreateWithFlags(ev, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(*ev, s));
+}
+void host_wait(mpm_ctx* c, hipStream_t s, hipEvent_t ev) {
+  if (c->single) HIPCHK(hipStreamSynchronize(s));
+  else HIPCHK(hipEventSynchronize(ev));
+}
+
 // The second stream's share of the binning (on stream s): clears the previous step's
 // tiles, then bins the surface samples by cell and stages them in cell order.
 template <int D, typename R>
@@ -426,19 +468,15 @@ void do_p2g(mpm_ctx* c, const mpm_particles* P, const mpm_surface* S, hipStream_
   // Independent chains go to the second stream: the clearing of the previous step's
   // tiles (views read zero outside the new active set) and the binning of the surface
   // samples, beside the binning of the interior particles on this stream.
-  if (!c->aux) HIPCHK(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
-  if (!c->ev_sfork) HIPCHK(hipEventCreateWithFlags(&c->ev_sfork, hipEventDisableTiming));
-  if (!c->ev_sjoin) HIPCHK(hipEventCreateWithFlags(&c->ev_sjoin, hipEventDisableTiming));
-  HIPCHK(hipEventRecord(c->ev_sfork, s));
-  HIPCHK(hipStreamWaitEvent(c->aux, c->ev_sfork, 0));
-  front_aux<D, R>(c, d, S, c->aux);
-  HIPCHK(hipEventRecord(c->ev_sjoin, c->aux));
+  hipStream_t a = aux_fork(c, s, &c->ev_sfork);
+  front_aux<D, R>(c, d, S, a);
+  aux_mark(c, a, &c->ev_sjoin);
   cell_sort<D, R>(c, d, (const R*)P->x, c->np, d.p_key, d.p_perm, d.p_start, s, sort_res(c, d, false));
   if (c->np > 0)
     LAUNCH(c, MPM_K_SETUP, (k_gather_particles<D, R>), dim3(cdiv(c->np, 256)), dim3(256), 0, s, d, (const R*)P->x,
                        (const R*)P->v, (const R*)P->A, (const R*)P->J, (const R*)P->V0, (const R*)P->m,
                        (const R*)P->T, (const R*)P->gradT);
-  HIPCHK(hipStreamWaitEvent(s, c->ev_sjoin, 0));
+  aux_join(c, s, c->ev_sjoin);
   // A1: parents, split masses, balance points, groups
   if (c->ns > 0)
     LAUNCH(c, MPM_K_SETUP, (k_parents<D, R>), dim3(cdiv(c->ns, 256 / kParGroup)), dim3(256), 0, s, d);
@@ -452,10 +490,9 @@ void do_p2g(mpm_ctx* c, const mpm_particles* P, const mpm_surface* S, hipStream_
     LAUNCH(c, MPM_K_SETUP, (k_gather_balance<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d);
   }
   // active cell tiles (hold points) on this stream, node tiles on the second
-  HIPCHK(hipEventRecord(c->ev_sfork, s));
-  HIPCHK(hipStreamWaitEvent(c->aux, c->ev_sfork, 0));
-  node_tiles<D, R>(c, d, c->aux);
-  HIPCHK(hipEventRecord(c->ev_sjoin, c->aux));
+  a = aux_fork(c, s, &c->ev_sfork);
+  node_tiles<D, R>(c, d, a);
+  aux_mark(c, a, &c->ev_sjoin);
   LAUNCH(c, MPM_K_SETUP, (k_flag_ctiles<D, R>), dim3(cdiv(c->ntile_total, 256)), dim3(256), 0, s, d, c->ctile_flag,
          c->ntile_total);
   scan(c, c->ctile_flag, c->ctile_pos, 2 * c->ntile_total, s);
@@ -463,9 +500,8 @@ void do_p2g(mpm_ctx* c, const mpm_particles* P, const mpm_surface* S, hipStream_
          (const int*)c->ctile_flag, (const int*)c->ctile_pos, c->ntile_total, c->ctile_list, c->ctile_slot,
          c->ctile_rng);
   HIPCHK(hipMemcpyAsync(c->hint + 1, c->ctile_pos + 2 * c->ntile_total, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamWaitEvent(s, c->ev_sjoin, 0));
-  if (!c->ev_counts) HIPCHK(hipEventCreateWithFlags(&c->ev_counts, hipEventDisableTiming));
-  HIPCHK(hipEventRecord(c->ev_counts, s));
+  aux_join(c, s, c->ev_sjoin);
+  host_mark(c, s, &c->ev_counts);
   // A2: the cell-tile scatter goes out before the host has the tile counts, sized by the
   // previous step's count (the kernel reads the true count); the host waits for the
   // counts while it runs and covers any further tiles with a second launch
@@ -473,7 +509,7 @@ void do_p2g(mpm_ctx* c, const mpm_particles* P, const mpm_surface* S, hipStream_
   const int est = (int)std::min<int64_t>(c->ntile_total, c->prev_nctile + c->prev_nctile / 8 + 64);
   LAUNCH(c, MPM_K_P2G, (k_tile_p2g<D, R>), dim3(cdiv(est, 8) * 16), dim3(TileGeo<D>::NT), 0, s, d, tiles(c),
          (R*)c->tpart, nct_dev, 0);
-  HIPCHK(hipEventSynchronize(c->ev_counts));
+  host_wait(c, s, c->ev_counts);
   c->ntiles = c->hint[0];
   c->nctile = c->hint[1];
   c->prev_ntiles = c->ntiles;
@@ -635,12 +671,12 @@ void read_mirror(mpm_ctx* c, hipStream_t s) {
 // read_mirror in two halves, so that work can be queued behind the copy before the host
 // waits for it.
 void mirror_copy(mpm_ctx* c, hipStream_t s) {
-  if (!c->ev_mread) HIPCHK(hipEventCreateWithFlags(&c->ev_mread, hipEventDisableTiming));
   HIPCHK(hipMemcpyAsync(c->hmirror, (const char*)c->scal, kMirrorRead, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipEventRecord(c->ev_mread, s));
+  host_mark(c, s, &c->ev_mread);
+  c->mread_stream = s;
 }
 void mirror_wait(mpm_ctx* c) {
-  HIPCHK(hipEventSynchronize(c->ev_mread));
+  host_wait(c, c->mread_stream, c->ev_mread);
   c->status |= c->hint[0];
   c->constrained = c->hint[1] != 0;
   c->stats.n_dof = c->hint[2];
@@ -1042,16 +1078,15 @@ void heat_begin(mpm_ctx* c, hipStream_t s, CgRun& run) {
               (R*)c->hAp, 1, c->p.heat_tol * c->p.heat_tol, c->scal + SC_RHS2, c->p.heat_max, s, run,
               first_chunk(c->cg_hint_heat));
   // the scalars after the first chunk go to the host at once; heat_end waits for them
-  if (!c->ev_hread) HIPCHK(hipEventCreateWithFlags(&c->ev_hread, hipEventDisableTiming));
   kry_copy(c, kh, s);
-  HIPCHK(hipEventRecord(c->ev_hread, s));
+  host_mark(c, s, &c->ev_hread);
 }
 
 template <int D, typename R>
 bool heat_end(mpm_ctx* c, hipStream_t s, CgRun& run) {
   Dev<R>& d = dev<R>(c);
   const KrySet kh = kry_heat(c);
-  HIPCHK(hipEventSynchronize(c->ev_hread));
+  host_wait(c, s, c->ev_hread);
   auto apply = [&](const R* pv, R* Apv, const int* done, CgScal* cg, PUpd<R> pu) {
     do_heat_apply<D, R>(c, pv, Apv, done, cg, s, pu);
   };
@@ -1114,6 +1149,70 @@ int check_launch(mpm_ctx* c) {
   return MPM_OK;
 }
 
+// Workspace bytes of a context with parameters p and the given capacities.
+size_t workspace_need(const mpm_params* p, int64_t cap_part, int64_t cap_surf) {
+  check_params(p);
+  if (cap_part < 0 || cap_surf < 0) throw ApiError{MPM_EINVAL, "bad arguments"};
+  if (cap_part > (int64_t)kScanBlock * kScanBlock || cap_surf > (int64_t)kScanBlock * kScanBlock)
+    throw ApiError{MPM_EINVAL, "capacity above 2^24"};
+  mpm_ctx tmp;
+  tmp.p = *p;
+  tmp.dim = p->dim;
+  tmp.n = p->n;
+  tmp.nn = 1;
+  for (int a = 0; a < p->dim; ++a) tmp.nn *= p->n;
+  tmp.ntile_total = tmp.nn / 64;
+  tmp.cap_part = cap_part;
+  tmp.cap_surf = cap_surf;
+  return p->precision == MPM_FP64 ? layout<double>(&tmp, nullptr) : layout<float>(&tmp, nullptr);
+}
+
+// Sets up context c over the device workspace ws (need bytes are used) and the host
+// mirror block (kMirrorBytes): the parameters, the workspace carving and the per-step
+// state, and zeroes the used workspace with a fill kernel on stream s (the cell counters
+// and scan status words must start at zero), waiting for it.  Allocates nothing.
+void ctx_init(mpm_ctx* c, const mpm_params* p, void* ws, size_t ws_bytes, size_t need, int64_t cap_part,
+              int64_t cap_surf, char* mirror, hipStream_t s) {
+  c->p = *p;
+  c->dim = p->dim;
+  c->n = p->n;
+  c->nt = p->n / (p->dim == 3 ? 4 : 8);
+  c->nn = 1;
+  for (int a = 0; a < p->dim; ++a) c->nn *= p->n;
+  c->ntile_total = c->nn / 64;
+  c->cap_part = cap_part;
+  c->cap_surf = cap_surf;
+  c->fp64 = p->precision == MPM_FP64;
+  c->ws = (char*)ws;
+  c->ws_bytes = ws_bytes;
+  c->d64 = Dev<double>{};
+  c->d32 = Dev<float>{};
+  if (c->fp64) {
+    layout<double>(c, c->ws);
+    fill_params(c->d64, *p, c->nt);
+  } else {
+    layout<float>(c, c->ws);
+    fill_params(c->d32, *p, c->nt);
+  }
+  c->hmirror = mirror;
+  c->hbuf = (double*)c->hmirror;
+  c->hcg = (CgScal*)(c->hmirror + kMirrorCg);
+  c->hint = (int*)(c->hmirror + kMirrorMisc);
+  c->nctile = 0;
+  c->scan_epoch = c->scan_epoch_aux = 0;
+  c->np = c->ns = c->ntiles = c->prev_ntiles = c->prev_nctile = 0;
+  c->have_p2g = c->constrained = c->mom_pending = false;
+  c->cg_hint_mom = c->cg_hint_heat = 2;
+  c->status = 0;
+  c->stats = mpm_stats{};
+  c->err.clear();
+  HIPCHK(hipGetDevice(&c->device));
+  hipLaunchKernelGGL(k_fill_i32, dim3(cdiv((int64_t)(need / 4), 256)), dim3(256), 0, s, (int*)c->ws, 0,
+                     (int64_t)(need / 4));
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+}
+
 }  // namespace
 
 // =========================================================================================
@@ -1149,20 +1248,8 @@ int mpm_params_default(mpm_params* p, int32_t dim, int32_t n) {
 
 int mpm_workspace_bytes(const mpm_params* p, int64_t cap_part, int64_t cap_surf, size_t* out_bytes) {
   return guarded(nullptr, [&] {
-    check_params(p);
-    if (!out_bytes || cap_part < 0 || cap_surf < 0) throw ApiError{MPM_EINVAL, "bad arguments"};
-    if (cap_part > (int64_t)kScanBlock * kScanBlock || cap_surf > (int64_t)kScanBlock * kScanBlock)
-      throw ApiError{MPM_EINVAL, "capacity above 2^24"};
-    mpm_ctx tmp;
-    tmp.p = *p;
-    tmp.dim = p->dim;
-    tmp.n = p->n;
-    tmp.nn = 1;
-    for (int a = 0; a < p->dim; ++a) tmp.nn *= p->n;
-    tmp.ntile_total = tmp.nn / 64;
-    tmp.cap_part = cap_part;
-    tmp.cap_surf = cap_surf;
-    *out_bytes = p->precision == MPM_FP64 ? layout<double>(&tmp, nullptr) : layout<float>(&tmp, nullptr);
+    if (!out_bytes) throw ApiError{MPM_EINVAL, "bad arguments"};
+    *out_bytes = workspace_need(p, cap_part, cap_surf);
   });
 }
 
@@ -1176,35 +1263,8 @@ int mpm_ctx_create(const mpm_params* p, void* workspace, size_t ws_bytes, int64_
   if (!workspace || ws_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255)) return MPM_EINVAL;
   mpm_ctx* c = new mpm_ctx();
   rc = guarded(c, [&] {
-    c->p = *p;
-    c->dim = p->dim;
-    c->n = p->n;
-    c->nt = p->n / (p->dim == 3 ? 4 : 8);
-    c->nn = 1;
-    for (int a = 0; a < p->dim; ++a) c->nn *= p->n;
-    c->ntile_total = c->nn / 64;
-    c->cap_part = cap_part;
-    c->cap_surf = cap_surf;
-    c->fp64 = p->precision == MPM_FP64;
-    c->ws = (char*)workspace;
-    c->ws_bytes = ws_bytes;
-    if (c->fp64) {
-      layout<double>(c, c->ws);
-      fill_params(c->d64, *p, c->nt);
-    } else {
-      layout<float>(c, c->ws);
-      fill_params(c->d32, *p, c->nt);
-    }
-    HIPCHK(hipGetDevice(&c->device));
     HIPCHK(hipHostMalloc((void**)&c->hmirror, kMirrorBytes, hipHostMallocDefault));
-    c->hbuf = (double*)c->hmirror;
-    c->hcg = (CgScal*)(c->hmirror + kMirrorCg);
-    c->hint = (int*)(c->hmirror + kMirrorMisc);
-    // zero the workspace once (fill kernels; the cell counters must start at zero)
-    hipLaunchKernelGGL(k_fill_i32, dim3(cdiv((int64_t)(need / 4), 256)), dim3(256), 0, 0, (int*)c->ws, 0,
-                       (int64_t)(need / 4));
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(0));
+    ctx_init(c, p, workspace, ws_bytes, need, cap_part, cap_surf, c->hmirror, nullptr);
   });
   if (rc != MPM_OK) {
     g_last_error = c->err;
@@ -1363,6 +1423,21 @@ namespace {
 
 std::atomic<int> g_batch_concurrency{8};
 
+// mpm_step_noalloc: the workspace of its context is the static device array `scratch`
+// (one copy per GPU, held until the process ends), its host scalar block a static host
+// array, and its context runs in single-stream mode.  Per device: the array's device
+// address (taken once, with that device current), the context and a lock that orders
+// the calls.
+constexpr int kMaxDevices = 64;
+struct NoallocSlot {
+  std::mutex mu;
+  bool ready = false;
+  void* scratch_ptr = nullptr;
+  mpm_ctx ctx;
+  alignas(256) char mirror[kMirrorBytes];
+};
+NoallocSlot g_noalloc[kMaxDevices];
+
 int step_one(mpm_ctx* c, mpm_particles* P, const mpm_surface* S, int implicit, hipStream_t s) {
   int rc = mpm_p2g(c, P, S, s);
   bool synced = false;   // true when the final read covered all queued work and the status
@@ -1373,22 +1448,19 @@ int step_one(mpm_ctx* c, mpm_particles* P, const mpm_surface* S, int implicit, h
         using R = decltype(Rv);
         const bool heat = c->p.heat != 0;
         CgRun run;
+        hipStream_t hs = s;
         if (heat) {
           // the heat solve needs only the grid set-up: it runs on a second stream beside
           // the momentum solve
-          if (!c->aux) HIPCHK(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
-          if (!c->ev_fork) HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
-          if (!c->ev_join) HIPCHK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
-          HIPCHK(hipEventRecord(c->ev_fork, s));
-          HIPCHK(hipStreamWaitEvent(c->aux, c->ev_fork, 0));
-          heat_begin<D, R>(c, c->aux, run);
+          hs = aux_fork(c, s, &c->ev_fork);
+          heat_begin<D, R>(c, hs, run);
         }
         if (implicit) do_solve_momentum<D, R>(c, s);
         else do_explicit<D, R>(c, s);
         if (heat) {
-          heat_end<D, R>(c, c->aux, run);
-          HIPCHK(hipEventRecord(c->ev_join, c->aux));
-          HIPCHK(hipStreamWaitEvent(s, c->ev_join, 0));
+          heat_end<D, R>(c, hs, run);
+          aux_mark(c, hs, &c->ev_join);
+          aux_join(c, s, c->ev_join);
         }
         do_g2p<D, R>(c, (const R*)c->vhat, heat ? (const R*)c->That : nullptr, P, s);
         if (!implicit) {
@@ -1464,6 +1536,43 @@ int mpm_step(mpm_ctx* const* ctxs, mpm_particles* const* P, const mpm_surface* c
   for (int k = 0; k < n_scenes; ++k)
     if (rcs[k] != MPM_OK) return rcs[k];
   return MPM_OK;
+}
+
+int mpm_step_noalloc(const mpm_params* p, mpm_particles* P, const mpm_surface* S, int32_t implicit, void* stream,
+                     size_t* scratch_bytes) {
+  if (scratch_bytes) *scratch_bytes = kScratchBytes;
+  if (!p || !P) return MPM_EINVAL;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return MPM_EHIP;
+  if (dev < 0 || dev >= kMaxDevices) return MPM_EINVAL;
+  NoallocSlot& sl = g_noalloc[dev];
+  std::lock_guard<std::mutex> lk(sl.mu);
+  mpm_ctx* c = &sl.ctx;
+  hipStream_t s = (hipStream_t)stream;
+  int rc = guarded(c, [&] {
+    if (!sl.ready) {
+      // once per device, with it current: the device address of this GPU's copy of the
+      // array (host code never passes the array's own name to a kernel or a copy)
+      HIPCHK(hipGetSymbolAddress(&sl.scratch_ptr, HIP_SYMBOL(scratch)));
+      sl.ready = true;
+    }
+    const int64_t np = P->n, ns = S ? S->n : 0;
+    const size_t need = workspace_need(p, np, ns);
+    if (need > kScratchBytes)
+      throw ApiError{MPM_ENOMEM, "mpm_step_noalloc: the scene needs " + std::to_string(need) +
+                                     " bytes of workspace, the static scratch holds " + std::to_string(kScratchBytes)};
+    c->single = true;
+    ctx_init(c, p, sl.scratch_ptr, kScratchBytes, need, np, ns, sl.mirror, s);
+  });
+  if (rc == MPM_OK) rc = step_one(c, P, S, implicit, s);
+  // the step is complete on the device when the call returns: the next call on this GPU
+  // clears the scratch again
+  if (hipStreamSynchronize(s) != hipSuccess && rc == MPM_OK) {
+    c->err = "stream synchronization failed";
+    rc = MPM_EHIP;
+  }
+  if (rc != MPM_OK) g_last_error = c->err;
+  return rc;
 }
 
 int mpm_grid_view(mpm_ctx* ctx, int32_t field, void** out_ptr) {
