@@ -1,0 +1,48 @@
+// Host stand-in for the library calls serve.cpp makes (the step itself): a context over
+// the caller's workspace; mpm_step flushes the stream's queued copies (stream order), then
+// writes the particles back reversed, as a step writes them back in cell order, and
+// exposes that permutation.
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+#include "mpm.h"
+struct mpm_ctx { mpm_params p; char* ws; size_t bytes; int64_t cap_part, cap_surf; int32_t* perm; char* mirror; mpm_stats st; };
+extern "C" {
+int mpm_workspace_bytes(const mpm_params* p, int64_t cp, int64_t cs, size_t* out) {
+  *out = 4096 + (size_t)cp * 4 + (size_t)(p->n) * 16; return MPM_OK; }
+int mpm_ctx_create(const mpm_params* p, void* ws, size_t bytes, int64_t cp, int64_t cs, mpm_ctx** out) {
+  size_t need; mpm_workspace_bytes(p, cp, cs, &need);
+  if (!ws || bytes < need) return MPM_EINVAL;
+  mpm_ctx* c = new mpm_ctx{*p, (char*)ws, bytes, cp, cs, (int32_t*)((char*)ws + 4096), nullptr, {}};
+  hipHostMalloc((void**)&c->mirror, 1024, 0);
+  std::memset(ws, 0, need);
+  *out = c; return MPM_OK; }
+int mpm_ctx_destroy(mpm_ctx* c) { hipHostFree(c->mirror); delete c; return MPM_OK; }
+int mpm_step(mpm_ctx* const* cs, mpm_particles* const* P, const mpm_surface* const* S, int32_t n, int32_t, void* s) {
+  hipStreamSynchronize((hipStream_t)s);
+  for (int k = 0; k < n; ++k) {
+    mpm_ctx* c = cs[k]; const int64_t N = P[k]->n; const int dim = c->p.dim;
+    if (N > c->cap_part || S[k]->n > c->cap_surf) return MPM_ENOMEM;
+    const bool f64 = c->p.precision == MPM_FP64; const size_t R = f64 ? 8 : 4;
+    // read every surface sample and label the step would read
+    volatile double acc = 0;
+    for (int64_t i = 0; i < S[k]->n; ++i) acc += S[k]->label[i];
+    void* f[8] = {P[k]->x, P[k]->v, P[k]->A, P[k]->J, P[k]->V0, P[k]->m, P[k]->T, P[k]->gradT};
+    int nc[8] = {dim, dim, dim * dim, 1, 1, 1, 1, dim};
+    std::vector<char> tmp;
+    for (int q = 0; q < 8; ++q)
+      for (int a = 0; a < nc[q]; ++a) {
+        char* base = (char*)f[q] + (size_t)a * N * R;
+        tmp.assign(base, base + N * R);
+        for (int64_t i = 0; i < N; ++i) std::memcpy(base + i * R, tmp.data() + (N - 1 - i) * R, R);
+      }
+    for (int64_t i = 0; i < N; ++i) c->perm[i] = (int32_t)(N - 1 - i);
+    c->st = mpm_stats{}; c->st.newton_iters = 1; c->st.n_part = N; c->st.n_surf = S[k]->n;
+  }
+  return MPM_OK; }
+int mpm_get_stats(const mpm_ctx* c, mpm_stats* o) { *o = c->st; return MPM_OK; }
+int mpm_grid_view(mpm_ctx* c, int32_t f, void** out) { if (f != MPM_F_PERM) return MPM_EINVAL; *out = c->perm; return MPM_OK; }
+}
+extern "C" int mpm_params_default(mpm_params* p, int32_t dim, int32_t n) {
+  std::memset(p, 0, sizeof(*p)); p->dim = dim; p->n = n; p->dx = 1.0 / n; p->dt = 1e-3; return MPM_OK; }
