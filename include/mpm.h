@@ -192,7 +192,9 @@ int mpm_ctx_create(const mpm_params* p, void* workspace, size_t ws_bytes, int64_
                    int64_t cap_surf, mpm_ctx** out);
 int mpm_ctx_destroy(mpm_ctx* ctx);
 const char* mpm_last_error(const mpm_ctx* ctx);
-/* Replaces the parameters of a context (same dim, n, precision and capacities). */
+/* Replaces the parameters of a context (same dim, n, precision and capacities).  What the
+ * grid set-up forms from them (k_r, mu_p, the per-particle Hessian factors, the Jacobi
+ * diagonals, the heat right side) follows at the next mpm_p2g. */
 int mpm_ctx_set_params(mpm_ctx* ctx, const mpm_params* p);
 
 /* Sections 4.1.2-4.2 and the grid set-up: bins particles and samples by cell, finds each

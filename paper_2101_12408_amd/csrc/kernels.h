@@ -23,11 +23,12 @@ struct Dev {
   int np, ns;
   // interior particles, cell-sorted
   int* p_start; int* p_perm; int* p_key;
-  R *px, *pv, *pA, *pm, *pmt, *pJ, *pV0, *pT, *pgT, *pmu, *pVn, *pS;
+  R *px, *pv, *pA, *pm, *pmt, *pJ, *pV0, *pT, *pgT, *pmu, *pVn;
+  R* pHc;   // Hessian coefficients: [0] dt^2 lam V0 J^2 (J term), [1] dt mu V^n (viscous)
   int* pcnt; int* pcnt_orig; int* grp_start; int* grp; int* gcur;
   // surface samples, cell-sorted
   int* s_start; int* s_perm; int* s_key;
-  R *ss, *sdA, *sk, *sk_orig, *sS, *sc, *sF;
+  R *ss, *sdA, *sk, *sk_orig, *sc, *sF;
   int* slabel; int* spar; int* s_parent_orig;
   // balance points, cell-sorted
   int* b_start; int* b_src; int* b_key; R* bx; R* bx_unsorted;
@@ -289,8 +290,13 @@ __global__ void k_gather_particles(Dev<R> d, const R* x, const R* v, const R* A,
   d.pV0[k] = V0k;
   d.pm[k] = m[i];
   d.pT[k] = Tk;
-  d.pVn[k] = Jk * V0k;
-  d.pmu[k] = d.mu0 == R(0) ? R(0) : d.mu0 * exp(-d.mu_k * (Tk - d.mu_T0));
+  const R Vn = Jk * V0k;
+  const R mu = d.mu0 == R(0) ? R(0) : d.mu0 * exp(-d.mu_k * (Tk - d.mu_T0));
+  d.pVn[k] = Vn;
+  d.pmu[k] = mu;
+  // the Hessian's per-particle factors, rounded as the Hessian kernel would form them
+  d.pHc[k] = d.dt * d.dt * d.lam * V0k * Jk * Jk;
+  d.pHc[N + k] = d.dt * (mu * Vn);
   d.pcnt[k] = 0;
 }
 

@@ -237,8 +237,8 @@ size_t layout(mpm_ctx* c, char* base) {
   d.px = b.take<R>(D * NP); d.pv = b.take<R>(D * NP); d.pA = b.take<R>(D * D * NP);
   d.pm = b.take<R>(NP); d.pmt = b.take<R>(NP); d.pJ = b.take<R>(NP); d.pV0 = b.take<R>(NP);
   d.pT = b.take<R>(NP); d.pgT = b.take<R>(D * NP); d.pmu = b.take<R>(NP); d.pVn = b.take<R>(NP);
-  d.pS = b.take<R>(D * D * NP);
-  d.ss = b.take<R>(D * NS); d.sdA = b.take<R>(D * NS); d.sk = b.take<R>(NS); d.sk_orig = b.take<R>(NS); d.sS = b.take<R>(D * D * NS);
+  d.pHc = b.take<R>(2 * NP);
+  d.ss = b.take<R>(D * NS); d.sdA = b.take<R>(D * NS); d.sk = b.take<R>(NS); d.sk_orig = b.take<R>(NS);
   d.sc = b.take<R>((D + D * D) * NS); d.sF = b.take<R>(D * D * NS); d.bx = b.take<R>(D * NS); d.bx_unsorted = b.take<R>(D * NS);
   d.gm = b.take<R>(NN); d.gW = b.take<R>(NN); d.gWT = b.take<R>(NN); d.gE = b.take<R>(NN);
   d.gET = b.take<R>(NN); d.gTn = b.take<R>(NN); d.hdiag = b.take<R>(NN); d.hrhs = b.take<R>(NN);
@@ -380,8 +380,11 @@ TileLists tiles(mpm_ctx* c) {
   t.ctile_rng = c->ctile_rng;
   t.nbr = c->nbr_slot;
   t.nctile = c->nctile;
+  t.xrun = xcd_run(c->nctile);
   return t;
 }
+// Grid of a tile kernel that takes its slot with xcd_slot.
+int tile_grid(const mpm_ctx* c) { return xcd_grid(c->nctile, xcd_run(c->nctile)); }
 
 int krylov_blocks(int nelem) { return std::max(1, std::min(1024, cdiv(nelem, kNodeThreads))); }
 int merge_blocks(const mpm_ctx* c) { return cdiv(c->ntiles, kMergeTiles); }
@@ -554,7 +557,7 @@ void do_energy_grad(mpm_ctx* c, const R* u, R* g, double* energy_dev, int red_sl
   Dev<R>& d = dev<R>(c);
   TileLists tl = tiles(c);
   if (c->nctile > 0)
-    LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_ENERGY>), dim3(c->nctile), dim3(TileGeo<D>::NT), 0, s, d, tl,
+    LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_ENERGY>), dim3(tile_grid(c)), dim3(TileGeo<D>::NT), 0, s, d, tl,
            u, (R*)c->tpart, 0, (const int*)nullptr, 2, pu, fout);
   if (c->ntiles > 0) {
     LAUNCH(c, MPM_K_ENERGY_NODE, (k_merge_stress<D, R>), dim3(merge_blocks(c)), dim3(64 * kMergeTiles), 0, s, d, tl,
@@ -587,7 +590,7 @@ void do_hessvec(mpm_ctx* c, const R* w, double alpha, R* out, bool mask_in, cons
   Dev<R> dh = d;
   if (f_lin) dh.sF = f_lin;
   if (c->nctile > 0)
-    LAUNCH(c, MPM_K_HESS_INT, (k_tile_stress<D, R, TM_HESS>), dim3(c->nctile), dim3(TileGeo<D>::NT), 0, s, dh, tl,
+    LAUNCH(c, MPM_K_HESS_INT, (k_tile_stress<D, R, TM_HESS>), dim3(tile_grid(c)), dim3(TileGeo<D>::NT), 0, s, dh, tl,
            w, (R*)c->tpart, (int)mask_in, done, -1, pu, (R*)nullptr);
   if (c->ntiles > 0)
     LAUNCH(c, MPM_K_HESS_NODE, (k_merge_stress<D, R>), dim3(merge_blocks(c)), dim3(64 * kMergeTiles), 0, s, d, tl, c->ntiles,
@@ -602,7 +605,7 @@ void do_hessvec_force(mpm_ctx* c, const R* u, R* out, hipStream_t s) {
   Dev<R>& d = dev<R>(c);
   TileLists tl = tiles(c);
   if (c->nctile > 0)
-    LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_FORCE>), dim3(c->nctile), dim3(TileGeo<D>::NT), 0, s, d, tl,
+    LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_FORCE>), dim3(tile_grid(c)), dim3(TileGeo<D>::NT), 0, s, d, tl,
            u, (R*)c->tpart, 0, (const int*)nullptr, -1, PUpd<R>{}, (R*)nullptr);
   if (c->ntiles > 0)
     LAUNCH(c, MPM_K_ENERGY_NODE, (k_merge_stress<D, R>), dim3(merge_blocks(c)), dim3(64 * kMergeTiles), 0, s, d, tl, c->ntiles,
@@ -620,7 +623,7 @@ void do_heat_apply(mpm_ctx* c, const R* T, R* out, const int* done, CgScal* cg, 
   Dev<R>& d = dev<R>(c);
   TileLists tl = tiles(c);
   if (c->nctile > 0)
-    LAUNCH(c, MPM_K_HEAT_PT, (k_tile_heat<D, R>), dim3(c->nctile), dim3(TileGeo<D>::NT), 0, s, d, tl, T,
+    LAUNCH(c, MPM_K_HEAT_PT, (k_tile_heat<D, R>), dim3(tile_grid(c)), dim3(TileGeo<D>::NT), 0, s, d, tl, T,
            (R*)c->tpart_heat, done, pu);
   if (c->ntiles > 0)
     LAUNCH(c, MPM_K_HEAT_NODE, (k_merge_heat<D, R>), dim3(merge_blocks(c)), dim3(64 * kMergeTiles), 0, s, d, tl,

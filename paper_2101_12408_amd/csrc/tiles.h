@@ -53,7 +53,21 @@ struct TileLists {
   const int* ctile_rng;    // per slot: [interior begin, end, surface begin, end, balance begin, end]
   const int* nbr;          // per active node tile ti: slots of the cell tiles at offsets -1..1 (kNbr)
   int nctile;
+  int xrun;                // slots per XCD run of the tile kernels (xcd_slot)
 };
+
+// Slot of the tile that workgroup b takes.  Workgroups are dealt to the 8 XCDs in turn,
+// and each XCD has an L2 of its own; neighbouring cell tiles (consecutive slots) read
+// overlapping node regions, so each XCD takes runs of `run` consecutive slots, the runs
+// dealt to the XCDs in turn.  The halo lines a tile shares with the previous one are then
+// in its own XCD's L2.  A launch covers whole rounds of 8 runs (xcd_grid); workgroups past
+// the last slot return.
+MPM_DEV int xcd_slot(int b, int run) {
+  const int x = b & 7, i = b >> 3;
+  return (i / run) * (8 * run) + x * run + (i % run);
+}
+inline int xcd_grid(int nslot, int run) { return (nslot + 8 * run - 1) / (8 * run) * 8 * run; }
+inline int xcd_run(int nslot) { return nslot >= 8192 ? 32 : (nslot >= 1024 ? 8 : 1); }
 
 constexpr int kNbr = 27;   // neighbour slots per node tile (3^D used)
 
@@ -545,8 +559,10 @@ struct StressLds {
 
 // A point's inputs to the stress scatter, loaded one chunk ahead so that the loads are in
 // flight while the previous chunk is scattered (and, for the first chunk, while the node
-// region is staged).  Interior: x, J^n, V0, mu V^n.  Surface: x, k_r, dA (the cached F_r
-// of the Hessian is loaded in the point phase: holding it across the scatter spills).
+// region is staged).  Interior: x, J^n, V0, mu V^n; for the Hessian x and the two
+// coefficients dt^2 lam V0 (J^n)^2 and dt mu V^n formed at the particle staging.  Surface:
+// x, k_r, dA (the cached F_r of the Hessian is loaded in the point phase: holding it
+// across the scatter spills).
 template <int D, typename R, int MODE>
 struct StressIn {
   static constexpr int NV = D + 1 + D;
@@ -568,9 +584,15 @@ MPM_DEV void stress_fetch(const Dev<R>& d, int q, int ntot, int npi, int pb, int
   if (in.interior) {
 #pragma unroll
     for (int a = 0; a < D; ++a) in.v[a] = d.px[a * N + k];
-    in.v[D] = d.pJ[k];
-    in.v[D + 1] = d.pV0[k];
-    in.v[D + 2] = visc ? d.pmu[k] * d.pVn[k] : R(0);
+    if constexpr (MODE == TM_HESS) {
+      in.v[D] = d.pHc[k];
+      in.v[D + 1] = visc ? d.pHc[N + k] : R(0);
+      in.v[D + 2] = R(0);
+    } else {
+      in.v[D] = d.pJ[k];
+      in.v[D + 1] = d.pV0[k];
+      in.v[D + 2] = visc ? d.pmu[k] * d.pVn[k] : R(0);
+    }
 #pragma unroll
     for (int a = 2; a < D; ++a) in.v[D + 1 + a] = R(0);
   } else {
@@ -590,7 +612,9 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
   constexpr int CH = StressLds<D, R>::CH, PS = StressLds<D, R>::PS;
   __shared__ StressLds<D, R> sm;
   if (done && *done) return;
-  const int ct = tl.ctile_list[blockIdx.x];
+  const int slot = xcd_slot(blockIdx.x, tl.xrun);
+  if (slot >= tl.nctile) return;
+  const int ct = tl.ctile_list[slot];
   const int S = d.ns, nn = d.nn;
   const int t = threadIdx.x;
   const R dt = d.dt;
@@ -600,7 +624,7 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
   const bool surf = (d.term_mask & 2) && S > 0;
   const bool vol = (d.term_mask & 5) != 0;
   const bool visc = (d.term_mask & 4) != 0;
-  const int* rg = tl.ctile_rng + 6 * blockIdx.x;
+  const int* rg = tl.ctile_rng + 6 * slot;
   const int pb = rg[0], pe = vol ? rg[1] : pb;
   const int sb = surf ? rg[2] : 0, se = surf ? rg[3] : 0;
   const int npi = pe - pb;
@@ -668,7 +692,7 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
         if (d.term_mask & 1) {
           R s;
           if (MODE == TM_HESS) {
-            s = dt * dt * d.lam * V0 * Jn * Jn * tr;
+            s = in.v[D] * tr;                  // (dt^2 lam V0 (J^n)^2) tr
           } else {
             R Jm1 = (R(1) + dt * tr) * Jn - R(1);
             if (MODE == TM_ENERGY) e += (double)(R(0.5) * d.lam * Jm1 * Jm1 * V0);
@@ -678,7 +702,7 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
           for (int a = 0; a < D; ++a) Sq[a][a] += s;
         }
         if (visc) {
-          R cV = dt * in.v[D + 2];
+          const R cV = MODE == TM_HESS ? in.v[D + 1] : dt * in.v[D + 2];
           R ee = 0;
 #pragma unroll
           for (int a = 0; a < D; ++a)
@@ -760,11 +784,11 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
   // ---- reduce onto the region and write the tile partial ----
   R* reg = sm.x.red.reg;
   reduce_cells_to_region<D, R, D, D>(acc, 0, sm.x.red.cellpart, reg, lcell, lk0, lk1, lane_on);
-  R* dst = tpart + (size_t)blockIdx.x * RN * D;
+  R* dst = tpart + (size_t)slot * RN * D;
   for (int i = t; i < RN * D; i += NT) dst[i] = reg[i];
   if (MODE == TM_ENERGY && energy_slot >= 0) {
     double bs = block_sum(e, sm.bsum);
-    if (t == 0) d.part[energy_slot * kPartSlot + blockIdx.x] = bs;
+    if (t == 0) d.part[energy_slot * kPartSlot + slot] = bs;
   }
 }
 
@@ -813,7 +837,9 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::HEAT) k_tile_heat(De
   constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN, PS = HeatLds<D, R>::PS, CH = HeatLds<D, R>::CH;
   __shared__ HeatLds<D, R> sm;
   if (done && *done) return;
-  const int ct = tl.ctile_list[blockIdx.x];
+  const int slot = xcd_slot(blockIdx.x, tl.xrun);
+  if (slot >= tl.nctile) return;
+  const int ct = tl.ctile_list[slot];
   const int N = d.np, S = d.ns;
   const int t = threadIdx.x;
   int org[3] = {0, 0, 0};
@@ -831,7 +857,7 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::HEAT) k_tile_heat(De
     sm.u[rn] = val;
   }
   const int cb = ct * 64;
-  const int* rg = tl.ctile_rng + 6 * blockIdx.x;
+  const int* rg = tl.ctile_rng + 6 * slot;
   const int pb = rg[0], pe = rg[1];
   const int sb = S ? rg[2] : 0, se = S ? rg[3] : 0;
   const int npi = pe - pb, ntot = npi + (se - sb);
@@ -902,7 +928,7 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::HEAT) k_tile_heat(De
   }
   R* reg = sm.x.red.reg;
   reduce_cells_to_region<D, R, 1, 1>(acc, 0, sm.x.red.cellpart, reg, lcell, lk0, lk1, lane_on);
-  R* dst = tpart + (size_t)blockIdx.x * RN;
+  R* dst = tpart + (size_t)slot * RN;
   for (int i = t; i < RN; i += NT) dst[i] = reg[i];
 }
 
