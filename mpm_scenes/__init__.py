@@ -39,6 +39,7 @@ DEFAULT_PARAMS = dict(
     newton_tol=1e-8, newton_max=20, cg_rel=1e-2, cg_max=1000, ls_max=10, ls_c1=1e-4,
     heat_tol=1e-10, heat_max=1000,
     hess_mode=0,                    # 0 = PSD (definiteness fix), 1 = EXACT
+    krylov=0,                       # 0 = CG, 1 = MINRES (for the indefinite EXACT Hessian)
     momentum_fix=1,
     term_mask=7,                    # bit0 J-term, bit1 surface, bit2 viscosity
     ls_radius=None,                 # union-of-spheres radius; None -> 0.73 dx (2D) / 0.867 dx (3D)

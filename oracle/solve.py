@@ -1,8 +1,10 @@
 """Implicit grid updates (Section 4.3).
 
 Momentum (Section 4.3.1): backward Euler solved with Newton's method.  The paper names
-Newton's method and defers the linear algebra to earlier work, so the solver details are
-chosen here: Jacobi-preconditioned CG on the projected Newton system, Armijo
+Newton's method and defers the linear algebra and the definiteness fix to earlier work,
+so the solver details are chosen here: Jacobi-preconditioned CG on the projected Newton
+system (or, for the exact and possibly indefinite surface Hessian, Jacobi-preconditioned
+MINRES with the same relative reduction in the preconditioned residual norm), Armijo
 backtracking on Phi (a trial is accepted when Phi does not exceed the Armijo bound by
 more than the round-off of Phi, 8 eps |Phi|, eps the unit round-off of the arithmetic:
 near convergence the Newton decrement falls below that round-off and the comparison
@@ -58,6 +60,59 @@ def pcg(apply, b, diag, tol_abs, maxit, x0=None):
     return x, it, float(np.sqrt(np.sum(r * r)))
 
 
+def minres(apply, b, diag, rel_tol, maxit):
+    """Preconditioned MINRES (Paige and Saunders 1975) for a symmetric, possibly indefinite
+    operator, with the SPD preconditioner diag(diag).  The Lanczos process on the
+    preconditioned operator builds a tridiagonal matrix, which a sequence of Givens
+    rotations reduces to upper triangular form one column at a time; the iterate is
+    updated along the directions w_k that this triangular factor defines, so the
+    preconditioned residual norm (tracked as phibar) never increases.  Stops when
+    phibar <= rel_tol * phibar_0, or after maxit iterations.  Returns (x, iterations,
+    phibar)."""
+    x = np.zeros_like(b)
+    r_prev = b.copy()                 # Lanczos residuals r_{k-1}, r_k (unpreconditioned)
+    r_cur = b.copy()
+    y = b / diag
+    beta = float(np.sqrt(np.sum(b * y)))
+    if beta == 0.0:
+        return x, 0, 0.0
+    beta_prev = 0.0
+    phibar = beta
+    tol = rel_tol * beta
+    c, s = -1.0, 0.0                  # last Givens rotation
+    dbar = eps_k = 0.0
+    w = np.zeros_like(b)
+    w_prev = np.zeros_like(b)
+    it = 0
+    while it < maxit and phibar > tol:
+        v = y / beta                  # Lanczos vector
+        y = apply(v)
+        if it > 0:
+            y = y - (beta / beta_prev) * r_prev
+        alpha = float(np.sum(v * y))
+        y = y - (alpha / beta) * r_cur
+        r_prev, r_cur = r_cur, y
+        y = r_cur / diag
+        beta_prev = beta
+        beta = float(np.sqrt(np.sum(r_cur * y)))
+        # previous rotation applied to the new column (entries eps, delta, gbar), then the
+        # rotation that annihilates the subdiagonal beta
+        eps_prev = eps_k
+        delta = c * dbar + s * alpha
+        gbar = s * dbar - c * alpha
+        eps_k = s * beta
+        dbar = -c * beta
+        gamma = max(float(np.hypot(gbar, beta)), np.finfo(np.float64).eps)
+        c, s = gbar / gamma, beta / gamma
+        phi = c * phibar
+        phibar = s * phibar
+        w_new = (v - eps_prev * w_prev - delta * w) / gamma
+        w_prev, w = w, w_new
+        x = x + phi * w
+        it += 1
+    return x, it, float(phibar)
+
+
 def newton(ctx, params):
     P = ctx.project
     v = P(ctx.vn.copy())
@@ -77,7 +132,12 @@ def newton(ctx, params):
         vl = v.copy()
         apply = lambda w: P(ctx.hessvec(vl, P(w)))
         cg_tol = max(params["cg_rel"] * gn, 0.1 * tol * g0)
-        delta, cit, _ = pcg(apply, -g, diag, cg_tol, params["cg_max"])
+        if params.get("krylov", 0) == 1:
+            # MINRES for an indefinite (EXACT) Hessian: the same relative reduction, measured
+            # in the preconditioned residual norm
+            delta, cit, _ = minres(apply, -g, diag, cg_tol / gn, params["cg_max"])
+        else:
+            delta, cit, _ = pcg(apply, -g, diag, cg_tol, params["cg_max"])
         stats["cg"] += cit
         stats["hessvec"] += cit
         phi0 = ctx.Phi(v)

@@ -117,3 +117,60 @@ def test_droplet_surface_energy_converges(dim):
         if R * n >= 16:
             assert errs[-1] < 0.10
     assert errs[0] > errs[1] > errs[2]
+
+
+def _sym_system(n, seed, indefinite):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.normal(size=(n, n)))
+    ev = rng.uniform(0.5, 4.0, size=n)
+    if indefinite:
+        ev[: n // 3] *= -1.0
+    A = (Q * ev) @ Q.T
+    b = rng.normal(size=n)
+    d = np.abs(np.diag(A)) + rng.uniform(0.5, 1.5, size=n)      # an SPD (diagonal) preconditioner
+    return A, b, d
+
+
+@pytest.mark.parametrize("indefinite", [False, True])
+def test_minres_solves_symmetric_systems(indefinite):
+    """MINRES (Paige-Saunders) on dense symmetric systems, definite and indefinite: the
+    solution of np.linalg.solve, and the same iterate count behaviour as SciPy's MINRES."""
+    from scipy.sparse.linalg import minres as sp_minres
+    A, b, d = _sym_system(40, 3 + indefinite, indefinite)
+    x, it, phibar = solve.minres(lambda v: A @ v, b, d, 1e-12, 400)
+    ref = np.linalg.solve(A, b)
+    assert np.linalg.norm(x - ref) <= 1e-9 * np.linalg.norm(ref)
+    xs, info = sp_minres(A, b, M=np.diag(1.0 / d), rtol=1e-12, maxiter=400)
+    assert info == 0 and np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(ref)
+
+
+def test_minres_tracks_the_preconditioned_residual():
+    """After every iteration k, the tracked phibar equals |b - A x_k| in the norm of the
+    inverse preconditioner, and it never increases (the defining property of MINRES)."""
+    A, b, d = _sym_system(30, 7, True)
+    prev = np.inf
+    for k in range(1, 31):
+        x, it, phibar = solve.minres(lambda v: A @ v, b, d, 0.0, k)
+        r = b - A @ x
+        true = np.sqrt(np.sum(r * r / d))
+        assert it == k
+        assert abs(phibar - true) <= 1e-9 * np.sqrt(np.sum(b * b / d)), (k, phibar, true)
+        assert phibar <= prev * (1 + 1e-12)
+        prev = phibar
+
+
+def test_newton_with_minres_and_exact_hessian():
+    """Newton with the exact surface Hessian, each step solved by MINRES: the solution is
+    stationary and conserves momentum with the translation correction."""
+    S = sc.square2d(n=32)
+    P, p = S["particles"], dict(S["params"], newton_tol=1e-10, hess_mode=1, krylov=1)
+    rng = np.random.default_rng(8)
+    P["v"] = rng.normal(size=P["v"].shape) * 0.05
+    newP, info = step.step(P, p)
+    assert info["converged"] and info["cg"] > 0
+    ctx = step.prepare(P, p, info["surf"])[-1]
+    g = ctx.project(ctx.grad_Phi(info["vhat"]))
+    assert np.linalg.norm(g) <= 1e-9 * info["g0"]
+    mom0 = (P["m"][:, None] * P["v"]).sum(0)
+    mom1 = (P["m"][:, None] * newP["v"]).sum(0)
+    assert np.allclose(mom0, mom1, rtol=0, atol=1e-15 * np.abs(P["m"][:, None] * P["v"]).sum())
