@@ -59,6 +59,7 @@ enum mpm_status {
 
 enum mpm_precision { MPM_FP64 = 0, MPM_MIXED = 1 };
 enum mpm_hess_mode { MPM_HESS_PSD = 0, MPM_HESS_EXACT = 1 };
+enum mpm_krylov { MPM_KRYLOV_CG = 0, MPM_KRYLOV_MINRES = 1 };
 enum mpm_term { MPM_TERM_J = 1, MPM_TERM_SURF = 2, MPM_TERM_VISC = 4 };
 
 /* Scene and solver parameters (Sections 3, 4 and the per-example values of Section 6). */
@@ -77,6 +78,11 @@ typedef struct mpm_params {
   int32_t heat;           /* 1: run the implicit heat update (Section 4.3.2)           */
   int32_t gamma_by_label; /* 1: k_r = gamma_label[label_r] (piecewise constant, Sec 3.6) */
   int32_t newton_max, cg_max, ls_max, heat_max;
+  int32_t krylov;         /* mpm_krylov: the Newton system's solver.  CG (with the PSD
+                             Hessian); MINRES (Paige-Saunders, Jacobi-preconditioned) for
+                             the EXACT Hessian, which may be indefinite: it stops at the
+                             same relative reduction as CG, measured in the preconditioned
+                             residual norm; cg_max caps both                            */
   double dx, dt;
   double gravity[3];
   double bulk;            /* lambda^l in Psi^p(J) = lambda/2 (J-1)^2 (Section 3.2.1)   */

@@ -18,7 +18,7 @@ MPM_FP64, MPM_MIXED = 0, 1
 class MpmParams(C.Structure):
     _fields_ = [(k, C.c_int32) for k in (
         "dim", "n", "precision", "hess_mode", "term_mask", "momentum_fix", "wall_layers", "slab",
-        "slab_axis", "heat", "gamma_by_label", "newton_max", "cg_max", "ls_max", "heat_max")] + [
+        "slab_axis", "heat", "gamma_by_label", "newton_max", "cg_max", "ls_max", "heat_max", "krylov")] + [
         ("dx", C.c_double), ("dt", C.c_double), ("gravity", C.c_double * 3), ("bulk", C.c_double),
         ("mu0", C.c_double), ("mu_k", C.c_double), ("mu_T0", C.c_double),
         ("g0", C.c_double), ("g1", C.c_double), ("gT0", C.c_double), ("gmin", C.c_double), ("gmax", C.c_double),

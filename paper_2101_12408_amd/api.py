@@ -33,7 +33,7 @@ def make_params(d, precision="fp64"):
     _check(lib.mpm_params_default(C.byref(p), int(d["dim"]), int(d["n"])), lib)
     p.precision = L.MPM_FP64 if precision == "fp64" else L.MPM_MIXED
     ints = ("hess_mode", "term_mask", "momentum_fix", "wall_layers", "slab", "slab_axis", "heat",
-            "gamma_by_label", "newton_max", "cg_max", "ls_max", "heat_max")
+            "gamma_by_label", "newton_max", "cg_max", "ls_max", "heat_max", "krylov")
     for k in ints:
         if k in d:
             setattr(p, k, int(d[k]))

@@ -949,6 +949,167 @@ __global__ void k_cg_update(const int* tl, int nelem, int nn, int ncomp, CgScal*
   }
 }
 
+// ---- preconditioned MINRES (Paige and Saunders 1975) -----------------------------------
+// For the Newton system with the exact surface Hessian, which may be indefinite.  The
+// Lanczos process on the Jacobi-preconditioned operator gives a tridiagonal matrix; one
+// Givens rotation per iteration keeps its QR factor, and the iterate moves along the
+// directions w of that factor, so the preconditioned residual norm phibar never grows.
+// Scalars in FP64 on the device; every kernel of an iteration returns at once when the
+// solve has finished.  Vectors: y (preconditioned residual, the Hessian's input), t (the
+// Hessian's output, then the next residual), v (Lanczos vector), r_prev, r_cur, w, w_prev,
+// x.
+struct MinresScal {
+  double beta, beta_prev, alpha, dbar, eps, eps_prev, delta, phibar, phi, c, s, gamma, tol;
+  int done, iters, maxit, breakdown;
+};
+
+// r_prev = r_cur = bscale b, y = r / diag, x = w = w_prev = 0; beta = sqrt(r . y).
+template <typename R>
+__global__ void k_minres_start(const int* tl, int nelem, int nn, int ncomp, const R* b, R bscale, const R* diag,
+                               R* x, R* rprev, R* rcur, R* y, R* w, R* wprev, double* part, unsigned* ctr,
+                               MinresScal* ms, double rel_tol, int maxit) {
+  __shared__ double sh[kRedSh];
+  double ry = 0;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nelem; e += gridDim.x * blockDim.x) {
+    const int node = elem_node(tl, e);
+    R bv[kMaxComp], dv[kMaxComp];
+#pragma unroll
+    for (int c = 0; c < kMaxComp; ++c) {
+      if (c >= ncomp) break;
+      bv[c] = b[c * nn + node];
+      dv[c] = diag[c * nn + node];
+    }
+#pragma unroll
+    for (int c = 0; c < kMaxComp; ++c) {
+      if (c >= ncomp) break;
+      const int j = c * nn + node;
+      const R rv = bscale * bv[c], yv = rv / dv[c];
+      x[j] = 0; w[j] = 0; wprev[j] = 0;
+      rprev[j] = rv; rcur[j] = rv; y[j] = yv;
+      ry += (double)rv * (double)yv;
+    }
+  }
+  double t = block_sum(ry, sh), r;
+  if (grid_reduce<1>(&t, part, ctr, sh, &r) && threadIdx.x == 0) {
+    const double beta = sqrt(r > 0 ? r : 0.0);
+    ms->beta = beta; ms->beta_prev = 0; ms->alpha = 0; ms->dbar = 0; ms->eps = 0; ms->eps_prev = 0;
+    ms->delta = 0; ms->phibar = beta; ms->phi = 0; ms->c = -1; ms->s = 0; ms->gamma = 0;
+    ms->tol = rel_tol * beta;
+    ms->iters = 0; ms->maxit = maxit; ms->breakdown = 0;
+    ms->done = (beta == 0.0 || !(beta == beta) || maxit <= 0) ? 1 : 0;
+  }
+}
+
+// Lanczos, first half (t holds A y): v = y / beta, t = A v - (beta / beta_prev) r_prev
+// (no r_prev term on the first iteration), alpha = v . t.
+template <typename R>
+__global__ void k_minres_lanczos(const int* tl, int nelem, int nn, int ncomp, const R* y, R* t, R* v, const R* rprev,
+                                 double* part, unsigned* ctr, MinresScal* ms) {
+  __shared__ double sh[kRedSh];
+  if (ms->done) return;
+  const double beta = ms->beta;
+  const R inv = (R)(1.0 / beta), co = ms->iters > 0 ? (R)(beta / ms->beta_prev) : R(0);
+  double va = 0;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nelem; e += gridDim.x * blockDim.x) {
+    const int node = elem_node(tl, e);
+    R yv[kMaxComp], tv[kMaxComp], rv[kMaxComp];
+#pragma unroll
+    for (int c = 0; c < kMaxComp; ++c) {
+      if (c >= ncomp) break;
+      const int j = c * nn + node;
+      yv[c] = y[j]; tv[c] = t[j]; rv[c] = rprev[j];
+    }
+#pragma unroll
+    for (int c = 0; c < kMaxComp; ++c) {
+      if (c >= ncomp) break;
+      const int j = c * nn + node;
+      const R vv = yv[c] * inv, tn = tv[c] * inv - co * rv[c];
+      v[j] = vv; t[j] = tn;
+      va += (double)vv * (double)tn;
+    }
+  }
+  double bsum = block_sum(va, sh), a;
+  if (grid_reduce<1>(&bsum, part, ctr, sh, &a) && threadIdx.x == 0) ms->alpha = a;
+}
+
+// Lanczos, second half, and the rotation: t -= (alpha / beta) r_cur (t becomes the next
+// residual), y = t / diag, beta' = sqrt(t . y); then the previous rotation applied to the
+// new column and the rotation that annihilates beta'.  Sets done at phibar <= tol or at
+// the iteration cap.
+template <typename R>
+__global__ void k_minres_rotate(const int* tl, int nelem, int nn, int ncomp, R* t, const R* rcur, const R* diag,
+                                R* y, double* part, unsigned* ctr, MinresScal* ms) {
+  __shared__ double sh[kRedSh];
+  if (ms->done) return;
+  const R co = (R)(ms->alpha / ms->beta);
+  double ty = 0;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nelem; e += gridDim.x * blockDim.x) {
+    const int node = elem_node(tl, e);
+    R tv[kMaxComp], rv[kMaxComp], dv[kMaxComp];
+#pragma unroll
+    for (int c = 0; c < kMaxComp; ++c) {
+      if (c >= ncomp) break;
+      const int j = c * nn + node;
+      tv[c] = t[j]; rv[c] = rcur[j]; dv[c] = diag[j];
+    }
+#pragma unroll
+    for (int c = 0; c < kMaxComp; ++c) {
+      if (c >= ncomp) break;
+      const int j = c * nn + node;
+      const R tn = tv[c] - co * rv[c], yn = tn / dv[c];
+      t[j] = tn; y[j] = yn;
+      ty += (double)tn * (double)yn;
+    }
+  }
+  double bsum = block_sum(ty, sh), b2;
+  if (grid_reduce<1>(&bsum, part, ctr, sh, &b2) && threadIdx.x == 0) {
+    const double beta = sqrt(b2 > 0 ? b2 : 0.0), alpha = ms->alpha;
+    ms->beta_prev = ms->beta;
+    ms->beta = beta;
+    ms->eps_prev = ms->eps;
+    ms->delta = ms->c * ms->dbar + ms->s * alpha;
+    const double gbar = ms->s * ms->dbar - ms->c * alpha;
+    ms->eps = ms->s * beta;
+    ms->dbar = -ms->c * beta;
+    const double gamma = fmax(hypot(gbar, beta), 2.220446049250313e-16);
+    ms->gamma = gamma;
+    ms->c = gbar / gamma;
+    ms->s = beta / gamma;
+    ms->phi = ms->c * ms->phibar;
+    ms->phibar = ms->s * ms->phibar;
+    ms->iters += 1;
+    if (!(b2 == b2) || !(alpha == alpha)) ms->breakdown = 1;
+    if (ms->breakdown || fabs(ms->phibar) <= ms->tol || ms->iters >= ms->maxit || beta == 0.0) ms->done = 1;
+  }
+}
+
+// The iterate of iteration `it` (skipped unless that iteration's rotation ran): w' = (v -
+// eps_prev w_prev - delta w) / gamma, written over w_prev, x += phi w'.
+template <typename R>
+__global__ void k_minres_step(const int* tl, int nelem, int nn, int ncomp, const R* v, const R* w, R* wprev, R* x,
+                              const MinresScal* ms, int it) {
+  if (ms->iters != it) return;
+  const R ep = (R)ms->eps_prev, de = (R)ms->delta, ig = (R)(1.0 / ms->gamma), ph = (R)ms->phi;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nelem; e += gridDim.x * blockDim.x) {
+    const int node = elem_node(tl, e);
+    R vv[kMaxComp], wv[kMaxComp], pv[kMaxComp], xv[kMaxComp];
+#pragma unroll
+    for (int c = 0; c < kMaxComp; ++c) {
+      if (c >= ncomp) break;
+      const int j = c * nn + node;
+      vv[c] = v[j]; wv[c] = w[j]; pv[c] = wprev[j]; xv[c] = x[j];
+    }
+#pragma unroll
+    for (int c = 0; c < kMaxComp; ++c) {
+      if (c >= ncomp) break;
+      const int j = c * nn + node;
+      const R wn = (vv[c] - ep * pv[c] - de * wv[c]) * ig;
+      wprev[j] = wn;
+      x[j] = xv[c] + ph * wn;
+    }
+  }
+}
+
 // After the loop: breakdown at the first iteration takes the preconditioned residual.
 template <typename R>
 __global__ void k_cg_fixup(const int* tl, int nelem, int nn, int ncomp, const CgScal* s, R* x, const R* z) {

@@ -308,6 +308,7 @@ void check_params(const mpm_params* p) {
   if (!(p->dt > 0)) throw ApiError{MPM_EINVAL, "dt must be positive"};
   if (p->precision != MPM_FP64 && p->precision != MPM_MIXED) throw ApiError{MPM_EINVAL, "bad precision"};
   if (p->slab_axis < 0 || p->slab_axis >= p->dim) throw ApiError{MPM_EINVAL, "bad slab_axis"};
+  if (p->krylov != MPM_KRYLOV_CG && p->krylov != MPM_KRYLOV_MINRES) throw ApiError{MPM_EINVAL, "bad krylov"};
 }
 
 // Scratch of one cell sort: cell counters (zero between sorts), the scan's status words
@@ -544,6 +545,11 @@ void do_p2g(mpm_ctx* c, const mpm_particles* P, const mpm_surface* S, hipStream_
 // the trial's slope g . delta.
 // SC_GO / SC_TOL2: the device's decision on the next Newton iteration (newton_decide).
 enum : int { SC_DOT = 1, SC_RHS2 = 5, SC_MOM = 8, SC_G0 = 16, SC_GT = 32, SC_GO = 40, SC_TOL2 = 41, SC_N = 48 };
+// MINRES scalars (momentum solve with krylov = MINRES) at scal[SC_N ..], inside the block
+// the host reads back.
+static_assert(SC_N * sizeof(double) + sizeof(MinresScal) <= (size_t)kScalDoubles * sizeof(double), "MINRES scalars");
+inline MinresScal* minres_dev(mpm_ctx* c) { return (MinresScal*)(c->scal + SC_N); }
+inline const MinresScal* minres_host(mpm_ctx* c) { return (const MinresScal*)(c->hbuf + SC_N); }
 
 // Phi(u), the momentum sums and |g|^2 into scal[red_slot ..] (Phi also into energy_dev if
 // given), projected gradient into g.
@@ -1026,6 +1032,154 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
   c->mom_pending = true;
 }
 
+// Preconditioned MINRES on the projected Newton system for the right side bscale * b,
+// into x; stops at phibar <= rel_tol phibar_0 or after maxit iterations.  Uses the two CG
+// vector sets (nine vectors) and the CG reduction slots.  Chunks of iterations are queued
+// ahead of the host's check, as for CG; iterations past convergence return at once.
+// Returns the iteration count.
+template <int D, typename R>
+int minres_solve(mpm_ctx* c, const R* b, double bscale, R* x, double rel_tol, int maxit, hipStream_t s) {
+  Dev<R>& d = dev<R>(c);
+  const int nelem = c->ntiles * 64, nb = krylov_blocks(nelem);
+  const int* tl = d.tile_list;
+  MinresScal* ms = minres_dev(c);
+  R* y = (R*)c->r;
+  R* t = (R*)c->z;
+  R* v = (R*)c->pp;
+  R* rp = (R*)c->Ap;
+  R* rc = (R*)c->cg2[0];
+  R* w = (R*)c->cg2[1];
+  R* wp = (R*)c->cg2[2];
+  unsigned* ctr_a = c->ctr + (size_t)CTR_CGSTART * kCtrSite;
+  unsigned* ctr_b = c->ctr + (size_t)CTR_CGUPD * kCtrSite;
+  LAUNCH(c, MPM_K_BLAS, k_minres_start<R>, dim3(nb), dim3(kNodeThreads), 0, s, tl, nelem, d.nn, D, b, (R)bscale,
+         (const R*)d.gdiag, x, rp, rc, y, w, wp, c->part, ctr_a, ms, rel_tol, maxit);
+  int launched = 0, chunk = first_chunk(c->cg_hint_mom);
+  for (;;) {
+    for (int j = 0; j < chunk; ++j) {
+      do_hessvec<D, R>(c, (const R*)y, 1.0, t, false, &ms->done, (CgScal*)nullptr, s);
+      LAUNCH(c, MPM_K_BLAS, k_minres_lanczos<R>, dim3(nb), dim3(kNodeThreads), 0, s, tl, nelem, d.nn, D, (const R*)y,
+             t, v, (const R*)rp, c->part, ctr_a, ms);
+      LAUNCH(c, MPM_K_BLAS, k_minres_rotate<R>, dim3(nb), dim3(kNodeThreads), 0, s, tl, nelem, d.nn, D, t,
+             (const R*)rc, (const R*)d.gdiag, y, c->part, ctr_b, ms);
+      LAUNCH(c, MPM_K_BLAS, k_minres_step<R>, dim3(nb), dim3(kNodeThreads), 0, s, tl, nelem, d.nn, D, (const R*)v,
+             (const R*)w, wp, x, (const MinresScal*)ms, launched + j + 1);
+      // (r_prev, r_cur) <- (r_cur, t); t takes the old r_prev; (w_prev, w) <- (w, w')
+      R* old_rp = rp;
+      rp = rc;
+      rc = t;
+      t = old_rp;
+      std::swap(w, wp);
+    }
+    launched += chunk;
+    read_mirror(c, s);
+    if (minres_host(c)->done || launched >= maxit + 32) break;
+    chunk = std::min(chunk * 2, 16);
+  }
+  const MinresScal* hm = minres_host(c);
+  if (hm->breakdown) c->status |= ST_NONFINITE;
+  c->cg_hint_mom = hm->iters;
+  return hm->iters;
+}
+
+// Newton on Phi with each step solved by MINRES (krylov = MINRES), in the order of the
+// oracle's Newton loop: no work is queued ahead of the host's decisions.  Same stopping
+// tests, Armijo line search and translation correction as the CG path.
+template <int D, typename R>
+void do_solve_momentum_minres(mpm_ctx* c, hipStream_t s) {
+  if (!c->have_p2g) throw ApiError{MPM_EINVAL, "mpm_p2g must run first"};
+  Dev<R>& d = dev<R>(c);
+  const mpm_params& p = c->p;
+  const int nelem = c->ntiles * 64, nb = krylov_blocks(nelem);
+  const int* tl = d.tile_list;
+  mpm_stats& st = c->stats;
+  LAUNCH(c, MPM_K_BLAS, k_project_copy<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const uint8_t*)d.gfree,
+         (const R*)d.gvn, (R*)c->vhat);
+  do_energy_grad<D, R>(c, (const R*)c->vhat, (R*)c->grad, nullptr, SC_G0, s, PUpd<R>{}, nullptr,
+                       (d.term_mask & 2) ? d.sF : nullptr);
+  read_mirror(c, s);
+  const bool fix = p.momentum_fix && !c->constrained;
+  const double msum = c->hbuf[SC_G0 + 1 + D];
+  const double floor_abs = 1e-14 * msum * p.dx / p.dt;
+  double phi = c->hbuf[SC_G0];
+  double gn = std::sqrt(std::max(c->hbuf[SC_G0 + D + 2], 0.0));
+  const double g0 = gn;
+  st.g0 = g0;
+  st.energy_evals = 1;
+  st.converged = 0;
+  const double eps = sizeof(R) == 8 ? 2.220446049250313e-16 : 1.1920928955078125e-07;
+  int it = 0;
+  double gn_prev = 1e300;
+  for (; it < p.newton_max; ++it) {
+    if (!(gn == gn) || !(phi == phi)) { c->status |= ST_NONFINITE; break; }
+    if (gn <= std::max(p.newton_tol * g0, floor_abs)) { st.converged = 1; break; }
+    // MIXED: the FP32 gradient's round-off floor, as in the CG path
+    if (sizeof(R) == 4 && it > 0 && gn <= 1e-4 * g0 && gn > 0.5 * gn_prev) { st.converged = 2; break; }
+    gn_prev = gn;
+    const double cg_tol = std::max(p.cg_rel * gn, 0.1 * p.newton_tol * g0);
+    R* delta = (R*)c->delta;
+    const int kit = minres_solve<D, R>(c, (const R*)c->grad, -1.0, delta, cg_tol / gn, p.cg_max, s);
+    st.cg_iters += kit;
+    st.hessvecs += kit;
+    auto trial = [&](double a) {
+      do_energy_grad<D, R>(c, (const R*)delta, (R*)c->gscratch, nullptr, SC_GT, s,
+                           PUpd<R>{(R*)c->vtrial, (const R*)c->vhat, nullptr, (R)a}, (const R*)c->grad,
+                           (d.term_mask & 2) ? (R*)c->sF_alt : nullptr);
+      if (p.momentum_fix)
+        LAUNCH(c, MPM_K_BLAS, (k_mom_fix<D, R>), dim3(nb), dim3(kNodeThreads), 0, s, tl, nelem, d.nn,
+               (const uint8_t*)d.gfree, (const R*)d.gm, (const double*)(c->scal + SC_GT + 1), p.dt, p.gravity[0],
+               p.gravity[1], p.gravity[2], (R*)c->vtrial, (R*)c->gscratch, c->part,
+               c->ctr + (size_t)CTR_MOM * kCtrSite, c->scal + SC_GT + D + 2, (const int*)(c->misc + 1),
+               (const R*)d.gvn, c->scal + SC_MOM, NextCgStart<R>{}, NewtonDecide{});
+      st.energy_evals++;
+      read_mirror(c, s);
+    };
+    double alpha = 1.0;
+    trial(alpha);
+    const double slope = c->hbuf[SC_GT + D + 3];
+    double phit = c->hbuf[SC_GT];
+    for (int ls = 1; ls < std::max(p.ls_max, 1); ++ls) {
+      const double noise = 8.0 * eps * std::max(std::fabs(phi), std::fabs(phit));
+      if (phit <= phi + p.ls_c1 * alpha * slope + noise) break;
+      alpha *= 0.5;
+      st.line_search_halvings++;
+      trial(alpha);
+      phit = c->hbuf[SC_GT];
+    }
+    // accept the last trial (its corrected point, gradient and surface linearization)
+    std::swap(c->vhat, c->vtrial);
+    {
+      R* f_acc = (R*)c->sF_alt;
+      c->sF_alt = d.sF;
+      d.sF = f_acc;
+    }
+    std::swap(c->grad, c->gscratch);
+    phi = phit;
+    if (fix) {
+      const double* red = c->hbuf + SC_GT + 1;
+      const double M = red[D];
+      double c2 = 0;
+      for (int a2 = 0; a2 < D; ++a2) {
+        const double ca = (red[a2] - p.dt * p.gravity[a2] * M) / M;
+        c2 += ca * ca;
+      }
+      phi -= 0.5 * M * c2;
+    }
+    gn = std::sqrt(std::max(c->hbuf[SC_GT + D + 2], 0.0));
+  }
+  if (it == p.newton_max && gn <= std::max(p.newton_tol * g0, floor_abs)) st.converged = 1;
+  st.newton_iters = it;
+  st.gnorm = gn;
+  st.phi = phi;
+  if (!st.converged && !(c->status & ST_NONFINITE)) c->status |= ST_NOCONV;
+  if (p.momentum_fix && it > 0) {
+    // the momentum sums of the accepted point were formed by its translation correction
+  } else {
+    mom_sums_async<D, R>(c, (const R*)c->vhat, s);
+  }
+  c->mom_pending = true;
+}
+
 template <int D, typename R>
 void do_explicit(mpm_ctx* c, hipStream_t s) {
   if (!c->have_p2g) throw ApiError{MPM_EINVAL, "mpm_p2g must run first"};
@@ -1395,7 +1549,8 @@ int mpm_solve_momentum(mpm_ctx* ctx, void* stream) {
     dispatch(ctx, [&](auto Dc, auto Rv) {
       constexpr int D = decltype(Dc)::value;
       using R = decltype(Rv);
-      do_solve_momentum<D, R>(ctx, s);
+      if (ctx->p.krylov == MPM_KRYLOV_MINRES) do_solve_momentum_minres<D, R>(ctx, s);
+      else do_solve_momentum<D, R>(ctx, s);
     });
   });
   if (rc != MPM_OK) return rc;
@@ -1458,8 +1613,9 @@ int step_one(mpm_ctx* c, mpm_particles* P, const mpm_surface* S, int implicit, h
           hs = aux_fork(c, s, &c->ev_fork);
           heat_begin<D, R>(c, hs, run);
         }
-        if (implicit) do_solve_momentum<D, R>(c, s);
-        else do_explicit<D, R>(c, s);
+        if (!implicit) do_explicit<D, R>(c, s);
+        else if (c->p.krylov == MPM_KRYLOV_MINRES) do_solve_momentum_minres<D, R>(c, s);
+        else do_solve_momentum<D, R>(c, s);
         if (heat) {
           heat_end<D, R>(c, hs, run);
           aux_mark(c, hs, &c->ev_join);

@@ -249,3 +249,45 @@ def test_batch_concurrent_matches_sequential():
         for a, b in zip(runs[0], other):
             for k in a:
                 assert np.array_equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("case", ["square2d", "marangoni3d_small", "contact_small"])
+def test_minres_exact_step_matches_oracle_fp64(case):
+    """krylov = MINRES with the exact (possibly indefinite) surface Hessian: one FP64 step
+    against the oracle's Newton-MINRES step, at the bar of the CG step tests."""
+    log(f"case minres step {case}")
+    if case == "square2d":
+        S = sc.square2d(n=32)
+        rng = np.random.default_rng(3)
+        S["particles"]["v"] = rng.normal(size=S["particles"]["v"].shape) * 0.05
+    elif case == "marangoni3d_small":
+        S = sc.marangoni3d(n=32, radius=0.25)
+    else:
+        S = sc.contact3d(n=48, radius=0.12)
+    P, p = S["particles"], dict(S["params"], hess_mode=1, krylov=1, **TIGHT)
+    surf = sampler.sample_surface(P["x"], p)
+    ref, info = ostep.step(P, p, surf)
+    got, st, rc = _gpu_step(P, surf, p)
+    log(f"  gpu newton {st['newton_iters']} minres {st['cg_iters']} rc {rc}; oracle newton {info['newton']} "
+        f"minres {info['cg']}")
+    assert rc == 0 and st["converged"] == 1
+    for k in ("v", "A", "J", "x", "T"):
+        e = rel(got[k] - P[k], ref[k] - P[k]) if k in ("x", "J") else rel(got[k], ref[k])
+        log(f"  {k}: rel {e:.3e}")
+        assert e < 1e-7, k
+
+
+def test_minres_mixed_step_error_report():
+    """MINRES in MIXED precision against the FP64 oracle: bounded at the FP32 level."""
+    S = sc.marangoni3d(n=32, radius=0.25)
+    P, p = S["particles"], dict(S["params"], hess_mode=1, krylov=1, newton_tol=1e-6)
+    surf = sampler.sample_surface(P["x"], p)
+    P32, surf32 = round_inputs(P, surf, "mixed")
+    ref, info = ostep.step(P32, p, surf32)
+    got, st, rc = _gpu_step(P32, surf32, p, precision="mixed")
+    log(f"  mixed minres: newton {st['newton_iters']} minres {st['cg_iters']} converged {st['converged']}")
+    assert rc == 0
+    for k in ("v", "A", "T"):
+        e = rel(got[k], ref[k])
+        log(f"  mixed {k}: rel {e:.3e}")
+        assert e < 1e-3, k
