@@ -95,6 +95,13 @@ typedef struct mpm_params {
   double cg_rel;          /* inner CG: |r| <= max(cg_rel |g|, 0.1 newton_tol |g_0|)    */
   double ls_c1;           /* Armijo constant of the backtracking line search           */
   double heat_tol;        /* heat CG: |r| <= heat_tol |rhs|                            */
+  double cfl;             /* > 0: mpm_step chooses each step's dt from the particles it
+                             is given (the paper's CFL-limited dt): explicit
+                             dt = clamp(cfl dx / (max_p |v_p| + sqrt(bulk / rho_min)),
+                             dt_min, dt_max), implicit dt = clamp(cfl dx / max_p |v_p|,
+                             dt_min, dt_max), rho_p = m_p / V0_p; the dt taken is in
+                             mpm_stats.dt.  <= 0: the fixed dt above                     */
+  double dt_min, dt_max;
 } mpm_params;
 
 /* Interior MPM particles (Section 4): SoA device buffers of real, n items each.
@@ -130,6 +137,7 @@ typedef struct mpm_stats {
   double momentum[3];     /* sum_i m_i v^_i over the grid after the solve (FP64); after
                              an implicit mpm_step, set by the next mpm_scene_status      */
   int64_t n_part, n_surf, n_dof, n_tiles;
+  double dt;              /* the time step of the last step                           */
 } mpm_stats;
 
 /* Grid fields readable through mpm_grid_view (device pointers into the workspace). */

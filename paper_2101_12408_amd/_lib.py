@@ -25,7 +25,8 @@ class MpmParams(C.Structure):
         ("gamma_label", C.c_double * 4),
         ("cp", C.c_double), ("K", C.c_double), ("h", C.c_double), ("T_amb", C.c_double), ("b", C.c_double),
         ("H", C.c_double), ("slab_lo", C.c_double * 3), ("slab_hi", C.c_double * 3),
-        ("newton_tol", C.c_double), ("cg_rel", C.c_double), ("ls_c1", C.c_double), ("heat_tol", C.c_double)]
+        ("newton_tol", C.c_double), ("cg_rel", C.c_double), ("ls_c1", C.c_double), ("heat_tol", C.c_double),
+        ("cfl", C.c_double), ("dt_min", C.c_double), ("dt_max", C.c_double)]
 
 
 class MpmParticles(C.Structure):
@@ -42,7 +43,7 @@ class MpmStats(C.Structure):
         "converged", "status")] + [
         ("g0", C.c_double), ("gnorm", C.c_double), ("phi", C.c_double), ("heat_res", C.c_double),
         ("momentum", C.c_double * 3), ("n_part", C.c_int64), ("n_surf", C.c_int64), ("n_dof", C.c_int64),
-        ("n_tiles", C.c_int64)]
+        ("n_tiles", C.c_int64), ("dt", C.c_double)]
 
 
 class MpmRequest(C.Structure):

@@ -38,7 +38,7 @@ def make_params(d, precision="fp64"):
         if k in d:
             setattr(p, k, int(d[k]))
     for k in ("dx", "dt", "bulk", "mu0", "mu_k", "mu_T0", "g0", "g1", "gT0", "gmin", "gmax", "cp", "K", "h",
-              "T_amb", "b", "H", "newton_tol", "cg_rel", "ls_c1", "heat_tol"):
+              "T_amb", "b", "H", "newton_tol", "cg_rel", "ls_c1", "heat_tol", "cfl", "dt_min", "dt_max"):
         if k in d:
             setattr(p, k, float(d[k]))
     for k, ln in (("gravity", 3), ("gamma_label", 4), ("slab_lo", 3), ("slab_hi", 3)):

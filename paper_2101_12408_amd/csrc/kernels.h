@@ -949,6 +949,44 @@ __global__ void k_cg_update(const int* tl, int nelem, int nn, int ncomp, CgScal*
   }
 }
 
+// ---- CFL-limited time step ------------------------------------------------------------
+// The fastest particle speed and the smallest density of a particle set, as the bit
+// patterns of non-negative doubles (whose unsigned order is their numeric order), so an
+// integer max / min gives the same result in any order.  out[0]: max |v_p|^2 (start 0),
+// out[1]: min m_p / V0_p (start +inf).  |v|^2 = (v0^2 + v1^2) + v2^2 with separate
+// roundings, as any reference summing axis by axis in FP64.
+MPM_DEV double speed2_rn(const double* v, int D) {
+  double s = __dmul_rn(v[0], v[0]);
+  for (int a = 1; a < D; ++a) s = __dadd_rn(s, __dmul_rn(v[a], v[a]));
+  return s;
+}
+
+__global__ void k_cfl_init(unsigned long long* out) {
+  out[0] = 0ull;
+  out[1] = 0x7FF0000000000000ull;   // +inf
+}
+
+template <int D, typename R>
+__global__ void k_max_speed(int n, const R* v, const R* m, const R* V0, unsigned long long* out) {
+  double vmax2 = 0, rmin = __longlong_as_double(0x7FF0000000000000ll);
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
+    double vv[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < D; ++a) vv[a] = (double)v[(size_t)a * n + p];
+    vmax2 = fmax(vmax2, speed2_rn(vv, D));
+    rmin = fmin(rmin, __ddiv_rn((double)m[p], (double)V0[p]));
+  }
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    vmax2 = fmax(vmax2, __shfl_xor(vmax2, o, kWave));
+    rmin = fmin(rmin, __shfl_xor(rmin, o, kWave));
+  }
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    atomicMax(&out[0], (unsigned long long)__double_as_longlong(vmax2));
+    atomicMin(&out[1], (unsigned long long)__double_as_longlong(rmin));
+  }
+}
+
 // ---- preconditioned MINRES (Paige and Saunders 1975) -----------------------------------
 // For the Newton system with the exact surface Hessian, which may be indefinite.  The
 // Lanczos process on the Jacobi-preconditioned operator gives a tridiagonal matrix; one

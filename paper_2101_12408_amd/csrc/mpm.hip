@@ -31,6 +31,8 @@ constexpr int kMirrorBytes = 1024, kMirrorCg = 512, kMirrorMisc = 768, kMirrorRe
 // Host-only slot of the pinned mirror (past the part that read_mirror copies): the heat
 // solve's CG scalars, read on their own stream.
 constexpr int kMirrorHeatHost = 896;
+// The CFL step's particle maxima (k_max_speed), behind the three CG scalar sets.
+constexpr int kMirrorCfl = 752;
 
 struct HipError {
   hipError_t e;
@@ -252,6 +254,7 @@ size_t layout(mpm_ctx* c, char* base) {
   d.scal = (double*)mirror;
   CgScal* cg = (CgScal*)(mirror + kMirrorCg);
   static_assert(kScalDoubles * sizeof(double) <= kMirrorCg && kMirrorCg + 3 * sizeof(CgScal) <= kMirrorMisc &&
+                    kMirrorCg + 3 * sizeof(CgScal) <= kMirrorCfl && kMirrorCfl + 16 <= kMirrorMisc &&
                     kMirrorMisc + 8 * sizeof(int) <= kMirrorRead && kMirrorRead <= kMirrorHeatHost &&
                     kMirrorHeatHost + sizeof(CgScal) <= kMirrorBytes,
                 "mirror layout");
@@ -1596,8 +1599,41 @@ struct NoallocSlot {
 };
 NoallocSlot g_noalloc[kMaxDevices];
 
+// The CFL-limited dt of the coming step (params cfl > 0), from the particles P: the
+// fastest speed and, for an explicit step, the pressure-wave speed sqrt(bulk / rho_min)
+// of the weakly compressible fluid; clamped to [dt_min, dt_max].  Sets the context's dt.
+void choose_dt(mpm_ctx* c, const mpm_particles* P, int implicit, hipStream_t s) {
+  if (!P || P->n <= 0 || !P->v || !P->m || !P->V0) throw ApiError{MPM_EINVAL, "null particle buffer"};
+  unsigned long long* dv = (unsigned long long*)((char*)c->scal + kMirrorCfl);
+  hipLaunchKernelGGL(k_cfl_init, dim3(1), dim3(1), 0, s, dv);
+  const int nb = std::min(1024, cdiv(P->n, 256));
+  dispatch(c, [&](auto Dc, auto Rv) {
+    constexpr int D = decltype(Dc)::value;
+    using R = decltype(Rv);
+    hipLaunchKernelGGL((k_max_speed<D, R>), dim3(nb), dim3(256), 0, s, (int)P->n, (const R*)P->v, (const R*)P->m,
+                       (const R*)P->V0, dv);
+  });
+  HIPCHK(hipGetLastError());
+  read_mirror(c, s);
+  const double vmax = std::sqrt(*(const double*)(c->hmirror + kMirrorCfl));
+  const double rho_min = *(const double*)(c->hmirror + kMirrorCfl + 8);
+  double speed = vmax;
+  if (!implicit) speed = vmax + std::sqrt(c->p.bulk / rho_min);
+  double dt = speed > 0 ? c->p.cfl * c->p.dx / speed : c->p.dt_max;
+  dt = std::min(std::max(dt, c->p.dt_min), c->p.dt_max);
+  if (!(dt > 0)) throw ApiError{MPM_EINVAL, "CFL dt not positive: dt_max must be > 0"};
+  c->p.dt = dt;
+  if (c->fp64) fill_params(c->d64, c->p, c->nt);
+  else fill_params(c->d32, c->p, c->nt);
+}
+
 int step_one(mpm_ctx* c, mpm_particles* P, const mpm_surface* S, int implicit, hipStream_t s) {
+  if (c->p.cfl > 0) {
+    const int rc0 = guarded(c, [&] { choose_dt(c, P, implicit, s); });
+    if (rc0 != MPM_OK) return rc0;
+  }
   int rc = mpm_p2g(c, P, S, s);
+  c->stats.dt = c->p.dt;
   bool synced = false;   // true when the final read covered all queued work and the status
   if (rc == MPM_OK) {
     rc = guarded(c, [&] {

@@ -139,6 +139,82 @@ def test_explicit_steps_conserve_on_gpu():
         assert np.allclose(com, hist[0][2], rtol=0, atol=1e-13)
 
 
+def _host_state(Pd, d):
+    N = Pd["m"].shape[0]
+    return dict(x=Pd["x"].cpu().numpy().T.astype(np.float64), v=Pd["v"].cpu().numpy().T.astype(np.float64),
+                A=Pd["A"].cpu().numpy().T.reshape(N, d, d).astype(np.float64),
+                J=Pd["J"].cpu().numpy().astype(np.float64), V0=Pd["V0"].cpu().numpy().astype(np.float64),
+                m=Pd["m"].cpu().numpy().astype(np.float64), T=Pd["T"].cpu().numpy().astype(np.float64),
+                gradT=Pd["gradT"].cpu().numpy().T.astype(np.float64))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("implicit", [True, False])
+def test_cfl_dt_matches_oracle(implicit, precision):
+    """CFL-limited step (Section 6): the device max-speed and min-density reduction and the
+    host rule give the oracle's dt bit for bit from the same particle state (FP32-rounded
+    in MIXED, where the reduction still runs in FP64)."""
+    from paper_2101_12408_amd import api
+    S = sc.ellipse2d(cfl=0.5)
+    P, p = S["particles"], dict(S["params"])
+    p["dt_max"] = 1e-3 if implicit else 1e-4
+    P["v"] = np.random.default_rng(8).normal(size=P["v"].shape) * 30.0
+    if precision == "mixed":
+        P = {k: v.astype(np.float32).astype(np.float64) for k, v in P.items()}
+    want = ostep.cfl_dt(P, p, implicit)
+    assert p["dt_min"] < want < p["dt_max"]
+    s = api.Scene(p, cap_part=len(P["m"]), cap_surf=20 * len(P["m"]), precision=precision)
+    Pd = s.to_device(P)
+    Sd = s.to_device(S=api.sample_surface(P["x"], p, step=0))
+    s.step(Pd, Sd, implicit=implicit)
+    got = s.stats()["dt"]
+    log(f"  cfl dt {got:.17g} oracle {want:.17g}")
+    assert got == want
+
+
+def test_ellipse_cfl_steps_on_gpu():
+    """Section 6.1 over 120 CFL-limited explicit steps in FP64 on the device path: every
+    step's dt is the oracle's rule applied to the state before it; linear and angular
+    momentum and the centre of mass stay at their initial values to round-off; after 120
+    steps the particles agree with the oracle's own 120 steps."""
+    from paper_2101_12408_amd import api
+    from paper_2101_12408_amd import _lib as L
+    S = sc.ellipse2d(cfl=0.01)
+    P, p = S["particles"], S["params"]
+    N = len(P["m"])
+    s = api.Scene(p, cap_part=N, cap_surf=20 * N, precision="fp64")
+    Pd = s.to_device(P)
+    order = np.arange(N)             # order[j]: input index of device particle j
+    hist, dts = [], []
+    for k in range(S["steps"]):
+        Q = _host_state(Pd, 2)
+        want = ostep.cfl_dt(Q, p, False)
+        Sd = s.to_device(S=api.sample_surface(Q["x"], p, step=k))
+        s.step(Pd, Sd, implicit=False)
+        dts.append(s.stats()["dt"])
+        assert dts[-1] == want, k
+        order = order[s.view(L.F_PERM).cpu().numpy()]
+        hist.append(_momenta(_host_state(Pd, 2), p["dx"]))
+    Q = _host_state(Pd, 2)
+    scale = np.abs(Q["m"][:, None] * Q["v"]).sum()
+    log(f"  dt {min(dts):.4e}..{max(dts):.4e}; momentum scale {scale:.3e}; final mom {hist[-1][0]}, "
+        f"L {hist[-1][1]:.3e}")
+    assert scale > 0 and p["dt_min"] < min(dts) and max(dts) < p["dt_max"]
+    com0 = (P["m"][:, None] * P["x"]).sum(0) / P["m"].sum()
+    for mom, Lz, com in hist:
+        assert np.all(np.abs(mom) < 1e-13 * scale)
+        assert abs(Lz) < 1e-13 * scale
+        assert np.allclose(com, com0, rtol=0, atol=1e-13)
+    Po = P
+    for k in range(S["steps"]):
+        Po, info = ostep.step(Po, p, implicit=False, step_index=k)
+    inv = np.empty_like(order)
+    inv[order] = np.arange(N)
+    ex, ev = np.max(np.abs(Q["x"][inv] - Po["x"])), rel(Q["v"][inv], Po["v"])
+    log(f"  vs oracle after {S['steps']} steps: max |dx| {ex:.3e}, v rel {ev:.3e}")
+    assert ex < 1e-12 and ev < 1e-9
+
+
 EPS32 = 2.0 ** -24
 
 

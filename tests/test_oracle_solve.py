@@ -65,17 +65,9 @@ def test_newton_solution_is_stationary_and_conserves_momentum():
     assert np.allclose(mom0, mom1, rtol=0, atol=1e-15 * np.abs(P["m"][:, None] * P["v"]).sum())
 
 
-def ellipse2d(n=63, seed=6):
-    p = sc.make_params(dim=2, n=64, dt=1e-5, bulk=4166.67, g0=0.1, seed=seed)
-    c = np.array([0.5, 0.5])
-    inside = lambda q: ((q[:, 0] - c[0]) / 0.2) ** 2 + ((q[:, 1] - c[1]) / 0.12) ** 2 < 1
-    # 8 particles per cell, uniformly random (Section 6.1)
-    rng = np.random.default_rng(seed)
-    cells = np.stack(np.meshgrid(np.arange(16, 48), np.arange(16, 48), indexing="xy"), -1).reshape(-1, 2)
-    x = (cells[:, None, :] + rng.uniform(0, 1, size=(len(cells), 8, 2))).reshape(-1, 2) / 64
-    x = x[inside(x)]
-    P = sc.particles_from_positions(x, 2, p["dx"], ppc=8)
-    return P, p
+def ellipse2d(cfl=0.0):
+    S = sc.ellipse2d(cfl=cfl)
+    return S["particles"], S["params"]
 
 
 def test_explicit_steps_conserve_momentum_and_centre_of_mass():
@@ -174,3 +166,53 @@ def test_newton_with_minres_and_exact_hessian():
     mom0 = (P["m"][:, None] * P["v"]).sum(0)
     mom1 = (P["m"][:, None] * newP["v"]).sum(0)
     assert np.allclose(mom0, mom1, rtol=0, atol=1e-15 * np.abs(P["m"][:, None] * P["v"]).sum())
+
+
+def _cfl_scene(seed):
+    S = sc.random_scene(3, 16, 200, seed, cfl=0.5, dt_min=1e-6, dt_max=10.0, bulk=1e4)
+    return S["particles"], S["params"]
+
+
+@pytest.mark.parametrize("implicit", [True, False])
+def test_cfl_dt_limits_the_fastest_crossing(implicit):
+    """CFL-limited dt (Section 6: dt restricted to a range by the CFL condition): unclamped,
+    the fastest particle (plus, explicit, the pressure wave sqrt(lambda/rho)) crosses
+    exactly cfl dx; the result does not depend on the particle order."""
+    P, p = _cfl_scene(21)
+    dt = step.cfl_dt(P, p, implicit)
+    assert p["dt_min"] < dt < p["dt_max"]
+    vmax = np.max(np.linalg.norm(P["v"], axis=1))
+    c = 0.0 if implicit else np.sqrt(p["bulk"] / np.min(P["m"] / P["V0"]))
+    assert (vmax + c) * dt == pytest.approx(p["cfl"] * p["dx"], rel=1e-14)
+    perm = np.random.default_rng(3).permutation(len(P["m"]))
+    assert step.cfl_dt({k: v[perm] for k, v in P.items()}, p, implicit) == dt
+
+
+def test_cfl_dt_clamps():
+    P, p = _cfl_scene(22)
+    P0 = dict(P, v=np.zeros_like(P["v"]))
+    assert step.cfl_dt(P0, p, True) == p["dt_max"]
+    Pf = dict(P, v=P["v"] * 1e9)
+    assert step.cfl_dt(Pf, p, True) == p["dt_min"]
+    assert step.cfl_dt(Pf, p, False) == p["dt_min"]
+
+
+def test_ellipse_conservation_with_cfl_steps():
+    """Section 6.1 at its parameters with CFL-limited explicit steps over 120 steps: total
+    linear and angular momentum (APIC spin included) and the centre of mass stay at their
+    initial values to round-off; the CFL rule, not a clamp, sets the steps."""
+    P, p = ellipse2d(cfl=0.01)
+    com0 = (P["m"][:, None] * P["x"]).sum(0) / P["m"].sum()
+    dts = []
+    for k in range(120):
+        P, info = step.step(P, p, implicit=False, step_index=k)
+        dts.append(info["dt"])
+    m, x, v, A = P["m"], P["x"], P["v"], P["A"]
+    scale = np.abs(m[:, None] * v).sum()
+    mom = (m[:, None] * v).sum(0)
+    L = np.sum(m * (x[:, 0] * v[:, 1] - x[:, 1] * v[:, 0])) + np.sum(m * (A[:, 1, 0] - A[:, 0, 1])) * p["dx"] ** 2 / 4
+    com = (m[:, None] * x).sum(0) / m.sum()
+    assert scale > 0 and p["dt_min"] < min(dts) and max(dts) < p["dt_max"]
+    assert np.all(np.abs(mom) <= 1e-13 * scale)
+    assert abs(L) <= 1e-13 * scale
+    assert np.allclose(com, com0, rtol=0, atol=1e-13)
