@@ -885,8 +885,11 @@ MPM_DEV bool newton_decide(const NewtonDecide& a) {
   const double gn = sqrt(fmax(scal[a.gt_slot + dim + 2], 0.0));
   const bool start_ok = g0 == g0 && phi == phi && !(g0 <= fmax(a.newton_tol * g0, floor_abs));
   const bool accept = !a.armijo || phit <= phi + a.c1 * slope + a.eps8 * fmax(fabs(phi), fabs(phit));
+  // the MIXED stop as the host takes it: |g| below 1e-4 |g0| or below eps32 times the size
+  // of the gradient's terms (sums slot dim+4), and not halved by the step
+  const double fl32 = 1.1920928955078125e-07 * sqrt(fmax(scal[a.gt_slot + dim + 4], 0.0));
   const bool go = start_ok && accept && gn == gn && phit == phit && !(gn <= fmax(a.newton_tol * g0, floor_abs)) &&
-                  !(a.mixed && gn <= 1e-4 * g0 && gn > 0.5 * gcur);
+                  !(a.mixed && (gn <= 1e-4 * g0 || gn <= fl32) && gn > 0.5 * gcur);
   const double t = fmax(a.cg_rel * gn, 0.1 * a.newton_tol * g0);
   scal[a.go_slot] = go ? 1.0 : 0.0;
   scal[a.tol_slot] = t * t;

@@ -23,7 +23,7 @@ static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
-constexpr int kNumParts = 20;   // partial-sum slots: momentum 0..15 (merge: D+4 from slot 4; correction: 2D+4 from 0), heat 16..19
+constexpr int kNumParts = 20;   // partial-sum slots: momentum 0..15 (merge: D+5 from slot 4; correction: 2D+4 from 0), heat 16..19
 constexpr int kScalDoubles = 64;
 // Device scalars the host reads back, in one block so that every read is one copy:
 // [0, 512) FP64 scalar slots, [512, 672) the two CG scalar sets, [768, 1024) status words.
@@ -545,9 +545,20 @@ void do_p2g(mpm_ctx* c, const mpm_particles* P, const mpm_surface* S, hipStream_
 // Device scalar slots (doubles at ctx->scal).
 // SC_G0 / SC_GT: the gradient merge's sums (see k_merge_stress) at the iterate and at the
 // line-search trial: [0] Phi, [1..D] sum m (v^ - v^n), [D+1] sum m, [D+2] |g|^2, [D+3]
-// the trial's slope g . delta.
+// the trial's slope g . delta, [D+4] the squared size of the gradient's terms (mixed_floor).
 // SC_GO / SC_TOL2: the device's decision on the next Newton iteration (newton_decide).
 enum : int { SC_DOT = 1, SC_RHS2 = 5, SC_MOM = 8, SC_G0 = 16, SC_GT = 32, SC_GO = 40, SC_TOL2 = 41, SC_N = 48 };
+// MIXED Newton: the gradient is formed in FP32, so its norm cannot fall much below eps32
+// times the size of the terms it is formed from (sums slot [D+4]).  Where the momentum is
+// large against the forces this floor can sit above any fraction of |g0| worth asking for.
+inline double mixed_floor(const double* sums, int D) {
+  return 1.1920928955078125e-07 * std::sqrt(std::max(sums[D + 4], 0.0));
+}
+// The MIXED stop: |g| at its FP32 floor (below 1e-4 |g0|, or below mixed_floor) and the
+// last Newton step did not halve it.
+inline bool mixed_stop(double gn, double gn_prev, double g0, double fl) {
+  return (gn <= 1e-4 * g0 || gn <= fl) && gn > 0.5 * gn_prev;
+}
 // MINRES scalars (momentum solve with krylov = MINRES) at scal[SC_N ..], inside the block
 // the host reads back.
 static_assert(SC_N * sizeof(double) + sizeof(MinresScal) <= (size_t)kScalDoubles * sizeof(double), "MINRES scalars");
@@ -574,7 +585,7 @@ void do_energy_grad(mpm_ctx* c, const R* u, R* g, double* energy_dev, int red_sl
            c->nctile > 0 ? (const double*)(c->part + 2 * kPartSlot) : nullptr, c->nctile, c->part + 4 * kPartSlot,
            c->ctr + (size_t)CTR_MERGE * kCtrSite, c->scal + red_slot, energy_dev, (CgScal*)nullptr, pu, slope_g);
   } else {
-    LAUNCH(c, MPM_K_BLAS, k_fill_r<double>, dim3(1), dim3(64), 0, s, c->scal + red_slot, 0.0, (int64_t)(D + 4));
+    LAUNCH(c, MPM_K_BLAS, k_fill_r<double>, dim3(1), dim3(64), 0, s, c->scal + red_slot, 0.0, (int64_t)(D + 5));
     if (energy_dev) LAUNCH(c, MPM_K_BLAS, k_fill_r<double>, dim3(1), dim3(1), 0, s, energy_dev, 0.0, (int64_t)1);
   }
 }
@@ -844,7 +855,7 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
   // trial's goes to sF_alt, which becomes the cache when the trial is accepted
   do_energy_grad<D, R>(c, vhat, g, nullptr, SC_G0, s, PUpd<R>{}, nullptr, (d.term_mask & 2) ? d.sF : nullptr);
   bool fix = false;
-  double msum = 0, floor_abs = 0, phi = 0, gn = 0, g0 = 0;
+  double msum = 0, floor_abs = 0, phi = 0, gn = 0, g0 = 0, fl32 = 0;
   auto start_values = [&] {   // from a read that covers the start's gradient merge
     fix = p.momentum_fix && !c->constrained;
     msum = c->hbuf[SC_G0 + 1 + D];
@@ -852,6 +863,7 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
     phi = c->hbuf[SC_G0];
     gn = std::sqrt(std::max(c->hbuf[SC_G0 + D + 2], 0.0));
     g0 = gn;
+    fl32 = mixed_floor(c->hbuf + SC_G0, D);
     st.g0 = g0;
   };
   if (p.newton_max <= 0) {
@@ -877,8 +889,8 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
       if (!(gn == gn) || !(phi == phi)) { c->status |= ST_NONFINITE; break; }
       if (gn <= std::max(p.newton_tol * g0, floor_abs)) { st.converged = 1; break; }
       // MIXED: the FP32 gradient cannot fall below its own round-off; once |g| is small
-      // (1e-4 |g0|) and a Newton step no longer halves it, the solve has reached that floor.
-      if (sizeof(R) == 4 && gn <= 1e-4 * g0 && gn > 0.5 * gn_prev) { st.converged = 2; break; }
+      // and a Newton step no longer halves it, the solve has reached that floor.
+      if (sizeof(R) == 4 && mixed_stop(gn, gn_prev, g0, fl32)) { st.converged = 2; break; }
     }
     gn_prev = gn;
     const int set = it & 1;
@@ -1024,6 +1036,7 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
       phi -= 0.5 * M * c2;
     }
     gn = std::sqrt(std::max(c->hbuf[SC_GT + D + 2], 0.0));
+    fl32 = mixed_floor(c->hbuf + SC_GT, D);
   }
   if (it == p.newton_max && gn <= std::max(p.newton_tol * g0, floor_abs)) st.converged = 1;
   st.newton_iters = it;
@@ -1107,6 +1120,7 @@ void do_solve_momentum_minres(mpm_ctx* c, hipStream_t s) {
   double phi = c->hbuf[SC_G0];
   double gn = std::sqrt(std::max(c->hbuf[SC_G0 + D + 2], 0.0));
   const double g0 = gn;
+  double fl32 = mixed_floor(c->hbuf + SC_G0, D);
   st.g0 = g0;
   st.energy_evals = 1;
   st.converged = 0;
@@ -1117,7 +1131,7 @@ void do_solve_momentum_minres(mpm_ctx* c, hipStream_t s) {
     if (!(gn == gn) || !(phi == phi)) { c->status |= ST_NONFINITE; break; }
     if (gn <= std::max(p.newton_tol * g0, floor_abs)) { st.converged = 1; break; }
     // MIXED: the FP32 gradient's round-off floor, as in the CG path
-    if (sizeof(R) == 4 && it > 0 && gn <= 1e-4 * g0 && gn > 0.5 * gn_prev) { st.converged = 2; break; }
+    if (sizeof(R) == 4 && it > 0 && mixed_stop(gn, gn_prev, g0, fl32)) { st.converged = 2; break; }
     gn_prev = gn;
     const double cg_tol = std::max(p.cg_rel * gn, 0.1 * p.newton_tol * g0);
     R* delta = (R*)c->delta;
@@ -1169,6 +1183,7 @@ void do_solve_momentum_minres(mpm_ctx* c, hipStream_t s) {
       phi -= 0.5 * M * c2;
     }
     gn = std::sqrt(std::max(c->hbuf[SC_GT + D + 2], 0.0));
+    fl32 = mixed_floor(c->hbuf + SC_GT, D);
   }
   if (it == p.newton_max && gn <= std::max(p.newton_tol * g0, floor_abs)) st.converged = 1;
   st.newton_iters = it;

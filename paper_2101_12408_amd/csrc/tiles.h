@@ -1361,7 +1361,10 @@ constexpr int kMergeTiles = 4;
 //  NM_GRAD: out = P[acc + m (v^ - v^n) - dt m g]; with phi the blocks also sum the tile
 //           energy partials (epart, nep entries) and the grid sums go to red: red[0] = Phi,
 //           red[1..D] = sum m (v^ - v^n), red[D+1] = sum m (nodes with mass), red[D+2] =
-//           |out|^2, red[D+3] = slope_g . u (u before the input update; 0 without slope_g).
+//           |out|^2, red[D+3] = slope_g . u (u before the input update; 0 without slope_g),
+//           red[D+4] = sum over free components of (|acc| + m |u| + m |v^n| + dt m |g|)^2,
+//           the size of the terms a component of the gradient is formed from (its
+//           round-off in the arithmetic of R is about eps_R times the square root).
 //  NM_HESS: out = P[acc + alpha m w]; with cg the grid sum of w . out sets the CG step.
 template <int D, typename R>
 __global__ void __launch_bounds__(64 * kMergeTiles) k_merge_stress(
@@ -1369,7 +1372,7 @@ __global__ void __launch_bounds__(64 * kMergeTiles) k_merge_stress(
     const int* done, const double* epart, int nep, double* npart, unsigned* ctr, double* red, double* phi2,
     CgScal* cg, PUpd<R> pu, const R* slope_g) {
   constexpr int RN = TileGeo<D>::RN;
-  constexpr int NV = D + 4;
+  constexpr int NV = D + 5;
   __shared__ double sh[NV * 64 * kMergeTiles];
   if (done && *done) return;
   const int ti = blockIdx.x * kMergeTiles + (threadIdx.x >> 6);
@@ -1429,6 +1432,11 @@ __global__ void __launch_bounds__(64 * kMergeTiles) k_merge_stress(
           double dv = (double)ua - (double)vn;
           vals[0] += 0.5 * (double)m * dv * dv - (double)d.dt * (double)m * (double)d.grav[a] * (double)ua;
           vals[1 + a] = (double)m * dv;
+        }
+        if (fa) {
+          const double mag = fabs((double)acc[a]) + fabs((double)m) * (fabs((double)ua) + fabs((double)vn) +
+                                                                      fabs((double)d.dt * (double)d.grav[a]));
+          vals[D + 4] += mag * mag;
         }
       } else {
         R wa = (!mask_in || fa) ? ua : R(0);

@@ -157,8 +157,9 @@ def test_cfl_dt_matches_oracle(implicit, precision):
     from paper_2101_12408_amd import api
     S = sc.ellipse2d(cfl=0.5)
     P, p = S["particles"], dict(S["params"])
-    p["dt_max"] = 1e-3 if implicit else 1e-4
-    P["v"] = np.random.default_rng(8).normal(size=P["v"].shape) * 30.0
+    p["dt_max"] = 1e-3
+    r = P["x"] - 0.5                 # rigid motion: spin 100 rad/s plus a drift
+    P["v"] = np.stack([-100.0 * r[:, 1] + 3.0, 100.0 * r[:, 0] - 2.0], 1)
     if precision == "mixed":
         P = {k: v.astype(np.float32).astype(np.float64) for k, v in P.items()}
     want = ostep.cfl_dt(P, p, implicit)
@@ -367,3 +368,27 @@ def test_minres_mixed_step_error_report():
         e = rel(got[k], ref[k])
         log(f"  mixed {k}: rel {e:.3e}")
         assert e < 1e-3, k
+
+
+@pytest.mark.parametrize("krylov", [0, 1])
+def test_mixed_newton_stops_at_fp32_floor(krylov):
+    """Large momentum against weak forces (the ellipse of Section 6.1 spinning at 100 rad/s
+    with a drift, dt 3.5e-4): the FP32 gradient's round-off, about eps32 times the size of
+    m v^, sits at a few percent of |g0|, so no relative tolerance is reachable in MIXED.
+    Newton stops at that floor (converged = 2) instead of running to the iteration cap, and
+    the step still agrees with the FP64 oracle at the FP32 level."""
+    S = sc.ellipse2d()
+    P, p = S["particles"], dict(S["params"], dt=3.5e-4, krylov=krylov)
+    r = P["x"] - 0.5
+    P["v"] = np.stack([-100.0 * r[:, 1] + 3.0, 100.0 * r[:, 0] - 2.0], 1)
+    surf = sampler.sample_surface(P["x"], p)
+    P32, surf32 = round_inputs(P, surf, "mixed")
+    ref, info = ostep.step(P32, p, surf32)
+    got, st, rc = _gpu_step(P32, surf32, p, precision="mixed")
+    log(f"  mixed krylov={krylov}: newton {st['newton_iters']} inner {st['cg_iters']} converged {st['converged']} "
+        f"|g| {st['gnorm']:.3e} of |g0| {st['g0']:.3e}")
+    assert rc == 0 and st["converged"] in (1, 2)
+    for k in ("x", "v", "A"):
+        e = rel(got[k], ref[k])
+        log(f"  mixed {k}: rel {e:.3e}")
+        assert e < 1e-5, k
