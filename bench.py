@@ -152,11 +152,12 @@ def mixed_vs_fp64(scene_fn):
     P, p = S["particles"], S["params"]
     surf = api.sample_surface(P["x"], p, step=0)
     N = len(P["m"])
-    res, grads, outs = {}, {}, {}
+    res, grads, outs, parents = {}, {}, {}, {}
     for prec in ("fp64", "mixed"):
         s = api.Scene(p, cap_part=N, cap_surf=len(surf["s"]) + 1024, precision=prec)
         Pd, Sd = s.to_device(P, surf)
         s.p2g(Pd, Sd)
+        parents[prec] = s.view(L.F_PARENT).cpu().numpy().copy()
         if prec == "fp64":
             vref = s.view(L.F_VN).clone()
         g = s.grid_vector()
@@ -181,7 +182,16 @@ def mixed_vs_fp64(scene_fn):
     for k in ("v", "T", "dx", "dJ"):
         res[f"step_{k}"] = err(outs["mixed"][k], outs["fp64"][k])
     log("mixed vs fp64: " + ", ".join(f"{k} {v['rel']:.2e}/{v['worst']:.2e}" for k, v in res.items()))
-    return {k: {kk: float(f"{vv:.3e}") for kk, vv in v.items()} for k, v in res.items()}
+    out = {k: {kk: float(f"{vv:.3e}") for kk, vv in v.items()} for k, v in res.items()}
+    # surface samples whose nearest parent differs once the positions are FP32, and whether
+    # the particle with the worst step-v error is a parent of one of them (either side)
+    flip = parents["mixed"] != parents["fp64"]
+    near = set(parents["mixed"][flip].tolist()) | set(parents["fp64"][flip].tolist())
+    dv = np.abs(outs["mixed"]["v"] - outs["fp64"]["v"]).max(axis=0)
+    worst_p = int(np.argmax(dv))
+    out["parent_flips"] = {"count": int(flip.sum()), "of": int(flip.size), "worst_v_is_flipped_parent": worst_p in near}
+    log(f"mixed vs fp64: {int(flip.sum())} of {flip.size} parents differ; worst v at a flipped parent: {worst_p in near}")
+    return out
 
 
 # ---------------------------------------------------------------------------------------
