@@ -179,7 +179,8 @@ enum mpm_kernel_class {
   MPM_K_G2P = 12,        /* G2P with merge and advection                                */
   MPM_K_BLAS = 13,       /* Krylov vector updates and dot products                      */
   MPM_K_P2G_NODE = 14,   /* P2G node phase: partial merge and the grid set-up           */
-  MPM_K_COUNT = 15
+  MPM_K_SAMPLE = 15,     /* device surface sampler (mpm_sample_surface_dev)             */
+  MPM_K_COUNT = 16
 };
 
 /* Node numbering helper (tile-major order described above). */
@@ -313,6 +314,25 @@ int mpm_sample_surface(int32_t dim, int32_t n, const double* x, int64_t n_part, 
                        double density, uint64_t seed, uint64_t step, const double* label_lo,
                        const double* label_hi, double* s, double* dA, int32_t* label, int64_t cap,
                        int64_t* out_n);
+
+/* Device surface sampler (Section 4.1.1): the samples mpm_sample_surface draws, computed
+ * on the context's GPU from device particle positions P->x ([dim][P->n] real of the
+ * context's precision, P->n <= the context's particle capacity; the other particle arrays
+ * are not read).  The same level set, isocontour, element ids and counter draws, with
+ * every floating-point operation of the geometry in the host stage's order and FP64
+ * arithmetic, so the samples equal the host stage's bit for bit (in MIXED the positions
+ * are the FP32 values and s, dA are rounded to FP32 on output).  Writes the samples to
+ * device buffers s_out, dA_out ([dim][count] real) and label ([count] int32, may be NULL)
+ * in element-id order, only when the count is <= cap; *out_n receives the count either
+ * way (call again with larger buffers).  The result can be passed to mpm_step as its
+ * mpm_surface {count, s_out, dA_out, label}.  Runs on stream, and waits for it once to read
+ * the count.  Uses the context's sampler scratch and its particle staging buffer (which
+ * the next mpm_p2g rewrites), not the state of the last step or its views.  radius and
+ * density <= 0 select the defaults of mpm_sample_surface; radius must be below dx.
+ * Errors: MPM_EINVAL for null or inconsistent arguments. */
+int mpm_sample_surface_dev(mpm_ctx* ctx, const mpm_particles* P, double radius, double density, uint64_t seed,
+                           uint64_t step, const double* label_lo, const double* label_hi, void* s_out,
+                           void* dA_out, int32_t* label, int64_t cap, int64_t* out_n, void* stream);
 
 /* ---- Serving: continuous batching of step requests -------------------------------
  * A server owns max_concurrent worker threads, each with its own non-blocking stream

@@ -102,10 +102,14 @@ EXPORTS = {
     "mpm_sample_surface": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_int64, C.c_double, C.c_double,
                                      C.c_uint64, C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]),
+    "mpm_sample_surface_dev": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_uint64, C.c_uint64,
+                                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                         C.POINTER(C.c_int64), C.c_void_p]),
 }
 
 KERNEL_CLASSES = ["sort", "setup", "p2g", "energy_int", "energy_surf", "energy_node", "hess_int",
-                  "hess_surf", "hess_node", "heat_pt", "heat_node", "g2p_split", "g2p", "blas", "p2g_node"]
+                  "hess_surf", "hess_node", "heat_pt", "heat_node", "g2p_split", "g2p", "blas", "p2g_node",
+                  "sample"]
 
 _lib = None
 

@@ -178,6 +178,37 @@ class Scene:
                             label=torch.from_numpy(np.ascontiguousarray(lab.astype(np.int32))).cuda()))
         return out[0] if len(out) == 1 else tuple(out)
 
+    def sample_surface(self, P, step=0, cap=None):
+        """Device sampler (mpm_sample_surface_dev) around the device positions P["x"]
+        ([dim][N] of the scene's dtype): the host sampler's samples, as device tensors
+        {s (dim, S), dA (dim, S), label (S,)} ready for step / p2g."""
+        torch = self.torch
+        prm = self.params
+        st = L.MpmParticles()
+        st.n = int(P["x"].shape[1])
+        assert P["x"].dtype == self.dtype and P["x"].is_contiguous() and P["x"].is_cuda
+        st.x = P["x"].data_ptr()
+        lo = (C.c_double * 3)(*(list(prm.get("label_lo", (0, 0, 0)))[:3] + [0.0] * 3)[:3])
+        hi = (C.c_double * 3)(*(list(prm.get("label_hi", (0, 0, 0)))[:3] + [0.0] * 3)[:3])
+        radius = float(prm.get("ls_radius") or 0.0)
+        density = float(prm.get("sample_density") or 0.0)
+        seed = int(prm.get("seed", 0))
+        cap = self.cap_surf if cap is None else int(cap)
+        cnt = C.c_int64(0)
+        for _ in range(2):
+            s = torch.empty(self.dim * max(cap, 1), dtype=self.dtype, device="cuda")
+            dA = torch.empty_like(s)
+            lab = torch.empty(max(cap, 1), dtype=torch.int32, device="cuda")
+            _check(self.lib.mpm_sample_surface_dev(self.ctx, C.byref(st), radius, density, seed, int(step), lo, hi,
+                                                   s.data_ptr(), dA.data_ptr(), lab.data_ptr(), cap, C.byref(cnt),
+                                                   self.stream()), self.lib, self.ctx)
+            S = cnt.value
+            if S <= cap:
+                d = self.dim
+                return dict(s=s[:d * S].view(d, S), dA=dA[:d * S].view(d, S), label=lab[:S])
+            cap = S
+        raise MpmError(L.MPM_ENOMEM, "sample buffer")
+
     def grid_vector(self, ncomp=None):
         ncomp = self.dim if ncomp is None else ncomp
         return self.torch.zeros((ncomp, self.nn), dtype=self.dtype, device="cuda")

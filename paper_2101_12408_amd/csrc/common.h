@@ -11,6 +11,23 @@
 
 namespace mpm {
 
+// Double products, sums and differences rounded one at a time.  HIP contracts a product
+// and a sum into one fused multiply-add by default (so do the _rn intrinsics, which are
+// plain operators here); under this pragma the operations carry no contraction flag, so
+// they round exactly as a host computation written in the same order.
+MPM_DEV double mul_nc(double a, double b) {
+#pragma clang fp contract(off)
+  return a * b;
+}
+MPM_DEV double add_nc(double a, double b) {
+#pragma clang fp contract(off)
+  return a + b;
+}
+MPM_DEV double sub_nc(double a, double b) {
+#pragma clang fp contract(off)
+  return a - b;
+}
+
 constexpr int kTileNodes = 64;   // nodes per tile: 4x4x4 (3D) or 8x8 (2D)
 constexpr int kMaxPartials = 1024;
 constexpr int kWave = 64;

@@ -318,9 +318,9 @@ __global__ void k_gather_surface(Dev<R> d, const R* s, const R* dA, const int* l
 // axis: the same arithmetic any reference evaluating ((d0^2 + d1^2) + d2^2) performs.
 template <int D>
 MPM_DEV double dist2_exact(const double* a, const double* b) {
-  double acc = __dmul_rn(a[0] - b[0], a[0] - b[0]);
+  double acc = mul_nc(a[0] - b[0], a[0] - b[0]);
 #pragma unroll
-  for (int k = 1; k < D; ++k) acc = __dadd_rn(acc, __dmul_rn(a[k] - b[k], a[k] - b[k]));
+  for (int k = 1; k < D; ++k) acc = add_nc(acc, mul_nc(a[k] - b[k], a[k] - b[k]));
   return acc;
 }
 
@@ -959,8 +959,8 @@ __global__ void k_cg_update(const int* tl, int nelem, int nn, int ncomp, CgScal*
 // out[1]: min m_p / V0_p (start +inf).  |v|^2 = (v0^2 + v1^2) + v2^2 with separate
 // roundings, as any reference summing axis by axis in FP64.
 MPM_DEV double speed2_rn(const double* v, int D) {
-  double s = __dmul_rn(v[0], v[0]);
-  for (int a = 1; a < D; ++a) s = __dadd_rn(s, __dmul_rn(v[a], v[a]));
+  double s = mul_nc(v[0], v[0]);
+  for (int a = 1; a < D; ++a) s = add_nc(s, mul_nc(v[a], v[a]));
   return s;
 }
 
@@ -977,7 +977,7 @@ __global__ void k_max_speed(int n, const R* v, const R* m, const R* V0, unsigned
 #pragma unroll
     for (int a = 0; a < D; ++a) vv[a] = (double)v[(size_t)a * n + p];
     vmax2 = fmax(vmax2, speed2_rn(vv, D));
-    rmin = fmin(rmin, __ddiv_rn((double)m[p], (double)V0[p]));
+    rmin = fmin(rmin, (double)m[p] / (double)V0[p]);
   }
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) {

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "tiles.h"
+#include "sampler_dev.h"
 
 using namespace mpm;
 
@@ -112,6 +113,10 @@ struct mpm_ctx {
   int* ccount_aux = nullptr;
   int* sort_tmp_aux = nullptr;
   void* sF_alt = nullptr;        // surface F_r at the line-search trial (swapped with d.sF)
+  // device surface sampler: its own particle binning and the dense node / cube arrays
+  int *smp_key = nullptr, *smp_perm = nullptr, *smp_start = nullptr, *smp_cnt = nullptr, *smp_off = nullptr;
+  uint8_t* smp_flag = nullptr;
+  double* smp_phi = nullptr;
   uint64_t* scan_flags_aux = nullptr;
   unsigned scan_epoch_aux = 0;
   int* misc = nullptr;          // [0] status, [1] constrained flag, [2] tile count
@@ -264,6 +269,13 @@ size_t layout(mpm_ctx* c, char* base) {
   int* sort_tmp_aux = b.take<int>(NS);
   void* sF_alt = b.take<R>(D * D * NS);
   uint64_t* scan_flags_aux = b.take<uint64_t>(kScanBlock);
+  int* smp_key = b.take<int>(NP);
+  int* smp_perm = b.take<int>(NP);
+  int* smp_start = b.take<int>(NN + 1);
+  int* smp_cnt = b.take<int>(NN);
+  int* smp_off = b.take<int>(NN + 1);
+  uint8_t* smp_flag = b.take<uint8_t>(NN);
+  double* smp_phi = b.take<double>(NN);
   d.status = misc;
   if (base) {
     c->vhat = vecs[0]; c->vtrial = vecs[1]; c->grad = vecs[2]; c->delta = vecs[3]; c->r = vecs[4];
@@ -280,6 +292,8 @@ size_t layout(mpm_ctx* c, char* base) {
     c->sort_tmp = sort_tmp;
     c->ccount_aux = ccount_aux; c->sort_tmp_aux = sort_tmp_aux; c->scan_flags_aux = scan_flags_aux;
     c->sF_alt = sF_alt;
+    c->smp_key = smp_key; c->smp_perm = smp_perm; c->smp_start = smp_start; c->smp_cnt = smp_cnt;
+    c->smp_off = smp_off; c->smp_flag = smp_flag; c->smp_phi = smp_phi;
     if constexpr (sizeof(R) == 8) c->d64 = d; else c->d32 = d;
   }
   return b.off + 256;
@@ -1282,6 +1296,47 @@ void do_solve_heat(mpm_ctx* c, hipStream_t s) {
   heat_end<D, R>(c, s, run);
 }
 
+// Device surface sampler (Section 4.1.1; kernels in sampler_dev.h).  Returns the sample
+// count; the samples are written only when it is <= cap.
+template <int D, typename R>
+int64_t do_sample(mpm_ctx* c, const mpm_particles* P, const SmpArgs& a, R* s_out, R* dA_out, int* label,
+                  int64_t cap, hipStream_t s) {
+  Dev<R>& d = dev<R>(c);
+  const int np = (int)P->n;
+  if (np <= 0) return 0;
+  const int n = a.n;
+  const int64_t nn = c->nn;
+  const int64_t ncube = (int64_t)(n - 1) * (n - 1) * (D == 3 ? (n - 1) : 1);
+  const R* x = (const R*)P->x;
+  // binning: keys and counts, dense cell starts, slots, each cell's segment in input order
+  LAUNCH(c, MPM_K_SAMPLE, (k_smp_keys<D, R>), dim3(cdiv(np, 256)), dim3(256), 0, s, x, np, n, c->nt, a.dx,
+         c->smp_key, d.ccount);
+  scan(c, d.ccount, c->smp_start, (int)nn, s);
+  LAUNCH(c, MPM_K_SAMPLE, k_cell_scatter, dim3(cdiv(np, 256)), dim3(256), 0, s, (const int*)c->smp_key, np,
+         (const int*)c->smp_start, d.ccount, c->sort_tmp, d.status);
+  segment_order(c, c->smp_key, c->smp_start, np, (const int*)c->sort_tmp, c->smp_perm, s);
+  LAUNCH(c, MPM_K_SAMPLE, (k_smp_gather<D, R>), dim3(cdiv(np, 256)), dim3(256), 0, s, x, np,
+         (const int*)c->smp_perm, d.px);
+  // the level set near the particles
+  LAUNCH(c, MPM_K_SAMPLE, k_fill_i32, dim3(cdiv(nn / 4, 256)), dim3(256), 0, s, (int*)c->smp_flag, 0,
+         (int64_t)(nn / 4));
+  LAUNCH(c, MPM_K_SAMPLE, (k_smp_inside<D, R>), dim3(cdiv(np, 256)), dim3(256), 0, s, x, np, a, c->smp_flag);
+  LAUNCH(c, MPM_K_SAMPLE, (k_smp_need<D>), dim3(cdiv(nn, 256)), dim3(256), 0, s, c->smp_flag, n);
+  LAUNCH(c, MPM_K_SAMPLE, (k_smp_phi<D, R>), dim3(cdiv(nn, 256)), dim3(256), 0, s, (const R*)d.px, np,
+         (const int*)c->smp_start, a, (const uint8_t*)c->smp_flag, c->smp_phi);
+  // elements and samples, in element-id order
+  LAUNCH(c, MPM_K_SAMPLE, (k_smp_count<D>), dim3(cdiv(ncube, 256)), dim3(256), 0, s, a,
+         (const uint8_t*)c->smp_flag, (const double*)c->smp_phi, c->smp_cnt);
+  scan(c, c->smp_cnt, c->smp_off, (int)ncube, s);
+  LAUNCH(c, MPM_K_SAMPLE, (k_smp_emit<D, R>), dim3(cdiv(ncube, 256)), dim3(256), 0, s, a,
+         (const uint8_t*)c->smp_flag, (const double*)c->smp_phi, (const int*)c->smp_cnt, (const int*)c->smp_off,
+         cap, s_out, dA_out, label);
+  HIPCHK(hipGetLastError());
+  int total = 0;
+  sync_read(c, s, c->smp_off + ncube, &total, sizeof(int));
+  return total;
+}
+
 // ---- dispatch ----------------------------------------------------------------------------
 template <class F>
 void dispatch(mpm_ctx* c, F&& f) {
@@ -1555,6 +1610,38 @@ int mpm_g2p(mpm_ctx* ctx, const void* v_hat, const void* T_hat, mpm_particles* P
       constexpr int D = decltype(Dc)::value;
       using R = decltype(Rv);
       do_g2p<D, R>(ctx, (const R*)v_hat, (const R*)T_hat, P, s);
+    });
+  });
+  return rc != MPM_OK ? rc : check_launch(ctx);
+}
+
+int mpm_sample_surface_dev(mpm_ctx* ctx, const mpm_particles* P, double radius, double density, uint64_t seed,
+                           uint64_t step, const double* label_lo, const double* label_hi, void* s_out,
+                           void* dA_out, int32_t* label, int64_t cap, int64_t* out_n, void* stream) {
+  if (!ctx || !P || !out_n || cap < 0 || P->n < 0 || (P->n > 0 && !P->x)) return MPM_EINVAL;
+  if (cap > 0 && (!s_out || !dA_out)) return MPM_EINVAL;
+  if (P->n > ctx->cap_part) { ctx->err = "more particles than the context's capacity"; return MPM_EINVAL; }
+  hipStream_t s = (hipStream_t)stream;
+  *out_n = 0;
+  int rc = guarded(ctx, [&] {
+    const mpm_params& p = ctx->p;
+    SmpArgs a{};
+    a.n = p.n;
+    a.nt = ctx->nt;
+    a.dx = 1.0 / p.n;
+    a.r = radius > 0 ? radius : (p.dim == 3 ? 0.867 : 0.73) * a.dx;
+    a.rho = density > 0 ? density : (p.dim == 3 ? 8.0 / (a.dx * a.dx) : 4.0 / a.dx);
+    if (!(a.r < a.dx)) throw ApiError{MPM_EINVAL, "sampler radius must be below dx"};
+    a.key = (seed << 32) + step;
+    a.has_label = label_lo && label_hi;
+    for (int q = 0; q < p.dim; ++q) {
+      a.lo[q] = a.has_label ? label_lo[q] : 0;
+      a.hi[q] = a.has_label ? label_hi[q] : 0;
+    }
+    dispatch(ctx, [&](auto Dc, auto Rv) {
+      constexpr int D = decltype(Dc)::value;
+      using R = decltype(Rv);
+      *out_n = do_sample<D, R>(ctx, P, a, (R*)s_out, (R*)dA_out, label, cap, s);
     });
   });
   return rc != MPM_OK ? rc : check_launch(ctx);
