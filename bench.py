@@ -11,11 +11,12 @@ same number of steps beside it.
 
 A step is one full pass of the hot path: cell sort, parents / balance points / split,
 P2G with the grid set-up, the Newton-CG momentum solve, the heat CG solve, G2P with
-merge and advection.  The surface samples are an input of the step (the host sampler is
-the input stage): they are drawn for every step of the trajectory in an untimed
-recording pass and kept in HBM, so the timed pass replays the same trajectory
-(bit-identical, the kernels are deterministic) with all inputs resident.  The rate that
-includes the host sampler is reported beside (all_in).
+merge and advection.  The surface samples are an input of the step: the device sampler
+(the host input stage's samples bit for bit) draws them for every step of the trajectory
+in an untimed recording pass and they stay in HBM, so the timed pass replays the same
+trajectory (bit-identical, the kernels are deterministic) with all inputs resident.  The
+rate with each step's device sampling inside the timed region is reported beside
+(all_in), and so is the rate a host sampler would give (host_stage).
 
 Also reported: the MIXED-vs-FP64 error of the grid forces and of one step's particle
 state on the headline workload; the other workloads (2D square droplet, Marangoni
@@ -54,9 +55,11 @@ def free_gpu():
 
 
 def run_gpu(scene_fn, precision, steps, warmup, want_timing, label):
-    """Records warmup + steps steps (host sampling of each step's surface, untimed), then
-    replays them with every input in HBM: the timed pass, and with want_timing a second
-    pass with per-launch HIP events for the per-class breakdown."""
+    """Records warmup + steps steps (each step's surface drawn by the device sampler and
+    kept in HBM), then replays them with every input in HBM: the timed pass, and with
+    want_timing a second pass with per-launch HIP events for the per-class breakdown.  A
+    last pass times the steps all-in, each with its own device sampling.  The host input
+    stage is timed once on the first step's positions for comparison."""
     import torch
     from paper_2101_12408_amd import api
     S = scene_fn()
@@ -65,36 +68,33 @@ def run_gpu(scene_fn, precision, steps, warmup, want_timing, label):
     t0 = time.perf_counter()
     ts = time.perf_counter()
     surf0 = api.sample_surface(P0["x"], p, step=0)
-    sample_s = [time.perf_counter() - ts]
+    host_sample_s = time.perf_counter() - ts
     cap_s = int(len(surf0["s"]) * 1.5) + 1024
     scene = api.Scene(p, cap_part=N, cap_surf=cap_s, precision=precision)
     Pd = scene.to_device(P0)
     init = clone_state(Pd)
-    surfs, upload_s = [], []
+    torch.cuda.synchronize()
+    tu = time.perf_counter()
+    scene.to_device(S=surf0)
+    torch.cuda.synchronize()
+    upload_s = time.perf_counter() - tu
+    surfs = []
     for k in range(warmup + steps):
-        if k > 0:
-            ts = time.perf_counter()
-            xh = Pd["x"].double().cpu().numpy().T.copy()
-            surf = api.sample_surface(xh, p, step=k)
-            sample_s.append(time.perf_counter() - ts)
-        else:
-            surf = surf0
-        torch.cuda.synchronize()
-        tu = time.perf_counter()
-        Sd = scene.to_device(S=surf)
-        torch.cuda.synchronize()
-        upload_s.append(time.perf_counter() - tu)
+        Sd = scene.sample_surface(Pd, step=k)
         surfs.append(Sd)
         scene.step(Pd, Sd)
     log(f"{label} {precision}: recorded {warmup + steps} steps in {time.perf_counter() - t0:.1f} s "
-        f"(N={N}, S~{len(surf0['s'])}, host sampling {np.mean(sample_s):.3f} s/step)")
+        f"(N={N}, S~{len(surf0['s'])}, host sampling {host_sample_s:.3f} s for one step)")
 
-    def replay(timed_events):
+    def reset_and_warm(sample):
         for k, v in init.items():
             Pd[k].copy_(v)
         for k in range(warmup):
-            scene.step(Pd, surfs[k])
+            scene.step(Pd, scene.sample_surface(Pd, step=k) if sample else surfs[k])
         torch.cuda.synchronize()
+
+    def replay(timed_events):
+        reset_and_warm(False)
         if timed_events:
             scene.timing(True)
         stats = []
@@ -117,10 +117,19 @@ def run_gpu(scene_fn, precision, steps, warmup, want_timing, label):
     timing, elapsed_ev = None, None
     if want_timing:
         elapsed_ev, _, timing = replay(True)
+    # all-in: device sampling and the step, from the same state
+    reset_and_warm(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for k in range(warmup, warmup + steps):
+        scene.step(Pd, scene.sample_surface(Pd, step=k))
+    torch.cuda.synchronize()
+    elapsed_all = time.perf_counter() - t1
     log(f"{label} {precision}: {1e3 * elapsed / steps:.3f} ms/step"
-        + (f", with per-launch events {1e3 * elapsed_ev / steps:.3f}" if want_timing else ""))
-    out = dict(N=N, elapsed=elapsed, elapsed_events=elapsed_ev, stats=stats, timing=timing, S=len(surf0["s"]),
-               params=p, sample_s=float(np.sum(sample_s[warmup:])), upload_s=float(np.sum(upload_s[warmup:])))
+        + (f", with per-launch events {1e3 * elapsed_ev / steps:.3f}" if want_timing else "")
+        + f", all-in with device sampling {1e3 * elapsed_all / steps:.3f}")
+    out = dict(N=N, elapsed=elapsed, elapsed_events=elapsed_ev, elapsed_all_in=elapsed_all, stats=stats,
+               timing=timing, S=len(surf0["s"]), params=p, host_sample_s=host_sample_s, upload_s=upload_s)
     del scene, Pd, init, surfs
     free_gpu()
     return out
@@ -588,8 +597,10 @@ def main():
         # where the heat solve's stream overlaps the momentum solve's)
         out_extra["kernel_sum_over_step"] = round(total / (main_run["elapsed"] * 1e3), 3)
         out_extra["ms_per_step_with_events"] = round(1e3 * main_run["elapsed_events"] / K, 3)
-    # the host sampler (input stage) and the upload of its samples included
-    all_in = N * K / (main_run["elapsed"] + main_run["sample_s"] + main_run["upload_s"])
+    # with each step's device sampling timed; and, for comparison, the host input stage and
+    # the upload of its samples added to the step
+    all_in = N * K / main_run["elapsed_all_in"]
+    host_stage = N / (main_run["elapsed"] / K + main_run["host_sample_s"] + main_run["upload_s"])
     fp64 = None
     k64 = K if args.fp64_steps < 0 else args.fp64_steps
     if k64 > 0 and args.precision != "fp64":
@@ -655,8 +666,10 @@ def main():
         "cg_iters_per_step": per_step(st, "cg_iters"),
         "heat_iters_per_step": per_step(st, "heat_iters"),
         "all_in": dict(value=round(all_in, 1), unit="particle-steps/s",
-                       host_sampling_s_per_step=round(main_run["sample_s"] / K, 4),
-                       upload_s_per_step=round(main_run["upload_s"] / K, 4)),
+                       ms_per_step=round(1e3 * main_run["elapsed_all_in"] / K, 3),
+                       sampling_ms_per_step=round(1e3 * (main_run["elapsed_all_in"] - main_run["elapsed"]) / K, 3),
+                       host_stage=dict(value=round(host_stage, 1), host_sampling_s_per_step=round(
+                           main_run["host_sample_s"], 4), upload_s_per_step=round(main_run["upload_s"], 4))),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fp64_gpu": fp64,

@@ -2,9 +2,11 @@
 //
 // A request carries a scene (parameters and the host particle state) and a number of
 // implicit steps.  Worker threads, each with its own non-blocking stream, take requests
-// in arrival order.  A worker draws the step's surface samples on the host, then waits
-// for its admission turn: requests are admitted strictly in arrival order, each once the
-// device arena (caller-allocated HBM) has room for its context workspace and buffers.
+// in arrival order.  A worker draws the first step's surface samples on the host (their
+// count sizes the request's memory), then waits for its admission turn: requests are
+// admitted strictly in arrival order, each once the device arena (caller-allocated HBM)
+// has room for its context workspace and buffers.  Later steps draw their samples on the
+// device from the resident positions (mpm_sample_surface_dev).
 // It uploads the state, runs the steps through mpm_step, downloads the result and frees
 // its memory.  Up to max_concurrent requests are on the device at once, on separate
 // streams, so a request that arrives while others run starts as soon as a worker and
@@ -231,21 +233,27 @@ int run_request(mpm_server* srv, Worker& w, Request& q, char* mem, size_t ws_byt
     if (!upload(w, pf[k], q.src[k], (size_t)components(k, dim) * N, fp64)) rc = MPM_EHIP;
   q.orig.resize(N);
   for (int64_t i = 0; i < N; ++i) q.orig[i] = i;
-  std::vector<double> xh((size_t)dim * N);
   std::vector<int32_t> perm(N);
   std::vector<int64_t> orig2(N);
   mpm_particles P{N, pf[0], pf[1], pf[2], pf[3], pf[4], pf[5], pf[6], pf[7]};
   for (int st = 0; st < q.r.n_steps && rc == MPM_OK; ++st) {
-    if (st > 0) {
-      if (!download(w, xh.data(), pf[0], (size_t)dim * N, fp64)) { rc = MPM_EHIP; break; }
-      if (!sample(q, xh.data(), N, q.r.first_step + st, q.surf)) { rc = MPM_EINVAL; break; }
-    }
-    if (q.surf.n > cap_surf) { rc = MPM_ENOMEM; break; }
-    const int64_t S = q.surf.n;
-    if (!upload(w, ds, q.surf.s.data(), (size_t)dim * S, fp64) || !upload(w, ddA, q.surf.dA.data(), (size_t)dim * S, fp64) ||
-        (S && hipMemcpyAsync(dlab, q.surf.label.data(), S * 4, hipMemcpyHostToDevice, w.stream) != hipSuccess)) {
-      rc = MPM_EHIP;
-      break;
+    int64_t S = 0;
+    if (st == 0) {
+      // the first step's samples were drawn on the host to size the request
+      if (q.surf.n > cap_surf) { rc = MPM_ENOMEM; break; }
+      S = q.surf.n;
+      if (!upload(w, ds, q.surf.s.data(), (size_t)dim * S, fp64) ||
+          !upload(w, ddA, q.surf.dA.data(), (size_t)dim * S, fp64) ||
+          (S && hipMemcpyAsync(dlab, q.surf.label.data(), S * 4, hipMemcpyHostToDevice, w.stream) != hipSuccess)) {
+        rc = MPM_EHIP;
+        break;
+      }
+    } else {
+      // later steps: the device sampler, on the resident positions
+      rc = mpm_sample_surface_dev(ctx, &P, q.r.ls_radius, q.r.sample_density, q.r.seed, q.r.first_step + st,
+                                  q.r.label_lo, q.r.label_hi, ds, ddA, dlab, cap_surf, &S, w.stream);
+      if (rc != MPM_OK) break;
+      if (S > cap_surf) { rc = MPM_ENOMEM; break; }
     }
     mpm_surface Sd{S, ds, ddA, dlab};
     mpm_ctx* cs[1] = {ctx};

@@ -41,6 +41,31 @@ int mpm_step(mpm_ctx* const* cs, mpm_particles* const* P, const mpm_surface* con
     c->st = mpm_stats{}; c->st.newton_iters = 1; c->st.n_part = N; c->st.n_surf = S[k]->n;
   }
   return MPM_OK; }
+// The device sampler: the host stage on the (host-resident) positions, written out in the
+// device layout [dim][count] of the context's real type.
+int mpm_sample_surface_dev(mpm_ctx* c, const mpm_particles* P, double radius, double density, uint64_t seed,
+                           uint64_t step, const double* lo, const double* hi, void* s_out, void* dA_out,
+                           int32_t* label, int64_t cap, int64_t* out_n, void* s) {
+  hipStreamSynchronize((hipStream_t)s);
+  const int dim = c->p.dim; const int64_t N = P->n; const bool f64 = c->p.precision == MPM_FP64;
+  std::vector<double> x((size_t)dim * N);
+  for (size_t i = 0; i < x.size(); ++i) x[i] = f64 ? ((const double*)P->x)[i] : ((const float*)P->x)[i];
+  int64_t hcap = 4 * N + 4096, cnt = 0;
+  std::vector<double> hs((size_t)dim * hcap), hdA((size_t)dim * hcap);
+  std::vector<int32_t> hl(hcap);
+  int rc = mpm_sample_surface(dim, c->p.n, x.data(), N, radius, density, seed, step, lo, hi, hs.data(), hdA.data(),
+                              hl.data(), hcap, &cnt);
+  if (rc != MPM_OK || cnt > hcap) return rc != MPM_OK ? rc : MPM_ENOMEM;
+  *out_n = cnt;
+  if (cnt > cap) return MPM_OK;
+  for (int a = 0; a < dim; ++a)
+    for (int64_t i = 0; i < cnt; ++i) {
+      if (f64) { ((double*)s_out)[a * cnt + i] = hs[a * hcap + i]; ((double*)dA_out)[a * cnt + i] = hdA[a * hcap + i]; }
+      else { ((float*)s_out)[a * cnt + i] = (float)hs[a * hcap + i]; ((float*)dA_out)[a * cnt + i] = (float)hdA[a * hcap + i]; }
+    }
+  if (label) std::memcpy(label, hl.data(), cnt * 4);
+  return MPM_OK;
+}
 int mpm_get_stats(const mpm_ctx* c, mpm_stats* o) { *o = c->st; return MPM_OK; }
 int mpm_grid_view(mpm_ctx* c, int32_t f, void** out) { if (f != MPM_F_PERM) return MPM_EINVAL; *out = c->perm; return MPM_OK; }
 }

@@ -164,3 +164,33 @@ def test_fullsize_step_properties(case, precision):
             2.0 * 2.0 ** -24 * np.sum(p["cp"] * m[dof] * np.abs(Th[dof])) / p["dt"]
         log(f"  heat balance: {lhs:.9e} vs {rhs:.9e} (scale {scale:.3e}, bound {bound:.3e})")
         assert abs(lhs - rhs) <= bound
+
+
+def test_device_sampler_at_256_equals_host_stage():
+    """The device sampler at the melting slab's full size (256^3, ~9.7M particles, FP32
+    positions as the MIXED bench holds them): the host stage's samples bit for bit, and the
+    oracle's sample for sample on a sub-slab small enough for it."""
+    from paper_2101_12408_amd import api
+    from oracle import sampler
+    S = sc.meltslab3d()
+    P, p = S["particles"], S["params"]
+    P = {k: v.astype(np.float32).astype(np.float64) for k, v in P.items()}
+    N = len(P["m"])
+    host = api.sample_surface(P["x"], p, step=2)
+    s = api.Scene(p, cap_part=N, cap_surf=len(host["s"]) + 1024, precision="mixed")
+    Pd = s.to_device(P)
+    got = s.sample_surface(Pd, step=2)
+    log(f"  256^3 device sampler: {got['s'].shape[1]} samples (host {len(host['s'])})")
+    assert got["s"].shape[1] == len(host["s"])
+    assert np.array_equal(got["s"].cpu().numpy().T, host["s"].astype(np.float32))
+    assert np.array_equal(got["dA"].cpu().numpy().T, host["dA"].astype(np.float32))
+    assert np.array_equal(got["label"].cpu().numpy(), host["label"])
+    # a sub-slab of the same grid against the oracle, FP64 outputs
+    Sb = sc.meltslab3d(lo=0.44, hi=0.56, height=0.06)
+    Pb, pb = Sb["particles"], Sb["params"]
+    ref = sampler.sample_surface(Pb["x"], pb, step=2)
+    sb = api.Scene(pb, cap_part=len(Pb["m"]), cap_surf=len(ref["s"]) + 1024, precision="fp64")
+    gb = sb.sample_surface(sb.to_device(Pb), step=2)
+    assert gb["s"].shape[1] == len(ref["s"])
+    assert np.max(np.abs(gb["s"].cpu().numpy().T - ref["s"])) <= 1e-13
+    assert np.max(np.abs(gb["dA"].cpu().numpy().T - ref["dA"])) <= 1e-15
