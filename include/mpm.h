@@ -76,7 +76,9 @@ typedef struct mpm_params {
   int32_t slab;           /* 1: component slab_axis fixed to 0 on nodes inside the box */
   int32_t slab_axis;
   int32_t heat;           /* 1: run the implicit heat update (Section 4.3.2)           */
-  int32_t gamma_by_label; /* 1: k_r = gamma_label[label_r] (piecewise constant, Sec 3.6) */
+  int32_t gamma_by_label; /* 1: k_r = gamma_label[label_r] (piecewise constant, Sec 3.6);
+                             2: k_r = gamma(T) on samples labelled 1 (the free surface)
+                             and gamma_label[0] on the others (against container walls) */
   int32_t newton_max, cg_max, ls_max, heat_max;
   int32_t krylov;         /* mpm_krylov: the Newton system's solver.  CG (with the PSD
                              Hessian); MINRES (Paige-Saunders, Jacobi-preconditioned) for

@@ -121,7 +121,7 @@ def grid_setup(P, surf, split, grid, params):
     Tn[useE] = grid["ET"][useE] / grid["E"][useE]
     free = constraint_mask(params, dof)
     s = surf["s"]
-    if params["gamma_by_label"]:
+    if params["gamma_by_label"] == 1:
         k = np.asarray(params["gamma_label"], np.float64)[surf["label"]]
     else:
         if len(s):
@@ -130,6 +130,10 @@ def grid_setup(P, surf, split, grid, params):
         else:
             Ts = np.zeros(0)
         k = gamma_of_T(Ts, params)
+        if params["gamma_by_label"] == 2:
+            # free surface (label 1) by temperature; samples against the container's
+            # walls (label 0) take the constant gamma_label[0]
+            k = np.where(surf["label"] == 1, k, params["gamma_label"][0])
     mu = mu_of_T(P["T"], params)
     Vn = P["J"] * P["V0"]
     return dict(dof=dof, free=free, vn=vn, Tn=Tn, k=k, mu=mu, Vn=Vn)

@@ -601,16 +601,19 @@ __global__ void k_clear_tiles(Dev<R> d, const int* list, R* const* extra, int ne
   if (threadIdx.x == 0) d.tile_flag[t] = 0;
 }
 
-// k_r = gamma(T^s_r), T^s_r = sum_i N_i(s_r) T^n_i (Section 4.3.1), or by label (Sec. 3.6).
+// k_r = gamma(T^s_r), T^s_r = sum_i N_i(s_r) T^n_i (Section 4.3.1), or by label (Sec. 3.6);
+// gamma_by_label 2: gamma(T^s_r) on the free surface (label 1), gamma_label[0] elsewhere.
 template <int D, typename R>
 __global__ void k_surface_k(Dev<R> d) {
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   int S = d.ns;
   if (r >= S) return;
   R kr;
-  if (d.gamma_by_label) {
+  if (d.gamma_by_label == 1) {
     int l = d.slabel[r];
     kr = d.gamma_label[l & 3];
+  } else if (d.gamma_by_label == 2 && d.slabel[r] != 1) {
+    kr = d.gamma_label[0];   // a sample against the container's walls
   } else {
     R x[D];
 #pragma unroll

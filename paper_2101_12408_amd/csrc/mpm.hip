@@ -326,6 +326,7 @@ void check_params(const mpm_params* p) {
   if (p->precision != MPM_FP64 && p->precision != MPM_MIXED) throw ApiError{MPM_EINVAL, "bad precision"};
   if (p->slab_axis < 0 || p->slab_axis >= p->dim) throw ApiError{MPM_EINVAL, "bad slab_axis"};
   if (p->krylov != MPM_KRYLOV_CG && p->krylov != MPM_KRYLOV_MINRES) throw ApiError{MPM_EINVAL, "bad krylov"};
+  if (p->gamma_by_label < 0 || p->gamma_by_label > 2) throw ApiError{MPM_EINVAL, "gamma_by_label must be 0, 1 or 2"};
 }
 
 // Scratch of one cell sort: cell counters (zero between sorts), the scan's status words

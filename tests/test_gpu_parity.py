@@ -17,7 +17,7 @@ from gpu_cases import TOL_FP64, TOL_MIXED_FORCE, GpuState, OracleState, check, l
 pytestmark = pytest.mark.gpu
 
 CASES = [("random", 2, 1), ("random", 3, 2), ("square2d", 2, 0), ("marangoni3d_small", 3, 0),
-         ("contact3d_small", 3, 0)]
+         ("contact3d_small", 3, 0), ("cavity2d", 2, 0)]
 
 
 def _case(kind, dim, seed, precision, **kw):

@@ -96,6 +96,21 @@ def test_kr_clamp_and_label_map():
     assert np.array_equal(st["k"], [0.072, 0.02, 0.02, 0.072])
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_kr_free_surface_and_wall_samples(dim):
+    """gamma_by_label 2 (the cavity's container walls): samples labelled 1 take gamma of
+    the interpolated grid temperature as in the pin above, the others gamma_label[0]."""
+    P, p, surf, sp, st, ok, expect = _kr_case(dim, 7 + dim)
+    lab = (np.arange(len(surf["s"])) % 3 == 0).astype(np.int32)
+    surf2 = dict(surf, label=lab)
+    p2 = dict(p, gamma_by_label=2, gamma_label=(0.013, 0.5, 0.0, 0.0))
+    _, _, st2 = _prepare(P, p2, surf2)
+    on = ok & (lab == 1)
+    assert on.sum() >= 10 and (lab == 0).sum() >= 10
+    assert np.max(np.abs(st2["k"][on] - expect[on]) / np.abs(expect[on])) < 1e-12
+    assert np.all(st2["k"][lab == 0] == 0.013)
+
+
 def test_sampler_labels_the_wetted_base():
     """Contact scene (Section 6.5 analog): samples on the cap's top are liquid-air (label 0),
     samples on the flat base resting on the slab are solid-liquid (label 1)."""

@@ -216,3 +216,24 @@ def test_ellipse_conservation_with_cfl_steps():
     assert np.all(np.abs(mom) <= 1e-13 * scale)
     assert abs(L) <= 1e-13 * scale
     assert np.allclose(com, com0, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("sign", [1, -1])
+def test_cavity_marangoni_flow_direction(sign):
+    """Lid-driven cavity (Section 6.4): the free surface moves toward higher surface
+    tension.  With k = 1 - T (hot left wall) the top layer flows to +x and its speed grows;
+    with k = T the flow reverses.  The wall samples carry no energy, so nothing else drives
+    the flow."""
+    S = sc.cavity2d(n=32)
+    P, p = S["particles"], dict(S["params"])
+    if sign < 0:
+        p.update(g0=0.0, g1=1.0)
+    ux = []
+    for k in range(6):
+        P, info = step.step(P, p, implicit=True, step_index=k)
+        assert info["converged"]
+        y = P["x"][:, 1]
+        top = y > y.max() - 2 * p["dx"]
+        ux.append(float(np.mean(P["v"][top, 0])))
+    ux = np.array(ux) * sign
+    assert np.all(ux > 0) and ux[-1] > 2 * ux[0]
