@@ -104,7 +104,22 @@ typedef struct mpm_params {
                              dt_min, dt_max), rho_p = m_p / V0_p; the dt taken is in
                              mpm_stats.dt.  <= 0: the fixed dt above                     */
   double dt_min, dt_max;
+  /* Collision objects: up to MPM_MAX_PLANES static half-spaces, object k occupying
+   * {x : (x - plane_o[k]) . plane_n[k] < 0} (plane_n a unit normal pointing out of the
+   * object), each with a Coulomb friction coefficient plane_mu[k].  mpm_step applies them
+   * to the grid velocity v^ after the momentum update and before G2P, object by object in
+   * index order, at every node with (x_i - o) . n <= 0: with v_n = v^ . n < 0 the
+   * tangential part v_t = v^ - v_n n keeps max(0, |v_t| + mu v_n) of its length
+   * (sticking when that is 0) and the normal part is removed; nodes moving away (v_n >= 0)
+   * keep v^.  n_planes = 0: none. */
+  int32_t n_planes;
+  int32_t pad0_;
+  double plane_o[4][3];
+  double plane_n[4][3];
+  double plane_mu[4];
 } mpm_params;
+
+enum { MPM_MAX_PLANES = 4 };
 
 /* Interior MPM particles (Section 4): SoA device buffers of real, n items each.
  * x, v: [dim][n]; A: [dim*dim][n] with entry (a,b) at component a*dim+b; gradT: [dim][n]. */

@@ -16,6 +16,7 @@ Workloads (the paper uses no dataset; every scene here is procedural):
   meltslab3d   3D slab heated by the ambient through the Robin term, mu(T) (256^3)
   ellipse2d    2D ellipse under surface tension, explicit steps (64^2)
   cavity2d     2D lid-driven Marangoni cavity, k = clamp(1 - T, 0, 1) (64^2)
+  ramp2d/3d    droplet landing on a 5.5 degree ramp with Coulomb friction (32^2 / 64^3)
   serving      stream of small droplet scenes (n in {16,32,48,64,96})
 """
 from __future__ import annotations
@@ -43,6 +44,7 @@ DEFAULT_PARAMS = dict(
     hess_mode=0,                    # 0 = PSD (definiteness fix), 1 = EXACT
     krylov=0,                       # 0 = CG, 1 = MINRES (for the indefinite EXACT Hessian)
     cfl=0.0, dt_min=0.0, dt_max=0.0,  # cfl > 0: dt chosen per step, clamped to [dt_min, dt_max]
+    planes=(),                      # collision half-spaces ((o, n, mu), ...): solid where (x-o).n < 0
     momentum_fix=1,
     term_mask=7,                    # bit0 J-term, bit1 surface, bit2 viscosity
     ls_radius=None,                 # union-of-spheres radius; None -> 0.73 dx (2D) / 0.867 dx (3D)
@@ -212,6 +214,49 @@ def cavity2d(seed=7, n=64, cfl=0.5):
     return dict(params=p, particles=particles_from_positions(x, 2, dx, T=T, gradT=gT), name="cavity2d", steps=500)
 
 
+def _ramp_plane(theta_deg, o):
+    t = math.radians(theta_deg)
+    return (tuple(o), (-math.sin(t), math.cos(t), 0.0))
+
+
+def ramp2d(seed=8, n=32, mu=0.2, theta=5.5, radius=0.15, v0=-0.5):
+    """2D droplet landing on a ramp (the mechanism of Section 6.3 in 2D): a static
+    half-space through (0.5, 0.25) rising at theta degrees toward +x, Coulomb friction mu,
+    the droplet (radius 0.15 at 2x2 per cell, gamma 0.072) just above it and moving down
+    at v0, gravity, slip domain walls, dt 1e-3."""
+    dx = 1.0 / n
+    o, nrm = _ramp_plane(theta, (0.5, 0.25, 0.0))
+    p = make_params(dim=2, n=n, dt=1e-3, bulk=1e4, g0=0.072, gravity=(0.0, -9.8, 0.0), wall_layers=2,
+                    momentum_fix=0, planes=((o, nrm, mu),), seed=seed)
+    t = math.radians(theta)
+    c = np.array([0.6, 0.25 + (0.6 - 0.5) * math.tan(t) + (radius + 1.5 * dx) / math.cos(t)])
+    inside = lambda q: np.sum((q - c) ** 2, axis=1) < radius ** 2
+    x = lattice(n, 2, inside, seed)
+    P = particles_from_positions(x, 2, dx)
+    P["v"][:, 1] = v0
+    return dict(params=p, particles=P, name="ramp2d", steps=100)
+
+
+def ramp3d(seed=9, n=64, mu=0.2, theta=5.5, radius=0.1, v0=-0.5):
+    """3D droplet falling on a 5.5 degree ramp with Coulomb friction 0.2 (Section 6.3; one
+    drop, gamma_LA 0.072 everywhere: the paper's per-ratio wetting of the ramp would need
+    labels along the inclined plane, which the box labels do not give), 8 particles per
+    cell, gravity, slip domain walls, dt 1e-3.  The paper's dx = 1/63 becomes 1/64."""
+    dx = 1.0 / n
+    o, nrm = _ramp_plane(theta, (0.5, 0.25, 0.5))
+    p = make_params(dim=3, n=n, dt=1e-3, bulk=1e4, g0=0.072, gravity=(0.0, -9.8, 0.0), wall_layers=2,
+                    momentum_fix=0, planes=((o, nrm, mu),), seed=seed)
+    t = math.radians(theta)
+    c = np.array([0.6, 0.25 + (0.6 - 0.5) * math.tan(t) + (radius + 1.5 * dx) / math.cos(t), 0.5])
+    inside = lambda q: np.sum((q - c) ** 2, axis=1) < radius ** 2
+    lo = np.floor((c - radius) * n).astype(int) - 1
+    hi = np.ceil((c + radius) * n).astype(int) + 1
+    x = lattice(n, 3, inside, seed, lo=lo, hi=hi)
+    P = particles_from_positions(x, 3, dx)
+    P["v"][:, 1] = v0
+    return dict(params=p, particles=P, name="ramp3d", steps=100)
+
+
 def droplet3d(n, seed, gamma0, grad, radius=0.24, dt=5e-4):
     """One serving-stream scene: sphere r=0.24 at the centre, linear temperature
     T = 300 + grad . (x - c), gamma(T) = gamma0 - 1.5e-4 (T - 300)."""
@@ -311,4 +356,4 @@ def random_surface(P, count, seed, spread=1.0, dx=None, dim=None):
 
 
 CONFIGS = dict(square2d=square2d, marangoni3d=marangoni3d, contact3d=contact3d,
-               meltslab3d=meltslab3d, cavity2d=cavity2d)
+               meltslab3d=meltslab3d, cavity2d=cavity2d, ramp2d=ramp2d, ramp3d=ramp3d)

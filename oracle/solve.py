@@ -183,6 +183,37 @@ def explicit_update(ctx):
     return ctx.project(v)
 
 
+def collide(vhat, params):
+    """Static collision objects with Coulomb friction, applied to the grid velocity after
+    the momentum update (the paper's ramps, Section 6.3, give only the friction
+    coefficient; the rule here is the usual grid-node collision of MPM).  Object k is the
+    half-space (x - o) . n < 0.  At a node x_i = (i + 1/2) dx with (x_i - o) . n <= 0
+    (evaluated in FP64, products and sums in axis order) and v_n = v^ . n < 0, the
+    normal part is removed and the tangential part v_t = v^ - v_n n keeps
+    max(0, |v_t| + mu v_n) of its length.  Objects act one after another in index order."""
+    planes = params.get("planes") or ()
+    if not planes:
+        return vhat
+    dim, n, dx = params["dim"], params["n"], params["dx"]
+    xi = (bspline.node_multi_index(np.arange(n ** dim), n, dim) + 0.5) * dx
+    v = vhat.copy()
+    for o, nrm, mu in planes:
+        o = np.asarray(o, np.float64)[:dim]
+        nr = np.asarray(nrm, np.float64)[:dim]
+        phi = (xi[:, 0] - o[0]) * nr[0]
+        vn = v[:, 0] * nr[0]
+        for a in range(1, dim):
+            phi = phi + (xi[:, a] - o[a]) * nr[a]
+            vn = vn + v[:, a] * nr[a]
+        hit = (phi <= 0) & (vn < 0)
+        vt = v[hit] - vn[hit, None] * nr[None, :]
+        tl = np.sqrt(np.sum(vt * vt, axis=1))
+        keep = np.maximum(0.0, tl + mu * vn[hit])
+        scale = np.where(tl > 0, keep / np.where(tl > 0, tl, 1.0), 0.0)
+        v[hit] = vt * scale[:, None]
+    return v
+
+
 class Heat:
     def __init__(self, P, surf, grid, setup, params):
         dim, n, dx = params["dim"], params["n"], params["dx"]

@@ -54,6 +54,7 @@ def step(P, params, surf=None, implicit=True, step_index=0):
         info.update(st)
     else:
         vhat = solve.explicit_update(ctx)
+    vhat = solve.collide(vhat, params)
     if params["heat"]:
         heat = solve.Heat(P, surf, grid, setup, params)
         That, hst = heat.solve(params)

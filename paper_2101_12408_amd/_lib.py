@@ -26,7 +26,9 @@ class MpmParams(C.Structure):
         ("cp", C.c_double), ("K", C.c_double), ("h", C.c_double), ("T_amb", C.c_double), ("b", C.c_double),
         ("H", C.c_double), ("slab_lo", C.c_double * 3), ("slab_hi", C.c_double * 3),
         ("newton_tol", C.c_double), ("cg_rel", C.c_double), ("ls_c1", C.c_double), ("heat_tol", C.c_double),
-        ("cfl", C.c_double), ("dt_min", C.c_double), ("dt_max", C.c_double)]
+        ("cfl", C.c_double), ("dt_min", C.c_double), ("dt_max", C.c_double),
+        ("n_planes", C.c_int32), ("pad0_", C.c_int32), ("plane_o", (C.c_double * 3) * 4),
+        ("plane_n", (C.c_double * 3) * 4), ("plane_mu", C.c_double * 4)]
 
 
 class MpmParticles(C.Structure):

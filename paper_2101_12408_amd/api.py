@@ -45,6 +45,14 @@ def make_params(d, precision="fp64"):
         if k in d:
             vals = list(d[k]) + [0.0] * ln
             getattr(p, k)[:] = [float(v) for v in vals[:ln]]
+    planes = d.get("planes") or ()
+    if len(planes) > 4:
+        raise MpmError(L.MPM_EINVAL, "at most 4 collision planes")
+    p.n_planes = len(planes)
+    for k, (o, nrm, mu) in enumerate(planes):
+        p.plane_o[k][:] = [float(v) for v in (list(o) + [0.0] * 3)[:3]]
+        p.plane_n[k][:] = [float(v) for v in (list(nrm) + [0.0] * 3)[:3]]
+        p.plane_mu[k] = float(mu)
     return p
 
 

@@ -993,6 +993,52 @@ __global__ void k_max_speed(int n, const R* v, const R* m, const R* V0, unsigned
   }
 }
 
+// ---- collision objects -------------------------------------------------------------------
+// Static half-spaces (x - o) . n < 0 with Coulomb friction, applied to v^ at the nodes of
+// the active tiles after the momentum update, object by object.  The inside test is taken
+// in FP64 with products and sums in axis order (the oracle's arithmetic); the velocity
+// update in the arithmetic of R.
+struct Planes {
+  int n;
+  double o[4][3], nrm[4][3], mu[4];
+};
+
+template <int D, typename R>
+__global__ void k_collide(const int* tile_list, int nelem, int nn, int nt, double dx, Planes pl, R* v) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nelem) return;
+  const int tile = tile_list[e >> 6];
+  const int node = tile * kTileNodes + (e & 63);
+  int i[3] = {0, 0, 0};
+  tiled_coords<D>(tile, e & 63, nt, i);
+  R vv[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) vv[a] = v[(int64_t)a * nn + node];
+  for (int k = 0; k < pl.n; ++k) {
+    double phi = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) phi = add_nc(phi, mul_nc(sub_nc(mul_nc((double)i[a] + 0.5, dx), pl.o[k][a]), pl.nrm[k][a]));
+    if (phi > 0) continue;
+    R vn = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) vn += vv[a] * (R)pl.nrm[k][a];
+    if (!(vn < 0)) continue;
+    R vt[D], t2 = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      vt[a] = vv[a] - vn * (R)pl.nrm[k][a];
+      t2 += vt[a] * vt[a];
+    }
+    const R tl = sqrt(t2);
+    const R keep = fmax(R(0), tl + (R)pl.mu[k] * vn);
+    const R sc = tl > 0 ? keep / tl : R(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) vv[a] = vt[a] * sc;
+  }
+#pragma unroll
+  for (int a = 0; a < D; ++a) v[(int64_t)a * nn + node] = vv[a];
+}
+
 // ---- preconditioned MINRES (Paige and Saunders 1975) -----------------------------------
 // For the Newton system with the exact surface Hessian, which may be indefinite.  The
 // Lanczos process on the Jacobi-preconditioned operator gives a tridiagonal matrix; one

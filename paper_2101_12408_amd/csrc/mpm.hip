@@ -327,6 +327,13 @@ void check_params(const mpm_params* p) {
   if (p->slab_axis < 0 || p->slab_axis >= p->dim) throw ApiError{MPM_EINVAL, "bad slab_axis"};
   if (p->krylov != MPM_KRYLOV_CG && p->krylov != MPM_KRYLOV_MINRES) throw ApiError{MPM_EINVAL, "bad krylov"};
   if (p->gamma_by_label < 0 || p->gamma_by_label > 2) throw ApiError{MPM_EINVAL, "gamma_by_label must be 0, 1 or 2"};
+  if (p->n_planes < 0 || p->n_planes > MPM_MAX_PLANES) throw ApiError{MPM_EINVAL, "n_planes must be in [0, 4]"};
+  for (int k = 0; k < p->n_planes; ++k) {
+    double l2 = 0;
+    for (int a = 0; a < 3; ++a) l2 += p->plane_n[k][a] * p->plane_n[k][a];
+    if (!(std::fabs(l2 - 1.0) < 1e-9)) throw ApiError{MPM_EINVAL, "plane_n must be unit normals"};
+    if (!(p->plane_mu[k] >= 0)) throw ApiError{MPM_EINVAL, "plane_mu must be >= 0"};
+  }
 }
 
 // Scratch of one cell sort: cell counters (zero between sorts), the scan's status words
@@ -1755,6 +1762,18 @@ int step_one(mpm_ctx* c, mpm_particles* P, const mpm_surface* S, int implicit, h
         if (!implicit) do_explicit<D, R>(c, s);
         else if (c->p.krylov == MPM_KRYLOV_MINRES) do_solve_momentum_minres<D, R>(c, s);
         else do_solve_momentum<D, R>(c, s);
+        if (c->p.n_planes > 0 && c->ntiles > 0) {
+          // collision objects act on v^ before G2P
+          Planes pl{};
+          pl.n = c->p.n_planes;
+          for (int k = 0; k < pl.n; ++k) {
+            for (int a = 0; a < 3; ++a) { pl.o[k][a] = c->p.plane_o[k][a]; pl.nrm[k][a] = c->p.plane_n[k][a]; }
+            pl.mu[k] = c->p.plane_mu[k];
+          }
+          const int nelem = c->ntiles * 64;
+          LAUNCH(c, MPM_K_BLAS, (k_collide<D, R>), dim3(cdiv(nelem, 256)), dim3(256), 0, s,
+                 (const int*)dev<R>(c).tile_list, nelem, (int)c->nn, c->nt, c->p.dx, pl, (R*)c->vhat);
+        }
         if (heat) {
           heat_end<D, R>(c, hs, run);
           aux_mark(c, hs, &c->ev_join);

@@ -445,3 +445,53 @@ def test_cavity_marangoni_circulation_on_gpu():
     grid = nat.reshape(2, p["n"], p["n"])          # [a][i1][i0]
     assert np.all(grid[0][:, :2] == 0) and np.all(grid[0][:, -2:] == 0)
     assert np.all(grid[1][:2, :] == 0) and np.all(grid[1][-2:, :] == 0)
+
+
+@pytest.mark.parametrize("case", ["ramp2d", "ramp3d_small"])
+def test_collision_step_matches_oracle_fp64(case):
+    """Collision objects with Coulomb friction (the ramps of Section 6.3): from a state in
+    contact (the oracle's trajectory after the droplet lands), one FP64 step against the
+    oracle's."""
+    if case == "ramp2d":
+        S, pre = sc.ramp2d(v0=-3.0), 22
+    else:
+        S, pre = sc.ramp3d(n=32, radius=0.15, v0=-3.0), 12
+    P, p = S["particles"], dict(S["params"], **TIGHT)
+    for k in range(pre):
+        P, _ = ostep.step(P, p, implicit=True, step_index=k)
+    o, nr, _ = p["planes"][0]
+    phi = (P["x"] - np.asarray(o)[:p["dim"]]) @ np.asarray(nr)[:p["dim"]]
+    assert phi.min() < 0.5 * p["dx"]       # the droplet's stencils reach into the object
+    surf = sampler.sample_surface(P["x"], p, step=pre)
+    ref, info = ostep.step(P, p, surf, step_index=pre)
+    got, st, rc = _gpu_step(P, surf, p)
+    assert rc == 0
+    for k in ("v", "A", "J", "x"):
+        e = rel(got[k] - P[k], ref[k] - P[k]) if k in ("x", "J") else rel(got[k], ref[k])
+        log(f"  {case} {k}: rel {e:.3e}")
+        assert e < 1e-7, k
+
+
+def test_ramp3d_friction_on_gpu():
+    """The 3D ramp at 64^3 over 60 implicit steps in MIXED with the device sampler: the
+    landed droplet slides down-slope, slower with friction 0.2 than without, and no
+    particle ends more than 1.5 cells inside the ramp (the collision acts on grid nodes,
+    so a particle's velocity also draws on the free nodes of its 3-node stencil above the
+    plane: a grid-node collision bounds the penetration by the stencil's reach, not by 0)."""
+    from paper_2101_12408_amd import api
+    ux = []
+    for mu in (0.0, 0.2):
+        S = sc.ramp3d(mu=mu, v0=-3.0)
+        P, p = S["particles"], S["params"]
+        N = len(P["m"])
+        s = api.Scene(p, cap_part=N, cap_surf=20 * N, precision="mixed")
+        Pd = s.to_device(P)
+        for k in range(60):
+            s.step(Pd, s.sample_surface(Pd, step=k))
+        Q = _host_state(Pd, 3)
+        o, nr, _ = p["planes"][0]
+        phi = (Q["x"] - np.asarray(o)) @ np.asarray(nr)
+        ux.append(float(np.sum(Q["m"] * Q["v"][:, 0]) / Q["m"].sum()))
+        log(f"  mu {mu}: mean u_x {ux[-1]:+.4e}, deepest particle {phi.min() / p['dx']:+.2f} dx")
+        assert phi.min() > -1.5 * p["dx"]
+    assert ux[0] < ux[1] < 0

@@ -328,3 +328,27 @@ def test_slab_box_enumerated():
     assert got == fixed
     assert np.all(free[dof][:, [0, 2]])
     assert not np.any(free[5])
+
+
+def test_collision_plane_coulomb_closed_form():
+    """Collision object y < 0.5 with friction mu (the ramps' mechanism, Section 6.3): a node
+    inside moving in (v_n < 0) loses its normal part and its tangential part shrinks by
+    mu |v_n| (to zero when that is not positive); nodes moving out, and nodes outside, keep
+    v^.  Planted mistake: friction added with the wrong sign gives |v_t| + mu |v_n|."""
+    p = sc.make_params(dim=2, n=16, planes=(((0.0, 0.5, 0.0), (0.0, 1.0, 0.0), 0.5),))
+    xi = (np.stack(np.meshgrid(np.arange(16), np.arange(16), indexing="xy"), -1).reshape(-1, 2) + 0.5) / 16
+    below = np.nonzero(xi[:, 1] < 0.5)[0]
+    above = np.nonzero(xi[:, 1] > 0.5)[0]
+    v = np.zeros((256, 2))
+    cases = [(below[3], (1.0, -1.0), (0.5, 0.0)), (below[7], (0.3, -1.0), (0.0, 0.0)),
+             (below[9], (-2.0, -2.0), (-1.0, 0.0)), (below[11], (1.0, 1.0), (1.0, 1.0)),
+             (above[5], (1.0, -1.0), (1.0, -1.0))]
+    for k, vin, _ in cases:
+        v[k] = vin
+    out = solve.collide(v, p)
+    for k, _, vout in cases:
+        assert np.allclose(out[k], vout, rtol=0, atol=1e-15), (k, out[k], vout)
+    p0 = dict(p, planes=(((0.0, 0.5, 0.0), (0.0, 1.0, 0.0), 0.0),))
+    assert np.allclose(solve.collide(v, p0)[below[3]], (1.0, 0.0), rtol=0, atol=1e-15)
+    vt, vn, mu = 1.0, -1.0, 0.5
+    assert abs((vt - mu * vn) - out[below[3]][0]) > 0.5   # the planted sign misses the pin

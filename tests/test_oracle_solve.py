@@ -237,3 +237,17 @@ def test_cavity_marangoni_flow_direction(sign):
         ux.append(float(np.mean(P["v"][top, 0])))
     ux = np.array(ux) * sign
     assert np.all(ux > 0) and ux[-1] > 2 * ux[0]
+
+
+def test_ramp_friction_orders_the_slide():
+    """A 2D droplet landing on a 5.5 degree ramp slides down-slope (-x); with more Coulomb
+    friction it slides slower: mean u_x ordered mu = 0 < 0.2 < 5 in magnitude after 40
+    steps, all negative."""
+    ux = []
+    for mu in (0.0, 0.2, 5.0):
+        S = sc.ramp2d(mu=mu, v0=-3.0)
+        P, p = S["particles"], S["params"]
+        for k in range(40):
+            P, info = step.step(P, p, implicit=True, step_index=k)
+        ux.append(float(np.sum(P["m"] * P["v"][:, 0]) / P["m"].sum()))
+    assert ux[0] < ux[1] < ux[2] < 0, ux
