@@ -54,7 +54,7 @@ def free_gpu():
     torch.cuda.empty_cache()
 
 
-def run_gpu(scene_fn, precision, steps, warmup, want_timing, label):
+def run_gpu(scene_fn, precision, steps, warmup, want_timing, label, autotune=False):
     """Records warmup + steps steps (each step's surface drawn by the device sampler and
     kept in HBM), then replays them with every input in HBM: the timed pass, and with
     want_timing a second pass with per-launch HIP events for the per-class breakdown.  A
@@ -79,6 +79,15 @@ def run_gpu(scene_fn, precision, steps, warmup, want_timing, label):
     torch.cuda.synchronize()
     upload_s = time.perf_counter() - tu
     surfs = []
+    tuning = None
+    if autotune:
+        # the tile kernels' XCD run lengths, timed on the first step's scene (bitwise
+        # the same results for every choice)
+        S0 = scene.sample_surface(Pd, step=0)
+        scene.p2g(Pd, S0)
+        tuning = scene.autotune()
+        log(f"{label} {precision}: autotune " + ", ".join(f"{k} run {v[0]}" for k, v in tuning.items()))
+        del S0
     for k in range(warmup + steps):
         Sd = scene.sample_surface(Pd, step=k)
         surfs.append(Sd)
@@ -129,7 +138,8 @@ def run_gpu(scene_fn, precision, steps, warmup, want_timing, label):
         + (f", with per-launch events {1e3 * elapsed_ev / steps:.3f}" if want_timing else "")
         + f", all-in with device sampling {1e3 * elapsed_all / steps:.3f}")
     out = dict(N=N, elapsed=elapsed, elapsed_events=elapsed_ev, elapsed_all_in=elapsed_all, stats=stats,
-               timing=timing, S=len(surf0["s"]), params=p, host_sample_s=host_sample_s, upload_s=upload_s)
+               timing=timing, S=len(surf0["s"]), params=p, host_sample_s=host_sample_s, upload_s=upload_s,
+               tuning=tuning)
     del scene, Pd, init, surfs
     free_gpu()
     return out
@@ -543,6 +553,7 @@ def main():
     ap.add_argument("--no-secondary", action="store_true", help="skip the other workloads")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the built-in tile run-length rule")
     ap.add_argument("--serving-requests", type=int, default=512,
                     help="requests of the serving stream (0: skip the serving measurement)")
     ap.add_argument("--serving-concurrency", type=int, default=8)
@@ -573,7 +584,8 @@ def main():
     if args.copy_calibration:
         copy_calibration()
     K = args.steps
-    main_run = run_gpu(scene_fn, args.precision, K, args.warmup, not args.no_timing, args.workload)
+    main_run = run_gpu(scene_fn, args.precision, K, args.warmup, not args.no_timing, args.workload,
+                       autotune=not args.no_autotune)
     N = main_run["N"]
     value = N * K / main_run["elapsed"]
     st = main_run["stats"]
@@ -670,6 +682,7 @@ def main():
                        sampling_ms_per_step=round(1e3 * (main_run["elapsed_all_in"] - main_run["elapsed"]) / K, 3),
                        host_stage=dict(value=round(host_stage, 1), host_sampling_s_per_step=round(
                            main_run["host_sample_s"], 4), upload_s_per_step=round(main_run["upload_s"], 4))),
+        "autotune": main_run["tuning"],
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fp64_gpu": fp64,

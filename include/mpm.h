@@ -332,6 +332,24 @@ int mpm_sample_surface(int32_t dim, int32_t n, const double* x, int64_t n_part, 
                        const double* label_hi, double* s, double* dA, int32_t* label, int64_t cap,
                        int64_t* out_n);
 
+/* Autotuner of the tile kernels' launch layout.  The stress (energy, Hessian) and heat
+ * tile kernels map workgroups to cell tiles in runs of `run` consecutive tiles per XCD
+ * (each XCD has its own L2; neighbouring tiles share node-region lines).  mpm_autotune
+ * times each kernel class on the context's current scene (after mpm_p2g) at run lengths
+ * 1, 2, 4, ..., 64 (the best of three launches each, the surface linearized at v^n) and
+ * keeps the fastest for the context's later launches.  The run length only assigns tiles
+ * to workgroups: results are bitwise the same for every choice.  Synchronizes stream; out
+ * (may be NULL) receives the times.  mpm_tuning_set fixes the run lengths (energy,
+ * Hessian, heat; 0 = the built-in size rule; run NULL resets all three). */
+typedef struct mpm_tuning {
+  int32_t run[3];          /* chosen run length per class (0: class not timed)          */
+  int32_t ncand;           /* candidates timed                                          */
+  int32_t cand[8];         /* their run lengths                                         */
+  double us[3][8];         /* best launch-pair time of each candidate, microseconds     */
+} mpm_tuning;
+int mpm_autotune(mpm_ctx* ctx, void* stream, mpm_tuning* out);
+int mpm_tuning_set(mpm_ctx* ctx, const int32_t* run);
+
 /* Device surface sampler (Section 4.1.1): the samples mpm_sample_surface draws, computed
  * on the context's GPU from device particle positions P->x ([dim][P->n] real of the
  * context's precision, P->n <= the context's particle capacity; the other particle arrays

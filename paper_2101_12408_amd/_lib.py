@@ -48,6 +48,10 @@ class MpmStats(C.Structure):
         ("n_tiles", C.c_int64), ("dt", C.c_double)]
 
 
+class MpmTuning(C.Structure):
+    _fields_ = [("run", C.c_int32 * 3), ("ncand", C.c_int32), ("cand", C.c_int32 * 8), ("us", (C.c_double * 8) * 3)]
+
+
 class MpmRequest(C.Structure):
     _fields_ = [("id", C.c_int64), ("params", MpmParams), ("n_steps", C.c_int32), ("implicit", C.c_int32),
                 ("keep_result", C.c_int32), ("borrow", C.c_int32), ("n_part", C.c_int64), ("seed", C.c_uint64),
@@ -104,6 +108,8 @@ EXPORTS = {
     "mpm_sample_surface": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_int64, C.c_double, C.c_double,
                                      C.c_uint64, C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]),
+    "mpm_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mpm_tuning_set": (C.c_int, [C.c_void_p, C.c_void_p]),
     "mpm_sample_surface_dev": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_uint64, C.c_uint64,
                                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                          C.POINTER(C.c_int64), C.c_void_p]),

@@ -186,6 +186,20 @@ class Scene:
                             label=torch.from_numpy(np.ascontiguousarray(lab.astype(np.int32))).cuda()))
         return out[0] if len(out) == 1 else tuple(out)
 
+    def autotune(self):
+        """mpm_autotune after p2g: {class: (chosen run length, {run: microseconds})}."""
+        t = L.MpmTuning()
+        _check(self.lib.mpm_autotune(self.ctx, self.stream(), C.byref(t)), self.lib, self.ctx)
+        out = {}
+        for k, name in enumerate(("energy", "hess", "heat")):
+            if t.run[k]:
+                out[name] = (int(t.run[k]), {int(t.cand[j]): round(float(t.us[k][j]), 2) for j in range(t.ncand)})
+        return out
+
+    def tuning_set(self, run=None):
+        arr = None if run is None else (C.c_int32 * 3)(*run)
+        _check(self.lib.mpm_tuning_set(self.ctx, arr), self.lib, self.ctx)
+
     def sample_surface(self, P, step=0, cap=None):
         """Device sampler (mpm_sample_surface_dev) around the device positions P["x"]
         ([dim][N] of the scene's dtype): the host sampler's samples, as device tensors

@@ -135,6 +135,9 @@ struct mpm_ctx {
   bool have_p2g = false, constrained = false, mom_pending = false;
   // Krylov launch schedule learned from the previous solves (first chunk sizes)
   int cg_hint_mom = 2, cg_hint_heat = 2;
+  // run lengths of the tile kernels' XCD slot mapping picked by mpm_autotune (energy,
+  // Hessian, heat; 0: the size heuristic xcd_run)
+  int run_tuned[3] = {0, 0, 0};
   int status = 0;
   mpm_stats stats{};
   std::string err;
@@ -399,18 +402,22 @@ template <typename R> Dev<R>& dev(mpm_ctx* c);
 template <> Dev<double>& dev<double>(mpm_ctx* c) { return c->d64; }
 template <> Dev<float>& dev<float>(mpm_ctx* c) { return c->d32; }
 
-TileLists tiles(mpm_ctx* c) {
+// Tile kernel classes whose XCD run length mpm_autotune picks.
+enum : int { TUNE_ENERGY = 0, TUNE_HESS = 1, TUNE_HEAT = 2, TUNE_COUNT = 3 };
+int run_for(const mpm_ctx* c, int k) { return c->run_tuned[k] > 0 ? c->run_tuned[k] : xcd_run(c->nctile); }
+
+TileLists tiles(mpm_ctx* c, int k = TUNE_ENERGY) {
   TileLists t;
   t.ctile_list = c->ctile_list;
   t.ctile_slot = c->ctile_slot;
   t.ctile_rng = c->ctile_rng;
   t.nbr = c->nbr_slot;
   t.nctile = c->nctile;
-  t.xrun = xcd_run(c->nctile);
+  t.xrun = run_for(c, k);
   return t;
 }
 // Grid of a tile kernel that takes its slot with xcd_slot.
-int tile_grid(const mpm_ctx* c) { return xcd_grid(c->nctile, xcd_run(c->nctile)); }
+int tile_grid(const mpm_ctx* c, int k = TUNE_ENERGY) { return xcd_grid(c->nctile, run_for(c, k)); }
 
 int krylov_blocks(int nelem) { return std::max(1, std::min(1024, cdiv(nelem, kNodeThreads))); }
 int merge_blocks(const mpm_ctx* c) { return cdiv(c->ntiles, kMergeTiles); }
@@ -628,11 +635,11 @@ template <int D, typename R>
 void do_hessvec(mpm_ctx* c, const R* w, double alpha, R* out, bool mask_in, const int* done, CgScal* cg,
                 hipStream_t s, PUpd<R> pu = PUpd<R>{}, R* f_lin = nullptr) {
   Dev<R>& d = dev<R>(c);
-  TileLists tl = tiles(c);
+  TileLists tl = tiles(c, TUNE_HESS);
   Dev<R> dh = d;
   if (f_lin) dh.sF = f_lin;
   if (c->nctile > 0)
-    LAUNCH(c, MPM_K_HESS_INT, (k_tile_stress<D, R, TM_HESS>), dim3(tile_grid(c)), dim3(TileGeo<D>::NT), 0, s, dh, tl,
+    LAUNCH(c, MPM_K_HESS_INT, (k_tile_stress<D, R, TM_HESS>), dim3(tile_grid(c, TUNE_HESS)), dim3(TileGeo<D>::NT), 0, s, dh, tl,
            w, (R*)c->tpart, (int)mask_in, done, -1, pu, (R*)nullptr);
   if (c->ntiles > 0)
     LAUNCH(c, MPM_K_HESS_NODE, (k_merge_stress<D, R>), dim3(merge_blocks(c)), dim3(64 * kMergeTiles), 0, s, d, tl, c->ntiles,
@@ -663,9 +670,9 @@ template <int D, typename R>
 void do_heat_apply(mpm_ctx* c, const R* T, R* out, const int* done, CgScal* cg, hipStream_t s,
                    PUpd<R> pu = PUpd<R>{}) {
   Dev<R>& d = dev<R>(c);
-  TileLists tl = tiles(c);
+  TileLists tl = tiles(c, TUNE_HEAT);
   if (c->nctile > 0)
-    LAUNCH(c, MPM_K_HEAT_PT, (k_tile_heat<D, R>), dim3(tile_grid(c)), dim3(TileGeo<D>::NT), 0, s, d, tl, T,
+    LAUNCH(c, MPM_K_HEAT_PT, (k_tile_heat<D, R>), dim3(tile_grid(c, TUNE_HEAT)), dim3(TileGeo<D>::NT), 0, s, d, tl, T,
            (R*)c->tpart_heat, done, pu);
   if (c->ntiles > 0)
     LAUNCH(c, MPM_K_HEAT_NODE, (k_merge_heat<D, R>), dim3(merge_blocks(c)), dim3(64 * kMergeTiles), 0, s, d, tl,
@@ -1621,6 +1628,70 @@ int mpm_g2p(mpm_ctx* ctx, const void* v_hat, const void* T_hat, mpm_particles* P
     });
   });
   return rc != MPM_OK ? rc : check_launch(ctx);
+}
+
+int mpm_autotune(mpm_ctx* ctx, void* stream, mpm_tuning* out) {
+  if (!ctx) return MPM_EINVAL;
+  if (!ctx->have_p2g) { ctx->err = "mpm_p2g must run first"; return MPM_EINVAL; }
+  hipStream_t s = (hipStream_t)stream;
+  mpm_tuning res{};
+  int rc = guarded(ctx, [&] {
+    const int cand[] = {1, 2, 4, 8, 16, 32, 64};
+    const int ncand = (int)(sizeof(cand) / sizeof(cand[0]));
+    res.ncand = ncand;
+    for (int j = 0; j < ncand; ++j) res.cand[j] = cand[j];
+    if (ctx->nctile <= 0) return;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    dispatch(ctx, [&](auto Dc, auto Rv) {
+      constexpr int D = decltype(Dc)::value;
+      using R = decltype(Rv);
+      Dev<R>& d = dev<R>(ctx);
+      const R* vn = (const R*)d.gvn;
+      // the Hessian's linearization at v^n (the solve forms its own from its start)
+      do_surface_lin<D, R>(ctx, vn, s);
+      auto op = [&](int k) {
+        if (k == TUNE_ENERGY) do_energy_grad<D, R>(ctx, vn, (R*)ctx->gscratch, nullptr, SC_GT, s);
+        else if (k == TUNE_HESS)
+          do_hessvec<D, R>(ctx, vn, 1.0, (R*)ctx->gscratch, true, nullptr, (CgScal*)nullptr, s);
+        else do_heat_apply<D, R>(ctx, (const R*)d.gTn, (R*)ctx->hr, nullptr, (CgScal*)nullptr, s);
+      };
+      for (int k = 0; k < TUNE_COUNT; ++k) {
+        if (k == TUNE_HEAT && !ctx->p.heat) continue;
+        double best = 1e300;
+        int pick = 0;
+        for (int j = 0; j < ncand; ++j) {
+          ctx->run_tuned[k] = cand[j];
+          op(k);   // warm-up
+          float tmin = 1e30f;
+          for (int rep = 0; rep < 3; ++rep) {
+            HIPCHK(hipEventRecord(e0, s));
+            op(k);
+            HIPCHK(hipEventRecord(e1, s));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            tmin = std::min(tmin, ms);
+          }
+          res.us[k][j] = 1e3 * tmin;
+          if (tmin < best) { best = tmin; pick = cand[j]; }
+        }
+        ctx->run_tuned[k] = pick;
+        res.run[k] = pick;
+      }
+    });
+    HIPCHK(hipEventDestroy(e0));
+    HIPCHK(hipEventDestroy(e1));
+  });
+  if (out) *out = res;
+  return rc != MPM_OK ? rc : check_launch(ctx);
+}
+
+int mpm_tuning_set(mpm_ctx* ctx, const int32_t* run) {
+  if (!ctx) return MPM_EINVAL;
+  for (int k = 0; k < 3; ++k) ctx->run_tuned[k] = run ? std::max(0, run[k]) : 0;
+  return MPM_OK;
 }
 
 int mpm_sample_surface_dev(mpm_ctx* ctx, const mpm_particles* P, double radius, double density, uint64_t seed,

@@ -101,7 +101,7 @@ def test_struct_layouts_match_c_compiler(tmp_path):
         pytest.skip("no C compiler")
     structs = {"mpm_params": L.MpmParams, "mpm_particles": L.MpmParticles, "mpm_surface": L.MpmSurface,
                "mpm_stats": L.MpmStats, "mpm_request": L.MpmRequest, "mpm_completion": L.MpmCompletion,
-               "mpm_server_info": L.MpmServerInfo}
+               "mpm_server_info": L.MpmServerInfo, "mpm_tuning": L.MpmTuning}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mpm.h"', 'int main(void) {']
     for cname, ct in structs.items():
         lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')

@@ -495,3 +495,32 @@ def test_ramp3d_friction_on_gpu():
         log(f"  mu {mu}: mean u_x {ux[-1]:+.4e}, deepest particle {phi.min() / p['dx']:+.2f} dx")
         assert phi.min() > -1.5 * p["dx"]
     assert ux[0] < ux[1] < 0
+
+
+def test_autotune_picks_a_layout_and_leaves_results_unchanged():
+    """mpm_autotune times the tile kernels at every run length and keeps the fastest; the
+    run length only deals tiles to workgroups, so a step is bitwise the same under the
+    tuned layout, the built-in rule and an extreme fixed one."""
+    from paper_2101_12408_amd import api
+    S = sc.marangoni3d(n=64, radius=0.25)
+    P, p = S["particles"], S["params"]
+    surf = sampler.sample_surface(P["x"], p)
+    res = []
+    for mode in ("rule", "tuned", "fixed64"):
+        s = api.Scene(p, cap_part=len(P["m"]), cap_surf=len(surf["s"]), precision="mixed")
+        Pd, Sd = s.to_device(P, surf)
+        if mode == "tuned":
+            s.p2g(Pd, Sd)
+            t = s.autotune()
+            log(f"  autotune: {t}")
+            assert set(t) == {"energy", "hess", "heat"}
+            for name, (run, times) in t.items():
+                assert run in times and all(v > 0 for v in times.values())
+                assert times[run] == min(times.values())
+        elif mode == "fixed64":
+            s.tuning_set((64, 64, 64))
+        s.step(Pd, Sd)
+        res.append({k: v.cpu().numpy().copy() for k, v in Pd.items()})
+    for r in res[1:]:
+        for k in r:
+            assert np.array_equal(r[k], res[0][k]), k
