@@ -45,6 +45,8 @@ DEFAULT_PARAMS = dict(
     krylov=0,                       # 0 = CG, 1 = MINRES (for the indefinite EXACT Hessian)
     cfl=0.0, dt_min=0.0, dt_max=0.0,  # cfl > 0: dt chosen per step, clamped to [dt_min, dt_max]
     planes=(),                      # collision half-spaces ((o, n, mu), ...): solid where (x-o).n < 0
+    T_melt=-1e300,                  # particles with T < T_melt are fixed-corotated solids
+    muh0=0.0, lamh0=0.0, kh=0.0, Th0=0.0,  # mu^h, lambda^h = (muh0, lamh0) exp(-kh (T - Th0))
     momentum_fix=1,
     term_mask=7,                    # bit0 J-term, bit1 surface, bit2 viscosity
     ls_radius=None,                 # union-of-spheres radius; None -> 0.73 dx (2D) / 0.867 dx (3D)

@@ -33,7 +33,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import bspline
+from . import bspline, transfer
 from .transfer import _scatter
 
 TERM_J, TERM_SURF, TERM_VISC = 1, 2, 4
@@ -96,6 +96,71 @@ def surface_hessvec(G, N, dG, exact):
     return H
 
 
+# ---- fixed-corotated solid (Section 3.2.1) ---------------------------------------------
+# psi^h(F) = mu^h sum_a (sigma_a - 1)^2 + lambda^h / 2 (J - 1)^2 = mu^h |F - R|^2 +
+# lambda^h / 2 (J - 1)^2 with R the orthogonal polar factor of F (S = R^T F symmetric
+# positive semidefinite, its eigenvalues the singular values).  Piola stress
+# P = 2 mu (F - R) + lambda (J - 1) cof(F), cof(F) = J F^{-T}.
+
+def polar(F):
+    """Orthogonal polar factor R and S = R^T F (Q, d, d), from the SVD F = U Sigma V^T."""
+    U, _, Vt = np.linalg.svd(F)
+    R = U @ Vt
+    return R, np.transpose(R, (0, 2, 1)) @ F
+
+
+def cofactor(F):
+    """det(F) F^{-T}."""
+    return np.linalg.det(F)[:, None, None] * np.transpose(np.linalg.inv(F), (0, 2, 1))
+
+
+def corotated_psi(F, mu, lam):
+    R, _ = polar(F)
+    J = np.linalg.det(F)
+    return mu * np.sum((F - R) ** 2, axis=(1, 2)) + 0.5 * lam * (J - 1.0) ** 2
+
+
+def corotated_P(F, mu, lam):
+    R, _ = polar(F)
+    J = np.linalg.det(F)
+    return 2.0 * mu[:, None, None] * (F - R) + (lam * (J - 1.0))[:, None, None] * cofactor(F)
+
+
+def corotated_dP(F, mu, lam, dF, exact):
+    """dP = dP/dF : dF.  EXACT: the full derivative, with dR = R [w]x, w solving
+    (tr(S) I - S) w = axial(R^T dF - dF^T R) (3D; 2D: w = (M_10 - M_01) / tr S), and
+    d cof = (cof : dF) F^{-T} - cof dF^T F^{-T}.  PSD (the definiteness fix): the rotation
+    held fixed and the (J - 1) d cof term dropped, 2 mu dF + lambda (cof : dF) cof, which
+    is positive semidefinite."""
+    C = cofactor(F)
+    cdf = np.sum(C * dF, axis=(1, 2))
+    out = 2.0 * mu[:, None, None] * dF + (lam * cdf)[:, None, None] * C
+    if not exact:
+        return out
+    d = F.shape[1]
+    R, S = polar(F)
+    M = np.transpose(R, (0, 2, 1)) @ dF
+    K = M - np.transpose(M, (0, 2, 1))
+    trS = np.trace(S, axis1=1, axis2=2)
+    if d == 2:
+        w = K[:, 1, 0] / trS
+        Om = np.zeros_like(F)
+        Om[:, 0, 1] = -w
+        Om[:, 1, 0] = w
+    else:
+        ax = np.stack([K[:, 2, 1], K[:, 0, 2], K[:, 1, 0]], axis=1)
+        A = trS[:, None, None] * np.eye(3)[None] - S
+        w = np.linalg.solve(A, ax[:, :, None])[:, :, 0]
+        Om = np.zeros_like(F)
+        Om[:, 0, 1], Om[:, 0, 2], Om[:, 1, 2] = -w[:, 2], w[:, 1], -w[:, 0]
+        Om[:, 1, 0], Om[:, 2, 0], Om[:, 2, 1] = w[:, 2], -w[:, 1], w[:, 0]
+    dR = R @ Om
+    Finv_t = np.transpose(np.linalg.inv(F), (0, 2, 1))
+    dC = cdf[:, None, None] * Finv_t - C @ np.transpose(dF, (0, 2, 1)) @ Finv_t
+    J = np.linalg.det(F)
+    return out - 2.0 * mu[:, None, None] * dR + (lam * (J - 1.0))[:, None, None] * dC
+
+
 def point_gradient(field, idx, G):
     """sum_j field_j (x) grad N_j(x_q) for every quadrature point q: (Q, d, d)."""
     return np.einsum("qja,qjb->qab", field[idx], G)
@@ -118,10 +183,17 @@ class Context:
         self.dA = surf["dA"]
         self.k = setup["k"]
         self.lam = params["bulk"]
-        self.V0 = P["V0"]
+        # solid particles (T below the melting point, with F given) take the fixed-corotated
+        # term in place of the fluid's J term, and no viscosity
+        self.solid = transfer.solid_mask(P["T"], params) if "F" in P else np.zeros(len(P["m"]), bool)
+        liq = ~self.solid
+        self.V0 = P["V0"] * liq
+        self.V0s = P["V0"][self.solid]
+        self.Fn = P["F"][self.solid] if "F" in P else np.zeros((0, params["dim"], params["dim"]))
+        self.muh, self.lamh = transfer.lame_of_T(P["T"][self.solid], params)
         self.Jn = P["J"]
         self.Vn = setup["Vn"]
-        self.mu = setup["mu"]
+        self.mu = setup["mu"] * liq
         self.m = grid["m"]
         self.vn = setup["vn"]
         self.dof = setup["dof"]
@@ -139,11 +211,19 @@ class Context:
         I = np.eye(self.dim)[None]
         return I + self.dt * point_gradient(vhat, self.sidx, self.sG)
 
+    def Fsolid(self, vhat):
+        """F_p = (I + dt grad v^(x_p)) F^n_p of the solid particles."""
+        I = np.eye(self.dim)[None]
+        sel = self.solid
+        return (I + self.dt * point_gradient(vhat, self.pidx[sel], self.pG[sel])) @ self.Fn
+
     def psi_terms(self, vhat):
         """e_J, e_sigma and D at y = x + dt v^."""
         eJ = es = D = 0.0
         if self.mask & TERM_J:
             eJ = float(np.sum(0.5 * self.lam * (self.Jp(vhat) - 1.0) ** 2 * self.V0))
+            if len(self.V0s):
+                eJ += float(np.sum(self.V0s * corotated_psi(self.Fsolid(vhat), self.muh, self.lamh)))
         if self.mask & TERM_SURF and len(self.k):
             a = cof_normal_definition(self.Fs(vhat), self.dA)
             es = float(np.sum(self.k * np.linalg.norm(a, axis=1)))
@@ -169,6 +249,11 @@ class Context:
         if self.mask & TERM_J:
             s = dt * self.lam * self.V0 * self.Jn * (self.Jp(vhat) - 1.0)
             out += scatter_stress(s[:, None, None] * I, self.pidx, self.pG, self.nn)
+            if len(self.V0s):
+                sel = self.solid
+                Pk = corotated_P(self.Fsolid(vhat), self.muh, self.lamh)
+                Sq = dt * self.V0s[:, None, None] * Pk @ np.transpose(self.Fn, (0, 2, 1))
+                out += scatter_stress(Sq, self.pidx[sel], self.pG[sel], self.nn)
         if self.mask & TERM_SURF and len(self.k):
             Q = surface_grad(self.Fs(vhat), self.dA)
             out += scatter_stress(dt * self.k[:, None, None] * Q, self.sidx, self.sG, self.nn)
@@ -193,6 +278,12 @@ class Context:
             dw = point_gradient(w, self.pidx, self.pG)
             s = dt * dt * self.lam * self.V0 * self.Jn ** 2 * np.trace(dw, axis1=1, axis2=2)
             out += scatter_stress(s[:, None, None] * I, self.pidx, self.pG, self.nn)
+            if len(self.V0s):
+                sel = self.solid
+                dF = dt * dw[sel] @ self.Fn
+                dP = corotated_dP(self.Fsolid(vlin), self.muh, self.lamh, dF, self.exact)
+                Sq = dt * self.V0s[:, None, None] * dP @ np.transpose(self.Fn, (0, 2, 1))
+                out += scatter_stress(Sq, self.pidx[sel], self.pG[sel], self.nn)
         if self.mask & TERM_SURF and len(self.k):
             dG = dt * point_gradient(w, self.sidx, self.sG)
             H = surface_hessvec(self.Fs(vlin), self.dA, dG, self.exact)

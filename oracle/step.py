@@ -65,5 +65,6 @@ def step(P, params, surf=None, implicit=True, step_index=0):
     if not params["heat"]:
         newP["T"] = P["T"].copy()
         newP["gradT"] = P["gradT"].copy()
+    newP = transfer.phase_change(P["T"], newP, params)
     info.update(vhat=vhat, That=That, dt=params["dt"])
     return newP, info

@@ -102,6 +102,18 @@ def gamma_of_T(T, params):
     return np.clip(params["g0"] + params["g1"] * (T - params["gT0"]), params["gmin"], params["gmax"])
 
 
+def solid_mask(T, params):
+    """Phase of each particle (Section 3.5): solid below the melting point."""
+    return np.asarray(T) < params.get("T_melt", -np.inf)
+
+
+def lame_of_T(T, params):
+    """mu^h and lambda^h of the solid (Section 3.5 lets them vary with temperature without
+    a form; read as the viscosity's form, (muh0, lamh0) exp(-kh (T - Th0)))."""
+    f = np.exp(-params.get("kh", 0.0) * (np.asarray(T) - params.get("Th0", 0.0)))
+    return params.get("muh0", 0.0) * f, params.get("lamh0", 0.0) * f
+
+
 def mu_of_T(T, params):
     if params["mu0"] == 0.0:
         return np.zeros_like(T)
@@ -170,6 +182,32 @@ def g2p(P, surf, split, vhat, That, params):
     Tnew = np.sum(N * That[idx], axis=1)
     gTnew = np.einsum("pj,pja->pa", That[idx], G)
     div = np.einsum("pja,pja->p", vhat[idx], G)
+    Jnew = (1.0 + dt * div) * P["J"]
     out = dict(P)
-    out.update(v=vnew, A=Anew, T=Tnew, gradT=gTnew, J=(1.0 + dt * div) * P["J"], x=x + dt * vnew)
+    if "F" in P:
+        # solids carry F: F <- (I + dt grad v^(x_p)) F, J = det F
+        solid = solid_mask(P["T"], params)
+        dv = np.einsum("pja,pjb->pab", vhat[idx][solid], G[solid])
+        Fnew = P["F"].copy()
+        Fnew[solid] = np.einsum("pab,pbc->pac", np.eye(dim)[None] + dt * dv, P["F"][solid])
+        Jnew[solid] = np.linalg.det(Fnew[solid])
+        out["F"] = Fnew
+    out.update(v=vnew, A=Anew, T=Tnew, gradT=gTnew, J=Jnew, x=x + dt * vnew)
     return out
+
+
+def phase_change(T_old, P, params):
+    """Phase change at T_melt (Section 3.5): a solid particle whose temperature reaches
+    T_melt becomes liquid with J = 1; a liquid particle that cools below it becomes solid
+    with F = I (and J = det F = 1).  P is updated in place."""
+    if "F" not in P:
+        return P
+    was = solid_mask(T_old, params)
+    now = solid_mask(P["T"], params)
+    flip = was != now
+    if np.any(flip):
+        P["J"] = P["J"].copy()
+        P["F"] = P["F"].copy()
+        P["J"][flip] = 1.0
+        P["F"][flip] = np.eye(P["F"].shape[1])
+    return P
