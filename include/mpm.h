@@ -117,6 +117,18 @@ typedef struct mpm_params {
   double plane_o[4][3];
   double plane_n[4][3];
   double plane_mu[4];
+  /* Solid phase (Sections 3.2.1, 3.5): a particle with T < T_melt is a fixed-corotated
+   * solid, psi^h(F) = mu^h sum_a (sigma_a - 1)^2 + lambda^h / 2 (J - 1)^2 per reference
+   * volume, with (mu^h, lambda^h) = (muh0, lamh0) exp(-kh (T - Th0)); it has no J-term
+   * pressure and no viscosity, and carries its deformation gradient in mpm_particles.F.
+   * G2P advances F <- (I + dt grad v^) F and J = det F; a particle whose temperature
+   * crosses T_melt upward becomes liquid with J = 1, one crossing downward becomes solid
+   * with F = I.  The phase is decided in FP64.  T_melt <= -1e299 (the default): no
+   * solids.  The solid's Hessian is the fixed-rotation form 2 mu dF + lambda (cof F : dF)
+   * cof F (positive semidefinite); hess_mode EXACT is not available with solids.  A
+   * context created without solids cannot enable them later. */
+  double T_melt;
+  double muh0, lamh0, kh, Th0;
 } mpm_params;
 
 enum { MPM_MAX_PLANES = 4 };
@@ -133,6 +145,10 @@ typedef struct mpm_particles {
   void* m;
   void* T;
   void* gradT;
+  void* F;                  /* [dim*dim][n], entry (a,b) at component a*dim+b: the
+                               deformation gradient of solid particles (liquid particles'
+                               entries are carried along); required when T_melt is set,
+                               else ignored (may be NULL)                                  */
 } mpm_particles;
 
 /* Surface samples s_r with area-weighted outward normals dA_r (Section 4.1.1), device

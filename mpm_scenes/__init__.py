@@ -152,17 +152,19 @@ def contact3d(seed=3, n=192, radius=0.15):
     return dict(params=p, particles=particles_from_positions(x, 3, dx), name="contact3d", steps=50)
 
 
-def meltslab3d(seed=4, n=256, ppc_axis=2, lo=0.2, hi=0.8, height=0.2):
+def meltslab3d(seed=4, n=256, ppc_axis=2, lo=0.2, hi=0.8, height=0.2, solid=False):
     """3D wax slab x,z in [lo,hi] (default [0.2,0.8]), y in [2dx, 2dx+height] (default 0.2),
     T0 290 K heated by a 400 K ambient through the Robin term (h 20, b 0, K 0.25, c_p 1),
     mu(T) = 1e3 exp(-0.05 (T-290)), gamma(T) as in marangoni3d, gravity -9.8, slip floor
-    (two node layers)."""
+    (two node layers).  solid=True: the wax starts as a fixed-corotated solid (F = I) that
+    melts at T_melt = 300 K (Section 3.5), Lame constants (5e3, 1e4) exp(-0.05 (T - 290))."""
     dx = 1.0 / n
+    extra = dict(T_melt=300.0, muh0=5e3, lamh0=1e4, kh=0.05, Th0=290.0) if solid else {}
     p = make_params(dim=3, n=n, dt=1e-3, bulk=1e4, gravity=(0.0, -9.8, 0.0),
                     mu0=1e3, mu_k=0.05, mu_T0=290.0,
                     g0=0.072, g1=-1.5e-4, gT0=300.0,
                     heat=1, cp=1.0, K=0.25, h=20.0, b=0.0, T_amb=400.0,
-                    wall_layers=2, momentum_fix=0, seed=seed)
+                    wall_layers=2, momentum_fix=0, seed=seed, **extra)
     y0, y1 = 2 * dx, 2 * dx + height
     inside = lambda q: (np.all((q[:, [0, 2]] >= lo) & (q[:, [0, 2]] < hi), axis=1)
                         & (q[:, 1] >= y0) & (q[:, 1] < y1))
@@ -170,8 +172,10 @@ def meltslab3d(seed=4, n=256, ppc_axis=2, lo=0.2, hi=0.8, height=0.2):
     chi = np.array([int(hi * n) + 2, int(y1 * n) + 2, int(hi * n) + 2])
     x = lattice(n, 3, inside, seed, ppc_axis=ppc_axis, lo=clo, hi=chi)
     T = np.full(x.shape[0], 290.0)
-    return dict(params=p, particles=particles_from_positions(x, 3, dx, ppc=ppc_axis ** 3, T=T),
-                name="meltslab3d", steps=20)
+    P = particles_from_positions(x, 3, dx, ppc=ppc_axis ** 3, T=T)
+    if solid:
+        P["F"] = np.tile(np.eye(3), (x.shape[0], 1, 1))
+    return dict(params=p, particles=P, name="meltslab3d_solid" if solid else "meltslab3d", steps=20)
 
 
 def ellipse2d(seed=6, n=64, cfl=0.0):

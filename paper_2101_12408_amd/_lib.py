@@ -28,11 +28,13 @@ class MpmParams(C.Structure):
         ("newton_tol", C.c_double), ("cg_rel", C.c_double), ("ls_c1", C.c_double), ("heat_tol", C.c_double),
         ("cfl", C.c_double), ("dt_min", C.c_double), ("dt_max", C.c_double),
         ("n_planes", C.c_int32), ("pad0_", C.c_int32), ("plane_o", (C.c_double * 3) * 4),
-        ("plane_n", (C.c_double * 3) * 4), ("plane_mu", C.c_double * 4)]
+        ("plane_n", (C.c_double * 3) * 4), ("plane_mu", C.c_double * 4),
+        ("T_melt", C.c_double), ("muh0", C.c_double), ("lamh0", C.c_double), ("kh", C.c_double),
+        ("Th0", C.c_double)]
 
 
 class MpmParticles(C.Structure):
-    _fields_ = [("n", C.c_int64)] + [(k, C.c_void_p) for k in ("x", "v", "A", "J", "V0", "m", "T", "gradT")]
+    _fields_ = [("n", C.c_int64)] + [(k, C.c_void_p) for k in ("x", "v", "A", "J", "V0", "m", "T", "gradT", "F")]
 
 
 class MpmSurface(C.Structure):

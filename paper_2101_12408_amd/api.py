@@ -38,7 +38,8 @@ def make_params(d, precision="fp64"):
         if k in d:
             setattr(p, k, int(d[k]))
     for k in ("dx", "dt", "bulk", "mu0", "mu_k", "mu_T0", "g0", "g1", "gT0", "gmin", "gmax", "cp", "K", "h",
-              "T_amb", "b", "H", "newton_tol", "cg_rel", "ls_c1", "heat_tol", "cfl", "dt_min", "dt_max"):
+              "T_amb", "b", "H", "newton_tol", "cg_rel", "ls_c1", "heat_tol", "cfl", "dt_min", "dt_max",
+              "T_melt", "muh0", "lamh0", "kh", "Th0"):
         if k in d:
             setattr(p, k, float(d[k]))
     for k, ln in (("gravity", 3), ("gamma_label", 4), ("slab_lo", 3), ("slab_hi", 3)):
@@ -151,7 +152,9 @@ class Scene:
     def particles_struct(self, P):
         st = L.MpmParticles()
         st.n = int(P["m"].shape[0])
-        for k in ("x", "v", "A", "J", "V0", "m", "T", "gradT"):
+        for k in ("x", "v", "A", "J", "V0", "m", "T", "gradT", "F"):
+            if k == "F" and k not in P:
+                continue
             t = P[k]
             assert t.dtype == self.dtype and t.is_contiguous() and t.is_cuda, k
             setattr(st, k, t.data_ptr())
@@ -176,8 +179,11 @@ class Scene:
             N = P["x"].shape[0]
             d = self.dim
             f = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=self.dtype).contiguous()
-            out.append(dict(x=f(P["x"].T), v=f(P["v"].T), A=f(P["A"].reshape(N, d * d).T), J=f(P["J"]),
-                            V0=f(P["V0"]), m=f(P["m"]), T=f(P["T"]), gradT=f(P["gradT"].T)))
+            Pd = dict(x=f(P["x"].T), v=f(P["v"].T), A=f(P["A"].reshape(N, d * d).T), J=f(P["J"]),
+                      V0=f(P["V0"]), m=f(P["m"]), T=f(P["T"]), gradT=f(P["gradT"].T))
+            if "F" in P:
+                Pd["F"] = f(P["F"].reshape(N, d * d).T)
+            out.append(Pd)
         if S is not None:
             f = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=self.dtype).contiguous()
             lab = S.get("label")

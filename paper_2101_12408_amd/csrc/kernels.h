@@ -19,15 +19,23 @@ struct Dev {
   R grav[3];
   R slab_lo[3], slab_hi[3];
   int slab, slab_axis, wall, term_mask, exact, gamma_by_label;
+  // solids: phase T < T_melt (decided in FP64), Lame constants (muh0, lamh0) exp(-kh (T - Th0))
+  int solids;
+  double T_melt;
+  R muh0, lamh0, kh, Th0;
   // point counts
   int np, ns;
   // interior particles, cell-sorted
   int* p_start; int* p_perm; int* p_key;
   R *px, *pv, *pA, *pm, *pmt, *pJ, *pV0, *pT, *pgT, *pmu, *pVn;
   R* pHc;   // Hessian coefficients: [0] dt^2 lam V0 J^2 (J term), [1] dt mu V^n (viscous)
+  // solids (with d.solids): F^n [D*D][N], phase 1/0 [N], mu^h V0 and lambda^h V0 [2][N]
+  R *pF, *pSol, *pLh;
   int* pcnt; int* pcnt_orig; int* grp_start; int* grp; int* gcur;
   // surface samples, cell-sorted
   int* s_start; int* s_perm; int* s_key;
+  // sF: the Hessian's linearization cache, [D*D][S] surface F_r followed (with solids) by
+  // [D*D][N] cof F_p of the solid particles
   R *ss, *sdA, *sk, *sk_orig, *sc, *sF;
   int* slabel; int* spar; int* s_parent_orig;
   // balance points, cell-sorted
@@ -272,7 +280,7 @@ __global__ void k_fill_r(R* p, R v, int64_t len) {
 // ======================================================================================
 template <int D, typename R>
 __global__ void k_gather_particles(Dev<R> d, const R* x, const R* v, const R* A, const R* J,
-                                   const R* V0, const R* m, const R* T, const R* gT) {
+                                   const R* V0, const R* m, const R* T, const R* gT, const R* F) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   int N = d.np;
   if (k >= N) return;
@@ -291,11 +299,23 @@ __global__ void k_gather_particles(Dev<R> d, const R* x, const R* v, const R* A,
   d.pm[k] = m[i];
   d.pT[k] = Tk;
   const R Vn = Jk * V0k;
-  const R mu = d.mu0 == R(0) ? R(0) : d.mu0 * exp(-d.mu_k * (Tk - d.mu_T0));
+  R mu = d.mu0 == R(0) ? R(0) : d.mu0 * exp(-d.mu_k * (Tk - d.mu_T0));
+  bool sol = false;
+  if (d.solids) {
+    // a solid has no fluid pressure and no viscosity
+    sol = (double)Tk < d.T_melt;
+    d.pSol[k] = sol ? R(1) : R(0);
+    const R fh = exp(-d.kh * (Tk - d.Th0));
+    d.pLh[k] = sol ? d.muh0 * fh * V0k : R(0);
+    d.pLh[N + k] = sol ? d.lamh0 * fh * V0k : R(0);
+#pragma unroll
+    for (int a = 0; a < D * D; ++a) d.pF[a * N + k] = F[a * N + i];
+    if (sol) mu = R(0);
+  }
   d.pVn[k] = Vn;
   d.pmu[k] = mu;
   // the Hessian's per-particle factors, rounded as the Hessian kernel would form them
-  d.pHc[k] = d.dt * d.dt * d.lam * V0k * Jk * Jk;
+  d.pHc[k] = sol ? R(0) : d.dt * d.dt * d.lam * V0k * Jk * Jk;
   d.pHc[N + k] = d.dt * (mu * Vn);
   d.pcnt[k] = 0;
 }

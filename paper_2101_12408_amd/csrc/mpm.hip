@@ -215,6 +215,8 @@ void prof_work(const Prof& pr, int k, double* ms, int64_t* n) {
     }                                                                         \
   } while (0)
 
+inline bool solids_on(const mpm_params& p) { return p.T_melt > -1e299; }
+
 template <typename R>
 size_t layout(mpm_ctx* c, char* base) {
   Bump b{base};
@@ -249,7 +251,13 @@ size_t layout(mpm_ctx* c, char* base) {
   d.pT = b.take<R>(NP); d.pgT = b.take<R>(D * NP); d.pmu = b.take<R>(NP); d.pVn = b.take<R>(NP);
   d.pHc = b.take<R>(2 * NP);
   d.ss = b.take<R>(D * NS); d.sdA = b.take<R>(D * NS); d.sk = b.take<R>(NS); d.sk_orig = b.take<R>(NS);
-  d.sc = b.take<R>((D + D * D) * NS); d.sF = b.take<R>(D * D * NS); d.bx = b.take<R>(D * NS); d.bx_unsorted = b.take<R>(D * NS);
+  const bool sol = solids_on(c->p);
+  const int64_t NL = NS + (sol ? NP : 0);   // linearization cache: surface samples, then solid particles
+  d.sc = b.take<R>((D + D * D) * NS); d.sF = b.take<R>(D * D * NL); d.bx = b.take<R>(D * NS); d.bx_unsorted = b.take<R>(D * NS);
+  d.solids = sol ? 1 : 0;
+  d.pF = sol ? b.take<R>(D * D * NP) : nullptr;
+  d.pSol = sol ? b.take<R>(NP) : nullptr;
+  d.pLh = sol ? b.take<R>(2 * NP) : nullptr;
   d.gm = b.take<R>(NN); d.gW = b.take<R>(NN); d.gWT = b.take<R>(NN); d.gE = b.take<R>(NN);
   d.gET = b.take<R>(NN); d.gTn = b.take<R>(NN); d.hdiag = b.take<R>(NN); d.hrhs = b.take<R>(NN);
   d.gmv = b.take<R>(D * NN); d.gvn = b.take<R>(D * NN); d.gdiag = b.take<R>(D * NN);
@@ -270,7 +278,7 @@ size_t layout(mpm_ctx* c, char* base) {
   int* sort_tmp = b.take<int>(std::max(NP, NS));
   int* ccount_aux = b.take<int>(NN);
   int* sort_tmp_aux = b.take<int>(NS);
-  void* sF_alt = b.take<R>(D * D * NS);
+  void* sF_alt = b.take<R>(D * D * NL);
   uint64_t* scan_flags_aux = b.take<uint64_t>(kScanBlock);
   int* smp_key = b.take<int>(NP);
   int* smp_perm = b.take<int>(NP);
@@ -316,6 +324,7 @@ void fill_params(Dev<R>& d, const mpm_params& p, int nt) {
   }
   d.slab = p.slab; d.slab_axis = p.slab_axis; d.wall = p.wall_layers; d.term_mask = p.term_mask;
   d.exact = p.hess_mode == MPM_HESS_EXACT; d.gamma_by_label = p.gamma_by_label;
+  d.T_melt = p.T_melt; d.muh0 = (R)p.muh0; d.lamh0 = (R)p.lamh0; d.kh = (R)p.kh; d.Th0 = (R)p.Th0;
 }
 
 void check_params(const mpm_params* p) {
@@ -331,6 +340,8 @@ void check_params(const mpm_params* p) {
   if (p->krylov != MPM_KRYLOV_CG && p->krylov != MPM_KRYLOV_MINRES) throw ApiError{MPM_EINVAL, "bad krylov"};
   if (p->gamma_by_label < 0 || p->gamma_by_label > 2) throw ApiError{MPM_EINVAL, "gamma_by_label must be 0, 1 or 2"};
   if (p->n_planes < 0 || p->n_planes > MPM_MAX_PLANES) throw ApiError{MPM_EINVAL, "n_planes must be in [0, 4]"};
+  if (p->T_melt > -1e299 && p->hess_mode == MPM_HESS_EXACT)
+    throw ApiError{MPM_EINVAL, "hess_mode EXACT is not available with solids (T_melt set)"};
   for (int k = 0; k < p->n_planes; ++k) {
     double l2 = 0;
     for (int a = 0; a < 3; ++a) l2 += p->plane_n[k][a] * p->plane_n[k][a];
@@ -405,6 +416,10 @@ template <> Dev<float>& dev<float>(mpm_ctx* c) { return c->d32; }
 // Tile kernel classes whose XCD run length mpm_autotune picks.
 enum : int { TUNE_ENERGY = 0, TUNE_HESS = 1, TUNE_HEAT = 2, TUNE_COUNT = 3 };
 int run_for(const mpm_ctx* c, int k) { return c->run_tuned[k] > 0 ? c->run_tuned[k] : xcd_run(c->nctile); }
+
+// Whether the energy evaluation caches a Hessian linearization (surface F_r, solid cof F_p).
+template <typename R>
+bool lin_cache(const Dev<R>& d) { return (d.term_mask & 2) || d.solids; }
 
 TileLists tiles(mpm_ctx* c, int k = TUNE_ENERGY) {
   TileLists t;
@@ -496,6 +511,7 @@ void do_p2g(mpm_ctx* c, const mpm_particles* P, const mpm_surface* S, hipStream_
   if (ns > 0 && (!S->s || !S->dA)) throw ApiError{MPM_EINVAL, "null surface buffer"};
   if (ns > 0 && P->n == 0) throw ApiError{MPM_EINVAL, "surface samples without particles"};
   Dev<R>& d = dev<R>(c);
+  if (d.solids && P->n > 0 && !P->F) throw ApiError{MPM_EINVAL, "particles need F when T_melt is set"};
   c->np = (int)P->n;
   c->ns = (int)ns;
   d.np = c->np;
@@ -511,7 +527,7 @@ void do_p2g(mpm_ctx* c, const mpm_particles* P, const mpm_surface* S, hipStream_
   if (c->np > 0)
     LAUNCH(c, MPM_K_SETUP, (k_gather_particles<D, R>), dim3(cdiv(c->np, 256)), dim3(256), 0, s, d, (const R*)P->x,
                        (const R*)P->v, (const R*)P->A, (const R*)P->J, (const R*)P->V0, (const R*)P->m,
-                       (const R*)P->T, (const R*)P->gradT);
+                       (const R*)P->T, (const R*)P->gradT, (const R*)P->F);
   aux_join(c, s, c->ev_sjoin);
   // A1: parents, split masses, balance points, groups
   if (c->ns > 0)
@@ -605,9 +621,14 @@ void do_energy_grad(mpm_ctx* c, const R* u, R* g, double* energy_dev, int red_sl
                     PUpd<R> pu = PUpd<R>{}, const R* slope_g = nullptr, R* fout = nullptr) {
   Dev<R>& d = dev<R>(c);
   TileLists tl = tiles(c);
-  if (c->nctile > 0)
-    LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_ENERGY>), dim3(tile_grid(c)), dim3(TileGeo<D>::NT), 0, s, d, tl,
-           u, (R*)c->tpart, 0, (const int*)nullptr, 2, pu, fout);
+  if (c->nctile > 0) {
+    if (d.solids)
+      LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_ENERGY, true>), dim3(tile_grid(c)), dim3(TileGeo<D>::NT), 0, s,
+             d, tl, u, (R*)c->tpart, 0, (const int*)nullptr, 2, pu, fout);
+    else
+      LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_ENERGY>), dim3(tile_grid(c)), dim3(TileGeo<D>::NT), 0, s, d,
+             tl, u, (R*)c->tpart, 0, (const int*)nullptr, 2, pu, fout);
+  }
   if (c->ntiles > 0) {
     LAUNCH(c, MPM_K_ENERGY_NODE, (k_merge_stress<D, R>), dim3(merge_blocks(c)), dim3(64 * kMergeTiles), 0, s, d, tl,
            c->ntiles, (const R*)c->tpart, u, g, (int)NM_GRAD, 0.0, 0, (const int*)nullptr,
@@ -625,6 +646,8 @@ void do_surface_lin(mpm_ctx* c, const R* vlin, hipStream_t s) {
   Dev<R>& d = dev<R>(c);
   if (c->ns > 0 && (d.term_mask & 2))
     LAUNCH(c, MPM_K_HESS_SURF, (k_surface_F<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d, vlin);
+  if (d.solids && c->np > 0)
+    LAUNCH(c, MPM_K_HESS_SURF, (k_solid_lin<D, R>), dim3(cdiv(c->np, 256)), dim3(256), 0, s, d, vlin);
 }
 
 // out = P(alpha M P w + H P w) with the surface term linearized at the cached F_r.  With cg
@@ -638,9 +661,14 @@ void do_hessvec(mpm_ctx* c, const R* w, double alpha, R* out, bool mask_in, cons
   TileLists tl = tiles(c, TUNE_HESS);
   Dev<R> dh = d;
   if (f_lin) dh.sF = f_lin;
-  if (c->nctile > 0)
-    LAUNCH(c, MPM_K_HESS_INT, (k_tile_stress<D, R, TM_HESS>), dim3(tile_grid(c, TUNE_HESS)), dim3(TileGeo<D>::NT), 0, s, dh, tl,
-           w, (R*)c->tpart, (int)mask_in, done, -1, pu, (R*)nullptr);
+  if (c->nctile > 0) {
+    if (d.solids)
+      LAUNCH(c, MPM_K_HESS_INT, (k_tile_stress<D, R, TM_HESS, true>), dim3(tile_grid(c, TUNE_HESS)), dim3(TileGeo<D>::NT),
+             0, s, dh, tl, w, (R*)c->tpart, (int)mask_in, done, -1, pu, (R*)nullptr);
+    else
+      LAUNCH(c, MPM_K_HESS_INT, (k_tile_stress<D, R, TM_HESS>), dim3(tile_grid(c, TUNE_HESS)), dim3(TileGeo<D>::NT), 0,
+             s, dh, tl, w, (R*)c->tpart, (int)mask_in, done, -1, pu, (R*)nullptr);
+  }
   if (c->ntiles > 0)
     LAUNCH(c, MPM_K_HESS_NODE, (k_merge_stress<D, R>), dim3(merge_blocks(c)), dim3(64 * kMergeTiles), 0, s, d, tl, c->ntiles,
            (const R*)c->tpart,
@@ -653,9 +681,14 @@ template <int D, typename R>
 void do_hessvec_force(mpm_ctx* c, const R* u, R* out, hipStream_t s) {
   Dev<R>& d = dev<R>(c);
   TileLists tl = tiles(c);
-  if (c->nctile > 0)
-    LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_FORCE>), dim3(tile_grid(c)), dim3(TileGeo<D>::NT), 0, s, d, tl,
-           u, (R*)c->tpart, 0, (const int*)nullptr, -1, PUpd<R>{}, (R*)nullptr);
+  if (c->nctile > 0) {
+    if (d.solids)
+      LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_FORCE, true>), dim3(tile_grid(c)), dim3(TileGeo<D>::NT), 0, s,
+             d, tl, u, (R*)c->tpart, 0, (const int*)nullptr, -1, PUpd<R>{}, (R*)nullptr);
+    else
+      LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_FORCE>), dim3(tile_grid(c)), dim3(TileGeo<D>::NT), 0, s, d,
+             tl, u, (R*)c->tpart, 0, (const int*)nullptr, -1, PUpd<R>{}, (R*)nullptr);
+  }
   if (c->ntiles > 0)
     LAUNCH(c, MPM_K_ENERGY_NODE, (k_merge_stress<D, R>), dim3(merge_blocks(c)), dim3(64 * kMergeTiles), 0, s, d, tl, c->ntiles,
            (const R*)c->tpart,
@@ -687,7 +720,8 @@ void do_g2p(mpm_ctx* c, const R* vh, const R* Th, mpm_particles* P, hipStream_t 
   if (c->ns > 0) LAUNCH(c, MPM_K_G2P_SPLIT, (k_g2p_split<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d, vh);
   if (c->nctile > 0)
     LAUNCH(c, MPM_K_G2P, (k_tile_g2p<D, R>), dim3(c->nctile), dim3(256), 0, s, d, tiles(c), vh, Th,
-           (R*)P->x, (R*)P->v, (R*)P->A, (R*)P->J, (R*)P->V0, (R*)P->m, (R*)P->T, (R*)P->gradT);
+           (R*)P->x, (R*)P->v, (R*)P->A, (R*)P->J, (R*)P->V0, (R*)P->m, (R*)P->T, (R*)P->gradT,
+           d.solids ? (R*)P->F : (R*)nullptr);
 }
 
 // a . b over the active nodes into scal[slot] (asynchronous).  heat: use the heat solve's
@@ -882,7 +916,7 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
          (const R*)d.gvn, vhat);
   // the start's energy evaluation also caches the surface linearization F_r at v^; each
   // trial's goes to sF_alt, which becomes the cache when the trial is accepted
-  do_energy_grad<D, R>(c, vhat, g, nullptr, SC_G0, s, PUpd<R>{}, nullptr, (d.term_mask & 2) ? d.sF : nullptr);
+  do_energy_grad<D, R>(c, vhat, g, nullptr, SC_G0, s, PUpd<R>{}, nullptr, lin_cache(d) ? d.sF : nullptr);
   bool fix = false;
   double msum = 0, floor_abs = 0, phi = 0, gn = 0, g0 = 0, fl32 = 0;
   auto start_values = [&] {   // from a read that covers the start's gradient merge
@@ -971,7 +1005,7 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
     auto trial_launch = [&](double a, bool first) {
       do_energy_grad<D, R>(c, (const R*)delta, (R*)c->gscratch, nullptr, SC_GT, s,
                            PUpd<R>{vtrial, (const R*)vhat, nullptr, (R)a}, (const R*)g,
-                           (d.term_mask & 2) ? (R*)c->sF_alt : nullptr);
+                           lin_cache(d) ? (R*)c->sF_alt : nullptr);
       if (p.momentum_fix) {
         const bool fuse = first && spec;
         LAUNCH(c, MPM_K_BLAS, (k_mom_fix<D, R>), dim3(nb), dim3(kNodeThreads), 0, s, tl, nelem, d.nn, (const uint8_t*)d.gfree,
@@ -990,7 +1024,7 @@ void do_solve_momentum(mpm_ctx* c, hipStream_t s) {
       LAUNCH(c, MPM_K_BLAS, k_newton_decide, dim3(1), dim3(1), 0, s, nd, kry_momentum(c, set ^ 1).cg);
     mirror_copy(c, s);
     if (spec) {
-      R* f_next = (d.term_mask & 2) ? (R*)c->sF_alt : nullptr;
+      R* f_next = lin_cache(d) ? (R*)c->sF_alt : nullptr;
       auto apply_next = [&](const R* pv, R* Apv, const int* done, CgScal* cg, PUpd<R> pu) {
         do_hessvec<D, R>(c, pv, 1.0, Apv, false, done, cg, s, pu, f_next);
       };
@@ -1141,7 +1175,7 @@ void do_solve_momentum_minres(mpm_ctx* c, hipStream_t s) {
   LAUNCH(c, MPM_K_BLAS, k_project_copy<R>, dim3(nb), dim3(256), 0, s, tl, nelem, d.nn, D, (const uint8_t*)d.gfree,
          (const R*)d.gvn, (R*)c->vhat);
   do_energy_grad<D, R>(c, (const R*)c->vhat, (R*)c->grad, nullptr, SC_G0, s, PUpd<R>{}, nullptr,
-                       (d.term_mask & 2) ? d.sF : nullptr);
+                       lin_cache(d) ? d.sF : nullptr);
   read_mirror(c, s);
   const bool fix = p.momentum_fix && !c->constrained;
   const double msum = c->hbuf[SC_G0 + 1 + D];
@@ -1170,7 +1204,7 @@ void do_solve_momentum_minres(mpm_ctx* c, hipStream_t s) {
     auto trial = [&](double a) {
       do_energy_grad<D, R>(c, (const R*)delta, (R*)c->gscratch, nullptr, SC_GT, s,
                            PUpd<R>{(R*)c->vtrial, (const R*)c->vhat, nullptr, (R)a}, (const R*)c->grad,
-                           (d.term_mask & 2) ? (R*)c->sF_alt : nullptr);
+                           lin_cache(d) ? (R*)c->sF_alt : nullptr);
       if (p.momentum_fix)
         LAUNCH(c, MPM_K_BLAS, (k_mom_fix<D, R>), dim3(nb), dim3(kNodeThreads), 0, s, tl, nelem, d.nn,
                (const uint8_t*)d.gfree, (const R*)d.gm, (const double*)(c->scal + SC_GT + 1), p.dt, p.gravity[0],
@@ -1553,6 +1587,8 @@ int mpm_ctx_set_params(mpm_ctx* ctx, const mpm_params* p) {
     check_params(p);
     if (p->dim != ctx->dim || p->n != ctx->n || (p->precision == MPM_FP64) != ctx->fp64)
       throw ApiError{MPM_EINVAL, "dim, n and precision are fixed per context"};
+    if (solids_on(*p) && !(ctx->fp64 ? ctx->d64.solids : ctx->d32.solids))
+      throw ApiError{MPM_EINVAL, "solids (T_melt) need a context created with them"};
     ctx->p = *p;
     if (ctx->fp64) fill_params(ctx->d64, *p, ctx->nt);
     else fill_params(ctx->d32, *p, ctx->nt);

@@ -540,6 +540,154 @@ MPM_DEV void lane_scatter_heat(const R* F, const R* W, R fn, int k0, int k1, con
 // cell-to-region reduction are never live together, so they share storage.  Keeping a
 // 9-wave block near 1/3 of the 160 KB lets three blocks (27 of the CU's 32 wave slots)
 // reside per CU.
+// ---- fixed-corotated solid (Section 3.2.1) ---------------------------------------------
+// F_p = (I + dt G) F^n_p with G the velocity gradient at the particle.
+template <int D, typename R>
+MPM_DEV void solid_F(const Dev<R>& d, int k, const R (&G)[D][D], R dt, R (&F)[D][D]) {
+  const int N = d.np;
+  R Fn[D][D];
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) Fn[a][b] = d.pF[(a * D + b) * N + k];
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      R acc = Fn[a][b];
+#pragma unroll
+      for (int c = 0; c < D; ++c) acc += dt * G[a][c] * Fn[c][b];
+      F[a][b] = acc;
+    }
+}
+
+template <int D, typename R>
+MPM_DEV R det_of(const R (&F)[D][D]) {
+  if constexpr (D == 2) {
+    return F[0][0] * F[1][1] - F[0][1] * F[1][0];
+  } else {
+    return F[0][0] * (F[1][1] * F[2][2] - F[1][2] * F[2][1]) - F[0][1] * (F[1][0] * F[2][2] - F[1][2] * F[2][0]) +
+           F[0][2] * (F[1][0] * F[2][1] - F[1][1] * F[2][0]);
+  }
+}
+
+// cof F = det(F) F^-T.
+template <int D, typename R>
+MPM_DEV void cofactor_of(const R (&F)[D][D], R (&C)[D][D]) {
+  if constexpr (D == 2) {
+    C[0][0] = F[1][1]; C[0][1] = -F[1][0];
+    C[1][0] = -F[0][1]; C[1][1] = F[0][0];
+  } else {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const int a1 = (a + 1) % 3, a2 = (a + 2) % 3, b1 = (b + 1) % 3, b2 = (b + 2) % 3;
+        C[a][b] = F[a1][b1] * F[a2][b2] - F[a1][b2] * F[a2][b1];
+      }
+  }
+}
+
+// Orthogonal polar factor R of F (det F > 0): 2D in closed form (the rotation by the
+// angle of (F00 + F11, F10 - F01)); 3D by Newton's iteration X <- (X + X^-T) / 2 from X = F,
+// which converges quadratically to R, ten steps (singular values within [1/100, 100]).
+template <int D, typename R>
+MPM_DEV void polar_R(const R (&F)[D][D], R (&Rm)[D][D]) {
+  if constexpr (D == 2) {
+    const R c = F[0][0] + F[1][1], s = F[1][0] - F[0][1];
+    const R h = R(1) / sqrt(c * c + s * s);
+    Rm[0][0] = c * h; Rm[0][1] = -s * h;
+    Rm[1][0] = s * h; Rm[1][1] = c * h;
+  } else {
+    R X[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) X[a][b] = F[a][b];
+    for (int it = 0; it < 10; ++it) {
+      R C[3][3];
+      cofactor_of<3, R>(X, C);
+      const R inv = R(1) / det_of<3, R>(X);
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) X[a][b] = R(0.5) * (X[a][b] + C[a][b] * inv);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) Rm[a][b] = X[a][b];
+  }
+}
+
+// The solid's stress-scatter matrix dt V0 P F^nT (energy and force modes: P the Piola
+// stress at F) or dt V0 dP F^nT (Hessian mode: dP = 2 mu dF + lambda (C : dF) C at the
+// cached C = cof F_lin, dF = dt G F^n).  Returns the energy V0 psi(F) in energy mode.
+template <int D, typename R, int MODE>
+MPM_DEV R solid_stress(const Dev<R>& d, int k, const R (&G)[D][D], R dt, R* fout, R (&Sq)[D][D]) {
+  const int N = d.np;
+  const R muV = d.pLh[k], lamV = d.pLh[N + k];
+  R Fn[D][D];
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) Fn[a][b] = d.pF[(a * D + b) * N + k];
+  R Pm[D][D];
+  R e = 0;
+  if constexpr (MODE == TM_HESS) {
+    const R* cache = d.sF + (size_t)D * D * d.ns;
+    R C[D][D], dF[D][D], cdf = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int b = 0; b < D; ++b) {
+        C[a][b] = cache[(a * D + b) * N + k];
+        R acc = 0;
+#pragma unroll
+        for (int c = 0; c < D; ++c) acc += G[a][c] * Fn[c][b];
+        dF[a][b] = dt * acc;
+        cdf += C[a][b] * dF[a][b];
+      }
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int b = 0; b < D; ++b) Pm[a][b] = R(2) * muV * dF[a][b] + lamV * cdf * C[a][b];
+  } else {
+    R F[D][D], Rm[D][D], C[D][D];
+    solid_F<D, R>(d, k, G, dt, F);
+    polar_R<D, R>(F, Rm);
+    cofactor_of<D, R>(F, C);
+    const R J = det_of<D, R>(F);
+    R fr2 = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int b = 0; b < D; ++b) {
+        const R df = F[a][b] - Rm[a][b];
+        fr2 += df * df;
+        Pm[a][b] = R(2) * muV * df + lamV * (J - R(1)) * C[a][b];
+      }
+    e = muV * fr2 + R(0.5) * lamV * (J - R(1)) * (J - R(1));
+    if (fout) {
+      R* cache = fout + (size_t)D * D * d.ns;
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = 0; b < D; ++b) cache[(a * D + b) * N + k] = C[a][b];
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      R acc = 0;
+#pragma unroll
+      for (int c = 0; c < D; ++c) acc += Pm[a][c] * Fn[b][c];
+      Sq[a][b] = dt * acc;
+    }
+  return e;
+}
+
 template <int D, typename R>
 struct StressLds {
   static constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
@@ -604,7 +752,7 @@ MPM_DEV void stress_fetch(const Dev<R>& d, int q, int ntot, int npi, int pb, int
   }
 }
 
-template <int D, typename R, int MODE>
+template <int D, typename R, int MODE, bool SOL = false>
 __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stress(Dev<R> d, TileLists tl, const R* u, R* tpart,
                                                                 int mask_in, const int* done, int energy_slot,
                                                                 PUpd<R> pu, R* fout) {
@@ -684,7 +832,13 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
       for (int a = 0; a < D; ++a)
 #pragma unroll
         for (int b = 0; b < D; ++b) Sq[a][b] = 0;
-      if (interior) {
+      if (SOL && interior && d.pSol[in.k] != R(0)) {
+        // a solid particle: the fixed-corotated term in place of pressure and viscosity
+        if (d.term_mask & 1) {
+          const R es = solid_stress<D, R, MODE>(d, in.k, G, dt, fout, Sq);
+          if (MODE == TM_ENERGY) e += (double)es;
+        }
+      } else if (interior) {
         R tr = 0;
 #pragma unroll
         for (int a = 0; a < D; ++a) tr += G[a][a];
@@ -809,6 +963,30 @@ __global__ void k_surface_F(Dev<R> d, const R* vlin) {
   for (int a = 0; a < D; ++a)
 #pragma unroll
     for (int b = 0; b < D; ++b) d.sF[(a * D + b) * S + r] = (a == b ? R(1) : R(0)) + d.dt * G[a][b];
+}
+
+// Linearization point of the solid particles: cof F_p of F_p = (I + dt grad v_lin(x_p)) F^n_p,
+// cached after the surface part.
+template <int D, typename R>
+__global__ void k_solid_lin(Dev<R> d, const R* vlin) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int N = d.np;
+  if (k >= N || d.pSol[k] == R(0)) return;
+  R x[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) x[a] = d.px[a * N + k];
+  Stencil<D, R> st; bool bad = false;
+  make_stencil<D, R>(x, d.n, d.fn, st, &bad);
+  R G[D][D];
+  gather_grad<D, R>(d, st, vlin, false, G);
+  R F[D][D], C[D][D];
+  solid_F<D, R>(d, k, G, d.dt, F);
+  cofactor_of<D, R>(F, C);
+  R* cache = d.sF + (size_t)D * D * d.ns;
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) cache[(a * D + b) * N + k] = C[a][b];
 }
 
 // ======================================================================================
@@ -1073,7 +1251,8 @@ MPM_DEV void p2g_group(const Dev<R>& d, const TileLists& tl, int ti, R* tpart, P
         R* H = P + 7 * D;                   // cJ, cV, cK, cR, cS
         if (type == 0) {
           R Jn = d.pJ[k], Vn = d.pVn[k];
-          H[0] = useJ ? dt * dt * d.lam * d.pV0[k] * Jn * Jn : R(0);
+          const bool solid = d.solids && d.pSol[k] != R(0);   // no fluid pressure in a solid
+          H[0] = useJ && !solid ? dt * dt * d.lam * d.pV0[k] * Jn * Jn : R(0);
           H[1] = useV ? dt * d.pmu[k] * Vn : R(0);
           H[2] = d.K * Vn;
           H[3] = 0;
@@ -1267,7 +1446,7 @@ struct G2PLds {
 
 template <int D, typename R>
 __global__ void __launch_bounds__(256) k_tile_g2p(Dev<R> d, TileLists tl, const R* vh, const R* Th, R* x, R* v,
-                                                  R* A, R* J, R* V0, R* m, R* T, R* gT) {
+                                                  R* A, R* J, R* V0, R* m, R* T, R* gT, R* Fout) {
   constexpr int NT = 256, RN = TileGeo<D>::RN;
   __shared__ G2PLds<D, R> sm;
   const int ct = tl.ctile_list[blockIdx.x];
@@ -1332,20 +1511,50 @@ __global__ void __launch_bounds__(256) k_tile_g2p(Dev<R> d, TileLists tl, const 
 #pragma unroll
       for (int b = 0; b < D; ++b) A[(a * D + b) * N + k] = cA * tt[a][b];
     }
-    J[k] = (R(1) + d.dt * div) * d.pJ[k];
+    R Jnew = (R(1) + d.dt * div) * d.pJ[k];
     V0[k] = d.pV0[k];
     m[k] = mp;
+    R Tnew;
     if (Th) {
       R GT[1][D], vT[1];
       region_grad<D, R, 1>(sm.T, lc, w, dw, GT, vT);
-      T[k] = vT[0];
+      Tnew = vT[0];
 #pragma unroll
       for (int a = 0; a < D; ++a) gT[a * N + k] = GT[0][a];
     } else {
-      T[k] = d.pT[k];
+      Tnew = d.pT[k];
 #pragma unroll
       for (int a = 0; a < D; ++a) gT[a * N + k] = d.pgT[a * N + k];
     }
+    T[k] = Tnew;
+    if (Fout) {
+      // solids: F <- (I + dt grad v^) F, J = det F; then the phase change at T_melt
+      // (melting: J = 1, F = I; freezing: F = I, J = 1), decided in FP64
+      R Fk[D][D];
+      const bool was = d.pSol[k] != R(0);
+      if (was) {
+        solid_F<D, R>(d, k, G, d.dt, Fk);
+        Jnew = det_of<D, R>(Fk);
+      } else {
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+          for (int b = 0; b < D; ++b) Fk[a][b] = d.pF[(a * D + b) * N + k];
+      }
+      const bool now = (double)Tnew < d.T_melt;
+      if (was != now) {
+        Jnew = R(1);
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+          for (int b = 0; b < D; ++b) Fk[a][b] = a == b ? R(1) : R(0);
+      }
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = 0; b < D; ++b) Fout[(a * D + b) * N + k] = Fk[a][b];
+    }
+    J[k] = Jnew;
   }
 }
 

@@ -32,8 +32,8 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_sizes_match_header_layout():
-    # 15 int32 then doubles (4 bytes padding), particles 8 + 8 pointers
-    assert C.sizeof(L.MpmParticles) == 8 + 8 * 8
+    # 16 int32 then doubles, particles 8 + 9 pointers (x ... gradT, F)
+    assert C.sizeof(L.MpmParticles) == 8 + 9 * 8
     assert C.sizeof(L.MpmSurface) == 8 + 3 * 8
     assert L.MpmParams.dx.offset == 64
 
