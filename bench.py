@@ -458,12 +458,15 @@ def cpu_baseline(n_energy, n_cg, n_heat):
 # Summaries of rocprofv3 output (host only): the kernel-trace table and the PMC traffic
 # per launch that profiles/ holds.
 # ---------------------------------------------------------------------------------------
-KERNEL_CLASS_OF = {"k_tile_stress<3, float, 1>": "hess_int", "k_tile_stress<3, double, 1>": "hess_int",
-                   "k_tile_stress<3, float, 0>": "energy_int", "k_tile_stress<3, double, 0>": "energy_int",
-                   "k_tile_heat<3, float>": "heat_pt", "k_tile_heat<3, double>": "heat_pt",
-                   "k_tile_p2g<3, float>": "p2g", "k_tile_p2g<3, double>": "p2g",
-                   "k_tile_g2p<3, float>": "g2p", "k_tile_g2p<3, double>": "g2p",
-                   "k_merge_heat<3, float>": "heat_node", "k_merge_heat<3, double>": "heat_node"}
+KERNEL_CLASS_OF = {}
+for _r in ("float", "double"):
+    for _sol in ("false", "true"):     # the fluid-only and the solid-phase instantiations
+        KERNEL_CLASS_OF[f"k_tile_stress<3, {_r}, 1, {_sol}>"] = "hess_int"
+        KERNEL_CLASS_OF[f"k_tile_stress<3, {_r}, 0, {_sol}>"] = "energy_int"
+        KERNEL_CLASS_OF[f"k_tile_g2p<3, {_r}, {_sol}>"] = "g2p"
+    KERNEL_CLASS_OF[f"k_tile_heat<3, {_r}>"] = "heat_pt"
+    KERNEL_CLASS_OF[f"k_tile_p2g<3, {_r}>"] = "p2g"
+    KERNEL_CLASS_OF[f"k_merge_heat<3, {_r}>"] = "heat_node"
 
 
 def _short(name):

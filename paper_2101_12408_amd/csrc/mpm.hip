@@ -719,9 +719,12 @@ void do_g2p(mpm_ctx* c, const R* vh, const R* Th, mpm_particles* P, hipStream_t 
   if (!P || P->n != c->np) throw ApiError{MPM_EINVAL, "g2p particle count differs from p2g"};
   if (c->ns > 0) LAUNCH(c, MPM_K_G2P_SPLIT, (k_g2p_split<D, R>), dim3(cdiv(c->ns, 256)), dim3(256), 0, s, d, vh);
   if (c->nctile > 0)
-    LAUNCH(c, MPM_K_G2P, (k_tile_g2p<D, R>), dim3(c->nctile), dim3(256), 0, s, d, tiles(c), vh, Th,
-           (R*)P->x, (R*)P->v, (R*)P->A, (R*)P->J, (R*)P->V0, (R*)P->m, (R*)P->T, (R*)P->gradT,
-           d.solids ? (R*)P->F : (R*)nullptr);
+    if (d.solids)
+      LAUNCH(c, MPM_K_G2P, (k_tile_g2p<D, R, true>), dim3(c->nctile), dim3(256), 0, s, d, tiles(c), vh, Th,
+             (R*)P->x, (R*)P->v, (R*)P->A, (R*)P->J, (R*)P->V0, (R*)P->m, (R*)P->T, (R*)P->gradT, (R*)P->F);
+    else
+      LAUNCH(c, MPM_K_G2P, (k_tile_g2p<D, R>), dim3(c->nctile), dim3(256), 0, s, d, tiles(c), vh, Th,
+             (R*)P->x, (R*)P->v, (R*)P->A, (R*)P->J, (R*)P->V0, (R*)P->m, (R*)P->T, (R*)P->gradT, (R*)nullptr);
 }
 
 // a . b over the active nodes into scal[slot] (asynchronous).  heat: use the heat solve's

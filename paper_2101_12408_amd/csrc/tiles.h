@@ -1444,7 +1444,7 @@ struct G2PLds {
   R T[RN];
 };
 
-template <int D, typename R>
+template <int D, typename R, bool SOL = false>
 __global__ void __launch_bounds__(256) k_tile_g2p(Dev<R> d, TileLists tl, const R* vh, const R* Th, R* x, R* v,
                                                   R* A, R* J, R* V0, R* m, R* T, R* gT, R* Fout) {
   constexpr int NT = 256, RN = TileGeo<D>::RN;
@@ -1527,7 +1527,7 @@ __global__ void __launch_bounds__(256) k_tile_g2p(Dev<R> d, TileLists tl, const 
       for (int a = 0; a < D; ++a) gT[a * N + k] = d.pgT[a * N + k];
     }
     T[k] = Tnew;
-    if (Fout) {
+    if (SOL && Fout) {
       // solids: F <- (I + dt grad v^) F, J = det F; then the phase change at T_melt
       // (melting: J = 1, F = I; freezing: F = I, J = 1), decided in FP64
       R Fk[D][D];
