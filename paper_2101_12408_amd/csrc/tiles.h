@@ -781,20 +781,22 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
   StressIn<D, R, MODE> in;
   if (t < CH) stress_fetch<D, R, MODE>(d, t, ntot, npi, pb, sb, visc, in);
   const R beta = pu.beta();
-  for (int rn = t; rn < RN; rn += NT) {
+  // one (node, component) per thread, component-major so that a wave reads one plane; the
+  // loads of u, z and the free flags are issued together (every grid node is a valid
+  // address) and the constraint mask is applied by selection after they return
+  for (int e2 = t; e2 < RN * D; e2 += NT) {
+    const int a = e2 / RN, rn = e2 - a * RN;
     int r[3];
     region_coords<D>(rn, r);
-    int gnode = region_node_global<D>(ct, r, d.n, d.nt);
-    uint8_t fr = (gnode >= 0 && mask_in) ? d.gfree[gnode] : 0xff;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      R val = R(0);
-      if (gnode >= 0 && ((fr >> a) & 1)) {
-        val = u[a * nn + gnode];
-        if (pu.z) val = cg_dir(pu.z[a * nn + gnode], beta, val);
-      }
-      sm.u[rn * D + a] = val;
+    const int gnode = region_node_global<D>(ct, r, d.n, d.nt);
+    R val = R(0);
+    if (gnode >= 0) {
+      const uint8_t fr = mask_in ? d.gfree[gnode] : 0xff;
+      R uv = u[a * nn + gnode];
+      if (pu.z) uv = cg_dir(pu.z[a * nn + gnode], beta, uv);
+      val = ((fr >> a) & 1) ? uv : R(0);
     }
+    sm.u[rn * D + a] = val;
   }
   int lcell, lk0, lk1;
   lane_map<D>(t, lcell, lk0, lk1);
