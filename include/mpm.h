@@ -391,8 +391,10 @@ int mpm_sample_surface_dev(mpm_ctx* ctx, const mpm_particles* P, double radius, 
  * aligned; the library allocates no device memory).  Requests are admitted strictly in
  * arrival order, each as soon as a worker is free and the arena holds its context
  * workspace, particle and surface buffers; a request larger than the whole arena
- * completes with MPM_EBUDGET.  A worker draws each step's surface samples on the host
- * (mpm_sample_surface), runs the steps with mpm_step, downloads the final particle state
+ * completes with MPM_EBUDGET.  A worker draws each step's surface samples on the device
+ * from the resident positions (mpm_sample_surface_dev; a request whose samples outgrow
+ * the first sizing, twice its particle count and at least 4096, runs again once sized
+ * by the count), runs the steps with mpm_step, downloads the final particle state
  * (in the request's particle order) and frees the memory.  Several admitted requests run
  * at once and their work overlaps on the device; each result is bitwise the same as
  * stepping the scene alone.  All entry points are host calls and thread-safe. */

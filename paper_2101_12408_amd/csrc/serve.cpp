@@ -2,11 +2,14 @@
 //
 // A request carries a scene (parameters and the host particle state) and a number of
 // implicit steps.  Worker threads, each with its own non-blocking stream, take requests
-// in arrival order.  A worker draws the first step's surface samples on the host (their
-// count sizes the request's memory), then waits for its admission turn: requests are
-// admitted strictly in arrival order, each once the device arena (caller-allocated HBM)
-// has room for its context workspace and buffers.  Later steps draw their samples on the
-// device from the resident positions (mpm_sample_surface_dev).
+// in arrival order.  A worker sizes the request's memory (the surface buffers for up to
+// twice as many samples as particles, at least 4096), then waits for its admission turn:
+// requests are admitted strictly in arrival order, each once the device arena
+// (caller-allocated HBM) has room for its context workspace and buffers.  Every step draws
+// its surface samples on the device from the resident positions (mpm_sample_surface_dev;
+// FP32 positions in MIXED).
+// A request whose samples outgrow that size releases its memory and goes back to the
+// front of the queue once, sized by the count it found.
 // It uploads the state, runs the steps through mpm_step, downloads the result and frees
 // its memory.  Up to max_concurrent requests are on the device at once, on separate
 // streams, so a request that arrives while others run starts as soon as a worker and
@@ -82,20 +85,18 @@ class Arena {
   std::map<size_t, size_t> free_;
 };
 
-struct HostSurface {
-  std::vector<double> s, dA;
-  std::vector<int32_t> label;
-  int64_t n = 0;
-};
-
 struct Request {
   mpm_request r{};
   const double* src[8] = {};     // input state: the caller's arrays (borrow) or f
   std::vector<double> f[8];      // x v A J V0 m T gradT, [comp][n] double: input copy, then result
   std::vector<int64_t> orig;     // request-order index of each device slot
   mpm_completion c{};
-  HostSurface surf;
+  int64_t cap_hint = 0;          // surface capacity after an overflow (0: the size rule)
+  bool requeued = false;
 };
+
+// run_request's status for a request whose samples exceeded its surface buffers.
+constexpr int kResize = -1;
 
 struct Worker {
   hipStream_t stream = nullptr;
@@ -134,30 +135,6 @@ int components(int field, int dim) {
   }
 }
 
-bool sample(const Request& q, const double* x, int64_t n, uint64_t step, HostSurface& out) {
-  const mpm_params& p = q.r.params;
-  int64_t cap = std::max<int64_t>(out.n > 0 ? out.n + out.n / 2 + 1024 : 2 * n + 4096, 1024);
-  for (int attempt = 0; attempt < 3; ++attempt) {
-    out.s.resize((size_t)cap * p.dim);
-    out.dA.resize((size_t)cap * p.dim);
-    out.label.resize((size_t)cap);
-    int64_t cnt = 0;
-    int rc = mpm_sample_surface(p.dim, p.n, x, n, q.r.ls_radius, q.r.sample_density, q.r.seed, step, q.r.label_lo,
-                                q.r.label_hi, out.s.data(), out.dA.data(), out.label.data(), cap, &cnt);
-    if (rc != MPM_OK) return false;
-    if (cnt <= cap) {
-      // compact [dim][cap] to [dim][cnt]
-      for (int a = 1; a < p.dim; ++a) {
-        std::memmove(out.s.data() + a * cnt, out.s.data() + a * cap, cnt * sizeof(double));
-        std::memmove(out.dA.data() + a * cnt, out.dA.data() + a * cap, cnt * sizeof(double));
-      }
-      out.n = cnt;
-      return true;
-    }
-    cap = cnt;
-  }
-  return false;
-}
 
 void ensure_stage(Worker& w, size_t bytes) {
   if (w.stage_bytes >= bytes) return;
@@ -238,22 +215,17 @@ int run_request(mpm_server* srv, Worker& w, Request& q, char* mem, size_t ws_byt
   mpm_particles P{N, pf[0], pf[1], pf[2], pf[3], pf[4], pf[5], pf[6], pf[7]};
   for (int st = 0; st < q.r.n_steps && rc == MPM_OK; ++st) {
     int64_t S = 0;
-    if (st == 0) {
-      // the first step's samples were drawn on the host to size the request
-      if (q.surf.n > cap_surf) { rc = MPM_ENOMEM; break; }
-      S = q.surf.n;
-      if (!upload(w, ds, q.surf.s.data(), (size_t)dim * S, fp64) ||
-          !upload(w, ddA, q.surf.dA.data(), (size_t)dim * S, fp64) ||
-          (S && hipMemcpyAsync(dlab, q.surf.label.data(), S * 4, hipMemcpyHostToDevice, w.stream) != hipSuccess)) {
-        rc = MPM_EHIP;
-        break;
+    rc = mpm_sample_surface_dev(ctx, &P, q.r.ls_radius, q.r.sample_density, q.r.seed, q.r.first_step + st,
+                                q.r.label_lo, q.r.label_hi, ds, ddA, dlab, cap_surf, &S, w.stream);
+    if (rc != MPM_OK) break;
+    if (S > cap_surf) {
+      if (st == 0 && !q.requeued) {
+        q.cap_hint = S + S / 2 + 1024;
+        rc = kResize;
+      } else {
+        rc = MPM_ENOMEM;
       }
-    } else {
-      // later steps: the device sampler, on the resident positions
-      rc = mpm_sample_surface_dev(ctx, &P, q.r.ls_radius, q.r.sample_density, q.r.seed, q.r.first_step + st,
-                                  q.r.label_lo, q.r.label_hi, ds, ddA, dlab, cap_surf, &S, w.stream);
-      if (rc != MPM_OK) break;
-      if (S > cap_surf) { rc = MPM_ENOMEM; break; }
+      break;
     }
     mpm_surface Sd{S, ds, ddA, dlab};
     mpm_ctx* cs[1] = {ctx};
@@ -324,14 +296,15 @@ void worker_main(mpm_server* srv) {
       ticket = srv->next_ticket++;
       srv->picked++;
     }
-    // the first step's samples (host input stage), then the exact memory need
+    // the memory need: the surface buffers hold twice as many samples as particles (a
+    // droplet at 8 per cell has 3 dx / R samples per particle), or the count an earlier
+    // attempt found
     const mpm_params& p = q->r.params;
     const int dim = p.dim;
     const int64_t N = q->r.n_part;
-    bool ok = sample(*q, q->src[0], N, q->r.first_step, q->surf);
-    const int64_t cap_surf = std::max<int64_t>(1, q->surf.n + q->surf.n / 2 + 1024);
+    const int64_t cap_surf = q->cap_hint > 0 ? q->cap_hint : std::max<int64_t>(4096, 2 * N);
     size_t ws_bytes = 0;
-    int rc = ok ? mpm_workspace_bytes(&p, N, cap_surf, &ws_bytes) : MPM_EINVAL;
+    int rc = mpm_workspace_bytes(&p, N, cap_surf, &ws_bytes);
     const size_t R = p.precision == MPM_FP64 ? 8 : 4;
     size_t need = align_up(ws_bytes);
     for (int k = 0; k < 8; ++k) need += align_up((size_t)components(k, dim) * N * R);
@@ -361,7 +334,16 @@ void worker_main(mpm_server* srv) {
       std::lock_guard<std::mutex> lk(srv->mu);
       srv->alloc.release(off, need);
       srv->running--;
-      finish(srv, q, rc);
+      if (rc == kResize) {
+        // once more, first in line, with surface buffers for the count it found
+        q->requeued = true;
+        q->c.steps_done = 0;
+        q->c.newton_iters = q->c.cg_iters = 0;
+        srv->queue.push_front(q);
+        srv->picked--;
+      } else {
+        finish(srv, q, rc);
+      }
     }
     srv->cv.notify_all();
   }
@@ -463,8 +445,10 @@ int mpm_server_result(mpm_server* srv, int64_t id, double* x, double* v, double*
   const int dim = q->r.params.dim;
   const size_t N = (size_t)q->r.n_part;
   double* dst[8] = {x, v, A, J, nullptr, nullptr, T, gradT};
+  // a request that failed (or borrowed its arrays and kept no result) has no state to copy
   for (int k = 0; k < 8; ++k)
-    if (dst[k]) std::memcpy(dst[k], q->f[k].data(), (size_t)components(k, dim) * N * sizeof(double));
+    if (dst[k] && q->f[k].size() == (size_t)components(k, dim) * N)
+      std::memcpy(dst[k], q->f[k].data(), q->f[k].size() * sizeof(double));
   const int status = q->c.status;
   delete q;
   return status;

@@ -1,6 +1,7 @@
 // Serving stream through the serving runtime with the host stand-ins: 8 workers, droplets
-// on n in {16, 32, 48, 64}, every request borrowing its host arrays, results checked
-// against the reversal the stand-in step applies (twice per two steps).
+// on n in {16, 32, 48, 64} and every tenth request a sparse cloud that outgrows its first
+// surface sizing, every request borrowing its host arrays, results checked against the
+// reversal the stand-in step applies (twice per two steps).
 #include <cmath>
 #include <cstdio>
 #include <random>
@@ -20,12 +21,19 @@ int main(int argc, char** argv) {
   for (int r = 0; r < nreq; ++r) {
     const int n = sizes[rng() % 4]; const double dx = 1.0 / n, rad = 0.24;
     std::vector<double> pts;
-    for (int k = 0; k < n; ++k) for (int j = 0; j < n; ++j) for (int i = 0; i < n; ++i)
-      for (int s = 0; s < 8; ++s) {
-        double x[3] = {(i + 0.25 + 0.5 * (s & 1)) * dx, (j + 0.25 + 0.5 * ((s >> 1) & 1)) * dx, (k + 0.25 + 0.5 * (s >> 2)) * dx};
-        double d2 = 0; for (double t : x) d2 += (t - 0.5) * (t - 0.5);
-        if (d2 < rad * rad) pts.insert(pts.end(), x, x + 3);
-      }
+    if (r % 10 == 7) {
+      // a sparse cloud: every particle its own sphere, far more samples than particles,
+      // so the request outgrows its first sizing and is queued again
+      std::uniform_real_distribution<double> u(0.2, 0.8);
+      for (int p = 0; p < 150; ++p) { double x[3] = {u(rng), u(rng), u(rng)}; pts.insert(pts.end(), x, x + 3); }
+    } else {
+      for (int k = 0; k < n; ++k) for (int j = 0; j < n; ++j) for (int i = 0; i < n; ++i)
+        for (int s = 0; s < 8; ++s) {
+          double x[3] = {(i + 0.25 + 0.5 * (s & 1)) * dx, (j + 0.25 + 0.5 * ((s >> 1) & 1)) * dx, (k + 0.25 + 0.5 * (s >> 2)) * dx};
+          double d2 = 0; for (double t : x) d2 += (t - 0.5) * (t - 0.5);
+          if (d2 < rad * rad) pts.insert(pts.end(), x, x + 3);
+        }
+    }
     Host& h = hs[r]; h.N = (int64_t)pts.size() / 3; h.steps = 1 + (int)(rng() % 2);
     const int nc[8] = {3, 3, 9, 1, 1, 1, 1, 3};
     for (int q = 0; q < 8; ++q) h.f[q].assign((size_t)nc[q] * h.N, 0.0);

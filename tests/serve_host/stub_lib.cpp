@@ -51,11 +51,16 @@ int mpm_sample_surface_dev(mpm_ctx* c, const mpm_particles* P, double radius, do
   std::vector<double> x((size_t)dim * N);
   for (size_t i = 0; i < x.size(); ++i) x[i] = f64 ? ((const double*)P->x)[i] : ((const float*)P->x)[i];
   int64_t hcap = 4 * N + 4096, cnt = 0;
-  std::vector<double> hs((size_t)dim * hcap), hdA((size_t)dim * hcap);
-  std::vector<int32_t> hl(hcap);
-  int rc = mpm_sample_surface(dim, c->p.n, x.data(), N, radius, density, seed, step, lo, hi, hs.data(), hdA.data(),
-                              hl.data(), hcap, &cnt);
-  if (rc != MPM_OK || cnt > hcap) return rc != MPM_OK ? rc : MPM_ENOMEM;
+  std::vector<double> hs, hdA;
+  std::vector<int32_t> hl;
+  for (;;) {
+    hs.assign((size_t)dim * hcap, 0.0); hdA.assign((size_t)dim * hcap, 0.0); hl.assign(hcap, 0);
+    int rc = mpm_sample_surface(dim, c->p.n, x.data(), N, radius, density, seed, step, lo, hi, hs.data(), hdA.data(),
+                                hl.data(), hcap, &cnt);
+    if (rc != MPM_OK) return rc;
+    if (cnt <= hcap) break;
+    hcap = cnt;
+  }
   *out_n = cnt;
   if (cnt > cap) return MPM_OK;
   for (int a = 0; a < dim; ++a)

@@ -61,7 +61,8 @@ def test_server_matches_direct_step():
     srv = api.Server(2 << 30, max_concurrent=2)
     got, _ = _run(srv, [S], 1)
     srv.close()
-    surf = api.sample_surface(P["x"], p, step=0)
+    # the server samples every step from the resident positions, FP32 in MIXED
+    surf = api.sample_surface(P["x"].astype(np.float32).astype(np.float64), p, step=0)
     s = api.Scene(p, cap_part=len(P["m"]), cap_surf=len(surf["s"]), precision="mixed")
     Pd, Sd = s.to_device(P, surf)
     s.step(Pd, Sd)
@@ -97,3 +98,31 @@ def test_admission_budget_queues_and_rejects():
     srv.close()
     assert comps[99]["status"] == L.MPM_EBUDGET
     assert comps[100]["status"] == L.MPM_OK
+
+
+def test_request_outgrowing_its_surface_sizing_runs_again():
+    """A sparse cloud (every particle its own sphere: about 75 samples per particle) has
+    more samples than the first sizing gives (twice the particles, at least 4096); the
+    request releases its memory, runs again sized by the count, and equals the direct
+    step."""
+    from paper_2101_12408_amd import _lib as L
+    from paper_2101_12408_amd import api
+    rng = np.random.default_rng(3)
+    p = sc.make_params(dim=3, n=32, dt=5e-4, bulk=1e4, g0=0.05, seed=9)
+    x = rng.uniform(0.25, 0.75, size=(150, 3))
+    P = sc.particles_from_positions(x, 3, p["dx"])
+    S = dict(params=p, particles=P)
+    surf = api.sample_surface(P["x"].astype(np.float32).astype(np.float64), p, step=0)
+    assert len(surf["s"]) > 4096
+    srv = api.Server(2 << 30, max_concurrent=2)
+    got, comps = _run(srv, [S], 1)
+    srv.close()
+    assert comps[0]["n_surf"] == len(surf["s"])
+    s = api.Scene(p, cap_part=len(P["m"]), cap_surf=len(surf["s"]), precision="mixed")
+    Pd, Sd = s.to_device(P, surf)
+    s.step(Pd, Sd)
+    perm = s.view(L.F_PERM).cpu().numpy()
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(len(perm))
+    for k, ref in (("x", Pd["x"].cpu().numpy().T[inv]), ("v", Pd["v"].cpu().numpy().T[inv])):
+        assert np.array_equal(got[0][k].astype(np.float32), ref), k
