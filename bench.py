@@ -156,6 +156,7 @@ def summary(r, steps):
                 surface_samples=r["S"], newton_iters_per_step=per_step(st, "newton_iters"),
                 cg_iters_per_step=per_step(st, "cg_iters"), heat_iters_per_step=per_step(st, "heat_iters"),
                 hessvec_per_s=round(sum(s["hessvecs"] for s in st) / r["elapsed"], 1),
+                host_waits_per_step=per_step(st, "host_waits"),
                 converged=[int(s["converged"]) for s in st][:3] + (["..."] if len(st) > 3 else []))
 
 
@@ -689,6 +690,7 @@ def main():
         "newton_iters_per_step": per_step(st, "newton_iters"),
         "cg_iters_per_step": per_step(st, "cg_iters"),
         "heat_iters_per_step": per_step(st, "heat_iters"),
+        "host_waits_per_step": per_step(st, "host_waits"),
         "all_in": dict(value=round(all_in, 1), unit="particle-steps/s",
                        ms_per_step=round(1e3 * main_run["elapsed_all_in"] / K, 3),
                        sampling_ms_per_step=round(1e3 * (main_run["elapsed_all_in"] - main_run["elapsed"]) / K, 3),

@@ -171,6 +171,8 @@ typedef struct mpm_stats {
                              an implicit mpm_step, set by the next mpm_scene_status      */
   int64_t n_part, n_surf, n_dof, n_tiles;
   double dt;              /* the time step of the last step                           */
+  int64_t host_waits;     /* blocking host waits on the device since the last mpm_step
+                             began (reads of counts and solver scalars)                  */
 } mpm_stats;
 
 /* Grid fields readable through mpm_grid_view (device pointers into the workspace). */

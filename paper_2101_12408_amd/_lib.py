@@ -47,7 +47,7 @@ class MpmStats(C.Structure):
         "converged", "status")] + [
         ("g0", C.c_double), ("gnorm", C.c_double), ("phi", C.c_double), ("heat_res", C.c_double),
         ("momentum", C.c_double * 3), ("n_part", C.c_int64), ("n_surf", C.c_int64), ("n_dof", C.c_int64),
-        ("n_tiles", C.c_int64), ("dt", C.c_double)]
+        ("n_tiles", C.c_int64), ("dt", C.c_double), ("host_waits", C.c_int64)]
 
 
 class MpmTuning(C.Structure):

@@ -440,6 +440,7 @@ int merge_blocks(const mpm_ctx* c) { return cdiv(c->ntiles, kMergeTiles); }
 void sync_read(mpm_ctx* c, hipStream_t s, const void* src, void* dst, size_t bytes) {
   HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  c->stats.host_waits++;
 }
 
 // The second stream of a context, ordered after the work queued so far on s (the
@@ -473,6 +474,7 @@ void host_mark(mpm_ctx* c, hipStream_t s, hipEvent_t* ev) {
 void host_wait(mpm_ctx* c, hipStream_t s, hipEvent_t ev) {
   if (c->single) HIPCHK(hipStreamSynchronize(s));
   else HIPCHK(hipEventSynchronize(ev));
+  c->stats.host_waits++;
 }
 
 // The second stream's share of the binning (on stream s): clears the previous step's
@@ -580,7 +582,9 @@ void do_p2g(mpm_ctx* c, const mpm_particles* P, const mpm_surface* S, hipStream_
     LAUNCH(c, MPM_K_SETUP, (k_dof_flags<D>), dim3(std::min(128, cdiv(c->ntiles, 4))), dim3(256), 0, s,
            (const int*)d.tile_list, c->ntiles * 64, (const uint8_t*)d.gfree, c->misc);
   c->have_p2g = true;
+  const int64_t waits = c->stats.host_waits;   // counted since the step began
   c->stats = mpm_stats{};
+  c->stats.host_waits = waits;
   c->stats.n_part = c->np;
   c->stats.n_surf = c->ns;
   c->stats.n_tiles = c->ntiles;
@@ -752,6 +756,7 @@ void mom_sums_async(mpm_ctx* c, const R* vh, hipStream_t s) {
 void read_mirror(mpm_ctx* c, hipStream_t s) {
   HIPCHK(hipMemcpyAsync(c->hmirror, (const char*)c->scal, kMirrorRead, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  c->stats.host_waits++;
   c->status |= c->hint[0];
   c->constrained = c->hint[1] != 0;
   c->stats.n_dof = c->hint[2];
@@ -817,6 +822,7 @@ void kry_read(mpm_ctx* c, const KrySet& k, hipStream_t s) {
   }
   kry_copy(c, k, s);
   HIPCHK(hipStreamSynchronize(s));
+  c->stats.host_waits++;
 }
 
 // First chunk of a solve: the iteration count of the previous solve of the same kind
@@ -1848,6 +1854,7 @@ void choose_dt(mpm_ctx* c, const mpm_particles* P, int implicit, hipStream_t s) 
 }
 
 int step_one(mpm_ctx* c, mpm_particles* P, const mpm_surface* S, int implicit, hipStream_t s) {
+  c->stats.host_waits = 0;
   if (c->p.cfl > 0) {
     const int rc0 = guarded(c, [&] { choose_dt(c, P, implicit, s); });
     if (rc0 != MPM_OK) return rc0;
