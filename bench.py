@@ -465,9 +465,10 @@ def cpu_baseline(n_energy, n_cg, n_heat):
 # ---------------------------------------------------------------------------------------
 KERNEL_CLASS_OF = {}
 for _r in ("float", "double"):
-    for _sol in ("false", "true"):     # the fluid-only and the solid-phase instantiations
-        KERNEL_CLASS_OF[f"k_tile_stress<3, {_r}, 1, {_sol}>"] = "hess_int"
-        KERNEL_CLASS_OF[f"k_tile_stress<3, {_r}, 0, {_sol}>"] = "energy_int"
+    for _var in ("0", "1", "2"):       # the fluid, solid-phase and J-term-only instantiations
+        KERNEL_CLASS_OF[f"k_tile_stress<3, {_r}, 1, {_var}>"] = "hess_int"
+        KERNEL_CLASS_OF[f"k_tile_stress<3, {_r}, 0, {_var}>"] = "energy_int"
+    for _sol in ("false", "true"):
         KERNEL_CLASS_OF[f"k_tile_g2p<3, {_r}, {_sol}>"] = "g2p"
     KERNEL_CLASS_OF[f"k_tile_heat<3, {_r}>"] = "heat_pt"
     KERNEL_CLASS_OF[f"k_tile_p2g<3, {_r}>"] = "p2g"

@@ -421,6 +421,14 @@ int run_for(const mpm_ctx* c, int k) { return c->run_tuned[k] > 0 ? c->run_tuned
 template <typename R>
 bool lin_cache(const Dev<R>& d) { return (d.term_mask & 2) || d.solids; }
 
+// The stress kernel variant of a scene: with solids; the J term alone (no viscosity: the
+// viscous term off, or mu0 = 0); else the full fluid.
+template <typename R>
+int stress_var(const Dev<R>& d) {
+  if (d.solids) return SV_SOLID;
+  return ((d.term_mask & 4) == 0 || d.mu0 == R(0)) ? SV_JONLY : SV_FLUID;
+}
+
 TileLists tiles(mpm_ctx* c, int k = TUNE_ENERGY) {
   TileLists t;
   t.ctile_list = c->ctile_list;
@@ -626,9 +634,13 @@ void do_energy_grad(mpm_ctx* c, const R* u, R* g, double* energy_dev, int red_sl
   Dev<R>& d = dev<R>(c);
   TileLists tl = tiles(c);
   if (c->nctile > 0) {
-    if (d.solids)
-      LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_ENERGY, true>), dim3(tile_grid(c)), dim3(TileGeo<D>::NT), 0, s,
-             d, tl, u, (R*)c->tpart, 0, (const int*)nullptr, 2, pu, fout);
+    const int var = stress_var(d);
+    if (var == SV_SOLID)
+      LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_ENERGY, SV_SOLID>), dim3(tile_grid(c)), dim3(TileGeo<D>::NT), 0,
+             s, d, tl, u, (R*)c->tpart, 0, (const int*)nullptr, 2, pu, fout);
+    else if (var == SV_JONLY)
+      LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_ENERGY, SV_JONLY>), dim3(tile_grid(c)), dim3(TileGeo<D>::NT), 0,
+             s, d, tl, u, (R*)c->tpart, 0, (const int*)nullptr, 2, pu, fout);
     else
       LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_ENERGY>), dim3(tile_grid(c)), dim3(TileGeo<D>::NT), 0, s, d,
              tl, u, (R*)c->tpart, 0, (const int*)nullptr, 2, pu, fout);
@@ -666,9 +678,13 @@ void do_hessvec(mpm_ctx* c, const R* w, double alpha, R* out, bool mask_in, cons
   Dev<R> dh = d;
   if (f_lin) dh.sF = f_lin;
   if (c->nctile > 0) {
-    if (d.solids)
-      LAUNCH(c, MPM_K_HESS_INT, (k_tile_stress<D, R, TM_HESS, true>), dim3(tile_grid(c, TUNE_HESS)), dim3(TileGeo<D>::NT),
-             0, s, dh, tl, w, (R*)c->tpart, (int)mask_in, done, -1, pu, (R*)nullptr);
+    const int var = stress_var(d);
+    if (var == SV_SOLID)
+      LAUNCH(c, MPM_K_HESS_INT, (k_tile_stress<D, R, TM_HESS, SV_SOLID>), dim3(tile_grid(c, TUNE_HESS)),
+             dim3(TileGeo<D>::NT), 0, s, dh, tl, w, (R*)c->tpart, (int)mask_in, done, -1, pu, (R*)nullptr);
+    else if (var == SV_JONLY)
+      LAUNCH(c, MPM_K_HESS_INT, (k_tile_stress<D, R, TM_HESS, SV_JONLY>), dim3(tile_grid(c, TUNE_HESS)),
+             dim3(TileGeo<D>::NT), 0, s, dh, tl, w, (R*)c->tpart, (int)mask_in, done, -1, pu, (R*)nullptr);
     else
       LAUNCH(c, MPM_K_HESS_INT, (k_tile_stress<D, R, TM_HESS>), dim3(tile_grid(c, TUNE_HESS)), dim3(TileGeo<D>::NT), 0,
              s, dh, tl, w, (R*)c->tpart, (int)mask_in, done, -1, pu, (R*)nullptr);
@@ -687,8 +703,8 @@ void do_hessvec_force(mpm_ctx* c, const R* u, R* out, hipStream_t s) {
   TileLists tl = tiles(c);
   if (c->nctile > 0) {
     if (d.solids)
-      LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_FORCE, true>), dim3(tile_grid(c)), dim3(TileGeo<D>::NT), 0, s,
-             d, tl, u, (R*)c->tpart, 0, (const int*)nullptr, -1, PUpd<R>{}, (R*)nullptr);
+      LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_FORCE, SV_SOLID>), dim3(tile_grid(c)), dim3(TileGeo<D>::NT), 0,
+             s, d, tl, u, (R*)c->tpart, 0, (const int*)nullptr, -1, PUpd<R>{}, (R*)nullptr);
     else
       LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_FORCE>), dim3(tile_grid(c)), dim3(TileGeo<D>::NT), 0, s, d,
              tl, u, (R*)c->tpart, 0, (const int*)nullptr, -1, PUpd<R>{}, (R*)nullptr);

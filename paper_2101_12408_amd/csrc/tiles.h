@@ -430,6 +430,63 @@ MPM_DEV void region_grad(const R* u, const int* lc, const R (&w)[D][3], const R 
   }
 }
 
+// The trace of region_grad's G for NC = D (the divergence of u), from the diagonal entries
+// alone, each formed with region_grad's operations in its order, so the value is the same.
+template <int D, typename R>
+MPM_DEV R region_div(const R* u, const int* lc, const R (&w)[D][3], const R (&dw)[D][3]) {
+  constexpr int RE = TileGeo<D>::RE;
+  R Gd[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) Gd[a] = 0;
+  if constexpr (D == 3) {
+#pragma unroll
+    for (int k2 = 0; k2 < 3; ++k2) {
+      R A0 = 0, B1 = 0, C2 = 0;
+#pragma unroll
+      for (int k1 = 0; k1 < 3; ++k1) {
+        int base = lc[0] + RE * ((lc[1] + k1) + RE * (lc[2] + k2));
+        {
+          R u0 = u[(base + 0) * 3 + 0], u1 = u[(base + 1) * 3 + 0], u2 = u[(base + 2) * 3 + 0];
+          R sd = u0 * dw[0][0] + u1 * dw[0][1] + u2 * dw[0][2];
+          A0 += sd * w[1][k1];
+        }
+        {
+          R u0 = u[(base + 0) * 3 + 1], u1 = u[(base + 1) * 3 + 1], u2 = u[(base + 2) * 3 + 1];
+          R sv = u0 * w[0][0] + u1 * w[0][1] + u2 * w[0][2];
+          B1 += sv * dw[1][k1];
+        }
+        {
+          R u0 = u[(base + 0) * 3 + 2], u1 = u[(base + 1) * 3 + 2], u2 = u[(base + 2) * 3 + 2];
+          R sv = u0 * w[0][0] + u1 * w[0][1] + u2 * w[0][2];
+          C2 += sv * w[1][k1];
+        }
+      }
+      Gd[0] += A0 * w[2][k2];
+      Gd[1] += B1 * w[2][k2];
+      Gd[2] += C2 * dw[2][k2];
+    }
+  } else {
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) {
+      int base = lc[0] + RE * (lc[1] + k1);
+      {
+        R u0 = u[(base + 0) * 2 + 0], u1 = u[(base + 1) * 2 + 0], u2 = u[(base + 2) * 2 + 0];
+        R sd = u0 * dw[0][0] + u1 * dw[0][1] + u2 * dw[0][2];
+        Gd[0] += sd * w[1][k1];
+      }
+      {
+        R u0 = u[(base + 0) * 2 + 1], u1 = u[(base + 1) * 2 + 1], u2 = u[(base + 2) * 2 + 1];
+        R sv = u0 * w[0][0] + u1 * w[0][1] + u2 * w[0][2];
+        Gd[1] += sv * dw[1][k1];
+      }
+    }
+  }
+  R tr = 0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) tr += Gd[a];
+  return tr;
+}
+
 // Lane (cell, k0[, k1]) view of a point's weights: the weights and gradients of its 3
 // nodes k = 0..2 along the last axis.
 template <int D, typename R>
@@ -514,6 +571,33 @@ MPM_DEV void lane_scatter_grad(const R* F, const R* W, R fn, int k0, int k1, con
       const R wy = W[3 + k], dwy = bs_dw_fn<R>(k, F[1], fn);
 #pragma unroll
       for (int a = 0; a < 2; ++a) acc[k][a] = fma_r(dwy, Qa[a], fma_r(wy, Pa[a], acc[k][a]));
+    }
+  }
+}
+
+// lane_scatter_grad for S = s I (the J term alone): the same products and sums with the
+// zero entries of S left out.
+template <int D, typename R>
+MPM_DEV void lane_scatter_iso(const R* F, const R* W, R fn, int k0, int k1, const LaneDw<R>& d0, const LaneDw<R>& d1,
+                              R s, R (&acc)[3][D]) {
+  if constexpr (D == 3) {
+    const R wx = W[k0], dwx = d0(F[0], fn), wy = W[3 + k1], dwy = d1(F[1], fn);
+    const R P0 = (dwx * wy) * s, P1 = (wx * dwy) * s, Q2 = (wx * wy) * s;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const R wz = W[6 + k], dwz = bs_dw_fn<R>(k, F[2], fn);
+      acc[k][0] = fma_r(wz, P0, acc[k][0]);
+      acc[k][1] = fma_r(wz, P1, acc[k][1]);
+      acc[k][2] = fma_r(dwz, Q2, acc[k][2]);
+    }
+  } else {
+    const R wx = W[k0], dwx = d0(F[0], fn);
+    const R P0 = dwx * s, Q1 = wx * s;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const R wy = W[3 + k], dwy = bs_dw_fn<R>(k, F[1], fn);
+      acc[k][0] = fma_r(wy, P0, acc[k][0]);
+      acc[k][1] = fma_r(dwy, Q1, acc[k][1]);
     }
   }
 }
@@ -752,7 +836,13 @@ MPM_DEV void stress_fetch(const Dev<R>& d, int q, int ntot, int npi, int pb, int
   }
 }
 
-template <int D, typename R, int MODE, bool SOL = false>
+// Variants of the stress tile kernel: the fluid (J term, viscosity, surface), the fluid with
+// the J term alone in its interior points (no viscosity: divergence and s I only), and the
+// fluid with solid particles.  Each is its own instantiation, so that no variant carries
+// the registers of another's paths.
+enum StressVar { SV_FLUID = 0, SV_SOLID = 1, SV_JONLY = 2 };
+
+template <int D, typename R, int MODE, int VAR = SV_FLUID>
 __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stress(Dev<R> d, TileLists tl, const R* u, R* tpart,
                                                                 int mask_in, const int* done, int energy_slot,
                                                                 PUpd<R> pu, R* fout) {
@@ -769,9 +859,10 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
   int org[3] = {0, 0, 0};
   tiled_coords<D>(ct, 0, d.nt, org);
   const int cb = ct * 64;
+  constexpr bool SOL = VAR == SV_SOLID, ISO = VAR == SV_JONLY;
   const bool surf = (d.term_mask & 2) && S > 0;
   const bool vol = (d.term_mask & 5) != 0;
-  const bool visc = (d.term_mask & 4) != 0;
+  const bool visc = !ISO && (d.term_mask & 4) != 0;
   const int* rg = tl.ctile_rng + 6 * slot;
   const int pb = rg[0], pe = vol ? rg[1] : pb;
   const int sb = surf ? rg[2] : 0, se = surf ? rg[3] : 0;
@@ -827,8 +918,13 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
       }
       R w[D][3], dw[D][3];
       weight_table<D, R>(f, d.fn, w, dw);
+      // the fluid's J term alone (no viscosity, no solids) needs only the divergence, and
+      // its stress is s I: one payload value instead of D x D
+      const bool jonly = ISO && interior;
       R G[D][D], val[D];
-      region_grad<D, R, D>(sm.u, lc, w, dw, G, val);
+      R trj = 0;
+      if (jonly) trj = region_div<D, R>(sm.u, lc, w, dw);
+      else region_grad<D, R, D>(sm.u, lc, w, dw, G, val);
       R Sq[D][D];
 #pragma unroll
       for (int a = 0; a < D; ++a)
@@ -842,8 +938,12 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
         }
       } else if (interior) {
         R tr = 0;
+        if (jonly) {
+          tr = trj;
+        } else {
 #pragma unroll
-        for (int a = 0; a < D; ++a) tr += G[a][a];
+          for (int a = 0; a < D; ++a) tr += G[a][a];
+        }
         const R Jn = in.v[D], V0 = in.v[D + 1];
         if (d.term_mask & 1) {
           R s;
@@ -911,10 +1011,14 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
 #pragma unroll
         for (int kk = 0; kk < 3; ++kk) P[D + a * 3 + kk] = w[a][kk];
       }
+      if (jonly) {
+        P[4 * D] = Sq[0][0];
+      } else {
 #pragma unroll
-      for (int a = 0; a < D; ++a)
+        for (int a = 0; a < D; ++a)
 #pragma unroll
-        for (int b = 0; b < D; ++b) P[4 * D + a * D + b] = Sq[a][b];
+          for (int b = 0; b < D; ++b) P[4 * D + a * D + b] = Sq[a][b];
+      }
     }
     __syncthreads();
     // next chunk's inputs: in flight during this chunk's scatter
@@ -924,6 +1028,14 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
       int lo = q0, hi = min(q0 + CH, ntot);
       for (int pass = 0; pass < 2; ++pass) {
         int b0 = max(pass == 0 ? cpb : csb, lo), b1 = min(pass == 0 ? cpe : cse, hi);
+        if (ISO && pass == 0) {
+          // interior points with the J term alone: s I
+          for (int qq = b0; qq < b1; ++qq) {
+            const R* P = &sm.x.pt[(qq - q0) * PS];
+            lane_scatter_iso<D, R>(P, P + D, d.fn, lk0, lk1, ldw0, ldw1, P[4 * D], acc.v);
+          }
+          continue;
+        }
         for (int qq = b0; qq < b1; ++qq) {
           const R* P = &sm.x.pt[(qq - q0) * PS];
           R Sq[D][D];
