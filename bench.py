@@ -288,6 +288,23 @@ def roofline_of(cls, tm, N, S, G, R, K, visc, traffic):
     return r
 
 
+def secondary_roofline(r, K, precision):
+    """The Hessian tile kernel's average launch and its HBM and VALU fractions on a
+    secondary workload (the section 8(d) counts of that scene's own terms)."""
+    if not r["timing"]:
+        return None
+    st = r["stats"]
+    N = r["N"]
+    G = int(np.mean([s["n_tiles"] for s in st])) * 64
+    S = int(np.mean([s["n_surf"] for s in st]))
+    visc = r["params"]["mu0"] > 0 and (r["params"]["term_mask"] & 4)
+    tm = r["timing"]["work"]
+    if not tm["hess_int"][1]:
+        return None
+    rf = roofline_of("hess_int", tm, N, S, G, 4 if precision == "mixed" else 8, K, visc, None)
+    return {k: rf[k] for k in ("bound", "frac", "avg_launch_us", "hbm_frac", "valu_frac")}
+
+
 def kernel_sources_digest():
     import hashlib
     h = hashlib.sha256()
@@ -641,8 +658,9 @@ def main():
                 continue
             secondary[name] = {}
             for prec in precs:
-                r = run_gpu(sc.CONFIGS[name], prec, steps, 2, False, name)
+                r = run_gpu(sc.CONFIGS[name], prec, steps, 2, True, name)
                 secondary[name][prec] = summary(r, steps)
+                secondary[name][prec]["hess_int"] = secondary_roofline(r, steps, prec)
             if len(precs) == 2:
                 secondary[name]["speedup_mixed_over_fp64"] = round(
                     secondary[name]["mixed"]["value"] / secondary[name]["fp64"]["value"], 3)
