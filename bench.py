@@ -291,7 +291,7 @@ def roofline_of(cls, tm, N, S, G, R, K, visc, traffic):
 def secondary_roofline(r, K, precision):
     """The Hessian tile kernel's average launch and its HBM and VALU fractions on a
     secondary workload (the section 8(d) counts of that scene's own terms)."""
-    if not r["timing"]:
+    if not r["timing"] or r["params"]["dim"] != 3:      # the counts are the 3D ones
         return None
     st = r["stats"]
     N = r["N"]
