@@ -836,6 +836,56 @@ MPM_DEV void stress_fetch(const Dev<R>& d, int q, int ntot, int npi, int pb, int
   }
 }
 
+// A thread's share of a tile's node region: one (node, component) item per NT threads,
+// component-major so that a wave reads one plane.  All of a thread's loads (u, z and the
+// free flags of every item) are issued before any is used (every grid node is a valid
+// address); the constraint mask and the CG direction are applied when the items are
+// written to LDS.
+template <int D, typename R>
+struct RegionPf {
+  static constexpr int NI = (TileGeo<D>::RN * D + TileGeo<D>::NT - 1) / TileGeo<D>::NT;
+  R uv[NI], zv[NI];
+  int fr[NI];   // free flags of the node; 0 outside the grid
+};
+
+template <int D, typename R>
+MPM_DEV void region_fetch(const Dev<R>& d, int ct, const R* u, const R* z, int mask_in, RegionPf<D, R>& pf) {
+  constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
+#pragma unroll
+  for (int i = 0; i < RegionPf<D, R>::NI; ++i) {
+    const int e2 = (int)threadIdx.x + i * NT;
+    pf.uv[i] = R(0);
+    pf.zv[i] = R(0);
+    pf.fr[i] = 0;
+    if (e2 < RN * D) {
+      const int a = e2 / RN, rn = e2 - a * RN;
+      int r[3];
+      region_coords<D>(rn, r);
+      const int gnode = region_node_global<D>(ct, r, d.n, d.nt);
+      if (gnode >= 0) {
+        pf.fr[i] = mask_in ? d.gfree[gnode] : 0xff;
+        pf.uv[i] = u[a * d.nn + gnode];
+        if (z) pf.zv[i] = z[a * d.nn + gnode];
+      }
+    }
+  }
+}
+
+template <int D, typename R>
+MPM_DEV void region_commit(const RegionPf<D, R>& pf, bool has_z, R beta, R* su) {
+  constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
+#pragma unroll
+  for (int i = 0; i < RegionPf<D, R>::NI; ++i) {
+    const int e2 = (int)threadIdx.x + i * NT;
+    if (e2 < RN * D) {
+      const int a = e2 / RN, rn = e2 - a * RN;
+      R uv = pf.uv[i];
+      if (has_z) uv = cg_dir(pf.zv[i], beta, uv);
+      su[rn * D + a] = ((pf.fr[i] >> a) & 1) ? uv : R(0);
+    }
+  }
+}
+
 // Variants of the stress tile kernel: the fluid (J term, viscosity, surface), the fluid with
 // the J term alone in its interior points (no viscosity: divergence and s I only), and the
 // fluid with solid particles.  Each is its own instantiation, so that no variant carries
@@ -853,7 +903,7 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
   const int slot = xcd_slot(blockIdx.x, tl.xrun);
   if (slot >= tl.nctile) return;
   const int ct = tl.ctile_list[slot];
-  const int S = d.ns, nn = d.nn;
+  const int S = d.ns;
   const int t = threadIdx.x;
   const R dt = d.dt;
   int org[3] = {0, 0, 0};
@@ -872,23 +922,10 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
   StressIn<D, R, MODE> in;
   if (t < CH) stress_fetch<D, R, MODE>(d, t, ntot, npi, pb, sb, visc, in);
   const R beta = pu.beta();
-  // one (node, component) per thread, component-major so that a wave reads one plane; the
-  // loads of u, z and the free flags are issued together (every grid node is a valid
-  // address) and the constraint mask is applied by selection after they return
-  for (int e2 = t; e2 < RN * D; e2 += NT) {
-    const int a = e2 / RN, rn = e2 - a * RN;
-    int r[3];
-    region_coords<D>(rn, r);
-    const int gnode = region_node_global<D>(ct, r, d.n, d.nt);
-    R val = R(0);
-    if (gnode >= 0) {
-      const uint8_t fr = mask_in ? d.gfree[gnode] : 0xff;
-      R uv = u[a * nn + gnode];
-      if (pu.z) uv = cg_dir(pu.z[a * nn + gnode], beta, uv);
-      val = ((fr >> a) & 1) ? uv : R(0);
-    }
-    sm.u[rn * D + a] = val;
-  }
+  // the node region, the lanes' cell ranges: every load is issued before the region is
+  // written to LDS, so that the block waits for one round trip
+  RegionPf<D, R> pf;
+  region_fetch<D, R>(d, ct, u, pu.z, mask_in, pf);
   int lcell, lk0, lk1;
   lane_map<D>(t, lcell, lk0, lk1);
   const LaneDw<R> ldw0(lk0), ldw1(lk1);
@@ -898,6 +935,7 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
     if (vol) { cpb = d.p_start[cb + lcell] - pb; cpe = d.p_start[cb + lcell + 1] - pb; }
     if (surf) { csb = d.s_start[cb + lcell] - sb + npi; cse = d.s_start[cb + lcell + 1] - sb + npi; }
   }
+  region_commit<D, R>(pf, pu.z != nullptr, beta, sm.u);
   LaneAcc<D, R, D> acc;
   acc.zero();
   double e = 0;
@@ -1137,16 +1175,19 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::HEAT) k_tile_heat(De
   int org[3] = {0, 0, 0};
   tiled_coords<D>(ct, 0, d.nt, org);
   const R beta = pu.beta();
-  for (int rn = t; rn < RN; rn += NT) {
+  // the region's values and the lanes' cell ranges are all loaded before the region is
+  // written to LDS (one round trip); the region has fewer nodes than the block threads
+  static_assert(RN <= NT, "one region node per thread");
+  R tv = R(0), zv = R(0);
+  int gnode = -1;
+  if (t < RN) {
     int r[3];
-    region_coords<D>(rn, r);
-    int gnode = region_node_global<D>(ct, r, d.n, d.nt);
-    R val = R(0);
+    region_coords<D>(t, r);
+    gnode = region_node_global<D>(ct, r, d.n, d.nt);
     if (gnode >= 0) {
-      val = T[gnode];
-      if (pu.z) val = cg_dir(pu.z[gnode], beta, val);
+      tv = T[gnode];
+      if (pu.z) zv = pu.z[gnode];
     }
-    sm.u[rn] = val;
   }
   const int cb = ct * 64;
   const int* rg = tl.ctile_rng + 6 * slot;
@@ -1162,6 +1203,7 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::HEAT) k_tile_heat(De
     cpb = d.p_start[cb + lcell] - pb; cpe = d.p_start[cb + lcell + 1] - pb;
     if (S) { csb = d.s_start[cb + lcell] - sb + npi; cse = d.s_start[cb + lcell + 1] - sb + npi; }
   }
+  if (t < RN) sm.u[t] = gnode >= 0 ? (pu.z ? cg_dir(zv, beta, tv) : tv) : R(0);
   LaneAcc<D, R, 1> acc;
   acc.zero();
   __syncthreads();
