@@ -636,13 +636,13 @@ void do_energy_grad(mpm_ctx* c, const R* u, R* g, double* energy_dev, int red_sl
   if (c->nctile > 0) {
     const int var = stress_var(d);
     if (var == SV_SOLID)
-      LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_ENERGY, SV_SOLID>), dim3(tile_grid(c)), dim3(TileGeo<D>::NT), 0,
+      LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_ENERGY, SV_SOLID>), dim3(tile_grid(c)), dim3(TileGeo<D>::NT), sizeof(StressLds<D, R>),
              s, d, tl, u, (R*)c->tpart, 0, (const int*)nullptr, 2, pu, fout);
     else if (var == SV_JONLY)
-      LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_ENERGY, SV_JONLY>), dim3(tile_grid(c)), dim3(TileGeo<D>::NT), 0,
+      LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_ENERGY, SV_JONLY>), dim3(tile_grid(c)), dim3(TileGeo<D>::NT), sizeof(StressLds<D, R>),
              s, d, tl, u, (R*)c->tpart, 0, (const int*)nullptr, 2, pu, fout);
     else
-      LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_ENERGY>), dim3(tile_grid(c)), dim3(TileGeo<D>::NT), 0, s, d,
+      LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_ENERGY>), dim3(tile_grid(c)), dim3(TileGeo<D>::NT), sizeof(StressLds<D, R>), s, d,
              tl, u, (R*)c->tpart, 0, (const int*)nullptr, 2, pu, fout);
   }
   if (c->ntiles > 0) {
@@ -681,12 +681,12 @@ void do_hessvec(mpm_ctx* c, const R* w, double alpha, R* out, bool mask_in, cons
     const int var = stress_var(d);
     if (var == SV_SOLID)
       LAUNCH(c, MPM_K_HESS_INT, (k_tile_stress<D, R, TM_HESS, SV_SOLID>), dim3(tile_grid(c, TUNE_HESS)),
-             dim3(TileGeo<D>::NT), 0, s, dh, tl, w, (R*)c->tpart, (int)mask_in, done, -1, pu, (R*)nullptr);
+             dim3(TileGeo<D>::NT), sizeof(StressLds<D, R>), s, dh, tl, w, (R*)c->tpart, (int)mask_in, done, -1, pu, (R*)nullptr);
     else if (var == SV_JONLY)
       LAUNCH(c, MPM_K_HESS_INT, (k_tile_stress<D, R, TM_HESS, SV_JONLY>), dim3(tile_grid(c, TUNE_HESS)),
-             dim3(TileGeo<D>::NT), 0, s, dh, tl, w, (R*)c->tpart, (int)mask_in, done, -1, pu, (R*)nullptr);
+             dim3(TileGeo<D>::NT), sizeof(StressLds<D, R>), s, dh, tl, w, (R*)c->tpart, (int)mask_in, done, -1, pu, (R*)nullptr);
     else
-      LAUNCH(c, MPM_K_HESS_INT, (k_tile_stress<D, R, TM_HESS>), dim3(tile_grid(c, TUNE_HESS)), dim3(TileGeo<D>::NT), 0,
+      LAUNCH(c, MPM_K_HESS_INT, (k_tile_stress<D, R, TM_HESS>), dim3(tile_grid(c, TUNE_HESS)), dim3(TileGeo<D>::NT), sizeof(StressLds<D, R>),
              s, dh, tl, w, (R*)c->tpart, (int)mask_in, done, -1, pu, (R*)nullptr);
   }
   if (c->ntiles > 0)
@@ -703,10 +703,10 @@ void do_hessvec_force(mpm_ctx* c, const R* u, R* out, hipStream_t s) {
   TileLists tl = tiles(c);
   if (c->nctile > 0) {
     if (d.solids)
-      LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_FORCE, SV_SOLID>), dim3(tile_grid(c)), dim3(TileGeo<D>::NT), 0,
+      LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_FORCE, SV_SOLID>), dim3(tile_grid(c)), dim3(TileGeo<D>::NT), sizeof(StressLds<D, R>),
              s, d, tl, u, (R*)c->tpart, 0, (const int*)nullptr, -1, PUpd<R>{}, (R*)nullptr);
     else
-      LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_FORCE>), dim3(tile_grid(c)), dim3(TileGeo<D>::NT), 0, s, d,
+      LAUNCH(c, MPM_K_ENERGY_INT, (k_tile_stress<D, R, TM_FORCE>), dim3(tile_grid(c)), dim3(TileGeo<D>::NT), sizeof(StressLds<D, R>), s, d,
              tl, u, (R*)c->tpart, 0, (const int*)nullptr, -1, PUpd<R>{}, (R*)nullptr);
   }
   if (c->ntiles > 0)

@@ -252,6 +252,54 @@ MPM_DEV void reduce_cells_to_region(const LaneAcc<D, R, NF>& acc, int f0, R* cel
                                            [&](int rn, int f, R v) { reg[rn * FC + f] = v; });
 }
 
+// The same reduction over a dense buffer B[rn][f][k] (k = k0 + 3 k1 + 9 k2, stride KS):
+// every (node, offset) slot that no cell of the tile reaches holds zero, so each node's
+// sum runs over all 3^D slots in k order without a predicate, and gives the same value as
+// the predicated form (the skipped terms are added as zeros there).  The buffer shares its
+// storage with the point payloads, so it is cleared first.  out(rn, f, v) receives the
+// sums.
+template <int D>
+struct DenseRed {
+  static constexpr int KN = D == 3 ? 27 : 9;
+  static constexpr int KS = (KN + 3) & ~3;   // whole 16-byte rows
+};
+
+template <int D, typename R, int NF, class Out>
+MPM_DEV void reduce_region_dense(const LaneAcc<D, R, NF>& acc, R* B, int lane_cell, int lane_k0, int lane_k1,
+                                 bool lane_on, Out&& out) {
+  constexpr int RN = TileGeo<D>::RN, NT = TileGeo<D>::NT, KN = DenseRed<D>::KN, KS = DenseRed<D>::KS;
+  constexpr int NB = RN * NF * KS;
+  static_assert((NB * sizeof(R)) % 16 == 0, "whole 16-byte rows");
+  uint4* B16 = reinterpret_cast<uint4*>(B);   // all-zero bits are 0.0 in both precisions
+  for (int i = threadIdx.x; i < (int)(NB * sizeof(R) / 16); i += NT) B16[i] = make_uint4(0, 0, 0, 0);
+  __syncthreads();
+  if (lane_on) {
+    int c[3];
+    local_cell<D>(lane_cell, c);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int kk[3] = {lane_k0, D == 3 ? lane_k1 : k, D == 3 ? k : 0};
+      int r[3] = {c[0] + kk[0], c[1] + kk[1], D == 3 ? c[2] + kk[2] : 0};
+      const int rn = region_index<D>(r);
+      const int kidx = kk[0] + 3 * kk[1] + 9 * kk[2];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) B[(rn * NF + f) * KS + kidx] = acc.v[k][f];
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < RN * NF; i += NT) {
+    const R* b = B + i * KS;
+    R v[KN];
+#pragma unroll
+    for (int k = 0; k < KN; ++k) v[k] = b[k];
+    R sum = 0;
+#pragma unroll
+    for (int k = 0; k < KN; ++k) sum += v[k];
+    out(i / NF, i - (i / NF) * NF, sum);
+  }
+  __syncthreads();
+}
+
 // Lane mapping of the scatter phase.
 template <int D>
 MPM_DEV void lane_map(int t, int& cell, int& k0, int& k1) {
@@ -772,6 +820,12 @@ MPM_DEV R solid_stress(const Dev<R>& d, int k, const R (&G)[D][D], R dt, R* fout
   return e;
 }
 
+// LDS of the stress tile kernel.  The point payloads of a chunk and the dense reduction
+// buffer are never live together, so they share storage; the buffer makes a 3D MIXED
+// block 75 KB, two per CU, which is also what 80 VGPRs at six waves per SIMD allow.  The
+// block takes the storage as dynamic LDS: with a static size above a third of the CU's
+// LDS the compiler would conclude that six waves per SIMD cannot be resident and spend
+// more registers, which would leave one block per CU.
 template <int D, typename R>
 struct StressLds {
   static constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
@@ -779,14 +833,11 @@ struct StressLds {
   static constexpr int PW = 4 * D + D * D;                  // f, w table, stress
   static constexpr int PS = PW | 1;                         // odd payload stride
   R u[RN * D];
+  double bsum[16];
   union {
     R pt[CH * PS];
-    struct {
-      R cellpart[64 * 27 * D];
-      R reg[RN * D];
-    } red;
+    R dense[RN * D * DenseRed<D>::KS];
   } x;
-  double bsum[16];
 };
 
 // A point's inputs to the stress scatter, loaded one chunk ahead so that the loads are in
@@ -898,7 +949,8 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
                                                                 PUpd<R> pu, R* fout) {
   constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
   constexpr int CH = StressLds<D, R>::CH, PS = StressLds<D, R>::PS;
-  __shared__ StressLds<D, R> sm;
+  extern __shared__ __align__(16) unsigned char stress_lds[];
+  StressLds<D, R>& sm = *reinterpret_cast<StressLds<D, R>*>(stress_lds);
   if (done && *done) return;
   const int slot = xcd_slot(blockIdx.x, tl.xrun);
   if (slot >= tl.nctile) return;
@@ -1088,10 +1140,9 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
     __syncthreads();
   }
   // ---- reduce onto the region and write the tile partial ----
-  R* reg = sm.x.red.reg;
-  reduce_cells_to_region<D, R, D, D>(acc, 0, sm.x.red.cellpart, reg, lcell, lk0, lk1, lane_on);
   R* dst = tpart + (size_t)slot * RN * D;
-  for (int i = t; i < RN * D; i += NT) dst[i] = reg[i];
+  reduce_region_dense<D, R, D>(acc, sm.x.dense, lcell, lk0, lk1, lane_on,
+                               [&](int rn, int f, R v) { dst[rn * D + f] = v; });
   if (MODE == TM_ENERGY && energy_slot >= 0) {
     double bs = block_sum(e, sm.bsum);
     if (t == 0) d.part[energy_slot * kPartSlot + slot] = bs;
