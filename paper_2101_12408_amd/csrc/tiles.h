@@ -244,14 +244,6 @@ MPM_DEV void reduce_cells_to_region_out(const LaneAcc<D, R, NF>& acc, int f0, R*
   __syncthreads();
 }
 
-// reduce_cells_to_region_out into an LDS buffer: reg[rn][f].
-template <int D, typename R, int NF, int FC>
-MPM_DEV void reduce_cells_to_region(const LaneAcc<D, R, NF>& acc, int f0, R* cellpart, R* reg, int lane_cell,
-                                    int lane_k0, int lane_k1, bool lane_on) {
-  reduce_cells_to_region_out<D, R, NF, FC>(acc, f0, cellpart, lane_cell, lane_k0, lane_k1, lane_on,
-                                           [&](int rn, int f, R v) { reg[rn * FC + f] = v; });
-}
-
 // The same reduction over a dense buffer B[rn][f][k] (k = k0 + 3 k1 + 9 k2, stride KS):
 // every (node, offset) slot that no cell of the tile reaches holds zero, so each node's
 // sum runs over all 3^D slots in k order without a predicate, and gives the same value as
@@ -1205,10 +1197,7 @@ struct HeatLds {
   R u[RN];
   union {
     R pt[CH * PS];
-    struct {
-      R cellpart[64 * 27];
-      R reg[RN];
-    } red;
+    R dense[RN * DenseRed<D>::KS];
   } x;
 };
 
@@ -1311,10 +1300,8 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::HEAT) k_tile_heat(De
     }
     __syncthreads();
   }
-  R* reg = sm.x.red.reg;
-  reduce_cells_to_region<D, R, 1, 1>(acc, 0, sm.x.red.cellpart, reg, lcell, lk0, lk1, lane_on);
   R* dst = tpart + (size_t)slot * RN;
-  for (int i = t; i < RN; i += NT) dst[i] = reg[i];
+  reduce_region_dense<D, R, 1>(acc, sm.x.dense, lcell, lk0, lk1, lane_on, [&](int rn, int, R v) { dst[rn] = v; });
 }
 
 // ======================================================================================
