@@ -646,8 +646,8 @@ void do_energy_grad(mpm_ctx* c, const R* u, R* g, double* energy_dev, int red_sl
              tl, u, (R*)c->tpart, 0, (const int*)nullptr, 2, pu, fout);
   }
   if (c->ntiles > 0) {
-    LAUNCH(c, MPM_K_ENERGY_NODE, (k_merge_stress<D, R>), dim3(merge_blocks(c)), dim3(64 * kMergeTiles), 0, s, d, tl,
-           c->ntiles, (const R*)c->tpart, u, g, (int)NM_GRAD, 0.0, 0, (const int*)nullptr,
+    LAUNCH(c, MPM_K_ENERGY_NODE, (k_merge_stress<D, R, NM_GRAD>), dim3(merge_blocks(c)), dim3(64 * kMergeTiles), 0, s, d, tl,
+           c->ntiles, (const R*)c->tpart, u, g, 0.0, 0, (const int*)nullptr,
            c->nctile > 0 ? (const double*)(c->part + 2 * kPartSlot) : nullptr, c->nctile, c->part + 4 * kPartSlot,
            c->ctr + (size_t)CTR_MERGE * kCtrSite, c->scal + red_slot, energy_dev, (CgScal*)nullptr, pu, slope_g);
   } else {
@@ -690,9 +690,9 @@ void do_hessvec(mpm_ctx* c, const R* w, double alpha, R* out, bool mask_in, cons
              s, dh, tl, w, (R*)c->tpart, (int)mask_in, done, -1, pu, (R*)nullptr);
   }
   if (c->ntiles > 0)
-    LAUNCH(c, MPM_K_HESS_NODE, (k_merge_stress<D, R>), dim3(merge_blocks(c)), dim3(64 * kMergeTiles), 0, s, d, tl, c->ntiles,
-           (const R*)c->tpart,
-           w, out, (int)NM_HESS, alpha, (int)mask_in, done, (const double*)nullptr, 0, c->part + 4 * kPartSlot,
+    LAUNCH(c, MPM_K_HESS_NODE, (k_merge_stress<D, R, NM_HESS>), dim3(merge_blocks(c)), dim3(64 * kMergeTiles), 0, s, d, tl,
+           c->ntiles, (const R*)c->tpart,
+           w, out, alpha, (int)mask_in, done, (const double*)nullptr, 0, c->part + 4 * kPartSlot,
            c->ctr + (size_t)CTR_MERGE * kCtrSite, (double*)nullptr, (double*)nullptr, cg, pu, (const R*)nullptr);
 }
 
@@ -710,9 +710,9 @@ void do_hessvec_force(mpm_ctx* c, const R* u, R* out, hipStream_t s) {
              tl, u, (R*)c->tpart, 0, (const int*)nullptr, -1, PUpd<R>{}, (R*)nullptr);
   }
   if (c->ntiles > 0)
-    LAUNCH(c, MPM_K_ENERGY_NODE, (k_merge_stress<D, R>), dim3(merge_blocks(c)), dim3(64 * kMergeTiles), 0, s, d, tl, c->ntiles,
-           (const R*)c->tpart,
-           u, out, (int)NM_HESS, 0.0, 0, (const int*)nullptr, (const double*)nullptr, 0, c->part + 4 * kPartSlot,
+    LAUNCH(c, MPM_K_ENERGY_NODE, (k_merge_stress<D, R, NM_HESS>), dim3(merge_blocks(c)), dim3(64 * kMergeTiles), 0, s, d, tl,
+           c->ntiles, (const R*)c->tpart,
+           u, out, 0.0, 0, (const int*)nullptr, (const double*)nullptr, 0, c->part + 4 * kPartSlot,
            c->ctr + (size_t)CTR_MERGE * kCtrSite, (double*)nullptr, (double*)nullptr, (CgScal*)nullptr, PUpd<R>{},
            (const R*)nullptr);
 }

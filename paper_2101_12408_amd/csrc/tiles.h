@@ -1769,14 +1769,17 @@ constexpr int kMergeTiles = 4;
 //           the size of the terms a component of the gradient is formed from (its
 //           round-off in the arithmetic of R is about eps_R times the square root).
 //  NM_HESS: out = P[acc + alpha m w]; with cg the grid sum of w . out sets the CG step.
-template <int D, typename R>
+// The mode is a template argument: the Hessian form, launched once per CG iteration, then
+// carries neither the registers nor the LDS of the gradient form's sums.
+template <int D, typename R, int MODE>
 __global__ void __launch_bounds__(64 * kMergeTiles) k_merge_stress(
-    Dev<R> d, TileLists tl, int ntiles, const R* tpart, const R* u, R* out, int mode, double alpha, int mask_in,
+    Dev<R> d, TileLists tl, int ntiles, const R* tpart, const R* u, R* out, double alpha, int mask_in,
     const int* done, const double* epart, int nep, double* npart, unsigned* ctr, double* red, double* phi2,
     CgScal* cg, PUpd<R> pu, const R* slope_g) {
   constexpr int RN = TileGeo<D>::RN;
   constexpr int NV = D + 5;
-  __shared__ double sh[NV * 64 * kMergeTiles];
+  constexpr int mode = MODE;
+  __shared__ double sh[(MODE == NM_GRAD ? NV : 1) * 64 * kMergeTiles];
   if (done && *done) return;
   const int ti = blockIdx.x * kMergeTiles + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
