@@ -21,7 +21,8 @@ namespace mpm {
 // such workgroup on one SIMD, so k resident workgroups need 3k wave slots on that SIMD:
 // two per CU fit at most 85 VGPRs (80 allocated), three need at most 56.  The kernels
 // ask for W waves per SIMD; the compiler honours that only while its own LDS estimate
-// allows W, so the LDS of a block stays under a third of the CU's 160 KB.  P2G fits 73
+// allows W, so the static LDS of a block stays under a third of the CU's 160 KB (the
+// stress kernel, larger, takes dynamic LDS, which the estimate does not see).  P2G fits 73
 // (MIXED) by itself.  FP64 kernels need about twice the registers: at one workgroup per
 // CU they ask for 3 or 4 waves per SIMD (up to 168 or 128 VGPRs); held to 80, the FP64
 // stress and heat kernels spilled over 300 bytes per lane.
