@@ -827,7 +827,7 @@ struct StressLds {
   static constexpr int PS = PW | 1;                         // odd payload stride
   R u[RN * D];
   double bsum[16];
-  union {
+  union alignas(16) {   // the dense buffer is cleared in 16-byte rows
     R pt[CH * PS];
     R dense[RN * D * DenseRed<D>::KS];
   } x;
@@ -1196,7 +1196,7 @@ struct HeatLds {
   static constexpr int PW = 4 * D + 1 + D;    // f, w table, c, q
   static constexpr int PS = PW | 1;           // odd payload stride (distinct banks per cell)
   R u[RN];
-  union {
+  union alignas(16) {   // the dense buffer is cleared in 16-byte rows
     R pt[CH * PS];
     R dense[RN * DenseRed<D>::KS];
   } x;
