@@ -54,14 +54,18 @@ def round_inputs(P, surf, precision):
 
 
 def make_case(kind, dim=3, seed=0, precision="fp64", n=None, **kw):
-    if kind == "random":
+    if kind in ("random", "dense"):
+        # "dense": every particle in a box smaller than one cell, so that one cell tile holds
+        # several chunks of points in every tile kernel (P2G 288 points per chunk in 3D, the
+        # stress and heat kernels 576; 192 in 2D)
         n = n or (16 if dim == 3 else 32)
-        count = kw.pop("count", 300)
-        nsurf = kw.pop("nsurf", 200)
+        count = kw.pop("count", 300 if kind == "random" else (1500 if dim == 3 else 1200))
+        nsurf = kw.pop("nsurf", 200 if kind == "random" else 600)
+        box = (0.3, 0.7) if kind == "random" else (0.5 + 0.1 / n, 0.5 + 0.9 / n)
         prm = dict(mu0=0.7, mu_k=0.01, mu_T0=300.0, g0=0.3, g1=0.004, gT0=300.0,
                    heat=1, cp=2.0, K=0.3, h=4.0, T_amb=330.0, b=3.0, dt=2e-3)
         prm.update(kw)
-        S = sc.random_scene(dim, n, count, seed, box=(0.3, 0.7), **prm)
+        S = sc.random_scene(dim, n, count, seed, box=box, **prm)
         P, p = S["particles"], S["params"]
         surf = sc.random_surface(P, nsurf, seed, dx=p["dx"], spread=0.8)
     else:

@@ -7,8 +7,10 @@ level stated per test.  Every floating comparison bounds both the norm-wise erro
 worst element (max |a - b| / max |b|).
 
 Cases: random clouds with random surface samples (2D, 3D), the 2D square droplet, the
-Marangoni droplet at 32^3, and the contact-angle scene at 48^3 (label table k_r, slab
-constraint, gravity)."""
+Marangoni droplet at 32^3, the contact-angle scene at 48^3 (label table k_r, slab
+constraint, gravity), the lid-driven cavity, random clouds with solid particles, and
+clouds packed into one cell (one cell tile holds several chunks of points in every tile
+kernel)."""
 import numpy as np
 import pytest
 
@@ -17,7 +19,8 @@ from gpu_cases import TOL_FP64, TOL_MIXED_FORCE, GpuState, OracleState, check, l
 pytestmark = pytest.mark.gpu
 
 CASES = [("random", 2, 1), ("random", 3, 2), ("square2d", 2, 0), ("marangoni3d_small", 3, 0),
-         ("contact3d_small", 3, 0), ("cavity2d", 2, 0), ("random_solid", 2, 3), ("random_solid", 3, 4)]
+         ("contact3d_small", 3, 0), ("cavity2d", 2, 0), ("random_solid", 2, 3), ("random_solid", 3, 4),
+         ("dense", 2, 5), ("dense", 3, 6)]
 
 # fixed-corotated solids below T_melt = 300 K (the random scene's T is uniform in 280-320 K)
 SOLID = dict(T_melt=300.0, muh0=50.0, lamh0=120.0, kh=0.01, Th0=300.0)
