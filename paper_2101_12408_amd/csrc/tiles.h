@@ -954,7 +954,7 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
   int org[3] = {0, 0, 0};
   tiled_coords<D>(ct, 0, d.nt, org);
   const int cb = ct * 64;
-  constexpr bool SOL = VAR == SV_SOLID, ISO = VAR == SV_JONLY;
+  constexpr bool SOL = VAR == SV_SOLID, ISO = VAR == SV_JONLY, SYM = VAR == SV_FLUID;
   const bool surf = (d.term_mask & 2) && S > 0;
   const bool vol = (d.term_mask & 5) != 0;
   const bool visc = !ISO && (d.term_mask & 4) != 0;
@@ -1096,6 +1096,12 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
       }
       if (jonly) {
         P[4 * D] = Sq[0][0];
+      } else if (SYM && interior) {
+        // the fluid's interior stress s I + cV sym(G) is symmetric: its upper triangle
+#pragma unroll
+        for (int a = 0, k = 0; a < D; ++a)
+#pragma unroll
+          for (int b = a; b < D; ++b, ++k) P[4 * D + k] = Sq[a][b];
       } else {
 #pragma unroll
         for (int a = 0; a < D; ++a)
@@ -1116,6 +1122,19 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
           for (int qq = b0; qq < b1; ++qq) {
             const R* P = &sm.x.pt[(qq - q0) * PS];
             lane_scatter_iso<D, R>(P, P + D, d.fn, lk0, lk1, ldw0, ldw1, P[4 * D], acc.v);
+          }
+          continue;
+        }
+        if (SYM && pass == 0) {
+          // interior points of the fluid: the stress from its upper triangle
+          for (int qq = b0; qq < b1; ++qq) {
+            const R* P = &sm.x.pt[(qq - q0) * PS];
+            R Sq[D][D];
+#pragma unroll
+            for (int a = 0, k = 0; a < D; ++a)
+#pragma unroll
+              for (int b = a; b < D; ++b, ++k) Sq[a][b] = Sq[b][a] = P[4 * D + k];
+            lane_scatter_grad<D, R>(P, P + D, d.fn, lk0, lk1, ldw0, ldw1, Sq, acc.v);
           }
           continue;
         }
