@@ -555,29 +555,28 @@ MPM_DEV void lane_nodes(const R* W, const R* DW, int k0, int k1, R (&wn)[3], R (
   }
 }
 
-// Derivative (per dx) of the 1D weight of stencil node k at cell-relative x, as in
-// weight_table.
+// Derivative (per dx) of the 1D weight of stencil node k at cell-relative x, from X = x fn
+// (the point payloads carry X): X - fn, fn - 2 X and X are (x - 1) fn, (1 - 2x) fn and x fn
+// of weight_table, bitwise when fn (the grid's n) is a power of two, as scaling by it is
+// exact.
 template <typename R>
-MPM_DEV R bs_dw_fn(int k, R x, R fn) {
-  return k == 0 ? (x - R(1)) * fn : (k == 1 ? (R(1) - R(2) * x) * fn : x * fn);
+MPM_DEV R bs_dw_fn(int k, R X, R fn) {
+  return k == 0 ? X - fn : (k == 1 ? fma_r(X, R(-2), fn) : X);
 }
 
 // bs_dw_fn for a node number k that varies across the lanes, without branches: all three
-// forms (x - 1, 1 - 2x, x) are formed and the lane's is selected, each rounded as in
-// bs_dw_fn.  Held per lane as the two comparisons of k (lane masks in scalar registers),
-// so that it takes no vector registers across the scatter loop.
+// forms are formed and the lane's is selected.  Held per lane as the two comparisons of k
+// (lane masks in scalar registers), so that it takes no vector registers across the
+// scatter loop.
 template <typename R>
 struct LaneDw {
   bool k0, k1;
   MPM_DEV explicit LaneDw(int k) : k0(k == 0), k1(k == 1) {}
-  MPM_DEV R operator()(R x, R fn) const {
-    const R t = k0 ? x - R(1) : (k1 ? fma_r(x, R(-2), R(1)) : x);
-    return t * fn;
-  }
+  MPM_DEV R operator()(R X, R fn) const { return k0 ? X - fn : (k1 ? fma_r(X, R(-2), fn) : X); }
 };
 
 // acc[k][a] += sum_b S[a][b] dN_k/dx_b over the lane's three nodes k (k2 = k in 3D, k1 = k
-// in 2D), from the point's cell-relative position F and weight table W.  The node
+// in 2D), from the point's scaled cell-relative position F (x fn) and weight table W.  The node
 // gradients share the lane's factors (3D: (al wz_k, be wz_k, ga dwz_k) with al = dwx wy,
 // be = wx dwy, ga = wx wy), so S g_k = wz_k (al S_.0 + be S_.1) + dwz_k (ga S_.2): 2 FMAs
 // per node and component, chained into the accumulator, after a per-point set-up.
@@ -823,7 +822,7 @@ template <int D, typename R>
 struct StressLds {
   static constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
   static constexpr int CH = NT;                             // points per chunk
-  static constexpr int PW = 4 * D + D * D;                  // f, w table, stress
+  static constexpr int PW = 4 * D + D * D;                  // x fn, w table, stress
   static constexpr int PS = PW | 1;                         // odd payload stride
   R u[RN * D];
   double bsum[16];
@@ -1090,7 +1089,7 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
       R* P = &sm.x.pt[t * PS];
 #pragma unroll
       for (int a = 0; a < D; ++a) {
-        P[a] = f[a];
+        P[a] = f[a] * d.fn;   // X = x fn: the lanes form their derivatives from it
 #pragma unroll
         for (int kk = 0; kk < 3; ++kk) P[D + a * 3 + kk] = w[a][kk];
       }
@@ -1212,7 +1211,7 @@ template <int D, typename R>
 struct HeatLds {
   static constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
   static constexpr int CH = NT;                             // points per chunk
-  static constexpr int PW = 4 * D + 1 + D;    // f, w table, c, q
+  static constexpr int PW = 4 * D + 1 + D;    // x fn, w table, c, q
   static constexpr int PS = PW | 1;           // odd payload stride (distinct banks per cell)
   R u[RN];
   union alignas(16) {   // the dense buffer is cleared in 16-byte rows
@@ -1289,7 +1288,7 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::HEAT) k_tile_heat(De
       R* P = &sm.x.pt[t * PS];
 #pragma unroll
       for (int a = 0; a < D; ++a) {
-        P[a] = f[a];
+        P[a] = f[a] * d.fn;   // X = x fn: the lanes form their derivatives from it
 #pragma unroll
         for (int kk = 0; kk < 3; ++kk) P[D + a * 3 + kk] = w[a][kk];
       }
