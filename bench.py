@@ -658,7 +658,7 @@ def main():
     if not args.no_secondary:
         secondary = {}
         plan = [("square2d", ["fp64"], 5), ("marangoni3d", ["mixed", "fp64"], 20),
-                ("contact3d", ["mixed", "fp64"], 50)]
+                ("contact3d", ["mixed", "fp64"], 50), ("meltslab3d_4ppc", ["mixed", "fp64"], 20)]
         for name, precs, steps in plan:
             if name == args.workload:
                 continue

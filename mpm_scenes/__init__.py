@@ -13,7 +13,8 @@ Workloads (the paper uses no dataset; every scene here is procedural):
   square2d     2D square droplet relaxing under constant surface tension (64^2)
   marangoni3d  3D droplet with a linear temperature field and gamma(T) (128^3)
   contact3d    3D hemisphere-cap droplet on a static slab, three surface energies (192^3)
-  meltslab3d   3D slab heated by the ambient through the Robin term, mu(T) (256^3)
+  meltslab3d   3D slab heated by the ambient through the Robin term, mu(T) (256^3, 8 ppc;
+               meltslab3d_4ppc: the same slab at 4 particles per cell)
   ellipse2d    2D ellipse under surface tension, explicit steps (64^2)
   cavity2d     2D lid-driven Marangoni cavity, k = clamp(1 - T, 0, 1) (64^2)
   ramp2d/3d    droplet landing on a 5.5 degree ramp with Coulomb friction (32^2 / 64^3)
@@ -71,19 +72,28 @@ def make_params(**kw):
     return p
 
 
-def lattice(n, dim, inside, seed, ppc_axis=2, jitter=0.25, lo=None, hi=None):
+# Four points per cell (3D): the corners of a regular tetrahedron inside the cell, at a
+# quarter of the cell from its faces (the face-centred pattern).
+TETRA4 = np.array([[0.25, 0.25, 0.25], [0.75, 0.75, 0.25], [0.75, 0.25, 0.75], [0.25, 0.75, 0.75]])
+
+
+def lattice(n, dim, inside, seed, ppc_axis=2, jitter=0.25, lo=None, hi=None, offsets=None):
     """Jittered sub-cell lattice: ppc_axis^dim points per cell at offsets
-    (k + 1/2)/ppc_axis * dx, each coordinate jittered by U[-jitter, jitter]*dx, kept
-    where inside(x) is true.  Cells are visited z-major, x fastest; the jitter stream is
-    numpy PCG64(seed), one draw per point and axis in visiting order."""
+    (k + 1/2)/ppc_axis * dx (or at the given per-cell offsets, in cells), each coordinate
+    jittered by U[-jitter, jitter]*dx, kept where inside(x) is true.  Cells are visited
+    z-major, x fastest; the jitter stream is numpy PCG64(seed), one draw per point and axis
+    in visiting order."""
     dx = 1.0 / n
     lo = np.zeros(dim, int) if lo is None else np.asarray(lo, int)
     hi = np.full(dim, n, int) if hi is None else np.asarray(hi, int)
     rng = np.random.Generator(np.random.PCG64(seed))
     axes = [np.arange(lo[a], hi[a]) for a in range(dim)]
     cells = np.stack(np.meshgrid(*axes[::-1], indexing="ij")[::-1], -1).reshape(-1, dim)
-    sub = np.stack(np.meshgrid(*([np.arange(ppc_axis)] * dim)[::-1], indexing="ij")[::-1], -1).reshape(-1, dim)
-    off = (sub + 0.5) / ppc_axis
+    if offsets is None:
+        sub = np.stack(np.meshgrid(*([np.arange(ppc_axis)] * dim)[::-1], indexing="ij")[::-1], -1).reshape(-1, dim)
+        off = (sub + 0.5) / ppc_axis
+    else:
+        off = np.asarray(offsets, np.float64).reshape(-1, dim)
     pts = (cells[:, None, :] + off[None, :, :]).reshape(-1, dim) * dx
     pts = pts + rng.uniform(-jitter, jitter, size=pts.shape) * dx
     keep = inside(pts)
@@ -152,12 +162,13 @@ def contact3d(seed=3, n=192, radius=0.15):
     return dict(params=p, particles=particles_from_positions(x, 3, dx), name="contact3d", steps=50)
 
 
-def meltslab3d(seed=4, n=256, ppc_axis=2, lo=0.2, hi=0.8, height=0.2, solid=False):
+def meltslab3d(seed=4, n=256, ppc_axis=2, lo=0.2, hi=0.8, height=0.2, solid=False, ppc=None):
     """3D wax slab x,z in [lo,hi] (default [0.2,0.8]), y in [2dx, 2dx+height] (default 0.2),
     T0 290 K heated by a 400 K ambient through the Robin term (h 20, b 0, K 0.25, c_p 1),
     mu(T) = 1e3 exp(-0.05 (T-290)), gamma(T) as in marangoni3d, gravity -9.8, slip floor
     (two node layers).  solid=True: the wax starts as a fixed-corotated solid (F = I) that
-    melts at T_melt = 300 K (Section 3.5), Lame constants (5e3, 1e4) exp(-0.05 (T - 290))."""
+    melts at T_melt = 300 K (Section 3.5), Lame constants (5e3, 1e4) exp(-0.05 (T - 290)).
+    ppc = 4: four particles per cell (TETRA4) instead of ppc_axis^3."""
     dx = 1.0 / n
     extra = dict(T_melt=300.0, muh0=5e3, lamh0=1e4, kh=0.05, Th0=290.0) if solid else {}
     p = make_params(dim=3, n=n, dt=1e-3, bulk=1e4, gravity=(0.0, -9.8, 0.0),
@@ -170,12 +181,16 @@ def meltslab3d(seed=4, n=256, ppc_axis=2, lo=0.2, hi=0.8, height=0.2, solid=Fals
                         & (q[:, 1] >= y0) & (q[:, 1] < y1))
     clo = np.array([int(lo * n) - 1, 2, int(lo * n) - 1])
     chi = np.array([int(hi * n) + 2, int(y1 * n) + 2, int(hi * n) + 2])
-    x = lattice(n, 3, inside, seed, ppc_axis=ppc_axis, lo=clo, hi=chi)
+    if ppc == 4:
+        x = lattice(n, 3, inside, seed, lo=clo, hi=chi, offsets=TETRA4)
+    else:
+        x = lattice(n, 3, inside, seed, ppc_axis=ppc_axis, lo=clo, hi=chi)
     T = np.full(x.shape[0], 290.0)
-    P = particles_from_positions(x, 3, dx, ppc=ppc_axis ** 3, T=T)
+    P = particles_from_positions(x, 3, dx, ppc=4 if ppc == 4 else ppc_axis ** 3, T=T)
     if solid:
         P["F"] = np.tile(np.eye(3), (x.shape[0], 1, 1))
-    return dict(params=p, particles=P, name="meltslab3d_solid" if solid else "meltslab3d", steps=20)
+    name = "meltslab3d_solid" if solid else ("meltslab3d_4ppc" if ppc == 4 else "meltslab3d")
+    return dict(params=p, particles=P, name=name, steps=20)
 
 
 def ellipse2d(seed=6, n=64, cfl=0.0):
@@ -362,4 +377,5 @@ def random_surface(P, count, seed, spread=1.0, dx=None, dim=None):
 
 
 CONFIGS = dict(square2d=square2d, marangoni3d=marangoni3d, contact3d=contact3d,
-               meltslab3d=meltslab3d, cavity2d=cavity2d, ramp2d=ramp2d, ramp3d=ramp3d)
+               meltslab3d=meltslab3d, cavity2d=cavity2d, ramp2d=ramp2d, ramp3d=ramp3d,
+               meltslab3d_4ppc=lambda **kw: meltslab3d(ppc=4, **kw))
