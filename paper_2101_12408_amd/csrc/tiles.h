@@ -528,6 +528,120 @@ MPM_DEV R region_div(const R* u, const int* lc, const R (&w)[D][3], const R (&dw
   return tr;
 }
 
+// 3D stencil sums from polynomial coefficients.  On a cell, the quadratic B-spline weights
+// of the nodes c - 1 + k (k = 0..2) at the cell-relative coordinate x sum a nodal line to a
+// quadratic in x: sum_k u_k w_k(x) = c0 + c1 x + c2 x^2 with c0 = (u0 + u1)/2, c1 = u1 - u0,
+// c2 = (u0 + u2)/2 - u1 (the three weights of weight_table expanded).  Applied along the
+// first two axes to the 3x3 node patch of each stencil start (sx, sy) of the tile, in each
+// node plane z of the region, this gives 9 coefficients c_pq of x^p y^q per component.  A
+// point then forms the value and the x and y derivatives of each of its three planes by
+// Horner's rule, and sums the planes with the z weights, where the direct sum runs over
+// the 27 nodes with the weight products.  NC components per node.
+template <int NC>
+struct MonoGeo {
+  static constexpr int E = TileGeo<3>::E, RE = TileGeo<3>::RE;
+  static constexpr int NS = E * E * RE;        // stencil starts (sx, sy) times node planes z
+  static constexpr int CS = (9 * NC + 3) & ~3;  // per start: NC x 9, padded to 16-byte rows
+  static constexpr int N = NS * CS;
+};
+
+// Coefficients of every start, from the staged region u[rn * NC + a]: one thread per
+// (start, component), NC * NS of the workgroup's threads.
+template <typename R, int NC>
+MPM_DEV void mono_build(const R* u, R* cf) {
+  constexpr int E = MonoGeo<NC>::E, RE = MonoGeo<NC>::RE, CS = MonoGeo<NC>::CS;
+  const int j = threadIdx.x;
+  if (j >= NC * MonoGeo<NC>::NS) return;
+  const int s = j / NC, a = j - NC * s;
+  const int sx = s % E, sy = (s / E) % E, z = s / (E * E);
+  R X[3][3];   // X[p][r]: the x^p coefficient of patch row r
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const R* row = u + (sx + RE * ((sy + r) + RE * z)) * NC + a;
+    const R u0 = row[0], u1 = row[NC], u2 = row[2 * NC];
+    X[0][r] = R(0.5) * (u0 + u1);
+    X[1][r] = u1 - u0;
+    X[2][r] = R(0.5) * (u0 + u2) - u1;
+  }
+  R* o = cf + s * CS + a * 9;
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+    o[p * 3 + 0] = R(0.5) * (X[p][0] + X[p][1]);
+    o[p * 3 + 1] = X[p][1] - X[p][0];
+    o[p * 3 + 2] = R(0.5) * (X[p][0] + X[p][2]) - X[p][1];
+  }
+}
+
+// One plane's sums for component a of a point at (x, y) in its cell: the value C and the
+// derivatives A (along x) and B (along y), per unit of the cell-relative coordinates.
+template <typename R>
+MPM_DEV void mono_plane(const R* c, R x, R x2, R y, R y2, R& A, R& B, R& C) {
+  R t[3], dd[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    t[q] = fma_r(x, fma_r(x, c[6 + q], c[3 + q]), c[q]);
+    dd[q] = fma_r(x2, c[6 + q], c[3 + q]);
+  }
+  C = fma_r(y, fma_r(y, t[2], t[1]), t[0]);
+  B = fma_r(y2, t[2], t[1]);
+  A = fma_r(y, fma_r(y, dd[2], dd[1]), dd[0]);
+}
+
+// region_grad (3D) from the coefficients: x, y the point's cell-relative coordinates, wz,
+// dwz its weight table along z; G the gradient and val the value of each component.
+template <typename R, int NC>
+MPM_DEV void mono_grad(const R* cf, const int* lc, R x, R y, R fn, const R (&wz)[3], const R (&dwz)[3],
+                       R (&G)[NC][3], R (&val)[NC]) {
+  constexpr int E = MonoGeo<NC>::E, CS = MonoGeo<NC>::CS;
+  const R* base = cf + (lc[0] + E * (lc[1] + E * lc[2])) * CS;
+  const R x2 = x + x, y2 = y + y;
+#pragma unroll
+  for (int a = 0; a < NC; ++a) {
+    val[a] = 0;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) G[a][b] = 0;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const R fw = fn * wz[k];
+#pragma unroll
+    for (int a = 0; a < NC; ++a) {
+      R A, B, C;
+      mono_plane<R>(base + k * E * E * CS + a * 9, x, x2, y, y2, A, B, C);
+      G[a][0] = fma_r(A, fw, G[a][0]);
+      G[a][1] = fma_r(B, fw, G[a][1]);
+      G[a][2] = fma_r(C, dwz[k], G[a][2]);
+      val[a] = fma_r(C, wz[k], val[a]);
+    }
+  }
+}
+
+// The trace of mono_grad's G, from the three diagonal entries alone, each formed with
+// mono_grad's operations in its order, so the value is the same.
+template <typename R>
+MPM_DEV R mono_div(const R* cf, const int* lc, R x, R y, R fn, const R (&wz)[3], const R (&dwz)[3]) {
+  constexpr int E = MonoGeo<3>::E, CS = MonoGeo<3>::CS;
+  const R* base = cf + (lc[0] + E * (lc[1] + E * lc[2])) * CS;
+  const R x2 = x + x, y2 = y + y;
+  R Gd[3] = {0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const R fw = fn * wz[k];
+    const R* c = base + k * E * E * CS;
+    R A, B, C, A1, B1, C1, A2, B2, C2;
+    mono_plane<R>(c, x, x2, y, y2, A, B, C);
+    mono_plane<R>(c + 9, x, x2, y, y2, A1, B1, C1);
+    mono_plane<R>(c + 18, x, x2, y, y2, A2, B2, C2);
+    Gd[0] = fma_r(A, fw, Gd[0]);
+    Gd[1] = fma_r(B1, fw, Gd[1]);
+    Gd[2] = fma_r(C2, dwz[k], Gd[2]);
+  }
+  R tr = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) tr += Gd[a];
+  return tr;
+}
+
 // Lane (cell, k0[, k1]) view of a point's weights: the weights and gradients of its 3
 // nodes k = 0..2 along the last axis.
 template <int D, typename R>
@@ -824,10 +938,14 @@ struct StressLds {
   static constexpr int CH = NT;                             // points per chunk
   static constexpr int PW = 4 * D + D * D;                  // x fn, w table, stress
   static constexpr int PS = PW | 1;                         // odd payload stride
+  // 3D: the gathers' polynomial coefficients follow the payloads (they share the room of
+  // the dense reduction buffer, which is only used after the last chunk)
+  static constexpr int NCF = D == 3 ? MonoGeo<3>::N : 0;
+  static_assert((CH * PS * sizeof(R)) % 16 == 0, "coefficients in 16-byte rows");
   R u[RN * D];
   double bsum[16];
   union alignas(16) {   // the dense buffer is cleared in 16-byte rows
-    R pt[CH * PS];
+    R pt[CH * PS + NCF];
     R dense[RN * D * DenseRed<D>::KS];
   } x;
 };
@@ -983,7 +1101,12 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
   LaneAcc<D, R, D> acc;
   acc.zero();
   double e = 0;
+  R* cf = sm.x.pt + CH * PS;
   __syncthreads();
+  if constexpr (D == 3) {
+    mono_build<R, 3>(sm.u, cf);
+    __syncthreads();
+  }
   for (int q0 = 0; q0 < ntot; q0 += CH) {
     // ---- point phase: weights, gradient of u, stress ----
     if (t < CH && in.k >= 0) {
@@ -1005,8 +1128,13 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
       const bool jonly = ISO && interior;
       R G[D][D], val[D];
       R trj = 0;
-      if (jonly) trj = region_div<D, R>(sm.u, lc, w, dw);
-      else region_grad<D, R, D>(sm.u, lc, w, dw, G, val);
+      if constexpr (D == 3) {
+        if (jonly) trj = mono_div<R>(cf, lc, f[0], f[1], d.fn, w[2], dw[2]);
+        else mono_grad<R, 3>(cf, lc, f[0], f[1], d.fn, w[2], dw[2], G, val);
+      } else {
+        if (jonly) trj = region_div<D, R>(sm.u, lc, w, dw);
+        else region_grad<D, R, D>(sm.u, lc, w, dw, G, val);
+      }
       R Sq[D][D];
 #pragma unroll
       for (int a = 0; a < D; ++a)
@@ -1213,9 +1341,12 @@ struct HeatLds {
   static constexpr int CH = NT;                             // points per chunk
   static constexpr int PW = 4 * D + 1 + D;    // x fn, w table, c, q
   static constexpr int PS = PW | 1;           // odd payload stride (distinct banks per cell)
+  // 3D: the gather's polynomial coefficients follow the payloads
+  static constexpr int NCF = D == 3 ? MonoGeo<1>::N : 0;
+  static_assert((CH * PS * sizeof(R)) % 16 == 0 || NCF == 0, "coefficients in 16-byte rows");
   R u[RN];
   union alignas(16) {   // the dense buffer is cleared in 16-byte rows
-    R pt[CH * PS];
+    R pt[CH * PS + NCF];
     R dense[RN * DenseRed<D>::KS];
   } x;
 };
@@ -1265,7 +1396,12 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::HEAT) k_tile_heat(De
   if (t < RN) sm.u[t] = gnode >= 0 ? (pu.z ? cg_dir(zv, beta, tv) : tv) : R(0);
   LaneAcc<D, R, 1> acc;
   acc.zero();
+  R* cf = sm.x.pt + CH * PS;
   __syncthreads();
+  if constexpr (D == 3) {
+    mono_build<R, 1>(sm.u, cf);
+    __syncthreads();
+  }
   for (int q0 = 0; q0 < ntot; q0 += CH) {
     int q = q0 + t;
     if (t < CH && q < ntot) {
@@ -1284,7 +1420,8 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::HEAT) k_tile_heat(De
       R w[D][3], dw[D][3];
       weight_table<D, R>(f, d.fn, w, dw);
       R G[1][D], val[1];
-      region_grad<D, R, 1>(sm.u, lc, w, dw, G, val);
+      if constexpr (D == 3) mono_grad<R, 1>(cf, lc, f[0], f[1], d.fn, w[2], dw[2], G, val);
+      else region_grad<D, R, 1>(sm.u, lc, w, dw, G, val);
       R* P = &sm.x.pt[t * PS];
 #pragma unroll
       for (int a = 0; a < D; ++a) {
