@@ -245,6 +245,26 @@ MPM_DEV void reduce_cells_to_region_out(const LaneAcc<D, R, NF>& acc, int f0, R*
   __syncthreads();
 }
 
+// The node terms of a plane patch from the coefficient sensitivities: g_ij = sum_pq
+// T_pi T_qj h_pq, with c_p = sum_i T_pi u_i the coefficient map of mono_build
+// (T = [[1/2, 1/2, 0], [-1, 1, 0], [1/2, -1, 1/2]]).
+template <typename R>
+MPM_DEV void mono_unmap(const R (&h)[3][3], R (&g)[3][3]) {
+  R m[3][3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    m[0][q] = R(0.5) * (h[0][q] + h[2][q]) - h[1][q];
+    m[1][q] = R(0.5) * h[0][q] + h[1][q] - h[2][q];
+    m[2][q] = R(0.5) * h[2][q];
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    g[i][0] = R(0.5) * (m[i][0] + m[i][2]) - m[i][1];
+    g[i][1] = R(0.5) * m[i][0] + m[i][1] - m[i][2];
+    g[i][2] = R(0.5) * m[i][2];
+  }
+}
+
 // The same reduction over a dense buffer B[rn][f][k] (k = k0 + 3 k1 + 9 k2, stride KS):
 // every (node, offset) slot that no cell of the tile reaches holds zero, so each node's
 // sum runs over all 3^D slots in k order without a predicate, and gives the same value as
@@ -257,7 +277,7 @@ struct DenseRed {
   static constexpr int KS = (KN + 3) & ~3;   // whole 16-byte rows
 };
 
-template <int D, typename R, int NF, class Out>
+template <int D, typename R, int NF, class Out, bool MONO = false>
 MPM_DEV void reduce_region_dense(const LaneAcc<D, R, NF>& acc, R* B, int lane_cell, int lane_k0, int lane_k1,
                                  bool lane_on, Out&& out) {
   constexpr int RN = TileGeo<D>::RN, NT = TileGeo<D>::NT, KN = DenseRed<D>::KN, KS = DenseRed<D>::KS;
@@ -269,14 +289,31 @@ MPM_DEV void reduce_region_dense(const LaneAcc<D, R, NF>& acc, R* B, int lane_ce
   if (lane_on) {
     int c[3];
     local_cell<D>(lane_cell, c);
+    if constexpr (MONO) {
+      // lane (component lane_k0, plane lane_k1): its coefficient sensitivities to the
+      // nodes of its plane patch (lane_scatter_mono)
+      static_assert(D == 3 && NF == 3, "plane patches of the 3D stress scatter");
+      R g[3][3];
+      mono_unmap<R>(acc.v, g);
+      const int a = lane_k0, kz = lane_k1;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const int kk[3] = {lane_k0, D == 3 ? lane_k1 : k, D == 3 ? k : 0};
-      int r[3] = {c[0] + kk[0], c[1] + kk[1], D == 3 ? c[2] + kk[2] : 0};
-      const int rn = region_index<D>(r);
-      const int kidx = kk[0] + 3 * kk[1] + 9 * kk[2];
+      for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int f = 0; f < NF; ++f) B[(rn * NF + f) * KS + kidx] = acc.v[k][f];
+        for (int j = 0; j < 3; ++j) {
+          int r[3] = {c[0] + i, c[1] + j, c[2] + kz};
+          const int rn = region_index<D>(r);
+          B[(rn * NF + a) * KS + i + 3 * j + 9 * kz] = g[i][j];
+        }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int kk[3] = {lane_k0, D == 3 ? lane_k1 : k, D == 3 ? k : 0};
+        int r[3] = {c[0] + kk[0], c[1] + kk[1], D == 3 ? c[2] + kk[2] : 0};
+        const int rn = region_index<D>(r);
+        const int kidx = kk[0] + 3 * kk[1] + 9 * kk[2];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) B[(rn * NF + f) * KS + kidx] = acc.v[k][f];
+      }
     }
   }
   __syncthreads();
@@ -640,6 +677,26 @@ MPM_DEV R mono_div(const R* cf, const int* lc, R x, R y, R fn, const R (&wz)[3],
 #pragma unroll
   for (int a = 0; a < 3; ++a) tr += Gd[a];
   return tr;
+}
+
+// The transpose of the coefficient gather, for the stress scatter (3D).  A lane (cell,
+// component a, plane kz) accumulates over its cell's points the sensitivities h_pq of
+// that plane's coefficients c_pq of component a to the point terms S_a . grad N:
+//   h_pq += gC x^p y^q + gB x^p q y^(q-1) + gA p x^(p-1) y^q,
+//   gA = S_a0 fn wz, gB = S_a1 fn wz, gC = S_a2 dwz
+// (mono_plane and the plane sums of mono_grad, differentiated by c_pq).  fw = fn wz.
+template <typename R>
+MPM_DEV void lane_scatter_mono(R x, R y, R fw, R dwz, R S0, R S1, R S2, R (&h)[3][3]) {
+  const R gA = S0 * fw, gB = S1 * fw, gC = S2 * dwz;
+  const R y2 = y * y, x2 = x * x, tx = x + x, ty = y + y;
+  const R V[3] = {gC, fma_r(gC, y, gB), fma_r(gC, y2, ty * gB)};
+  const R U[3] = {gA, gA * y, gA * y2};
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    h[0][q] += V[q];
+    h[1][q] = fma_r(x, V[q], h[1][q]) + U[q];
+    h[2][q] = fma_r(x2, V[q], fma_r(tx, U[q], h[2][q]));
+  }
 }
 
 // Lane (cell, k0[, k1]) view of a point's weights: the weights and gradients of its 3
@@ -1072,6 +1129,9 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
   tiled_coords<D>(ct, 0, d.nt, org);
   const int cb = ct * 64;
   constexpr bool SOL = VAR == SV_SOLID, ISO = VAR == SV_JONLY, SYM = VAR == SV_FLUID;
+  // 3D, but for the J term alone (whose s I scatter is cheaper node by node): the scatter
+  // accumulates coefficient sensitivities (lane_scatter_mono)
+  constexpr bool MONO = D == 3 && !ISO;
   const bool surf = (d.term_mask & 2) && S > 0;
   const bool vol = (d.term_mask & 5) != 0;
   const bool visc = !ISO && (d.term_mask & 4) != 0;
@@ -1215,32 +1275,57 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
           for (int b = 0; b < D; ++b) Sq[a][b] = sc * Q[a][b];
       }
       R* P = &sm.x.pt[t * PS];
+      // MONO: x, y, fn wz, dwz and the stress at SO (lane_scatter_mono); else X = x fn (the
+      // lanes form their derivatives from it), the weight table and the stress at 4 D
+      constexpr int SO = MONO ? 8 : 4 * D;
+      if constexpr (MONO) {
+        P[0] = f[0];
+        P[1] = f[1];
 #pragma unroll
-      for (int a = 0; a < D; ++a) {
-        P[a] = f[a] * d.fn;   // X = x fn: the lanes form their derivatives from it
+        for (int kk = 0; kk < 3; ++kk) {
+          P[2 + kk] = d.fn * w[2][kk];
+          P[5 + kk] = dw[2][kk];
+        }
+      } else {
 #pragma unroll
-        for (int kk = 0; kk < 3; ++kk) P[D + a * 3 + kk] = w[a][kk];
+        for (int a = 0; a < D; ++a) {
+          P[a] = f[a] * d.fn;
+#pragma unroll
+          for (int kk = 0; kk < 3; ++kk) P[D + a * 3 + kk] = w[a][kk];
+        }
       }
       if (jonly) {
-        P[4 * D] = Sq[0][0];
-      } else if (SYM && interior) {
+        P[SO] = Sq[0][0];
+      } else if (SYM && interior && !MONO) {
         // the fluid's interior stress s I + cV sym(G) is symmetric: its upper triangle
 #pragma unroll
         for (int a = 0, k = 0; a < D; ++a)
 #pragma unroll
-          for (int b = a; b < D; ++b, ++k) P[4 * D + k] = Sq[a][b];
+          for (int b = a; b < D; ++b, ++k) P[SO + k] = Sq[a][b];
       } else {
 #pragma unroll
         for (int a = 0; a < D; ++a)
 #pragma unroll
-          for (int b = 0; b < D; ++b) P[4 * D + a * D + b] = Sq[a][b];
+          for (int b = 0; b < D; ++b) P[SO + a * D + b] = Sq[a][b];
       }
     }
     __syncthreads();
     // next chunk's inputs: in flight during this chunk's scatter
     if (t < CH) stress_fetch<D, R, MODE>(d, q0 + CH + t, ntot, npi, pb, sb, visc, in);
     // ---- scatter phase: the lane's cell points inside this chunk ----
-    if (lane_on) {
+    if constexpr (MONO) {
+      // lane (component a = lk0, plane kz = lk1): the a row of the stress
+      const int lo = q0, hi = min(q0 + CH, ntot);
+      const int a = lk0, kz = lk1;
+      for (int pass = 0; pass < 2 && lane_on; ++pass) {
+        const int b0 = max(pass == 0 ? cpb : csb, lo), b1 = min(pass == 0 ? cpe : cse, hi);
+        for (int qq = b0; qq < b1; ++qq) {
+          const R* P = &sm.x.pt[(qq - q0) * PS];
+          const R* Sa = P + 8 + 3 * a;
+          lane_scatter_mono<R>(P[0], P[1], P[2 + kz], P[5 + kz], Sa[0], Sa[1], Sa[2], acc.v);
+        }
+      }
+    } else if (lane_on) {
       int lo = q0, hi = min(q0 + CH, ntot);
       for (int pass = 0; pass < 2; ++pass) {
         int b0 = max(pass == 0 ? cpb : csb, lo), b1 = min(pass == 0 ? cpe : cse, hi);
@@ -1280,8 +1365,8 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
   }
   // ---- reduce onto the region and write the tile partial ----
   R* dst = tpart + (size_t)slot * RN * D;
-  reduce_region_dense<D, R, D>(acc, sm.x.dense, lcell, lk0, lk1, lane_on,
-                               [&](int rn, int f, R v) { dst[rn * D + f] = v; });
+  auto wr = [&](int rn, int f, R v) { dst[rn * D + f] = v; };
+  reduce_region_dense<D, R, D, decltype(wr)&, MONO>(acc, sm.x.dense, lcell, lk0, lk1, lane_on, wr);
   if (MODE == TM_ENERGY && energy_slot >= 0) {
     double bs = block_sum(e, sm.bsum);
     if (t == 0) d.part[energy_slot * kPartSlot + slot] = bs;
