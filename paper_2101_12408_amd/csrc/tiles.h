@@ -13,6 +13,7 @@
 // partials of the <= 2^d tiles whose region holds it (fixed order) and applies the
 // node-level terms.  No float atomics anywhere: results are bitwise reproducible.
 #pragma once
+#include <type_traits>
 #include "kernels.h"
 
 namespace mpm {
@@ -277,9 +278,9 @@ struct DenseRed {
   static constexpr int KS = (KN + 3) & ~3;   // whole 16-byte rows
 };
 
-template <int D, typename R, int NF, class Out, bool MONO = false>
-MPM_DEV void reduce_region_dense(const LaneAcc<D, R, NF>& acc, R* B, int lane_cell, int lane_k0, int lane_k1,
-                                 bool lane_on, Out&& out) {
+template <int D, typename R, int NF, class Out, bool MONO = false, class Acc>
+MPM_DEV void reduce_region_dense(const Acc& acc, R* B, int lane_cell, int lane_k0, int lane_k1, bool lane_on,
+                                 Out&& out) {
   constexpr int RN = TileGeo<D>::RN, NT = TileGeo<D>::NT, KN = DenseRed<D>::KN, KS = DenseRed<D>::KS;
   constexpr int NB = RN * NF * KS;
   static_assert((NB * sizeof(R)) % 16 == 0, "whole 16-byte rows");
@@ -292,7 +293,7 @@ MPM_DEV void reduce_region_dense(const LaneAcc<D, R, NF>& acc, R* B, int lane_ce
     if constexpr (MONO) {
       // lane (component lane_k0, plane lane_k1): its coefficient sensitivities to the
       // nodes of its plane patch (lane_scatter_mono)
-      static_assert(D == 3 && NF == 3, "plane patches of the 3D stress scatter");
+      static_assert(D == 3 && (NF == 3 || NF == 1), "plane patches of the 3D scatters");
       R g[3][3];
       mono_unmap<R>(acc.v, g);
       const int a = lane_k0, kz = lane_k1;
@@ -686,8 +687,7 @@ MPM_DEV R mono_div(const R* cf, const int* lc, R x, R y, R fn, const R (&wz)[3],
 //   gA = S_a0 fn wz, gB = S_a1 fn wz, gC = S_a2 dwz
 // (mono_plane and the plane sums of mono_grad, differentiated by c_pq).  fw = fn wz.
 template <typename R>
-MPM_DEV void lane_scatter_mono(R x, R y, R fw, R dwz, R S0, R S1, R S2, R (&h)[3][3]) {
-  const R gA = S0 * fw, gB = S1 * fw, gC = S2 * dwz;
+MPM_DEV void lane_scatter_mono_g(R x, R y, R gA, R gB, R gC, R (&h)[3][3]) {
   const R y2 = y * y, x2 = x * x, tx = x + x, ty = y + y;
   const R V[3] = {gC, fma_r(gC, y, gB), fma_r(gC, y2, ty * gB)};
   const R U[3] = {gA, gA * y, gA * y2};
@@ -697,6 +697,11 @@ MPM_DEV void lane_scatter_mono(R x, R y, R fw, R dwz, R S0, R S1, R S2, R (&h)[3
     h[1][q] = fma_r(x, V[q], h[1][q]) + U[q];
     h[2][q] = fma_r(x2, V[q], fma_r(tx, U[q], h[2][q]));
   }
+}
+
+template <typename R>
+MPM_DEV void lane_scatter_mono(R x, R y, R fw, R dwz, R S0, R S1, R S2, R (&h)[3][3]) {
+  lane_scatter_mono_g<R>(x, y, S0 * fw, S1 * fw, S2 * dwz, h);
 }
 
 // Lane (cell, k0[, k1]) view of a point's weights: the weights and gradients of its 3
@@ -1469,17 +1474,25 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::HEAT) k_tile_heat(De
   const int pb = rg[0], pe = rg[1];
   const int sb = S ? rg[2] : 0, se = S ? rg[3] : 0;
   const int npi = pe - pb, ntot = npi + (se - sb);
+  // 3D: the scatter accumulates coefficient sensitivities (lane_scatter_mono_g), one lane
+  // per (cell, z plane), 192 lanes; 2D: lanes (cell, k0) over the nodes
+  constexpr bool HM = D == 3;
   int lcell, lk0, lk1;
   lane_map<D>(t, lcell, lk0, lk1);
+  if constexpr (HM) {
+    lcell = t / 3;
+    lk0 = 0;
+    lk1 = t % 3;
+  }
   const LaneDw<R> ldw0(lk0), ldw1(lk1);
-  const bool lane_on = t < 64 * TileGeo<D>::LPC;
+  const bool lane_on = t < 64 * (HM ? 3 : TileGeo<D>::LPC);
   int cpb = 0, cpe = 0, csb = 0, cse = 0;
   if (lane_on) {
     cpb = d.p_start[cb + lcell] - pb; cpe = d.p_start[cb + lcell + 1] - pb;
     if (S) { csb = d.s_start[cb + lcell] - sb + npi; cse = d.s_start[cb + lcell + 1] - sb + npi; }
   }
   if (t < RN) sm.u[t] = gnode >= 0 ? (pu.z ? cg_dir(zv, beta, tv) : tv) : R(0);
-  LaneAcc<D, R, 1> acc;
+  std::conditional_t<HM, LaneAcc<3, R, 3>, LaneAcc<D, R, 1>> acc;
   acc.zero();
   R* cf = sm.x.pt + CH * PS;
   __syncthreads();
@@ -1508,24 +1521,38 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::HEAT) k_tile_heat(De
       if constexpr (D == 3) mono_grad<R, 1>(cf, lc, f[0], f[1], d.fn, w[2], dw[2], G, val);
       else region_grad<D, R, 1>(sm.u, lc, w, dw, G, val);
       R* P = &sm.x.pt[t * PS];
+      // 3D: x, y, fn wz, dwz, wz, then c and q at CO; 2D: X = x fn (the lanes form their
+      // derivatives from it), the weight table, then c and q
+      constexpr int CO = HM ? 11 : 4 * D;
+      if constexpr (HM) {
+        P[0] = f[0];
+        P[1] = f[1];
 #pragma unroll
-      for (int a = 0; a < D; ++a) {
-        P[a] = f[a] * d.fn;   // X = x fn: the lanes form their derivatives from it
+        for (int kk = 0; kk < 3; ++kk) {
+          P[2 + kk] = d.fn * w[2][kk];
+          P[5 + kk] = dw[2][kk];
+          P[8 + kk] = w[2][kk];
+        }
+      } else {
 #pragma unroll
-        for (int kk = 0; kk < 3; ++kk) P[D + a * 3 + kk] = w[a][kk];
+        for (int a = 0; a < D; ++a) {
+          P[a] = f[a] * d.fn;
+#pragma unroll
+          for (int kk = 0; kk < 3; ++kk) P[D + a * 3 + kk] = w[a][kk];
+        }
       }
       if (interior) {
         R c = d.K * d.pVn[k];
-        P[4 * D] = 0;
+        P[CO] = 0;
 #pragma unroll
-        for (int a = 0; a < D; ++a) P[4 * D + 1 + a] = c * G[0][a];
+        for (int a = 0; a < D; ++a) P[CO + 1 + a] = c * G[0][a];
       } else {
         R area = 0;
 #pragma unroll
         for (int a = 0; a < D; ++a) area += d.sdA[a * S + k] * d.sdA[a * S + k];
-        P[4 * D] = d.h * sqrt(area) * val[0];
+        P[CO] = d.h * sqrt(area) * val[0];
 #pragma unroll
-        for (int a = 0; a < D; ++a) P[4 * D + 1 + a] = 0;
+        for (int a = 0; a < D; ++a) P[CO + 1 + a] = 0;
       }
     }
     __syncthreads();
@@ -1535,14 +1562,21 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::HEAT) k_tile_heat(De
         int b0 = max(pass == 0 ? cpb : csb, lo), b1 = min(pass == 0 ? cpe : cse, hi);
         for (int qq = b0; qq < b1; ++qq) {
           const R* P = &sm.x.pt[(qq - q0) * PS];
-          lane_scatter_heat<D, R>(P, P + D, d.fn, lk0, lk1, ldw0, ldw1, P[4 * D], P + 4 * D + 1, acc.v);
+          if constexpr (HM) {
+            // c N + q . grad N: gA = q_0 fn wz, gB = q_1 fn wz, gC = c wz + q_2 dwz
+            const R fw = P[2 + lk1], dwz = P[5 + lk1], wz = P[8 + lk1];
+            lane_scatter_mono_g<R>(P[0], P[1], P[12] * fw, P[13] * fw, fma_r(P[11], wz, P[14] * dwz), acc.v);
+          } else {
+            lane_scatter_heat<D, R>(P, P + D, d.fn, lk0, lk1, ldw0, ldw1, P[4 * D], P + 4 * D + 1, acc.v);
+          }
         }
       }
     }
     __syncthreads();
   }
   R* dst = tpart + (size_t)slot * RN;
-  reduce_region_dense<D, R, 1>(acc, sm.x.dense, lcell, lk0, lk1, lane_on, [&](int rn, int, R v) { dst[rn] = v; });
+  auto wr = [&](int rn, int, R v) { dst[rn] = v; };
+  reduce_region_dense<D, R, 1, decltype(wr)&, HM>(acc, sm.x.dense, lcell, lk0, lk1, lane_on, wr);
 }
 
 // ======================================================================================
