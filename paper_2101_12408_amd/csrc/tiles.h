@@ -7,7 +7,10 @@
 // node region (6^3 / 10^2 nodes, staged in LDS) and stores a per-point payload; the
 // scatter phase maps lanes to (cell, k0, k1): each lane accumulates, in registers and in
 // the fixed order of the cell's points, the contributions to the 3 nodes
-// (c0-1+k0, c1-1+k1, c2-1+k2), k2 = 0..2 (3D) or to the 3 nodes along k1 (2D); the
+// (c0-1+k0, c1-1+k1, c2-1+k2), k2 = 0..2 (3D) or to the 3 nodes along k1 (2D).  The 3D
+// stress and heat kernels gather from, and scatter into, per-plane polynomial coefficients
+// of the region instead (mono_build, mono_grad, lane_scatter_mono): their lanes stand for
+// (cell, component, z plane) and map their sums to the plane patch's nodes at the end.  The
 // per-cell partials are then reduced in LDS, in fixed order, onto the node region, which
 // is written to a per-tile partial buffer.  A merge kernel sums, for every node, the
 // partials of the <= 2^d tiles whose region holds it (fixed order) and applies the
