@@ -443,7 +443,7 @@ TileLists tiles(mpm_ctx* c, int k = TUNE_ENERGY) {
 int tile_grid(const mpm_ctx* c, int k = TUNE_ENERGY) { return xcd_grid(c->nctile, run_for(c, k)); }
 
 int krylov_blocks(int nelem) { return std::max(1, std::min(1024, cdiv(nelem, kNodeThreads))); }
-int merge_blocks(const mpm_ctx* c) { return cdiv(c->ntiles, kMergeTiles); }
+int merge_blocks(const mpm_ctx* c) { return merge_grid(c->ntiles); }
 
 void sync_read(mpm_ctx* c, hipStream_t s, const void* src, void* dst, size_t bytes) {
   HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));

@@ -2035,8 +2035,14 @@ __global__ void __launch_bounds__(256) k_tile_g2p(Dev<R> d, TileLists tl, const 
 // cell tiles that cover it (fixed order: cell tiles in lexicographic order).
 // ======================================================================================
 
-// Node kernels of the operators: one wave per node tile, kMergeTiles tiles per block.
+// Node kernels of the operators: one wave per node tile, kMergeTiles tiles per block.  The
+// blocks go to the XCDs in runs of kMergeRun (xcd_slot): a cell tile's partial is read by
+// the merges of its own node tile and of its neighbours, and the neighbours along x (and
+// some along y) then take its lines from the same L2.  Blocks past the last tile only
+// join the grid sums.
 constexpr int kMergeTiles = 4;
+constexpr int kMergeRun = 16;
+inline int merge_grid(int ntiles) { return xcd_grid((ntiles + kMergeTiles - 1) / kMergeTiles, kMergeRun); }
 
 // Stress merge: node-level terms.
 //  NM_GRAD: out = P[acc + m (v^ - v^n) - dt m g]; with phi the blocks also sum the tile
@@ -2059,7 +2065,7 @@ __global__ void __launch_bounds__(64 * kMergeTiles) k_merge_stress(
   constexpr int mode = MODE;
   __shared__ double sh[(MODE == NM_GRAD ? NV : 1) * 64 * kMergeTiles];
   if (done && *done) return;
-  const int ti = blockIdx.x * kMergeTiles + (threadIdx.x >> 6);
+  const int ti = xcd_slot(blockIdx.x, kMergeRun) * kMergeTiles + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   double vals[NV];
 #pragma unroll
@@ -2160,7 +2166,7 @@ __global__ void __launch_bounds__(64 * kMergeTiles) k_merge_heat(Dev<R> d, TileL
   constexpr int RN = TileGeo<D>::RN;
   __shared__ double sh[kRedSh];
   if (done && *done) return;
-  const int ti = blockIdx.x * kMergeTiles + (threadIdx.x >> 6);
+  const int ti = xcd_slot(blockIdx.x, kMergeRun) * kMergeTiles + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   double dotv = 0;
   if (ti < ntiles) {
