@@ -614,17 +614,18 @@ MPM_DEV void mono_build(const R* u, R* cf) {
 }
 
 // One plane's sums for component a of a point at (x, y) in its cell: the value C and the
-// derivatives A (along x) and B (along y), per unit of the cell-relative coordinates.
+// derivatives A (along x) and B (along y), per unit of the cell-relative coordinates;
+// tx = 2x, ty = 2y.
 template <typename R>
-MPM_DEV void mono_plane(const R* c, R x, R x2, R y, R y2, R& A, R& B, R& C) {
+MPM_DEV void mono_plane(const R* c, R x, R tx, R y, R ty, R& A, R& B, R& C) {
   R t[3], dd[3];
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     t[q] = fma_r(x, fma_r(x, c[6 + q], c[3 + q]), c[q]);
-    dd[q] = fma_r(x2, c[6 + q], c[3 + q]);
+    dd[q] = fma_r(tx, c[6 + q], c[3 + q]);
   }
   C = fma_r(y, fma_r(y, t[2], t[1]), t[0]);
-  B = fma_r(y2, t[2], t[1]);
+  B = fma_r(ty, t[2], t[1]);
   A = fma_r(y, fma_r(y, dd[2], dd[1]), dd[0]);
 }
 
@@ -635,7 +636,7 @@ MPM_DEV void mono_grad(const R* cf, const int* lc, R x, R y, R fn, const R (&wz)
                        R (&G)[NC][3], R (&val)[NC]) {
   constexpr int E = MonoGeo<NC>::E, CS = MonoGeo<NC>::CS;
   const R* base = cf + (lc[0] + E * (lc[1] + E * lc[2])) * CS;
-  const R x2 = x + x, y2 = y + y;
+  const R tx = x + x, ty = y + y;
 #pragma unroll
   for (int a = 0; a < NC; ++a) {
     val[a] = 0;
@@ -648,7 +649,7 @@ MPM_DEV void mono_grad(const R* cf, const int* lc, R x, R y, R fn, const R (&wz)
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
       R A, B, C;
-      mono_plane<R>(base + k * E * E * CS + a * 9, x, x2, y, y2, A, B, C);
+      mono_plane<R>(base + k * E * E * CS + a * 9, x, tx, y, ty, A, B, C);
       G[a][0] = fma_r(A, fw, G[a][0]);
       G[a][1] = fma_r(B, fw, G[a][1]);
       G[a][2] = fma_r(C, dwz[k], G[a][2]);
@@ -663,16 +664,16 @@ template <typename R>
 MPM_DEV R mono_div(const R* cf, const int* lc, R x, R y, R fn, const R (&wz)[3], const R (&dwz)[3]) {
   constexpr int E = MonoGeo<3>::E, CS = MonoGeo<3>::CS;
   const R* base = cf + (lc[0] + E * (lc[1] + E * lc[2])) * CS;
-  const R x2 = x + x, y2 = y + y;
+  const R tx = x + x, ty = y + y;
   R Gd[3] = {0, 0, 0};
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const R fw = fn * wz[k];
     const R* c = base + k * E * E * CS;
     R A, B, C, A1, B1, C1, A2, B2, C2;
-    mono_plane<R>(c, x, x2, y, y2, A, B, C);
-    mono_plane<R>(c + 9, x, x2, y, y2, A1, B1, C1);
-    mono_plane<R>(c + 18, x, x2, y, y2, A2, B2, C2);
+    mono_plane<R>(c, x, tx, y, ty, A, B, C);
+    mono_plane<R>(c + 9, x, tx, y, ty, A1, B1, C1);
+    mono_plane<R>(c + 18, x, tx, y, ty, A2, B2, C2);
     Gd[0] = fma_r(A, fw, Gd[0]);
     Gd[1] = fma_r(B1, fw, Gd[1]);
     Gd[2] = fma_r(C2, dwz[k], Gd[2]);
@@ -688,20 +689,21 @@ MPM_DEV R mono_div(const R* cf, const int* lc, R x, R y, R fn, const R (&wz)[3],
 // that plane's coefficients c_pq of component a to the point terms S_a . grad N:
 //   h_pq += gC x^p y^q + gB x^p q y^(q-1) + gA p x^(p-1) y^q,
 //   gA = S_a0 fn wz, gB = S_a1 fn wz, gC = S_a2 dwz
-// (mono_plane and the plane sums of mono_grad, differentiated by c_pq).  fw = fn wz.
+// (mono_plane and the plane sums of mono_grad, differentiated by c_pq).
 template <typename R>
 MPM_DEV void lane_scatter_mono_g(R x, R y, R gA, R gB, R gC, R (&h)[3][3]) {
-  const R y2 = y * y, x2 = x * x, tx = x + x, ty = y + y;
-  const R V[3] = {gC, fma_r(gC, y, gB), fma_r(gC, y2, ty * gB)};
-  const R U[3] = {gA, gA * y, gA * y2};
+  const R yy = y * y, xx = x * x, tx = x + x, ty = y + y;
+  const R V[3] = {gC, fma_r(gC, y, gB), fma_r(gC, yy, ty * gB)};
+  const R U[3] = {gA, gA * y, gA * yy};
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     h[0][q] += V[q];
     h[1][q] = fma_r(x, V[q], h[1][q]) + U[q];
-    h[2][q] = fma_r(x2, V[q], fma_r(tx, U[q], h[2][q]));
+    h[2][q] = fma_r(xx, V[q], fma_r(tx, U[q], h[2][q]));
   }
 }
 
+// The stress form: fw = fn wz and dwz of the lane's plane, S0..S2 the row a of the stress.
 template <typename R>
 MPM_DEV void lane_scatter_mono(R x, R y, R fw, R dwz, R S0, R S1, R S2, R (&h)[3][3]) {
   lane_scatter_mono_g<R>(x, y, S0 * fw, S1 * fw, S2 * dwz, h);
