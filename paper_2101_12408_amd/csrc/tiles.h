@@ -1064,53 +1064,62 @@ MPM_DEV void stress_fetch(const Dev<R>& d, int q, int ntot, int npi, int pb, int
   }
 }
 
-// A thread's share of a tile's node region: one (node, component) item per NT threads,
-// component-major so that a wave reads one plane.  All of a thread's loads (u, z and the
-// free flags of every item) are issued before any is used (every grid node is a valid
-// address); the constraint mask and the CG direction are applied when the items are
-// written to LDS.
+// A thread's share of a tile's node region: thread t < RN holds region node t, all of its
+// D components (each load instruction of a wave reads one component of 64 consecutive
+// region nodes).  All of a thread's loads (u, z and the node's free flags) are issued
+// before any is used; the constraint mask and the CG direction are applied when the node
+// is written to LDS.
 template <int D, typename R>
 struct RegionPf {
-  static constexpr int NI = (TileGeo<D>::RN * D + TileGeo<D>::NT - 1) / TileGeo<D>::NT;
-  R uv[NI], zv[NI];
-  int fr[NI];   // free flags of the node; 0 outside the grid
+  R uv[D], zv[D];
+  int fr;   // free flags of the node; 0 outside the grid or past the region
 };
 
+// org: the tile's first cell (tiled_coords).  The node number is region_node_global's.
 template <int D, typename R>
-MPM_DEV void region_fetch(const Dev<R>& d, int ct, const R* u, const R* z, int mask_in, RegionPf<D, R>& pf) {
-  constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
+MPM_DEV void region_fetch(const Dev<R>& d, const int* org, const R* u, const R* z, int mask_in,
+                          RegionPf<D, R>& pf) {
+  constexpr int RN = TileGeo<D>::RN, E = Tiling<D>::E, L = Tiling<D>::LOG;
+  static_assert(RN <= TileGeo<D>::NT, "one region node per thread");
+  const int t = threadIdx.x;
 #pragma unroll
-  for (int i = 0; i < RegionPf<D, R>::NI; ++i) {
-    const int e2 = (int)threadIdx.x + i * NT;
-    pf.uv[i] = R(0);
-    pf.zv[i] = R(0);
-    pf.fr[i] = 0;
-    if (e2 < RN * D) {
-      const int a = e2 / RN, rn = e2 - a * RN;
-      int r[3];
-      region_coords<D>(rn, r);
-      const int gnode = region_node_global<D>(ct, r, d.n, d.nt);
-      if (gnode >= 0) {
-        pf.fr[i] = mask_in ? d.gfree[gnode] : 0xff;
-        pf.uv[i] = u[a * d.nn + gnode];
-        if (z) pf.zv[i] = z[a * d.nn + gnode];
-      }
-    }
+  for (int a = 0; a < D; ++a) {
+    pf.uv[a] = R(0);
+    pf.zv[a] = R(0);
+  }
+  pf.fr = 0;
+  if (t >= RN) return;
+  int r[3];
+  region_coords<D>(t, r);
+  const int stride[3] = {1, d.nt, d.nt * d.nt};   // node tiles along each axis
+  bool ok = true;
+  int tile = 0, local = 0;
+#pragma unroll
+  for (int b = 0; b < D; ++b) {
+    const int g = org[b] - 1 + r[b];
+    ok = ok && (unsigned)g < (unsigned)d.n;
+    tile += (g >> L) * stride[b];
+    local += (g & (E - 1)) << (L * b);
+  }
+  if (!ok) return;
+  const int gnode = tile * kTileNodes + local;
+  pf.fr = mask_in ? d.gfree[gnode] : 0xff;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    pf.uv[a] = u[a * d.nn + gnode];
+    if (z) pf.zv[a] = z[a * d.nn + gnode];
   }
 }
 
 template <int D, typename R>
 MPM_DEV void region_commit(const RegionPf<D, R>& pf, bool has_z, R beta, R* su) {
-  constexpr int NT = TileGeo<D>::NT, RN = TileGeo<D>::RN;
+  const int t = threadIdx.x;
+  if (t >= TileGeo<D>::RN) return;
 #pragma unroll
-  for (int i = 0; i < RegionPf<D, R>::NI; ++i) {
-    const int e2 = (int)threadIdx.x + i * NT;
-    if (e2 < RN * D) {
-      const int a = e2 / RN, rn = e2 - a * RN;
-      R uv = pf.uv[i];
-      if (has_z) uv = cg_dir(pf.zv[i], beta, uv);
-      su[rn * D + a] = ((pf.fr[i] >> a) & 1) ? uv : R(0);
-    }
+  for (int a = 0; a < D; ++a) {
+    R uv = pf.uv[a];
+    if (has_z) uv = cg_dir(pf.zv[a], beta, uv);
+    su[t * D + a] = ((pf.fr >> a) & 1) ? uv : R(0);
   }
 }
 
@@ -1157,7 +1166,7 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
   // the node region, the lanes' cell ranges: every load is issued before the region is
   // written to LDS, so that the block waits for one round trip
   RegionPf<D, R> pf;
-  region_fetch<D, R>(d, ct, u, pu.z, mask_in, pf);
+  region_fetch<D, R>(d, org, u, pu.z, mask_in, pf);
   int lcell, lk0, lk1;
   lane_map<D>(t, lcell, lk0, lk1);
   const LaneDw<R> ldw0(lk0), ldw1(lk1);
