@@ -170,19 +170,38 @@ MPM_DEV int region_index(const int* r) {
   return r[0] + RE * (r[1] + (D == 3 ? RE * r[2] : 0));
 }
 
-// Global tiled index of region node r of cell tile ct (region origin = first cell - 1);
-// -1 outside the grid.
+// The first cell of cell tile `tile` (tiled_coords with local 0), in 32-bit arithmetic.
 template <int D>
-MPM_DEV int region_node_global(int ct, const int* r, int n, int nt) {
-  int t[3] = {0, 0, 0};
-  tiled_coords<D>(ct, 0, nt, t);       // first cell of the tile
-  int g[3] = {0, 0, 0};
-#pragma unroll
-  for (int a = 0; a < D; ++a) {
-    g[a] = t[a] - 1 + r[a];
-    if (g[a] < 0 || g[a] >= n) return -1;
+MPM_DEV void tile_origin(int tile, int nt, int* o) {
+  constexpr int L = Tiling<D>::LOG;
+  const unsigned t = (unsigned)tile, n = (unsigned)nt;
+  const unsigned q = t / n;
+  o[0] = (int)(t - q * n) << L;
+  if (D == 3) {
+    const unsigned q2 = q / n;
+    o[1] = (int)(q - q2 * n) << L;
+    o[2] = (int)q2 << L;
+  } else {
+    o[1] = (int)q << L;
   }
-  return (int)tiled_index<D>(g, nt);
+}
+
+// Global tiled index (tiled_index) of region node r of the cell tile whose first cell is
+// org (region origin = org - 1), -1 outside the grid: 32-bit, one bounds test for all axes.
+template <int D>
+MPM_DEV int region_node_at(const int* org, const int* r, int n, int nt) {
+  constexpr int E = Tiling<D>::E, L = Tiling<D>::LOG;
+  const int stride[3] = {1, nt, nt * nt};   // node tiles along each axis
+  bool ok = true;
+  int tile = 0, local = 0;
+#pragma unroll
+  for (int b = 0; b < D; ++b) {
+    const int g = org[b] - 1 + r[b];
+    ok = ok && (unsigned)g < (unsigned)n;
+    tile += (g >> L) * stride[b];
+    local += (g & (E - 1)) << (L * b);
+  }
+  return ok ? tile * kTileNodes + local : -1;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1075,11 +1094,11 @@ struct RegionPf {
   int fr;   // free flags of the node; 0 outside the grid or past the region
 };
 
-// org: the tile's first cell (tiled_coords).  The node number is region_node_global's.
+// org: the tile's first cell (tile_origin).
 template <int D, typename R>
 MPM_DEV void region_fetch(const Dev<R>& d, const int* org, const R* u, const R* z, int mask_in,
                           RegionPf<D, R>& pf) {
-  constexpr int RN = TileGeo<D>::RN, E = Tiling<D>::E, L = Tiling<D>::LOG;
+  constexpr int RN = TileGeo<D>::RN;
   static_assert(RN <= TileGeo<D>::NT, "one region node per thread");
   const int t = threadIdx.x;
 #pragma unroll
@@ -1091,18 +1110,8 @@ MPM_DEV void region_fetch(const Dev<R>& d, const int* org, const R* u, const R* 
   if (t >= RN) return;
   int r[3];
   region_coords<D>(t, r);
-  const int stride[3] = {1, d.nt, d.nt * d.nt};   // node tiles along each axis
-  bool ok = true;
-  int tile = 0, local = 0;
-#pragma unroll
-  for (int b = 0; b < D; ++b) {
-    const int g = org[b] - 1 + r[b];
-    ok = ok && (unsigned)g < (unsigned)d.n;
-    tile += (g >> L) * stride[b];
-    local += (g & (E - 1)) << (L * b);
-  }
-  if (!ok) return;
-  const int gnode = tile * kTileNodes + local;
+  const int gnode = region_node_at<D>(org, r, d.n, d.nt);
+  if (gnode < 0) return;
   pf.fr = mask_in ? d.gfree[gnode] : 0xff;
 #pragma unroll
   for (int a = 0; a < D; ++a) {
@@ -1145,7 +1154,7 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
   const int t = threadIdx.x;
   const R dt = d.dt;
   int org[3] = {0, 0, 0};
-  tiled_coords<D>(ct, 0, d.nt, org);
+  tile_origin<D>(ct, d.nt, org);
   const int cb = ct * 64;
   constexpr bool SOL = VAR == SV_SOLID, ISO = VAR == SV_JONLY, SYM = VAR == SV_FLUID;
   // 3D, but for the J term alone (whose s I scatter is cheaper node by node): the scatter
@@ -1467,7 +1476,7 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::HEAT) k_tile_heat(De
   const int N = d.np, S = d.ns;
   const int t = threadIdx.x;
   int org[3] = {0, 0, 0};
-  tiled_coords<D>(ct, 0, d.nt, org);
+  tile_origin<D>(ct, d.nt, org);
   const R beta = pu.beta();
   // the region's values and the lanes' cell ranges are all loaded before the region is
   // written to LDS (one round trip); the region has fewer nodes than the block threads
@@ -1477,7 +1486,7 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::HEAT) k_tile_heat(De
   if (t < RN) {
     int r[3];
     region_coords<D>(t, r);
-    gnode = region_node_global<D>(ct, r, d.n, d.nt);
+    gnode = region_node_at<D>(org, r, d.n, d.nt);
     if (gnode >= 0) {
       tv = T[gnode];
       if (pu.z) zv = pu.z[gnode];
@@ -1938,11 +1947,11 @@ __global__ void __launch_bounds__(256) k_tile_g2p(Dev<R> d, TileLists tl, const 
   const int N = d.np, S = d.ns, nn = d.nn;
   const int t = threadIdx.x;
   int org[3] = {0, 0, 0};
-  tiled_coords<D>(ct, 0, d.nt, org);
+  tile_origin<D>(ct, d.nt, org);
   for (int rn = t; rn < RN; rn += NT) {
     int r[3];
     region_coords<D>(rn, r);
-    int gnode = region_node_global<D>(ct, r, d.n, d.nt);
+    int gnode = region_node_at<D>(org, r, d.n, d.nt);
 #pragma unroll
     for (int a = 0; a < D; ++a) sm.u[rn * D + a] = gnode >= 0 ? vh[a * nn + gnode] : R(0);
     sm.T[rn] = (gnode >= 0 && Th) ? Th[gnode] : R(0);
