@@ -1338,8 +1338,8 @@ __global__ void MPM_TILE_KERNEL(TileGeo<D>::NT, TileOcc<R>::STRESS) k_tile_stres
       }
     }
     __syncthreads();
-    // next chunk's inputs: in flight during this chunk's scatter
-    if (t < CH) stress_fetch<D, R, MODE>(d, q0 + CH + t, ntot, npi, pb, sb, visc, in);
+    // next chunk's inputs, if there is one: in flight during this chunk's scatter
+    if (q0 + CH < ntot && t < CH) stress_fetch<D, R, MODE>(d, q0 + CH + t, ntot, npi, pb, sb, visc, in);
     // ---- scatter phase: the lane's cell points inside this chunk ----
     if constexpr (MONO) {
       // lane (component a = lk0, plane kz = lk1): the a row of the stress
