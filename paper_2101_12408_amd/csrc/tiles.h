@@ -303,7 +303,8 @@ struct DenseRed {
 template <int D, typename R, int NF, class Out, bool MONO = false, class Acc>
 MPM_DEV void reduce_region_dense(const Acc& acc, R* B, int lane_cell, int lane_k0, int lane_k1, bool lane_on,
                                  Out&& out) {
-  constexpr int RN = TileGeo<D>::RN, NT = TileGeo<D>::NT, KN = DenseRed<D>::KN, KS = DenseRed<D>::KS;
+  constexpr int RN = TileGeo<D>::RN, RE = TileGeo<D>::RE, NT = TileGeo<D>::NT, KN = DenseRed<D>::KN,
+                KS = DenseRed<D>::KS;
   constexpr int NB = RN * NF * KS;
   static_assert((NB * sizeof(R)) % 16 == 0, "whole 16-byte rows");
   uint4* B16 = reinterpret_cast<uint4*>(B);   // all-zero bits are 0.0 in both precisions
@@ -319,24 +320,24 @@ MPM_DEV void reduce_region_dense(const Acc& acc, R* B, int lane_cell, int lane_k
       R g[3][3];
       mono_unmap<R>(acc.v, g);
       const int a = lane_k0, kz = lane_k1;
+      // slot (node c + (i, j, kz), field a, offset i + 3 j + 9 kz): one base index and
+      // compile-time steps along i and j
+      const int r0[3] = {c[0], c[1], c[2] + kz};
+      const int base = (region_index<D>(r0) * NF + a) * KS + 9 * kz;
 #pragma unroll
       for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          int r[3] = {c[0] + i, c[1] + j, c[2] + kz};
-          const int rn = region_index<D>(r);
-          B[(rn * NF + a) * KS + i + 3 * j + 9 * kz] = g[i][j];
-        }
+        for (int j = 0; j < 3; ++j) B[base + i * (NF * KS + 1) + j * (RE * NF * KS + 3)] = g[i][j];
     } else {
+      // slot (node c + (k0, k1, k) in 3D or c + (k0, k) in 2D, field f, offset k0 + 3 k1 +
+      // 9 k2): one base index and compile-time steps along k and f
+      const int r0[3] = {c[0] + lane_k0, c[1] + (D == 3 ? lane_k1 : 0), D == 3 ? c[2] : 0};
+      const int base = region_index<D>(r0) * NF * KS + lane_k0 + (D == 3 ? 3 * lane_k1 : 0);
+      constexpr int step = D == 3 ? RE * RE * NF * KS + 9 : RE * NF * KS + 3;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const int kk[3] = {lane_k0, D == 3 ? lane_k1 : k, D == 3 ? k : 0};
-        int r[3] = {c[0] + kk[0], c[1] + kk[1], D == 3 ? c[2] + kk[2] : 0};
-        const int rn = region_index<D>(r);
-        const int kidx = kk[0] + 3 * kk[1] + 9 * kk[2];
+      for (int k = 0; k < 3; ++k)
 #pragma unroll
-        for (int f = 0; f < NF; ++f) B[(rn * NF + f) * KS + kidx] = acc.v[k][f];
-      }
+        for (int f = 0; f < NF; ++f) B[base + k * step + f * KS] = acc.v[k][f];
     }
   }
   __syncthreads();
